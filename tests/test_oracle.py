@@ -1,0 +1,292 @@
+"""Pins for the FP64 CPU oracle against facts fixed by mathematics, not by the
+oracle itself (closed forms, exact rational inverses, special cases that
+reduce to exact arithmetic, library routines and invariants).
+
+The oracle computes the three stages of the paper's Algorithm 1 (Section 2)
+at tile order b = 1.  Each stage is pinned separately so that a dropped term,
+a wrong sign, a wrong index or a transposed operand in any stage fails a test.
+"""
+from fractions import Fraction
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1002_4057_amd import inputs
+
+U = 2.0 ** -53
+
+
+def rel_fro(x, y):
+    return np.linalg.norm(x - y) / np.linalg.norm(y)
+
+
+# --------------------------------------------------------------------------
+# tridiag(-1, 2, -1): closed forms for every stage (1-based indices)
+# --------------------------------------------------------------------------
+def tridiag_L(n):
+    l = np.zeros((n, n))
+    for i in range(1, n + 1):
+        l[i - 1, i - 1] = math.sqrt((i + 1) / i)
+        if i < n:
+            l[i, i - 1] = -math.sqrt(i / (i + 1))
+    return l
+
+
+def tridiag_Linv(n):
+    x = np.zeros((n, n))
+    for i in range(1, n + 1):
+        for j in range(1, i + 1):
+            x[i - 1, j - 1] = j / math.sqrt(i * (i + 1))
+    return x
+
+
+def tridiag_inv(n):
+    y = np.zeros((n, n))
+    for i in range(1, n + 1):
+        for j in range(1, n + 1):
+            y[i - 1, j - 1] = min(i, j) * (n + 1 - max(i, j)) / (n + 1)
+    return y
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 65, 200])
+def test_tridiag_stage1_cholesky_closed_form(n):
+    l = oracle.potrf(inputs.tridiag(n))
+    np.testing.assert_allclose(l, tridiag_L(n), rtol=0, atol=8 * n * U)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 65, 200])
+def test_tridiag_stage2_trtri_closed_form(n):
+    # stage 2 is fed the exact closed-form factor, so its own error is isolated
+    x = oracle.trtri(tridiag_L(n))
+    assert rel_fro(x, tridiag_Linv(n)) <= 16 * n * U
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 65, 200])
+def test_tridiag_stage3_lauum_closed_form(n):
+    y = oracle.lauum(tridiag_Linv(n))
+    assert rel_fro(y, np.tril(tridiag_inv(n))) <= 16 * n * U
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 64, 512])
+def test_tridiag_end_to_end_closed_form(n):
+    y = oracle.spd_inverse(inputs.tridiag(n))
+    # kappa(tridiag) ~ 4 (n+1)^2 / pi^2
+    kappa = 4.0 * (n + 1) ** 2 / math.pi ** 2
+    assert rel_fro(y, tridiag_inv(n)) <= 1e-14 * max(kappa, 1.0)
+
+
+def test_tridiag_kappa_512_matches_estimate():
+    ev = np.linalg.eigvalsh(inputs.tridiag(512))
+    assert abs(ev[-1] / ev[0] / 1.0666e5 - 1) < 1e-3
+
+
+# --------------------------------------------------------------------------
+# Hilbert matrices: exact integer inverse (Choi 1983), input made exact by
+# scaling with lcm(1..2n-1)
+# --------------------------------------------------------------------------
+def hilbert_inverse_exact(n):
+    c = math.comb
+    return [[(-1) ** (i + j) * (i + j - 1) * c(n + i - 1, n - j) * c(n + j - 1, n - i)
+             * c(i + j - 2, i - 1) ** 2 for j in range(1, n + 1)] for i in range(1, n + 1)]
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 7, 8])
+def test_hilbert_integer_inverse(n):
+    a, s = inputs.hilbert_scaled(n)
+    exact = np.array(hilbert_inverse_exact(n), dtype=np.float64) / s
+    y = oracle.spd_inverse(a)
+    kappa = np.linalg.cond(a)
+    assert rel_fro(y, exact) <= 32 * n * U * kappa
+
+
+def test_hilbert_formula_is_an_inverse():
+    # the closed form itself, checked in exact rationals
+    n = 6
+    hinv = hilbert_inverse_exact(n)
+    for i in range(n):
+        for j in range(n):
+            s = sum(Fraction(1, i + k + 1) * hinv[k][j] for k in range(n))
+            assert s == (1 if i == j else 0)
+
+
+# --------------------------------------------------------------------------
+# exact rational Gauss-Jordan on small integer SPD matrices
+# --------------------------------------------------------------------------
+def gauss_jordan_inverse(a):
+    n = len(a)
+    m = [[Fraction(int(a[i][j])) for j in range(n)] + [Fraction(int(i == j)) for j in range(n)]
+         for i in range(n)]
+    for c in range(n):
+        p = next(r for r in range(c, n) if m[r][c] != 0)
+        m[c], m[p] = m[p], m[c]
+        piv = m[c][c]
+        m[c] = [v / piv for v in m[c]]
+        for r in range(n):
+            if r != c and m[r][c] != 0:
+                f = m[r][c]
+                m[r] = [vr - f * vc for vr, vc in zip(m[r], m[c])]
+    return [[float(m[i][n + j]) for j in range(n)] for i in range(n)]
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (4, 2), (7, 3), (12, 4), (16, 5)])
+def test_gauss_jordan_rational(n, seed):
+    a = inputs.small_integer_spd(n, seed)
+    exact = np.array(gauss_jordan_inverse(a))
+    y = oracle.spd_inverse(a)
+    kappa = np.linalg.cond(a)
+    assert rel_fro(y, exact) <= 16 * n * U * kappa
+
+
+# --------------------------------------------------------------------------
+# special cases with exact results
+# --------------------------------------------------------------------------
+def test_identity_is_fixed_point():
+    for n in (1, 3, 33):
+        np.testing.assert_array_equal(oracle.spd_inverse(np.eye(n)), np.eye(n))
+
+
+def test_diagonal_powers_of_four_exact():
+    d = 4.0 ** np.array([-3, 0, 2, 5, -1, 1, 7])
+    y = oracle.spd_inverse(np.diag(d))
+    np.testing.assert_array_equal(y, np.diag(1.0 / d))
+    np.testing.assert_array_equal(oracle.potrf(np.diag(d)), np.diag(np.sqrt(d)))
+
+
+def test_lauum_special_cases():
+    np.testing.assert_array_equal(oracle.lauum(np.eye(9)), np.eye(9))
+    d = np.array([3.0, -2.0, 0.5, 7.0])
+    np.testing.assert_array_equal(oracle.lauum(np.diag(d)), np.diag(d * d))
+
+
+def test_lauum_is_xt_x_on_integer_input():
+    # integer lower triangular X: X^T X is exact in binary64 at this size
+    rng = np.random.default_rng(7)
+    x = np.tril(rng.integers(-9, 10, size=(11, 11))).astype(np.float64)
+    np.testing.assert_array_equal(oracle.lauum(x), np.tril(x.T @ x))
+
+
+def test_trtri_unit_lower_integer_exact():
+    # unit lower bidiagonal with -1 below: inverse is the all-ones lower triangle
+    n = 10
+    l = np.eye(n) - np.eye(n, k=-1)
+    np.testing.assert_array_equal(oracle.trtri(l), np.tril(np.ones((n, n))))
+
+
+def test_cholesky_of_integer_gram_exact():
+    # A = L L^T with L integer lower with unit positive diagonal: exact recovery
+    rng = np.random.default_rng(3)
+    n = 9
+    l = np.tril(rng.integers(-3, 4, size=(n, n))).astype(np.float64)
+    np.fill_diagonal(l, rng.integers(1, 4, size=n).astype(np.float64))
+    a = l @ l.T
+    np.testing.assert_allclose(oracle.potrf(a), l, rtol=0, atol=64 * U * np.abs(l).max())
+
+
+# --------------------------------------------------------------------------
+# INFO semantics (LAPACK xPOTRF convention)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [1, 2, 5, 9])
+def test_info_negative_pivot(k):
+    d = np.ones(9)
+    d[k - 1] = -1.0
+    with pytest.raises(oracle.OracleInfo) as e:
+        oracle.spd_inverse(np.diag(d))
+    assert e.value.info == k
+
+
+def test_info_nan_and_zero():
+    a = np.eye(5)
+    a[3, 3] = np.nan
+    with pytest.raises(oracle.OracleInfo) as e:
+        oracle.spd_inverse(a)
+    assert e.value.info == 4
+    a = np.ones((3, 3))  # rank one: second pivot is exactly 0
+    with pytest.raises(oracle.OracleInfo) as e:
+        oracle.spd_inverse(a)
+    assert e.value.info == 2
+
+
+# --------------------------------------------------------------------------
+# invariants and library cross-checks on random SPD input
+# --------------------------------------------------------------------------
+def test_upper_triangle_never_read_or_written():
+    a = inputs.wishart_shift(40, seed=11).numpy()
+    poisoned = a.copy()
+    poisoned[np.triu_indices(40, 1)] = np.nan
+    low = oracle.spd_inverse_lower(poisoned)
+    assert np.all(np.isfinite(np.tril(low)))
+    assert np.all(np.isnan(low[np.triu_indices(40, 1)]))
+    np.testing.assert_array_equal(np.tril(low), np.tril(oracle.spd_inverse_lower(a)))
+
+
+@pytest.mark.parametrize("n,seed", [(50, 0), (130, 1), (300, 2)])
+def test_invariants_and_library_crosscheck(n, seed):
+    a = inputs.wishart_shift(n, seed=seed).numpy()
+    l = oracle.potrf(a)
+    assert np.all(np.diag(l) > 0) and np.allclose(np.triu(l, 1), 0)
+    assert np.linalg.norm(l @ l.T - a) <= 4 * n * U * np.linalg.norm(a)
+    np.testing.assert_allclose(l, np.linalg.cholesky(a), rtol=0, atol=1e-13 * np.abs(l).max())
+    x = oracle.trtri(l)
+    assert np.linalg.norm(l @ x - np.eye(n)) <= 8 * n * U * np.linalg.cond(l)
+    y = oracle.spd_inverse(a)
+    np.testing.assert_array_equal(y, y.T)
+    kappa = np.linalg.cond(a)
+    assert np.linalg.norm(np.eye(n) - a @ y) <= 8 * n * U * kappa
+    assert rel_fro(y, np.linalg.inv(a)) <= 8 * n * U * kappa
+
+
+def test_spectrum_matrix_against_analytic_inverse():
+    a, q, lam = inputs.spectrum(256, 1e6, seed=0, return_factors=True)
+    y = oracle.spd_inverse(a.numpy())
+    ref = inputs.analytic_inverse(q, lam).numpy()
+    assert rel_fro(y, ref) <= 1e-12 * 1e6
+
+
+# --------------------------------------------------------------------------
+# gradient: closed forms and central finite differences through the oracle
+# --------------------------------------------------------------------------
+def test_grad_diagonal_closed_form():
+    d = np.array([1.5, 2.0, 0.25, 4.0, 3.0])
+    g = inputs.randn((5, 5), seed=1).numpy()
+    s = 0.5 * (g + g.T)
+    ref = -s / np.outer(d, d)
+    np.testing.assert_allclose(oracle.inverse_grad(np.diag(1.0 / d), g), ref, rtol=1e-15, atol=0)
+
+
+def test_grad_identity_upstream_is_minus_inverse_squared():
+    a = inputs.wishart_shift(20, seed=4).numpy()
+    y = oracle.spd_inverse(a)
+    grad = oracle.inverse_grad(y, np.eye(20))
+    ref = -np.linalg.inv(a) @ np.linalg.inv(a)
+    assert rel_fro(grad, ref) <= 1e-12
+
+
+def test_grad_central_finite_differences():
+    n = 12
+    a = inputs.wishart_shift(n, seed=5).numpy()
+    g = inputs.randn((n, n), seed=1).numpy()
+    grad = oracle.inverse_grad(oracle.spd_inverse(a), g)
+    h = 1e-6
+    rng = np.random.default_rng(2)
+    for _ in range(10):
+        p, q = sorted(rng.integers(0, n, size=2))[::-1]
+        e = np.zeros((n, n))
+        e[p, q] += 1.0
+        if p != q:
+            e[q, p] += 1.0
+        lp = math.fsum((g * oracle.spd_inverse(a + h * e)).ravel())
+        lm = math.fsum((g * oracle.spd_inverse(a - h * e)).ravel())
+        fd = (lp - lm) / (2 * h)
+        analytic = grad[p, q] * (2.0 if p != q else 1.0)
+        assert abs(fd - analytic) <= 1e-6 * max(1.0, abs(analytic))
+
+
+def test_grad_reads_only_lower_triangle_of_inverse():
+    n = 9
+    y = oracle.spd_inverse(inputs.wishart_shift(n, seed=6).numpy())
+    g = inputs.randn((n, n), seed=2).numpy()
+    low = np.tril(y)
+    low[np.triu_indices(n, 1)] = np.nan
+    np.testing.assert_array_equal(oracle.inverse_grad(low, g), oracle.inverse_grad(y, g))
