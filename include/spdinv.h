@@ -1,0 +1,189 @@
+/*
+ * spdinv -- explicit inverse of symmetric positive definite matrices on
+ * MI355X (gfx950), as the three-stage tile algorithm of Agullo, Bouwmeester,
+ * Dongarra, Kurzak, Langou and Rosenberg, "Towards an Efficient Tile Matrix
+ * Inversion of Symmetric Positive Definite Matrices on Multicore
+ * Architectures":
+ *
+ *   step 1  A = L L^T          (tile Cholesky: POTRF, SYRK, GEMM, TRSM)
+ *   step 2  X = L^{-1}         (tile triangular inverse: TRTRI, TRMM, GEMM)
+ *   step 3  A^{-1} = X^T X     (tile product: LAUUM, TRMM, GEMM, SYRK)
+ *
+ * (Section 2, Algorithm 1), with the anti-dependences removed by array
+ * renaming, the step-2 GEMM chain reversed (loop order UDU) and the three
+ * steps pipelined through one dependency-tracked DAG (Section 3, Table 1).
+ * Every task runs on the GPU inside one persistent scheduler kernel.
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ * - Matrices are column-major with a leading dimension ld >= max(1, n).
+ *   Pointers documented as "device" must be device memory of the current HIP
+ *   device; "host" pointers are ordinary host memory.
+ * - Only the lower triangle (row >= column) of an input SPD matrix is read;
+ *   on success the lower triangle holds the lower triangle of A^{-1}.  The
+ *   strictly upper triangle is neither read nor written unless
+ *   spdinv_opts.fill_upper is set (then it receives the mirror image).
+ * - The caller owns every buffer.  The library never frees caller memory and
+ *   performs no allocation on the call path, except that the first call for
+ *   a given tile count and variant uploads that plan into a library-owned
+ *   device arena that lives until spdinv_release_plans() or process exit.
+ * - Work is enqueued on `stream` and the call returns without waiting, unless
+ *   a host report is requested.
+ * - Return value: 0 = enqueued; -i = the i-th argument is invalid (checked on
+ *   the host, nothing enqueued); SPDINV_ERR_WORKSPACE = work_bytes too small;
+ *   SPDINV_ERR_HIP = a HIP runtime call failed; SPDINV_ERR_TIMEOUT = the
+ *   device scheduler gave up waiting (reported only when a host report was
+ *   requested).
+ * - Numerical failure is reported asynchronously through `d_info` (device
+ *   int, may be NULL), with the LAPACK xPOTRF meaning: k > 0 when the leading
+ *   minor of order k is not positive definite (the contents of A are then
+ *   unspecified).  n = 0 returns 0 at once.
+ */
+#ifndef SPDINV_H
+#define SPDINV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* hipStream_t without the HIP headers */
+typedef struct ihipStream_t* spdinv_stream_t;
+
+enum {
+  SPDINV_ERR_WORKSPACE = 1,
+  SPDINV_ERR_HIP = 2,
+  SPDINV_ERR_TIMEOUT = 3,
+  SPDINV_ERR_UNSUPPORTED = 4
+};
+
+typedef enum {
+  SPDINV_FP64 = 0,       /* every tile task in binary64 */
+  SPDINV_FP32 = 1,       /* reserved */
+  SPDINV_MIXED_FP32 = 2, /* reserved */
+  SPDINV_MIXED_BF16 = 3  /* reserved */
+} spdinv_mode;
+
+typedef struct {
+  int nb;          /* tile order; 0 = library choice.  Supported: 128        */
+  int pipelined;   /* 1 = one DAG over the three steps (default); 0 = barriers
+                      between steps (Section 3, "Pipelining")                 */
+  int renamed;     /* 1 = out-of-place variant with copies B = L and C = L^{-1}
+                      (default, Section 3 "Array renaming"); 0 = in place     */
+  int loop_order;  /* 0 = UDU (default), 1 = UUU (Section 3, "Loop reversal") */
+  int trtri_first; /* 0 = LAPACK 3.2.1 order in step 2 (default); 1 = TRTRI(j)
+                      at the head of iteration j                              */
+  int workers;     /* 0 = every resident workgroup; > 0 caps the persistent
+                      grid (1 = program order on one worker)                  */
+  int fill_upper;  /* 1 = also write the strictly upper triangle (mirror)     */
+  int trace;       /* 1 = record per-task timestamps (see spdinv_trace_*)    */
+  int max_refine;  /* reserved for mixed modes                                */
+  double refine_tol;
+} spdinv_opts;
+
+typedef struct {
+  int info;            /* as d_info */
+  int status;          /* 0, or SPDINV_ERR_TIMEOUT */
+  int nb;              /* tile order used */
+  int tiles;           /* t = ceil(n / nb) */
+  long long tasks;     /* tasks executed */
+  int critical_path;   /* critical path of the executed DAG, in tasks */
+  int workers;         /* persistent workgroups launched */
+} spdinv_report;
+
+/* Fills `opts` with the defaults. */
+void spdinv_default_opts(spdinv_opts* opts);
+
+/* Bytes of device workspace that spd_inverse needs for order n.  The
+   workspace holds the three tile copies (A, B, C), the inverted diagonal
+   tiles and the scheduler state. */
+size_t spd_inverse_workspace_bytes(int n, spdinv_mode mode, const spdinv_opts* opts);
+
+/*
+ * A <- A^{-1} for one SPD matrix (Algorithm 1 with the variants of Section 3).
+ *   n        order (>= 0)
+ *   A        device, column-major, lda >= max(1,n); lower triangle read and
+ *            overwritten with the lower triangle of A^{-1}
+ *   work     device workspace of at least spd_inverse_workspace_bytes bytes
+ *            (any contents on entry; clobbered)
+ *   stream   HIP stream (NULL = default stream)
+ *   opts     host, may be NULL (defaults)
+ *   d_info   device int or NULL; receives INFO (0 on success)
+ *   report   host or NULL; when given, the call waits for the stream and
+ *            fills it (INFO is then also returned through report->info)
+ */
+int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t work_bytes,
+                spdinv_stream_t stream, const spdinv_opts* opts, int* d_info,
+                spdinv_report* report);
+
+/* Frees every cached plan (device arena and host tables). */
+void spdinv_release_plans(void);
+
+/* ---- planner introspection (host only; no GPU needed) -------------------- */
+
+typedef struct {
+  long long tasks;
+  long long edges;
+  long long count[16];   /* tasks per kind, indexed by the SPDINV_TASK_* ids */
+  int cp_step[3];        /* critical path of each step's own DAG (Table 1)   */
+  int cp_unpipelined;    /* sum of the three                                  */
+  int cp_plan;           /* critical path of the DAG the plan executes        */
+} spdinv_plan_stats;
+
+enum {
+  SPDINV_TASK_NOP = 0, SPDINV_TASK_SYRK1 = 1, SPDINV_TASK_POTRF = 2, SPDINV_TASK_GEMM1 = 3,
+  SPDINV_TASK_TRSM1 = 4, SPDINV_TASK_TRTRI = 5, SPDINV_TASK_TRMM2L = 6, SPDINV_TASK_GEMM2 = 7,
+  SPDINV_TASK_TRSM2R = 8, SPDINV_TASK_TRMM3 = 9, SPDINV_TASK_LAUUM = 10, SPDINV_TASK_GEMM3 = 11,
+  SPDINV_TASK_SYRK3 = 12
+};
+
+/* Builds (without caching) the plan for t tiles per side and returns its
+   statistics.  Returns 0, or -1 for t < 1 or t > 1024. */
+int spdinv_plan_stats_get(int t, const spdinv_opts* opts, spdinv_plan_stats* out);
+
+/*
+ * Exports a plan for inspection: per task (program order) 8 int32 fields
+ *   kind, out, a, b, copy, aux, succ_begin, succ_end
+ * (tile indices into the pool layout: A tiles [0,T), B [T,2T), C [2T,3T),
+ * inverted diagonal tiles [3T, 3T+t), T = t(t+1)/2, lower tile (i,j) at
+ * i(i+1)/2+j), the successor array, the step of each task, its packed paper
+ * indices (i<<20 | j<<10 | k) and the device dispatch order.  Pass NULL
+ * buffers to query the sizes (ntasks, nsucc).  `workers` sizes the
+ * list-scheduling simulation that produces the order.
+ */
+int spdinv_plan_export(int t, const spdinv_opts* opts, int workers, int32_t* tasks8,
+                       int32_t* succ, int32_t* step, int32_t* idx, int32_t* order,
+                       long long* ntasks, long long* nsucc);
+
+/* ---- per-task trace (opts.trace = 1) -------------------------------------- */
+/* Copies the per-task trace that the last spd_inverse call with
+   opts->trace = 1 left in its workspace `work` (device) into `host`: 4 int64
+   per task in plan order (worker, claim, start, end), the times in ticks of
+   the device's constant 100 MHz real-time counter; start is the moment the
+   task's dependencies were satisfied.  n and opts must be those of that call.
+   Synchronous.  Returns the number of tasks copied (at most max_tasks) or a
+   negative value on error. */
+long long spdinv_trace_copy(const void* work, int n, const spdinv_opts* opts, int64_t* host,
+                            long long max_tasks);
+
+/* ---- kernel timing --------------------------------------------------------- */
+/* enable != 0: from now on every spd_inverse call records a pair of HIP events
+   on its stream immediately around the launch of the scheduler kernel (the
+   kernel that executes every tile task).  enable = 0 stops recording.  Both
+   discard what was recorded so far.  Returns 0. */
+int spdinv_kernel_timer(int enable);
+/* Waits for the recorded events, returns the summed scheduler-kernel time in
+   milliseconds over the launches recorded since the last read (their count
+   in *launches if non-NULL) and discards them.  Negative on a HIP error. */
+double spdinv_kernel_timer_read(long long* launches);
+
+/* Library version string. */
+const char* spdinv_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPDINV_H */

@@ -1,0 +1,146 @@
+"""MI355X-native tile inversion of symmetric positive definite matrices.
+
+The package is a thin Python layer over ``libspdinv.so`` (C-ABI in
+``include/spdinv.h``).  PyTorch provides device memory and streams; every
+step of the inversion runs in the library's HIP kernels.
+
+Main entry points
+-----------------
+``spd_inverse(a)``      full symmetric A^{-1} of a CUDA float64 tensor
+``spd_inverse_(a_cm)``  in place on a column-major view (lower triangle)
+``plan_stats(t)``       planner statistics (critical paths of Table 1)
+``plan_export(t)``      the task DAG the device executes
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import LibraryNotBuilt, load, make_opts, TASK_NAMES  # noqa: F401
+
+__all__ = ["spd_inverse", "spd_inverse_", "workspace_bytes", "plan_stats", "plan_export",
+           "SpdInverseError", "NotPositiveDefinite"]
+
+
+class SpdInverseError(RuntimeError):
+    pass
+
+
+class NotPositiveDefinite(SpdInverseError):
+    def __init__(self, info: int):
+        super().__init__(f"leading minor of order {info} is not positive definite")
+        self.info = info
+
+
+def _stream_ptr(device) -> int:
+    import torch
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def workspace_bytes(n: int, **opts) -> int:
+    o = make_opts(**opts)
+    return int(load().spd_inverse_workspace_bytes(int(n), _lib.SPDINV_FP64, ctypes.byref(o)))
+
+
+def spd_inverse_(a_cm, *, work=None, report: bool = False, info=None, **opts):
+    """A <- A^{-1} in place on a column-major CUDA float64 view.
+
+    ``a_cm`` must have strides (1, ld) with ld >= n (e.g. ``x.t()`` of a
+    row-major tensor).  Its lower triangle in column-major indexing, i.e.
+    ``a_cm[i, j]`` for i >= j, is read and replaced.  ``work`` may be a
+    preallocated uint8 CUDA tensor of at least ``workspace_bytes`` bytes.
+    ``info`` may be a CUDA int32 tensor of one element receiving INFO.  With
+    ``report=True`` the call synchronises and returns the library report as a
+    dict (raising NotPositiveDefinite on INFO > 0).
+    """
+    import torch
+    if a_cm.dtype != torch.float64 or not a_cm.is_cuda or a_cm.dim() != 2:
+        raise TypeError("expected a 2-D CUDA float64 tensor")
+    n = a_cm.shape[0]
+    if a_cm.shape[1] != n:
+        raise ValueError("matrix must be square")
+    if n > 1 and a_cm.stride(0) != 1:
+        raise ValueError("expected a column-major view (stride(0) == 1)")
+    lda = max(1, a_cm.stride(1) if n > 1 else max(1, n))
+    lib = load()
+    o = make_opts(**opts)
+    need = int(lib.spd_inverse_workspace_bytes(n, _lib.SPDINV_FP64, ctypes.byref(o)))
+    if work is None:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=a_cm.device)
+    elif work.numel() * work.element_size() < need:
+        raise ValueError(f"workspace too small: need {need} bytes")
+    rep = _lib.Report()
+    info_ptr = info.data_ptr() if info is not None else None
+    rc = lib.spd_inverse(n, a_cm.data_ptr(), lda, _lib.SPDINV_FP64, work.data_ptr(), need,
+                         _stream_ptr(a_cm.device), ctypes.byref(o), info_ptr,
+                         ctypes.byref(rep) if report else None)
+    if rc != 0:
+        raise SpdInverseError(f"spd_inverse returned {rc}")
+    if report:
+        r = {f: getattr(rep, f) for f, _ in _lib.Report._fields_}
+        if r["info"] > 0:
+            raise NotPositiveDefinite(r["info"])
+        return r
+    return None
+
+
+def spd_inverse(a, **opts):
+    """Full symmetric A^{-1} of a CUDA float64 tensor (lower triangle read)."""
+    import torch
+    n = a.shape[-1]
+    buf = a.t().contiguous()          # column-major storage of a: lower triangle = a's lower
+    rep = spd_inverse_(buf.t(), fill_upper=1, report=True, **opts) if n else None
+    del rep
+    return buf.t().contiguous() if n else torch.empty_like(a)
+
+
+def plan_stats(t: int, **opts) -> dict:
+    o = make_opts(**opts)
+    st = _lib.PlanStats()
+    if load().spdinv_plan_stats_get(int(t), ctypes.byref(o), ctypes.byref(st)) != 0:
+        raise ValueError("invalid tile count")
+    return {"tasks": st.tasks, "edges": st.edges,
+            "count": {TASK_NAMES[k]: st.count[k] for k in range(len(TASK_NAMES))},
+            "cp_step": list(st.cp_step), "cp_unpipelined": st.cp_unpipelined,
+            "cp_plan": st.cp_plan}
+
+
+def plan_export(t: int, workers: int = 1, **opts) -> dict:
+    """The plan as numpy arrays: tasks (ntasks x 8 int32), succ, step, idx, order."""
+    lib = load()
+    o = make_opts(**opts)
+    nt, ns = ctypes.c_longlong(), ctypes.c_longlong()
+    if lib.spdinv_plan_export(int(t), ctypes.byref(o), int(workers), None, None, None, None, None,
+                              ctypes.byref(nt), ctypes.byref(ns)) != 0:
+        raise ValueError("invalid tile count")
+    tasks = np.zeros((nt.value, 8), dtype=np.int32)
+    succ = np.zeros(max(ns.value, 1), dtype=np.int32)
+    step = np.zeros(nt.value, dtype=np.int32)
+    idx = np.zeros(nt.value, dtype=np.int32)
+    order = np.zeros(nt.value, dtype=np.int32)
+    p = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
+    lib.spdinv_plan_export(int(t), ctypes.byref(o), int(workers), p(tasks), p(succ), p(step),
+                           p(idx), p(order), None, None)
+    return {"tasks": tasks, "succ": succ[:ns.value], "step": step, "idx": idx, "order": order,
+            "t": int(t), "T": t * (t + 1) // 2}
+
+
+def trace(work, n: int, **opts) -> np.ndarray:
+    """Per-task trace left in ``work`` by a call with trace=1:
+    int64 rows (worker, claim, start, end), ticks of the 100 MHz device clock,
+    indexed by task (plan order)."""
+    lib = load()
+    o = make_opts(**opts)
+    t = -(-int(n) // 128)
+    nt = plan_stats(t, **{k: v for k, v in opts.items()
+                          if k in ("renamed", "loop_order", "pipelined", "trtri_first")})["tasks"] + 2
+    buf = np.zeros((nt, 4), dtype=np.int64)
+    import torch
+    torch.cuda.synchronize()
+    got = lib.spdinv_trace_copy(work.data_ptr(), int(n), ctypes.byref(o),
+                                buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), nt)
+    if got < 0:
+        raise SpdInverseError("no trace available")
+    return buf[:got]

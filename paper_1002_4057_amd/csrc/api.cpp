@@ -1,0 +1,382 @@
+// C-ABI of the spdinv library: argument checking, plan cache, workspace
+// layout and the launch sequence of one inversion.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "device.hpp"
+#include "plan.hpp"
+#include "spdinv.h"
+
+using namespace spdinv;
+
+namespace {
+
+// Relative durations of the task kinds, used only to order the dispatch list
+// (list-scheduling simulation); a 128^3 tile product is the unit.
+const double kCost[K_COUNT] = {
+    0.0,   // NOP
+    1.0,   // SYRK1
+    2.0,   // POTRF (factor + inverse of the factor tile)
+    1.0,   // GEMM1
+    1.0,   // TRSM1
+    0.1,   // TRTRI (copy)
+    1.0,   // TRMM2L
+    1.0,   // GEMM2
+    1.0,   // TRSM2R
+    1.0,   // TRMM3
+    1.0,   // LAUUM
+    1.0,   // GEMM3
+    1.0,   // SYRK3
+};
+
+struct Key {
+  int device, t, renamed, loop_order, pipelined, trtri_first, workers;
+  bool operator<(const Key& o) const {
+    return std::tie(device, t, renamed, loop_order, pipelined, trtri_first, workers) <
+           std::tie(o.device, o.t, o.renamed, o.loop_order, o.pipelined, o.trtri_first, o.workers);
+  }
+};
+
+struct DevPlan {
+  Plan host;
+  void* arena = nullptr;
+  DevTask* d_tasks = nullptr;
+  int32_t* d_succ = nullptr;
+  int32_t* d_order = nullptr;
+  int32_t* d_indeg0 = nullptr;
+};
+
+std::mutex g_mu;
+std::map<Key, std::unique_ptr<DevPlan>> g_plans;
+std::map<int, int> g_grid;  // device -> persistent workgroups
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+spdinv_opts defaults() {
+  spdinv_opts o;
+  std::memset(&o, 0, sizeof(o));
+  o.nb = 0;
+  o.pipelined = 1;
+  o.renamed = 1;
+  o.loop_order = 0;
+  o.trtri_first = 0;
+  o.workers = 0;
+  o.fill_upper = 0;
+  o.trace = 0;
+  o.max_refine = 0;
+  o.refine_tol = 0.0;
+  return o;
+}
+
+int tiles_for(int n) { return (n + NB - 1) / NB; }
+
+long long task_count(int t) {
+  const long long tt = t;
+  return 3 * (tt * (tt - 1) * (tt - 2) / 6) + 6 * (tt * (tt - 1) / 2) + 3 * tt + 2;
+}
+
+struct Layout {
+  size_t pool, indeg, ctrl, trace, total;
+};
+
+Layout layout(int n, const spdinv_opts& o) {
+  Layout L;
+  const int t = tiles_for(n);
+  const long long nt = task_count(t);
+  L.pool = 0;
+  L.indeg = align_up((size_t)pool_tiles(t) * NB * NB * sizeof(double), 256);
+  L.ctrl = L.indeg + align_up((size_t)nt * sizeof(int32_t), 256);
+  L.trace = L.ctrl + align_up(CTRL_WORDS * sizeof(int32_t), 256);
+  L.total = L.trace + (o.trace ? align_up((size_t)nt * 4 * sizeof(long long), 256) : 0);
+  return L;
+}
+
+int check_opts(const spdinv_opts& o) {
+  if (o.nb != 0 && o.nb != NB) return 1;
+  if (o.loop_order < 0 || o.loop_order > 1) return 1;
+  if (o.workers < 0) return 1;
+  return 0;
+}
+
+int grid_for(int device, const spdinv_opts& o) {
+  int g;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_grid.find(device);
+    if (it != g_grid.end()) {
+      g = it->second;
+    } else {
+      int cus = 0;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+          cus <= 0)
+        cus = 1;
+      g = cus * sched_blocks_per_cu();
+      g_grid[device] = g;
+    }
+  }
+  if (o.workers > 0 && o.workers < g) g = o.workers;
+  return g;
+}
+
+DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, hipError_t* err) {
+  Key k{device, t, o.renamed ? 1 : 0, o.loop_order, o.pipelined ? 1 : 0, o.trtri_first ? 1 : 0,
+        workers};
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_plans.find(k);
+  if (it != g_plans.end()) return it->second.get();
+  std::unique_ptr<DevPlan> dp(new DevPlan);
+  PlanOptions po;
+  po.t = t;
+  po.renamed = k.renamed;
+  po.loop_order = k.loop_order;
+  po.pipelined = k.pipelined;
+  po.trtri_first = k.trtri_first;
+  build_plan(po, workers, kCost, &dp->host);
+  const Plan& p = dp->host;
+  const size_t nt = p.tasks.size();
+  const size_t o_tasks = 0;
+  const size_t o_succ = align_up(o_tasks + nt * sizeof(DevTask), 256);
+  const size_t o_order = align_up(o_succ + p.succ.size() * sizeof(int32_t) + 4, 256);
+  const size_t o_indeg = align_up(o_order + nt * sizeof(int32_t), 256);
+  const size_t bytes = align_up(o_indeg + nt * sizeof(int32_t), 256);
+  void* arena = nullptr;
+  *err = hipMalloc(&arena, bytes);
+  if (*err != hipSuccess) return nullptr;
+  char* base = (char*)arena;
+  std::vector<char> host(bytes, 0);
+  std::memcpy(host.data() + o_tasks, p.tasks.data(), nt * sizeof(DevTask));
+  if (!p.succ.empty()) std::memcpy(host.data() + o_succ, p.succ.data(), p.succ.size() * sizeof(int32_t));
+  std::memcpy(host.data() + o_order, p.order.data(), nt * sizeof(int32_t));
+  std::memcpy(host.data() + o_indeg, p.indeg.data(), nt * sizeof(int32_t));
+  *err = hipMemcpy(arena, host.data(), bytes, hipMemcpyHostToDevice);
+  if (*err != hipSuccess) {
+    (void)hipFree(arena);
+    return nullptr;
+  }
+  dp->arena = arena;
+  dp->d_tasks = (DevTask*)(base + o_tasks);
+  dp->d_succ = (int32_t*)(base + o_succ);
+  dp->d_order = (int32_t*)(base + o_order);
+  dp->d_indeg0 = (int32_t*)(base + o_indeg);
+  DevPlan* raw = dp.get();
+  g_plans[k] = std::move(dp);
+  return raw;
+}
+
+// Optional timing of the scheduler kernel: a pair of HIP events recorded on
+// the caller's stream around each scheduler launch.
+struct KernelTimer {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t used = 0;
+};
+KernelTimer g_timer;
+
+bool timer_pair(hipEvent_t* a, hipEvent_t* b) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_timer.on) return false;
+  if (g_timer.used == g_timer.ev.size()) {
+    hipEvent_t x, y;
+    if (hipEventCreate(&x) != hipSuccess) return false;
+    if (hipEventCreate(&y) != hipSuccess) return false;
+    g_timer.ev.push_back({x, y});
+  }
+  *a = g_timer.ev[g_timer.used].first;
+  *b = g_timer.ev[g_timer.used].second;
+  g_timer.used++;
+  return true;
+}
+
+long long spin_limit() {
+  const char* e = std::getenv("SPDINV_SPIN_LIMIT");
+  if (e && *e) {
+    long long v = std::atoll(e);
+    if (v > 0) return v;
+  }
+  return 20000000LL;
+}
+
+}  // namespace
+
+extern "C" {
+
+void spdinv_default_opts(spdinv_opts* opts) {
+  if (opts) *opts = defaults();
+}
+
+size_t spd_inverse_workspace_bytes(int n, spdinv_mode mode, const spdinv_opts* opts) {
+  (void)mode;
+  if (n <= 0) return 0;
+  const spdinv_opts o = opts ? *opts : defaults();
+  return layout(n, o).total;
+}
+
+int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t work_bytes,
+                spdinv_stream_t stream_, const spdinv_opts* opts, int* d_info,
+                spdinv_report* report) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  if (n < 0) return -1;
+  if (n > 0 && !A) return -2;
+  if (lda < (n > 1 ? n : 1)) return -3;
+  if (mode != SPDINV_FP64) return -4;
+  const spdinv_opts o = opts ? *opts : defaults();
+  if (check_opts(o)) return -8;
+  if (report) std::memset(report, 0, sizeof(*report));
+  if (n == 0) {
+    if (d_info) {
+      int zero = 0;
+      if (hipMemcpyAsync(d_info, &zero, sizeof(int), hipMemcpyHostToDevice, stream) != hipSuccess)
+        return SPDINV_ERR_HIP;
+      if (hipStreamSynchronize(stream) != hipSuccess) return SPDINV_ERR_HIP;
+    }
+    return 0;
+  }
+  if (!work) return -5;
+  const Layout L = layout(n, o);
+  if (work_bytes < L.total) return SPDINV_ERR_WORKSPACE;
+
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return SPDINV_ERR_HIP;
+  const int t = tiles_for(n);
+  const int grid = grid_for(device, o);
+  hipError_t err = hipSuccess;
+  DevPlan* dp = get_plan(device, t, o, grid, &err);
+  if (!dp) return SPDINV_ERR_HIP;
+  const int ntask = (int)dp->host.tasks.size();
+
+  char* w = (char*)work;
+  double* pool = (double*)(w + L.pool);
+  int32_t* indeg = (int32_t*)(w + L.indeg);
+  int32_t* ctrl = (int32_t*)(w + L.ctrl);
+  long long* trace = o.trace ? (long long*)(w + L.trace) : nullptr;
+
+  if (launch_reset(dp->d_indeg0, indeg, ntask, ctrl, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (launch_copy_in(A, lda, n, t, pool, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  SchedArgs a;
+  a.tasks = dp->d_tasks;
+  a.succ = dp->d_succ;
+  a.order = dp->d_order;
+  a.indeg = indeg;
+  a.ctrl = ctrl;
+  a.pool = pool;
+  a.trace = trace;
+  a.ntask = ntask;
+  a.tiles_T = t * (t + 1) / 2;
+  a.info_base = 0;
+  a.spin_limit = spin_limit();
+  hipEvent_t ev0, ev1;
+  const bool timed = timer_pair(&ev0, &ev1);
+  if (timed && hipEventRecord(ev0, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (launch_sched(a, grid, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (timed && hipEventRecord(ev1, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (launch_copy_out(pool, t, A, lda, n, o.fill_upper, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (launch_info_out(ctrl, d_info, stream) != hipSuccess) return SPDINV_ERR_HIP;
+
+  if (report) {
+    if (hipStreamSynchronize(stream) != hipSuccess) return SPDINV_ERR_HIP;
+    int32_t c[CTRL_WORDS];
+    if (hipMemcpy(c, ctrl, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess) return SPDINV_ERR_HIP;
+    report->info = (c[CTRL_INFO] == INT_MAX) ? 0 : c[CTRL_INFO];
+    report->status = c[CTRL_ABORT] ? SPDINV_ERR_TIMEOUT : 0;
+    report->nb = NB;
+    report->tiles = t;
+    report->tasks = c[CTRL_DONE];
+    report->critical_path = dp->host.stats.cp_plan;
+    report->workers = grid;
+    if (c[CTRL_ABORT]) return SPDINV_ERR_TIMEOUT;
+  }
+  return 0;
+}
+
+void spdinv_release_plans(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (auto& kv : g_plans)
+    if (kv.second->arena) (void)hipFree(kv.second->arena);
+  g_plans.clear();
+}
+
+static PlanOptions plan_options(int t, const spdinv_opts* opts) {
+  const spdinv_opts o = opts ? *opts : defaults();
+  PlanOptions po;
+  po.t = t;
+  po.renamed = o.renamed ? 1 : 0;
+  po.loop_order = o.loop_order;
+  po.pipelined = o.pipelined ? 1 : 0;
+  po.trtri_first = o.trtri_first ? 1 : 0;
+  return po;
+}
+
+int spdinv_plan_stats_get(int t, const spdinv_opts* opts, spdinv_plan_stats* out) {
+  if (t < 1 || t > 1024 || !out) return -1;
+  Plan p;
+  build_plan(plan_options(t, opts), 1, nullptr, &p);
+  std::memset(out, 0, sizeof(*out));
+  out->tasks = p.stats.ntasks;
+  out->edges = p.stats.nedges;
+  for (int k = 0; k < K_COUNT; ++k) out->count[k] = p.stats.count[k];
+  for (int s = 0; s < 3; ++s) out->cp_step[s] = p.stats.cp_step[s];
+  out->cp_unpipelined = p.stats.cp_unpipelined;
+  out->cp_plan = p.stats.cp_plan;
+  return 0;
+}
+
+int spdinv_plan_export(int t, const spdinv_opts* opts, int workers, int32_t* tasks8, int32_t* succ,
+                       int32_t* step, int32_t* idx, int32_t* order, long long* ntasks,
+                       long long* nsucc) {
+  if (t < 1 || t > 1024) return -1;
+  Plan p;
+  build_plan(plan_options(t, opts), workers > 0 ? workers : 1, kCost, &p);
+  if (ntasks) *ntasks = (long long)p.tasks.size();
+  if (nsucc) *nsucc = (long long)p.succ.size();
+  if (tasks8) std::memcpy(tasks8, p.tasks.data(), p.tasks.size() * sizeof(DevTask));
+  if (succ && !p.succ.empty()) std::memcpy(succ, p.succ.data(), p.succ.size() * sizeof(int32_t));
+  if (step) std::memcpy(step, p.step.data(), p.step.size() * sizeof(int32_t));
+  if (idx) std::memcpy(idx, p.idx.data(), p.idx.size() * sizeof(int32_t));
+  if (order) std::memcpy(order, p.order.data(), p.order.size() * sizeof(int32_t));
+  return 0;
+}
+
+long long spdinv_trace_copy(const void* work, int n, const spdinv_opts* opts, int64_t* host,
+                            long long max_tasks) {
+  if (!work || !host || n <= 0 || !opts || !opts->trace) return -1;
+  const Layout L = layout(n, *opts);
+  const long long nt = task_count(tiles_for(n));
+  const long long m = nt < max_tasks ? nt : max_tasks;
+  if (hipMemcpy(host, (const char*)work + L.trace, (size_t)m * 4 * sizeof(long long),
+                hipMemcpyDeviceToHost) != hipSuccess)
+    return -2;
+  return m;
+}
+
+int spdinv_kernel_timer(int enable) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_timer.on = enable != 0;
+  g_timer.used = 0;
+  return 0;
+}
+
+double spdinv_kernel_timer_read(long long* launches) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  double total = 0.0;
+  for (size_t k = 0; k < g_timer.used; ++k) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(g_timer.ev[k].second) != hipSuccess) return -1.0;
+    if (hipEventElapsedTime(&ms, g_timer.ev[k].first, g_timer.ev[k].second) != hipSuccess) return -1.0;
+    total += ms;
+  }
+  if (launches) *launches = (long long)g_timer.used;
+  g_timer.used = 0;
+  return total;
+}
+
+const char* spdinv_version(void) { return "spdinv 0.1 (gfx950, FP64 tile inverse)"; }
+
+}  // extern "C"

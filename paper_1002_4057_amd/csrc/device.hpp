@@ -1,0 +1,62 @@
+// Internal interface between the C-ABI layer (api.cpp) and the HIP kernels
+// (device.hip).  Not part of the public header.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.hpp"
+
+namespace spdinv {
+
+constexpr int NB = 128;          // tile order
+constexpr int NTHREADS = 256;    // threads per worker workgroup (4 wave64)
+
+// Scheduler control block in the caller's workspace (int32 words).
+enum Ctrl : int {
+  CTRL_TICKET = 0,   // next dispatch ticket
+  CTRL_INFO = 1,     // LAPACK-style INFO (0 = ok); min over failing pivots
+  CTRL_ABORT = 2,    // set when a worker's dependency wait timed out
+  CTRL_FAILED = 3,   // set once a diagonal factorization broke down
+  CTRL_DONE = 4,     // tasks completed
+  CTRL_WORDS = 16
+};
+
+struct SchedArgs {
+  const DevTask* tasks;
+  const int32_t* succ;
+  const int32_t* order;
+  int32_t* indeg;      // mutable in-degree counters (reset before each run)
+  int32_t* ctrl;       // Ctrl words
+  double* pool;        // tile pool
+  long long* trace;    // 4 per task, or nullptr
+  int ntask;
+  int tiles_T;         // lower tiles per copy, T = t(t+1)/2 (pool layout)
+  int info_base;       // offset added to the global pivot index in INFO
+  long long spin_limit;
+};
+
+// Resets the in-degree counters and the control block (a fill kernel, so
+// that the sequence stays capturable in a graph).
+hipError_t launch_reset(const int32_t* indeg0, int32_t* indeg, int ntask, int32_t* ctrl,
+                        hipStream_t s);
+
+// Column-major lower triangle of A -> A tiles of the pool, identity padding
+// beyond n (the padded matrix is block diagonal with an identity block, whose
+// inverse holds A^{-1} in its leading block).
+hipError_t launch_copy_in(const double* A, int lda, int n, int t, double* pool, hipStream_t s);
+
+// A tiles of the pool -> lower triangle of A (and its mirror if fill_upper).
+hipError_t launch_copy_out(const double* pool, int t, double* A, int lda, int n, int fill_upper,
+                           hipStream_t s);
+
+// Copies ctrl[CTRL_INFO] to a device int (may be nullptr: no-op).
+hipError_t launch_info_out(const int32_t* ctrl, int* d_info, hipStream_t s);
+
+// Persistent scheduler over the plan's tasks.
+hipError_t launch_sched(const SchedArgs& a, int grid, hipStream_t s);
+
+// Persistent workgroups per CU that fit for the scheduler kernel.
+int sched_blocks_per_cu();
+
+}  // namespace spdinv

@@ -1,0 +1,277 @@
+// Host-side planner: task stream of the tile SPD inverse, hazard DAG,
+// critical paths and the device dispatch order.  See plan.hpp.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <queue>
+#include <utility>
+
+namespace spdinv {
+namespace {
+
+struct Builder {
+  const PlanOptions& o;
+  int t, T;
+  Plan* p;
+  // hazard state over the paper's tile names (A, B, C copies)
+  std::vector<int32_t> last_writer;
+  std::vector<std::vector<int32_t>> readers;
+  // predecessor lists, in program order
+  std::vector<std::vector<int32_t>> preds;
+  int cur_step = 0;
+  int barrier = -1;  // barrier task that the current step's sources must follow
+
+  Builder(const PlanOptions& opt, Plan* plan) : o(opt), t(opt.t), p(plan) {
+    T = t * (t + 1) / 2;
+    last_writer.assign(3 * (size_t)T, -1);
+    readers.resize(3 * (size_t)T);
+  }
+
+  int tri(int i, int j) const { return i * (i + 1) / 2 + j; }
+  int A(int i, int j) const { return tri(i, j); }
+  int B(int i, int j) const { return T + tri(i, j); }
+  int C(int i, int j) const { return 2 * T + tri(i, j); }
+  int D(int j) const { return 3 * T + j; }
+
+  // Emits one task.  reads/writes are hazard names (A/B/C tile ids); the
+  // device operands are given separately.
+  int emit(int kind, int i, int j, int k, std::initializer_list<int> reads,
+           std::initializer_list<int> writes, int out, int a, int b, int copy, int aux) {
+    const int v = (int)p->tasks.size();
+    DevTask d;
+    d.kind = kind;
+    d.out = out;
+    d.a = a;
+    d.b = b;
+    d.copy = copy;
+    d.aux = aux;
+    d.succ_begin = d.succ_end = 0;
+    p->tasks.push_back(d);
+    p->step.push_back(cur_step);
+    p->idx.push_back(((i & 1023) << 20) | ((j & 1023) << 10) | (k & 1023));
+    std::vector<int32_t> pr;
+    for (int r : reads)
+      if (last_writer[r] >= 0) pr.push_back(last_writer[r]);  // RAW
+    for (int w : writes) {
+      if (last_writer[w] >= 0) pr.push_back(last_writer[w]);  // WAW
+      for (int rd : readers[w]) pr.push_back(rd);             // WAR
+    }
+    std::sort(pr.begin(), pr.end());
+    pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+    if (barrier >= 0) {
+      bool has_same_step = false;
+      for (int q : pr)
+        if (p->step[q] == cur_step) { has_same_step = true; break; }
+      if (!has_same_step) pr.push_back(barrier);
+    }
+    preds.push_back(std::move(pr));
+    for (int r : reads) readers[r].push_back(v);
+    for (int w : writes) {
+      last_writer[w] = v;
+      readers[w].clear();
+    }
+    return v;
+  }
+
+  // Barrier after the step just emitted: depends on that step's sinks.
+  void emit_barrier() {
+    const int v = (int)p->tasks.size();
+    std::vector<char> has_succ(v, 0);
+    for (int q = 0; q < v; ++q)
+      for (int pr : preds[q]) has_succ[pr] = 1;
+    std::vector<int32_t> pr;
+    for (int q = 0; q < v; ++q)
+      if (p->step[q] == cur_step && !has_succ[q]) pr.push_back(q);
+    DevTask d{K_NOP, -1, -1, -1, -1, -1, 0, 0};
+    p->tasks.push_back(d);
+    p->step.push_back(0);
+    p->idx.push_back(0);
+    preds.push_back(std::move(pr));
+    barrier = v;
+  }
+
+  void step1() {
+    cur_step = 1;
+    for (int j = 0; j < t; ++j) {
+      for (int k = 0; k < j; ++k)
+        emit(K_SYRK1, j, j, k, {A(j, k), A(j, j)}, {A(j, j)}, A(j, j), A(j, k), -1, -1, -1);
+      if (o.renamed)
+        emit(K_POTRF, j, j, 0, {A(j, j)}, {A(j, j), B(j, j)}, A(j, j), -1, -1, B(j, j), D(j));
+      else
+        emit(K_POTRF, j, j, 0, {A(j, j)}, {A(j, j)}, A(j, j), -1, -1, -1, D(j));
+      for (int i = j + 1; i < t; ++i)
+        for (int k = 0; k < j; ++k)
+          emit(K_GEMM1, i, j, k, {A(i, k), A(j, k), A(i, j)}, {A(i, j)}, A(i, j), A(i, k), A(j, k),
+               -1, -1);
+      for (int i = j + 1; i < t; ++i) {
+        if (o.renamed)
+          emit(K_TRSM1, i, j, 0, {A(j, j), A(i, j)}, {A(i, j), B(i, j)}, A(i, j), -1, D(j), B(i, j),
+               -1);
+        else
+          emit(K_TRSM1, i, j, 0, {A(j, j), A(i, j)}, {A(i, j)}, A(i, j), -1, D(j), -1, -1);
+      }
+    }
+  }
+
+  void trtri(int j) {
+    if (o.renamed)
+      emit(K_TRTRI, j, j, 0, {A(j, j)}, {A(j, j), C(j, j)}, A(j, j), -1, D(j), C(j, j), -1);
+    else
+      emit(K_TRTRI, j, j, 0, {A(j, j)}, {A(j, j)}, A(j, j), -1, D(j), -1, -1);
+  }
+
+  void step2() {
+    cur_step = 2;
+    const bool down = (o.loop_order == 0);  // UDU: step-2 chain runs downward
+    for (int j = t - 1; j >= 0; --j) {
+      if (o.trtri_first) trtri(j);
+      for (int i = t - 1; i > j; --i) {
+        emit(K_TRMM2L, i, j, 0, {A(i, i), A(i, j)}, {A(i, j)}, A(i, j), A(i, i), -1, -1, -1);
+        for (int s = 0; s < i - j - 1; ++s) {
+          const int k = down ? (i - 1 - s) : (j + 1 + s);
+          const int lkj = o.renamed ? B(k, j) : A(k, j);
+          emit(K_GEMM2, i, j, k, {A(i, k), lkj, A(i, j)}, {A(i, j)}, A(i, j), A(i, k), lkj, -1, -1);
+        }
+        // right multiplication by the inverse of the diagonal tile: by L_jj
+        // (solve) in the LAPACK order, by X_jj after TRTRI(j) otherwise
+        const int djj = (o.trtri_first || !o.renamed) ? A(j, j) : B(j, j);
+        if (o.renamed)
+          emit(K_TRSM2R, i, j, 0, {djj, A(i, j)}, {A(i, j), C(i, j)}, A(i, j), -1, D(j), C(i, j), -1);
+        else
+          emit(K_TRSM2R, i, j, 0, {djj, A(i, j)}, {A(i, j)}, A(i, j), -1, D(j), -1, -1);
+      }
+      if (!o.trtri_first) trtri(j);
+    }
+  }
+
+  void step3() {
+    cur_step = 3;
+    for (int i = 0; i < t; ++i) {
+      const int xii = o.renamed ? C(i, i) : A(i, i);
+      for (int j = 0; j < i; ++j)
+        emit(K_TRMM3, i, j, 0, {xii, A(i, j)}, {A(i, j)}, A(i, j), xii, -1, -1, -1);
+      emit(K_LAUUM, i, i, 0, {A(i, i)}, {A(i, i)}, A(i, i), -1, -1, -1, -1);
+      for (int j = 0; j < i; ++j)
+        for (int k = i + 1; k < t; ++k) {
+          const int xki = o.renamed ? C(k, i) : A(k, i);
+          const int xkj = o.renamed ? C(k, j) : A(k, j);
+          emit(K_GEMM3, i, j, k, {xki, xkj, A(i, j)}, {A(i, j)}, A(i, j), xki, xkj, -1, -1);
+        }
+      for (int k = i + 1; k < t; ++k) {
+        const int xki = o.renamed ? C(k, i) : A(k, i);
+        emit(K_SYRK3, i, i, k, {xki, A(i, i)}, {A(i, i)}, A(i, i), xki, -1, -1, -1);
+      }
+    }
+  }
+};
+
+inline int weight(int kind) { return kind == K_NOP ? 0 : 1; }
+
+}  // namespace
+
+void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p) {
+  *p = Plan();
+  p->opt = opt;
+  const int t = opt.t;
+  p->T = t * (t + 1) / 2;
+  Builder bld(opt, p);
+  bld.step1();
+  if (!opt.pipelined) bld.emit_barrier();
+  bld.step2();
+  if (!opt.pipelined) bld.emit_barrier();
+  bld.step3();
+
+  const int n = (int)p->tasks.size();
+  // CSR successors
+  std::vector<int32_t> outdeg(n, 0);
+  int64_t ne = 0;
+  p->indeg.assign(n, 0);
+  for (int v = 0; v < n; ++v) {
+    p->indeg[v] = (int32_t)bld.preds[v].size();
+    for (int q : bld.preds[v]) outdeg[q]++;
+    ne += (int64_t)bld.preds[v].size();
+  }
+  std::vector<int32_t> ptr(n + 1, 0);
+  for (int v = 0; v < n; ++v) ptr[v + 1] = ptr[v] + outdeg[v];
+  p->succ.assign(ne, 0);
+  std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+  for (int v = 0; v < n; ++v)
+    for (int q : bld.preds[v]) p->succ[fill[q]++] = v;
+  for (int v = 0; v < n; ++v) {
+    p->tasks[v].succ_begin = ptr[v];
+    p->tasks[v].succ_end = ptr[v + 1];
+  }
+
+  // statistics: task counts and critical paths (unit weight per task)
+  PlanStats& st = p->stats;
+  std::memset(&st, 0, sizeof(st));
+  st.ntasks = n;
+  st.nedges = ne;
+  for (int v = 0; v < n; ++v) st.count[p->tasks[v].kind]++;
+  std::vector<int32_t> lp(n, 0), ls(n, 0);
+  int cp = 0, cps[4] = {0, 0, 0, 0};
+  for (int v = 0; v < n; ++v) {  // program order is a topological order
+    int best = 0, best_s = 0;
+    for (int q : bld.preds[v]) {
+      best = std::max(best, lp[q]);
+      if (p->step[q] == p->step[v]) best_s = std::max(best_s, ls[q]);
+    }
+    lp[v] = best + weight(p->tasks[v].kind);
+    ls[v] = best_s + weight(p->tasks[v].kind);
+    cp = std::max(cp, lp[v]);
+    cps[p->step[v]] = std::max(cps[p->step[v]], ls[v]);
+  }
+  st.cp_step[0] = cps[1];
+  st.cp_step[1] = cps[2];
+  st.cp_step[2] = cps[3];
+  st.cp_unpipelined = cps[1] + cps[2] + cps[3];
+  st.cp_plan = cp;
+  st.cp_pipelined = opt.pipelined ? cp : -1;
+
+  // dispatch order: list-scheduling simulation with `workers` workers,
+  // priority = weighted bottom level (longest remaining path), ties broken by
+  // program order
+  std::vector<double> dur(n), bl(n, 0.0);
+  for (int v = 0; v < n; ++v) dur[v] = cost ? cost[p->tasks[v].kind] : (double)weight(p->tasks[v].kind);
+  for (int v = n - 1; v >= 0; --v) {
+    double m = 0.0;
+    for (int e = ptr[v]; e < ptr[v + 1]; ++e) m = std::max(m, bl[p->succ[e]]);
+    bl[v] = dur[v] + m;
+  }
+  auto cmp = [&](int x, int y) {  // max-heap on bl, then min program index
+    if (bl[x] != bl[y]) return bl[x] < bl[y];
+    return x > y;
+  };
+  std::priority_queue<int, std::vector<int>, decltype(cmp)> ready(cmp);
+  using Ev = std::pair<double, int>;
+  std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> running;
+  std::vector<int32_t> deg(p->indeg);
+  for (int v = 0; v < n; ++v)
+    if (deg[v] == 0) ready.push(v);
+  p->order.clear();
+  p->order.reserve(n);
+  double now = 0.0;
+  int busy = 0;
+  const int P = std::max(1, workers);
+  while ((int)p->order.size() < n || !running.empty()) {
+    while (busy < P && !ready.empty()) {
+      const int v = ready.top();
+      ready.pop();
+      p->order.push_back(v);
+      running.push({now + dur[v], v});
+      ++busy;
+    }
+    if (running.empty()) break;  // cannot happen for an acyclic plan
+    now = running.top().first;
+    while (!running.empty() && running.top().first <= now) {
+      const int v = running.top().second;
+      running.pop();
+      --busy;
+      for (int e = ptr[v]; e < ptr[v + 1]; ++e)
+        if (--deg[p->succ[e]] == 0) ready.push(p->succ[e]);
+    }
+  }
+}
+
+}  // namespace spdinv

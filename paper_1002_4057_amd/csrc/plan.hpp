@@ -1,0 +1,105 @@
+// Host-side planner for the tile SPD inverse.
+//
+// The paper (Section 2, Algorithm 1; Section 3) describes the inversion as a
+// sequential stream of tile tasks that a dynamic scheduler unfolds into a DAG
+// using read-after-write, write-after-read and write-after-write hazards.  The
+// planner does exactly that on the host: it emits the task stream of the
+// chosen variant in program order, each task with the tiles it reads and
+// writes (named as in the paper: A_ij, the renaming copies B_ij and C_ij),
+// derives every hazard edge, and computes critical paths and a priority order
+// for the device scheduler.
+//
+// Variants (Section 3):
+//   renamed     -- array renaming: the out-of-place variant where step 2 reads
+//                  the copy B of L and step 3 reads the copy C of L^{-1}, so
+//                  that the anti-dependences disappear.  Copies are fused into
+//                  the task that produces the final tile (weight 0).
+//   loop_order  -- loop reversal: UDU (the step-2 GEMM chain runs k downward)
+//                  or UUU (all chains upward).
+//   pipelined   -- one DAG over the three steps, or barriers between them.
+//   trtri_first -- the step-2 reading with TRTRI(j) at the head of iteration j
+//                  and the right multiplication by the inverted diagonal tile;
+//                  the default is the LAPACK 3.2.1 order (right solve with the
+//                  factor's diagonal tile, TRTRI(j) after column j).
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace spdinv {
+
+// Task kinds.  The device executes each kind as one tile operation; see
+// kernels.hip for the arithmetic of each.
+enum Kind : int32_t {
+  K_NOP = 0,     // barrier between steps (no work, weight 0)
+  K_SYRK1 = 1,   // A_jj -= A_jk A_jk^T
+  K_POTRF = 2,   // A_jj <- chol(A_jj); also D_j <- inverse of the factor tile
+  K_GEMM1 = 3,   // A_ij -= A_ik A_jk^T
+  K_TRSM1 = 4,   // A_ij <- A_ij L_jj^{-T}
+  K_TRTRI = 5,   // A_jj <- L_jj^{-1}
+  K_TRMM2L = 6,  // A_ij <- X_ii A_ij
+  K_GEMM2 = 7,   // A_ij += X_ik L_kj
+  K_TRSM2R = 8,  // A_ij <- -A_ij L_jj^{-1}
+  K_TRMM3 = 9,   // A_ij <- X_ii^T A_ij
+  K_LAUUM = 10,  // A_ii <- A_ii^T A_ii
+  K_GEMM3 = 11,  // A_ij += X_ki^T X_kj
+  K_SYRK3 = 12,  // A_ii += X_ki^T X_ki
+  K_COUNT = 13
+};
+
+struct PlanOptions {
+  int t = 1;            // tiles per side
+  int renamed = 1;
+  int loop_order = 0;   // 0 = UDU, 1 = UUU
+  int pipelined = 1;
+  int trtri_first = 0;
+};
+
+// Device task descriptor (32 bytes).  Tile fields index the tile pool:
+//   [0, T)        A tiles, T = t(t+1)/2, lower tile (i,j) at i(i+1)/2 + j
+//   [T, 2T)       B tiles (copy of L)
+//   [2T, 3T)      C tiles (copy of L^{-1})
+//   [3T, 3T+t)    D_j, inverse of the j-th diagonal factor tile
+struct DevTask {
+  int32_t kind;
+  int32_t out;   // tile updated in place
+  int32_t a;     // first operand tile (or -1)
+  int32_t b;     // second operand tile (or -1)
+  int32_t copy;  // renaming destination that receives the same result (or -1)
+  int32_t aux;   // extra output (POTRF: D_j) (or -1)
+  int32_t succ_begin;
+  int32_t succ_end;
+};
+
+struct PlanStats {
+  int64_t ntasks;
+  int64_t nedges;
+  int64_t count[K_COUNT];
+  int cp_step[3];        // critical path of each step's DAG alone (tasks)
+  int cp_unpipelined;    // sum of the step critical paths
+  int cp_pipelined;      // critical path of the single DAG over all steps
+  int cp_plan;           // critical path of the DAG this plan executes
+};
+
+struct Plan {
+  PlanOptions opt;
+  int T = 0;                       // lower tiles per copy
+  std::vector<DevTask> tasks;      // program order
+  std::vector<int32_t> step;       // step (1..3, 0 for barriers) per task
+  std::vector<int32_t> idx;        // packed (i,j,k) paper indices, 10 bits each
+  std::vector<int32_t> succ;       // CSR successor lists (by task)
+  std::vector<int32_t> indeg;      // initial in-degree per task
+  std::vector<int32_t> order;      // device dispatch order (topological)
+  PlanStats stats{};
+};
+
+// Builds the plan.  `workers` and `cost` drive the list-scheduling simulation
+// that orders the dispatch list (cost[kind] = estimated duration, any unit).
+void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* out);
+
+// Tile pool size in tiles for t tiles per side.
+inline int64_t pool_tiles(int t) {
+  int64_t T = (int64_t)t * (t + 1) / 2;
+  return 3 * T + t;
+}
+
+}  // namespace spdinv

@@ -1,0 +1,74 @@
+"""C-ABI surface (CPU only, no compute): the built library loads, exports
+every function declared in include/spdinv.h, and rejects invalid arguments
+on the host before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1002_4057_amd as spd
+from paper_1002_4057_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "spdinv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:[A-Za-z_][\w\s\*]*?)\b(spd\w+|spdinv_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_loads_and_reports_version():
+    lib = _lib.load()
+    assert b"gfx950" in lib.spdinv_version()
+
+
+def test_every_declared_symbol_is_exported():
+    lib = _lib.load()
+    names = declared_functions()
+    assert {"spd_inverse", "spd_inverse_workspace_bytes", "spdinv_plan_stats_get"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in spdinv.h but not exported"
+
+
+def test_library_links_no_oracle_code():
+    data = open(_lib.LIB_PATH, "rb").read()
+    assert b"oracle_" not in data
+
+
+def test_workspace_bytes():
+    assert spd.workspace_bytes(0) == 0
+    t = 4
+    pool = (3 * t * (t + 1) // 2 + t) * 128 * 128 * 8
+    assert spd.workspace_bytes(512) >= pool
+    assert spd.workspace_bytes(513) > spd.workspace_bytes(512)
+    assert spd.workspace_bytes(512, trace=1) > spd.workspace_bytes(512)
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 1, 1, 0), -1),     # n < 0
+    ((4, 0, 4, 0), -2),      # null A
+    ((4, 1, 3, 0), -3),      # lda < n
+    ((4, 1, 4, 7), -4),      # unknown mode
+])
+def test_invalid_arguments_rejected_on_host(args, code):
+    lib = _lib.load()
+    n, a, lda, mode = args
+    rc = lib.spd_inverse(n, a, lda, mode, None, 0, None, None, None, None)
+    assert rc == code
+
+
+def test_bad_options_rejected():
+    lib = _lib.load()
+    o = spd.make_opts(nb=96)
+    assert lib.spd_inverse(4, 1, 4, 0, 1, 1 << 30, None, ctypes.byref(o), None, None) == -8
+    o = spd.make_opts(loop_order=5)
+    assert lib.spd_inverse(4, 1, 4, 0, 1, 1 << 30, None, ctypes.byref(o), None, None) == -8
+
+
+def test_too_small_workspace_rejected():
+    lib = _lib.load()
+    assert lib.spd_inverse(512, 1, 512, 0, 1, 16, None, None, None, None) == _lib.ERR_WORKSPACE
+    assert lib.spd_inverse(512, 1, 512, 0, None, 0, None, None, None, None) == -5

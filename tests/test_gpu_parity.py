@@ -1,0 +1,247 @@
+"""GPU parity of spd_inverse (through the C-ABI) against the FP64 oracle.
+
+Tolerance: relative Frobenius error <= 1e-12 * kappa_2(A) (kappa from the
+construction or from eigvalsh), the bar stated for the FP64 path.  The
+variants that execute the same tile operations in the same per-tile order
+(pipelined or not, any worker count, in place or renamed, either step-2
+reading) must agree bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1002_4057_amd as spd
+from paper_1002_4057_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+def colmajor_device(a):
+    """Device buffer whose column-major storage is the numpy matrix a."""
+    return torch.from_numpy(np.ascontiguousarray(a.T)).to(DEV)
+
+
+def run(a, poison_upper=False, lda=None, **opts):
+    """Inverts the lower triangle of a on the GPU; returns (buffer as numpy
+    column-major full matrix, report)."""
+    n = a.shape[0]
+    ld = lda or n
+    host = np.full((ld, n), np.nan if poison_upper else 0.0)   # column-major (ld x n)
+    host[:n, :n] = np.tril(a) + (np.triu(np.full((n, n), np.nan), 1) if poison_upper else np.triu(a, 1))
+    buf = torch.from_numpy(np.ascontiguousarray(host.T)).to(DEV)  # row-major (n x ld) = col-major (ld x n)
+    view = buf.t()[:n, :]                                         # strides (1, ld)
+    rep = spd.spd_inverse_(view, report=True, **opts)
+    out = buf.cpu().numpy().T[:n, :n]
+    return out, rep
+
+
+def rel_fro(x, y):
+    return np.linalg.norm(x - y) / np.linalg.norm(y)
+
+
+def sym_from_lower(x):
+    low = np.tril(x)
+    return low + np.tril(low, -1).T
+
+
+def kappa(a):
+    ev = np.linalg.eigvalsh(a)
+    return ev[-1] / ev[0]
+
+
+def test_config0_n512_against_oracle():
+    a = inputs.wishart_shift(512, seed=0).numpy()
+    out, rep = run(a)
+    ref = oracle.spd_inverse(a)
+    assert rep["info"] == 0 and rep["status"] == 0 and rep["tiles"] == 4
+    assert rel_fro(sym_from_lower(out), ref) <= 1e-12 * kappa(a)
+    # element by element as well
+    np.testing.assert_allclose(np.tril(out), np.tril(ref), rtol=0, atol=1e-12 * kappa(a) * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 127, 128, 129, 200, 255, 257, 383, 385, 640])
+def test_ragged_sizes_against_oracle(n):
+    a = inputs.wishart_shift(n, seed=n).numpy()
+    out, rep = run(a)
+    assert rep["info"] == 0
+    assert rel_fro(sym_from_lower(out), oracle.spd_inverse(a)) <= 1e-12 * kappa(a)
+
+
+def test_tridiag_closed_form_n512():
+    n = 512
+    out, _ = run(inputs.tridiag(n))
+    i = np.arange(1, n + 1)
+    exact = np.minimum.outer(i, i) * (n + 1 - np.maximum.outer(i, i)) / (n + 1)
+    assert rel_fro(sym_from_lower(out), exact) <= 1e-12 * 1.07e5
+
+
+@pytest.mark.parametrize("n", [2, 4, 6, 8])
+def test_hilbert_exact_inverse(n):
+    import math
+    a, s = inputs.hilbert_scaled(n)
+    c = math.comb
+    exact = np.array([[(-1) ** (i + j) * (i + j - 1) * c(n + i - 1, n - j) * c(n + j - 1, n - i)
+                       * c(i + j - 2, i - 1) ** 2 for j in range(1, n + 1)]
+                      for i in range(1, n + 1)], dtype=np.float64) / s
+    out, _ = run(a)
+    assert rel_fro(sym_from_lower(out), exact) <= 1e-12 * np.linalg.cond(a)
+
+
+def test_identity_and_diagonal_exact():
+    out, _ = run(np.eye(300))
+    np.testing.assert_array_equal(np.tril(out), np.eye(300))
+    d = 4.0 ** ((np.arange(260) % 9) - 4)
+    out, _ = run(np.diag(d))
+    np.testing.assert_array_equal(np.tril(out), np.diag(1.0 / d))
+
+
+def test_upper_triangle_not_read_or_written():
+    n = 300
+    a = inputs.wishart_shift(n, seed=8).numpy()
+    clean, _ = run(a)
+    poisoned, _ = run(a, poison_upper=True)
+    np.testing.assert_array_equal(np.tril(poisoned), np.tril(clean))
+    assert np.all(np.isnan(poisoned[np.triu_indices(n, 1)]))
+
+
+def test_fill_upper_and_leading_dimension():
+    n = 260
+    a = inputs.wishart_shift(n, seed=9).numpy()
+    ref, _ = run(a)
+    full, _ = run(a, fill_upper=1, lda=n + 37)
+    np.testing.assert_array_equal(np.tril(full), np.tril(ref))
+    np.testing.assert_array_equal(full, full.T)
+
+
+@pytest.mark.parametrize("opts", [dict(pipelined=0), dict(workers=1), dict(workers=7),
+                                  dict(workers=64), dict(renamed=0), dict(trtri_first=1),
+                                  dict(renamed=0, trtri_first=1)])
+def test_variants_bit_identical(opts):
+    n = 700
+    a = inputs.wishart_shift(n, seed=10).numpy()
+    ref, _ = run(a)
+    out, rep = run(a, **opts)
+    assert rep["status"] == 0
+    np.testing.assert_array_equal(np.tril(out), np.tril(ref))
+
+
+def test_uuu_within_tolerance():
+    n = 700
+    a = inputs.wishart_shift(n, seed=10).numpy()
+    out, _ = run(a, loop_order=1)
+    assert rel_fro(sym_from_lower(out), oracle.spd_inverse(a)) <= 1e-12 * kappa(a)
+
+
+def test_repeated_calls_deterministic_and_workspace_reuse():
+    n = 513
+    a = inputs.wishart_shift(n, seed=12).numpy()
+    buf0 = colmajor_device(a)
+    need = spd.workspace_bytes(n)
+    work = torch.full((need,), 0x7F, dtype=torch.uint8, device=DEV)   # garbage on entry
+    outs = []
+    for _ in range(3):
+        b = buf0.clone()
+        spd.spd_inverse_(b.t(), work=work)
+        torch.cuda.synchronize()
+        outs.append(b.cpu().numpy().T)
+    for o in outs[1:]:
+        np.testing.assert_array_equal(np.tril(o), np.tril(outs[0]))
+
+
+@pytest.mark.parametrize("k", [1, 5, 128, 129, 300])
+def test_info_not_positive_definite(k):
+    n = 384
+    d = np.ones(n)
+    d[k - 1] = -1.0
+    a = np.diag(d)
+    with pytest.raises(spd.NotPositiveDefinite) as e:
+        run(a)
+    assert e.value.info == k
+    # asynchronous INFO through a device int
+    buf = colmajor_device(a)
+    info = torch.full((1,), -7, dtype=torch.int32, device=DEV)
+    spd.spd_inverse_(buf.t(), info=info)
+    assert int(info.item()) == k
+
+
+def test_info_nan_input():
+    a = inputs.wishart_shift(200, seed=13).numpy()
+    a[150, 150] = np.nan
+    with pytest.raises(spd.NotPositiveDefinite) as e:
+        run(a)
+    assert e.value.info == 151
+
+
+def test_n_zero():
+    buf = torch.empty((0, 0), dtype=torch.float64, device=DEV)
+    info = torch.full((1,), -7, dtype=torch.int32, device=DEV)
+    spd.spd_inverse_(buf, info=info)
+    assert int(info.item()) == 0
+
+
+def test_spd_inverse_wrapper_full_symmetric():
+    a = inputs.wishart_shift(333, seed=14)
+    x = spd.spd_inverse(a.to(DEV)).cpu().numpy()
+    np.testing.assert_array_equal(x, x.T)
+    assert rel_fro(x, oracle.spd_inverse(a.numpy())) <= 1e-12 * kappa(a.numpy())
+
+
+def test_spectrum_kappa_1e10_against_analytic():
+    n = 1024
+    a, q, lam = inputs.spectrum(n, 1e10, seed=2, return_factors=True)
+    x = spd.spd_inverse(a.to(DEV)).cpu()
+    ref = inputs.analytic_inverse(q, lam)
+    assert rel_fro(x.numpy(), ref.numpy()) <= 1e-12 * 1e10
+    assert rel_fro(x.numpy(), oracle.spd_inverse(a.numpy())) <= 1e-12 * 1e10
+
+
+def test_trace_records_every_task():
+    n = 640
+    a = inputs.wishart_shift(n, seed=15).numpy()
+    buf = colmajor_device(a)
+    need = spd.workspace_bytes(n, trace=1)
+    work = torch.empty(need, dtype=torch.uint8, device=DEV)
+    rep = spd.spd_inverse_(buf.t(), work=work, trace=1, report=True)
+    tr = spd.trace(work, n, trace=1)
+    nt = rep["tasks"]
+    assert tr.shape[0] >= nt
+    tr = tr[:nt]
+    assert np.all(tr[:, 2] >= tr[:, 1]) and np.all(tr[:, 3] >= tr[:, 2])
+    assert np.all((tr[:, 0] >= 0) & (tr[:, 0] < rep["workers"]))
+    # dependencies respected in time: a task starts after each predecessor ends
+    p = spd.plan_export(5, workers=rep["workers"])
+    for v in range(len(p["tasks"])):
+        for s in p["succ"][p["tasks"][v, 6]:p["tasks"][v, 7]]:
+            assert tr[s, 2] >= tr[v, 3] - 2   # clock granularity
+
+
+@pytest.mark.parametrize("n", [8192])
+def test_bench_size_against_analytic_inverse(n):
+    """The benchmark workload at full size (kappa = 1e4), same launch
+    configuration as bench.py: parity against Q diag(1/lambda) Q^T."""
+    a, q, lam = inputs.spectrum(n, 1e4, seed=0, device=DEV, return_factors=True)
+    x = spd.spd_inverse(a)
+    ref = inputs.analytic_inverse(q, lam)
+    err = (torch.linalg.norm(x - ref) / torch.linalg.norm(ref)).item()
+    assert err <= 1e-12 * 1e4
+    eye = torch.eye(n, dtype=torch.float64, device=DEV)
+    res = (torch.linalg.norm(eye - a @ x) / torch.linalg.norm(eye)).item()
+    assert res <= 1e-12 * 1e4
+
+
+def test_scheduler_wait_timeout_is_reported(monkeypatch):
+    """A tiny bound on the scheduler's own dependency wait (set from the host)
+    makes workers give up; the kernel still drains and the call reports the
+    timeout instead of hanging."""
+    n = 1024
+    a = inputs.wishart_shift(n, seed=16).numpy()
+    monkeypatch.setenv("SPDINV_SPIN_LIMIT", "1")
+    with pytest.raises(spd.SpdInverseError) as e:
+        run(a)
+    assert "returned 3" in str(e.value)
+    monkeypatch.delenv("SPDINV_SPIN_LIMIT")
+    out, rep = run(a)
+    assert rep["status"] == 0
+    assert rel_fro(sym_from_lower(out), oracle.spd_inverse(a)) <= 1e-12 * kappa(a)
