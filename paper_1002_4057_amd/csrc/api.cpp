@@ -201,7 +201,7 @@ long long spin_limit() {
     long long v = std::atoll(e);
     if (v > 0) return v;
   }
-  return 20000000LL;
+  return 2000000000LL;  // 20 s
 }
 
 }  // namespace

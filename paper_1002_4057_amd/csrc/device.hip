@@ -105,7 +105,7 @@ __device__ __forceinline__ void panel_store(double* __restrict__ S, int k0, cons
 // or B: every operand read precedes the first store.  copy (may be null)
 // receives the same result.
 // Waves form a 2 x 2 grid of 64 x 64 output blocks, each a 4 x 4 array of
-// 16 x 16 MFMA accumulators (lane l holds rows 4*(l/16)..+3 of column l%16).
+// 16 x 16 MFMA accumulators.
 // ---------------------------------------------------------------------------
 template <bool TA, bool TB, bool MA, bool MB, bool LOWER, bool NEG, bool ACC>
 __device__ __forceinline__ void tile_mma(double* C, const double* A, const double* B, double* copy,
@@ -116,16 +116,20 @@ __device__ __forceinline__ void tile_mma(double* C, const double* A, const doubl
   const int lr = lane & 15, lk = lane >> 4;
   const bool active = !(LOWER && wm == 0 && wn == 1);
 
+  // v_mfma_f64_16x16x4(x, y, d): d[i][j] += sum_k x[i][k] y[k][j] with x[i][k]
+  // from lane i+16k, y[k][j] from lane j+16k, and d[i][j] in register r = i/4
+  // of lane j + 16*(i%4).  The operands are passed as (op(B) block, op(A)
+  // block), so that d is the transposed 16x16 output block: lane l, register
+  // r holds output row (l%16) of column (l/16) + 4r, and a group of 16 lanes
+  // covers 16 consecutive rows of one column (one 128-byte segment).
   d4 acc[4][4];
   if (ACC) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const double* p = C + (wm * 64 + i * 16 + 4 * lk) + (size_t)NB * (wn * 64 + j * 16 + lr);
-        const d2 lo = *reinterpret_cast<const d2*>(p);
-        const d2 hi = *reinterpret_cast<const d2*>(p + 2);
-        acc[i][j] = d4{lo.x, lo.y, hi.x, hi.y};
+        const double* p = C + (wm * 64 + i * 16 + lr) + (size_t)NB * (wn * 64 + j * 16 + lk);
+        acc[i][j] = d4{p[0], p[4 * NB], p[8 * NB], p[12 * NB]};
       }
   } else {
 #pragma unroll
@@ -163,7 +167,7 @@ __device__ __forceinline__ void tile_mma(double* C, const double* A, const doubl
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
       }
     }
     if (c + 1 < NCH) {
@@ -179,17 +183,11 @@ __device__ __forceinline__ void tile_mma(double* C, const double* A, const doubl
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const size_t off = (wm * 64 + i * 16 + 4 * lk) + (size_t)NB * (wn * 64 + j * 16 + lr);
-      d2 lo, hi;
-      lo.x = acc[i][j][0];
-      lo.y = acc[i][j][1];
-      hi.x = acc[i][j][2];
-      hi.y = acc[i][j][3];
-      *reinterpret_cast<d2*>(C + off) = lo;
-      *reinterpret_cast<d2*>(C + off + 2) = hi;
-      if (copy) {
-        *reinterpret_cast<d2*>(copy + off) = lo;
-        *reinterpret_cast<d2*>(copy + off + 2) = hi;
+      const size_t off = (wm * 64 + i * 16 + lr) + (size_t)NB * (wn * 64 + j * 16 + lk);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        C[off + (size_t)NB * 4 * r] = acc[i][j][r];
+        if (copy) copy[off + (size_t)NB * 4 * r] = acc[i][j][r];
       }
     }
 }
@@ -245,7 +243,10 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
     }
     __syncthreads();
     const double d = cb[j];
-    if (!(d > 0.0)) {  // same value in every thread: uniform exit
+    // every thread reads the same pivot; readfirstlane makes the exit visibly
+    // wave-uniform, so that the compiler keeps this loop (and its barriers)
+    // uniform instead of splitting lanes across iterations
+    if (__builtin_amdgcn_readfirstlane(!(d > 0.0) ? 1 : 0)) {
       fail = j + 1;
       break;
     }
@@ -427,60 +428,75 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
   }
 }
 
+// Persistent worker loop.  Thread 0 of each workgroup is the only one that
+// talks to the scheduler state: at the head of every iteration it first
+// releases the successors of the task the workgroup just finished (one
+// decrement of each successor's in-degree, after the release fence that all
+// threads executed), then claims the next dispatch ticket and waits until
+// that task's in-degree is zero.  Keeping both in one thread-0 region at the
+// loop head leaves the loop body (and every barrier in it) in uniform control
+// flow.
 __global__ __launch_bounds__(NTHREADS) void sched_kernel(SchedArgs g, int T) {
   __shared__ double smem[SMEM_DOUBLES];
   __shared__ int s_task;
   __shared__ int s_skip;
+  int prev = -1;  // meaningful in thread 0 only
   for (;;) {
     if (threadIdx.x == 0) {
-      long long t_claim = 0, t_start = 0;
+      if (prev >= 0) {
+        if (g.trace) g.trace[4 * (size_t)prev + 3] = now_ticks();
+        const DevTask& pt = g.tasks[prev];
+        for (int e = pt.succ_begin; e < pt.succ_end; ++e)
+          __hip_atomic_fetch_sub(&g.indeg[g.succ[e]], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&g.ctrl[CTRL_DONE], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      long long t_claim = 0;
       if (g.trace) t_claim = now_ticks();
       const int tk = __hip_atomic_fetch_add(&g.ctrl[CTRL_TICKET], 1, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
       int v = tk < g.ntask ? g.order[tk] : -1;
       if (v >= 0) {
+        // bounded wait: gives up after spin_limit ticks of the 100 MHz clock
+        const long long t0 = now_ticks();
         long long spins = 0;
         while (__hip_atomic_load(&g.indeg[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0) {
           __builtin_amdgcn_s_sleep(1);
-          ++spins;
-          if ((spins & 1023) == 0 &&
-              __hip_atomic_load(&g.ctrl[CTRL_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-            v = -1;
-            break;
-          }
-          if (spins > g.spin_limit) {
-            __hip_atomic_store(&g.ctrl[CTRL_ABORT], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            v = -1;
-            break;
+          if ((++spins & 63) == 0) {
+            if (__hip_atomic_load(&g.ctrl[CTRL_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+              v = -1;
+              break;
+            }
+            if (now_ticks() - t0 > g.spin_limit) {
+              __hip_atomic_store(&g.ctrl[CTRL_ABORT], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              v = -1;
+              break;
+            }
           }
         }
       }
       if (v >= 0) {
         fence_acquire();
         if (g.trace) {
-          t_start = now_ticks();
           g.trace[4 * (size_t)v + 0] = blockIdx.x;
           g.trace[4 * (size_t)v + 1] = t_claim;
-          g.trace[4 * (size_t)v + 2] = t_start;
+          g.trace[4 * (size_t)v + 2] = now_ticks();
         }
         s_skip = __hip_atomic_load(&g.ctrl[CTRL_FAILED], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       s_task = v;
+      prev = v;
     }
     __syncthreads();
-    const int v = s_task;
+    // s_task and s_skip hold one value for the whole workgroup; reading them
+    // through readfirstlane makes the loop exit and the task dispatch
+    // wave-uniform
+    const int v = __builtin_amdgcn_readfirstlane(s_task);
     if (v < 0) break;
     fence_acquire();
     const DevTask t = g.tasks[v];
-    if (!s_skip) run_task(t, g, smem, T);
+    if (!__builtin_amdgcn_readfirstlane(s_skip)) run_task(t, g, smem, T);
     fence_release();
     __syncthreads();
-    if (threadIdx.x == 0) {
-      if (g.trace) g.trace[4 * (size_t)v + 3] = now_ticks();
-      for (int e = t.succ_begin; e < t.succ_end; ++e)
-        __hip_atomic_fetch_sub(&g.indeg[g.succ[e]], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&g.ctrl[CTRL_DONE], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
   }
 }
 

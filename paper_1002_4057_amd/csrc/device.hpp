@@ -33,7 +33,7 @@ struct SchedArgs {
   int ntask;
   int tiles_T;         // lower tiles per copy, T = t(t+1)/2 (pool layout)
   int info_base;       // offset added to the global pivot index in INFO
-  long long spin_limit;
+  long long spin_limit;  // longest dependency wait, in 100 MHz clock ticks
 };
 
 // Resets the in-degree counters and the control block (a fill kernel, so
