@@ -270,6 +270,7 @@ int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t 
   a.trace = trace;
   a.ntask = ntask;
   a.tiles_T = t * (t + 1) / 2;
+  a.tiles = t;
   a.info_base = 0;
   a.spin_limit = spin_limit();
   hipEvent_t ev0, ev1;

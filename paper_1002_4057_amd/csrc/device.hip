@@ -23,67 +23,107 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 
-constexpr int KC = 16;                    // k-panel depth
+constexpr int KC = 32;                    // k-panel depth
 constexpr int NCH = NB / KC;              // k-panels per tile
-constexpr int LDS_STRIDE = NB + 16;       // padded row of a [k][m] panel (doubles)
+// Row stride of a [k][r] panel in LDS (doubles).  With 130, element (k, r)
+// falls in dword bank (4k + 2r) mod 64: the transposing stores (4
+// consecutive r x 16 even k per wave) cover all 64 banks, contiguous stores
+// of a k-row are conflict-free, and operand reads (16 consecutive r of 4
+// consecutive k) conflict at most 2-way.
+constexpr int LDS_STRIDE = NB + 2;
 constexpr int PANEL = KC * LDS_STRIDE;    // doubles per operand panel
-constexpr int GEMM_SMEM = 4 * PANEL;      // 2 buffers x 2 operands
-constexpr int POTRF_SMEM = 8 * NB + NB * NB;  // broadcast rows + the factor tile
+constexpr int GEMM_SMEM = 4 * PANEL;      // 2 buffers x 2 operands (133,120 bytes)
+constexpr int POTRF_SMEM = NB * NB + 12 * 256 + 8;  // tile + diagonal inverses + scratch
 constexpr int SMEM_DOUBLES = GEMM_SMEM > POTRF_SMEM ? GEMM_SMEM : POTRF_SMEM;
 constexpr size_t TILE = (size_t)NB * NB;
+constexpr int PAIRS = NB * KC / 2 / NTHREADS;  // 16-byte loads per thread per panel
 
 __device__ __forceinline__ double* tile_ptr(double* pool, int idx) {
   return pool + (size_t)idx * TILE;
 }
 
 // ---------------------------------------------------------------------------
+// Agent-coherent tile access.  A tile written by one task is read by other
+// workgroups, possibly on another XCD whose L2 is not kept coherent with the
+// writer's.  Every access to pool tiles inside the scheduler therefore uses
+// the sc1 cache policy -- the policy of agent-scope atomics -- through buffer
+// loads and stores (which also bounds-check against the 128 KiB tile): each
+// such access is coherent across the device by itself.  A task publishes its
+// results by waiting for its stores to complete before its successors'
+// counters are decremented, and a consumer needs no cache invalidation, so
+// neither the L2 write-back of a release fence nor the L2 invalidation of an
+// acquire fence is needed.
+// ---------------------------------------------------------------------------
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int CPOL_AGENT = 16;                 // sc1
+constexpr int RSRC_WORD3 = 0x00020000;         // raw dword access (gfx9 family)
+
+__device__ __forceinline__ rsrc_t tile_rsrc(const double* tile) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(tile), 0, (int)(TILE * 8),
+                                           RSRC_WORD3);
+}
+__device__ __forceinline__ d2 ld2(rsrc_t r, int elem) {
+  return __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, elem * 8, 0, CPOL_AGENT));
+}
+__device__ __forceinline__ double ld1(rsrc_t r, int elem) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, elem * 8, 0, CPOL_AGENT));
+}
+__device__ __forceinline__ void st2(rsrc_t r, int elem, d2 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, v), r, elem * 8, 0, CPOL_AGENT);
+}
+__device__ __forceinline__ void st1(rsrc_t r, int elem, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), r, elem * 8, 0, CPOL_AGENT);
+}
+
+// ---------------------------------------------------------------------------
 // k-panel staging.  A panel holds op(X)[r][k] for r = 0..127 (the output row
 // for the left operand, the output column for the right one) and k in one
 // KC-deep slice, stored in LDS as S[k * LDS_STRIDE + r].
-//   CONTIG: element (r, k) is X[r + NB*k] (r runs down a stored column)
-//  !CONTIG: element (r, k) is X[k + NB*r] (k runs down a stored column)
-// MASK treats X as lower triangular (entries above its diagonal read as 0);
-// NEG negates the panel.  Each thread moves 4 pairs of doubles per panel with
-// 16-byte global loads.
+//   contig: element (r, k) is X[r + NB*k] (r runs down a stored column)
+//  !contig: element (r, k) is X[k + NB*r] (k runs down a stored column)
+// mask treats X as lower triangular (entries above its diagonal read as 0).
+// Each thread moves PAIRS pairs of doubles per panel with 16-byte loads.
 // ---------------------------------------------------------------------------
-template <bool CONTIG>
-__device__ __forceinline__ void panel_load(const double* __restrict__ X, int k0, d2 (&r)[4]) {
+__device__ __forceinline__ void panel_load(rsrc_t X, int k0, bool contig, d2 (&r)[PAIRS]) {
   const int tid = threadIdx.x;
+  if (contig) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int p = tid + NTHREADS * q;
-    if (CONTIG) {
-      r[q] = reinterpret_cast<const d2*>(X + (size_t)NB * k0)[p];
-    } else {
-      const int rr = p >> 3, kk = (p & 7) * 2;
-      r[q] = *reinterpret_cast<const d2*>(X + k0 + kk + (size_t)NB * rr);
+    for (int q = 0; q < PAIRS; ++q) r[q] = ld2(X, NB * k0 + 2 * (tid + NTHREADS * q));
+  } else {
+#pragma unroll
+    for (int q = 0; q < PAIRS; ++q) {
+      const int p = tid + NTHREADS * q;
+      const int rr = p / (KC / 2), kk = (p % (KC / 2)) * 2;
+      r[q] = ld2(X, k0 + kk + NB * rr);
     }
   }
 }
 
-template <bool CONTIG, bool MASK, bool NEG>
-__device__ __forceinline__ void panel_store(double* __restrict__ S, int k0, const d2 (&r)[4]) {
+__device__ __forceinline__ void panel_store(double* __restrict__ S, int k0, bool contig, bool mask,
+                                            const d2 (&r)[PAIRS]) {
   const int tid = threadIdx.x;
+  if (contig) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int p = tid + NTHREADS * q;
-    double v0 = r[q].x, v1 = r[q].y;
-    if (NEG) { v0 = -v0; v1 = -v1; }
-    if (CONTIG) {
-      const int e = 2 * p, rr = e & (NB - 1), kk = e >> 7;
+    for (int q = 0; q < PAIRS; ++q) {
+      const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), kk = e >> 7;
+      d2 v = r[q];
       // stored element (row rr+s, col k0+kk); lower triangle keeps row >= col
-      if (MASK) {
-        if (rr < k0 + kk) v0 = 0.0;
-        if (rr + 1 < k0 + kk) v1 = 0.0;
+      if (mask) {
+        if (rr < k0 + kk) v.x = 0.0;
+        if (rr + 1 < k0 + kk) v.y = 0.0;
       }
-      d2 v;
-      v.x = v0;
-      v.y = v1;
       *reinterpret_cast<d2*>(S + kk * LDS_STRIDE + rr) = v;
-    } else {
-      const int rr = p >> 3, kk = (p & 7) * 2;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < PAIRS; ++q) {
+      const int p = tid + NTHREADS * q;
+      const int rr = p / (KC / 2), kk = (p % (KC / 2)) * 2;
+      double v0 = r[q].x, v1 = r[q].y;
       // stored element (row k0+kk+s, col rr)
-      if (MASK) {
+      if (mask) {
         if (k0 + kk < rr) v0 = 0.0;
         if (k0 + kk + 1 < rr) v1 = 0.0;
       }
@@ -95,26 +135,39 @@ __device__ __forceinline__ void panel_store(double* __restrict__ S, int k0, cons
 
 // ---------------------------------------------------------------------------
 // Tile product on the FP64 matrix cores.
-//   C (+)= (NEG ? -1 : 1) * op(A) * op(B),   op(A) = TA ? A^T : A,
-//                                            op(B) = TB ? B^T : B
-// ACC: accumulate into C (else overwrite).  MA/MB: the operand tile is lower
-// triangular.  LOWER: only the output blocks on or below the diagonal are
-// stored (the wave owning rows 0-63 x columns 64-127 computes but does not
-// store: it runs alone on its SIMD, so skipping its work would save no time
-// and would cost registers).  C may alias A
-// or B: every operand read precedes the first store.  copy (may be null)
-// receives the same result.
+//   C (+)= (F_NEG ? -1 : 1) * op(A) * op(B),   op(A) = F_TA ? A^T : A,
+//                                              op(B) = F_TB ? B^T : B
+// (FAST: the renamed plan's case op(A) = A, op(B) = B^T without masks)
+// F_ACC: accumulate into C (else overwrite).  F_MA/F_MB: the operand tile is
+// lower triangular.  F_LOWER: only the output blocks on or below the diagonal
+// are stored (the wave owning rows 0-63 x columns 64-127 computes but does
+// not store: it runs alone on its SIMD, so skipping its work would save no
+// time).  C may alias A or B: every operand read precedes the first store.
+// copy (may be null) receives the same result, transposed with F_COPYT.
 // Waves form a 2 x 2 grid of 64 x 64 output blocks, each a 4 x 4 array of
-// 16 x 16 MFMA accumulators.
+// 16 x 16 MFMA accumulators.  The sign is handled without touching the
+// operands: the accumulator starts from -C and the result is negated on the
+// way out (both exact), so that C - P is rounded exactly like -(-C + P).
+// The panels are double-buffered in LDS; the next panel's global loads are
+// issued before the current panel's MFMAs and consumed after them
+// (scheduling barriers keep the compiler from pulling their consumers into
+// the MFMA sequence).
 // ---------------------------------------------------------------------------
-template <bool TA, bool TB, bool MA, bool MB, bool LOWER, bool NEG, bool ACC>
-__device__ __forceinline__ void tile_mma(double* C, const double* A, const double* B, double* copy,
-                         double* smem) {
+template <bool FAST>
+__device__ __forceinline__ void tile_mma(int f, double* C, const double* A, const double* B,
+                                         double* copy, double* smem) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int wm = w & 1, wn = w >> 1;
   const int lr = lane & 15, lk = lane >> 4;
-  const bool active = !(LOWER && wm == 0 && wn == 1);
+  // FAST: op(A) = A, op(B) = B^T, no triangular masks (both operands read
+  // along contiguous columns); otherwise every flag is honoured
+  const bool a_contig = FAST || !(f & F_TA), b_contig = FAST || (f & F_TB) != 0;
+  const bool ma = !FAST && (f & F_MA) != 0, mb = !FAST && (f & F_MB) != 0;
+  const bool neg = (f & F_NEG) != 0, copy_t = (f & F_COPYT) != 0;
+  const rsrc_t rA = tile_rsrc(A), rB = tile_rsrc(B), rC = tile_rsrc(C);
+  const bool accum = (f & F_ACC) != 0;
+  const bool active = !((f & F_LOWER) && wm == 0 && wn == 1);
 
   // v_mfma_f64_16x16x4(x, y, d): d[i][j] += sum_k x[i][k] y[k][j] with x[i][k]
   // from lane i+16k, y[k][j] from lane j+16k, and d[i][j] in register r = i/4
@@ -123,14 +176,21 @@ __device__ __forceinline__ void tile_mma(double* C, const double* A, const doubl
   // r holds output row (l%16) of column (l/16) + 4r, and a group of 16 lanes
   // covers 16 consecutive rows of one column (one 128-byte segment).
   d4 acc[4][4];
-  if (ACC) {
+  if (accum) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const double* p = C + (wm * 64 + i * 16 + lr) + (size_t)NB * (wn * 64 + j * 16 + lk);
-        acc[i][j] = d4{p[0], p[4 * NB], p[8 * NB], p[12 * NB]};
+        const int off = (wm * 64 + i * 16 + lr) + NB * (wn * 64 + j * 16 + lk);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] = ld1(rC, off + NB * 4 * r);
       }
+    if (neg) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = -acc[i][j];
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -138,42 +198,44 @@ __device__ __forceinline__ void tile_mma(double* C, const double* A, const doubl
       for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
   }
 
-  d2 ra[4], rb[4];
-  panel_load<!TA>(A, 0, ra);
-  panel_load<TB>(B, 0, rb);
-  panel_store<!TA, MA, NEG>(smem, 0, ra);
-  panel_store<TB, MB, false>(smem + PANEL, 0, rb);
+  d2 ra[PAIRS], rb[PAIRS];
+  panel_load(rA, 0, a_contig, ra);
+  panel_load(rB, 0, b_contig, rb);
+  panel_store(smem, 0, a_contig, ma, ra);
+  panel_store(smem + PANEL, 0, b_contig, mb, rb);
   __syncthreads();
 
+#pragma unroll 1
   for (int c = 0; c < NCH; ++c) {
-    double* As = smem + (c & 1) * 2 * PANEL;
-    double* Bs = As + PANEL;
-    if (c + 1 < NCH) {
-      panel_load<!TA>(A, (c + 1) * KC, ra);
-      panel_load<TB>(B, (c + 1) * KC, rb);
+    const double* As = smem + (c & 1) * 2 * PANEL;
+    const double* Bs = As + PANEL;
+    const bool more = c + 1 < NCH;
+    if (more) {
+      panel_load(rA, (c + 1) * KC, a_contig, ra);
+      panel_load(rB, (c + 1) * KC, b_contig, rb);
     }
-    {
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int ks = 0; ks < KC / 4; ++ks) {
-        const double* Ar = As + (4 * ks + lk) * LDS_STRIDE + wm * 64 + lr;
-        const double* Br = Bs + (4 * ks + lk) * LDS_STRIDE + wn * 64 + lr;
-        double a[4], b[4];
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const double* Ar = As + (4 * ks + lk) * LDS_STRIDE + wm * 64 + lr;
+      const double* Br = Bs + (4 * ks + lk) * LDS_STRIDE + wn * 64 + lr;
+      double a[4], b[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          a[i] = Ar[16 * i];
-          b[i] = Br[16 * i];
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < 4; ++i) {
+        a[i] = Ar[16 * i];
+        b[i] = Br[16 * i];
       }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
     }
-    if (c + 1 < NCH) {
+    __builtin_amdgcn_sched_barrier(0);
+    if (more) {
       double* An = smem + ((c + 1) & 1) * 2 * PANEL;
-      panel_store<!TA, MA, NEG>(An, (c + 1) * KC, ra);
-      panel_store<TB, MB, false>(An + PANEL, (c + 1) * KC, rb);
+      panel_store(An, (c + 1) * KC, a_contig, ma, ra);
+      panel_store(An + PANEL, (c + 1) * KC, b_contig, mb, rb);
     }
     __syncthreads();
   }
@@ -183,245 +245,300 @@ __device__ __forceinline__ void tile_mma(double* C, const double* A, const doubl
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const size_t off = (wm * 64 + i * 16 + lr) + (size_t)NB * (wn * 64 + j * 16 + lk);
+      const int off = (wm * 64 + i * 16 + lr) + NB * (wn * 64 + j * 16 + lk);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) st1(rC, off + NB * 4 * r, neg ? -acc[i][j][r] : acc[i][j][r]);
+    }
+  if (!copy) return;
+  const rsrc_t rD = tile_rsrc(copy);
+  // renaming copy, stored as is or transposed
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = wm * 64 + i * 16 + lr, col0 = wn * 64 + j * 16 + lk;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        C[off + (size_t)NB * 4 * r] = acc[i][j][r];
-        if (copy) copy[off + (size_t)NB * 4 * r] = acc[i][j][r];
+        const double v = neg ? -acc[i][j][r] : acc[i][j][r];
+        const int col = col0 + 4 * r;
+        st1(rD, copy_t ? col + NB * row : row + NB * col, v);
       }
     }
 }
 
+// The general product (transposed or triangular operands) serves only the
+// in-place plan; it is kept out of line so that its registers do not weigh
+// on the inlined fast product.
+__device__ __attribute__((noinline)) void tile_mma_general(int f, double* C, const double* A,
+                                                           const double* B, double* copy,
+                                                           double* smem) {
+  tile_mma<false>(f, C, A, B, copy, smem);
+}
+
 // ---------------------------------------------------------------------------
-// Diagonal tile: Cholesky factor L of the lower triangle of A (right-looking,
-// one column per step) and its inverse X = L^{-1} (forward substitution of
-// L X = I, one row per step).  Thread (tr, tc) = (tid % 16, tid / 16) owns the
-// entries (tr + 16a, tc + 16b), a, b = 0..7, in registers; the pivot column
-// (factorization) or the pivot row and column (inverse) are broadcast through
-// LDS, double-buffered so that one barrier per step suffices.
-// Returns 0, or the 1-based local index of the first pivot that is not
-// positive (or NaN).  On failure nothing is stored.
+// Diagonal tile: Cholesky factor L of the lower triangle of A and its inverse
+// X = L^{-1}, blocked by 16 (tile held in LDS, column-major, ld = NB):
+//   for each 16-column panel p:
+//     one wave factors the 16 x 16 diagonal block and inverts the factor
+//     (diag16: pivots broadcast with readlane, one row per lane);
+//     L_ip = A_ip X_pp^T for the blocks below it (16x16x16 MFMA blocks);
+//     A_ij -= L_ip L_jp^T on the trailing lower blocks (MFMA).
+//   Then X by block forward substitution, one block column per wave:
+//     X_ip = -X_ii (sum_{m=p..i-1} L_im X_mp).
+// MFMA 16x16 blocks use the same lane layout as tile_mma: lane l, register r
+// holds row l%16, column l/16 + 4r of the block.
 // ---------------------------------------------------------------------------
-// Register slot of the owned entry (tr+16a, tc+16b), b <= a: only blocks on
-// or below the diagonal are held (36 doubles per thread).
-#define PK(a, b) ((a) * ((a) + 1) / 2 + (b))
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
-__device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, double* Lout, double* Lcopy,
-                                              double* Xout, double* smem) {
-  const int tid = threadIdx.x;
-  const int tr = tid & 15, tc = tid >> 4;
-  double* colbuf = smem;               // [2][NB]
-  double* rdiag = smem + 2 * NB;       // [NB]
-  double* xrow = smem + 4 * NB;        // [2][NB]
-  double* Ls = smem + 8 * NB;          // [NB * NB], the finished factor
-
-  // entry (tr+16a, tc+16b) is on or below the diagonal iff b < a, or b == a
-  // and tr >= tc
-  const bool own_lower_diag = tr >= tc;
-  double L[36];
+// Cholesky factor and inverse of the 16 x 16 block at S (column-major, ld),
+// executed by one whole wave; lane r (mod 16) holds row r.  Writes L (zeros
+// above the diagonal) back to S and X = L^{-1} to XD (16 x 16, ld 16).
+// Returns 0 or the 1-based index of the first non-positive pivot (uniform).
+__device__ __forceinline__ int diag16(double* S, int ld, double* XD) {
+  const int r = threadIdx.x & 15;
+  double row[16], x[16];
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int c = 0; c < 16; ++c) {
+    row[c] = (c <= r) ? S[r + ld * c] : 0.0;
+    x[c] = (c == r) ? 1.0 : 0.0;
+  }
 #pragma unroll
-    for (int b = 0; b <= a; ++b) {
-      const double v = Ain[(tr + 16 * a) + (size_t)NB * (tc + 16 * b)];
-      L[PK(a, b)] = (b < a || own_lower_diag) ? v : 0.0;
+  for (int k = 0; k < 16; ++k) {
+    const double d = readlane_d(row[k], k);
+    if (!(d > 0.0)) return k + 1;  // d is a scalar: uniform exit
+    const double lkk = sqrt(d);
+    const double rinv = 1.0 / lkk;
+    // column k of L: scale below the pivot
+    row[k] = (r > k) ? row[k] * rinv : ((r == k) ? lkk : row[k]);
+    // right-looking update of the trailing rows with column k
+#pragma unroll
+    for (int c = k + 1; c < 16; ++c) {
+      const double lck = readlane_d(row[k], c);
+      if (c <= r) row[c] = fma(-row[k], lck, row[c]);
     }
-
-  int fail = 0;
-  for (int j = 0; j < NB; ++j) {
-    double* cb = colbuf + (j & 1) * NB;
-    const int q = j >> 4, jl = j & 15;
-    if (tc == jl) {
+    // inverse, row k of X is final: scale it, then update the rows below
+    if (r == k) {
 #pragma unroll
-      for (int a = 0; a < 8; ++a) {
-        double v = 0.0;
-#pragma unroll
-        for (int b = 0; b <= a; ++b)
-          if (b == q) v = L[PK(a, b)];
-        cb[tr + 16 * a] = v;
-      }
+      for (int c = 0; c <= k; ++c) x[c] *= rinv;
     }
-    __syncthreads();
-    const double d = cb[j];
-    // every thread reads the same pivot; readfirstlane makes the exit visibly
-    // wave-uniform, so that the compiler keeps this loop (and its barriers)
-    // uniform instead of splitting lanes across iterations
-    if (__builtin_amdgcn_readfirstlane(!(d > 0.0) ? 1 : 0)) {
-      fail = j + 1;
-      break;
-    }
-    const double ljj = sqrt(d);
-    const double rinv = 1.0 / ljj;
-    double lk[8];
 #pragma unroll
-    for (int b = 0; b < 8; ++b) lk[b] = cb[tc + 16 * b] * rinv;
-    // trailing update of entries (i, k) with i >= k > j: row block a >= q,
-    // column block q <= b <= a; at the block edges the thread's offset decides
-    const bool row_past = tr > jl;   // row tr+16q is below the pivot
-    const bool col_past = tc > jl;   // column tc+16q is right of the pivot
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      if (a >= q) {
-        const double li = cb[tr + 16 * a] * rinv;
-#pragma unroll
-        for (int b = 0; b <= a; ++b) {
-          if (b >= q) {
-            const bool ok = (b > q || col_past) && (b < a || own_lower_diag) && (a > q || row_past);
-            if (ok) L[PK(a, b)] = fma(-li, lk[b], L[PK(a, b)]);
-          }
-        }
-        // the pivot column itself becomes column j of the factor
-        if (tc == jl) {
-#pragma unroll
-          for (int b = 0; b <= a; ++b)
-            if (b == q) {
-              if (a > q || row_past) L[PK(a, b)] = li;
-              else if (tr == jl) L[PK(a, b)] = ljj;
-            }
-        }
-      }
+    for (int c = 0; c <= k; ++c) {
+      const double xkc = readlane_d(x[c], k);
+      if (r > k) x[c] = fma(-row[k], xkc, x[c]);
     }
   }
-  if (fail) return fail;
-
-  // the factor goes to LDS (column-major, zeros above the diagonal) and to
-  // its global destinations; registers are reused for the inverse
+  if ((threadIdx.x & 63) < 16) {
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const size_t off = (tr + 16 * a) + (size_t)NB * (tc + 16 * b);
-      const double v = (b <= a) ? L[PK(a, b < a ? b : a)] : 0.0;
-      Ls[off] = v;
-      Lout[off] = v;
-      if (Lcopy) Lcopy[off] = v;
-    }
-  if (tr == tc) {
-#pragma unroll
-    for (int a = 0; a < 8; ++a) rdiag[tr + 16 * a] = 1.0 / L[PK(a, a)];
-  }
-  // inverse of the factor: row r of X is final at step r, then the rows
-  // below it are updated with column r of L
-  const bool own_diag = tr == tc;
-  double X[36];
-#pragma unroll
-  for (int a = 0; a < 8; ++a)
-#pragma unroll
-    for (int b = 0; b <= a; ++b) X[PK(a, b)] = (a == b && own_diag) ? 1.0 : 0.0;
-  __syncthreads();
-
-  for (int r = 0; r < NB; ++r) {
-    double* xr = xrow + (r & 1) * NB;
-    const int q = r >> 4;
-    const int rl = r & 15;
-    const bool col_le = tc <= rl;    // column tc+16q is at or left of r
-    if (tr == rl) {
-      const double s = rdiag[r];
-#pragma unroll
-      for (int a = 0; a < 8; ++a)
-        if (a == q) {
-#pragma unroll
-          for (int b = 0; b <= a; ++b) {
-            if (b < q || col_le) X[PK(a, b)] *= s;
-            xr[tc + 16 * b] = X[PK(a, b)];
-          }
-        }
-    }
-    __syncthreads();
-    const double* lc = Ls + (size_t)NB * r;
-    const bool row_gt = tr > rl;     // row tr+16q is below r
-    double xk[8];
-#pragma unroll
-    for (int b = 0; b < 8; ++b) xk[b] = xr[tc + 16 * b];
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      if (a >= q) {
-        const double l = lc[tr + 16 * a];
-#pragma unroll
-        for (int b = 0; b <= a; ++b) {
-          if (b <= q) {
-            const bool ok = (a > q || row_gt) && (b < q || col_le);
-            if (ok) X[PK(a, b)] = fma(-l, xk[b], X[PK(a, b)]);
-          }
-        }
-      }
+    for (int c = 0; c < 16; ++c) {
+      S[r + ld * c] = (c <= r) ? row[c] : 0.0;
+      XD[r + 16 * c] = (c <= r) ? x[c] : 0.0;
     }
   }
-
-#pragma unroll
-  for (int a = 0; a < 8; ++a)
-#pragma unroll
-    for (int b = 0; b < 8; ++b)
-      Xout[(tr + 16 * a) + (size_t)NB * (tc + 16 * b)] = (b <= a) ? X[PK(a, b < a ? b : a)] : 0.0;
   return 0;
 }
-#undef PK
 
-__device__ __forceinline__ void tile_copy2(const double* __restrict__ src, double* dst0, double* dst1) {
-  const d2* s = reinterpret_cast<const d2*>(src);
-  for (int p = threadIdx.x; p < (int)(TILE / 2); p += NTHREADS) {
-    const d2 v = s[p];
-    reinterpret_cast<d2*>(dst0)[p] = v;
-    if (dst1) reinterpret_cast<d2*>(dst1)[p] = v;
+// acc (one 16x16 block, MFMA layout) += A_blk * op(B)_blk over K = 16, with
+// A_blk[m][k] = A[m + lda*k] and op(B)_blk[k][n] = B[n + ldb*k] (tb, i.e. the
+// block B^T of a column-major B) or B[k + ldb*n] (!tb).
+__device__ __forceinline__ d4 blk_mma16(d4 acc, const double* A, int lda, const double* B, int ldb,
+                                        bool tb) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int k = 4 * kk + lk;
+    const double a = A[lr + lda * k];
+    const double b = tb ? B[lr + ldb * k] : B[k + ldb * lr];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ d4 blk_load(const double* S, int ld) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  return d4{S[lr + ld * lk], S[lr + ld * (lk + 4)], S[lr + ld * (lk + 8)], S[lr + ld * (lk + 12)]};
+}
+
+__device__ __forceinline__ void blk_store(double* S, int ld, d4 v) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) S[lr + ld * (lk + 4 * q)] = v[q];
+}
+
+// Outputs: the factor (Lout), its transpose (LcopyT, may be null), the
+// inverse of the factor (Xout) and its transpose (XoutT), each with explicit
+// zeros in the other triangle.  Returns 0, or the 1-based local index of the
+// first pivot that is not positive (or NaN); on failure nothing is stored.
+__device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, double* Lout,
+                                                         double* LcopyT, double* Xout,
+                                                         double* XoutT, double* smem) {
+  constexpr int LD = NB;
+  double* T = smem;                    // [NB * NB] the tile, column-major
+  double* XD = smem + NB * NB;         // [8][256] inverses of the diagonal blocks
+  double* SCR = XD + 8 * 256;          // [4][256] per-wave scratch block
+  int* flag = reinterpret_cast<int*>(SCR + 4 * 256);
+  const int tid = threadIdx.x, w = tid >> 6;
+  const rsrc_t rIn = tile_rsrc(Ain), rL = tile_rsrc(Lout), rX = tile_rsrc(Xout),
+               rXT = tile_rsrc(XoutT);
+
+  // load the tile: batches of independent 16-byte loads, so that their
+  // latencies overlap
+  for (int e0 = 0; e0 < NB * NB; e0 += 2 * NTHREADS * 16) {
+    d2 v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = ld2(rIn, e0 + 2 * (tid + NTHREADS * u));
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = e0 + 2 * (tid + NTHREADS * u), rr = e & (NB - 1), cc = e >> 7;
+      T[e] = (rr >= cc) ? v[u].x : 0.0;
+      T[e + 1] = (rr + 1 >= cc) ? v[u].y : 0.0;
+    }
+  }
+  __syncthreads();
+
+  for (int p = 0; p < 8; ++p) {
+    double* Dpp = T + 16 * p * (LD + 1);
+    if (w == 0) {
+      const int f = diag16(Dpp, LD, XD + 256 * p);
+      if (tid == 0) *flag = f ? 16 * p + f : 0;
+    }
+    __syncthreads();
+    const int fail = __builtin_amdgcn_readfirstlane(*flag);
+    if (fail) return fail;
+    // panel: L_ip = A_ip X_pp^T
+    for (int i = p + 1 + w; i < 8; i += 4) {
+      double* Bip = T + 16 * i + LD * 16 * p;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      acc = blk_mma16(acc, Bip, LD, XD + 256 * p, 16, true);
+      blk_store(Bip, LD, acc);
+    }
+    __syncthreads();
+    // trailing update: A_ij -= L_ip L_jp^T, p < j <= i
+    const int nb = 7 - p;
+    for (int q = w; q < nb * (nb + 1) / 2; q += 4) {
+      int i = 0;
+      while ((i + 1) * (i + 2) / 2 <= q) ++i;
+      const int j = q - i * (i + 1) / 2;
+      const int bi = p + 1 + i, bj = p + 1 + j;
+      double* Cij = T + 16 * bi + LD * 16 * bj;
+      d4 acc = -blk_load(Cij, LD);
+      acc = blk_mma16(acc, T + 16 * bi + LD * 16 * p, LD, T + 16 * bj + LD * 16 * p, LD, true);
+      blk_store(Cij, LD, -acc);
+    }
+    __syncthreads();
+  }
+
+  // the factor: global copies (and its transpose)
+  const rsrc_t rLT = tile_rsrc(LcopyT ? LcopyT : Lout);
+  for (int e = tid; e < NB * NB; e += NTHREADS) {
+    const int rr = e & (NB - 1), cc = e >> 7;
+    const double v = (rr >= cc) ? T[e] : 0.0;
+    st1(rL, e, v);
+    if (LcopyT) st1(rLT, cc + NB * rr, v);
+  }
+  __syncthreads();  // the inverse below writes the upper blocks of T
+
+  // inverse by block columns; wave w takes columns w and 7 - w.  X_mp for
+  // m > p is kept transposed in the (unused) upper block (p, m) of T.
+  double* scr = SCR + 256 * w;
+  for (int side = 0; side < 2; ++side) {
+    const int p = side ? 7 - w : w;
+    for (int i = p + 1; i < 8; ++i) {
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      // L_ip X_pp
+      acc = blk_mma16(acc, T + 16 * i + LD * 16 * p, LD, XD + 256 * p, 16, false);
+      for (int m = p + 1; m < i; ++m)  // L_im X_mp, X_mp^T stored at block (p, m)
+        acc = blk_mma16(acc, T + 16 * i + LD * 16 * m, LD, T + 16 * p + LD * 16 * m, LD, true);
+      blk_store(scr, 16, acc);
+      d4 xip = {0.0, 0.0, 0.0, 0.0};
+      xip = blk_mma16(xip, XD + 256 * i, 16, scr, 16, false);  // X_ii S
+      xip = -xip;
+      // X_ip transposed into block (p, i) of T, and to the outputs
+      const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rr = 16 * i + lr, cc = 16 * p + lk + 4 * q;
+        T[cc + LD * rr] = xip[q];
+        st1(rX, rr + NB * cc, xip[q]);
+        st1(rXT, cc + NB * rr, xip[q]);
+      }
+    }
+  }
+  // diagonal blocks and the zero triangles of the inverse
+  for (int e = tid; e < NB * NB; e += NTHREADS) {
+    const int rr = e & (NB - 1), cc = e >> 7;
+    const int bi = rr >> 4, bj = cc >> 4;
+    if (bi == bj) {
+      const double v = XD[256 * bi + (rr & 15) + 16 * (cc & 15)];
+      st1(rX, e, v);
+      st1(rXT, cc + NB * rr, v);
+    } else if (bi < bj) {
+      st1(rX, e, 0.0);
+      st1(rXT, cc + NB * rr, 0.0);
+    }
+  }
+  return 0;
+}
+
+// dst <- src for one tile; loads are issued in batches of 16 independent
+// 16-byte loads per thread so that their latencies overlap.
+__device__ __forceinline__ void tile_copy(const double* src, double* dst) {
+  const rsrc_t rs = tile_rsrc(src), rd = tile_rsrc(dst);
+#pragma unroll
+  for (int h = 0; h < (int)(TILE / 2) / (NTHREADS * 16); ++h) {
+    d2 v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = ld2(rs, 2 * (h * NTHREADS * 16 + threadIdx.x + NTHREADS * u));
+#pragma unroll
+    for (int u = 0; u < 16; ++u) st2(rd, 2 * (h * NTHREADS * 16 + threadIdx.x + NTHREADS * u), v[u]);
   }
 }
 
-__device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-__device__ __forceinline__ void fence_acquire() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+// A task's results are published when its agent-coherent stores have
+// completed: every thread waits for its outstanding memory operations before
+// the workgroup barrier that precedes the successors' counter decrements.
+__device__ __forceinline__ void stores_complete() { __builtin_amdgcn_s_waitcnt(0); }
 
 __device__ __forceinline__ long long now_ticks() {
   return (long long)__builtin_amdgcn_s_memrealtime();
 }
 
-__device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, double* smem, int T) {
+__device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, double* smem, int T,
+                                         int tiles) {
   double* P = g.pool;
+  const int kind = t.kind & 0xff, f = (t.kind >> 8) & 0xff;  // see DevTask::kind
   double* out = t.out >= 0 ? tile_ptr(P, t.out) : nullptr;
   const double* a = t.a >= 0 ? tile_ptr(P, t.a) : nullptr;
   const double* b = t.b >= 0 ? tile_ptr(P, t.b) : nullptr;
   double* cp = t.copy >= 0 ? tile_ptr(P, t.copy) : nullptr;
-  switch (t.kind) {
-    case K_SYRK1:   // A_jj -= A_jk A_jk^T
-      tile_mma<false, true, false, false, true, true, true>(out, a, a, nullptr, smem);
-      break;
-    case K_GEMM1:   // A_ij -= A_ik A_jk^T
-      tile_mma<false, true, false, false, false, true, true>(out, a, b, nullptr, smem);
-      break;
-    case K_TRSM1:   // A_ij <- A_ij D_j^T, D_j = L_jj^{-1}
-      tile_mma<false, true, false, true, false, false, false>(out, out, b, cp, smem);
-      break;
-    case K_TRMM2L:  // A_ij <- X_ii A_ij
-      tile_mma<false, false, true, false, false, false, false>(out, a, out, nullptr, smem);
-      break;
-    case K_GEMM2:   // A_ij += X_ik L_kj
-      tile_mma<false, false, false, false, false, false, true>(out, a, b, nullptr, smem);
-      break;
-    case K_TRSM2R:  // A_ij <- -A_ij D_j
-      tile_mma<false, false, false, true, false, true, false>(out, out, b, cp, smem);
-      break;
-    case K_TRMM3:   // A_ij <- X_ii^T A_ij
-      tile_mma<true, false, true, false, false, false, false>(out, a, out, nullptr, smem);
-      break;
-    case K_LAUUM:   // A_ii <- A_ii^T A_ii (lower)
-      tile_mma<true, false, true, true, true, false, false>(out, out, out, nullptr, smem);
-      break;
-    case K_GEMM3:   // A_ij += X_ki^T X_kj
-      tile_mma<true, false, false, false, false, false, true>(out, a, b, nullptr, smem);
-      break;
-    case K_SYRK3:   // A_ii += X_ki^T X_ki (lower)
-      tile_mma<true, false, false, false, true, false, true>(out, a, a, nullptr, smem);
+  switch (kind) {
+    case K_SYRK1: case K_GEMM1: case K_TRSM1: case K_TRMM2L: case K_GEMM2: case K_TRSM2R:
+    case K_TRMM3: case K_LAUUM: case K_GEMM3: case K_SYRK3:
+      // tile products; the planner chose operands and flags (Algorithm 1's
+      // operation on the renamed or in-place tiles)
+      if ((f & (F_TA | F_MA | F_MB)) == 0 && (f & F_TB))
+        tile_mma<true>(f, out, a, b, cp, smem);
+      else
+        tile_mma_general(f, out, a, b, cp, smem);
       break;
     case K_POTRF: {
       double* X = tile_ptr(P, t.aux);
-      const int f = potrf_inv_tile(out, out, cp, X, smem);
-      if (f && threadIdx.x == 0) {
+      double* Xt = tile_ptr(P, t.aux + tiles);
+      const int fl = potrf_inv_tile(out, out, cp, X, Xt, smem);
+      if (fl && threadIdx.x == 0) {
         const int jt = t.aux - 3 * T;  // diagonal tile index
-        atomicMin(&g.ctrl[CTRL_INFO], g.info_base + jt * NB + f);
+        atomicMin(&g.ctrl[CTRL_INFO], g.info_base + jt * NB + fl);
         __hip_atomic_store(&g.ctrl[CTRL_FAILED], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       break;
     }
-    case K_TRTRI:   // A_jj <- D_j (inverse made by POTRF(j))
-      tile_copy2(b, out, cp);
+    case K_TRTRI:   // A_jj <- D_j, and C_jj <- D_j^T (inverse made by POTRF(j))
+      tile_copy(a, out);
+      if (cp) tile_copy(b, cp);
       break;
     default:
       break;
@@ -431,12 +548,13 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
 // Persistent worker loop.  Thread 0 of each workgroup is the only one that
 // talks to the scheduler state: at the head of every iteration it first
 // releases the successors of the task the workgroup just finished (one
-// decrement of each successor's in-degree, after the release fence that all
-// threads executed), then claims the next dispatch ticket and waits until
-// that task's in-degree is zero.  Keeping both in one thread-0 region at the
+// decrement of each successor's in-degree, once every thread's stores of that
+// task have completed), then claims the next dispatch ticket and waits until
+// that task's in-degree is zero.  Counters and tiles are accessed with
+// agent-scope coherence, so no cache maintenance is needed.  Keeping both in one thread-0 region at the
 // loop head leaves the loop body (and every barrier in it) in uniform control
 // flow.
-__global__ __launch_bounds__(NTHREADS) void sched_kernel(SchedArgs g, int T) {
+__global__ __launch_bounds__(NTHREADS) void sched_kernel(SchedArgs g, int T, int tiles) {
   __shared__ double smem[SMEM_DOUBLES];
   __shared__ int s_task;
   __shared__ int s_skip;
@@ -475,7 +593,6 @@ __global__ __launch_bounds__(NTHREADS) void sched_kernel(SchedArgs g, int T) {
         }
       }
       if (v >= 0) {
-        fence_acquire();
         if (g.trace) {
           g.trace[4 * (size_t)v + 0] = blockIdx.x;
           g.trace[4 * (size_t)v + 1] = t_claim;
@@ -492,10 +609,9 @@ __global__ __launch_bounds__(NTHREADS) void sched_kernel(SchedArgs g, int T) {
     // wave-uniform
     const int v = __builtin_amdgcn_readfirstlane(s_task);
     if (v < 0) break;
-    fence_acquire();
     const DevTask t = g.tasks[v];
-    if (!__builtin_amdgcn_readfirstlane(s_skip)) run_task(t, g, smem, T);
-    fence_release();
+    if (!__builtin_amdgcn_readfirstlane(s_skip)) run_task(t, g, smem, T, tiles);
+    stores_complete();
     __syncthreads();
   }
 }
@@ -584,7 +700,7 @@ hipError_t launch_info_out(const int32_t* ctrl, int* d_info, hipStream_t s) {
 }
 
 hipError_t launch_sched(const SchedArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(sched_kernel, dim3(grid), dim3(NTHREADS), 0, s, a, a.tiles_T);
+  hipLaunchKernelGGL(sched_kernel, dim3(grid), dim3(NTHREADS), 0, s, a, a.tiles_T, a.tiles);
   return hipGetLastError();
 }
 

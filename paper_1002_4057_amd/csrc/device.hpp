@@ -32,6 +32,7 @@ struct SchedArgs {
   long long* trace;    // 4 per task, or nullptr
   int ntask;
   int tiles_T;         // lower tiles per copy, T = t(t+1)/2 (pool layout)
+  int tiles;           // tiles per side, t
   int info_base;       // offset added to the global pivot index in INFO
   long long spin_limit;  // longest dependency wait, in 100 MHz clock ticks
 };

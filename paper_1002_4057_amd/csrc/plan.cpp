@@ -37,10 +37,11 @@ struct Builder {
   // Emits one task.  reads/writes are hazard names (A/B/C tile ids); the
   // device operands are given separately.
   int emit(int kind, int i, int j, int k, std::initializer_list<int> reads,
-           std::initializer_list<int> writes, int out, int a, int b, int copy, int aux) {
+           std::initializer_list<int> writes, int out, int a, int b, int copy, int aux,
+           int flags = 0) {
     const int v = (int)p->tasks.size();
     DevTask d;
-    d.kind = kind;
+    d.kind = kind | (flags << 8);
     d.out = out;
     d.a = a;
     d.b = b;
@@ -91,34 +92,46 @@ struct Builder {
     barrier = v;
   }
 
+  int Dt(int j) const { return 3 * T + t + j; }
+
+  // Device operands.  The hazard names (reads/writes) are always the paper's
+  // tiles; the device may read a different tile that holds the same values
+  // (a renaming copy, or D_j / D_j^T for the inverted diagonal tile), which
+  // is safe when that tile is written by the same task that is the last
+  // writer of the paper's tile before the reader.  In the renamed plan every
+  // product reads op(A) = A and op(B) = B^T contiguously; the in-place plan
+  // uses the paper's tiles with transposes and triangular masks.
   void step1() {
     cur_step = 1;
+    const int cpt = o.renamed ? F_COPYT : 0;
     for (int j = 0; j < t; ++j) {
-      for (int k = 0; k < j; ++k)
-        emit(K_SYRK1, j, j, k, {A(j, k), A(j, j)}, {A(j, j)}, A(j, j), A(j, k), -1, -1, -1);
+      for (int k = 0; k < j; ++k)  // A_jj -= A_jk A_jk^T
+        emit(K_SYRK1, j, j, k, {A(j, k), A(j, j)}, {A(j, j)}, A(j, j), A(j, k), A(j, k), -1, -1,
+             F_TB | F_LOWER | F_NEG | F_ACC);
       if (o.renamed)
         emit(K_POTRF, j, j, 0, {A(j, j)}, {A(j, j), B(j, j)}, A(j, j), -1, -1, B(j, j), D(j));
       else
         emit(K_POTRF, j, j, 0, {A(j, j)}, {A(j, j)}, A(j, j), -1, -1, -1, D(j));
       for (int i = j + 1; i < t; ++i)
-        for (int k = 0; k < j; ++k)
+        for (int k = 0; k < j; ++k)  // A_ij -= A_ik A_jk^T
           emit(K_GEMM1, i, j, k, {A(i, k), A(j, k), A(i, j)}, {A(i, j)}, A(i, j), A(i, k), A(j, k),
-               -1, -1);
-      for (int i = j + 1; i < t; ++i) {
+               -1, -1, F_TB | F_NEG | F_ACC);
+      for (int i = j + 1; i < t; ++i) {  // A_ij <- A_ij L_jj^{-T} = A_ij D_j^T
         if (o.renamed)
-          emit(K_TRSM1, i, j, 0, {A(j, j), A(i, j)}, {A(i, j), B(i, j)}, A(i, j), -1, D(j), B(i, j),
-               -1);
+          emit(K_TRSM1, i, j, 0, {A(j, j), A(i, j)}, {A(i, j), B(i, j)}, A(i, j), A(i, j), D(j),
+               B(i, j), -1, F_TB | cpt);
         else
-          emit(K_TRSM1, i, j, 0, {A(j, j), A(i, j)}, {A(i, j)}, A(i, j), -1, D(j), -1, -1);
+          emit(K_TRSM1, i, j, 0, {A(j, j), A(i, j)}, {A(i, j)}, A(i, j), A(i, j), D(j), -1, -1,
+               F_TB);
       }
     }
   }
 
-  void trtri(int j) {
+  void trtri(int j) {  // A_jj <- D_j (and C_jj <- D_j^T)
     if (o.renamed)
-      emit(K_TRTRI, j, j, 0, {A(j, j)}, {A(j, j), C(j, j)}, A(j, j), -1, D(j), C(j, j), -1);
+      emit(K_TRTRI, j, j, 0, {A(j, j)}, {A(j, j), C(j, j)}, A(j, j), D(j), Dt(j), C(j, j), -1);
     else
-      emit(K_TRTRI, j, j, 0, {A(j, j)}, {A(j, j)}, A(j, j), -1, D(j), -1, -1);
+      emit(K_TRTRI, j, j, 0, {A(j, j)}, {A(j, j)}, A(j, j), D(j), -1, -1, -1);
   }
 
   void step2() {
@@ -127,19 +140,31 @@ struct Builder {
     for (int j = t - 1; j >= 0; --j) {
       if (o.trtri_first) trtri(j);
       for (int i = t - 1; i > j; --i) {
-        emit(K_TRMM2L, i, j, 0, {A(i, i), A(i, j)}, {A(i, j)}, A(i, j), A(i, i), -1, -1, -1);
-        for (int s = 0; s < i - j - 1; ++s) {
+        // A_ij <- X_ii L_ij
+        if (o.renamed)
+          emit(K_TRMM2L, i, j, 0, {A(i, i), A(i, j)}, {A(i, j)}, A(i, j), A(i, i), B(i, j), -1, -1,
+               F_TB);
+        else
+          emit(K_TRMM2L, i, j, 0, {A(i, i), A(i, j)}, {A(i, j)}, A(i, j), A(i, i), A(i, j), -1, -1,
+               F_MA);
+        for (int s = 0; s < i - j - 1; ++s) {  // A_ij += X_ik L_kj
           const int k = down ? (i - 1 - s) : (j + 1 + s);
-          const int lkj = o.renamed ? B(k, j) : A(k, j);
-          emit(K_GEMM2, i, j, k, {A(i, k), lkj, A(i, j)}, {A(i, j)}, A(i, j), A(i, k), lkj, -1, -1);
+          if (o.renamed)
+            emit(K_GEMM2, i, j, k, {A(i, k), B(k, j), A(i, j)}, {A(i, j)}, A(i, j), A(i, k), B(k, j),
+                 -1, -1, F_TB | F_ACC);
+          else
+            emit(K_GEMM2, i, j, k, {A(i, k), A(k, j), A(i, j)}, {A(i, j)}, A(i, j), A(i, k), A(k, j),
+                 -1, -1, F_ACC);
         }
-        // right multiplication by the inverse of the diagonal tile: by L_jj
-        // (solve) in the LAPACK order, by X_jj after TRTRI(j) otherwise
+        // A_ij <- -A_ij L_jj^{-1} = -A_ij D_j: by L_jj (solve) in the LAPACK
+        // order, by X_jj after TRTRI(j) otherwise
         const int djj = (o.trtri_first || !o.renamed) ? A(j, j) : B(j, j);
         if (o.renamed)
-          emit(K_TRSM2R, i, j, 0, {djj, A(i, j)}, {A(i, j), C(i, j)}, A(i, j), -1, D(j), C(i, j), -1);
+          emit(K_TRSM2R, i, j, 0, {djj, A(i, j)}, {A(i, j), C(i, j)}, A(i, j), A(i, j), Dt(j),
+               C(i, j), -1, F_TB | F_NEG | F_COPYT);
         else
-          emit(K_TRSM2R, i, j, 0, {djj, A(i, j)}, {A(i, j)}, A(i, j), -1, D(j), -1, -1);
+          emit(K_TRSM2R, i, j, 0, {djj, A(i, j)}, {A(i, j)}, A(i, j), A(i, j), Dt(j), -1, -1,
+               F_TB | F_NEG);
       }
       if (!o.trtri_first) trtri(j);
     }
@@ -148,25 +173,43 @@ struct Builder {
   void step3() {
     cur_step = 3;
     for (int i = 0; i < t; ++i) {
-      const int xii = o.renamed ? C(i, i) : A(i, i);
+      for (int j = 0; j < i; ++j) {  // A_ij <- X_ii^T A_ij
+        if (o.renamed)
+          emit(K_TRMM3, i, j, 0, {C(i, i), A(i, j)}, {A(i, j)}, A(i, j), C(i, i), C(i, j), -1, -1,
+               F_TB);
+        else
+          emit(K_TRMM3, i, j, 0, {A(i, i), A(i, j)}, {A(i, j)}, A(i, j), A(i, i), A(i, j), -1, -1,
+               F_TA | F_MA);
+      }
+      // A_ii <- A_ii^T A_ii (lower)
+      if (o.renamed)
+        emit(K_LAUUM, i, i, 0, {A(i, i)}, {A(i, i)}, A(i, i), C(i, i), C(i, i), -1, -1,
+             F_TB | F_LOWER);
+      else
+        emit(K_LAUUM, i, i, 0, {A(i, i)}, {A(i, i)}, A(i, i), A(i, i), A(i, i), -1, -1,
+             F_TA | F_MA | F_MB | F_LOWER);
       for (int j = 0; j < i; ++j)
-        emit(K_TRMM3, i, j, 0, {xii, A(i, j)}, {A(i, j)}, A(i, j), xii, -1, -1, -1);
-      emit(K_LAUUM, i, i, 0, {A(i, i)}, {A(i, i)}, A(i, i), -1, -1, -1, -1);
-      for (int j = 0; j < i; ++j)
-        for (int k = i + 1; k < t; ++k) {
-          const int xki = o.renamed ? C(k, i) : A(k, i);
-          const int xkj = o.renamed ? C(k, j) : A(k, j);
-          emit(K_GEMM3, i, j, k, {xki, xkj, A(i, j)}, {A(i, j)}, A(i, j), xki, xkj, -1, -1);
+        for (int k = i + 1; k < t; ++k) {  // A_ij += X_ki^T X_kj
+          if (o.renamed)
+            emit(K_GEMM3, i, j, k, {C(k, i), C(k, j), A(i, j)}, {A(i, j)}, A(i, j), C(k, i), C(k, j),
+                 -1, -1, F_TB | F_ACC);
+          else
+            emit(K_GEMM3, i, j, k, {A(k, i), A(k, j), A(i, j)}, {A(i, j)}, A(i, j), A(k, i), A(k, j),
+                 -1, -1, F_TA | F_ACC);
         }
-      for (int k = i + 1; k < t; ++k) {
-        const int xki = o.renamed ? C(k, i) : A(k, i);
-        emit(K_SYRK3, i, i, k, {xki, A(i, i)}, {A(i, i)}, A(i, i), xki, -1, -1, -1);
+      for (int k = i + 1; k < t; ++k) {  // A_ii += X_ki^T X_ki (lower)
+        if (o.renamed)
+          emit(K_SYRK3, i, i, k, {C(k, i), A(i, i)}, {A(i, i)}, A(i, i), C(k, i), C(k, i), -1, -1,
+               F_TB | F_LOWER | F_ACC);
+        else
+          emit(K_SYRK3, i, i, k, {A(k, i), A(i, i)}, {A(i, i)}, A(i, i), A(k, i), A(k, i), -1, -1,
+               F_TA | F_LOWER | F_ACC);
       }
     }
   }
 };
 
-inline int weight(int kind) { return kind == K_NOP ? 0 : 1; }
+inline int weight(int kind) { return task_kind(kind) == K_NOP ? 0 : 1; }
 
 }  // namespace
 
@@ -208,7 +251,7 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
   std::memset(&st, 0, sizeof(st));
   st.ntasks = n;
   st.nedges = ne;
-  for (int v = 0; v < n; ++v) st.count[p->tasks[v].kind]++;
+  for (int v = 0; v < n; ++v) st.count[task_kind(p->tasks[v].kind)]++;
   std::vector<int32_t> lp(n, 0), ls(n, 0);
   int cp = 0, cps[4] = {0, 0, 0, 0};
   for (int v = 0; v < n; ++v) {  // program order is a topological order
@@ -233,7 +276,8 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
   // priority = weighted bottom level (longest remaining path), ties broken by
   // program order
   std::vector<double> dur(n), bl(n, 0.0);
-  for (int v = 0; v < n; ++v) dur[v] = cost ? cost[p->tasks[v].kind] : (double)weight(p->tasks[v].kind);
+  for (int v = 0; v < n; ++v)
+    dur[v] = cost ? cost[task_kind(p->tasks[v].kind)] : (double)weight(p->tasks[v].kind);
   for (int v = n - 1; v >= 0; --v) {
     double m = 0.0;
     for (int e = ptr[v]; e < ptr[v + 1]; ++e) m = std::max(m, bl[p->succ[e]]);

@@ -54,18 +54,38 @@ struct PlanOptions {
   int trtri_first = 0;
 };
 
+// Operation flags of a tile product, C (+)= +-op(A) op(B) (bits 8-15 of
+// DevTask::kind).
+enum ProductFlags : int32_t {
+  F_TA = 1,       // op(A) = A^T
+  F_TB = 2,       // op(B) = B^T
+  F_MA = 4,       // A is lower triangular (entries above the diagonal ignored)
+  F_MB = 8,       // B is lower triangular
+  F_LOWER = 16,   // only output blocks on or below the diagonal are stored
+  F_NEG = 32,     // C gets -op(A) op(B)
+  F_ACC = 64,     // accumulate into C (else overwrite)
+  F_COPYT = 128   // the copy destination receives the transposed result
+};
+inline int32_t task_kind(int32_t k) { return k & 0xff; }
+inline int32_t task_flags(int32_t k) { return (k >> 8) & 0xff; }
+
 // Device task descriptor (32 bytes).  Tile fields index the tile pool:
-//   [0, T)        A tiles, T = t(t+1)/2, lower tile (i,j) at i(i+1)/2 + j
-//   [T, 2T)       B tiles (copy of L)
-//   [2T, 3T)      C tiles (copy of L^{-1})
-//   [3T, 3T+t)    D_j, inverse of the j-th diagonal factor tile
+//   [0, T)          A tiles, T = t(t+1)/2, lower tile (i,j) at i(i+1)/2 + j
+//   [T, 2T)         B tiles: the renaming copy of L, stored transposed
+//                   (B_ij holds L_ij^T)
+//   [2T, 3T)        C tiles: the renaming copy of L^{-1}, stored transposed
+//   [3T, 3T+t)      D_j, inverse of the j-th diagonal factor tile (zeros above
+//                   the diagonal)
+//   [3T+t, 3T+2t)   D_j^T
+// Storing the copies transposed lets every product of the renamed plan read
+// both operands along contiguous columns (op(A) = A, op(B) = B^T).
 struct DevTask {
-  int32_t kind;
+  int32_t kind;  // task kind (bits 0-7) | product flags (bits 8-15)
   int32_t out;   // tile updated in place
   int32_t a;     // first operand tile (or -1)
   int32_t b;     // second operand tile (or -1)
   int32_t copy;  // renaming destination that receives the same result (or -1)
-  int32_t aux;   // extra output (POTRF: D_j) (or -1)
+  int32_t aux;   // POTRF: D_j (D_j^T follows t tiles later) (or -1)
   int32_t succ_begin;
   int32_t succ_end;
 };
@@ -99,7 +119,7 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* o
 // Tile pool size in tiles for t tiles per side.
 inline int64_t pool_tiles(int t) {
   int64_t T = (int64_t)t * (t + 1) / 2;
-  return 3 * T + t;
+  return 3 * T + 2 * (int64_t)t;
 }
 
 }  // namespace spdinv

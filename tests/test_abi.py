@@ -41,7 +41,7 @@ def test_library_links_no_oracle_code():
 def test_workspace_bytes():
     assert spd.workspace_bytes(0) == 0
     t = 4
-    pool = (3 * t * (t + 1) // 2 + t) * 128 * 128 * 8
+    pool = (3 * t * (t + 1) // 2 + 2 * t) * 128 * 128 * 8
     assert spd.workspace_bytes(512) >= pool
     assert spd.workspace_bytes(513) > spd.workspace_bytes(512)
     assert spd.workspace_bytes(512, trace=1) > spd.workspace_bytes(512)

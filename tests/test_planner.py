@@ -103,7 +103,7 @@ def test_exported_plan_structure(opts):
     assert indeg[0] == 0
     T = p["T"]
     # operand tiles stay inside the pool
-    ntiles = 3 * T + t
+    ntiles = 3 * T + 2 * t
     for col in (1, 2, 3, 4, 5):
         vals = tasks[:, col]
         assert np.all((vals == -1) | ((vals >= 0) & (vals < ntiles)))

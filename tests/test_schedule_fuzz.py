@@ -50,8 +50,7 @@ def _war_edges(plan):
     for u in range(len(tasks)):
         ku, ou, au, bu = (int(x) for x in tasks[u, :4])
         reads = {x for x in (au, bu) if x >= 0}
-        if ku in (tx.TRSM1, tx.TRMM2L, tx.TRSM2R, tx.TRMM3, tx.LAUUM, tx.GEMM1, tx.GEMM2,
-                  tx.GEMM3, tx.SYRK1, tx.SYRK3):
+        if (ku & 0xFF) in tx.PRODUCTS and (ku >> 8) & tx.F_ACC:
             reads.add(ou)
         writes_u = {ou, int(tasks[u, 4]), int(tasks[u, 5])}
         for v in succ[tasks[u, 6]:tasks[u, 7]]:

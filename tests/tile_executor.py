@@ -10,6 +10,8 @@ oracle on the CPU.
 import numpy as np
 
 NOP, SYRK1, POTRF, GEMM1, TRSM1, TRTRI, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEMM3, SYRK3 = range(13)
+PRODUCTS = {SYRK1, GEMM1, TRSM1, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEMM3, SYRK3}
+F_TA, F_TB, F_MA, F_MB, F_LOWER, F_NEG, F_ACC, F_COPYT = 1, 2, 4, 8, 16, 32, 64, 128
 
 
 def tri(i, j):
@@ -23,7 +25,7 @@ def to_pool(a, t, nb):
     full = np.eye(m)
     full[:n, :n] = np.tril(a)
     T = t * (t + 1) // 2
-    pool = np.zeros((3 * T + t, nb, nb))
+    pool = np.zeros((3 * T + 2 * t, nb, nb))
     for i in range(t):
         for j in range(i + 1):
             pool[tri(i, j)] = full[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb]
@@ -40,45 +42,42 @@ def from_pool(pool, t, nb, n):
     return low + np.tril(low, -1).T
 
 
-def run_task(pool, task):
-    kind, out, a, b, cp, aux = (int(x) for x in task[:6])
+def run_task(pool, task, t):
+    """One task with the device semantics: a tile product C (+)= +-op(A) op(B)
+    driven by the flags, the diagonal factorization, or the TRTRI copy."""
+    code, out, a, b, cp, aux = (int(x) for x in task[:6])
+    kind, f = code & 0xFF, (code >> 8) & 0xFF
     if kind == NOP:
         return
-    O = pool[out]
-    A = pool[a] if a >= 0 else None
-    B = pool[b] if b >= 0 else None
-    if kind == SYRK1:
-        r = O - A @ A.T
-    elif kind == GEMM1:
-        r = O - A @ B.T
+    if kind in PRODUCTS:
+        A = pool[a].T if f & F_TA else pool[a]
+        B = pool[b].T if f & F_TB else pool[b]
+        if f & F_MA:
+            A = np.triu(A) if f & F_TA else np.tril(A)
+        if f & F_MB:
+            B = np.triu(B) if f & F_TB else np.tril(B)
+        p = A @ B
+        if f & F_NEG:
+            p = -p
+        r = pool[out] + p if f & F_ACC else p
+        pool[out] = r
+        if cp >= 0:
+            pool[cp] = r.T if f & F_COPYT else r
     elif kind == POTRF:
+        O = pool[out]
         L = np.linalg.cholesky(np.tril(O) + np.tril(O, -1).T)
-        pool[aux] = np.linalg.inv(L)
-        pool[aux] = np.tril(pool[aux])
-        r = L
-    elif kind == TRSM1:
-        r = O @ np.tril(B).T
+        X = np.tril(np.linalg.inv(L))
+        pool[aux] = X
+        pool[aux + t] = X.T
+        pool[out] = L
+        if cp >= 0:
+            pool[cp] = L.T
     elif kind == TRTRI:
-        r = B.copy()
-    elif kind == TRMM2L:
-        r = np.tril(A) @ O
-    elif kind == GEMM2:
-        r = O + A @ B
-    elif kind == TRSM2R:
-        r = -(O @ np.tril(B))
-    elif kind == TRMM3:
-        r = np.tril(A).T @ O
-    elif kind == LAUUM:
-        r = np.tril(O).T @ np.tril(O)
-    elif kind == GEMM3:
-        r = O + A.T @ B
-    elif kind == SYRK3:
-        r = O + A.T @ A
+        pool[out] = pool[a]
+        if cp >= 0:
+            pool[cp] = pool[b]
     else:
         raise ValueError(kind)
-    pool[out] = r
-    if cp >= 0:
-        pool[cp] = r
 
 
 def random_topological_order(tasks, succ, rng, removed=None):
@@ -109,5 +108,5 @@ def execute(plan, a, nb, order=None):
     pool = to_pool(a, t, nb)
     tasks = plan["tasks"]
     for v in (range(len(tasks)) if order is None else order):
-        run_task(pool, tasks[v])
+        run_task(pool, tasks[v], t)
     return from_pool(pool, t, nb, a.shape[0])
