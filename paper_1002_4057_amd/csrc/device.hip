@@ -33,7 +33,7 @@ constexpr int NCH = NB / KC;              // k-panels per tile
 constexpr int LDS_STRIDE = NB + 2;
 constexpr int PANEL = KC * LDS_STRIDE;    // doubles per operand panel
 constexpr int GEMM_SMEM = 4 * PANEL;      // 2 buffers x 2 operands (133,120 bytes)
-constexpr int POTRF_SMEM = NB * NB + 12 * 256 + 8;  // tile + diagonal inverses + scratch
+constexpr int POTRF_SMEM = NB * (NB + 1) + 12 * 256 + 8;  // tile + diagonal inverses + scratch
 constexpr int SMEM_DOUBLES = GEMM_SMEM > POTRF_SMEM ? GEMM_SMEM : POTRF_SMEM;
 constexpr size_t TILE = (size_t)NB * NB;
 constexpr int PAIRS = NB * KC / 2 / NTHREADS;  // 16-byte loads per thread per panel
@@ -240,30 +240,46 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
     __syncthreads();
   }
 
-  if (!active) return;
+  if (active) {
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int off = (wm * 64 + i * 16 + lr) + NB * (wn * 64 + j * 16 + lk);
+      for (int j = 0; j < 4; ++j) {
+        const int off = (wm * 64 + i * 16 + lr) + NB * (wn * 64 + j * 16 + lk);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) st1(rC, off + NB * 4 * r, neg ? -acc[i][j][r] : acc[i][j][r]);
-    }
-  if (!copy) return;
-  const rsrc_t rD = tile_rsrc(copy);
-  // renaming copy, stored as is or transposed
+        for (int r = 0; r < 4; ++r) st1(rC, off + NB * 4 * r, neg ? -acc[i][j][r] : acc[i][j][r]);
+      }
+  }
+  if (!copy) return;  // uniform: the copy pointer is the same in every thread
+  // renaming copy (as is, or transposed with F_COPYT): the result is staged
+  // in LDS as R[col + RLD * row] (odd stride RLD, conflict-free for these
+  // writes), then leaves as contiguous 16-byte stores; the panels are no
+  // longer in use after the k-loop's last barrier
+  constexpr int RLD = NB + 1;
+  double* R = smem;
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int row = wm * 64 + i * 16 + lr, col0 = wn * 64 + j * 16 + lk;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const double v = neg ? -acc[i][j][r] : acc[i][j][r];
-        const int col = col0 + 4 * r;
-        st1(rD, copy_t ? col + NB * row : row + NB * col, v);
-      }
+      for (int r = 0; r < 4; ++r) R[(col0 + 4 * r) + RLD * row] = neg ? -acc[i][j][r] : acc[i][j][r];
     }
+  __syncthreads();
+  const rsrc_t rD = tile_rsrc(copy);
+#pragma unroll 4
+  for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
+    const int e = 2 * (threadIdx.x + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
+    d2 v;  // copy element (rr, cc) is result(cc, rr) or result(rr, cc)
+    if (copy_t) {
+      v.x = R[rr + RLD * cc];
+      v.y = R[rr + 1 + RLD * cc];
+    } else {
+      v.x = R[cc + RLD * rr];
+      v.y = R[cc + RLD * (rr + 1)];
+    }
+    st2(rD, e, v);
+  }
 }
 
 // The general product (transposed or triangular operands) serves only the
@@ -311,8 +327,12 @@ __device__ __forceinline__ int diag16(double* S, int ld, double* XD) {
   for (int k = 0; k < 16; ++k) {
     const double d = readlane_d(row[k], k);
     if (!(d > 0.0)) return k + 1;  // d is a scalar: uniform exit
-    const double lkk = sqrt(d);
-    const double rinv = 1.0 / lkk;
+    // 1/sqrt(d) from the hardware estimate and one Newton step
+    // (y <- y + y (1 - d y^2) / 2), then sqrt(d) = d / sqrt(d)
+    double rinv = __builtin_amdgcn_rsq(d);
+    const double h = d * rinv;
+    rinv = fma(rinv * 0.5, fma(-h, rinv, 1.0), rinv);
+    const double lkk = d * rinv;
     // column k of L: scale below the pivot
     row[k] = (r > k) ? row[k] * rinv : ((r == k) ? lkk : row[k]);
     // right-looking update of the trailing rows with column k
@@ -376,9 +396,9 @@ __device__ __forceinline__ void blk_store(double* S, int ld, d4 v) {
 __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, double* Lout,
                                                          double* LcopyT, double* Xout,
                                                          double* XoutT, double* smem) {
-  constexpr int LD = NB;
-  double* T = smem;                    // [NB * NB] the tile, column-major
-  double* XD = smem + NB * NB;         // [8][256] inverses of the diagonal blocks
+  constexpr int LD = NB + 1;           // odd row stride: transposed LDS reads spread over banks
+  double* T = smem;                    // [NB * LD] the tile, column-major
+  double* XD = smem + NB * LD;         // [8][256] inverses of the diagonal blocks
   double* SCR = XD + 8 * 256;          // [4][256] per-wave scratch block
   int* flag = reinterpret_cast<int*>(SCR + 4 * 256);
   const int tid = threadIdx.x, w = tid >> 6;
@@ -394,8 +414,8 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
       const int e = e0 + 2 * (tid + NTHREADS * u), rr = e & (NB - 1), cc = e >> 7;
-      T[e] = (rr >= cc) ? v[u].x : 0.0;
-      T[e + 1] = (rr + 1 >= cc) ? v[u].y : 0.0;
+      T[rr + LD * cc] = (rr >= cc) ? v[u].x : 0.0;
+      T[rr + 1 + LD * cc] = (rr + 1 >= cc) ? v[u].y : 0.0;
     }
   }
   __syncthreads();
@@ -433,12 +453,22 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
   }
 
   // the factor: global copies (and its transpose)
+  // the factor and its transpose, as contiguous 16-byte stores (the
+  // transpose is taken on the LDS side)
   const rsrc_t rLT = tile_rsrc(LcopyT ? LcopyT : Lout);
-  for (int e = tid; e < NB * NB; e += NTHREADS) {
-    const int rr = e & (NB - 1), cc = e >> 7;
-    const double v = (rr >= cc) ? T[e] : 0.0;
-    st1(rL, e, v);
-    if (LcopyT) st1(rLT, cc + NB * rr, v);
+#pragma unroll 4
+  for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
+    const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
+    d2 v;
+    v.x = (rr >= cc) ? T[rr + LD * cc] : 0.0;
+    v.y = (rr + 1 >= cc) ? T[rr + 1 + LD * cc] : 0.0;
+    st2(rL, e, v);
+    if (LcopyT) {  // element (rr, cc) of L^T is L(cc, rr)
+      d2 u;
+      u.x = (cc >= rr) ? T[cc + LD * rr] : 0.0;
+      u.y = (cc >= rr + 1) ? T[cc + LD * (rr + 1)] : 0.0;
+      st2(rLT, e, u);
+    }
   }
   __syncthreads();  // the inverse below writes the upper blocks of T
 
@@ -457,29 +487,30 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
       d4 xip = {0.0, 0.0, 0.0, 0.0};
       xip = blk_mma16(xip, XD + 256 * i, 16, scr, 16, false);  // X_ii S
       xip = -xip;
-      // X_ip transposed into block (p, i) of T, and to the outputs
+      // X_ip transposed into block (p, i) of T
       const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int rr = 16 * i + lr, cc = 16 * p + lk + 4 * q;
-        T[cc + LD * rr] = xip[q];
-        st1(rX, rr + NB * cc, xip[q]);
-        st1(rXT, cc + NB * rr, xip[q]);
-      }
+      for (int q = 0; q < 4; ++q) T[(16 * p + lk + 4 * q) + LD * (16 * i + lr)] = xip[q];
     }
   }
-  // diagonal blocks and the zero triangles of the inverse
-  for (int e = tid; e < NB * NB; e += NTHREADS) {
-    const int rr = e & (NB - 1), cc = e >> 7;
-    const int bi = rr >> 4, bj = cc >> 4;
-    if (bi == bj) {
-      const double v = XD[256 * bi + (rr & 15) + 16 * (cc & 15)];
-      st1(rX, e, v);
-      st1(rXT, cc + NB * rr, v);
-    } else if (bi < bj) {
-      st1(rX, e, 0.0);
-      st1(rXT, cc + NB * rr, 0.0);
-    }
+  __syncthreads();
+  // X and X^T as contiguous 16-byte stores: X(r, c) is XD for diagonal
+  // blocks, T(c, r) below them (stored transposed), zero above
+  auto xval = [&](int r, int c) -> double {
+    const int br = r >> 4, bc = c >> 4;
+    if (br == bc) return XD[256 * br + (r & 15) + 16 * (c & 15)];
+    return (br > bc) ? T[c + LD * r] : 0.0;
+  };
+#pragma unroll 4
+  for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
+    const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
+    d2 v, u;
+    v.x = xval(rr, cc);
+    v.y = xval(rr + 1, cc);
+    u.x = xval(cc, rr);
+    u.y = xval(cc, rr + 1);
+    st2(rX, e, v);
+    st2(rXT, e, u);
   }
   return 0;
 }
