@@ -77,6 +77,10 @@ def main():
     ap.add_argument("--kappa", type=float, default=1e4)
     ap.add_argument("--cpu-n", type=int, default=6144, help="oracle sample order (0 = skip)")
     ap.add_argument("--no-unpipelined", action="store_true")
+    ap.add_argument("--input", choices=["spectrum", "wishart"], default="spectrum",
+                    help="wishart (B B^T/n + I, no QR) is for profiler counter runs only")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after timing, run a plain device copy of this many MiB (profiler scale)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -93,8 +97,15 @@ def main():
     torch.cuda.set_device(dev)
     lib = _lib.load()
     n, K, W = args.n, args.steps, args.warmup
-    log(f"[bench] building input n={n} kappa={args.kappa:g}")
-    a, q, lam = inputs.spectrum(n, args.kappa, seed=0, device="cuda", return_factors=True)
+    log(f"[bench] building input n={n} kappa={args.kappa:g} ({args.input})")
+    if args.input == "spectrum":
+        a, q, lam = inputs.spectrum(n, args.kappa, seed=0, device="cuda", return_factors=True)
+    else:
+        b0 = inputs.randn((n, n), 0).to(dev)
+        a = b0 @ b0.t() / n + torch.eye(n, dtype=torch.float64, device=dev)
+        a = 0.5 * (a + a.t())
+        del b0
+        q = lam = None
     a_cm = a.t().contiguous()                       # column-major storage of A
     bufs = [a_cm.clone() for _ in range(K + W)]
     work = torch.empty(spd.workspace_bytes(n), dtype=torch.uint8, device=dev)
@@ -105,12 +116,14 @@ def main():
         spd.spd_inverse_(bufs[K + k].t(), work=work)
     torch.cuda.synchronize()
     # parity of one result (untimed) against the analytic inverse
-    x = bufs[K].t()                                   # lower triangle holds A^{-1}
-    ref = inputs.analytic_inverse(q, lam)
-    low = torch.tril(x)
-    xs = low + torch.tril(low, -1).t()
-    rel = (torch.linalg.norm(xs - ref) / torch.linalg.norm(ref)).item()
-    del xs, low, ref
+    rel = None
+    if q is not None:
+        x = bufs[K].t()                               # lower triangle holds A^{-1}
+        ref = inputs.analytic_inverse(q, lam)
+        low = torch.tril(x)
+        xs = low + torch.tril(low, -1).t()
+        rel = (torch.linalg.norm(xs - ref) / torch.linalg.norm(ref)).item()
+        del xs, low, ref
 
     log(f"[bench] timing {K} steps")
     lib.spdinv_kernel_timer(1)
@@ -144,6 +157,16 @@ def main():
         pipe = {"pipelined_gflops": res["pipelined"], "unpipelined_gflops": res["unpipelined"],
                 "steps": reps}
 
+    if args.calibrate_copy > 0:
+        # plain copy of known size, for scaling profiler byte counters
+        nel = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
+        del src, dst
+
     cpu = None
     if args.cpu_n > 0:
         log(f"[bench] oracle sample n={args.cpu_n}")
@@ -171,7 +194,8 @@ def main():
                      "traffic": traffic_per_launch(), "kernel": "sched_kernel",
                      "kernel_ms": round(sched_avg_s * 1e3, 3)},
         "cpu_baseline": cpu,
-        "parity": {"rel_fro_vs_analytic": rel, "bar": 1e-12 * args.kappa},
+        "parity": ({"rel_fro_vs_analytic": rel, "bar": 1e-12 * args.kappa} if rel is not None
+                   else None),
         "pipelining": pipe,
     }
     print(json.dumps(line), flush=True)
