@@ -118,6 +118,33 @@ int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t 
                 spdinv_stream_t stream, const spdinv_opts* opts, int* d_info,
                 spdinv_report* report);
 
+/* ---- backward ------------------------------------------------------------- */
+/* Bytes of device workspace that spd_inverse_backward needs for order n
+   (three square tile-major matrices of ceil(n/128)*128). */
+size_t spd_inverse_backward_workspace_bytes(int n);
+
+/*
+ * Adjoint of the inverse.  For the loss L = sum(G o A^{-1}) of a symmetric A
+ * (A parametrized as a symmetric matrix), the gradient is
+ *     gradA = -sym(A^{-1} G A^{-1}) = -X S X,   X = A^{-1},  S = (G + G^T)/2,
+ * formed as W = X S followed by the lower tiles of -W X, mirrored.  It is the
+ * derivative of the map of Section 2 (A -> A^{-1}), which the paper does not
+ * treat; the operation count is about 3 n^3.
+ *   n       order (>= 0)
+ *   X       device, column-major, ldx >= max(1,n): the inverse, of which only
+ *           the lower triangle is used (the output of spd_inverse)
+ *   G       device, column-major, ldg >= max(1,n): the full upstream
+ *           gradient dL/dA^{-1} (not necessarily symmetric)
+ *   gradA   device, column-major, ldga >= max(1,n): receives the full
+ *           symmetric gradient (both triangles); must not overlap X or G
+ *   work    device workspace of spd_inverse_backward_workspace_bytes(n)
+ *   stream  HIP stream; the call is asynchronous
+ * Returns 0, -i for an invalid i-th argument (nothing enqueued),
+ * SPDINV_ERR_WORKSPACE or SPDINV_ERR_HIP.  n = 0 returns 0 at once.
+ */
+int spd_inverse_backward(int n, const double* X, int ldx, const double* G, int ldg, double* gradA,
+                         int ldga, void* work, size_t work_bytes, spdinv_stream_t stream);
+
 /* Frees every cached plan (device arena and host tables). */
 void spdinv_release_plans(void);
 

@@ -8,6 +8,8 @@ Main entry points
 -----------------
 ``spd_inverse(a)``      full symmetric A^{-1} of a CUDA float64 tensor
 ``spd_inverse_(a_cm)``  in place on a column-major view (lower triangle)
+``spd_inverse_backward(x, g)``  -X sym(G) X, the adjoint of the inverse
+``SpdInverse.apply(a)`` autograd Function (forward + backward on the GPU)
 ``plan_stats(t)``       planner statistics (critical paths of Table 1)
 ``plan_export(t)``      the task DAG the device executes
 """
@@ -21,6 +23,7 @@ from . import _lib
 from ._lib import LibraryNotBuilt, load, make_opts, TASK_NAMES  # noqa: F401
 
 __all__ = ["spd_inverse", "spd_inverse_", "workspace_bytes", "plan_stats", "plan_export",
+           "spd_inverse_backward", "backward_workspace_bytes", "SpdInverse", "spd_inverse_ad",
            "SpdInverseError", "NotPositiveDefinite"]
 
 
@@ -94,6 +97,92 @@ def spd_inverse(a, **opts):
     rep = spd_inverse_(buf.t(), fill_upper=1, report=True, **opts) if n else None
     del rep
     return buf.t().contiguous() if n else torch.empty_like(a)
+
+
+def backward_workspace_bytes(n: int) -> int:
+    return int(load().spd_inverse_backward_workspace_bytes(int(n)))
+
+
+def spd_inverse_backward(x, g, *, work=None, out=None):
+    """Gradient of L = sum(g * A^{-1}) with respect to a symmetric A:
+    -X sym(g) X, X = A^{-1} (full symmetric n x n CUDA float64, e.g. the
+    output of ``spd_inverse``), g any n x n CUDA float64 tensor.  Returns the
+    full symmetric gradient (or writes it into ``out``).
+
+    Row-major tensors are passed as column-major buffers of their transposes:
+    X is symmetric, sym(g^T) = sym(g) and the result is symmetric, so the
+    storage order does not matter."""
+    import torch
+    for name, v in (("x", x), ("g", g)):
+        if v.dtype != torch.float64 or not v.is_cuda or v.dim() != 2:
+            raise TypeError(f"{name}: expected a 2-D CUDA float64 tensor")
+    n = x.shape[0]
+    if x.shape != (n, n) or g.shape != (n, n):
+        raise ValueError("x and g must be n x n")
+    xc, gc = x.contiguous(), g.contiguous()
+    if out is None:
+        out = torch.empty((n, n), dtype=torch.float64, device=x.device)
+    elif out.shape != (n, n) or not out.is_contiguous() or out.dtype != torch.float64:
+        raise ValueError("out must be a contiguous n x n float64 tensor")
+    if n == 0:
+        return out
+    lib = load()
+    need = int(lib.spd_inverse_backward_workspace_bytes(n))
+    if work is None:
+        work = torch.empty(need, dtype=torch.uint8, device=x.device)
+    elif work.numel() * work.element_size() < need:
+        raise ValueError(f"workspace too small: need {need} bytes")
+    rc = lib.spd_inverse_backward(n, xc.data_ptr(), n, gc.data_ptr(), n, out.data_ptr(), n,
+                                  work.data_ptr(), need, _stream_ptr(x.device))
+    if rc != 0:
+        raise SpdInverseError(f"spd_inverse_backward returned {rc}")
+    return out
+
+
+def _autograd_function():
+    import torch
+
+    class SpdInverse(torch.autograd.Function):
+        """A -> A^{-1} for symmetric positive definite A (lower triangle read),
+        with the gradient taken over symmetric matrices: dL/dA =
+        -A^{-1} sym(dL/dA^{-1}) A^{-1}.  Both directions run in the HIP
+        library.  A leading batch dimension is handled one matrix at a time."""
+
+        @staticmethod
+        def forward(ctx, a):
+            if a.dim() == 2:
+                x = spd_inverse(a)
+            else:
+                x = torch.stack([spd_inverse(m) for m in a])
+            ctx.save_for_backward(x)
+            return x
+
+        @staticmethod
+        def backward(ctx, gx):
+            (x,) = ctx.saved_tensors
+            if x.dim() == 2:
+                return spd_inverse_backward(x, gx)
+            return torch.stack([spd_inverse_backward(xm, gm) for xm, gm in zip(x, gx)])
+
+    return SpdInverse
+
+
+_SPD_FN = None
+
+
+def __getattr__(name):
+    # the autograd Function class is created on first use (torch is imported lazily)
+    global _SPD_FN
+    if name == "SpdInverse":
+        if _SPD_FN is None:
+            _SPD_FN = _autograd_function()
+        return _SPD_FN
+    raise AttributeError(name)
+
+
+def spd_inverse_ad(a):
+    """Differentiable A^{-1} (see ``SpdInverse``)."""
+    return __getattr__("SpdInverse").apply(a)
 
 
 def plan_stats(t: int, **opts) -> dict:

@@ -83,6 +83,10 @@ def load():
     lib.spdinv_kernel_timer.restype = i
     lib.spdinv_kernel_timer_read.argtypes = [P(ctypes.c_longlong)]
     lib.spdinv_kernel_timer_read.restype = ctypes.c_double
+    lib.spd_inverse_backward_workspace_bytes.argtypes = [i]
+    lib.spd_inverse_backward_workspace_bytes.restype = sz
+    lib.spd_inverse_backward.argtypes = [i, vp, i, vp, i, vp, i, vp, sz, vp]
+    lib.spd_inverse_backward.restype = i
     lib.spdinv_version.argtypes = []
     lib.spdinv_version.restype = ctypes.c_char_p
     _lib = lib

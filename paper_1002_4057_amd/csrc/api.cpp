@@ -11,6 +11,7 @@
 #include <tuple>
 #include <vector>
 
+#include "dense.hpp"
 #include "device.hpp"
 #include "plan.hpp"
 #include "spdinv.h"
@@ -294,6 +295,41 @@ int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t 
     report->workers = grid;
     if (c[CTRL_ABORT]) return SPDINV_ERR_TIMEOUT;
   }
+  return 0;
+}
+
+size_t spd_inverse_backward_workspace_bytes(int n) {
+  if (n <= 0) return 0;
+  const size_t t = (size_t)tiles_for(n);
+  return 3 * t * t * (size_t)NB * NB * sizeof(double);
+}
+
+int spd_inverse_backward(int n, const double* X, int ldx, const double* G, int ldg, double* gradA,
+                         int ldga, void* work, size_t work_bytes, spdinv_stream_t stream_) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  const int ldmin = n > 1 ? n : 1;
+  if (n < 0) return -1;
+  if (n > 0 && !X) return -2;
+  if (ldx < ldmin) return -3;
+  if (n > 0 && !G) return -4;
+  if (ldg < ldmin) return -5;
+  if (n > 0 && !gradA) return -6;
+  if (ldga < ldmin) return -7;
+  if (n == 0) return 0;
+  if (!work) return -8;
+  if (work_bytes < spd_inverse_backward_workspace_bytes(n)) return SPDINV_ERR_WORKSPACE;
+  const int t = tiles_for(n);
+  const size_t sq = (size_t)t * t * NB * NB;
+  double* Xf = (double*)work;  // X, full symmetric
+  double* S = Xf + sq;         // sym(G), later the lower tiles of the gradient
+  double* W = S + sq;          // X sym(G)
+  if (launch_pack(X, ldx, n, t, PACK_SYM_LOWER, Xf, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (launch_pack(G, ldg, n, t, PACK_SYM_AVG, S, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  // W = X S: W(i, j) = sum_k X(i, k) S(k, j) = sum_k X(i, k) S(j, k)^T (S symmetric)
+  if (launch_gemm_nt(Xf, S, W, t, 0, 0, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  // grad = -W X on the lower tiles: sum_k W(i, k) X(j, k)^T (X symmetric)
+  if (launch_gemm_nt(W, Xf, S, t, 1, 1, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (launch_unpack_sym(S, t, n, gradA, ldga, stream) != hipSuccess) return SPDINV_ERR_HIP;
   return 0;
 }
 

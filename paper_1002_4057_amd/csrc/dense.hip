@@ -1,0 +1,167 @@
+// Dense kernels on tile-major square matrices: symmetric packing, the chained
+// FP64 MFMA product C = +-A B^T over whole tile rows, and unpacking with a
+// mirror.  They serve the backward of the inverse,
+//   grad_A = -X sym(G) X,  X = A^{-1} (symmetric),  sym(G) = (G + G^T) / 2,
+// computed as W = X S (S = sym(G)), then the lower tiles of -W X, mirrored.
+//
+// Square tile-major layout: t x t tiles of NB x NB, tile (i, j) at index
+// i + t*j, each tile column-major and contiguous.  Entries beyond the order n
+// are zero, so the padding adds nothing to any product.
+#include "dense.hpp"
+#include "mfma_tile.hpp"
+
+namespace spdinv {
+namespace {
+
+using namespace tile;
+
+constexpr int SB = 32;  // sub-block of the transposing copies
+
+// dst tile (bi, bj) of the square tile-major matrix, from a column-major
+// source (ld) of order n:
+//   mode PACK_SYM_LOWER: the symmetric matrix whose lower triangle is src's
+//                        (entry (r, c) = src(max, min))
+//   mode PACK_SYM_AVG:   (src + src^T) / 2
+// The transposed reads go through LDS in 32 x 32 sub-blocks so that every
+// global access is a run of 32 consecutive doubles.
+__global__ __launch_bounds__(NTHREADS) void pack_kernel(const double* __restrict__ src, int ld,
+                                                        int n, int t, int mode,
+                                                        double* __restrict__ dst) {
+  __shared__ double L[SB][SB + 1];
+  const int bi = blockIdx.x % t, bj = blockIdx.x / t;
+  double* out = dst + (size_t)blockIdx.x * TILE;
+  const int tx = threadIdx.x & (SB - 1), ty = threadIdx.x / SB;  // ty in 0..7
+  for (int sb = 0; sb < (NB / SB) * (NB / SB); ++sb) {
+    const int lr0 = (sb % (NB / SB)) * SB, lc0 = (sb / (NB / SB)) * SB;  // within the tile
+    const int r0 = bi * NB + lr0, c0 = bj * NB + lc0;                      // global
+    // transposed source block: element (c0 + tx, r0 + j) into L[tx][j]
+#pragma unroll
+    for (int q = 0; q < SB / 8; ++q) {
+      const int j = ty + 8 * q;
+      const int sr = c0 + tx, sc = r0 + j;
+      L[tx][j] = (sr < n && sc < n) ? src[sr + (size_t)ld * sc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SB / 8; ++q) {
+      const int j = ty + 8 * q;
+      const int gr = r0 + tx, gc = c0 + j;
+      const double tv = L[j][tx];  // src(gc, gr)
+      const double dv = (gr < n && gc < n) ? src[gr + (size_t)ld * gc] : 0.0;
+      double v;
+      if (mode == PACK_SYM_LOWER)
+        v = (gr >= gc) ? dv : tv;
+      else
+        v = 0.5 * (dv + tv);
+      out[(lr0 + tx) + NB * (lc0 + j)] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Output tile list: all t*t tiles (lower = 0) or the t(t+1)/2 lower tiles
+// (lower = 1), consecutive blocks spread over the XCDs in contiguous runs so
+// that the workgroups of one XCD share operand tiles in its L2.
+__device__ __forceinline__ void out_tile(int b, int nblk, int t, bool lower, int& i, int& j) {
+  // blocks are handed to the 8 XCDs round-robin (block b to XCD b % 8): XCD
+  // x receives the contiguous run of logical ids starting at
+  // x * (nblk / 8) + min(x, nblk % 8)
+  const int x = b % 8, y = b / 8, q = nblk / 8, r = nblk % 8;
+  const int id = x * q + min(x, r) + y;
+  if (!lower) {
+    // groups of 4 tile rows, column-major inside a group
+    const int G = 4;
+    const int grp = id / (G * t), rem = id % (G * t);
+    const int rows = min(G, t - grp * G);
+    i = grp * G + rem % rows;
+    j = rem / rows;
+  } else {
+    int r = (int)((sqrtf(8.0f * (float)id + 1.0f) - 1.0f) * 0.5f);
+    while (r * (r + 1) / 2 > id) --r;
+    while ((r + 1) * (r + 2) / 2 <= id) ++r;
+    i = r;
+    j = id - r * (r + 1) / 2;
+  }
+}
+
+// C(i, j) = s * sum_k A(i, k) B(j, k)^T over k < t, one output tile per
+// workgroup (s = -1 when neg).  With lower = 1 only tiles i >= j are formed.
+__global__ __launch_bounds__(NTHREADS) void gemm_nt_kernel(const double* __restrict__ A,
+                                                           const double* __restrict__ B,
+                                                           double* __restrict__ C, int t,
+                                                           int lower, int neg) {
+  __shared__ double smem[GEMM_SMEM];
+  const int nblk = lower ? t * (t + 1) / 2 : t * t;
+  int i, j;
+  out_tile(blockIdx.x, nblk, t, lower != 0, i, j);
+  Acc acc;
+  acc_zero(acc);
+  auto pair = [&](int k, const double*& pa, const double*& pb) {
+    pa = A + (size_t)(i + t * k) * TILE;
+    pb = B + (size_t)(j + t * k) * TILE;
+  };
+  mma_chain<0>(acc, t, pair, smem);
+  acc_store<0>(C + (size_t)(i + t * j) * TILE, acc, neg != 0, false);
+}
+
+// out (column-major, ld, order n) <- the symmetric matrix whose lower tiles
+// (i >= j) are in the square tile-major src; both triangles are written.
+__global__ __launch_bounds__(NTHREADS) void unpack_sym_kernel(const double* __restrict__ src,
+                                                              int t, int n,
+                                                              double* __restrict__ out, int ld) {
+  __shared__ double L[SB][SB + 1];
+  const int bi = blockIdx.x % t, bj = blockIdx.x / t;
+  const int tx = threadIdx.x & (SB - 1), ty = threadIdx.x / SB;
+  // output tile (bi, bj): lower tiles are copied, upper ones are the
+  // transpose of tile (bj, bi); a diagonal tile mirrors its own lower part
+  const int si = bi >= bj ? bi : bj, sj = bi >= bj ? bj : bi;
+  const double* s = src + (size_t)(si + t * sj) * TILE;
+  for (int sb = 0; sb < (NB / SB) * (NB / SB); ++sb) {
+    const int lr0 = (sb % (NB / SB)) * SB, lc0 = (sb / (NB / SB)) * SB;
+    // transposed: element (lc0 + tx, lr0 + j) of the source tile into L[tx][j]
+#pragma unroll
+    for (int q = 0; q < SB / 8; ++q) {
+      const int j = ty + 8 * q;
+      L[tx][j] = s[(lc0 + tx) + NB * (lr0 + j)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SB / 8; ++q) {
+      const int j = ty + 8 * q;
+      const int lr = lr0 + tx, lc = lc0 + j;
+      const int gr = bi * NB + lr, gc = bj * NB + lc;
+      if (gr < n && gc < n) {
+        double v;
+        if (bi > bj || (bi == bj && lr >= lc))
+          v = s[lr + NB * lc];
+        else
+          v = L[j][tx];  // source element (lc, lr)
+        out[gr + (size_t)ld * gc] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_pack(const double* src, int ld, int n, int t, int mode, double* dst,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(pack_kernel, dim3(t * t), dim3(NTHREADS), 0, s, src, ld, n, t, mode, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_nt(const double* A, const double* B, double* C, int t, int lower, int neg,
+                          hipStream_t s) {
+  const int nblk = lower ? t * (t + 1) / 2 : t * t;
+  hipLaunchKernelGGL(gemm_nt_kernel, dim3(nblk), dim3(NTHREADS), 0, s, A, B, C, t, lower, neg);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_sym(const double* src, int t, int n, double* out, int ld,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(unpack_sym_kernel, dim3(t * t), dim3(NTHREADS), 0, s, src, t, n, out, ld);
+  return hipGetLastError();
+}
+
+}  // namespace spdinv

@@ -14,124 +14,17 @@
 //     through LDS and the finished factor kept in LDS for the inverse;
 //   * a tile copy (TRTRI reuses the inverse made by POTRF, bit for bit).
 #include "device.hpp"
+#include "mfma_tile.hpp"
 
 #include <climits>
 
 namespace spdinv {
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef double d2 __attribute__((ext_vector_type(2)));
+using namespace tile;
 
-constexpr int KC = 32;                    // k-panel depth
-constexpr int NCH = NB / KC;              // k-panels per tile
-// Row stride of a [k][r] panel in LDS (doubles).  With 130, element (k, r)
-// falls in dword bank (4k + 2r) mod 64: the transposing stores (4
-// consecutive r x 16 even k per wave) cover all 64 banks, contiguous stores
-// of a k-row are conflict-free, and operand reads (16 consecutive r of 4
-// consecutive k) conflict at most 2-way.
-constexpr int LDS_STRIDE = NB + 2;
-constexpr int PANEL = KC * LDS_STRIDE;    // doubles per operand panel
-constexpr int GEMM_SMEM = 4 * PANEL;      // 2 buffers x 2 operands (133,120 bytes)
 constexpr int POTRF_SMEM = NB * (NB + 1) + 12 * 256 + 8;  // tile + diagonal inverses + scratch
 constexpr int SMEM_DOUBLES = GEMM_SMEM > POTRF_SMEM ? GEMM_SMEM : POTRF_SMEM;
-constexpr size_t TILE = (size_t)NB * NB;
-constexpr int PAIRS = NB * KC / 2 / NTHREADS;  // 16-byte loads per thread per panel
-
-__device__ __forceinline__ double* tile_ptr(double* pool, int idx) {
-  return pool + (size_t)idx * TILE;
-}
-
-// ---------------------------------------------------------------------------
-// Agent-coherent tile access.  A tile written by one task is read by other
-// workgroups, possibly on another XCD whose L2 is not kept coherent with the
-// writer's.  Every access to pool tiles inside the scheduler therefore uses
-// the sc1 cache policy -- the policy of agent-scope atomics -- through buffer
-// loads and stores (which also bounds-check against the 128 KiB tile): each
-// such access is coherent across the device by itself.  A task publishes its
-// results by waiting for its stores to complete before its successors'
-// counters are decremented, and a consumer needs no cache invalidation, so
-// neither the L2 write-back of a release fence nor the L2 invalidation of an
-// acquire fence is needed.
-// ---------------------------------------------------------------------------
-typedef unsigned int u4v __attribute__((ext_vector_type(4)));
-typedef unsigned int u2v __attribute__((ext_vector_type(2)));
-typedef __amdgpu_buffer_rsrc_t rsrc_t;
-constexpr int CPOL_AGENT = 16;                 // sc1
-constexpr int RSRC_WORD3 = 0x00020000;         // raw dword access (gfx9 family)
-
-__device__ __forceinline__ rsrc_t tile_rsrc(const double* tile) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(tile), 0, (int)(TILE * 8),
-                                           RSRC_WORD3);
-}
-__device__ __forceinline__ d2 ld2(rsrc_t r, int elem) {
-  return __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, elem * 8, 0, CPOL_AGENT));
-}
-__device__ __forceinline__ double ld1(rsrc_t r, int elem) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, elem * 8, 0, CPOL_AGENT));
-}
-__device__ __forceinline__ void st2(rsrc_t r, int elem, d2 v) {
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, v), r, elem * 8, 0, CPOL_AGENT);
-}
-__device__ __forceinline__ void st1(rsrc_t r, int elem, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), r, elem * 8, 0, CPOL_AGENT);
-}
-
-// ---------------------------------------------------------------------------
-// k-panel staging.  A panel holds op(X)[r][k] for r = 0..127 (the output row
-// for the left operand, the output column for the right one) and k in one
-// KC-deep slice, stored in LDS as S[k * LDS_STRIDE + r].
-//   contig: element (r, k) is X[r + NB*k] (r runs down a stored column)
-//  !contig: element (r, k) is X[k + NB*r] (k runs down a stored column)
-// mask treats X as lower triangular (entries above its diagonal read as 0).
-// Each thread moves PAIRS pairs of doubles per panel with 16-byte loads.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void panel_load(rsrc_t X, int k0, bool contig, d2 (&r)[PAIRS]) {
-  const int tid = threadIdx.x;
-  if (contig) {
-#pragma unroll
-    for (int q = 0; q < PAIRS; ++q) r[q] = ld2(X, NB * k0 + 2 * (tid + NTHREADS * q));
-  } else {
-#pragma unroll
-    for (int q = 0; q < PAIRS; ++q) {
-      const int p = tid + NTHREADS * q;
-      const int rr = p / (KC / 2), kk = (p % (KC / 2)) * 2;
-      r[q] = ld2(X, k0 + kk + NB * rr);
-    }
-  }
-}
-
-__device__ __forceinline__ void panel_store(double* __restrict__ S, int k0, bool contig, bool mask,
-                                            const d2 (&r)[PAIRS]) {
-  const int tid = threadIdx.x;
-  if (contig) {
-#pragma unroll
-    for (int q = 0; q < PAIRS; ++q) {
-      const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), kk = e >> 7;
-      d2 v = r[q];
-      // stored element (row rr+s, col k0+kk); lower triangle keeps row >= col
-      if (mask) {
-        if (rr < k0 + kk) v.x = 0.0;
-        if (rr + 1 < k0 + kk) v.y = 0.0;
-      }
-      *reinterpret_cast<d2*>(S + kk * LDS_STRIDE + rr) = v;
-    }
-  } else {
-#pragma unroll
-    for (int q = 0; q < PAIRS; ++q) {
-      const int p = tid + NTHREADS * q;
-      const int rr = p / (KC / 2), kk = (p % (KC / 2)) * 2;
-      double v0 = r[q].x, v1 = r[q].y;
-      // stored element (row k0+kk+s, col rr)
-      if (mask) {
-        if (k0 + kk < rr) v0 = 0.0;
-        if (k0 + kk + 1 < rr) v1 = 0.0;
-      }
-      S[kk * LDS_STRIDE + rr] = v0;
-      S[(kk + 1) * LDS_STRIDE + rr] = v1;
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Tile product on the FP64 matrix cores.

@@ -1,0 +1,243 @@
+// Building blocks of the FP64 tile products on the gfx950 matrix cores, shared
+// by the scheduler's tile tasks and the dense kernels (backward, refinement).
+//
+// A tile is NB x NB (NB = 128) binary64, column-major and contiguous
+// (128 KiB).  One workgroup of 256 threads (4 wave64) computes one 128 x 128
+// output: the waves form a 2 x 2 grid of 64 x 64 blocks, each a 4 x 4 array
+// of 16 x 16 accumulators of v_mfma_f64_16x16x4f64.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace spdinv {
+namespace tile {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+constexpr int KC = 32;                    // k-panel depth
+constexpr int NCH = NB / KC;              // k-panels per tile
+// Row stride of a [k][r] panel in LDS (doubles).  With 130, element (k, r)
+// falls in dword bank (4k + 2r) mod 64: the transposing stores (4
+// consecutive r x 16 even k per wave) cover all 64 banks, contiguous stores
+// of a k-row are conflict-free, and operand reads (16 consecutive r of 4
+// consecutive k) conflict at most 2-way.
+constexpr int LDS_STRIDE = NB + 2;
+constexpr int PANEL = KC * LDS_STRIDE;    // doubles per operand panel
+constexpr int GEMM_SMEM = 4 * PANEL;      // 2 buffers x 2 operands (133,120 bytes)
+constexpr size_t TILE = (size_t)NB * NB;
+constexpr int PAIRS = NB * KC / 2 / NTHREADS;  // 16-byte loads per thread per panel
+
+__device__ __forceinline__ double* tile_ptr(double* pool, int idx) {
+  return pool + (size_t)idx * TILE;
+}
+
+// ---------------------------------------------------------------------------
+// Tile access through buffer resources (bounds-checked against the 128 KiB
+// tile).  The cache policy is a template parameter: CPOL_AGENT (sc1, the
+// policy of agent-scope atomics) makes each access coherent across the whole
+// device by itself, which the scheduler needs because a tile written by one
+// task is read by workgroups on other XCDs, whose L2 caches are not kept
+// coherent with the writer's.  Kernels whose operands were written by an
+// earlier launch use the default policy (0) and keep L2 reuse.
+// ---------------------------------------------------------------------------
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int CPOL_AGENT = 16;                 // sc1
+constexpr int RSRC_WORD3 = 0x00020000;         // raw dword access (gfx9 family)
+
+__device__ __forceinline__ rsrc_t tile_rsrc(const double* tile) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(tile), 0, (int)(TILE * 8),
+                                           RSRC_WORD3);
+}
+template <int CP = CPOL_AGENT>
+__device__ __forceinline__ d2 ld2(rsrc_t r, int elem) {
+  return __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, elem * 8, 0, CP));
+}
+template <int CP = CPOL_AGENT>
+__device__ __forceinline__ double ld1(rsrc_t r, int elem) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, elem * 8, 0, CP));
+}
+template <int CP = CPOL_AGENT>
+__device__ __forceinline__ void st2(rsrc_t r, int elem, d2 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, v), r, elem * 8, 0, CP);
+}
+template <int CP = CPOL_AGENT>
+__device__ __forceinline__ void st1(rsrc_t r, int elem, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v), r, elem * 8, 0, CP);
+}
+
+// ---------------------------------------------------------------------------
+// k-panel staging.  A panel holds op(X)[r][k] for r = 0..127 (the output row
+// for the left operand, the output column for the right one) and k in one
+// KC-deep slice, stored in LDS as S[k * LDS_STRIDE + r].
+//   contig: element (r, k) is X[r + NB*k] (r runs down a stored column)
+//  !contig: element (r, k) is X[k + NB*r] (k runs down a stored column)
+// mask treats X as lower triangular (entries above its diagonal read as 0).
+// Each thread moves PAIRS pairs of doubles per panel with 16-byte loads.
+// ---------------------------------------------------------------------------
+template <int CP = CPOL_AGENT>
+__device__ __forceinline__ void panel_load(rsrc_t X, int k0, bool contig, d2 (&r)[PAIRS]) {
+  const int tid = threadIdx.x;
+  if (contig) {
+#pragma unroll
+    for (int q = 0; q < PAIRS; ++q) r[q] = ld2<CP>(X, NB * k0 + 2 * (tid + NTHREADS * q));
+  } else {
+#pragma unroll
+    for (int q = 0; q < PAIRS; ++q) {
+      const int p = tid + NTHREADS * q;
+      const int rr = p / (KC / 2), kk = (p % (KC / 2)) * 2;
+      r[q] = ld2<CP>(X, k0 + kk + NB * rr);
+    }
+  }
+}
+
+__device__ __forceinline__ void panel_store(double* __restrict__ S, int k0, bool contig, bool mask,
+                                            const d2 (&r)[PAIRS]) {
+  const int tid = threadIdx.x;
+  if (contig) {
+#pragma unroll
+    for (int q = 0; q < PAIRS; ++q) {
+      const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), kk = e >> 7;
+      d2 v = r[q];
+      // stored element (row rr+s, col k0+kk); lower triangle keeps row >= col
+      if (mask) {
+        if (rr < k0 + kk) v.x = 0.0;
+        if (rr + 1 < k0 + kk) v.y = 0.0;
+      }
+      *reinterpret_cast<d2*>(S + kk * LDS_STRIDE + rr) = v;
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < PAIRS; ++q) {
+      const int p = tid + NTHREADS * q;
+      const int rr = p / (KC / 2), kk = (p % (KC / 2)) * 2;
+      double v0 = r[q].x, v1 = r[q].y;
+      // stored element (row k0+kk+s, col rr)
+      if (mask) {
+        if (k0 + kk < rr) v0 = 0.0;
+        if (k0 + kk + 1 < rr) v1 = 0.0;
+      }
+      S[kk * LDS_STRIDE + rr] = v0;
+      S[(kk + 1) * LDS_STRIDE + rr] = v1;
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// MFMA register layout.  v_mfma_f64_16x16x4(x, y, d): d[i][j] += sum_k
+// x[i][k] y[k][j] with x[i][k] from lane i+16k, y[k][j] from lane j+16k, and
+// d[i][j] in register r = i/4 of lane j + 16*(i%4).  The products below pass
+// (op(B) block, op(A) block), so that d is the transposed 16x16 output block:
+// lane l, register r holds output row (l%16) of column (l/16) + 4r, and a
+// group of 16 lanes covers 16 consecutive rows of one column (one 128-byte
+// segment).  Wave w owns rows 64*(w%2) .. +63 and columns 64*(w/2) .. +63.
+// ---------------------------------------------------------------------------
+typedef d4 Acc[4][4];
+
+__device__ __forceinline__ void acc_zero(Acc& acc) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
+// Offset in a tile of element (row, col) held by register 0 of accumulator
+// (i, j) in this lane; register r adds 4*NB*r.
+__device__ __forceinline__ int acc_offset(int i, int j) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  return ((w & 1) * 64 + i * 16 + (lane & 15)) + NB * ((w >> 1) * 64 + j * 16 + (lane >> 4));
+}
+
+// One KC-deep panel step: acc += op(A)[:, k-panel] op(B)[k-panel, :] from the
+// LDS panels As, Bs (layout of panel_store).
+__device__ __forceinline__ void panel_mma(Acc& acc, const double* As, const double* Bs) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w & 1, wn = w >> 1, lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int ks = 0; ks < KC / 4; ++ks) {
+    const double* Ar = As + (4 * ks + lk) * LDS_STRIDE + wm * 64 + lr;
+    const double* Br = Bs + (4 * ks + lk) * LDS_STRIDE + wn * 64 + lr;
+    double a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      a[i] = Ar[16 * i];
+      b[i] = Br[16 * i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
+  }
+}
+
+// Chained product: acc += sum_{p < count} A_p B_p^T, where pair(p, a, b)
+// names the two contiguous tiles of link p.  Both operands are read along
+// stored columns.  The k-panels of all links form one double-buffered
+// stream through LDS (smem: 4 * PANEL doubles), so the first panel of link
+// p+1 is loaded while the last panel of link p is multiplied.  The pair
+// function must give the same pointers in every thread.  The accumulator is
+// never written to memory here.
+template <int CP, class PairFn>
+__device__ __forceinline__ void mma_chain(Acc& acc, int count, PairFn pair, double* smem) {
+  if (count <= 0) return;
+  const double *pa, *pb;
+  pair(0, pa, pb);
+  rsrc_t rA = tile_rsrc(pa), rB = tile_rsrc(pb);
+  d2 ra[PAIRS], rb[PAIRS];
+  panel_load<CP>(rA, 0, true, ra);
+  panel_load<CP>(rB, 0, true, rb);
+  panel_store(smem, 0, true, false, ra);
+  panel_store(smem + PANEL, 0, true, false, rb);
+  __syncthreads();
+  const int total = count * NCH;
+#pragma unroll 1
+  for (int g = 0; g < total; ++g) {
+    const double* As = smem + (g & 1) * 2 * PANEL;
+    const double* Bs = As + PANEL;
+    const bool more = g + 1 < total;
+    if (more) {
+      const int c1 = (g + 1) % NCH;
+      if (c1 == 0) {
+        pair((g + 1) / NCH, pa, pb);
+        rA = tile_rsrc(pa);
+        rB = tile_rsrc(pb);
+      }
+      panel_load<CP>(rA, c1 * KC, true, ra);
+      panel_load<CP>(rB, c1 * KC, true, rb);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    panel_mma(acc, As, Bs);
+    __builtin_amdgcn_sched_barrier(0);
+    if (more) {
+      double* An = smem + ((g + 1) & 1) * 2 * PANEL;
+      panel_store(An, 0, true, false, ra);
+      panel_store(An + PANEL, 0, true, false, rb);
+    }
+    __syncthreads();
+  }
+}
+
+// C <- s * acc for one output tile (s = +1 or -1, exact); `lower` skips the
+// block that lies strictly above the diagonal (rows 0-63 x columns 64-127).
+template <int CP>
+__device__ __forceinline__ void acc_store(double* C, const Acc& acc, bool neg, bool lower) {
+  const int w = threadIdx.x >> 6;
+  if (lower && w == 2) return;
+  const rsrc_t rC = tile_rsrc(C);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int off = acc_offset(i, j);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) st1<CP>(rC, off + NB * 4 * r, neg ? -acc[i][j][r] : acc[i][j][r]);
+    }
+}
+
+}  // namespace tile
+}  // namespace spdinv

@@ -72,3 +72,27 @@ def test_too_small_workspace_rejected():
     lib = _lib.load()
     assert lib.spd_inverse(512, 1, 512, 0, 1, 16, None, None, None, None) == _lib.ERR_WORKSPACE
     assert lib.spd_inverse(512, 1, 512, 0, None, 0, None, None, None, None) == -5
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 1, 1, 1, 1, 1, 1), -1),   # n < 0
+    ((4, 0, 4, 1, 4, 1, 4), -2),    # null X
+    ((4, 1, 3, 1, 4, 1, 4), -3),    # ldx < n
+    ((4, 1, 4, 0, 4, 1, 4), -4),    # null G
+    ((4, 1, 4, 1, 2, 1, 4), -5),    # ldg < n
+    ((4, 1, 4, 1, 4, 0, 4), -6),    # null gradA
+    ((4, 1, 4, 1, 4, 1, 1), -7),    # ldga < n
+])
+def test_backward_invalid_arguments_rejected_on_host(args, code):
+    lib = _lib.load()
+    n, x, ldx, g, ldg, ga, ldga = args
+    assert lib.spd_inverse_backward(n, x, ldx, g, ldg, ga, ldga, 1, 1 << 40, None) == code
+
+
+def test_backward_workspace():
+    lib = _lib.load()
+    assert lib.spd_inverse_backward_workspace_bytes(0) == 0
+    assert lib.spd_inverse_backward_workspace_bytes(129) == 3 * 4 * 128 * 128 * 8
+    assert lib.spd_inverse_backward(0, None, 1, None, 1, None, 1, None, 0, None) == 0
+    assert lib.spd_inverse_backward(8, 1, 8, 1, 8, 1, 8, None, 0, None) == -8
+    assert lib.spd_inverse_backward(8, 1, 8, 1, 8, 1, 8, 1, 16, None) == _lib.ERR_WORKSPACE
