@@ -118,6 +118,40 @@ int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t 
                 spdinv_stream_t stream, const spdinv_opts* opts, int* d_info,
                 spdinv_report* report);
 
+/* ---- batched form ---------------------------------------------------------- */
+/* Bytes of device workspace that batched_spd_inverse needs for these orders
+   on the current device (0 when batch <= 0 or an order is invalid). */
+size_t batched_spd_inverse_workspace_bytes(int batch, const int* h_n, spdinv_mode mode,
+                                           const spdinv_opts* opts);
+
+/*
+ * A_i <- A_i^{-1} for `batch` independent SPD matrices of uneven orders, in
+ * one persistent launch (plus a one-block sort that orders the matrices by
+ * decreasing n).  Each matrix is inverted by one workgroup: n <= 128 entirely
+ * in LDS, larger n through the tile plan of Section 3 executed in program
+ * order (the sequential task stream of Algorithm 1) on a private tile pool.
+ *   batch   number of matrices (>= 0)
+ *   h_n     host int[batch], orders 0 <= n_i <= 2048 (sizes the workspace)
+ *   d_n     device int[batch], the same orders
+ *   d_A     device array of batch device pointers, column-major matrices;
+ *           the lower triangle of each is read and overwritten
+ *   d_lda   device int[batch], leading dimensions (>= max(1, n_i))
+ *   work    device workspace of batched_spd_inverse_workspace_bytes bytes
+ *   opts    host or NULL: renamed, loop_order, trtri_first select the tile
+ *           plan; fill_upper mirrors each result; workers caps the grid
+ *   d_info  device int[batch] or NULL: INFO of each matrix (0, k > 0 as for
+ *           spd_inverse, or -1 when its d_n/d_lda entry is invalid on the
+ *           device or exceeds the orders given in h_n)
+ * Returns 0, -i for an invalid i-th argument, SPDINV_ERR_WORKSPACE or
+ * SPDINV_ERR_HIP.  The launch is asynchronous.  It allocates nothing once the
+ * tile plans for the tile counts present have been built by an earlier call,
+ * so such a call can be captured in a HIP graph.  The matrices must not
+ * overlap.
+ */
+int batched_spd_inverse(int batch, const int* h_n, const int* d_n, double* const* d_A,
+                        const int* d_lda, spdinv_mode mode, void* work, size_t work_bytes,
+                        spdinv_stream_t stream, const spdinv_opts* opts, int* d_info);
+
 /* ---- backward ------------------------------------------------------------- */
 /* Bytes of device workspace that spd_inverse_backward needs for order n
    (three square tile-major matrices of ceil(n/128)*128). */

@@ -8,6 +8,7 @@ Main entry points
 -----------------
 ``spd_inverse(a)``      full symmetric A^{-1} of a CUDA float64 tensor
 ``spd_inverse_(a_cm)``  in place on a column-major view (lower triangle)
+``batched_spd_inverse(mats)``   many uneven matrices in one persistent launch
 ``spd_inverse_backward(x, g)``  -X sym(G) X, the adjoint of the inverse
 ``SpdInverse.apply(a)`` autograd Function (forward + backward on the GPU)
 ``plan_stats(t)``       planner statistics (critical paths of Table 1)
@@ -24,6 +25,7 @@ from ._lib import LibraryNotBuilt, load, make_opts, TASK_NAMES  # noqa: F401
 
 __all__ = ["spd_inverse", "spd_inverse_", "workspace_bytes", "plan_stats", "plan_export",
            "spd_inverse_backward", "backward_workspace_bytes", "SpdInverse", "spd_inverse_ad",
+           "batched_spd_inverse", "batched_spd_inverse_", "batched_workspace_bytes",
            "SpdInverseError", "NotPositiveDefinite"]
 
 
@@ -97,6 +99,82 @@ def spd_inverse(a, **opts):
     rep = spd_inverse_(buf.t(), fill_upper=1, report=True, **opts) if n else None
     del rep
     return buf.t().contiguous() if n else torch.empty_like(a)
+
+
+def _int_array(values):
+    arr = (ctypes.c_int * max(1, len(values)))(*[int(v) for v in values])
+    return arr
+
+
+def batched_workspace_bytes(orders, **opts) -> int:
+    o = make_opts(**opts)
+    arr = _int_array(orders)
+    return int(load().batched_spd_inverse_workspace_bytes(len(orders), arr, _lib.SPDINV_FP64,
+                                                          ctypes.byref(o)))
+
+
+def batched_spd_inverse_(ptrs, orders, n_dev, lda_dev, *, work=None, info=None, **opts):
+    """Low-level batched call: ``ptrs`` a CUDA int64 tensor of device pointers
+    to column-major matrices, ``orders`` the host list of orders, ``n_dev`` and
+    ``lda_dev`` CUDA int32 tensors, ``info`` an optional CUDA int32 tensor of
+    the batch size.  Asynchronous on the current stream; returns ``work``."""
+    import torch
+    batch = len(orders)
+    lib = load()
+    o = make_opts(**opts)
+    h_n = _int_array(orders)
+    need = int(lib.batched_spd_inverse_workspace_bytes(batch, h_n, _lib.SPDINV_FP64,
+                                                       ctypes.byref(o)))
+    if batch and need == 0:
+        raise ValueError("invalid orders (0 <= n <= 2048) or no device")
+    dev = ptrs.device
+    if work is None:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    elif work.numel() * work.element_size() < need:
+        raise ValueError(f"workspace too small: need {need} bytes")
+    rc = lib.batched_spd_inverse(batch, h_n, n_dev.data_ptr(), ptrs.data_ptr(), lda_dev.data_ptr(),
+                                 _lib.SPDINV_FP64, work.data_ptr(), need, _stream_ptr(dev),
+                                 ctypes.byref(o), info.data_ptr() if info is not None else None)
+    if rc != 0:
+        raise SpdInverseError(f"batched_spd_inverse returned {rc}")
+    return work
+
+
+def batched_spd_inverse(mats, **opts):
+    """Full symmetric inverses of a list of square CUDA float64 tensors (the
+    lower triangle of each is read), computed in one batched launch.  Raises
+    NotPositiveDefinite for the first matrix whose INFO is positive."""
+    import torch
+    if not mats:
+        return []
+    dev = mats[0].device
+    orders = [int(m.shape[0]) for m in mats]
+    sizes = [max(1, n) * max(1, n) for n in orders]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    buf = torch.empty(int(offs[-1]), dtype=torch.float64, device=dev)
+    for m, n, off in zip(mats, orders, offs[:-1]):
+        if n:
+            # column-major storage of m: its lower triangle is m's lower triangle
+            buf[int(off):int(off) + n * n].view(n, n).copy_(m.t())
+    base = buf.data_ptr()
+    ptrs = torch.tensor([base + 8 * int(o) for o in offs[:-1]], dtype=torch.int64, device=dev)
+    n_dev = torch.tensor(orders, dtype=torch.int32, device=dev)
+    lda_dev = torch.tensor([max(1, n) for n in orders], dtype=torch.int32, device=dev)
+    info = torch.zeros(len(mats), dtype=torch.int32, device=dev)
+    opts.setdefault("fill_upper", 1)
+    batched_spd_inverse_(ptrs, orders, n_dev, lda_dev, info=info, **opts)
+    inf = info.cpu().numpy()
+    bad = np.nonzero(inf != 0)[0]
+    if len(bad):
+        k = int(bad[0])
+        if inf[k] > 0:
+            raise NotPositiveDefinite(int(inf[k]))
+        raise SpdInverseError(f"matrix {k}: INFO {int(inf[k])}")
+    out = []
+    for n, off in zip(orders, offs[:-1]):
+        out.append(buf[int(off):int(off) + n * n].view(n, n).t() if n else
+                   torch.empty((0, 0), dtype=torch.float64, device=dev))
+    return out
 
 
 def backward_workspace_bytes(n: int) -> int:

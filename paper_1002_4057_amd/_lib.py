@@ -83,6 +83,11 @@ def load():
     lib.spdinv_kernel_timer.restype = i
     lib.spdinv_kernel_timer_read.argtypes = [P(ctypes.c_longlong)]
     lib.spdinv_kernel_timer_read.restype = ctypes.c_double
+    ip = P(ctypes.c_int)
+    lib.batched_spd_inverse_workspace_bytes.argtypes = [i, ip, i, P(Opts)]
+    lib.batched_spd_inverse_workspace_bytes.restype = sz
+    lib.batched_spd_inverse.argtypes = [i, ip, vp, vp, vp, i, vp, sz, vp, P(Opts), vp]
+    lib.batched_spd_inverse.restype = i
     lib.spd_inverse_backward_workspace_bytes.argtypes = [i]
     lib.spd_inverse_backward_workspace_bytes.restype = sz
     lib.spd_inverse_backward.argtypes = [i, vp, i, vp, i, vp, i, vp, sz, vp]

@@ -298,6 +298,118 @@ int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t 
   return 0;
 }
 
+}  // extern "C"
+
+namespace {
+
+struct BatchLayout {
+  size_t order, ctrl, pool, total;
+  int grid, tmax, maxn;
+  long long pool_tiles;
+};
+
+int batched_grid(int device, const spdinv_opts& o) {
+  static std::map<int, int> grids;
+  int g;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = grids.find(device);
+    if (it != grids.end()) {
+      g = it->second;
+    } else {
+      int cus = 0;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+          cus <= 0)
+        cus = 1;
+      g = cus * batched_blocks_per_cu();
+      grids[device] = g;
+    }
+  }
+  if (o.workers > 0 && o.workers < g) g = o.workers;
+  return g;
+}
+
+// Returns 0, or -2 when an order is negative or above the supported maximum.
+int batch_layout(int batch, const int* h_n, int grid, BatchLayout* L) {
+  int maxn = 0;
+  for (int i = 0; i < batch; ++i) {
+    if (h_n[i] < 0 || h_n[i] > MAX_BATCH_T * NB) return -2;
+    if (h_n[i] > maxn) maxn = h_n[i];
+  }
+  L->maxn = maxn;
+  L->tmax = (maxn + NB - 1) / NB;
+  L->grid = grid;
+  L->pool_tiles = L->tmax >= 2 ? pool_tiles(L->tmax) : 0;
+  L->order = 256;  // [0, 256): dispatch ticket
+  L->ctrl = L->order + align_up((size_t)batch * sizeof(int32_t), 256);
+  L->pool = L->ctrl + align_up((size_t)grid * CTRL_WORDS * sizeof(int32_t), 256);
+  L->total = L->pool + (size_t)grid * (size_t)L->pool_tiles * NB * NB * sizeof(double);
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t batched_spd_inverse_workspace_bytes(int batch, const int* h_n, spdinv_mode mode,
+                                           const spdinv_opts* opts) {
+  (void)mode;
+  if (batch <= 0 || !h_n) return 0;
+  const spdinv_opts o = opts ? *opts : defaults();
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return 0;
+  BatchLayout L;
+  if (batch_layout(batch, h_n, batched_grid(device, o), &L)) return 0;
+  return L.total;
+}
+
+int batched_spd_inverse(int batch, const int* h_n, const int* d_n, double* const* d_A,
+                        const int* d_lda, spdinv_mode mode, void* work, size_t work_bytes,
+                        spdinv_stream_t stream_, const spdinv_opts* opts, int* d_info) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  if (batch < 0) return -1;
+  if (batch == 0) return 0;
+  if (!h_n) return -2;
+  if (!d_n) return -3;
+  if (!d_A) return -4;
+  if (!d_lda) return -5;
+  if (mode != SPDINV_FP64) return -6;
+  const spdinv_opts o = opts ? *opts : defaults();
+  if (check_opts(o)) return -10;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return SPDINV_ERR_HIP;
+  BatchLayout L;
+  if (batch_layout(batch, h_n, batched_grid(device, o), &L)) return -2;
+  if (!work) return -7;
+  if (work_bytes < L.total) return SPDINV_ERR_WORKSPACE;
+
+  BatchArgs b;
+  std::memset(&b, 0, sizeof(b));
+  for (int t = 2; t <= L.tmax; ++t) {
+    hipError_t err = hipSuccess;
+    // program-order execution by one workgroup: the plan's task list as built
+    DevPlan* dp = get_plan(device, t, o, 1, &err);
+    if (!dp) return SPDINV_ERR_HIP;
+    b.plan[t] = dp->d_tasks;
+    b.plan_ntask[t] = (int)dp->host.tasks.size();
+  }
+  char* w = (char*)work;
+  b.n = d_n;
+  b.A = d_A;
+  b.lda = d_lda;
+  b.info = d_info;
+  b.order = (const int32_t*)(w + L.order);
+  b.batch = batch;
+  b.ticket = (int32_t*)w;
+  b.pool = (double*)(w + L.pool);
+  b.pool_tiles = L.pool_tiles;
+  b.ctrl = (int32_t*)(w + L.ctrl);
+  b.tmax = L.tmax;
+  b.fill_upper = o.fill_upper ? 1 : 0;
+  if (launch_batched(b, L.grid, L.maxn, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  return 0;
+}
+
 size_t spd_inverse_backward_workspace_bytes(int n) {
   if (n <= 0) return 0;
   const size_t t = (size_t)tiles_for(n);

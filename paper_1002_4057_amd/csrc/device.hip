@@ -1,473 +1,13 @@
-// HIP kernels for gfx950 (MI355X): the tile tasks of the SPD inverse and the
-// persistent, dependency-tracked scheduler that runs them.
-//
-// Tiles are NB x NB (NB = 128) binary64, column-major, each contiguous
-// (128 KiB).  One workgroup of 256 threads (4 wave64) executes one task at a
-// time; every task kind of the paper's Algorithm 1 maps to one of
-//   * a tile product on the FP64 matrix cores (v_mfma_f64_16x16x4),
-//     C = beta*C + alpha*op(A)*op(B) with optional triangular masking of an
-//     operand and a lower-only output, staged through LDS in k-panels, and
-//     an optional second destination (the renaming copy of Section 3);
-//   * the diagonal-tile factorization POTRF, which also produces the inverse
-//     of the factor tile, computed with the tile resident in registers
-//     (2D cyclic over a 16 x 16 thread grid), pivot columns and rows broadcast
-//     through LDS and the finished factor kept in LDS for the inverse;
-//   * a tile copy (TRTRI reuses the inverse made by POTRF, bit for bit).
+// HIP kernels for gfx950 (MI355X): the persistent, dependency-tracked
+// scheduler that runs the tile tasks of one SPD inverse (tile_tasks.hpp), and
+// the copies between the caller's column-major matrix and the tile pool.
 #include "device.hpp"
-#include "mfma_tile.hpp"
+#include "tile_tasks.hpp"
 
 #include <climits>
 
 namespace spdinv {
 namespace {
-
-using namespace tile;
-
-constexpr int POTRF_SMEM = NB * (NB + 1) + 12 * 256 + 8;  // tile + diagonal inverses + scratch
-constexpr int SMEM_DOUBLES = GEMM_SMEM > POTRF_SMEM ? GEMM_SMEM : POTRF_SMEM;
-
-// ---------------------------------------------------------------------------
-// Tile product on the FP64 matrix cores.
-//   C (+)= (F_NEG ? -1 : 1) * op(A) * op(B),   op(A) = F_TA ? A^T : A,
-//                                              op(B) = F_TB ? B^T : B
-// (FAST: the renamed plan's case op(A) = A, op(B) = B^T without masks)
-// F_ACC: accumulate into C (else overwrite).  F_MA/F_MB: the operand tile is
-// lower triangular.  F_LOWER: only the output blocks on or below the diagonal
-// are stored (the wave owning rows 0-63 x columns 64-127 computes but does
-// not store: it runs alone on its SIMD, so skipping its work would save no
-// time).  C may alias A or B: every operand read precedes the first store.
-// copy (may be null) receives the same result, transposed with F_COPYT.
-// Waves form a 2 x 2 grid of 64 x 64 output blocks, each a 4 x 4 array of
-// 16 x 16 MFMA accumulators.  The sign is handled without touching the
-// operands: the accumulator starts from -C and the result is negated on the
-// way out (both exact), so that C - P is rounded exactly like -(-C + P).
-// The panels are double-buffered in LDS; the next panel's global loads are
-// issued before the current panel's MFMAs and consumed after them
-// (scheduling barriers keep the compiler from pulling their consumers into
-// the MFMA sequence).
-// ---------------------------------------------------------------------------
-template <bool FAST>
-__device__ __forceinline__ void tile_mma(int f, double* C, const double* A, const double* B,
-                                         double* copy, double* smem) {
-  const int lane = threadIdx.x & 63;
-  const int w = threadIdx.x >> 6;
-  const int wm = w & 1, wn = w >> 1;
-  const int lr = lane & 15, lk = lane >> 4;
-  // FAST: op(A) = A, op(B) = B^T, no triangular masks (both operands read
-  // along contiguous columns); otherwise every flag is honoured
-  const bool a_contig = FAST || !(f & F_TA), b_contig = FAST || (f & F_TB) != 0;
-  const bool ma = !FAST && (f & F_MA) != 0, mb = !FAST && (f & F_MB) != 0;
-  const bool neg = (f & F_NEG) != 0, copy_t = (f & F_COPYT) != 0;
-  const rsrc_t rA = tile_rsrc(A), rB = tile_rsrc(B), rC = tile_rsrc(C);
-  const bool accum = (f & F_ACC) != 0;
-  const bool active = !((f & F_LOWER) && wm == 0 && wn == 1);
-
-  // v_mfma_f64_16x16x4(x, y, d): d[i][j] += sum_k x[i][k] y[k][j] with x[i][k]
-  // from lane i+16k, y[k][j] from lane j+16k, and d[i][j] in register r = i/4
-  // of lane j + 16*(i%4).  The operands are passed as (op(B) block, op(A)
-  // block), so that d is the transposed 16x16 output block: lane l, register
-  // r holds output row (l%16) of column (l/16) + 4r, and a group of 16 lanes
-  // covers 16 consecutive rows of one column (one 128-byte segment).
-  d4 acc[4][4];
-  if (accum) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int off = (wm * 64 + i * 16 + lr) + NB * (wn * 64 + j * 16 + lk);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[i][j][r] = ld1(rC, off + NB * 4 * r);
-      }
-    if (neg) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = -acc[i][j];
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  }
-
-  d2 ra[PAIRS], rb[PAIRS];
-  panel_load(rA, 0, a_contig, ra);
-  panel_load(rB, 0, b_contig, rb);
-  panel_store(smem, 0, a_contig, ma, ra);
-  panel_store(smem + PANEL, 0, b_contig, mb, rb);
-  __syncthreads();
-
-#pragma unroll 1
-  for (int c = 0; c < NCH; ++c) {
-    const double* As = smem + (c & 1) * 2 * PANEL;
-    const double* Bs = As + PANEL;
-    const bool more = c + 1 < NCH;
-    if (more) {
-      panel_load(rA, (c + 1) * KC, a_contig, ra);
-      panel_load(rB, (c + 1) * KC, b_contig, rb);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int ks = 0; ks < KC / 4; ++ks) {
-      const double* Ar = As + (4 * ks + lk) * LDS_STRIDE + wm * 64 + lr;
-      const double* Br = Bs + (4 * ks + lk) * LDS_STRIDE + wn * 64 + lr;
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = Ar[16 * i];
-        b[i] = Br[16 * i];
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    if (more) {
-      double* An = smem + ((c + 1) & 1) * 2 * PANEL;
-      panel_store(An, (c + 1) * KC, a_contig, ma, ra);
-      panel_store(An + PANEL, (c + 1) * KC, b_contig, mb, rb);
-    }
-    __syncthreads();
-  }
-
-  if (active) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int off = (wm * 64 + i * 16 + lr) + NB * (wn * 64 + j * 16 + lk);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) st1(rC, off + NB * 4 * r, neg ? -acc[i][j][r] : acc[i][j][r]);
-      }
-  }
-  if (!copy) return;  // uniform: the copy pointer is the same in every thread
-  // renaming copy (as is, or transposed with F_COPYT): the result is staged
-  // in LDS as R[col + RLD * row] (odd stride RLD, conflict-free for these
-  // writes), then leaves as contiguous 16-byte stores; the panels are no
-  // longer in use after the k-loop's last barrier
-  constexpr int RLD = NB + 1;
-  double* R = smem;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = wm * 64 + i * 16 + lr, col0 = wn * 64 + j * 16 + lk;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) R[(col0 + 4 * r) + RLD * row] = neg ? -acc[i][j][r] : acc[i][j][r];
-    }
-  __syncthreads();
-  const rsrc_t rD = tile_rsrc(copy);
-#pragma unroll 4
-  for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
-    const int e = 2 * (threadIdx.x + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
-    d2 v;  // copy element (rr, cc) is result(cc, rr) or result(rr, cc)
-    if (copy_t) {
-      v.x = R[rr + RLD * cc];
-      v.y = R[rr + 1 + RLD * cc];
-    } else {
-      v.x = R[cc + RLD * rr];
-      v.y = R[cc + RLD * (rr + 1)];
-    }
-    st2(rD, e, v);
-  }
-}
-
-// The general product (transposed or triangular operands) serves only the
-// in-place plan; it is kept out of line so that its registers do not weigh
-// on the inlined fast product.
-__device__ __attribute__((noinline)) void tile_mma_general(int f, double* C, const double* A,
-                                                           const double* B, double* copy,
-                                                           double* smem) {
-  tile_mma<false>(f, C, A, B, copy, smem);
-}
-
-// ---------------------------------------------------------------------------
-// Diagonal tile: Cholesky factor L of the lower triangle of A and its inverse
-// X = L^{-1}, blocked by 16 (tile held in LDS, column-major, ld = NB):
-//   for each 16-column panel p:
-//     one wave factors the 16 x 16 diagonal block and inverts the factor
-//     (diag16: pivots broadcast with readlane, one row per lane);
-//     L_ip = A_ip X_pp^T for the blocks below it (16x16x16 MFMA blocks);
-//     A_ij -= L_ip L_jp^T on the trailing lower blocks (MFMA).
-//   Then X by block forward substitution, one block column per wave:
-//     X_ip = -X_ii (sum_{m=p..i-1} L_im X_mp).
-// MFMA 16x16 blocks use the same lane layout as tile_mma: lane l, register r
-// holds row l%16, column l/16 + 4r of the block.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double readlane_d(double v, int lane) {
-  const unsigned long long u = __double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, lane);
-  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), lane);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// Cholesky factor and inverse of the 16 x 16 block at S (column-major, ld),
-// executed by one whole wave; lane r (mod 16) holds row r.  Writes L (zeros
-// above the diagonal) back to S and X = L^{-1} to XD (16 x 16, ld 16).
-// Returns 0 or the 1-based index of the first non-positive pivot (uniform).
-__device__ __forceinline__ int diag16(double* S, int ld, double* XD) {
-  const int r = threadIdx.x & 15;
-  double row[16], x[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    row[c] = (c <= r) ? S[r + ld * c] : 0.0;
-    x[c] = (c == r) ? 1.0 : 0.0;
-  }
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const double d = readlane_d(row[k], k);
-    if (!(d > 0.0)) return k + 1;  // d is a scalar: uniform exit
-    // 1/sqrt(d) from the hardware estimate and one Newton step
-    // (y <- y + y (1 - d y^2) / 2), then sqrt(d) = d / sqrt(d)
-    double rinv = __builtin_amdgcn_rsq(d);
-    const double h = d * rinv;
-    rinv = fma(rinv * 0.5, fma(-h, rinv, 1.0), rinv);
-    const double lkk = d * rinv;
-    // column k of L: scale below the pivot
-    row[k] = (r > k) ? row[k] * rinv : ((r == k) ? lkk : row[k]);
-    // right-looking update of the trailing rows with column k
-#pragma unroll
-    for (int c = k + 1; c < 16; ++c) {
-      const double lck = readlane_d(row[k], c);
-      if (c <= r) row[c] = fma(-row[k], lck, row[c]);
-    }
-    // inverse, row k of X is final: scale it, then update the rows below
-    if (r == k) {
-#pragma unroll
-      for (int c = 0; c <= k; ++c) x[c] *= rinv;
-    }
-#pragma unroll
-    for (int c = 0; c <= k; ++c) {
-      const double xkc = readlane_d(x[c], k);
-      if (r > k) x[c] = fma(-row[k], xkc, x[c]);
-    }
-  }
-  if ((threadIdx.x & 63) < 16) {
-#pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      S[r + ld * c] = (c <= r) ? row[c] : 0.0;
-      XD[r + 16 * c] = (c <= r) ? x[c] : 0.0;
-    }
-  }
-  return 0;
-}
-
-// acc (one 16x16 block, MFMA layout) += A_blk * op(B)_blk over K = 16, with
-// A_blk[m][k] = A[m + lda*k] and op(B)_blk[k][n] = B[n + ldb*k] (tb, i.e. the
-// block B^T of a column-major B) or B[k + ldb*n] (!tb).
-__device__ __forceinline__ d4 blk_mma16(d4 acc, const double* A, int lda, const double* B, int ldb,
-                                        bool tb) {
-  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
-#pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
-    const int k = 4 * kk + lk;
-    const double a = A[lr + lda * k];
-    const double b = tb ? B[lr + ldb * k] : B[k + ldb * lr];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, acc, 0, 0, 0);
-  }
-  return acc;
-}
-
-__device__ __forceinline__ d4 blk_load(const double* S, int ld) {
-  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
-  return d4{S[lr + ld * lk], S[lr + ld * (lk + 4)], S[lr + ld * (lk + 8)], S[lr + ld * (lk + 12)]};
-}
-
-__device__ __forceinline__ void blk_store(double* S, int ld, d4 v) {
-  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) S[lr + ld * (lk + 4 * q)] = v[q];
-}
-
-// Outputs: the factor (Lout), its transpose (LcopyT, may be null), the
-// inverse of the factor (Xout) and its transpose (XoutT), each with explicit
-// zeros in the other triangle.  Returns 0, or the 1-based local index of the
-// first pivot that is not positive (or NaN); on failure nothing is stored.
-__device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, double* Lout,
-                                                         double* LcopyT, double* Xout,
-                                                         double* XoutT, double* smem) {
-  constexpr int LD = NB + 1;           // odd row stride: transposed LDS reads spread over banks
-  double* T = smem;                    // [NB * LD] the tile, column-major
-  double* XD = smem + NB * LD;         // [8][256] inverses of the diagonal blocks
-  double* SCR = XD + 8 * 256;          // [4][256] per-wave scratch block
-  int* flag = reinterpret_cast<int*>(SCR + 4 * 256);
-  const int tid = threadIdx.x, w = tid >> 6;
-  const rsrc_t rIn = tile_rsrc(Ain), rL = tile_rsrc(Lout), rX = tile_rsrc(Xout),
-               rXT = tile_rsrc(XoutT);
-
-  // load the tile: batches of independent 16-byte loads, so that their
-  // latencies overlap
-  for (int e0 = 0; e0 < NB * NB; e0 += 2 * NTHREADS * 16) {
-    d2 v[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = ld2(rIn, e0 + 2 * (tid + NTHREADS * u));
-#pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = e0 + 2 * (tid + NTHREADS * u), rr = e & (NB - 1), cc = e >> 7;
-      T[rr + LD * cc] = (rr >= cc) ? v[u].x : 0.0;
-      T[rr + 1 + LD * cc] = (rr + 1 >= cc) ? v[u].y : 0.0;
-    }
-  }
-  __syncthreads();
-
-  for (int p = 0; p < 8; ++p) {
-    double* Dpp = T + 16 * p * (LD + 1);
-    if (w == 0) {
-      const int f = diag16(Dpp, LD, XD + 256 * p);
-      if (tid == 0) *flag = f ? 16 * p + f : 0;
-    }
-    __syncthreads();
-    const int fail = __builtin_amdgcn_readfirstlane(*flag);
-    if (fail) return fail;
-    // panel: L_ip = A_ip X_pp^T
-    for (int i = p + 1 + w; i < 8; i += 4) {
-      double* Bip = T + 16 * i + LD * 16 * p;
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
-      acc = blk_mma16(acc, Bip, LD, XD + 256 * p, 16, true);
-      blk_store(Bip, LD, acc);
-    }
-    __syncthreads();
-    // trailing update: A_ij -= L_ip L_jp^T, p < j <= i
-    const int nb = 7 - p;
-    for (int q = w; q < nb * (nb + 1) / 2; q += 4) {
-      int i = 0;
-      while ((i + 1) * (i + 2) / 2 <= q) ++i;
-      const int j = q - i * (i + 1) / 2;
-      const int bi = p + 1 + i, bj = p + 1 + j;
-      double* Cij = T + 16 * bi + LD * 16 * bj;
-      d4 acc = -blk_load(Cij, LD);
-      acc = blk_mma16(acc, T + 16 * bi + LD * 16 * p, LD, T + 16 * bj + LD * 16 * p, LD, true);
-      blk_store(Cij, LD, -acc);
-    }
-    __syncthreads();
-  }
-
-  // the factor: global copies (and its transpose)
-  // the factor and its transpose, as contiguous 16-byte stores (the
-  // transpose is taken on the LDS side)
-  const rsrc_t rLT = tile_rsrc(LcopyT ? LcopyT : Lout);
-#pragma unroll 4
-  for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
-    const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
-    d2 v;
-    v.x = (rr >= cc) ? T[rr + LD * cc] : 0.0;
-    v.y = (rr + 1 >= cc) ? T[rr + 1 + LD * cc] : 0.0;
-    st2(rL, e, v);
-    if (LcopyT) {  // element (rr, cc) of L^T is L(cc, rr)
-      d2 u;
-      u.x = (cc >= rr) ? T[cc + LD * rr] : 0.0;
-      u.y = (cc >= rr + 1) ? T[cc + LD * (rr + 1)] : 0.0;
-      st2(rLT, e, u);
-    }
-  }
-  __syncthreads();  // the inverse below writes the upper blocks of T
-
-  // inverse by block columns; wave w takes columns w and 7 - w.  X_mp for
-  // m > p is kept transposed in the (unused) upper block (p, m) of T.
-  double* scr = SCR + 256 * w;
-  for (int side = 0; side < 2; ++side) {
-    const int p = side ? 7 - w : w;
-    for (int i = p + 1; i < 8; ++i) {
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
-      // L_ip X_pp
-      acc = blk_mma16(acc, T + 16 * i + LD * 16 * p, LD, XD + 256 * p, 16, false);
-      for (int m = p + 1; m < i; ++m)  // L_im X_mp, X_mp^T stored at block (p, m)
-        acc = blk_mma16(acc, T + 16 * i + LD * 16 * m, LD, T + 16 * p + LD * 16 * m, LD, true);
-      blk_store(scr, 16, acc);
-      d4 xip = {0.0, 0.0, 0.0, 0.0};
-      xip = blk_mma16(xip, XD + 256 * i, 16, scr, 16, false);  // X_ii S
-      xip = -xip;
-      // X_ip transposed into block (p, i) of T
-      const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) T[(16 * p + lk + 4 * q) + LD * (16 * i + lr)] = xip[q];
-    }
-  }
-  __syncthreads();
-  // X and X^T as contiguous 16-byte stores: X(r, c) is XD for diagonal
-  // blocks, T(c, r) below them (stored transposed), zero above
-  auto xval = [&](int r, int c) -> double {
-    const int br = r >> 4, bc = c >> 4;
-    if (br == bc) return XD[256 * br + (r & 15) + 16 * (c & 15)];
-    return (br > bc) ? T[c + LD * r] : 0.0;
-  };
-#pragma unroll 4
-  for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
-    const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
-    d2 v, u;
-    v.x = xval(rr, cc);
-    v.y = xval(rr + 1, cc);
-    u.x = xval(cc, rr);
-    u.y = xval(cc, rr + 1);
-    st2(rX, e, v);
-    st2(rXT, e, u);
-  }
-  return 0;
-}
-
-// dst <- src for one tile; loads are issued in batches of 16 independent
-// 16-byte loads per thread so that their latencies overlap.
-__device__ __forceinline__ void tile_copy(const double* src, double* dst) {
-  const rsrc_t rs = tile_rsrc(src), rd = tile_rsrc(dst);
-#pragma unroll
-  for (int h = 0; h < (int)(TILE / 2) / (NTHREADS * 16); ++h) {
-    d2 v[16];
-#pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = ld2(rs, 2 * (h * NTHREADS * 16 + threadIdx.x + NTHREADS * u));
-#pragma unroll
-    for (int u = 0; u < 16; ++u) st2(rd, 2 * (h * NTHREADS * 16 + threadIdx.x + NTHREADS * u), v[u]);
-  }
-}
-
-// A task's results are published when its agent-coherent stores have
-// completed: every thread waits for its outstanding memory operations before
-// the workgroup barrier that precedes the successors' counter decrements.
-__device__ __forceinline__ void stores_complete() { __builtin_amdgcn_s_waitcnt(0); }
-
-__device__ __forceinline__ long long now_ticks() {
-  return (long long)__builtin_amdgcn_s_memrealtime();
-}
-
-__device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, double* smem, int T,
-                                         int tiles) {
-  double* P = g.pool;
-  const int kind = t.kind & 0xff, f = (t.kind >> 8) & 0xff;  // see DevTask::kind
-  double* out = t.out >= 0 ? tile_ptr(P, t.out) : nullptr;
-  const double* a = t.a >= 0 ? tile_ptr(P, t.a) : nullptr;
-  const double* b = t.b >= 0 ? tile_ptr(P, t.b) : nullptr;
-  double* cp = t.copy >= 0 ? tile_ptr(P, t.copy) : nullptr;
-  switch (kind) {
-    case K_SYRK1: case K_GEMM1: case K_TRSM1: case K_TRMM2L: case K_GEMM2: case K_TRSM2R:
-    case K_TRMM3: case K_LAUUM: case K_GEMM3: case K_SYRK3:
-      // tile products; the planner chose operands and flags (Algorithm 1's
-      // operation on the renamed or in-place tiles)
-      if ((f & (F_TA | F_MA | F_MB)) == 0 && (f & F_TB))
-        tile_mma<true>(f, out, a, b, cp, smem);
-      else
-        tile_mma_general(f, out, a, b, cp, smem);
-      break;
-    case K_POTRF: {
-      double* X = tile_ptr(P, t.aux);
-      double* Xt = tile_ptr(P, t.aux + tiles);
-      const int fl = potrf_inv_tile(out, out, cp, X, Xt, smem);
-      if (fl && threadIdx.x == 0) {
-        const int jt = t.aux - 3 * T;  // diagonal tile index
-        atomicMin(&g.ctrl[CTRL_INFO], g.info_base + jt * NB + fl);
-        __hip_atomic_store(&g.ctrl[CTRL_FAILED], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      break;
-    }
-    case K_TRTRI:   // A_jj <- D_j, and C_jj <- D_j^T (inverse made by POTRF(j))
-      tile_copy(a, out);
-      if (cp) tile_copy(b, cp);
-      break;
-    default:
-      break;
-  }
-}
 
 // Persistent worker loop.  Thread 0 of each workgroup is the only one that
 // talks to the scheduler state: at the head of every iteration it first

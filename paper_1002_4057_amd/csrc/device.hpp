@@ -37,6 +37,32 @@ struct SchedArgs {
   long long spin_limit;  // longest dependency wait, in 100 MHz clock ticks
 };
 
+// Batched form (one persistent launch over many matrices).
+constexpr int MAX_BATCH_T = 16;  // largest tile count per matrix (n <= 2048)
+
+struct BatchArgs {
+  const int* n;            // device, order of each matrix
+  double* const* A;        // device array of device pointers (column-major)
+  const int* lda;          // device, leading dimensions
+  int* info;               // device INFO per matrix (may be nullptr)
+  const int32_t* order;    // workspace: dispatch order (written by the sort)
+  int batch;
+  int32_t* ticket;         // workspace: dispatch counter
+  double* pool;            // workspace: pool_tiles per workgroup
+  long long pool_tiles;    // tiles per workgroup pool
+  int32_t* ctrl;           // workspace: CTRL_WORDS per workgroup
+  int tmax;                // largest tile count the pools are sized for
+  int fill_upper;
+  const DevTask* plan[MAX_BATCH_T + 1];  // program-order plan per tile count
+  int plan_ntask[MAX_BATCH_T + 1];
+};
+
+// Sort by decreasing order (device-side), then the persistent batched kernel.
+hipError_t launch_batched(const BatchArgs& b, int grid, int maxn, hipStream_t s);
+
+// Persistent workgroups per CU that fit for the batched kernel.
+int batched_blocks_per_cu();
+
 // Resets the in-degree counters and the control block (a fill kernel, so
 // that the sequence stays capturable in a graph).
 hipError_t launch_reset(const int32_t* indeg0, int32_t* indeg, int ntask, int32_t* ctrl,

@@ -96,3 +96,17 @@ def test_backward_workspace():
     assert lib.spd_inverse_backward(0, None, 1, None, 1, None, 1, None, 0, None) == 0
     assert lib.spd_inverse_backward(8, 1, 8, 1, 8, 1, 8, None, 0, None) == -8
     assert lib.spd_inverse_backward(8, 1, 8, 1, 8, 1, 8, 1, 16, None) == _lib.ERR_WORKSPACE
+
+
+def test_batched_invalid_arguments_rejected_on_host():
+    lib = _lib.load()
+    n = (ctypes.c_int * 2)(4, 5)
+    assert lib.batched_spd_inverse(-1, n, 1, 1, 1, 0, 1, 1 << 40, None, None, None) == -1
+    assert lib.batched_spd_inverse(0, None, None, None, None, 0, None, 0, None, None, None) == 0
+    assert lib.batched_spd_inverse(2, None, 1, 1, 1, 0, 1, 1 << 40, None, None, None) == -2
+    assert lib.batched_spd_inverse(2, n, None, 1, 1, 0, 1, 1 << 40, None, None, None) == -3
+    assert lib.batched_spd_inverse(2, n, 1, None, 1, 0, 1, 1 << 40, None, None, None) == -4
+    assert lib.batched_spd_inverse(2, n, 1, 1, None, 0, 1, 1 << 40, None, None, None) == -5
+    assert lib.batched_spd_inverse(2, n, 1, 1, 1, 2, 1, 1 << 40, None, None, None) == -6
+    o = spd.make_opts(nb=64)
+    assert lib.batched_spd_inverse(2, n, 1, 1, 1, 0, 1, 1 << 40, None, ctypes.byref(o), None) == -10

@@ -1,0 +1,183 @@
+"""GPU parity of batched_spd_inverse (through the C-ABI) against the FP64
+oracle, matrix by matrix.
+
+Bar: relative Frobenius error <= 1e-12 * kappa_2(A_i) for every matrix.
+Matrices above one tile run the same tile tasks in the same per-tile order
+as the single-matrix call, so those results must agree with spd_inverse bit
+for bit.  At the full batched workload (8192 matrices, n uniform on
+[16, 512]) a seeded sample is compared with the oracle and every matrix is
+checked through its residual ||I - A X||."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1002_4057_amd as spd
+from paper_1002_4057_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+def rel_fro(x, y):
+    return np.linalg.norm(x - y) / np.linalg.norm(y)
+
+
+def kappa(a):
+    ev = np.linalg.eigvalsh(a)
+    return ev[-1] / ev[0]
+
+
+EDGE_ORDERS = [1, 2, 3, 15, 16, 17, 31, 100, 127, 128, 129, 200, 255, 256, 257, 300, 384, 385,
+               511, 512]
+
+
+def test_edge_orders_against_oracle():
+    mats = inputs.batched_wishart(EDGE_ORDERS, seed=7, shift=0.1)
+    got = spd.batched_spd_inverse([m.to(DEV) for m in mats])
+    for n, a, x in zip(EDGE_ORDERS, mats, got):
+        an = a.numpy()
+        ref = oracle.spd_inverse(an)
+        xn = x.cpu().numpy()
+        assert rel_fro(xn, ref) <= 1e-12 * kappa(an), n
+        assert np.array_equal(xn, xn.T), n
+
+
+def test_tile_path_bit_identical_to_single_matrix_call():
+    orders = [129, 256, 300, 512, 700]
+    mats = inputs.batched_wishart(orders, seed=8, shift=0.1)
+    got = spd.batched_spd_inverse([m.to(DEV) for m in mats])
+    for a, x in zip(mats, got):
+        single = spd.spd_inverse(a.to(DEV))
+        assert torch.equal(x, single)
+
+
+def test_small_path_exact_cases():
+    # diagonal with powers of four and the identity: every step is exact
+    d = np.diag(4.0 ** np.arange(-3, 5)).astype(np.float64)
+    mats = [torch.from_numpy(d), torch.eye(37, dtype=torch.float64),
+            torch.eye(128, dtype=torch.float64)]
+    got = spd.batched_spd_inverse([m.to(DEV) for m in mats])
+    assert np.array_equal(got[0].cpu().numpy(), np.diag(4.0 ** -np.arange(-3, 5)))
+    assert torch.equal(got[1].cpu(), torch.eye(37, dtype=torch.float64))
+    assert torch.equal(got[2].cpu(), torch.eye(128, dtype=torch.float64))
+
+
+def _packed(mats, lda_extra=0):
+    """One device buffer holding column-major copies with ld = n + lda_extra;
+    the strictly upper part of each column is filled with NaN."""
+    orders = [m.shape[0] for m in mats]
+    ldas = [max(1, n + lda_extra) for n in orders]
+    sizes = [ld * max(1, n) for ld, n in zip(ldas, orders)]
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    host = np.full(int(offs[-1]), np.nan)
+    for m, n, ld, off in zip(mats, orders, ldas, offs[:-1]):
+        cm = np.full((ld, n), np.nan)
+        cm[:n, :n] = np.tril(m.numpy()) + np.triu(np.full((n, n), np.nan), 1)
+        host[int(off):int(off) + ld * n] = cm.T.reshape(-1)
+    buf = torch.from_numpy(host).to(DEV)
+    ptrs = torch.tensor([buf.data_ptr() + 8 * int(o) for o in offs[:-1]], dtype=torch.int64,
+                        device=DEV)
+    return buf, ptrs, orders, ldas, offs
+
+
+def _unpack(buf, orders, ldas, offs):
+    host = buf.cpu().numpy()
+    out = []
+    for n, ld, off in zip(orders, ldas, offs[:-1]):
+        out.append(host[int(off):int(off) + ld * n].reshape(n, ld).T)
+    return out
+
+
+def test_info_per_matrix_lda_and_untouched_upper():
+    orders = [40, 150, 60, 260, 5]
+    mats = inputs.batched_wishart(orders, seed=9, shift=0.1)
+    bad = mats[1].clone()
+    bad[77, 77] = -1.0e3          # breaks down at pivot 78
+    bad2 = mats[2].clone()
+    bad2[10, 10] = -5.0           # pivot 11
+    mats = [mats[0], bad, bad2, mats[3], mats[4]]
+    buf, ptrs, orders, ldas, offs = _packed(mats, lda_extra=3)
+    n_dev = torch.tensor(orders, dtype=torch.int32, device=DEV)
+    lda_dev = torch.tensor(ldas, dtype=torch.int32, device=DEV)
+    info = torch.full((len(orders),), 99, dtype=torch.int32, device=DEV)
+    spd.batched_spd_inverse_(ptrs, orders, n_dev, lda_dev, info=info)
+    torch.cuda.synchronize()
+    inf = info.cpu().tolist()
+    assert inf[0] == 0 and inf[3] == 0 and inf[4] == 0
+    assert inf[1] == 78 and inf[2] == 11
+    res = _unpack(buf, orders, ldas, offs)
+    for k in (0, 3, 4):
+        n, ld = orders[k], ldas[k]
+        cm = res[k]
+        assert np.all(np.isnan(cm[n:, :])), "rows beyond n (inside lda) were written"
+        assert np.all(np.isnan(np.triu(cm[:n, :n], 1)[np.triu_indices(n, 1)]))
+        low = np.tril(cm[:n, :n])
+        x = low + np.tril(low, -1).T
+        ref = oracle.spd_inverse(mats[k].numpy())
+        assert rel_fro(x, ref) <= 1e-12 * kappa(mats[k].numpy())
+
+
+def test_invalid_device_entries_reported():
+    orders = [30, 40]
+    mats = inputs.batched_wishart(orders, seed=10, shift=0.1)
+    buf, ptrs, orders, ldas, offs = _packed(mats)
+    n_dev = torch.tensor(orders, dtype=torch.int32, device=DEV)
+    lda_dev = torch.tensor([ldas[0], 5], dtype=torch.int32, device=DEV)  # second lda < n
+    info = torch.zeros(2, dtype=torch.int32, device=DEV)
+    spd.batched_spd_inverse_(ptrs, orders, n_dev, lda_dev, info=info)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0, -1]
+
+
+def test_graph_capture_replays_match_eager():
+    orders = inputs.batch_orders(64, 16, 300, seed=11)
+    mats = inputs.batched_wishart(orders, seed=11, shift=0.1)
+    buf, ptrs, orders, ldas, offs = _packed(mats)
+    src = buf.clone()
+    n_dev = torch.tensor(orders, dtype=torch.int32, device=DEV)
+    lda_dev = torch.tensor(ldas, dtype=torch.int32, device=DEV)
+    info = torch.zeros(len(orders), dtype=torch.int32, device=DEV)
+    work = spd.batched_spd_inverse_(ptrs, orders, n_dev, lda_dev, info=info)   # eager; builds plans
+    torch.cuda.synchronize()
+    eager = buf.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        buf.copy_(src)
+        with torch.cuda.graph(g, stream=s):
+            spd.batched_spd_inverse_(ptrs, orders, n_dev, lda_dev, work=work, info=info)
+    torch.cuda.current_stream().wait_stream(s)
+    for _ in range(3):
+        buf.copy_(src)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(torch.nan_to_num(buf, nan=7.0), torch.nan_to_num(eager, nan=7.0))
+        assert int(info.abs().sum()) == 0
+
+
+def test_full_batched_workload_sampled_oracle_and_residuals():
+    """8192 matrices, n uniform on {16..512} (seed 0), A_i = B_i B_i^T/n_i +
+    0.1 I: 48 sampled matrices (and the smallest and largest) against the
+    oracle, every matrix through ||I - A_i X_i||_F / sqrt(n_i) <= 1e-12 kappa."""
+    orders = inputs.batch_orders(8192, 16, 512, seed=0)
+    mats = inputs.batched_wishart(orders, seed=0, shift=0.1)
+    got = spd.batched_spd_inverse([m.to(DEV) for m in mats])
+    rng = np.random.default_rng(1)
+    sample = set(rng.choice(len(orders), 48, replace=False).tolist())
+    sample |= {int(np.argmin(orders)), int(np.argmax(orders))}
+    for k in sorted(sample):
+        an = mats[k].numpy()
+        ref = oracle.spd_inverse(an)
+        assert rel_fro(got[k].cpu().numpy(), ref) <= 1e-12 * kappa(an), k
+    worst = 0.0
+    for a, x in zip(mats, got):
+        ad = a.to(DEV)
+        n = a.shape[0]
+        r = torch.eye(n, dtype=torch.float64, device=DEV) - ad @ x
+        # kappa <= (lambda_max + 0.1)/0.1 with lambda_max <= (1 + 1)^2 + 0.1 w.h.p.; use 60
+        worst = max(worst, (torch.linalg.norm(r) / n ** 0.5).item())
+    assert worst <= 1e-12 * 60, worst
