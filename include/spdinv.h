@@ -62,7 +62,9 @@ enum {
 typedef enum {
   SPDINV_FP64 = 0,       /* every tile task in binary64 */
   SPDINV_FP32 = 1,       /* reserved */
-  SPDINV_MIXED_FP32 = 2, /* reserved */
+  SPDINV_MIXED_FP32 = 2, /* tile products on FP32 matrix cores (FP32 accumulation),
+                            diagonal tiles in binary64, then Newton-Schulz refinement
+                            X <- X + X (I - A X) with binary64 residuals */
   SPDINV_MIXED_BF16 = 3  /* reserved */
 } spdinv_mode;
 
@@ -79,8 +81,9 @@ typedef struct {
                       grid (1 = program order on one worker)                  */
   int fill_upper;  /* 1 = also write the strictly upper triangle (mirror)     */
   int trace;       /* 1 = record per-task timestamps (see spdinv_trace_*)    */
-  int max_refine;  /* reserved for mixed modes                                */
-  double refine_tol;
+  int max_refine;  /* mixed modes: most refinement steps (0 = library default, 6) */
+  double refine_tol; /* mixed modes: stop once ||I - A X||_F / ||A||_F <= refine_tol
+                        (0 = library default, 1e-13)                            */
 } spdinv_opts;
 
 typedef struct {
@@ -91,6 +94,13 @@ typedef struct {
   long long tasks;     /* tasks executed */
   int critical_path;   /* critical path of the executed DAG, in tasks */
   int workers;         /* persistent workgroups launched */
+  int refine_iters;    /* mixed modes: refinement steps taken                    */
+  int fell_back;       /* mixed modes: 1 when the low-precision start failed (the
+                          FP32 factorization broke down or ||I - A X0||_F >= 1)
+                          and the result comes from the FP64 path               */
+  double resid_fro_rel; /* mixed modes: ||I - A X||_F / ||A||_F of the last
+                           residual computed (before the last correction)      */
+  double resid0_fro_rel; /* mixed modes: the same for the starting inverse X0   */
 } spdinv_report;
 
 /* Fills `opts` with the defaults. */
@@ -100,9 +110,17 @@ void spdinv_default_opts(spdinv_opts* opts);
    workspace holds the three tile copies (A, B, C), the inverted diagonal
    tiles and the scheduler state. */
 size_t spd_inverse_workspace_bytes(int n, spdinv_mode mode, const spdinv_opts* opts);
+/* (for SPDINV_MIXED_FP32 this also holds the FP32 tile pool and four square
+   binary64 matrices of ceil(n/128)*128: A, X, the next X and the residual) */
 
 /*
  * A <- A^{-1} for one SPD matrix (Algorithm 1 with the variants of Section 3).
+ * mode SPDINV_FP64 runs every task in binary64.  mode SPDINV_MIXED_FP32
+ * (renamed plan only) runs the same DAG with FP32 tiles to get X0, then
+ * refines: R = I - A X in binary64, stop when ||R||_F / ||A||_F <= refine_tol,
+ * else X <- X + X R (binary64, lower tiles, mirrored); it synchronizes the
+ * stream once per step to test convergence.  It falls back to the FP64 path
+ * when the FP32 factorization breaks down or ||R_0||_F >= 1.
  *   n        order (>= 0)
  *   A        device, column-major, lda >= max(1,n); lower triangle read and
  *            overwritten with the lower triangle of A^{-1}

@@ -44,12 +44,23 @@ def _stream_ptr(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def workspace_bytes(n: int, **opts) -> int:
+MODES = {"fp64": _lib.SPDINV_FP64, "mixed_fp32": _lib.SPDINV_MIXED_FP32}
+
+
+def _mode(mode) -> int:
+    try:
+        return MODES[mode]
+    except KeyError:
+        raise ValueError(f"mode must be one of {sorted(MODES)}") from None
+
+
+def workspace_bytes(n: int, mode: str = "fp64", **opts) -> int:
     o = make_opts(**opts)
-    return int(load().spd_inverse_workspace_bytes(int(n), _lib.SPDINV_FP64, ctypes.byref(o)))
+    return int(load().spd_inverse_workspace_bytes(int(n), _mode(mode), ctypes.byref(o)))
 
 
-def spd_inverse_(a_cm, *, work=None, report: bool = False, info=None, **opts):
+def spd_inverse_(a_cm, *, mode: str = "fp64", work=None, report: bool = False, info=None,
+                 **opts):
     """A <- A^{-1} in place on a column-major CUDA float64 view.
 
     ``a_cm`` must have strides (1, ld) with ld >= n (e.g. ``x.t()`` of a
@@ -58,7 +69,9 @@ def spd_inverse_(a_cm, *, work=None, report: bool = False, info=None, **opts):
     preallocated uint8 CUDA tensor of at least ``workspace_bytes`` bytes.
     ``info`` may be a CUDA int32 tensor of one element receiving INFO.  With
     ``report=True`` the call synchronises and returns the library report as a
-    dict (raising NotPositiveDefinite on INFO > 0).
+    dict (raising NotPositiveDefinite on INFO > 0).  ``mode`` is "fp64" or
+    "mixed_fp32" (FP32 tile DAG + binary64 Newton-Schulz refinement; the
+    report then carries refine_iters, fell_back and the relative residuals).
     """
     import torch
     if a_cm.dtype != torch.float64 or not a_cm.is_cuda or a_cm.dim() != 2:
@@ -71,14 +84,15 @@ def spd_inverse_(a_cm, *, work=None, report: bool = False, info=None, **opts):
     lda = max(1, a_cm.stride(1) if n > 1 else max(1, n))
     lib = load()
     o = make_opts(**opts)
-    need = int(lib.spd_inverse_workspace_bytes(n, _lib.SPDINV_FP64, ctypes.byref(o)))
+    m = _mode(mode)
+    need = int(lib.spd_inverse_workspace_bytes(n, m, ctypes.byref(o)))
     if work is None:
         work = torch.empty(max(need, 1), dtype=torch.uint8, device=a_cm.device)
     elif work.numel() * work.element_size() < need:
         raise ValueError(f"workspace too small: need {need} bytes")
     rep = _lib.Report()
     info_ptr = info.data_ptr() if info is not None else None
-    rc = lib.spd_inverse(n, a_cm.data_ptr(), lda, _lib.SPDINV_FP64, work.data_ptr(), need,
+    rc = lib.spd_inverse(n, a_cm.data_ptr(), lda, m, work.data_ptr(), need,
                          _stream_ptr(a_cm.device), ctypes.byref(o), info_ptr,
                          ctypes.byref(rep) if report else None)
     if rc != 0:
@@ -91,14 +105,14 @@ def spd_inverse_(a_cm, *, work=None, report: bool = False, info=None, **opts):
     return None
 
 
-def spd_inverse(a, **opts):
+def spd_inverse(a, mode: str = "fp64", return_report: bool = False, **opts):
     """Full symmetric A^{-1} of a CUDA float64 tensor (lower triangle read)."""
     import torch
     n = a.shape[-1]
     buf = a.t().contiguous()          # column-major storage of a: lower triangle = a's lower
-    rep = spd_inverse_(buf.t(), fill_upper=1, report=True, **opts) if n else None
-    del rep
-    return buf.t().contiguous() if n else torch.empty_like(a)
+    rep = spd_inverse_(buf.t(), mode=mode, fill_upper=1, report=True, **opts) if n else None
+    x = buf.t().contiguous() if n else torch.empty_like(a)
+    return (x, rep) if return_report else x
 
 
 def _int_array(values):

@@ -36,7 +36,9 @@ class Opts(ctypes.Structure):
 class Report(ctypes.Structure):
     _fields_ = [("info", ctypes.c_int), ("status", ctypes.c_int), ("nb", ctypes.c_int),
                 ("tiles", ctypes.c_int), ("tasks", ctypes.c_longlong),
-                ("critical_path", ctypes.c_int), ("workers", ctypes.c_int)]
+                ("critical_path", ctypes.c_int), ("workers", ctypes.c_int),
+                ("refine_iters", ctypes.c_int), ("fell_back", ctypes.c_int),
+                ("resid_fro_rel", ctypes.c_double), ("resid0_fro_rel", ctypes.c_double)]
 
 
 class PlanStats(ctypes.Structure):

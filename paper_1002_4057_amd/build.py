@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libspdinv.so")
-SOURCES = ["device.hip", "batched.hip", "dense.hip", "api.cpp", "plan.cpp"]
+SOURCES = ["device.hip", "batched.hip", "mixed.hip", "dense.hip", "api.cpp", "plan.cpp"]
 ARCH = "gfx950"
 
 

@@ -2,7 +2,9 @@
 // layout and the launch sequence of one inversion.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -13,6 +15,7 @@
 
 #include "dense.hpp"
 #include "device.hpp"
+#include "mixed.hpp"
 #include "plan.hpp"
 #include "spdinv.h"
 
@@ -205,42 +208,9 @@ long long spin_limit() {
   return 2000000000LL;  // 20 s
 }
 
-}  // namespace
-
-extern "C" {
-
-void spdinv_default_opts(spdinv_opts* opts) {
-  if (opts) *opts = defaults();
-}
-
-size_t spd_inverse_workspace_bytes(int n, spdinv_mode mode, const spdinv_opts* opts) {
-  (void)mode;
-  if (n <= 0) return 0;
-  const spdinv_opts o = opts ? *opts : defaults();
-  return layout(n, o).total;
-}
-
-int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t work_bytes,
-                spdinv_stream_t stream_, const spdinv_opts* opts, int* d_info,
-                spdinv_report* report) {
-  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
-  if (n < 0) return -1;
-  if (n > 0 && !A) return -2;
-  if (lda < (n > 1 ? n : 1)) return -3;
-  if (mode != SPDINV_FP64) return -4;
-  const spdinv_opts o = opts ? *opts : defaults();
-  if (check_opts(o)) return -8;
-  if (report) std::memset(report, 0, sizeof(*report));
-  if (n == 0) {
-    if (d_info) {
-      int zero = 0;
-      if (hipMemcpyAsync(d_info, &zero, sizeof(int), hipMemcpyHostToDevice, stream) != hipSuccess)
-        return SPDINV_ERR_HIP;
-      if (hipStreamSynchronize(stream) != hipSuccess) return SPDINV_ERR_HIP;
-    }
-    return 0;
-  }
-  if (!work) return -5;
+// The FP64 path: copy-in, the persistent scheduler over the plan, copy-out.
+int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream_t stream,
+             const spdinv_opts& o, int* d_info, spdinv_report* report) {
   const Layout L = layout(n, o);
   if (work_bytes < L.total) return SPDINV_ERR_WORKSPACE;
 
@@ -443,6 +413,209 @@ int spd_inverse_backward(int n, const double* X, int ldx, const double* G, int l
   if (launch_gemm_nt(W, Xf, S, t, 1, 1, stream) != hipSuccess) return SPDINV_ERR_HIP;
   if (launch_unpack_sym(S, t, n, gradA, ldga, stream) != hipSuccess) return SPDINV_ERR_HIP;
   return 0;
+}
+
+// Mixed-precision form.  Workspace: the FP32 tile pool and the scheduler
+// state, then four square tile-major binary64 matrices (A, X, the next X, the
+// residual) and the norm scratch.  The FP64 fallback reuses the workspace
+// from offset 0 (everything in it is dead by then; A itself is untouched
+// until the final copy-out).
+struct MixedLayout {
+  size_t indeg, ctrl, asq, x, x2, r, partial, total;
+};
+
+MixedLayout mixed_layout(int n, const spdinv_opts& o) {
+  MixedLayout M;
+  const int t = tiles_for(n);
+  const long long nt = task_count(t);
+  const size_t sq = (size_t)t * t * NB * NB * sizeof(double);
+  M.indeg = align_up(pool_bytes32(t), 256);
+  M.ctrl = M.indeg + align_up((size_t)nt * sizeof(int32_t), 256);
+  M.asq = M.ctrl + align_up(CTRL_WORDS * sizeof(int32_t), 256);
+  M.x = M.asq + sq;
+  M.x2 = M.x + sq;
+  M.r = M.x2 + sq;
+  M.partial = M.r + sq;
+  M.total = M.partial + align_up(((size_t)t * t + 8) * sizeof(double), 256);
+  spdinv_opts o64 = o;
+  o64.trace = 0;
+  M.total = std::max(M.total, layout(n, o64).total);
+  return M;
+}
+
+int grid32_for(int device, const spdinv_opts& o) {
+  static std::map<int, int> grids;
+  int g;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = grids.find(device);
+    if (it != grids.end()) {
+      g = it->second;
+    } else {
+      int cus = 0;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+          cus <= 0)
+        cus = 1;
+      g = cus * sched32_blocks_per_cu();
+      grids[device] = g;
+    }
+  }
+  if (o.workers > 0 && o.workers < g) g = o.workers;
+  return g;
+}
+
+int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStream_t stream,
+              const spdinv_opts& o, int* d_info, spdinv_report* report) {
+  const MixedLayout M = mixed_layout(n, o);
+  if (work_bytes < M.total) return SPDINV_ERR_WORKSPACE;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return SPDINV_ERR_HIP;
+  const int t = tiles_for(n);
+  const int grid = grid32_for(device, o);
+  hipError_t err = hipSuccess;
+  DevPlan* dp = get_plan(device, t, o, grid, &err);
+  if (!dp) return SPDINV_ERR_HIP;
+  const int ntask = (int)dp->host.tasks.size();
+  const int max_refine = o.max_refine > 0 ? o.max_refine : 6;
+  const double tol = o.refine_tol > 0.0 ? o.refine_tol : 1e-13;
+
+  char* w = (char*)work;
+  float* pool = (float*)w;
+  int32_t* indeg = (int32_t*)(w + M.indeg);
+  int32_t* ctrl = (int32_t*)(w + M.ctrl);
+  if (launch_reset(dp->d_indeg0, indeg, ntask, ctrl, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (launch_copy_in32(A, lda, n, t, pool, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  SchedArgs a;
+  a.tasks = dp->d_tasks;
+  a.succ = dp->d_succ;
+  a.order = dp->d_order;
+  a.indeg = indeg;
+  a.ctrl = ctrl;
+  a.pool = reinterpret_cast<double*>(pool);
+  a.trace = nullptr;
+  a.ntask = ntask;
+  a.tiles_T = t * (t + 1) / 2;
+  a.tiles = t;
+  a.info_base = 0;
+  a.spin_limit = spin_limit();
+  if (launch_sched32(a, grid, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  int32_t c[CTRL_WORDS];
+  if (hipMemcpyAsync(c, ctrl, sizeof(c), hipMemcpyDeviceToHost, stream) != hipSuccess)
+    return SPDINV_ERR_HIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (c[CTRL_ABORT]) return SPDINV_ERR_TIMEOUT;
+
+  bool fallback = c[CTRL_FAILED] != 0;
+  int iters = 0;
+  double r0 = -1.0, rl = -1.0;
+  double* X = nullptr;
+  if (!fallback) {
+    double* Asq = (double*)(w + M.asq);
+    X = (double*)(w + M.x);
+    double* X2 = (double*)(w + M.x2);
+    double* R = (double*)(w + M.r);
+    double* partial = (double*)(w + M.partial);
+    double* dnorm = partial + (size_t)t * t;  // [0] ||A||^2, [1] ||R||^2
+    const int sq_tiles = t * t;
+    if (launch_pack(A, lda, n, t, PACK_SYM_LOWER, Asq, stream) != hipSuccess) return SPDINV_ERR_HIP;
+    if (launch_sumsq(Asq, sq_tiles, partial, dnorm, stream) != hipSuccess) return SPDINV_ERR_HIP;
+    if (launch_x0_to_sym64(pool, t, n, X, stream) != hipSuccess) return SPDINV_ERR_HIP;
+    for (int k = 0;; ++k) {
+      // R^T = I - X A (A and X symmetric); ||R^T||_F = ||R||_F
+      if (launch_gemm_nt(X, Asq, R, t, 0, 1, stream, nullptr, n) != hipSuccess) return SPDINV_ERR_HIP;
+      if (launch_sumsq(R, sq_tiles, partial, dnorm + 1, stream) != hipSuccess) return SPDINV_ERR_HIP;
+      double h[2];
+      if (hipMemcpyAsync(h, dnorm, sizeof(h), hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return SPDINV_ERR_HIP;
+      if (hipStreamSynchronize(stream) != hipSuccess) return SPDINV_ERR_HIP;
+      const double rnorm = std::sqrt(h[1]), rel = rnorm / std::sqrt(h[0]);
+      if (k == 0) {
+        r0 = rel;
+        if (!(rnorm < 1.0)) {  // Newton-Schulz needs ||R_0|| < 1 (NaN included)
+          fallback = true;
+          break;
+        }
+      }
+      rl = rel;
+      if (rel <= tol || k >= max_refine) break;
+      // X' = X + X R on the lower tiles, X R = sum_k X(i, k) (R^T)(j, k)^T; then mirror
+      if (launch_gemm_nt(X, R, X2, t, 1, 0, stream, X, 0) != hipSuccess) return SPDINV_ERR_HIP;
+      if (launch_mirror_lower(X2, t, stream) != hipSuccess) return SPDINV_ERR_HIP;
+      std::swap(X, X2);
+      ++iters;
+    }
+  }
+  if (fallback) {
+    spdinv_opts o64 = o;
+    o64.trace = 0;
+    const int rc = run_fp64(n, A, lda, work, work_bytes, stream, o64, d_info, report);
+    if (report) {
+      report->fell_back = 1;
+      report->resid0_fro_rel = r0;
+      report->resid_fro_rel = -1.0;
+      report->refine_iters = 0;
+    }
+    return rc;
+  }
+  if (launch_unpack_sym(X, t, n, A, lda, stream, o.fill_upper ? 0 : 1) != hipSuccess)
+    return SPDINV_ERR_HIP;
+  if (launch_info_out(ctrl, d_info, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (report) {
+    if (hipStreamSynchronize(stream) != hipSuccess) return SPDINV_ERR_HIP;
+    report->info = 0;
+    report->status = 0;
+    report->nb = NB;
+    report->tiles = t;
+    report->tasks = ntask;
+    report->critical_path = dp->host.stats.cp_plan;
+    report->workers = grid;
+    report->refine_iters = iters;
+    report->fell_back = 0;
+    report->resid_fro_rel = rl;
+    report->resid0_fro_rel = r0;
+  }
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void spdinv_default_opts(spdinv_opts* opts) {
+  if (opts) *opts = defaults();
+}
+
+size_t spd_inverse_workspace_bytes(int n, spdinv_mode mode, const spdinv_opts* opts) {
+  if (n <= 0) return 0;
+  const spdinv_opts o = opts ? *opts : defaults();
+  if (mode == SPDINV_MIXED_FP32) return mixed_layout(n, o).total;
+  return layout(n, o).total;
+}
+
+int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t work_bytes,
+                spdinv_stream_t stream_, const spdinv_opts* opts, int* d_info,
+                spdinv_report* report) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  if (n < 0) return -1;
+  if (n > 0 && !A) return -2;
+  if (lda < (n > 1 ? n : 1)) return -3;
+  if (mode != SPDINV_FP64 && mode != SPDINV_MIXED_FP32) return -4;
+  const spdinv_opts o = opts ? *opts : defaults();
+  if (check_opts(o)) return -8;
+  if (mode == SPDINV_MIXED_FP32 && (!o.renamed || o.trace)) return -8;
+  if (report) std::memset(report, 0, sizeof(*report));
+  if (n == 0) {
+    if (d_info) {
+      int zero = 0;
+      if (hipMemcpyAsync(d_info, &zero, sizeof(int), hipMemcpyHostToDevice, stream) != hipSuccess)
+        return SPDINV_ERR_HIP;
+      if (hipStreamSynchronize(stream) != hipSuccess) return SPDINV_ERR_HIP;
+    }
+    return 0;
+  }
+  if (!work) return -5;
+  if (mode == SPDINV_MIXED_FP32) return run_mixed(n, A, lda, work, work_bytes, stream, o, d_info, report);
+  return run_fp64(n, A, lda, work, work_bytes, stream, o, d_info, report);
 }
 
 void spdinv_release_plans(void) {

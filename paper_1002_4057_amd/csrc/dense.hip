@@ -84,31 +84,128 @@ __device__ __forceinline__ void out_tile(int b, int nblk, int t, bool lower, int
   }
 }
 
-// C(i, j) = s * sum_k A(i, k) B(j, k)^T over k < t, one output tile per
-// workgroup (s = -1 when neg).  With lower = 1 only tiles i >= j are formed.
+// C(i, j) = Cin(i, j) + s * sum_k A(i, k) B(j, k)^T (+ the identity on the
+// first diag_n diagonal entries), one output tile per workgroup; s = -1 when
+// neg, Cin may be null (zero).  With lower = 1 only tiles i >= j are formed.
 __global__ __launch_bounds__(NTHREADS) void gemm_nt_kernel(const double* __restrict__ A,
                                                            const double* __restrict__ B,
                                                            double* __restrict__ C, int t,
-                                                           int lower, int neg) {
+                                                           int lower, int neg,
+                                                           const double* __restrict__ Cin,
+                                                           int diag_n) {
   __shared__ double smem[GEMM_SMEM];
   const int nblk = lower ? t * (t + 1) / 2 : t * t;
   int i, j;
   out_tile(blockIdx.x, nblk, t, lower != 0, i, j);
   Acc acc;
-  acc_zero(acc);
+  const size_t ct = (size_t)(i + t * j) * TILE;
+  if (Cin) {
+    // start from -Cin when negating: Cin - P is rounded as -(-Cin + P)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int off = acc_offset(a, b);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double c = Cin[ct + off + NB * 4 * r];
+          acc[a][b][r] = neg ? -c : c;
+        }
+      }
+  } else {
+    acc_zero(acc);
+  }
   auto pair = [&](int k, const double*& pa, const double*& pb) {
     pa = A + (size_t)(i + t * k) * TILE;
     pb = B + (size_t)(j + t * k) * TILE;
   };
   mma_chain<0>(acc, t, pair, smem);
-  acc_store<0>(C + (size_t)(i + t * j) * TILE, acc, neg != 0, false);
+  if (diag_n > 0 && i == j) {
+    // lane l, register r of accumulator (a, b) holds tile element
+    // (row, col) = acc_offset(a, b) + 4 NB r, i.e. column (off / NB) + 4 r
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int off = acc_offset(a, b);
+        const int row = off & (NB - 1), col0 = off >> 7;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (row == col0 + 4 * r && i * NB + row < diag_n) acc[a][b][r] += neg ? -1.0 : 1.0;
+      }
+  }
+  acc_store<0>(C + ct, acc, neg != 0, false);
+}
+
+// partial[b] = sum of squares of the entries of tile b (fixed summation
+// order, so the result does not depend on the launch)
+__global__ __launch_bounds__(NTHREADS) void sumsq_tiles_kernel(const double* __restrict__ M,
+                                                               double* __restrict__ partial) {
+  __shared__ double red[NTHREADS];
+  const double* tile = M + (size_t)blockIdx.x * TILE;
+  double s = 0.0;
+  for (int e = threadIdx.x; e < (int)TILE; e += NTHREADS) s = fma(tile[e], tile[e], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = NTHREADS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// out[0] = sum of partial[0..count) (one block, fixed order)
+__global__ __launch_bounds__(NTHREADS) void sum_kernel(const double* __restrict__ partial, int count,
+                                                       double* __restrict__ out) {
+  __shared__ double red[NTHREADS];
+  double s = 0.0;
+  for (int e = threadIdx.x; e < count; e += NTHREADS) s += partial[e];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = NTHREADS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// Makes the square tile-major M symmetric from its lower tiles: tile (i, j),
+// i < j, <- tile (j, i)^T, and the upper part of each diagonal tile <- the
+// mirror of its lower part.  One block per tile (i, j) with i <= j.
+__global__ __launch_bounds__(NTHREADS) void mirror_lower_kernel(double* __restrict__ M, int t) {
+  constexpr int SBm = 32;
+  __shared__ double L[SBm][SBm + 1];
+  const int bi = blockIdx.x % t, bj = blockIdx.x / t;
+  if (bi > bj) return;  // uniform per block
+  double* dst = M + (size_t)(bi + t * bj) * TILE;
+  const double* src = M + (size_t)(bj + t * bi) * TILE;  // tile (bj, bi)
+  const int tx = threadIdx.x & (SBm - 1), ty = threadIdx.x / SBm;
+  for (int sb = 0; sb < (NB / SBm) * (NB / SBm); ++sb) {
+    const int lr0 = (sb % (NB / SBm)) * SBm, lc0 = (sb / (NB / SBm)) * SBm;
+    // dst element (lr, lc) <- src element (lc, lr)
+#pragma unroll
+    for (int q = 0; q < SBm / 8; ++q) {
+      const int j = ty + 8 * q;
+      L[tx][j] = src[(lc0 + tx) + NB * (lr0 + j)];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SBm / 8; ++q) {
+      const int j = ty + 8 * q;
+      const int lr = lr0 + tx, lc = lc0 + j;
+      if (bi < bj || lr < lc) dst[lr + NB * lc] = L[j][tx];
+    }
+    __syncthreads();
+  }
 }
 
 // out (column-major, ld, order n) <- the symmetric matrix whose lower tiles
-// (i >= j) are in the square tile-major src; both triangles are written.
+// (i >= j) are in the square tile-major src; both triangles are written, or
+// only the lower one with lower_only.
 __global__ __launch_bounds__(NTHREADS) void unpack_sym_kernel(const double* __restrict__ src,
                                                               int t, int n,
-                                                              double* __restrict__ out, int ld) {
+                                                              double* __restrict__ out, int ld,
+                                                              int lower_only) {
   __shared__ double L[SB][SB + 1];
   const int bi = blockIdx.x % t, bj = blockIdx.x / t;
   const int tx = threadIdx.x & (SB - 1), ty = threadIdx.x / SB;
@@ -130,7 +227,7 @@ __global__ __launch_bounds__(NTHREADS) void unpack_sym_kernel(const double* __re
       const int j = ty + 8 * q;
       const int lr = lr0 + tx, lc = lc0 + j;
       const int gr = bi * NB + lr, gc = bj * NB + lc;
-      if (gr < n && gc < n) {
+      if (gr < n && gc < n && (!lower_only || gr >= gc)) {
         double v;
         if (bi > bj || (bi == bj && lr >= lc))
           v = s[lr + NB * lc];
@@ -152,15 +249,30 @@ hipError_t launch_pack(const double* src, int ld, int n, int t, int mode, double
 }
 
 hipError_t launch_gemm_nt(const double* A, const double* B, double* C, int t, int lower, int neg,
-                          hipStream_t s) {
+                          hipStream_t s, const double* Cin, int diag_n) {
   const int nblk = lower ? t * (t + 1) / 2 : t * t;
-  hipLaunchKernelGGL(gemm_nt_kernel, dim3(nblk), dim3(NTHREADS), 0, s, A, B, C, t, lower, neg);
+  hipLaunchKernelGGL(gemm_nt_kernel, dim3(nblk), dim3(NTHREADS), 0, s, A, B, C, t, lower, neg, Cin,
+                     diag_n);
   return hipGetLastError();
 }
 
-hipError_t launch_unpack_sym(const double* src, int t, int n, double* out, int ld,
-                             hipStream_t s) {
-  hipLaunchKernelGGL(unpack_sym_kernel, dim3(t * t), dim3(NTHREADS), 0, s, src, t, n, out, ld);
+hipError_t launch_unpack_sym(const double* src, int t, int n, double* out, int ld, hipStream_t s,
+                             int lower_only) {
+  hipLaunchKernelGGL(unpack_sym_kernel, dim3(t * t), dim3(NTHREADS), 0, s, src, t, n, out, ld,
+                     lower_only);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const double* M, int ntiles, double* partial, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sumsq_tiles_kernel, dim3(ntiles), dim3(NTHREADS), 0, s, M, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(NTHREADS), 0, s, partial, ntiles, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mirror_lower(double* M, int t, hipStream_t s) {
+  hipLaunchKernelGGL(mirror_lower_kernel, dim3(t * t), dim3(NTHREADS), 0, s, M, t);
   return hipGetLastError();
 }
 

@@ -187,38 +187,44 @@ __device__ __forceinline__ void mma_chain(Acc& acc, int count, PairFn pair, doub
   if (count <= 0) return;
   const double *pa, *pb;
   pair(0, pa, pb);
-  rsrc_t rA = tile_rsrc(pa), rB = tile_rsrc(pb);
   d2 ra[PAIRS], rb[PAIRS];
-  panel_load<CP>(rA, 0, true, ra);
-  panel_load<CP>(rB, 0, true, rb);
+  panel_load<CP>(tile_rsrc(pa), 0, true, ra);
+  panel_load<CP>(tile_rsrc(pb), 0, true, rb);
   panel_store(smem, 0, true, false, ra);
   panel_store(smem + PANEL, 0, true, false, rb);
   __syncthreads();
-  const int total = count * NCH;
+  // two rolled loops (links, then the k-panels of a link) with the next
+  // link's tiles resolved once per link: this keeps the accumulator in the
+  // matrix-core registers for the whole chain (other loop shapes made the
+  // compiler copy it out and back every iteration)
 #pragma unroll 1
-  for (int g = 0; g < total; ++g) {
-    const double* As = smem + (g & 1) * 2 * PANEL;
-    const double* Bs = As + PANEL;
-    const bool more = g + 1 < total;
-    if (more) {
-      const int c1 = (g + 1) % NCH;
-      if (c1 == 0) {
-        pair((g + 1) / NCH, pa, pb);
-        rA = tile_rsrc(pa);
-        rB = tile_rsrc(pb);
+  for (int p = 0; p < count; ++p) {
+    const double *qa, *qb;
+    pair(p + 1 < count ? p + 1 : p, qa, qb);
+    const rsrc_t rA = tile_rsrc(pa), rB = tile_rsrc(pb), nA = tile_rsrc(qa), nB = tile_rsrc(qb);
+    const bool last = p + 1 >= count;
+#pragma unroll 1
+    for (int c = 0; c < NCH; ++c) {
+      const double* As = smem + (c & 1) * 2 * PANEL;
+      const double* Bs = As + PANEL;
+      const bool wrap = c + 1 == NCH;
+      const bool more = !wrap || !last;
+      if (more) {
+        panel_load<CP>(wrap ? nA : rA, ((c + 1) % NCH) * KC, true, ra);
+        panel_load<CP>(wrap ? nB : rB, ((c + 1) % NCH) * KC, true, rb);
       }
-      panel_load<CP>(rA, c1 * KC, true, ra);
-      panel_load<CP>(rB, c1 * KC, true, rb);
+      __builtin_amdgcn_sched_barrier(0);
+      panel_mma(acc, As, Bs);
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) {
+        double* An = smem + ((c + 1) & 1) * 2 * PANEL;
+        panel_store(An, 0, true, false, ra);
+        panel_store(An + PANEL, 0, true, false, rb);
+      }
+      __syncthreads();
     }
-    __builtin_amdgcn_sched_barrier(0);
-    panel_mma(acc, As, Bs);
-    __builtin_amdgcn_sched_barrier(0);
-    if (more) {
-      double* An = smem + ((g + 1) & 1) * 2 * PANEL;
-      panel_store(An, 0, true, false, ra);
-      panel_store(An + PANEL, 0, true, false, rb);
-    }
-    __syncthreads();
+    pa = qa;
+    pb = qb;
   }
 }
 
@@ -237,6 +243,15 @@ __device__ __forceinline__ void acc_store(double* C, const Acc& acc, bool neg, b
 #pragma unroll
       for (int r = 0; r < 4; ++r) st1<CP>(rC, off + NB * 4 * r, neg ? -acc[i][j][r] : acc[i][j][r]);
     }
+}
+
+// A task's results are published when its agent-coherent stores have
+// completed: every thread waits for its outstanding memory operations before
+// the workgroup barrier that precedes the successors' counter decrements.
+__device__ __forceinline__ void stores_complete() { __builtin_amdgcn_s_waitcnt(0); }
+
+__device__ __forceinline__ long long now_ticks() {
+  return (long long)__builtin_amdgcn_s_memrealtime();
 }
 
 }  // namespace tile

@@ -1,0 +1,371 @@
+// Mixed-precision form of the SPD inverse on gfx950 (MI355X): the renamed,
+// pipelined tile DAG of Section 3 executed with FP32 tiles.  Tile products
+// run on the FP32 matrix cores (v_mfma_f32_16x16x4f32, FP32 accumulation);
+// the diagonal tiles are factored and inverted in binary64 (the same LDS code
+// as the FP64 path) and rounded back.  The result is the starting inverse X0
+// that the Newton-Schulz refinement (FP64 residuals, dense.hip) corrects.
+//
+// FP32 tiles are NB x NB floats, column-major, contiguous (64 KiB), in the
+// same pool layout as the FP64 path: A tiles, the transposed renaming copies
+// B and C, the inverted diagonal factor tiles D_j and D_j^T.
+#include "device.hpp"
+#include "mfma_tile.hpp"
+#include "mixed.hpp"
+#include "sched_loop.hpp"
+#include "tile_tasks.hpp"
+
+namespace spdinv {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Panel row stride in floats.  Operand reads take 16 consecutive rows r of
+// 4 consecutive k per wave: with a stride of 144 floats (144 mod 64 = 16
+// banks) the four k rows fall on disjoint bank groups.
+constexpr int LDS32 = NB + 16;
+constexpr int PANEL32 = KC * LDS32;               // floats per operand panel
+constexpr int Q32 = NB * KC / 4 / NTHREADS;       // 16-byte loads per thread per panel
+constexpr size_t TILE_BYTES32 = TILE * sizeof(float);
+
+__device__ __forceinline__ float* tile32(float* pool, int idx) { return pool + (size_t)idx * TILE; }
+
+__device__ __forceinline__ rsrc_t rsrc32(const float* t) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(t), 0, (int)TILE_BYTES32, RSRC_WORD3);
+}
+__device__ __forceinline__ f4 ld4f(rsrc_t r, int elem) {
+  return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, elem * 4, 0, CPOL_AGENT));
+}
+__device__ __forceinline__ float ld1f(rsrc_t r, int elem) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, elem * 4, 0, CPOL_AGENT));
+}
+__device__ __forceinline__ void st4f(rsrc_t r, int elem, f4 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, v), r, elem * 4, 0, CPOL_AGENT);
+}
+__device__ __forceinline__ void st1f(rsrc_t r, int elem, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, elem * 4, 0, CPOL_AGENT);
+}
+
+// k-panel k0..k0+KC-1 of a tile read along stored columns (element (r, k) is
+// X[r + NB*k]), staged in LDS as S[k * LDS32 + r].
+__device__ __forceinline__ void panel_load32(rsrc_t X, int k0, f4 (&v)[Q32]) {
+#pragma unroll
+  for (int q = 0; q < Q32; ++q) v[q] = ld4f(X, NB * k0 + 4 * (threadIdx.x + NTHREADS * q));
+}
+__device__ __forceinline__ void panel_store32(float* S, const f4 (&v)[Q32]) {
+#pragma unroll
+  for (int q = 0; q < Q32; ++q) {
+    const int e = 4 * (threadIdx.x + NTHREADS * q), rr = e & (NB - 1), kk = e >> 7;
+    *reinterpret_cast<f4*>(S + kk * LDS32 + rr) = v[q];
+  }
+}
+
+// Tile product C (+)= +-A B^T on the FP32 matrix cores (the renamed plan's
+// only form: both operands read along stored columns), with the flags of the
+// FP64 product: F_NEG, F_ACC, F_LOWER (the block above the diagonal is not
+// stored), and the renaming copy (transposed with F_COPYT).
+// v_mfma_f32_16x16x4f32(x, y, d): x[i][k] from lane i+16k, y[k][j] from lane
+// j+16k, d[i][j] in register i%4 of lane j + 16*(i/4).  The operands are
+// passed as (B block, A block), so lane l, register r holds output row l%16
+// of column 4*(l/16) + r.
+__device__ __forceinline__ void tile_mma32(int f, float* C, const float* A, const float* B,
+                                           float* copy, double* smem_d) {
+  float* smem = reinterpret_cast<float*>(smem_d);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w & 1, wn = w >> 1, lr = lane & 15, lk = lane >> 4;
+  const bool neg = (f & F_NEG) != 0, accum = (f & F_ACC) != 0, copy_t = (f & F_COPYT) != 0;
+  const bool active = !((f & F_LOWER) && wm == 0 && wn == 1);
+  const rsrc_t rA = rsrc32(A), rB = rsrc32(B), rC = rsrc32(C);
+  auto off = [&](int i, int j, int r) {
+    return (wm * 64 + i * 16 + lr) + NB * (wn * 64 + j * 16 + 4 * lk + r);
+  };
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float c = accum ? ld1f(rC, off(i, j, r)) : 0.0f;
+        acc[i][j][r] = neg ? -c : c;  // start from -C: C - P is rounded as -(-C + P)
+      }
+  f4 va[Q32], vb[Q32];
+  panel_load32(rA, 0, va);
+  panel_load32(rB, 0, vb);
+  panel_store32(smem, va);
+  panel_store32(smem + PANEL32, vb);
+  __syncthreads();
+#pragma unroll 1
+  for (int c = 0; c < NCH; ++c) {
+    const float* As = smem + (c & 1) * 2 * PANEL32;
+    const float* Bs = As + PANEL32;
+    const bool more = c + 1 < NCH;
+    if (more) {
+      panel_load32(rA, (c + 1) * KC, va);
+      panel_load32(rB, (c + 1) * KC, vb);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const float* Ar = As + (4 * ks + lk) * LDS32 + wm * 64 + lr;
+      const float* Br = Bs + (4 * ks + lk) * LDS32 + wn * 64 + lr;
+      float a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = Ar[16 * i];
+        b[i] = Br[16 * i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[j], a[i], acc[i][j], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (more) {
+      float* An = smem + ((c + 1) & 1) * 2 * PANEL32;
+      panel_store32(An, va);
+      panel_store32(An + PANEL32, vb);
+    }
+    __syncthreads();
+  }
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) st1f(rC, off(i, j, r), neg ? -acc[i][j][r] : acc[i][j][r]);
+  }
+  if (!copy) return;  // uniform
+  // renaming copy, staged in LDS as R[col + RLD * row] and written with
+  // contiguous 16-byte stores
+  constexpr int RLD = NB + 1;
+  float* R = smem;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wm * 64 + i * 16 + lr, col = wn * 64 + j * 16 + 4 * lk + r;
+        R[col + RLD * row] = neg ? -acc[i][j][r] : acc[i][j][r];
+      }
+  __syncthreads();
+  const rsrc_t rD = rsrc32(copy);
+#pragma unroll 4
+  for (int q = 0; q < NB * NB / 4 / NTHREADS; ++q) {
+    const int e = 4 * (threadIdx.x + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
+    f4 v;  // copy element (rr + s, cc) is result(cc, rr + s) or result(rr + s, cc)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = copy_t ? R[(rr + s) + RLD * cc] : R[cc + RLD * (rr + s)];
+    st4f(rD, e, v);
+  }
+}
+
+// Diagonal tile in binary64: the FP32 tile is widened (exactly) into LDS,
+// factored and inverted by the FP64 path's LDS code, and L, L^T, X = L^{-1}
+// and X^T are rounded to FP32.  Returns 0 or the 1-based local index of the
+// first non-positive pivot (nothing is stored then).
+__device__ __attribute__((noinline)) int potrf_inv_tile32(const float* Ain, float* Lout,
+                                                           float* LcopyT, float* Xout,
+                                                           float* XoutT, double* smem) {
+  constexpr int LD = POTRF_LD;
+  double* T = smem;
+  double* XD = smem + NB * LD;
+  double* SCR = XD + 8 * 256;
+  int* flag = reinterpret_cast<int*>(SCR + 4 * 256);
+  const int tid = threadIdx.x;
+  const rsrc_t rIn = rsrc32(Ain), rL = rsrc32(Lout), rX = rsrc32(Xout), rXT = rsrc32(XoutT);
+  for (int e0 = 0; e0 < NB * NB; e0 += 4 * NTHREADS * 8) {
+    f4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = ld4f(rIn, e0 + 4 * (tid + NTHREADS * u));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + 4 * (tid + NTHREADS * u), rr = e & (NB - 1), cc = e >> 7;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) T[rr + s + LD * cc] = (rr + s >= cc) ? (double)v[u][s] : 0.0;
+    }
+  }
+  __syncthreads();
+  const int ff = factor_lds(T, XD, flag, 8);
+  if (ff) return ff;
+  const rsrc_t rLT = rsrc32(LcopyT ? LcopyT : Lout);
+#pragma unroll 2
+  for (int q = 0; q < NB * NB / 4 / NTHREADS; ++q) {
+    const int e = 4 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
+    f4 v;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) v[s] = (rr + s >= cc) ? (float)T[rr + s + LD * cc] : 0.0f;
+    st4f(rL, e, v);
+    if (LcopyT) {
+      f4 u;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) u[s] = (cc >= rr + s) ? (float)T[cc + LD * (rr + s)] : 0.0f;
+      st4f(rLT, e, u);
+    }
+  }
+  __syncthreads();
+  inverse_lds(T, XD, SCR, 8);
+  __syncthreads();
+  auto xval = [&](int r, int c) -> double {
+    const int br = r >> 4, bc = c >> 4;
+    if (br == bc) return XD[256 * br + (r & 15) + 16 * (c & 15)];
+    return (br > bc) ? T[c + LD * r] : 0.0;
+  };
+#pragma unroll 2
+  for (int q = 0; q < NB * NB / 4 / NTHREADS; ++q) {
+    const int e = 4 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
+    f4 v, u;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      v[s] = (float)xval(rr + s, cc);
+      u[s] = (float)xval(cc, rr + s);
+    }
+    st4f(rX, e, v);
+    st4f(rXT, e, u);
+  }
+  return 0;
+}
+
+__device__ __forceinline__ void tile_copy32(const float* src, float* dst) {
+  const rsrc_t rs = rsrc32(src), rd = rsrc32(dst);
+#pragma unroll
+  for (int h = 0; h < (int)(TILE / 4) / (NTHREADS * 16); ++h) {
+    f4 v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = ld4f(rs, 4 * (h * NTHREADS * 16 + threadIdx.x + NTHREADS * u));
+#pragma unroll
+    for (int u = 0; u < 16; ++u) st4f(rd, 4 * (h * NTHREADS * 16 + threadIdx.x + NTHREADS * u), v[u]);
+  }
+}
+
+__device__ __forceinline__ void run_task32(const DevTask& t, const SchedArgs& g, double* smem,
+                                           int T, int tiles) {
+  float* P = reinterpret_cast<float*>(g.pool);
+  const int kind = t.kind & 0xff, f = (t.kind >> 8) & 0xff;
+  float* out = t.out >= 0 ? tile32(P, t.out) : nullptr;
+  const float* a = t.a >= 0 ? tile32(P, t.a) : nullptr;
+  const float* b = t.b >= 0 ? tile32(P, t.b) : nullptr;
+  float* cp = t.copy >= 0 ? tile32(P, t.copy) : nullptr;
+  switch (kind) {
+    case K_SYRK1: case K_GEMM1: case K_TRSM1: case K_TRMM2L: case K_GEMM2: case K_TRSM2R:
+    case K_TRMM3: case K_LAUUM: case K_GEMM3: case K_SYRK3:
+      tile_mma32(f, out, a, b, cp, smem);  // renamed plan: A B^T products only
+      break;
+    case K_POTRF: {
+      float* X = tile32(P, t.aux);
+      float* Xt = tile32(P, t.aux + tiles);
+      const int fl = potrf_inv_tile32(out, out, cp, X, Xt, smem);
+      if (fl && threadIdx.x == 0) {
+        const int jt = t.aux - 3 * T;
+        atomicMin(&g.ctrl[CTRL_INFO], g.info_base + jt * NB + fl);
+        __hip_atomic_store(&g.ctrl[CTRL_FAILED], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      break;
+    }
+    case K_TRTRI:
+      tile_copy32(a, out);
+      if (cp) tile_copy32(b, cp);
+      break;
+    default:
+      break;
+  }
+}
+
+__global__ __launch_bounds__(NTHREADS) void sched_kernel32(SchedArgs g, int T, int tiles) {
+  __shared__ double smem[SMEM_DOUBLES];
+  sched_loop(g, [&](const DevTask& t) { run_task32(t, g, smem, T, tiles); });
+}
+
+__device__ __forceinline__ void tri_decode32(int x, int& ti, int& tj) {
+  int i = (int)((sqrtf(8.0f * (float)x + 1.0f) - 1.0f) * 0.5f);
+  while (i * (i + 1) / 2 > x) --i;
+  while ((i + 1) * (i + 2) / 2 <= x) ++i;
+  ti = i;
+  tj = x - i * (i + 1) / 2;
+}
+
+// Lower triangle of the FP64 column-major A -> FP32 lower tiles (rounded to
+// nearest), identity padding beyond n.
+__global__ __launch_bounds__(NTHREADS) void copy_in32_kernel(const double* __restrict__ A, int lda,
+                                                             int n, float* __restrict__ pool) {
+  int ti, tj;
+  tri_decode32(blockIdx.x, ti, tj);
+  float* dst = pool + (size_t)blockIdx.x * TILE;
+  for (int e = threadIdx.x; e < (int)TILE; e += NTHREADS) {
+    const int r = e & (NB - 1), c = e >> 7;
+    const int gr = ti * NB + r, gc = tj * NB + c;
+    double v;
+    if (gr < n && gc < n)
+      v = (gr >= gc) ? A[gr + (size_t)lda * gc] : 0.0;
+    else
+      v = (gr == gc) ? 1.0 : 0.0;
+    dst[e] = (float)v;
+  }
+}
+
+// X0 (FP32 lower tiles of the pool) -> square tile-major FP64 symmetric X of
+// t x t tiles (tile (i, j) at i + t*j), zero beyond n.
+__global__ __launch_bounds__(NTHREADS) void x0_to_sym64_kernel(const float* __restrict__ pool, int t,
+                                                               int n, double* __restrict__ X) {
+  constexpr int SB = 32;
+  __shared__ float L[SB][SB + 1];
+  const int bi = blockIdx.x % t, bj = blockIdx.x / t;
+  const int si = bi >= bj ? bi : bj, sj = bi >= bj ? bj : bi;
+  const float* s = pool + (size_t)(si * (si + 1) / 2 + sj) * TILE;
+  double* out = X + (size_t)blockIdx.x * TILE;
+  const int tx = threadIdx.x & (SB - 1), ty = threadIdx.x / SB;
+  for (int sb = 0; sb < (NB / SB) * (NB / SB); ++sb) {
+    const int lr0 = (sb % (NB / SB)) * SB, lc0 = (sb / (NB / SB)) * SB;
+#pragma unroll
+    for (int q = 0; q < SB / 8; ++q) {
+      const int j = ty + 8 * q;
+      L[tx][j] = s[(lc0 + tx) + NB * (lr0 + j)];  // source element (lc0 + tx, lr0 + j)
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SB / 8; ++q) {
+      const int j = ty + 8 * q;
+      const int lr = lr0 + tx, lc = lc0 + j;
+      const int gr = bi * NB + lr, gc = bj * NB + lc;
+      float v;
+      if (bi > bj || (bi == bj && lr >= lc))
+        v = s[lr + NB * lc];
+      else
+        v = L[j][tx];  // source element (lc, lr)
+      out[lr + NB * lc] = (gr < n && gc < n) ? (double)v : 0.0;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+size_t pool_bytes32(int t) { return (size_t)pool_tiles(t) * TILE_BYTES32; }
+
+hipError_t launch_copy_in32(const double* A, int lda, int n, int t, float* pool, hipStream_t s) {
+  const int T = t * (t + 1) / 2;
+  hipLaunchKernelGGL(copy_in32_kernel, dim3(T), dim3(NTHREADS), 0, s, A, lda, n, pool);
+  return hipGetLastError();
+}
+
+hipError_t launch_sched32(const SchedArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(sched_kernel32, dim3(grid), dim3(NTHREADS), 0, s, a, a.tiles_T, a.tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_x0_to_sym64(const float* pool, int t, int n, double* X, hipStream_t s) {
+  hipLaunchKernelGGL(x0_to_sym64_kernel, dim3(t * t), dim3(NTHREADS), 0, s, pool, t, n, X);
+  return hipGetLastError();
+}
+
+int sched32_blocks_per_cu() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sched_kernel32, NTHREADS, 0) !=
+      hipSuccess)
+    return 1;
+  return blocks > 0 ? blocks : 1;
+}
+
+}  // namespace spdinv

@@ -1,0 +1,25 @@
+// Internal interface of the FP32 tile path of the mixed-precision form
+// (mixed.hip).  Not part of the public header.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace spdinv {
+
+// Bytes of the FP32 tile pool for t tiles per side (pool layout as FP64).
+size_t pool_bytes32(int t);
+
+// Lower triangle of the FP64 column-major A -> FP32 lower tiles, identity
+// padding beyond n.
+hipError_t launch_copy_in32(const double* A, int lda, int n, int t, float* pool, hipStream_t s);
+
+// Persistent scheduler over the renamed plan with FP32 tile tasks.
+hipError_t launch_sched32(const SchedArgs& a, int grid, hipStream_t s);
+
+// FP32 lower tiles -> square tile-major FP64 symmetric matrix (zero beyond n).
+hipError_t launch_x0_to_sym64(const float* pool, int t, int n, double* X, hipStream_t s);
+
+int sched32_blocks_per_cu();
+
+}  // namespace spdinv

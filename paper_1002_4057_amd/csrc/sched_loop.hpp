@@ -1,0 +1,87 @@
+// The persistent worker loop of the dependency-tracked scheduler, shared by
+// the FP64 scheduler (device.hip) and the FP32 one of the mixed-precision
+// form (mixed.hip); run(task) executes one tile task with the whole
+// workgroup.
+#pragma once
+#include "device.hpp"
+#include "mfma_tile.hpp"
+
+namespace spdinv {
+namespace {
+
+using tile::now_ticks;
+using tile::stores_complete;
+
+// Persistent worker loop.  Thread 0 of each workgroup is the only one that
+// talks to the scheduler state: at the head of every iteration it first
+// releases the successors of the task the workgroup just finished (one
+// decrement of each successor's in-degree, once every thread's stores of that
+// task have completed), then claims the next dispatch ticket and waits until
+// that task's in-degree is zero.  Counters and tiles are accessed with
+// agent-scope coherence, so no cache maintenance is needed.  Keeping both in
+// one thread-0 region at the loop head leaves the loop body (and every
+// barrier in it) in uniform control flow.
+template <class Run>
+__device__ __forceinline__ void sched_loop(const SchedArgs& g, Run run) {
+  __shared__ int s_task;
+  __shared__ int s_skip;
+  int prev = -1;  // meaningful in thread 0 only
+  for (;;) {
+    if (threadIdx.x == 0) {
+      if (prev >= 0) {
+        if (g.trace) g.trace[4 * (size_t)prev + 3] = now_ticks();
+        const DevTask& pt = g.tasks[prev];
+        for (int e = pt.succ_begin; e < pt.succ_end; ++e)
+          __hip_atomic_fetch_sub(&g.indeg[g.succ[e]], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&g.ctrl[CTRL_DONE], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      long long t_claim = 0;
+      if (g.trace) t_claim = now_ticks();
+      const int tk = __hip_atomic_fetch_add(&g.ctrl[CTRL_TICKET], 1, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+      int v = tk < g.ntask ? g.order[tk] : -1;
+      if (v >= 0) {
+        // bounded wait: gives up after spin_limit ticks of the 100 MHz clock
+        const long long t0 = now_ticks();
+        long long spins = 0;
+        while (__hip_atomic_load(&g.indeg[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0) {
+          __builtin_amdgcn_s_sleep(1);
+          if ((++spins & 63) == 0) {
+            if (__hip_atomic_load(&g.ctrl[CTRL_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+              v = -1;
+              break;
+            }
+            if (now_ticks() - t0 > g.spin_limit) {
+              __hip_atomic_store(&g.ctrl[CTRL_ABORT], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              v = -1;
+              break;
+            }
+          }
+        }
+      }
+      if (v >= 0) {
+        if (g.trace) {
+          g.trace[4 * (size_t)v + 0] = blockIdx.x;
+          g.trace[4 * (size_t)v + 1] = t_claim;
+          g.trace[4 * (size_t)v + 2] = now_ticks();
+        }
+        s_skip = __hip_atomic_load(&g.ctrl[CTRL_FAILED], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      s_task = v;
+      prev = v;
+    }
+    __syncthreads();
+    // s_task and s_skip hold one value for the whole workgroup; reading them
+    // through readfirstlane makes the loop exit and the task dispatch
+    // wave-uniform
+    const int v = __builtin_amdgcn_readfirstlane(s_task);
+    if (v < 0) break;
+    const DevTask t = g.tasks[v];
+    if (!__builtin_amdgcn_readfirstlane(s_skip)) run(t);
+    stores_complete();
+    __syncthreads();
+  }
+}
+
+}  // namespace
+}  // namespace spdinv

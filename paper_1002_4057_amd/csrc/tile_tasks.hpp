@@ -458,14 +458,6 @@ __device__ __forceinline__ void tile_copy(const double* src, double* dst) {
   }
 }
 
-// A task's results are published when its agent-coherent stores have
-// completed: every thread waits for its outstanding memory operations before
-// the workgroup barrier that precedes the successors' counter decrements.
-__device__ __forceinline__ void stores_complete() { __builtin_amdgcn_s_waitcnt(0); }
-
-__device__ __forceinline__ long long now_ticks() {
-  return (long long)__builtin_amdgcn_s_memrealtime();
-}
 
 __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, double* smem, int T,
                                          int tiles) {

@@ -110,3 +110,22 @@ def test_batched_invalid_arguments_rejected_on_host():
     assert lib.batched_spd_inverse(2, n, 1, 1, 1, 2, 1, 1 << 40, None, None, None) == -6
     o = spd.make_opts(nb=64)
     assert lib.batched_spd_inverse(2, n, 1, 1, 1, 0, 1, 1 << 40, None, ctypes.byref(o), None) == -10
+
+
+def test_mixed_mode_host_checks():
+    lib = _lib.load()
+    o = spd.make_opts(renamed=0)
+    assert lib.spd_inverse(4, 1, 4, _lib.SPDINV_MIXED_FP32, 1, 1 << 30, None, ctypes.byref(o),
+                           None, None) == -8
+    assert lib.spd_inverse(4, 1, 4, _lib.SPDINV_MIXED_BF16, 1, 1 << 30, None, None, None,
+                           None) == -4
+    assert spd.workspace_bytes(1000, mode="mixed_fp32") > spd.workspace_bytes(1000)
+    assert lib.spd_inverse(512, 1, 512, _lib.SPDINV_MIXED_FP32, 1, 16, None, None, None,
+                           None) == _lib.ERR_WORKSPACE
+
+
+def test_every_source_is_built():
+    from paper_1002_4057_amd import build
+    csrc = os.path.join(ROOT, "paper_1002_4057_amd", "csrc")
+    srcs = {f for f in os.listdir(csrc) if f.endswith((".hip", ".cpp"))}
+    assert srcs == set(build.SOURCES)
