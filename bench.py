@@ -68,6 +68,122 @@ def cpu_baseline(n_sample: int, kappa: float):
                       f"(same construction, kappa={kappa:g}), {dt:.1f} s wall"}
 
 
+def time_events(fn, reps, prep=None):
+    """Average milliseconds of fn() over reps, HIP events on torch's current
+    stream (the stream the library launches on); prep() runs untimed before
+    each call."""
+    import torch
+    times = []
+    for _ in range(reps):
+        if prep is not None:
+            prep()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return sum(times) / len(times)
+
+
+def batched_row(reps: int):
+    """Batched workload: 8192 matrices, n uniform on {16..512} (seed 0),
+    A_i = B_i B_i^T / n_i + 0.1 I, one persistent launch per step."""
+    import numpy as np
+    import torch
+    import paper_1002_4057_amd as spd
+    from paper_1002_4057_amd import inputs
+    dev = torch.device("cuda:0")
+    orders = inputs.batch_orders(8192, 16, 512, seed=0)
+    mats = inputs.batched_wishart(orders, seed=0, shift=0.1)
+    offs = np.concatenate([[0], np.cumsum([n * n for n in orders])]).astype(np.int64)
+    host = torch.empty(int(offs[-1]), dtype=torch.float64)
+    for m, n, o in zip(mats, orders, offs[:-1]):
+        host[int(o):int(o) + n * n] = m.t().reshape(-1)   # column-major
+    src = host.to(dev)
+    buf = src.clone()
+    ptrs = torch.tensor([buf.data_ptr() + 8 * int(o) for o in offs[:-1]], dtype=torch.int64,
+                        device=dev)
+    n_dev = torch.tensor(orders, dtype=torch.int32, device=dev)
+    info = torch.zeros(len(orders), dtype=torch.int32, device=dev)
+    work = spd.batched_spd_inverse_(ptrs, orders, n_dev, n_dev, info=info)   # warm: plans
+    torch.cuda.synchronize()
+    if int(info.abs().sum()) != 0:
+        raise RuntimeError("batched warm-up reported INFO != 0")
+    ms = time_events(lambda: spd.batched_spd_inverse_(ptrs, orders, n_dev, n_dev, work=work,
+                                                      info=info),
+                     reps, prep=lambda: buf.copy_(src))
+    flops = float(sum(float(n) ** 3 for n in orders))
+    return {"workload": "8192 SPD matrices, n uniform on [16,512] (seed 0), A_i = B_i B_i^T/n_i "
+                        "+ 0.1 I, FP64, one persistent launch",
+            "ms": round(ms, 3), "matrices_per_s": round(len(orders) / (ms / 1e3), 1),
+            "gflops": round(flops / (ms / 1e3) / 1e9, 1), "flops": flops, "reps": reps}
+
+
+def backward_row(reps: int):
+    """Differentiation workload (a): grad_A = -X sym(G) X at n = 4096."""
+    import torch
+    import paper_1002_4057_amd as spd
+    from paper_1002_4057_amd import inputs
+    dev = torch.device("cuda:0")
+    n = 4096
+    a = inputs.wishart_shift(n, seed=0).to(dev)
+    g = inputs.randn((n, n), seed=1).to(dev)
+    x = spd.spd_inverse(a)
+    out = torch.empty_like(x)
+    work = torch.empty(spd.backward_workspace_bytes(n), dtype=torch.uint8, device=dev)
+    spd.spd_inverse_backward(x, g, work=work, out=out)
+    torch.cuda.synchronize()
+    ms = time_events(lambda: spd.spd_inverse_backward(x, g, work=work, out=out), reps)
+    flops = 3.0 * float(n) ** 3
+    return {"workload": "backward of the inverse, n=4096, FP64 (3 n^3 flops)",
+            "ms": round(ms, 3), "gflops": round(flops / (ms / 1e3) / 1e9, 1),
+            "frac_fp64_peak": round(flops / (ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+            "reps": reps}
+
+
+def mixed_row(reps: int, n: int = 16384, kappa: float = 1e2):
+    """Precision workload: FP64 form vs mixed-refined form (FP32 tile DAG +
+    binary64 Newton-Schulz) at n = 16384, kappa = 1e2, time to solution of
+    each and ||I - A X||_F / ||A||_F of each result (measured untimed with a
+    library GEMM)."""
+    import torch
+    import paper_1002_4057_amd as spd
+    from paper_1002_4057_amd import inputs
+    dev = torch.device("cuda:0")
+    a, q, lam = inputs.spectrum(n, kappa, seed=0, device="cuda", return_factors=True)
+    del q, lam
+    a_cm = a.t().contiguous()
+    need = max(spd.workspace_bytes(n), spd.workspace_bytes(n, mode="mixed_fp32"))
+    work = torch.empty(need, dtype=torch.uint8, device=dev)
+    buf = a_cm.clone()
+    anorm = torch.linalg.norm(a).item()
+
+    def resid():
+        low = torch.tril(buf.t())
+        x = low + torch.tril(low, -1).t()
+        r = torch.eye(n, dtype=torch.float64, device=dev) - a @ x
+        return (torch.linalg.norm(r) / anorm).item()
+
+    out = {"workload": f"precision form, n={n}, A = Q diag(lambda) Q^T, lambda log-spaced over "
+                       f"[1,{kappa:g}]; FP64 vs mixed (FP32 tiles + binary64 refinement, "
+                       f"stop at ||I-AX||_F/||A||_F <= 1e-13)"}
+    reports = {}
+    for label, mode in (("fp64", "fp64"), ("mixed_fp32", "mixed_fp32")):
+        buf.copy_(a_cm)
+        reports[label] = spd.spd_inverse_(buf.t(), mode=mode, work=work, report=True)   # warm
+        ms = time_events(lambda: spd.spd_inverse_(buf.t(), mode=mode, work=work, report=True),
+                         reps, prep=lambda: buf.copy_(a_cm))
+        out[label] = {"ms": round(ms, 2), "gflops": round(float(n) ** 3 / (ms / 1e3) / 1e9, 1),
+                      "resid_fro_rel": resid()}
+    rep = reports["mixed_fp32"]
+    out["mixed_fp32"].update({"refine_iters": rep["refine_iters"], "fell_back": rep["fell_back"],
+                              "resid0_fro_rel": rep["resid0_fro_rel"]})
+    out["speedup_mixed_over_fp64"] = round(out["fp64"]["ms"] / out["mixed_fp32"]["ms"], 3)
+    out["reps"] = reps
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,8 +191,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--kappa", type=float, default=1e4)
-    ap.add_argument("--cpu-n", type=int, default=6144, help="oracle sample order (0 = skip)")
+    ap.add_argument("--cpu-n", type=int, default=8192, help="oracle sample order (0 = skip)")
     ap.add_argument("--no-unpipelined", action="store_true")
+    ap.add_argument("--rows", default="batched,backward,mixed",
+                    help="extra measured rows: batched, backward, mixed (comma list, '' = none)")
     ap.add_argument("--input", choices=["spectrum", "wishart"], default="spectrum",
                     help="wishart (B B^T/n + I, no QR) is for profiler counter runs only")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -167,6 +285,18 @@ def main():
         log(f"[bench] calibration copy of {args.calibrate_copy} MiB done")
         del src, dst
 
+    rows = {}
+    wanted = [r for r in args.rows.split(",") if r]
+    if "batched" in wanted:
+        log("[bench] batched row")
+        rows["batched"] = batched_row(max(2, min(K, 5)))
+    if "backward" in wanted:
+        log("[bench] backward row")
+        rows["backward"] = backward_row(max(2, min(K, 5)))
+    if "mixed" in wanted:
+        log("[bench] mixed row")
+        rows["mixed"] = mixed_row(max(2, min(K, 3)))
+
     cpu = None
     if args.cpu_n > 0:
         log(f"[bench] oracle sample n={args.cpu_n}")
@@ -197,6 +327,7 @@ def main():
         "parity": ({"rel_fro_vs_analytic": rel, "bar": 1e-12 * args.kappa} if rel is not None
                    else None),
         "pipelining": pipe,
+        "rows": rows,
     }
     print(json.dumps(line), flush=True)
 

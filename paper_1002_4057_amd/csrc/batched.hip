@@ -60,7 +60,7 @@ __device__ int small_inverse(double* A, int lda, int n, int fill_upper, double* 
     T[r + LD * c] = v;
   }
   __syncthreads();
-  const int f = factor_lds(T, XD, flag, P);
+  const int f = factor_lds(T, XD, SCR, flag, P);
   if (f) return f;
   inverse_lds(T, XD, SCR, P);
   __syncthreads();

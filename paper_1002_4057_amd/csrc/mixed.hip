@@ -175,7 +175,8 @@ __device__ __attribute__((noinline)) int potrf_inv_tile32(const float* Ain, floa
   double* SCR = XD + 8 * 256;
   int* flag = reinterpret_cast<int*>(SCR + 4 * 256);
   const int tid = threadIdx.x;
-  const rsrc_t rIn = rsrc32(Ain), rL = rsrc32(Lout), rX = rsrc32(Xout), rXT = rsrc32(XoutT);
+  const rsrc_t rIn = rsrc32(Ain), rL = rsrc32(Lout ? Lout : Xout), rX = rsrc32(Xout),
+               rXT = rsrc32(XoutT);
   for (int e0 = 0; e0 < NB * NB; e0 += 4 * NTHREADS * 8) {
     f4 v[8];
 #pragma unroll
@@ -188,21 +189,23 @@ __device__ __attribute__((noinline)) int potrf_inv_tile32(const float* Ain, floa
     }
   }
   __syncthreads();
-  const int ff = factor_lds(T, XD, flag, 8);
+  const int ff = factor_lds(T, XD, SCR, flag, 8);
   if (ff) return ff;
-  const rsrc_t rLT = rsrc32(LcopyT ? LcopyT : Lout);
+  const rsrc_t rLT = rsrc32(LcopyT ? LcopyT : Xout);
+  if (Lout) {  // skipped when nothing reads the factor
 #pragma unroll 2
-  for (int q = 0; q < NB * NB / 4 / NTHREADS; ++q) {
-    const int e = 4 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
-    f4 v;
+    for (int q = 0; q < NB * NB / 4 / NTHREADS; ++q) {
+      const int e = 4 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
+      f4 v;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) v[s] = (rr + s >= cc) ? (float)T[rr + s + LD * cc] : 0.0f;
-    st4f(rL, e, v);
-    if (LcopyT) {
-      f4 u;
+      for (int s = 0; s < 4; ++s) v[s] = (rr + s >= cc) ? (float)T[rr + s + LD * cc] : 0.0f;
+      st4f(rL, e, v);
+      if (LcopyT) {
+        f4 u;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) u[s] = (cc >= rr + s) ? (float)T[cc + LD * (rr + s)] : 0.0f;
-      st4f(rLT, e, u);
+        for (int s = 0; s < 4; ++s) u[s] = (cc >= rr + s) ? (float)T[cc + LD * (rr + s)] : 0.0f;
+        st4f(rLT, e, u);
+      }
     }
   }
   __syncthreads();
@@ -256,7 +259,8 @@ __device__ __forceinline__ void run_task32(const DevTask& t, const SchedArgs& g,
     case K_POTRF: {
       float* X = tile32(P, t.aux);
       float* Xt = tile32(P, t.aux + tiles);
-      const int fl = potrf_inv_tile32(out, out, cp, X, Xt, smem);
+      const bool live = !(t.kind & K_POTRF_FACTOR_DEAD);
+      const int fl = potrf_inv_tile32(out, live ? out : nullptr, cp, X, Xt, smem);
       if (fl && threadIdx.x == 0) {
         const int jt = t.aux - 3 * T;
         atomicMin(&g.ctrl[CTRL_INFO], g.info_base + jt * NB + fl);

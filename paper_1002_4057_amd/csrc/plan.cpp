@@ -225,6 +225,35 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
   if (!opt.pipelined) bld.emit_barrier();
   bld.step3();
 
+  // dead factor stores: a POTRF whose factor tile is not read before it is
+  // rewritten, and whose renaming copy is never read, stores only D_j, D_j^T
+  {
+    const int nt = (int)p->tasks.size();
+    std::vector<char> copy_read(pool_tiles(opt.t), 0);
+    for (const DevTask& d : p->tasks) {
+      if (d.a >= 0) copy_read[d.a] = 1;
+      if (d.b >= 0) copy_read[d.b] = 1;
+    }
+    for (int u = 0; u < nt; ++u) {
+      DevTask& d = p->tasks[u];
+      if (task_kind(d.kind) != K_POTRF) continue;
+      bool read = d.copy >= 0 && copy_read[d.copy];
+      for (int v = u + 1; v < nt && !read; ++v) {
+        const DevTask& e = p->tasks[v];
+        if (task_kind(e.kind) == K_NOP) continue;
+        if (e.a == d.out || e.b == d.out) read = true;
+        if (e.out == d.out) {  // next writer: an accumulating product reads it first
+          if (task_flags(e.kind) & F_ACC) read = true;
+          break;
+        }
+      }
+      if (!read) {
+        d.kind |= K_POTRF_FACTOR_DEAD;
+        d.copy = -1;
+      }
+    }
+  }
+
   const int n = (int)p->tasks.size();
   // CSR successors
   std::vector<int32_t> outdeg(n, 0);

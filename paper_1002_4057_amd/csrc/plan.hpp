@@ -66,6 +66,11 @@ enum ProductFlags : int32_t {
   F_ACC = 64,     // accumulate into C (else overwrite)
   F_COPYT = 128   // the copy destination receives the transposed result
 };
+// Bit 16 of DevTask::kind on a POTRF task: no task reads the factor tile
+// (in place or as its renaming copy) -- the device uses the explicit inverse
+// D_j instead -- so only D_j and D_j^T are stored.  The task keeps every
+// hazard edge of the paper's DAG.
+constexpr int32_t K_POTRF_FACTOR_DEAD = 1 << 16;
 inline int32_t task_kind(int32_t k) { return k & 0xff; }
 inline int32_t task_flags(int32_t k) { return (k >> 8) & 0xff; }
 

@@ -189,14 +189,9 @@ __device__ __attribute__((noinline)) void tile_mma_general(int f, double* C, con
 
 // ---------------------------------------------------------------------------
 // Diagonal tile: Cholesky factor L of the lower triangle of A and its inverse
-// X = L^{-1}, blocked by 16 (tile held in LDS, column-major, ld = NB):
-//   for each 16-column panel p:
-//     one wave factors the 16 x 16 diagonal block and inverts the factor
-//     (diag16: pivots broadcast with readlane, one row per lane);
-//     L_ip = A_ip X_pp^T for the blocks below it (16x16x16 MFMA blocks);
-//     A_ij -= L_ip L_jp^T on the trailing lower blocks (MFMA).
-//   Then X by block forward substitution, one block column per wave:
-//     X_ip = -X_ii (sum_{m=p..i-1} L_im X_mp).
+// X = L^{-1}, blocked by 16 with the tile held in LDS (factor_lds, then
+// inverse_lds: X by block forward substitution, one block column per wave,
+// X_ip = -X_ii (sum_{m=p..i-1} L_im X_mp)).
 // MFMA 16x16 blocks use the same lane layout as tile_mma: lane l, register r
 // holds row l%16, column l/16 + 4r of the block.
 // ---------------------------------------------------------------------------
@@ -207,18 +202,16 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Cholesky factor and inverse of the 16 x 16 block at S (column-major, ld),
-// executed by one whole wave; lane r (mod 16) holds row r.  Writes L (zeros
-// above the diagonal) back to S and X = L^{-1} to XD (16 x 16, ld 16).
-// Returns 0 or the 1-based index of the first non-positive pivot (uniform).
-__device__ __forceinline__ int diag16(double* S, int ld, double* XD) {
+// Cholesky factor of the 16 x 16 block at S (column-major, ld), executed by
+// one whole wave; lane r (mod 16) holds row r, pivots and pivot columns are
+// broadcast with readlane.  Writes L (zeros above the diagonal) back to S and
+// the reciprocal pivots 1/L_kk to rd[0..15].  Returns 0 or the 1-based index
+// of the first non-positive (or NaN) pivot (uniform).
+__device__ __forceinline__ int chol16(double* S, int ld, double* rd) {
   const int r = threadIdx.x & 15;
-  double row[16], x[16];
+  double row[16];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    row[c] = (c <= r) ? S[r + ld * c] : 0.0;
-    x[c] = (c == r) ? 1.0 : 0.0;
-  }
+  for (int c = 0; c < 16; ++c) row[c] = (c <= r) ? S[r + ld * c] : 0.0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     const double d = readlane_d(row[k], k);
@@ -229,6 +222,7 @@ __device__ __forceinline__ int diag16(double* S, int ld, double* XD) {
     const double h = d * rinv;
     rinv = fma(rinv * 0.5, fma(-h, rinv, 1.0), rinv);
     const double lkk = d * rinv;
+    if ((threadIdx.x & 63) == 0) rd[k] = rinv;
     // column k of L: scale below the pivot
     row[k] = (r > k) ? row[k] * rinv : ((r == k) ? lkk : row[k]);
     // right-looking update of the trailing rows with column k
@@ -237,23 +231,10 @@ __device__ __forceinline__ int diag16(double* S, int ld, double* XD) {
       const double lck = readlane_d(row[k], c);
       if (c <= r) row[c] = fma(-row[k], lck, row[c]);
     }
-    // inverse, row k of X is final: scale it, then update the rows below
-    if (r == k) {
-#pragma unroll
-      for (int c = 0; c <= k; ++c) x[c] *= rinv;
-    }
-#pragma unroll
-    for (int c = 0; c <= k; ++c) {
-      const double xkc = readlane_d(x[c], k);
-      if (r > k) x[c] = fma(-row[k], xkc, x[c]);
-    }
   }
   if ((threadIdx.x & 63) < 16) {
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
-      S[r + ld * c] = (c <= r) ? row[c] : 0.0;
-      XD[r + 16 * c] = (c <= r) ? x[c] : 0.0;
-    }
+    for (int c = 0; c < 16; ++c) S[r + ld * c] = (c <= r) ? row[c] : 0.0;
   }
   return 0;
 }
@@ -287,51 +268,94 @@ __device__ __forceinline__ void blk_store(double* S, int ld, d4 v) {
 
 // Blocked Cholesky factorization, in place, of the leading 16P x 16P block
 // of the lower triangle held in LDS (T, column-major, ld POTRF_LD; entries
-// above the diagonal are zero):
-//   for each 16-column panel p:
-//     one wave factors the 16 x 16 diagonal block and inverts the factor
-//     (diag16, into XD + 256 p);
-//     L_ip = A_ip X_pp^T for the blocks below it (16x16x16 MFMA blocks);
-//     A_ij -= L_ip L_jp^T on the trailing lower blocks (MFMA).
-// Returns 0 or the 1-based index of the first pivot that is not positive
-// (or NaN); the value is uniform over the workgroup.
+// above the diagonal are zero), with one block of lookahead:
+//   wave 0 factors the 16 x 16 diagonal block p (chol16);
+//   panel p: L_ip = A_ip L_pp^{-T} by forward substitution, one row per
+//     thread, L_pp read from LDS;
+//   trailing update A_ij -= L_ip L_jp^T (16x16x16 MFMA blocks): wave 0 first
+//     updates the next diagonal block and factors it while waves 1-3 update
+//     the other blocks.
+// Then the inverses X_pp = L_pp^{-1} of all diagonal blocks into XD (16 x 16
+// column-major each), 16 lanes per block, one column of X_pp per lane.
+// rd receives the 16P reciprocal pivots.  Returns 0 or the 1-based index of
+// the first pivot that is not positive (or NaN); the value is uniform over
+// the workgroup.
 constexpr int POTRF_LD = NB + 1;  // odd row stride: transposed LDS reads spread over banks
 
-__device__ __forceinline__ int factor_lds(double* T, double* XD, int* flag, int P) {
+__device__ __forceinline__ int factor_lds(double* T, double* XD, double* rd, int* flag, int P) {
   constexpr int LD = POTRF_LD;
   const int tid = threadIdx.x, w = tid >> 6;
-  for (int p = 0; p < P; ++p) {
-    double* Dpp = T + 16 * p * (LD + 1);
-    if (w == 0) {
-      const int f = diag16(Dpp, LD, XD + 256 * p);
-      if (tid == 0) *flag = f ? 16 * p + f : 0;
-    }
-    __syncthreads();
-    const int fail = __builtin_amdgcn_readfirstlane(*flag);
-    if (fail) return fail;
-    // panel: L_ip = A_ip X_pp^T
-    for (int i = p + 1 + w; i < P; i += 4) {
-      double* Bip = T + 16 * i + LD * 16 * p;
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
-      acc = blk_mma16(acc, Bip, LD, XD + 256 * p, 16, true);
-      blk_store(Bip, LD, acc);
-    }
-    __syncthreads();
-    // trailing update: A_ij -= L_ip L_jp^T, p < j <= i
-    const int nb = P - 1 - p;
-    for (int q = w; q < nb * (nb + 1) / 2; q += 4) {
-      int i = 0;
-      while ((i + 1) * (i + 2) / 2 <= q) ++i;
-      const int j = q - i * (i + 1) / 2;
-      const int bi = p + 1 + i, bj = p + 1 + j;
-      double* Cij = T + 16 * bi + LD * 16 * bj;
-      d4 acc = -blk_load(Cij, LD);
-      acc = blk_mma16(acc, T + 16 * bi + LD * 16 * p, LD, T + 16 * bj + LD * 16 * p, LD, true);
-      blk_store(Cij, LD, -acc);
-    }
-    __syncthreads();
+  if (w == 0) {
+    const int f = chol16(T, LD, rd);
+    if (tid == 0) *flag = f;
   }
-
+  __syncthreads();
+  int fail = __builtin_amdgcn_readfirstlane(*flag);
+  if (fail) return fail;
+  for (int p = 0; p < P; ++p) {
+    // panel: row R of the blocks below the diagonal block solves x L_pp^T = a
+    const int rows = 16 * (P - 1 - p);
+    if (tid < rows) {
+      const int R = 16 * (p + 1) + tid;
+      const double* Lpp = T + 16 * p * (LD + 1);
+      double* a = T + R + LD * 16 * p;
+      double x[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        double s = a[LD * c];
+#pragma unroll
+        for (int m = 0; m < c; ++m) s = fma(-x[m], Lpp[c + LD * m], s);
+        x[c] = s * rd[16 * p + c];
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) a[LD * c] = x[c];
+    }
+    __syncthreads();
+    if (p + 1 == P) break;
+    // trailing update: A_ij -= L_ip L_jp^T, p < j <= i; block (p+1, p+1)
+    // first (wave 0, which then factors it), the others on waves 1-3
+    const int nb = P - 1 - p;
+    if (w == 0) {
+      double* Cnn = T + 16 * (p + 1) * (LD + 1);
+      const double* Lnp = T + 16 * (p + 1) + LD * 16 * p;
+      d4 acc = -blk_load(Cnn, LD);
+      acc = blk_mma16(acc, Lnp, LD, Lnp, LD, true);
+      blk_store(Cnn, LD, -acc);
+      const int f = chol16(Cnn, LD, rd + 16 * (p + 1));
+      if (tid == 0) *flag = f ? 16 * (p + 1) + f : 0;
+    } else {
+      for (int q = w; q < nb * (nb + 1) / 2; q += 3) {
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= q) ++i;
+        const int j = q - i * (i + 1) / 2;
+        const int bi = p + 1 + i, bj = p + 1 + j;
+        double* Cij = T + 16 * bi + LD * 16 * bj;
+        d4 acc = -blk_load(Cij, LD);
+        acc = blk_mma16(acc, T + 16 * bi + LD * 16 * p, LD, T + 16 * bj + LD * 16 * p, LD, true);
+        blk_store(Cij, LD, -acc);
+      }
+    }
+    __syncthreads();
+    fail = __builtin_amdgcn_readfirstlane(*flag);
+    if (fail) return fail;
+  }
+  // X_bb = L_bb^{-1}: lane c of group b solves L_bb x = e_c by forward
+  // substitution (x_r = 0 for r < c comes out exactly)
+  const int g = tid >> 4, c = tid & 15;
+  if (g < P) {
+    const double* Lb = T + 16 * g * (LD + 1);
+    double x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      double s = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int m = 0; m < r; ++m) s = fma(-Lb[r + LD * m], x[m], s);
+      x[r] = s * rd[16 * g + r];
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) XD[256 * g + r + 16 * c] = x[r];
+  }
+  __syncthreads();
   return 0;
 }
 
@@ -367,9 +391,9 @@ __device__ __forceinline__ void inverse_lds(double* T, const double* XD, double*
   }
 }
 
-// Outputs: the factor (Lout), its transpose (LcopyT, may be null), the
-// inverse of the factor (Xout) and its transpose (XoutT), each with explicit
-// zeros in the other triangle.  Returns 0, or the 1-based local index of the
+// Outputs: the factor (Lout, may be null: not stored), its transpose (LcopyT,
+// may be null), the inverse of the factor (Xout) and its transpose (XoutT),
+// each with explicit zeros in the other triangle.  Returns 0, or the 1-based local index of the
 // first pivot that is not positive (or NaN); on failure nothing is stored.
 __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, double* Lout,
                                                          double* LcopyT, double* Xout,
@@ -380,7 +404,7 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
   double* SCR = XD + 8 * 256;          // [4][256] per-wave scratch block
   int* flag = reinterpret_cast<int*>(SCR + 4 * 256);
   const int tid = threadIdx.x, w = tid >> 6;
-  const rsrc_t rIn = tile_rsrc(Ain), rL = tile_rsrc(Lout), rX = tile_rsrc(Xout),
+  const rsrc_t rIn = tile_rsrc(Ain), rL = tile_rsrc(Lout ? Lout : Xout), rX = tile_rsrc(Xout),
                rXT = tile_rsrc(XoutT);
 
   // load the tile: batches of independent 16-byte loads, so that their
@@ -398,13 +422,13 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
   }
   __syncthreads();
 
-  const int ff = factor_lds(T, XD, flag, 8);
+  const int ff = factor_lds(T, XD, SCR, flag, 8);
   if (ff) return ff;
 
-  // the factor: global copies (and its transpose)
   // the factor and its transpose, as contiguous 16-byte stores (the
-  // transpose is taken on the LDS side)
-  const rsrc_t rLT = tile_rsrc(LcopyT ? LcopyT : Lout);
+  // transpose is taken on the LDS side); skipped when nothing reads them
+  const rsrc_t rLT = tile_rsrc(LcopyT ? LcopyT : Xout);
+  if (Lout) {
 #pragma unroll 4
   for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
     const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
@@ -418,6 +442,7 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
       u.y = (cc >= rr + 1) ? T[cc + LD * (rr + 1)] : 0.0;
       st2(rLT, e, u);
     }
+  }
   }
   __syncthreads();  // the inverse below writes the upper blocks of T
 
@@ -480,7 +505,8 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
     case K_POTRF: {
       double* X = tile_ptr(P, t.aux);
       double* Xt = tile_ptr(P, t.aux + tiles);
-      const int fl = potrf_inv_tile(out, out, cp, X, Xt, smem);
+      const bool live = !(t.kind & K_POTRF_FACTOR_DEAD);
+      const int fl = potrf_inv_tile(out, live ? out : nullptr, cp, X, Xt, smem);
       if (fl && threadIdx.x == 0) {
         const int jt = t.aux - 3 * T;  // diagonal tile index
         atomicMin(&g.ctrl[CTRL_INFO], g.info_base + jt * NB + fl);

@@ -107,10 +107,16 @@ def test_exported_plan_structure(opts):
     for col in (1, 2, 3, 4, 5):
         vals = tasks[:, col]
         assert np.all((vals == -1) | ((vals >= 0) & (vals < ntiles)))
-    # renaming copies target B (step 1) and C (step 2) only when renamed
+    # renaming copies target B (step 1) and C (step 2) only when renamed; the
+    # diagonal copies B_jj of the factor are never read (the device uses the
+    # explicit inverse D_j), so POTRF stores neither them nor the factor
+    kind = tasks[:, 0] & 0xFF
+    potrf = kind == 2
+    assert np.all(tasks[potrf, 0] & (1 << 16)), "every POTRF factor store is dead"
+    assert np.all(tasks[potrf, 4] == -1)
     copies = tasks[:, 4][tasks[:, 4] >= 0]
     if opts.get("renamed", 1):
-        assert len(copies) == 2 * T
+        assert len(copies) == 2 * T - t
         assert np.all((copies >= T) & (copies < 3 * T))
     else:
         assert len(copies) == 0

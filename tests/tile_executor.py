@@ -10,6 +10,7 @@ oracle on the CPU.
 import numpy as np
 
 NOP, SYRK1, POTRF, GEMM1, TRSM1, TRTRI, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEMM3, SYRK3 = range(13)
+POTRF_FACTOR_DEAD = 1 << 16
 PRODUCTS = {SYRK1, GEMM1, TRSM1, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEMM3, SYRK3}
 F_TA, F_TB, F_MA, F_MB, F_LOWER, F_NEG, F_ACC, F_COPYT = 1, 2, 4, 8, 16, 32, 64, 128
 
@@ -47,6 +48,7 @@ def run_task(pool, task, t):
     driven by the flags, the diagonal factorization, or the TRTRI copy."""
     code, out, a, b, cp, aux = (int(x) for x in task[:6])
     kind, f = code & 0xFF, (code >> 8) & 0xFF
+    factor_dead = bool(code & POTRF_FACTOR_DEAD)
     if kind == NOP:
         return
     if kind in PRODUCTS:
@@ -69,9 +71,10 @@ def run_task(pool, task, t):
         X = np.tril(np.linalg.inv(L))
         pool[aux] = X
         pool[aux + t] = X.T
-        pool[out] = L
-        if cp >= 0:
-            pool[cp] = L.T
+        if not factor_dead:      # a dead factor is not stored (nothing reads it)
+            pool[out] = L
+            if cp >= 0:
+                pool[cp] = L.T
     elif kind == TRTRI:
         pool[out] = pool[a]
         if cp >= 0:
