@@ -52,9 +52,8 @@ struct Key {
 struct DevPlan {
   Plan host;
   void* arena = nullptr;
-  DevTask* d_tasks = nullptr;
+  DevTask* d_tasks = nullptr;  // dispatch order
   int32_t* d_succ = nullptr;
-  int32_t* d_order = nullptr;
   int32_t* d_indeg0 = nullptr;
 };
 
@@ -146,20 +145,35 @@ DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, hipError
   build_plan(po, workers, kCost, &dp->host);
   const Plan& p = dp->host;
   const size_t nt = p.tasks.size();
+  // device arrays in dispatch order: task id on the device = dispatch ticket
+  std::vector<int32_t> pos(nt);
+  for (size_t k = 0; k < nt; ++k) pos[p.order[k]] = (int32_t)k;
+  std::vector<DevTask> dtask(nt);
+  std::vector<int32_t> dsucc;
+  dsucc.reserve(p.succ.size());
+  std::vector<int32_t> dindeg(nt);
+  for (size_t k = 0; k < nt; ++k) {
+    const int v = p.order[k];
+    DevTask d = p.tasks[v];
+    const int b = (int)dsucc.size();
+    for (int e = d.succ_begin; e < d.succ_end; ++e) dsucc.push_back(pos[p.succ[e]]);
+    d.succ_begin = b;
+    d.succ_end = (int)dsucc.size();
+    dtask[k] = d;
+    dindeg[k] = p.indeg[v];
+  }
   const size_t o_tasks = 0;
   const size_t o_succ = align_up(o_tasks + nt * sizeof(DevTask), 256);
-  const size_t o_order = align_up(o_succ + p.succ.size() * sizeof(int32_t) + 4, 256);
-  const size_t o_indeg = align_up(o_order + nt * sizeof(int32_t), 256);
+  const size_t o_indeg = align_up(o_succ + dsucc.size() * sizeof(int32_t) + 4, 256);
   const size_t bytes = align_up(o_indeg + nt * sizeof(int32_t), 256);
   void* arena = nullptr;
   *err = hipMalloc(&arena, bytes);
   if (*err != hipSuccess) return nullptr;
   char* base = (char*)arena;
   std::vector<char> host(bytes, 0);
-  std::memcpy(host.data() + o_tasks, p.tasks.data(), nt * sizeof(DevTask));
-  if (!p.succ.empty()) std::memcpy(host.data() + o_succ, p.succ.data(), p.succ.size() * sizeof(int32_t));
-  std::memcpy(host.data() + o_order, p.order.data(), nt * sizeof(int32_t));
-  std::memcpy(host.data() + o_indeg, p.indeg.data(), nt * sizeof(int32_t));
+  std::memcpy(host.data() + o_tasks, dtask.data(), nt * sizeof(DevTask));
+  if (!dsucc.empty()) std::memcpy(host.data() + o_succ, dsucc.data(), dsucc.size() * sizeof(int32_t));
+  std::memcpy(host.data() + o_indeg, dindeg.data(), nt * sizeof(int32_t));
   *err = hipMemcpy(arena, host.data(), bytes, hipMemcpyHostToDevice);
   if (*err != hipSuccess) {
     (void)hipFree(arena);
@@ -168,7 +182,6 @@ DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, hipError
   dp->arena = arena;
   dp->d_tasks = (DevTask*)(base + o_tasks);
   dp->d_succ = (int32_t*)(base + o_succ);
-  dp->d_order = (int32_t*)(base + o_order);
   dp->d_indeg0 = (int32_t*)(base + o_indeg);
   DevPlan* raw = dp.get();
   g_plans[k] = std::move(dp);
@@ -234,7 +247,6 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   SchedArgs a;
   a.tasks = dp->d_tasks;
   a.succ = dp->d_succ;
-  a.order = dp->d_order;
   a.indeg = indeg;
   a.ctrl = ctrl;
   a.pool = pool;
@@ -488,7 +500,6 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
   SchedArgs a;
   a.tasks = dp->d_tasks;
   a.succ = dp->d_succ;
-  a.order = dp->d_order;
   a.indeg = indeg;
   a.ctrl = ctrl;
   a.pool = reinterpret_cast<double*>(pool);
@@ -669,12 +680,26 @@ int spdinv_plan_export(int t, const spdinv_opts* opts, int workers, int32_t* tas
 long long spdinv_trace_copy(const void* work, int n, const spdinv_opts* opts, int64_t* host,
                             long long max_tasks) {
   if (!work || !host || n <= 0 || !opts || !opts->trace) return -1;
-  const Layout L = layout(n, *opts);
-  const long long nt = task_count(tiles_for(n));
-  const long long m = nt < max_tasks ? nt : max_tasks;
-  if (hipMemcpy(host, (const char*)work + L.trace, (size_t)m * 4 * sizeof(long long),
+  const spdinv_opts o = *opts;
+  const Layout L = layout(n, o);
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return -2;
+  hipError_t err = hipSuccess;
+  DevPlan* dp = get_plan(device, tiles_for(n), o, grid_for(device, o), &err);
+  if (!dp) return -2;
+  const Plan& p = dp->host;
+  const long long nt = (long long)p.tasks.size();
+  // the device records by dispatch position; the host order is program order
+  std::vector<long long> dev((size_t)nt * 4);
+  if (hipMemcpy(dev.data(), (const char*)work + L.trace, (size_t)nt * 4 * sizeof(long long),
                 hipMemcpyDeviceToHost) != hipSuccess)
     return -2;
+  const long long m = nt < max_tasks ? nt : max_tasks;
+  for (long long k = 0; k < nt; ++k) {
+    const long long v = p.order[k];
+    if (v < m)
+      for (int f = 0; f < 4; ++f) host[4 * v + f] = dev[4 * k + f];
+  }
   return m;
 }
 

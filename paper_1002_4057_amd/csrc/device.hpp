@@ -22,10 +22,10 @@ enum Ctrl : int {
   CTRL_WORDS = 16
 };
 
+// Task arrays on the device are in dispatch order: task id = ticket.
 struct SchedArgs {
   const DevTask* tasks;
   const int32_t* succ;
-  const int32_t* order;
   int32_t* indeg;      // mutable in-degree counters (reset before each run)
   int32_t* ctrl;       // Ctrl words
   double* pool;        // tile pool

@@ -12,14 +12,19 @@ namespace {
 using tile::now_ticks;
 using tile::stores_complete;
 
-// Persistent worker loop.  Thread 0 of each workgroup is the only one that
-// talks to the scheduler state: at the head of every iteration it first
-// releases the successors of the task the workgroup just finished (one
-// decrement of each successor's in-degree, once every thread's stores of that
-// task have completed), then claims the next dispatch ticket and waits until
-// that task's in-degree is zero.  Counters and tiles are accessed with
-// agent-scope coherence, so no cache maintenance is needed.  Keeping both in
-// one thread-0 region at the loop head leaves the loop body (and every
+// Persistent worker loop.  On the device the tasks are numbered in dispatch
+// order (the planner's list-scheduling order, a topological order), so a
+// dispatch ticket is the task id itself.  Thread 0 of each workgroup claims
+// the next ticket at the head of every iteration and waits until that task's
+// in-degree is zero; since tickets are topological, every claimed task's
+// predecessors hold earlier tickets, which makes the loop deadlock-free for
+// any number of resident workgroups.  The successor ids of the task are
+// loaded when it starts, one per thread, so that at its end (once every
+// thread's stores have completed) the threads release the successors with
+// parallel in-degree decrements.  Every divergent region (the thread-0 claim,
+// the release) sits between workgroup barriers.  Counters and tiles are accessed with
+// agent-scope coherence, so no cache maintenance is needed.  The claim sits in
+// one thread-0 region at the loop head, which leaves the loop body (and every
 // barrier in it) in uniform control flow.
 template <class Run>
 __device__ __forceinline__ void sched_loop(const SchedArgs& g, Run run) {
@@ -30,16 +35,13 @@ __device__ __forceinline__ void sched_loop(const SchedArgs& g, Run run) {
     if (threadIdx.x == 0) {
       if (prev >= 0) {
         if (g.trace) g.trace[4 * (size_t)prev + 3] = now_ticks();
-        const DevTask& pt = g.tasks[prev];
-        for (int e = pt.succ_begin; e < pt.succ_end; ++e)
-          __hip_atomic_fetch_sub(&g.indeg[g.succ[e]], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(&g.ctrl[CTRL_DONE], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
       long long t_claim = 0;
       if (g.trace) t_claim = now_ticks();
       const int tk = __hip_atomic_fetch_add(&g.ctrl[CTRL_TICKET], 1, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
-      int v = tk < g.ntask ? g.order[tk] : -1;
+      int v = tk < g.ntask ? tk : -1;
       if (v >= 0) {
         // bounded wait: gives up after spin_limit ticks of the 100 MHz clock
         const long long t0 = now_ticks();
@@ -77,8 +79,20 @@ __device__ __forceinline__ void sched_loop(const SchedArgs& g, Run run) {
     const int v = __builtin_amdgcn_readfirstlane(s_task);
     if (v < 0) break;
     const DevTask t = g.tasks[v];
+    const int nsucc = t.succ_end - t.succ_begin;
+    const int my_succ = (int)threadIdx.x < nsucc ? g.succ[t.succ_begin + threadIdx.x] : -1;
     if (!__builtin_amdgcn_readfirstlane(s_skip)) run(t);
     stores_complete();
+    __syncthreads();
+    // every store of the task has completed: release its successors
+    if (my_succ >= 0)
+      __hip_atomic_fetch_sub(&g.indeg[my_succ], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int e = threadIdx.x + NTHREADS; e < nsucc; e += NTHREADS)
+      __hip_atomic_fetch_sub(&g.indeg[g.succ[t.succ_begin + e]], 1, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    // convergence point: the divergent release and the thread-0 region at
+    // the loop head must not be merged across the back edge (the loop body,
+    // with its barriers, has to stay one level deep)
     __syncthreads();
   }
 }
