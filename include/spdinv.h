@@ -65,7 +65,9 @@ typedef enum {
   SPDINV_MIXED_FP32 = 2, /* tile products on FP32 matrix cores (FP32 accumulation),
                             diagonal tiles in binary64, then Newton-Schulz refinement
                             X <- X + X (I - A X) with binary64 residuals */
-  SPDINV_MIXED_BF16 = 3  /* reserved */
+  SPDINV_MIXED_BF16 = 3  /* as MIXED_FP32 with bfloat16 operands (rounded to nearest
+                            even from the FP32 tiles) on v_mfma_f32_16x16x16_bf16,
+                            FP32 accumulation; default max_refine 8 */
 } spdinv_mode;
 
 typedef struct {
@@ -81,7 +83,8 @@ typedef struct {
                       grid (1 = program order on one worker)                  */
   int fill_upper;  /* 1 = also write the strictly upper triangle (mirror)     */
   int trace;       /* 1 = record per-task timestamps (see spdinv_trace_*)    */
-  int max_refine;  /* mixed modes: most refinement steps (0 = library default, 6) */
+  int max_refine;  /* mixed modes: most refinement steps (0 = library default:
+                      6 for MIXED_FP32, 8 for MIXED_BF16)                     */
   double refine_tol; /* mixed modes: stop once ||I - A X||_F / ||A||_F <= refine_tol
                         (0 = library default, 1e-13)                            */
 } spdinv_opts;
@@ -110,7 +113,7 @@ void spdinv_default_opts(spdinv_opts* opts);
    workspace holds the three tile copies (A, B, C), the inverted diagonal
    tiles and the scheduler state. */
 size_t spd_inverse_workspace_bytes(int n, spdinv_mode mode, const spdinv_opts* opts);
-/* (for SPDINV_MIXED_FP32 this also holds the FP32 tile pool and four square
+/* (for the mixed modes this also holds the FP32 tile pool and four square
    binary64 matrices of ceil(n/128)*128: A, X, the next X and the residual) */
 
 /*

@@ -44,7 +44,8 @@ def _stream_ptr(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-MODES = {"fp64": _lib.SPDINV_FP64, "mixed_fp32": _lib.SPDINV_MIXED_FP32}
+MODES = {"fp64": _lib.SPDINV_FP64, "mixed_fp32": _lib.SPDINV_MIXED_FP32,
+         "mixed_bf16": _lib.SPDINV_MIXED_BF16}
 
 
 def _mode(mode) -> int:
@@ -69,9 +70,10 @@ def spd_inverse_(a_cm, *, mode: str = "fp64", work=None, report: bool = False, i
     preallocated uint8 CUDA tensor of at least ``workspace_bytes`` bytes.
     ``info`` may be a CUDA int32 tensor of one element receiving INFO.  With
     ``report=True`` the call synchronises and returns the library report as a
-    dict (raising NotPositiveDefinite on INFO > 0).  ``mode`` is "fp64" or
+    dict (raising NotPositiveDefinite on INFO > 0).  ``mode`` is "fp64",
     "mixed_fp32" (FP32 tile DAG + binary64 Newton-Schulz refinement; the
-    report then carries refine_iters, fell_back and the relative residuals).
+    report then carries refine_iters, fell_back and the relative residuals)
+    or "mixed_bf16" (the same with bfloat16 operands in the tile products).
     """
     import torch
     if a_cm.dtype != torch.float64 or not a_cm.is_cuda or a_cm.dim() != 2:

@@ -477,7 +477,7 @@ int grid32_for(int device, const spdinv_opts& o) {
 }
 
 int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStream_t stream,
-              const spdinv_opts& o, int* d_info, spdinv_report* report) {
+              const spdinv_opts& o, bool bf16, int* d_info, spdinv_report* report) {
   const MixedLayout M = mixed_layout(n, o);
   if (work_bytes < M.total) return SPDINV_ERR_WORKSPACE;
   int device = 0;
@@ -488,7 +488,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
   DevPlan* dp = get_plan(device, t, o, grid, &err);
   if (!dp) return SPDINV_ERR_HIP;
   const int ntask = (int)dp->host.tasks.size();
-  const int max_refine = o.max_refine > 0 ? o.max_refine : 6;
+  const int max_refine = o.max_refine > 0 ? o.max_refine : (bf16 ? 8 : 6);
   const double tol = o.refine_tol > 0.0 ? o.refine_tol : 1e-13;
 
   char* w = (char*)work;
@@ -509,7 +509,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
   a.tiles = t;
   a.info_base = 0;
   a.spin_limit = spin_limit();
-  if (launch_sched32(a, grid, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (launch_sched32(a, grid, bf16, stream) != hipSuccess) return SPDINV_ERR_HIP;
   int32_t c[CTRL_WORDS];
   if (hipMemcpyAsync(c, ctrl, sizeof(c), hipMemcpyDeviceToHost, stream) != hipSuccess)
     return SPDINV_ERR_HIP;
@@ -599,7 +599,7 @@ void spdinv_default_opts(spdinv_opts* opts) {
 size_t spd_inverse_workspace_bytes(int n, spdinv_mode mode, const spdinv_opts* opts) {
   if (n <= 0) return 0;
   const spdinv_opts o = opts ? *opts : defaults();
-  if (mode == SPDINV_MIXED_FP32) return mixed_layout(n, o).total;
+  if (mode == SPDINV_MIXED_FP32 || mode == SPDINV_MIXED_BF16) return mixed_layout(n, o).total;
   return layout(n, o).total;
 }
 
@@ -610,10 +610,11 @@ int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t 
   if (n < 0) return -1;
   if (n > 0 && !A) return -2;
   if (lda < (n > 1 ? n : 1)) return -3;
-  if (mode != SPDINV_FP64 && mode != SPDINV_MIXED_FP32) return -4;
+  if (mode != SPDINV_FP64 && mode != SPDINV_MIXED_FP32 && mode != SPDINV_MIXED_BF16) return -4;
   const spdinv_opts o = opts ? *opts : defaults();
   if (check_opts(o)) return -8;
-  if (mode == SPDINV_MIXED_FP32 && (!o.renamed || o.trace)) return -8;
+  const bool mixed = mode == SPDINV_MIXED_FP32 || mode == SPDINV_MIXED_BF16;
+  if (mixed && (!o.renamed || o.trace)) return -8;
   if (report) std::memset(report, 0, sizeof(*report));
   if (n == 0) {
     if (d_info) {
@@ -625,7 +626,9 @@ int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t 
     return 0;
   }
   if (!work) return -5;
-  if (mode == SPDINV_MIXED_FP32) return run_mixed(n, A, lda, work, work_bytes, stream, o, d_info, report);
+  if (mixed)
+    return run_mixed(n, A, lda, work, work_bytes, stream, o, mode == SPDINV_MIXED_BF16, d_info,
+                     report);
   return run_fp64(n, A, lda, work, work_bytes, stream, o, d_info, report);
 }
 

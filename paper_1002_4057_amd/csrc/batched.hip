@@ -134,7 +134,9 @@ __device__ int tile_sequential(double* A, int lda, int n, int fill_upper, const 
   g.info_base = 0;
   __shared__ int s_info;
   for (int k = 0; k < ntask; ++k) {
-    const DevTask task = tasks[k];
+    DevTask task = tasks[k];
+    // the pool is reused by the next matrix: keep every read device-coherent
+    task.kind &= ~(K_NC_A | K_NC_B);
     run_task(task, g, smem, T, t);
     stores_complete();
     __syncthreads();

@@ -1,6 +1,8 @@
 // Mixed-precision form of the SPD inverse on gfx950 (MI355X): the renamed,
 // pipelined tile DAG of Section 3 executed with FP32 tiles.  Tile products
-// run on the FP32 matrix cores (v_mfma_f32_16x16x4f32, FP32 accumulation);
+// run on the FP32 matrix cores (v_mfma_f32_16x16x4f32, FP32 accumulation) or,
+// in the BF16 variant, on bfloat16 operands rounded from the FP32 tiles
+// (v_mfma_f32_16x16x16_bf16, FP32 accumulation);
 // the diagonal tiles are factored and inverted in binary64 (the same LDS code
 // as the FP64 path) and rounded back.  The result is the starting inverse X0
 // that the Newton-Schulz refinement (FP64 residuals, dense.hip) corrects.
@@ -18,6 +20,14 @@ namespace spdinv {
 namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, rounded to nearest even (finite inputs)
+__device__ __forceinline__ short bf16_rne(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
 
 // Panel row stride in floats.  Operand reads take 16 consecutive rows r of
 // 4 consecutive k per wave: with a stride of 144 floats (144 mod 64 = 16
@@ -67,6 +77,7 @@ __device__ __forceinline__ void panel_store32(float* S, const f4 (&v)[Q32]) {
 // j+16k, d[i][j] in register i%4 of lane j + 16*(i/4).  The operands are
 // passed as (B block, A block), so lane l, register r holds output row l%16
 // of column 4*(l/16) + r.
+template <bool BF16>
 __device__ __forceinline__ void tile_mma32(int f, float* C, const float* A, const float* B,
                                            float* copy, double* smem_d) {
   float* smem = reinterpret_cast<float*>(smem_d);
@@ -104,21 +115,46 @@ __device__ __forceinline__ void tile_mma32(int f, float* C, const float* A, cons
       panel_load32(rB, (c + 1) * KC, vb);
     }
     __builtin_amdgcn_sched_barrier(0);
+    if constexpr (!BF16) {
 #pragma unroll
-    for (int ks = 0; ks < KC / 4; ++ks) {
-      const float* Ar = As + (4 * ks + lk) * LDS32 + wm * 64 + lr;
-      const float* Br = Bs + (4 * ks + lk) * LDS32 + wn * 64 + lr;
-      float a[4], b[4];
+      for (int ks = 0; ks < KC / 4; ++ks) {
+        const float* Ar = As + (4 * ks + lk) * LDS32 + wm * 64 + lr;
+        const float* Br = Bs + (4 * ks + lk) * LDS32 + wn * 64 + lr;
+        float a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = Ar[16 * i];
-        b[i] = Br[16 * i];
+        for (int i = 0; i < 4; ++i) {
+          a[i] = Ar[16 * i];
+          b[i] = Br[16 * i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[j], a[i], acc[i][j], 0, 0, 0);
       }
+    } else {
+      // v_mfma_f32_16x16x16_bf16: x[i][k] and y[k][j] from lane i (or j) +
+      // 16*(k/4), element k%4, accumulator layout as the FP32 instruction;
+      // the operands are rounded to bfloat16 as they leave LDS
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int kq = 0; kq < KC / 16; ++kq) {
+        s4 a[4], b[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[j], a[i], acc[i][j], 0, 0, 0);
+        for (int e = 0; e < 4; ++e) {
+          const float* Ar = As + (16 * kq + 4 * lk + e) * LDS32 + wm * 64 + lr;
+          const float* Br = Bs + (16 * kq + 4 * lk + e) * LDS32 + wn * 64 + lr;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            a[i][e] = bf16_rne(Ar[16 * i]);
+            b[i][e] = bf16_rne(Br[16 * i]);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b[j], a[i], acc[i][j], 0, 0, 0);
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
     if (more) {
@@ -243,6 +279,7 @@ __device__ __forceinline__ void tile_copy32(const float* src, float* dst) {
   }
 }
 
+template <bool BF16>
 __device__ __forceinline__ void run_task32(const DevTask& t, const SchedArgs& g, double* smem,
                                            int T, int tiles) {
   float* P = reinterpret_cast<float*>(g.pool);
@@ -254,7 +291,7 @@ __device__ __forceinline__ void run_task32(const DevTask& t, const SchedArgs& g,
   switch (kind) {
     case K_SYRK1: case K_GEMM1: case K_TRSM1: case K_TRMM2L: case K_GEMM2: case K_TRSM2R:
     case K_TRMM3: case K_LAUUM: case K_GEMM3: case K_SYRK3:
-      tile_mma32(f, out, a, b, cp, smem);  // renamed plan: A B^T products only
+      tile_mma32<BF16>(f, out, a, b, cp, smem);  // renamed plan: A B^T products only
       break;
     case K_POTRF: {
       float* X = tile32(P, t.aux);
@@ -277,9 +314,10 @@ __device__ __forceinline__ void run_task32(const DevTask& t, const SchedArgs& g,
   }
 }
 
+template <bool BF16>
 __global__ __launch_bounds__(NTHREADS) void sched_kernel32(SchedArgs g, int T, int tiles) {
   __shared__ double smem[SMEM_DOUBLES];
-  sched_loop(g, [&](const DevTask& t) { run_task32(t, g, smem, T, tiles); });
+  sched_loop(g, [&](const DevTask& t) { run_task32<BF16>(t, g, smem, T, tiles); });
 }
 
 __device__ __forceinline__ void tri_decode32(int x, int& ti, int& tj) {
@@ -354,8 +392,12 @@ hipError_t launch_copy_in32(const double* A, int lda, int n, int t, float* pool,
   return hipGetLastError();
 }
 
-hipError_t launch_sched32(const SchedArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(sched_kernel32, dim3(grid), dim3(NTHREADS), 0, s, a, a.tiles_T, a.tiles);
+hipError_t launch_sched32(const SchedArgs& a, int grid, bool bf16, hipStream_t s) {
+  if (bf16)
+    hipLaunchKernelGGL(sched_kernel32<true>, dim3(grid), dim3(NTHREADS), 0, s, a, a.tiles_T, a.tiles);
+  else
+    hipLaunchKernelGGL(sched_kernel32<false>, dim3(grid), dim3(NTHREADS), 0, s, a, a.tiles_T,
+                       a.tiles);
   return hipGetLastError();
 }
 
@@ -366,7 +408,7 @@ hipError_t launch_x0_to_sym64(const float* pool, int t, int n, double* X, hipStr
 
 int sched32_blocks_per_cu() {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sched_kernel32, NTHREADS, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sched_kernel32<false>, NTHREADS, 0) !=
       hipSuccess)
     return 1;
   return blocks > 0 ? blocks : 1;

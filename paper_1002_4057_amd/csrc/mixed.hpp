@@ -14,8 +14,9 @@ size_t pool_bytes32(int t);
 // padding beyond n.
 hipError_t launch_copy_in32(const double* A, int lda, int n, int t, float* pool, hipStream_t s);
 
-// Persistent scheduler over the renamed plan with FP32 tile tasks.
-hipError_t launch_sched32(const SchedArgs& a, int grid, hipStream_t s);
+// Persistent scheduler over the renamed plan with FP32 tile tasks (bf16: the
+// products take bfloat16 operands).
+hipError_t launch_sched32(const SchedArgs& a, int grid, bool bf16, hipStream_t s);
 
 // FP32 lower tiles -> square tile-major FP64 symmetric matrix (zero beyond n).
 hipError_t launch_x0_to_sym64(const float* pool, int t, int n, double* X, hipStream_t s);

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstring>
 #include <queue>
+#include <unordered_map>
 #include <utility>
 
 namespace spdinv {
@@ -251,6 +252,44 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
         d.kind |= K_POTRF_FACTOR_DEAD;
         d.copy = -1;
       }
+    }
+  }
+
+  // L2-cacheable operand reads: only tiles written exactly once in the plan
+  // and not accessed at all before that write (the renaming copies and the
+  // inverted diagonal tiles).  Device-coherent loads may still leave lines
+  // in the reading XCD's L2, so a tile that was read (or written) in an
+  // earlier version during the launch is never read through the cache.
+  {
+    const int nt = (int)p->tasks.size();
+    const int64_t ntiles = pool_tiles(opt.t);
+    std::vector<int32_t> writes(ntiles, 0);
+    std::vector<char> touched_first(ntiles, 0);  // accessed before its first write
+    for (int u = 0; u < nt; ++u) {
+      const DevTask& d = p->tasks[u];
+      const int k = task_kind(d.kind);
+      if (k == K_NOP) continue;
+      const bool acc = k != K_POTRF && k != K_TRTRI && (task_flags(d.kind) & F_ACC);
+      for (int tile : {d.a, d.b}) {
+        if (tile >= 0 && writes[tile] == 0) touched_first[tile] = 1;
+      }
+      if ((acc || k == K_POTRF) && d.out >= 0 && writes[d.out] == 0) touched_first[d.out] = 1;
+      if (d.out >= 0) writes[d.out]++;
+      if (d.copy >= 0) writes[d.copy]++;
+      if (k == K_POTRF) {
+        writes[d.aux]++;
+        writes[d.aux + opt.t]++;
+      }
+    }
+    auto cacheable = [&](int tile) {
+      return tile >= 0 && writes[tile] == 1 && !touched_first[tile];
+    };
+    for (int u = 0; u < nt; ++u) {
+      DevTask& d = p->tasks[u];
+      const int k = task_kind(d.kind);
+      if (k == K_NOP || k == K_POTRF || k == K_TRTRI) continue;
+      if (cacheable(d.a)) d.kind |= K_NC_A;
+      if (cacheable(d.b)) d.kind |= K_NC_B;
     }
   }
 

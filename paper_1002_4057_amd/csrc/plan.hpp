@@ -71,6 +71,17 @@ enum ProductFlags : int32_t {
 // D_j instead -- so only D_j and D_j^T are stored.  The task keeps every
 // hazard edge of the paper's DAG.
 constexpr int32_t K_POTRF_FACTOR_DEAD = 1 << 16;
+// Bits 17/18 of DevTask::kind on a tile product: operand a / b may be read
+// through the L2 cache (default cache policy) instead of the device-coherent
+// policy.  The planner grants it only for tiles that are written exactly once
+// in the plan and not accessed before that write (the renaming copies and the
+// inverted diagonal tiles): their only version is read after it is written
+// (RAW), so no L2 line of such a tile can hold anything else within a
+// launch, and lines left by an earlier launch are invalidated at the kernel
+// boundary.  (Device-coherent loads can leave lines in the reading XCD's L2,
+// so a tile read in an earlier version is never read through the cache.)
+constexpr int32_t K_NC_A = 1 << 17;
+constexpr int32_t K_NC_B = 1 << 18;
 inline int32_t task_kind(int32_t k) { return k & 0xff; }
 inline int32_t task_flags(int32_t k) { return (k >> 8) & 0xff; }
 

@@ -51,7 +51,8 @@ constexpr int SMEM_DOUBLES = GEMM_SMEM > POTRF_SMEM ? GEMM_SMEM : POTRF_SMEM;
 // ---------------------------------------------------------------------------
 template <bool FAST>
 __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, const double* B,
-                                         double* copy, double* smem) {
+                                         double* copy, double* smem, bool nca = false,
+                                         bool ncb = false) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int wm = w & 1, wn = w >> 1;
@@ -95,8 +96,18 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
   }
 
   d2 ra[PAIRS], rb[PAIRS];
-  panel_load(rA, 0, a_contig, ra);
-  panel_load(rB, 0, b_contig, rb);
+  // operand panels: through the L2 when the planner allows it for this read
+  // (nca / ncb), device-coherent otherwise
+  auto load_a = [&](int k0) {
+    if (nca) panel_load<0>(rA, k0, a_contig, ra);
+    else panel_load<CPOL_AGENT>(rA, k0, a_contig, ra);
+  };
+  auto load_b = [&](int k0) {
+    if (ncb) panel_load<0>(rB, k0, b_contig, rb);
+    else panel_load<CPOL_AGENT>(rB, k0, b_contig, rb);
+  };
+  load_a(0);
+  load_b(0);
   panel_store(smem, 0, a_contig, ma, ra);
   panel_store(smem + PANEL, 0, b_contig, mb, rb);
   __syncthreads();
@@ -107,8 +118,8 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
     const double* Bs = As + PANEL;
     const bool more = c + 1 < NCH;
     if (more) {
-      panel_load(rA, (c + 1) * KC, a_contig, ra);
-      panel_load(rB, (c + 1) * KC, b_contig, rb);
+      load_a((c + 1) * KC);
+      load_b((c + 1) * KC);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -498,7 +509,7 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
       // tile products; the planner chose operands and flags (Algorithm 1's
       // operation on the renamed or in-place tiles)
       if ((f & (F_TA | F_MA | F_MB)) == 0 && (f & F_TB))
-        tile_mma<true>(f, out, a, b, cp, smem);
+        tile_mma<true>(f, out, a, b, cp, smem, (t.kind & K_NC_A) != 0, (t.kind & K_NC_B) != 0);
       else
         tile_mma_general(f, out, a, b, cp, smem);
       break;

@@ -117,8 +117,12 @@ def test_mixed_mode_host_checks():
     o = spd.make_opts(renamed=0)
     assert lib.spd_inverse(4, 1, 4, _lib.SPDINV_MIXED_FP32, 1, 1 << 30, None, ctypes.byref(o),
                            None, None) == -8
-    assert lib.spd_inverse(4, 1, 4, _lib.SPDINV_MIXED_BF16, 1, 1 << 30, None, None, None,
+    assert lib.spd_inverse(4, 1, 4, _lib.SPDINV_FP32, 1, 1 << 30, None, None, None,
                            None) == -4
+    assert lib.spd_inverse(4, 1, 4, _lib.SPDINV_MIXED_BF16, 1, 1 << 30, None, ctypes.byref(o),
+                           None, None) == -8
+    assert spd.workspace_bytes(1000, mode="mixed_bf16") == spd.workspace_bytes(1000,
+                                                                               mode="mixed_fp32")
     assert spd.workspace_bytes(1000, mode="mixed_fp32") > spd.workspace_bytes(1000)
     assert lib.spd_inverse(512, 1, 512, _lib.SPDINV_MIXED_FP32, 1, 16, None, None, None,
                            None) == _lib.ERR_WORKSPACE

@@ -112,3 +112,34 @@ def test_precision_workload_n16384(kappa):
     assert err <= 1e-12 * kappa
     if not rep["fell_back"]:
         assert rep["resid_fro_rel"] <= 1e-13
+
+
+@pytest.mark.parametrize("n", [64, 300, 700])
+def test_mixed_bf16_well_conditioned_against_oracle(n):
+    """bfloat16 operands in the tile products: X0 carries a residual of the
+    bfloat16 unit roundoff's order, far above the FP32 start, and the
+    binary64 refinement still reaches the stop rule."""
+    a = inputs.wishart_shift(n, seed=40 + n, shift=1.0).numpy()
+    x, rep = spd.spd_inverse(torch.from_numpy(a).to(DEV), mode="mixed_bf16", return_report=True)
+    _, rep32 = spd.spd_inverse(torch.from_numpy(a).to(DEV), mode="mixed_fp32", return_report=True)
+    ref = oracle.spd_inverse(a)
+    ev = np.linalg.eigvalsh(a)
+    err = rel_fro(x.cpu().numpy(), ref)
+    print(f"bf16 n={n}: err {err:.3e}, report {rep}")
+    assert rep["fell_back"] == 0
+    assert rep["resid0_fro_rel"] > 30 * rep32["resid0_fro_rel"]   # bfloat16, not FP32, products
+    assert rep["resid_fro_rel"] <= 1e-13
+    assert err <= 1e-12 * ev[-1] / ev[0]
+
+
+def test_mixed_bf16_kappa_1e2_result_within_fp64_bar():
+    n = 513
+    a = inputs.spectrum(n, 1e2, seed=41).numpy()
+    x, rep = spd.spd_inverse(torch.from_numpy(a).to(DEV), mode="mixed_bf16", return_report=True)
+    print(f"bf16 kappa=1e2: report {rep}")
+    ref = oracle.spd_inverse(a)
+    assert rel_fro(x.cpu().numpy(), ref) <= 1e-12 * 1e2
+    if rep["fell_back"]:
+        assert torch.equal(x, spd.spd_inverse(torch.from_numpy(a).to(DEV)))
+    else:
+        assert rep["resid_fro_rel"] <= 1e-13

@@ -150,6 +150,33 @@ def test_repeated_calls_deterministic_and_workspace_reuse():
         np.testing.assert_array_equal(np.tril(o), np.tril(outs[0]))
 
 
+def test_alternating_matrices_share_one_workspace():
+    """Different matrices inverted one after the other through the same
+    workspace: every result must equal (bit for bit) the result of a fresh
+    workspace, so nothing read through the cache can come from the previous
+    call's tiles."""
+    n = 2048
+    mats = []
+    for seed in (1, 2):
+        a, q, lam = inputs.spectrum(n, 1e3, seed=seed, device=DEV, return_factors=True)
+        mats.append((a, inputs.analytic_inverse(q, lam)))
+    fresh = []
+    for a, _ in mats:
+        b = a.t().contiguous()
+        spd.spd_inverse_(b.t())
+        fresh.append(b.clone())
+    work = torch.empty(spd.workspace_bytes(n), dtype=torch.uint8, device=DEV)
+    for rep in range(6):
+        a, ref = mats[rep % 2]
+        b = a.t().contiguous()
+        spd.spd_inverse_(b.t(), work=work)
+        torch.cuda.synchronize()
+        assert torch.equal(b, fresh[rep % 2]), rep
+        low = torch.tril(b.t())
+        x = low + torch.tril(low, -1).t()
+        assert (torch.linalg.norm(x - ref) / torch.linalg.norm(ref)).item() <= 1e-12 * 1e3
+
+
 @pytest.mark.parametrize("k", [1, 5, 128, 129, 300])
 def test_info_not_positive_definite(k):
     n = 384

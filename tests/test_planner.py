@@ -125,3 +125,55 @@ def test_exported_plan_structure(opts):
 def test_invalid_tile_count():
     with pytest.raises(ValueError):
         spd.plan_stats(0)
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(pipelined=0), dict(renamed=0), dict(loop_order=1),
+                                  dict(renamed=0, trtri_first=1)])
+@pytest.mark.parametrize("t", [2, 5, 7])
+def test_l2_cacheable_reads_only_of_write_once_tiles(opts, t):
+    """Operand reads marked L2-cacheable (bits 17/18) may only target tiles
+    that the plan writes exactly once and that no task touches before that
+    write, and every such read must come after the write in the DAG."""
+    p = spd.plan_export(t, workers=4, **opts)
+    tasks, succ = p["tasks"], p["succ"]
+    n = len(tasks)
+    kind = tasks[:, 0] & 0xFF
+    writes, first_access, writer = {}, {}, {}
+    for u in range(n):
+        k = int(kind[u])
+        if k == 0:
+            continue
+        code, out, a, b, cp, aux = (int(x) for x in tasks[u, :6])
+        acc = k not in (2, 5) and ((code >> 8) & 64)
+        for tile in (a, b):
+            if tile >= 0:
+                first_access.setdefault(tile, "read")
+        if out >= 0 and (acc or k == 2):
+            first_access.setdefault(out, "read")
+        for tile in [out, cp] + ([aux, aux + t] if k == 2 else []):
+            if tile >= 0:
+                first_access.setdefault(tile, "write")
+                writes[tile] = writes.get(tile, 0) + 1
+                writer[tile] = u
+
+    def descendants(u):
+        seen, stack = set(), [u]
+        while stack:
+            x = stack.pop()
+            for s in succ[tasks[x, 6]:tasks[x, 7]]:
+                if int(s) not in seen:
+                    seen.add(int(s))
+                    stack.append(int(s))
+        return seen
+
+    count = 0
+    for u in range(n):
+        code = int(tasks[u, 0])
+        for bit, tile in ((17, int(tasks[u, 2])), (18, int(tasks[u, 3]))):
+            if (code >> bit) & 1:
+                count += 1
+                assert writes.get(tile) == 1, (u, tile)
+                assert first_access[tile] == "write", (u, tile)
+                assert u in descendants(writer[tile]), (u, tile)
+    if opts.get("renamed", 1):
+        assert count > 0
