@@ -87,6 +87,13 @@ typedef struct {
                       6 for MIXED_FP32, 8 for MIXED_BF16)                     */
   double refine_tol; /* mixed modes: stop once ||I - A X||_F / ||A||_F <= refine_tol
                         (0 = library default, 1e-13)                            */
+  int chain;       /* FP64 scheduler: most consecutive products of one output
+                      tile's update chain that run as one device task, the tile
+                      staying in registers between them (0 = library default,
+                      8; 1 = one device task per task of the paper's stream;
+                      at most 16).  Same products in the same order: results
+                      are bit-identical for every value.  The last product
+                      before a chain's closing task always runs alone.  */
 } spdinv_opts;
 
 typedef struct {
@@ -231,13 +238,17 @@ int spdinv_plan_stats_get(int t, const spdinv_opts* opts, spdinv_plan_stats* out
  * (tile indices into the pool layout: A tiles [0,T), B [T,2T), C [2T,3T),
  * inverted diagonal tiles [3T, 3T+t), T = t(t+1)/2, lower tile (i,j) at
  * i(i+1)/2+j), the successor array, the step of each task, its packed paper
- * indices (i<<20 | j<<10 | k) and the device dispatch order.  Pass NULL
- * buffers to query the sizes (ntasks, nsucc).  `workers` sizes the
- * list-scheduling simulation that produces the order.
+ * indices (i<<20 | j<<10 | k) and the device dispatch order.  With
+ * opts->chain != 1 a product task may carry further links: bits 20-23 of
+ * kind count them, aux indexes the first in `links` (int32 pairs: operand
+ * tiles a, b, bit 30 set where the operand is read through the L2 cache).
+ * Pass NULL buffers to query the sizes (ntasks, nsucc, nlinks).  `workers`
+ * sizes the list-scheduling simulation that produces the order.
  */
 int spdinv_plan_export(int t, const spdinv_opts* opts, int workers, int32_t* tasks8,
                        int32_t* succ, int32_t* step, int32_t* idx, int32_t* order,
-                       long long* ntasks, long long* nsucc);
+                       long long* ntasks, long long* nsucc, int32_t* links,
+                       long long* nlinks);
 
 /* ---- per-task trace (opts.trace = 1) -------------------------------------- */
 /* Copies the per-task trace that the last spd_inverse call with

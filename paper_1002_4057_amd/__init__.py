@@ -291,23 +291,26 @@ def plan_stats(t: int, **opts) -> dict:
 
 
 def plan_export(t: int, workers: int = 1, **opts) -> dict:
-    """The plan as numpy arrays: tasks (ntasks x 8 int32), succ, step, idx, order."""
+    """The plan as numpy arrays: tasks (ntasks x 8 int32), succ, step, idx,
+    order, and links (nlinks x 2 int32: the further operand pairs of chained
+    product tasks)."""
     lib = load()
     o = make_opts(**opts)
-    nt, ns = ctypes.c_longlong(), ctypes.c_longlong()
+    nt, ns, nl = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
     if lib.spdinv_plan_export(int(t), ctypes.byref(o), int(workers), None, None, None, None, None,
-                              ctypes.byref(nt), ctypes.byref(ns)) != 0:
+                              ctypes.byref(nt), ctypes.byref(ns), None, ctypes.byref(nl)) != 0:
         raise ValueError("invalid tile count")
     tasks = np.zeros((nt.value, 8), dtype=np.int32)
     succ = np.zeros(max(ns.value, 1), dtype=np.int32)
     step = np.zeros(nt.value, dtype=np.int32)
     idx = np.zeros(nt.value, dtype=np.int32)
     order = np.zeros(nt.value, dtype=np.int32)
+    links = np.zeros(max(nl.value, 2), dtype=np.int32)
     p = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
     lib.spdinv_plan_export(int(t), ctypes.byref(o), int(workers), p(tasks), p(succ), p(step),
-                           p(idx), p(order), None, None)
+                           p(idx), p(order), None, None, p(links), None)
     return {"tasks": tasks, "succ": succ[:ns.value], "step": step, "idx": idx, "order": order,
-            "t": int(t), "T": t * (t + 1) // 2}
+            "links": links[:nl.value].reshape(-1, 2), "t": int(t), "T": t * (t + 1) // 2}
 
 
 def trace(work, n: int, **opts) -> np.ndarray:

@@ -30,7 +30,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("nb", ctypes.c_int), ("pipelined", ctypes.c_int), ("renamed", ctypes.c_int),
                 ("loop_order", ctypes.c_int), ("trtri_first", ctypes.c_int),
                 ("workers", ctypes.c_int), ("fill_upper", ctypes.c_int), ("trace", ctypes.c_int),
-                ("max_refine", ctypes.c_int), ("refine_tol", ctypes.c_double)]
+                ("max_refine", ctypes.c_int), ("refine_tol", ctypes.c_double),
+                ("chain", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -77,7 +78,8 @@ def load():
     lib.spdinv_plan_stats_get.restype = i
     i32p = P(ctypes.c_int32)
     lib.spdinv_plan_export.argtypes = [i, P(Opts), i, i32p, i32p, i32p, i32p, i32p,
-                                       P(ctypes.c_longlong), P(ctypes.c_longlong)]
+                                       P(ctypes.c_longlong), P(ctypes.c_longlong), i32p,
+                                       P(ctypes.c_longlong)]
     lib.spdinv_plan_export.restype = i
     lib.spdinv_trace_copy.argtypes = [vp, i, P(Opts), P(ctypes.c_int64), ctypes.c_longlong]
     lib.spdinv_trace_copy.restype = ctypes.c_longlong

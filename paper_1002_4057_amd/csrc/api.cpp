@@ -41,11 +41,15 @@ const double kCost[K_COUNT] = {
     1.0,   // SYRK3
 };
 
+// Products per device task of the FP64 scheduler when opts.chain is 0.
+constexpr int kDefaultChain = 8;
+
 struct Key {
-  int device, t, renamed, loop_order, pipelined, trtri_first, workers;
+  int device, t, renamed, loop_order, pipelined, trtri_first, workers, chain;
   bool operator<(const Key& o) const {
-    return std::tie(device, t, renamed, loop_order, pipelined, trtri_first, workers) <
-           std::tie(o.device, o.t, o.renamed, o.loop_order, o.pipelined, o.trtri_first, o.workers);
+    return std::tie(device, t, renamed, loop_order, pipelined, trtri_first, workers, chain) <
+           std::tie(o.device, o.t, o.renamed, o.loop_order, o.pipelined, o.trtri_first, o.workers,
+                    o.chain);
   }
 };
 
@@ -55,6 +59,7 @@ struct DevPlan {
   DevTask* d_tasks = nullptr;  // dispatch order
   int32_t* d_succ = nullptr;
   int32_t* d_indeg0 = nullptr;
+  int32_t* d_links = nullptr;  // further links of chained tasks (or null)
 };
 
 std::mutex g_mu;
@@ -76,8 +81,11 @@ spdinv_opts defaults() {
   o.trace = 0;
   o.max_refine = 0;
   o.refine_tol = 0.0;
+  o.chain = 0;
   return o;
 }
+
+int chain_for(const spdinv_opts& o) { return o.chain > 0 ? o.chain : kDefaultChain; }
 
 int tiles_for(int n) { return (n + NB - 1) / NB; }
 
@@ -106,6 +114,7 @@ int check_opts(const spdinv_opts& o) {
   if (o.nb != 0 && o.nb != NB) return 1;
   if (o.loop_order < 0 || o.loop_order > 1) return 1;
   if (o.workers < 0) return 1;
+  if (o.chain < 0 || o.chain > MAX_CHAIN) return 1;
   return 0;
 }
 
@@ -129,9 +138,13 @@ int grid_for(int device, const spdinv_opts& o) {
   return g;
 }
 
-DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, hipError_t* err) {
+// The plan for t tiles per side, built once per (device, variant, workers,
+// chain) and kept with its device copy.  chain: most products per device
+// task (1 for executors that run the paper's tasks one by one).
+DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, int chain,
+                  hipError_t* err) {
   Key k{device, t, o.renamed ? 1 : 0, o.loop_order, o.pipelined ? 1 : 0, o.trtri_first ? 1 : 0,
-        workers};
+        workers, chain};
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_plans.find(k);
   if (it != g_plans.end()) return it->second.get();
@@ -142,6 +155,7 @@ DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, hipError
   po.loop_order = k.loop_order;
   po.pipelined = k.pipelined;
   po.trtri_first = k.trtri_first;
+  po.chain = k.chain;
   build_plan(po, workers, kCost, &dp->host);
   const Plan& p = dp->host;
   const size_t nt = p.tasks.size();
@@ -165,7 +179,8 @@ DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, hipError
   const size_t o_tasks = 0;
   const size_t o_succ = align_up(o_tasks + nt * sizeof(DevTask), 256);
   const size_t o_indeg = align_up(o_succ + dsucc.size() * sizeof(int32_t) + 4, 256);
-  const size_t bytes = align_up(o_indeg + nt * sizeof(int32_t), 256);
+  const size_t o_links = align_up(o_indeg + nt * sizeof(int32_t), 256);
+  const size_t bytes = align_up(o_links + p.links.size() * sizeof(int32_t) + 4, 256);
   void* arena = nullptr;
   *err = hipMalloc(&arena, bytes);
   if (*err != hipSuccess) return nullptr;
@@ -174,6 +189,8 @@ DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, hipError
   std::memcpy(host.data() + o_tasks, dtask.data(), nt * sizeof(DevTask));
   if (!dsucc.empty()) std::memcpy(host.data() + o_succ, dsucc.data(), dsucc.size() * sizeof(int32_t));
   std::memcpy(host.data() + o_indeg, dindeg.data(), nt * sizeof(int32_t));
+  if (!p.links.empty())
+    std::memcpy(host.data() + o_links, p.links.data(), p.links.size() * sizeof(int32_t));
   *err = hipMemcpy(arena, host.data(), bytes, hipMemcpyHostToDevice);
   if (*err != hipSuccess) {
     (void)hipFree(arena);
@@ -183,6 +200,7 @@ DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, hipError
   dp->d_tasks = (DevTask*)(base + o_tasks);
   dp->d_succ = (int32_t*)(base + o_succ);
   dp->d_indeg0 = (int32_t*)(base + o_indeg);
+  dp->d_links = p.links.empty() ? nullptr : (int32_t*)(base + o_links);
   DevPlan* raw = dp.get();
   g_plans[k] = std::move(dp);
   return raw;
@@ -232,7 +250,7 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   const int t = tiles_for(n);
   const int grid = grid_for(device, o);
   hipError_t err = hipSuccess;
-  DevPlan* dp = get_plan(device, t, o, grid, &err);
+  DevPlan* dp = get_plan(device, t, o, grid, chain_for(o), &err);
   if (!dp) return SPDINV_ERR_HIP;
   const int ntask = (int)dp->host.tasks.size();
 
@@ -250,6 +268,7 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   a.indeg = indeg;
   a.ctrl = ctrl;
   a.pool = pool;
+  a.links = dp->d_links;
   a.trace = trace;
   a.ntask = ntask;
   a.tiles_T = t * (t + 1) / 2;
@@ -370,7 +389,7 @@ int batched_spd_inverse(int batch, const int* h_n, const int* d_n, double* const
   for (int t = 2; t <= L.tmax; ++t) {
     hipError_t err = hipSuccess;
     // program-order execution by one workgroup: the plan's task list as built
-    DevPlan* dp = get_plan(device, t, o, 1, &err);
+    DevPlan* dp = get_plan(device, t, o, 1, 1, &err);
     if (!dp) return SPDINV_ERR_HIP;
     b.plan[t] = dp->d_tasks;
     b.plan_ntask[t] = (int)dp->host.tasks.size();
@@ -485,7 +504,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
   const int t = tiles_for(n);
   const int grid = grid32_for(device, o);
   hipError_t err = hipSuccess;
-  DevPlan* dp = get_plan(device, t, o, grid, &err);
+  DevPlan* dp = get_plan(device, t, o, grid, 1, &err);
   if (!dp) return SPDINV_ERR_HIP;
   const int ntask = (int)dp->host.tasks.size();
   const int max_refine = o.max_refine > 0 ? o.max_refine : (bf16 ? 8 : 6);
@@ -503,6 +522,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
   a.indeg = indeg;
   a.ctrl = ctrl;
   a.pool = reinterpret_cast<double*>(pool);
+  a.links = nullptr;
   a.trace = nullptr;
   a.ntask = ntask;
   a.tiles_T = t * (t + 1) / 2;
@@ -647,6 +667,7 @@ static PlanOptions plan_options(int t, const spdinv_opts* opts) {
   po.loop_order = o.loop_order;
   po.pipelined = o.pipelined ? 1 : 0;
   po.trtri_first = o.trtri_first ? 1 : 0;
+  po.chain = std::min(std::max(chain_for(o), 1), MAX_CHAIN);
   return po;
 }
 
@@ -666,7 +687,7 @@ int spdinv_plan_stats_get(int t, const spdinv_opts* opts, spdinv_plan_stats* out
 
 int spdinv_plan_export(int t, const spdinv_opts* opts, int workers, int32_t* tasks8, int32_t* succ,
                        int32_t* step, int32_t* idx, int32_t* order, long long* ntasks,
-                       long long* nsucc) {
+                       long long* nsucc, int32_t* links, long long* nlinks) {
   if (t < 1 || t > 1024) return -1;
   Plan p;
   build_plan(plan_options(t, opts), workers > 0 ? workers : 1, kCost, &p);
@@ -677,6 +698,9 @@ int spdinv_plan_export(int t, const spdinv_opts* opts, int workers, int32_t* tas
   if (step) std::memcpy(step, p.step.data(), p.step.size() * sizeof(int32_t));
   if (idx) std::memcpy(idx, p.idx.data(), p.idx.size() * sizeof(int32_t));
   if (order) std::memcpy(order, p.order.data(), p.order.size() * sizeof(int32_t));
+  if (nlinks) *nlinks = (long long)p.links.size();
+  if (links && !p.links.empty())
+    std::memcpy(links, p.links.data(), p.links.size() * sizeof(int32_t));
   return 0;
 }
 
@@ -688,7 +712,7 @@ long long spdinv_trace_copy(const void* work, int n, const spdinv_opts* opts, in
   int device = 0;
   if (hipGetDevice(&device) != hipSuccess) return -2;
   hipError_t err = hipSuccess;
-  DevPlan* dp = get_plan(device, tiles_for(n), o, grid_for(device, o), &err);
+  DevPlan* dp = get_plan(device, tiles_for(n), o, grid_for(device, o), chain_for(o), &err);
   if (!dp) return -2;
   const Plan& p = dp->host;
   const long long nt = (long long)p.tasks.size();

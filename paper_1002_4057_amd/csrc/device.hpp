@@ -29,6 +29,7 @@ struct SchedArgs {
   int32_t* indeg;      // mutable in-degree counters (reset before each run)
   int32_t* ctrl;       // Ctrl words
   double* pool;        // tile pool
+  const int32_t* links;  // further links of chained products (or nullptr)
   long long* trace;    // 4 per task, or nullptr
   int ntask;
   int tiles_T;         // lower tiles per copy, T = t(t+1)/2 (pool layout)

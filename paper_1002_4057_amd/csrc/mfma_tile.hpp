@@ -245,6 +245,21 @@ __device__ __forceinline__ void acc_store(double* C, const Acc& acc, bool neg, b
     }
 }
 
+// Arguments of an out-of-line device function arrive in vector registers,
+// where the compiler has to assume that they differ between lanes: a buffer
+// access through such a pointer becomes a loop over its distinct values.
+// The callers pass wave-uniform values, so re-reading them from the first
+// lane is exact and gives scalar addressing back.  (LDS pointers are left
+// alone: the compiler has already resolved their address space.)
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return reinterpret_cast<T*>(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // A task's results are published when its agent-coherent stores have
 // completed: every thread waits for its outstanding memory operations before
 // the workgroup barrier that precedes the successors' counter decrements.

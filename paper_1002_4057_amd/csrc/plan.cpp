@@ -212,6 +212,116 @@ struct Builder {
 
 inline int weight(int kind) { return task_kind(kind) == K_NOP ? 0 : 1; }
 
+// A product that reads both operands along stored columns (op(A) = A,
+// op(B) = B^T, no masks): the form the chained device product executes.
+bool column_product(const DevTask& d) {
+  const int k = task_kind(d.kind);
+  if (k == K_NOP || k == K_POTRF || k == K_TRTRI) return false;
+  const int f = task_flags(d.kind);
+  return (f & (F_TA | F_MA | F_MB)) == 0 && (f & F_TB) != 0;
+}
+
+// v can continue the chain of u: the next product on u's output tile,
+// accumulating, with the same sign and output mask, operands other than the
+// output tile, and no renaming copy of u's (intermediate) result.
+bool chainable(const DevTask& u, const DevTask& v) {
+  if (!column_product(u) || !column_product(v)) return false;
+  const int fu = task_flags(u.kind), fv = task_flags(v.kind);
+  return u.copy < 0 && (fv & F_ACC) && ((fu ^ fv) & (F_NEG | F_LOWER)) == 0 && v.a != v.out &&
+         v.b != v.out;
+}
+
+// Contracts runs of consecutive products of one output tile into device
+// tasks of at most `chain` links.  A run is extended by v only if every
+// predecessor of v other than the previous link comes before the run's head
+// in program order (so the contracted DAG stays acyclic and program order
+// stays topological), and never by the last product of a chain (the one
+// followed by a non-chainable writer of the tile, or by none): that product
+// waits for the most recently finished operand, so it stays a task of its
+// own.  The contracted task sits at the head's position; its predecessors
+// are the union of the members' external predecessors.
+void chain_products(int chain, Plan* p, std::vector<std::vector<int32_t>>& preds) {
+  const int n = (int)p->tasks.size();
+  std::vector<int32_t> next_out(n, -1);
+  {
+    std::unordered_map<int32_t, int32_t> last;
+    for (int v = n - 1; v >= 0; --v) {
+      const int o = p->tasks[v].out;
+      if (o < 0) continue;
+      auto it = last.find(o);
+      next_out[v] = it == last.end() ? -1 : it->second;
+      last[o] = v;
+    }
+  }
+  auto tail = [&](int v) {  // v is the last product of its chain
+    const int w = next_out[v];
+    return w < 0 || !chainable(p->tasks[v], p->tasks[w]);
+  };
+  std::vector<int32_t> head(n, -1);  // contracted task of each member
+  std::vector<std::vector<int32_t>> members(n);
+  for (int u = 0; u < n; ++u) {
+    if (head[u] >= 0) continue;
+    head[u] = u;
+    members[u].push_back(u);
+    if (!column_product(p->tasks[u]) || tail(u)) continue;
+    int last = u;
+    while ((int)members[u].size() < chain) {
+      const int v = next_out[last];
+      if (v < 0 || !chainable(p->tasks[last], p->tasks[v]) || tail(v) || head[v] >= 0) break;
+      bool early = true;
+      for (int q : preds[v])
+        if (q != last && q >= u) { early = false; break; }
+      if (!early) break;
+      head[v] = u;
+      members[u].push_back(v);
+      last = v;
+    }
+  }
+  std::vector<int32_t> pos(n, -1);
+  int m = 0;
+  for (int u = 0; u < n; ++u)
+    if (head[u] == u) pos[u] = m++;
+  std::vector<DevTask> tasks;
+  std::vector<int32_t> step, idx;
+  std::vector<std::vector<int32_t>> np;
+  tasks.reserve(m);
+  step.reserve(m);
+  idx.reserve(m);
+  np.reserve(m);
+  p->links.clear();
+  for (int u = 0; u < n; ++u) {
+    if (head[u] != u) continue;
+    const std::vector<int32_t>& mem = members[u];
+    DevTask d = p->tasks[u];
+    if (mem.size() > 1) {
+      const DevTask& z = p->tasks[mem.back()];
+      d.copy = z.copy;
+      d.kind = (d.kind & ~(F_COPYT << 8)) | (z.kind & (F_COPYT << 8));
+      d.kind |= (int32_t)(mem.size() - 1) << K_LINKS_SHIFT;
+      d.aux = (int32_t)(p->links.size() / 2);
+      for (size_t q = 1; q < mem.size(); ++q) {
+        const DevTask& e = p->tasks[mem[q]];
+        p->links.push_back(e.a | ((e.kind & K_NC_A) ? LINK_NC : 0));
+        p->links.push_back(e.b | ((e.kind & K_NC_B) ? LINK_NC : 0));
+      }
+    }
+    std::vector<int32_t> pr;
+    for (int x : mem)
+      for (int q : preds[x])
+        if (head[q] != u) pr.push_back(pos[head[q]]);
+    std::sort(pr.begin(), pr.end());
+    pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+    tasks.push_back(d);
+    step.push_back(p->step[u]);
+    idx.push_back(p->idx[u]);
+    np.push_back(std::move(pr));
+  }
+  p->tasks.swap(tasks);
+  p->step.swap(step);
+  p->idx.swap(idx);
+  preds.swap(np);
+}
+
 }  // namespace
 
 void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p) {
@@ -293,6 +403,40 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
     }
   }
 
+  // statistics of the paper's DAG: task counts and critical paths (unit
+  // weight per task)
+  {
+    const int n = (int)p->tasks.size();
+    PlanStats& st = p->stats;
+    std::memset(&st, 0, sizeof(st));
+    st.ntasks = n;
+    for (int v = 0; v < n; ++v) {
+      st.nedges += (int64_t)bld.preds[v].size();
+      st.count[task_kind(p->tasks[v].kind)]++;
+    }
+    std::vector<int32_t> lp(n, 0), ls(n, 0);
+    int cp = 0, cps[4] = {0, 0, 0, 0};
+    for (int v = 0; v < n; ++v) {  // program order is a topological order
+      int best = 0, best_s = 0;
+      for (int q : bld.preds[v]) {
+        best = std::max(best, lp[q]);
+        if (p->step[q] == p->step[v]) best_s = std::max(best_s, ls[q]);
+      }
+      lp[v] = best + weight(p->tasks[v].kind);
+      ls[v] = best_s + weight(p->tasks[v].kind);
+      cp = std::max(cp, lp[v]);
+      cps[p->step[v]] = std::max(cps[p->step[v]], ls[v]);
+    }
+    st.cp_step[0] = cps[1];
+    st.cp_step[1] = cps[2];
+    st.cp_step[2] = cps[3];
+    st.cp_unpipelined = cps[1] + cps[2] + cps[3];
+    st.cp_plan = cp;
+    st.cp_pipelined = opt.pipelined ? cp : -1;
+  }
+
+  if (opt.chain > 1) chain_products(opt.chain, p, bld.preds);
+
   const int n = (int)p->tasks.size();
   // CSR successors
   std::vector<int32_t> outdeg(n, 0);
@@ -314,38 +458,13 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
     p->tasks[v].succ_end = ptr[v + 1];
   }
 
-  // statistics: task counts and critical paths (unit weight per task)
-  PlanStats& st = p->stats;
-  std::memset(&st, 0, sizeof(st));
-  st.ntasks = n;
-  st.nedges = ne;
-  for (int v = 0; v < n; ++v) st.count[task_kind(p->tasks[v].kind)]++;
-  std::vector<int32_t> lp(n, 0), ls(n, 0);
-  int cp = 0, cps[4] = {0, 0, 0, 0};
-  for (int v = 0; v < n; ++v) {  // program order is a topological order
-    int best = 0, best_s = 0;
-    for (int q : bld.preds[v]) {
-      best = std::max(best, lp[q]);
-      if (p->step[q] == p->step[v]) best_s = std::max(best_s, ls[q]);
-    }
-    lp[v] = best + weight(p->tasks[v].kind);
-    ls[v] = best_s + weight(p->tasks[v].kind);
-    cp = std::max(cp, lp[v]);
-    cps[p->step[v]] = std::max(cps[p->step[v]], ls[v]);
-  }
-  st.cp_step[0] = cps[1];
-  st.cp_step[1] = cps[2];
-  st.cp_step[2] = cps[3];
-  st.cp_unpipelined = cps[1] + cps[2] + cps[3];
-  st.cp_plan = cp;
-  st.cp_pipelined = opt.pipelined ? cp : -1;
-
   // dispatch order: list-scheduling simulation with `workers` workers,
   // priority = weighted bottom level (longest remaining path), ties broken by
   // program order
   std::vector<double> dur(n), bl(n, 0.0);
   for (int v = 0; v < n; ++v)
-    dur[v] = cost ? cost[task_kind(p->tasks[v].kind)] : (double)weight(p->tasks[v].kind);
+    dur[v] = (cost ? cost[task_kind(p->tasks[v].kind)] : (double)weight(p->tasks[v].kind)) *
+             (1 + task_links(p->tasks[v].kind));
   for (int v = n - 1; v >= 0; --v) {
     double m = 0.0;
     for (int e = ptr[v]; e < ptr[v + 1]; ++e) m = std::max(m, bl[p->succ[e]]);

@@ -21,6 +21,13 @@
 //                  and the right multiplication by the inverted diagonal tile;
 //                  the default is the LAPACK 3.2.1 order (right solve with the
 //                  factor's diagonal tile, TRTRI(j) after column j).
+//   chain       -- device task granularity (not a variant of the paper): up to
+//                  `chain` consecutive products of one output tile's update
+//                  chain run as one device task that keeps the tile in
+//                  registers between them.  The products, their order and
+//                  their operands are unchanged, so results are bit-identical
+//                  to chain = 1 (one device task per task of the paper's
+//                  stream); the statistics always describe the paper's DAG.
 #pragma once
 #include <cstdint>
 #include <vector>
@@ -52,7 +59,9 @@ struct PlanOptions {
   int loop_order = 0;   // 0 = UDU, 1 = UUU
   int pipelined = 1;
   int trtri_first = 0;
+  int chain = 1;        // most products per device task (1 <= chain <= MAX_CHAIN)
 };
+constexpr int MAX_CHAIN = 16;
 
 // Operation flags of a tile product, C (+)= +-op(A) op(B) (bits 8-15 of
 // DevTask::kind).
@@ -82,6 +91,15 @@ constexpr int32_t K_POTRF_FACTOR_DEAD = 1 << 16;
 // so a tile read in an earlier version is never read through the cache.)
 constexpr int32_t K_NC_A = 1 << 17;
 constexpr int32_t K_NC_B = 1 << 18;
+// Bits 20-23 of DevTask::kind on a tile product: number of further links of
+// a chained task.  Link p (p = 1..count) multiplies the operand tiles
+// links[2 (aux + p - 1)] and links[2 (aux + p - 1) + 1] (the same op and sign
+// as the first link, always accumulating); LINK_NC marks an operand that may
+// be read through the L2 cache (the rule of K_NC_A / K_NC_B).
+constexpr int K_LINKS_SHIFT = 20;
+constexpr int32_t K_LINKS_MASK = 0xf << K_LINKS_SHIFT;
+constexpr int32_t LINK_NC = 1 << 30;
+inline int task_links(int32_t k) { return (k & K_LINKS_MASK) >> K_LINKS_SHIFT; }
 inline int32_t task_kind(int32_t k) { return k & 0xff; }
 inline int32_t task_flags(int32_t k) { return (k >> 8) & 0xff; }
 
@@ -101,7 +119,8 @@ struct DevTask {
   int32_t a;     // first operand tile (or -1)
   int32_t b;     // second operand tile (or -1)
   int32_t copy;  // renaming destination that receives the same result (or -1)
-  int32_t aux;   // POTRF: D_j (D_j^T follows t tiles later) (or -1)
+  int32_t aux;   // POTRF: D_j (D_j^T follows t tiles later); chained
+                 // product: index of its first further link; else -1
   int32_t succ_begin;
   int32_t succ_end;
 };
@@ -125,7 +144,8 @@ struct Plan {
   std::vector<int32_t> succ;       // CSR successor lists (by task)
   std::vector<int32_t> indeg;      // initial in-degree per task
   std::vector<int32_t> order;      // device dispatch order (topological)
-  PlanStats stats{};
+  std::vector<int32_t> links;      // further links of chained tasks (pairs)
+  PlanStats stats{};               // of the paper's DAG (before chaining)
 };
 
 // Builds the plan.  `workers` and `cost` drive the list-scheduling simulation

@@ -189,13 +189,192 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
   }
 }
 
+// ---------------------------------------------------------------------------
+// Chained tile product: C (+)= +-(A_0 B_0^T + A_1 B_1^T + ... + A_L B_L^T),
+// the consecutive products of one output tile's update chain run as one task
+// (op(A) = A, op(B) = B^T for every link; flags as in tile_mma).  Link 0 is
+// (A, B); link p >= 1 reads the tiles named by links[2(p-1)] and
+// links[2(p-1)+1] (LINK_NC: through the L2 cache).  The accumulator starts
+// from +-C and takes the links' products in order, k-panel by k-panel, so
+// every rounding is that of the separate tasks (whose stores and reloads of
+// the intermediate tile are exact); C is read and written once.  The
+// k-panels of all links form one double-buffered stream through LDS: the
+// first panel of link p+1 is loaded while the last panel of link p is
+// multiplied.  Two rolled loops (links, then panels) keep the accumulator in
+// the matrix-core registers; out of line, so that the single product's
+// register allocation is left as it is.
+// ---------------------------------------------------------------------------
+__device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const double* A,
+                                                         const double* B, double* copy,
+                                                         double* smem, bool nca, bool ncb,
+                                                         const int32_t* links, int nlink,
+                                                         double* pool) {
+  f = uniform_int(f);
+  C = uniform_ptr(C);
+  A = uniform_ptr(A);
+  B = uniform_ptr(B);
+  copy = uniform_ptr(copy);
+  nca = uniform_int(nca) != 0;
+  ncb = uniform_int(ncb) != 0;
+  links = uniform_ptr(links);
+  nlink = uniform_int(nlink);
+  pool = uniform_ptr(pool);
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int wm = w & 1, wn = w >> 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  const bool neg = (f & F_NEG) != 0, copy_t = (f & F_COPYT) != 0;
+  const bool accum = (f & F_ACC) != 0;
+  const bool active = !((f & F_LOWER) && wm == 0 && wn == 1);
+  const rsrc_t rC = tile_rsrc(C);
+
+  d4 acc[4][4];
+  if (accum) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int off = (wm * 64 + i * 16 + lr) + NB * (wn * 64 + j * 16 + lk);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[i][j][r] = ld1(rC, off + NB * 4 * r);
+      }
+    if (neg) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = -acc[i][j];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  }
+
+  d2 ra[PAIRS], rb[PAIRS];
+  auto load = [&](rsrc_t r, bool nc, int k0, d2 (&dst)[PAIRS]) {
+    if (nc) panel_load<0>(r, k0, true, dst);
+    else panel_load<CPOL_AGENT>(r, k0, true, dst);
+  };
+  // operands of link p (wave-uniform)
+  auto link = [&](int p, rsrc_t& ra_, rsrc_t& rb_, bool& na_, bool& nb_) {
+    if (p == 0) {
+      ra_ = tile_rsrc(A);
+      rb_ = tile_rsrc(B);
+      na_ = nca;
+      nb_ = ncb;
+    } else {
+      const int va = __builtin_amdgcn_readfirstlane(links[2 * (p - 1)]);
+      const int vb = __builtin_amdgcn_readfirstlane(links[2 * (p - 1) + 1]);
+      ra_ = tile_rsrc(tile_ptr(pool, va & ~LINK_NC));
+      rb_ = tile_rsrc(tile_ptr(pool, vb & ~LINK_NC));
+      na_ = (va & LINK_NC) != 0;
+      nb_ = (vb & LINK_NC) != 0;
+    }
+  };
+  rsrc_t cA, cB;
+  bool cna, cnb;
+  link(0, cA, cB, cna, cnb);
+  load(cA, cna, 0, ra);
+  load(cB, cnb, 0, rb);
+  panel_store(smem, 0, true, false, ra);
+  panel_store(smem + PANEL, 0, true, false, rb);
+  __syncthreads();
+
+#pragma unroll 1
+  for (int p = 0; p <= nlink; ++p) {
+    const bool last = p == nlink;
+    rsrc_t nA = cA, nB = cB;
+    bool nna = cna, nnb = cnb;
+    if (!last) link(p + 1, nA, nB, nna, nnb);
+#pragma unroll 1
+    for (int c = 0; c < NCH; ++c) {
+      const double* As = smem + (c & 1) * 2 * PANEL;
+      const double* Bs = As + PANEL;
+      const bool wrap = c + 1 == NCH;
+      const bool more = !wrap || !last;
+      if (more) {
+        const int k0 = wrap ? 0 : (c + 1) * KC;
+        load(wrap ? nA : cA, wrap ? nna : cna, k0, ra);
+        load(wrap ? nB : cB, wrap ? nnb : cnb, k0, rb);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int ks = 0; ks < KC / 4; ++ks) {
+        const double* Ar = As + (4 * ks + lk) * LDS_STRIDE + wm * 64 + lr;
+        const double* Br = Bs + (4 * ks + lk) * LDS_STRIDE + wn * 64 + lr;
+        double a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          a[i] = Ar[16 * i];
+          b[i] = Br[16 * i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) {
+        double* An = smem + ((c + 1) & 1) * 2 * PANEL;
+        panel_store(An, 0, true, false, ra);
+        panel_store(An + PANEL, 0, true, false, rb);
+      }
+      __syncthreads();
+    }
+    cA = nA;
+    cB = nB;
+    cna = nna;
+    cnb = nnb;
+  }
+
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int off = (wm * 64 + i * 16 + lr) + NB * (wn * 64 + j * 16 + lk);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) st1(rC, off + NB * 4 * r, neg ? -acc[i][j][r] : acc[i][j][r]);
+      }
+  }
+  if (!copy) return;  // uniform
+  constexpr int RLD = NB + 1;
+  double* R = smem;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = wm * 64 + i * 16 + lr, col0 = wn * 64 + j * 16 + lk;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) R[(col0 + 4 * r) + RLD * row] = neg ? -acc[i][j][r] : acc[i][j][r];
+    }
+  __syncthreads();
+  const rsrc_t rD = tile_rsrc(copy);
+#pragma unroll 4
+  for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
+    const int e = 2 * (threadIdx.x + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
+    d2 v;
+    if (copy_t) {
+      v.x = R[rr + RLD * cc];
+      v.y = R[rr + 1 + RLD * cc];
+    } else {
+      v.x = R[cc + RLD * rr];
+      v.y = R[cc + RLD * (rr + 1)];
+    }
+    st2(rD, e, v);
+  }
+}
+
 // The general product (transposed or triangular operands) serves only the
 // in-place plan; it is kept out of line so that its registers do not weigh
 // on the inlined fast product.
 __device__ __attribute__((noinline)) void tile_mma_general(int f, double* C, const double* A,
                                                            const double* B, double* copy,
                                                            double* smem) {
-  tile_mma<false>(f, C, A, B, copy, smem);
+  tile_mma<false>(uniform_int(f), uniform_ptr(C), uniform_ptr(A), uniform_ptr(B),
+                  uniform_ptr(copy), smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -409,6 +588,11 @@ __device__ __forceinline__ void inverse_lds(double* T, const double* XD, double*
 __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, double* Lout,
                                                          double* LcopyT, double* Xout,
                                                          double* XoutT, double* smem) {
+  Ain = uniform_ptr(Ain);
+  Lout = uniform_ptr(Lout);
+  LcopyT = uniform_ptr(LcopyT);
+  Xout = uniform_ptr(Xout);
+  XoutT = uniform_ptr(XoutT);
   constexpr int LD = POTRF_LD;
   double* T = smem;                    // [NB * LD] the tile, column-major
   double* XD = smem + NB * LD;         // [8][256] inverses of the diagonal blocks
@@ -508,8 +692,15 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
     case K_TRMM3: case K_LAUUM: case K_GEMM3: case K_SYRK3:
       // tile products; the planner chose operands and flags (Algorithm 1's
       // operation on the renamed or in-place tiles)
-      if ((f & (F_TA | F_MA | F_MB)) == 0 && (f & F_TB))
-        tile_mma<true>(f, out, a, b, cp, smem, (t.kind & K_NC_A) != 0, (t.kind & K_NC_B) != 0);
+      if ((f & (F_TA | F_MA | F_MB)) == 0 && (f & F_TB)) {
+        const int nl = (t.kind & K_LINKS_MASK) >> K_LINKS_SHIFT;
+        if (nl)
+          tile_mma_chain(f, out, a, b, cp, smem, (t.kind & K_NC_A) != 0, (t.kind & K_NC_B) != 0,
+                         g.links + 2 * t.aux, nl, P);
+        else
+          tile_mma<true>(f, out, a, b, cp, smem, (t.kind & K_NC_A) != 0,
+                         (t.kind & K_NC_B) != 0);
+      }
       else
         tile_mma_general(f, out, a, b, cp, smem);
       break;

@@ -117,7 +117,9 @@ def test_fill_upper_and_leading_dimension():
 
 @pytest.mark.parametrize("opts", [dict(pipelined=0), dict(workers=1), dict(workers=7),
                                   dict(workers=64), dict(renamed=0), dict(trtri_first=1),
-                                  dict(renamed=0, trtri_first=1)])
+                                  dict(renamed=0, trtri_first=1), dict(chain=1), dict(chain=2),
+                                  dict(chain=16), dict(chain=16, workers=3),
+                                  dict(renamed=0, chain=1)])
 def test_variants_bit_identical(opts):
     n = 700
     a = inputs.wishart_shift(n, seed=10).numpy()

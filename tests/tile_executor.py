@@ -11,6 +11,7 @@ import numpy as np
 
 NOP, SYRK1, POTRF, GEMM1, TRSM1, TRTRI, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEMM3, SYRK3 = range(13)
 POTRF_FACTOR_DEAD = 1 << 16
+LINKS_SHIFT, LINK_NC = 20, 1 << 30   # chained products: further links (see plan.hpp)
 PRODUCTS = {SYRK1, GEMM1, TRSM1, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEMM3, SYRK3}
 F_TA, F_TB, F_MA, F_MB, F_LOWER, F_NEG, F_ACC, F_COPYT = 1, 2, 4, 8, 16, 32, 64, 128
 
@@ -43,26 +44,34 @@ def from_pool(pool, t, nb, n):
     return low + np.tril(low, -1).T
 
 
-def run_task(pool, task, t):
+def run_task(pool, task, t, links=None):
     """One task with the device semantics: a tile product C (+)= +-op(A) op(B)
-    driven by the flags, the diagonal factorization, or the TRTRI copy."""
+    driven by the flags (a chained product applies its further links in
+    order, each accumulating, and copies the final tile), the diagonal
+    factorization, or the TRTRI copy."""
     code, out, a, b, cp, aux = (int(x) for x in task[:6])
     kind, f = code & 0xFF, (code >> 8) & 0xFF
     factor_dead = bool(code & POTRF_FACTOR_DEAD)
     if kind == NOP:
         return
     if kind in PRODUCTS:
-        A = pool[a].T if f & F_TA else pool[a]
-        B = pool[b].T if f & F_TB else pool[b]
-        if f & F_MA:
-            A = np.triu(A) if f & F_TA else np.tril(A)
-        if f & F_MB:
-            B = np.triu(B) if f & F_TB else np.tril(B)
-        p = A @ B
-        if f & F_NEG:
-            p = -p
-        r = pool[out] + p if f & F_ACC else p
-        pool[out] = r
+        ops = [(a, b)]
+        for q in range((code >> LINKS_SHIFT) & 0xF):
+            la, lb = (int(x) & ~LINK_NC for x in links[aux + q])
+            ops.append((la, lb))
+        for q, (oa, ob) in enumerate(ops):
+            fq = f if q == 0 else f | F_ACC
+            A = pool[oa].T if fq & F_TA else pool[oa]
+            B = pool[ob].T if fq & F_TB else pool[ob]
+            if fq & F_MA:
+                A = np.triu(A) if fq & F_TA else np.tril(A)
+            if fq & F_MB:
+                B = np.triu(B) if fq & F_TB else np.tril(B)
+            p = A @ B
+            if fq & F_NEG:
+                p = -p
+            pool[out] = pool[out] + p if fq & F_ACC else p
+        r = pool[out]
         if cp >= 0:
             pool[cp] = r.T if f & F_COPYT else r
     elif kind == POTRF:
@@ -111,5 +120,5 @@ def execute(plan, a, nb, order=None):
     pool = to_pool(a, t, nb)
     tasks = plan["tasks"]
     for v in (range(len(tasks)) if order is None else order):
-        run_task(pool, tasks[v], t)
+        run_task(pool, tasks[v], t, plan.get("links"))
     return from_pool(pool, t, nb, a.shape[0])
