@@ -27,7 +27,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6       # MI355X dense FP64 matrix peak
-KERNEL_SRC = os.path.join(ROOT, "paper_1002_4057_amd", "csrc", "device.hip")
+# sources that determine the scheduler kernel and the plan it runs: committed
+# traffic counters are used only while these are unchanged
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1002_4057_amd", "csrc", f) for f in
+               ("device.hip", "device.hpp", "tile_tasks.hpp", "mfma_tile.hpp", "sched_loop.hpp",
+                "plan.hpp", "plan.cpp", "api.cpp")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sched_kernel_n8192.json")
 
 
@@ -36,7 +40,10 @@ def log(*a):
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_per_launch():
