@@ -24,21 +24,25 @@ using namespace spdinv;
 namespace {
 
 // Relative durations of the task kinds, used only to order the dispatch list
-// (list-scheduling simulation); a 128^3 tile product is the unit.
-const double kCost[K_COUNT] = {
-    0.0,   // NOP
-    1.0,   // SYRK1
-    2.0,   // POTRF (factor + inverse of the factor tile)
-    1.0,   // GEMM1
-    1.0,   // TRSM1
-    0.1,   // TRTRI (copy)
-    1.0,   // TRMM2L
-    1.0,   // GEMM2
-    1.0,   // TRSM2R
-    1.0,   // TRMM3
-    1.0,   // LAUUM
-    1.0,   // GEMM3
-    1.0,   // SYRK3
+// (list-scheduling simulation); a single 128^3 tile product task is the unit.
+// Measured per-task times at n = 8192 on MI355X: product 25.5 us, POTRF
+// (factor + inverse of the factor tile) 63 us, TRTRI copy 8.5 us, each further
+// link of a chained product 19.5 us (the last entry).
+const double kCost[K_COUNT + 1] = {
+    0.0,    // NOP
+    1.0,    // SYRK1
+    2.47,   // POTRF
+    1.0,    // GEMM1
+    0.96,   // TRSM1
+    0.33,   // TRTRI (copy)
+    1.0,    // TRMM2L
+    1.0,    // GEMM2
+    0.96,   // TRSM2R
+    1.0,    // TRMM3
+    1.0,    // LAUUM
+    1.0,    // GEMM3
+    1.0,    // SYRK3
+    0.76,   // each further link of a chained product
 };
 
 // Products per device task of the FP64 scheduler when opts.chain is 0.

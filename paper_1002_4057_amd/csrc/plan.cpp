@@ -212,6 +212,71 @@ struct Builder {
 
 inline int weight(int kind) { return task_kind(kind) == K_NOP ? 0 : 1; }
 
+// List-scheduling simulation of a DAG given by predecessor lists in a
+// topological program order: `workers` identical workers, priority =
+// weighted bottom level (longest remaining path), ties broken by program
+// order.  Returns the dispatch order and, if asked, each task's simulated
+// start time.
+void list_schedule(const std::vector<std::vector<int32_t>>& preds, const std::vector<double>& dur,
+                   int workers, std::vector<int32_t>* order, std::vector<double>* start) {
+  const int n = (int)preds.size();
+  std::vector<int32_t> ptr(n + 1, 0), deg(n, 0);
+  for (int v = 0; v < n; ++v)
+    for (int q : preds[v]) ptr[q + 1]++;
+  for (int v = 0; v < n; ++v) ptr[v + 1] += ptr[v];
+  std::vector<int32_t> succ(ptr[n]);
+  {
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int v = 0; v < n; ++v) {
+      deg[v] = (int32_t)preds[v].size();
+      for (int q : preds[v]) succ[fill[q]++] = v;
+    }
+  }
+  std::vector<double> bl(n, 0.0);
+  for (int v = n - 1; v >= 0; --v) {
+    double m = 0.0;
+    for (int e = ptr[v]; e < ptr[v + 1]; ++e) m = std::max(m, bl[succ[e]]);
+    bl[v] = dur[v] + m;
+  }
+  auto cmp = [&](int x, int y) {  // max-heap on bl, then min program index
+    if (bl[x] != bl[y]) return bl[x] < bl[y];
+    return x > y;
+  };
+  std::priority_queue<int, std::vector<int>, decltype(cmp)> ready(cmp);
+  using Ev = std::pair<double, int>;
+  std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> running;
+  for (int v = 0; v < n; ++v)
+    if (deg[v] == 0) ready.push(v);
+  if (order) {
+    order->clear();
+    order->reserve(n);
+  }
+  if (start) start->assign(n, 0.0);
+  double now = 0.0;
+  int busy = 0, done = 0;
+  const int P = std::max(1, workers);
+  while (done < n) {
+    while (busy < P && !ready.empty()) {
+      const int v = ready.top();
+      ready.pop();
+      if (order) order->push_back(v);
+      if (start) (*start)[v] = now;
+      running.push({now + dur[v], v});
+      ++busy;
+    }
+    if (running.empty()) break;  // cannot happen for an acyclic plan
+    now = running.top().first;
+    while (!running.empty() && running.top().first <= now) {
+      const int v = running.top().second;
+      running.pop();
+      --busy;
+      ++done;
+      for (int e = ptr[v]; e < ptr[v + 1]; ++e)
+        if (--deg[succ[e]] == 0) ready.push(succ[e]);
+    }
+  }
+}
+
 // A product that reads both operands along stored columns (op(A) = A,
 // op(B) = B^T, no masks): the form the chained device product executes.
 bool column_product(const DevTask& d) {
@@ -232,15 +297,25 @@ bool chainable(const DevTask& u, const DevTask& v) {
 }
 
 // Contracts runs of consecutive products of one output tile into device
-// tasks of at most `chain` links.  A run is extended by v only if every
-// predecessor of v other than the previous link comes before the run's head
-// in program order (so the contracted DAG stays acyclic and program order
-// stays topological), and never by the last product of a chain (the one
-// followed by a non-chainable writer of the tile, or by none): that product
-// waits for the most recently finished operand, so it stays a task of its
-// own.  The contracted task sits at the head's position; its predecessors
-// are the union of the members' external predecessors.
-void chain_products(int chain, Plan* p, std::vector<std::vector<int32_t>>& preds) {
+// tasks of at most `chain` links.  A run is extended by v only if
+//  - every predecessor of v other than the previous link comes before the
+//    run's head in program order (so the contracted DAG stays acyclic and
+//    program order stays topological);
+//  - v is not the last product of its chain (the one followed by a
+//    non-chainable writer of the tile, or by none): that product waits for
+//    the most recently finished operand, so it stays a task of its own;
+//  - in the simulated schedule of the uncontracted DAG (start times `st`,
+//    durations `dur`, `link` per further link), v's other predecessors have
+//    finished by the time the contracted task would reach v, give or take
+//    `slack`, so contraction delays the head by at most that much.  (On
+//    MI355X at n = 8192, a slack of 5 single-product durations made chain
+//    lengths 6 to 12 equally fast; without the rule, lengths above 8 held
+//    early tasks back and lost up to 20 %.)
+// The contracted task sits at the head's position; its predecessors are the
+// union of the members' external predecessors.
+void chain_products(int chain, Plan* p, std::vector<std::vector<int32_t>>& preds,
+                    const std::vector<double>& st, const std::vector<double>& dur, double link,
+                    double slack) {
   const int n = (int)p->tasks.size();
   std::vector<int32_t> next_out(n, -1);
   {
@@ -268,9 +343,11 @@ void chain_products(int chain, Plan* p, std::vector<std::vector<int32_t>>& preds
     while ((int)members[u].size() < chain) {
       const int v = next_out[last];
       if (v < 0 || !chainable(p->tasks[last], p->tasks[v]) || tail(v) || head[v] >= 0) break;
+      // the contracted task reaches link m = members.size() at this time
+      const double reach = st[u] + dur[u] + link * (double)(members[u].size() - 1);
       bool early = true;
       for (int q : preds[v])
-        if (q != last && q >= u) { early = false; break; }
+        if (q != last && (q >= u || st[q] + dur[q] > reach + slack)) { early = false; break; }
       if (!early) break;
       head[v] = u;
       members[u].push_back(v);
@@ -435,7 +512,15 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
     st.cp_pipelined = opt.pipelined ? cp : -1;
   }
 
-  if (opt.chain > 1) chain_products(opt.chain, p, bld.preds);
+  if (opt.chain > 1) {
+    const int n0 = (int)p->tasks.size();
+    std::vector<double> dur0(n0), st0;
+    for (int v = 0; v < n0; ++v)
+      dur0[v] = cost ? cost[task_kind(p->tasks[v].kind)] : (double)weight(p->tasks[v].kind);
+    list_schedule(bld.preds, dur0, workers, nullptr, &st0);
+    // slack: 5 single-product durations (the unit of `cost`)
+    chain_products(opt.chain, p, bld.preds, st0, dur0, cost ? cost[K_COUNT] : 1.0, 5.0);
+  }
 
   const int n = (int)p->tasks.size();
   // CSR successors
@@ -458,51 +543,12 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
     p->tasks[v].succ_end = ptr[v + 1];
   }
 
-  // dispatch order: list-scheduling simulation with `workers` workers,
-  // priority = weighted bottom level (longest remaining path), ties broken by
-  // program order
-  std::vector<double> dur(n), bl(n, 0.0);
+  // dispatch order: list-scheduling simulation of the executed DAG
+  std::vector<double> dur(n);
   for (int v = 0; v < n; ++v)
-    dur[v] = (cost ? cost[task_kind(p->tasks[v].kind)] : (double)weight(p->tasks[v].kind)) *
-             (1 + task_links(p->tasks[v].kind));
-  for (int v = n - 1; v >= 0; --v) {
-    double m = 0.0;
-    for (int e = ptr[v]; e < ptr[v + 1]; ++e) m = std::max(m, bl[p->succ[e]]);
-    bl[v] = dur[v] + m;
-  }
-  auto cmp = [&](int x, int y) {  // max-heap on bl, then min program index
-    if (bl[x] != bl[y]) return bl[x] < bl[y];
-    return x > y;
-  };
-  std::priority_queue<int, std::vector<int>, decltype(cmp)> ready(cmp);
-  using Ev = std::pair<double, int>;
-  std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> running;
-  std::vector<int32_t> deg(p->indeg);
-  for (int v = 0; v < n; ++v)
-    if (deg[v] == 0) ready.push(v);
-  p->order.clear();
-  p->order.reserve(n);
-  double now = 0.0;
-  int busy = 0;
-  const int P = std::max(1, workers);
-  while ((int)p->order.size() < n || !running.empty()) {
-    while (busy < P && !ready.empty()) {
-      const int v = ready.top();
-      ready.pop();
-      p->order.push_back(v);
-      running.push({now + dur[v], v});
-      ++busy;
-    }
-    if (running.empty()) break;  // cannot happen for an acyclic plan
-    now = running.top().first;
-    while (!running.empty() && running.top().first <= now) {
-      const int v = running.top().second;
-      running.pop();
-      --busy;
-      for (int e = ptr[v]; e < ptr[v + 1]; ++e)
-        if (--deg[p->succ[e]] == 0) ready.push(p->succ[e]);
-    }
-  }
+    dur[v] = cost ? cost[task_kind(p->tasks[v].kind)] + cost[K_COUNT] * task_links(p->tasks[v].kind)
+                  : (double)weight(p->tasks[v].kind) * (1 + task_links(p->tasks[v].kind));
+  list_schedule(bld.preds, dur, workers, &p->order, nullptr);
 }
 
 }  // namespace spdinv

@@ -149,7 +149,9 @@ struct Plan {
 };
 
 // Builds the plan.  `workers` and `cost` drive the list-scheduling simulation
-// that orders the dispatch list (cost[kind] = estimated duration, any unit).
+// that orders the dispatch list (cost[kind] = estimated duration of a task of
+// that kind, any unit; cost[K_COUNT] = duration of each further link of a
+// chained product; null = unit durations).
 void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* out);
 
 // Tile pool size in tiles for t tiles per side.

@@ -140,7 +140,21 @@ def test_last_product_before_closing_task_runs_alone(t):
         nxt = flat[lst[j + 1]]
         assert nxt[0] == "prod" and nxt[4] & F_ACC and nxt[2] != out and nxt[3] != out
     assert seq  # non-empty
-    assert len(ch["tasks"]) < len(base["tasks"])
+    assert len(ch["tasks"]) <= len(base["tasks"])
+
+
+@pytest.mark.parametrize("t,workers", [(16, 16), (32, 64), (64, 256)])
+def test_chains_form_where_operands_are_ready_early(t, workers):
+    """Links join a chain only when the simulated schedule has their operands
+    ready (give or take the slack) by the time the chain reaches them; at
+    realistic sizes most of the step-3 products (operands made in earlier
+    steps) still chain."""
+    base = spd.plan_export(t, workers=workers, chain=1)
+    ch = spd.plan_export(t, workers=workers, chain=8)
+    assert len(ch["tasks"]) < 0.55 * len(base["tasks"])
+    step3 = ch["step"] == 3
+    nl = (ch["tasks"][:, 0] >> LINKS_SHIFT) & 0xF
+    assert nl[step3].sum() > 0.5 * step3.sum()
 
 
 def test_chain_option_range_checked():
