@@ -87,7 +87,7 @@ typedef struct {
                       6 for MIXED_FP32, 8 for MIXED_BF16)                     */
   double refine_tol; /* mixed modes: stop once ||I - A X||_F / ||A||_F <= refine_tol
                         (0 = library default, 1e-13)                            */
-  int chain;       /* FP64 scheduler: most consecutive products of one output
+  int chain;       /* FP64 and batched forms: most consecutive products of one output
                       tile's update chain that run as one device task, the tile
                       staying in registers between them (0 = library default,
                       8; 1 = one device task per task of the paper's stream;

@@ -273,6 +273,7 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   a.ctrl = ctrl;
   a.pool = pool;
   a.links = dp->d_links;
+  a.coherent_only = 0;
   a.trace = trace;
   a.ntask = ntask;
   a.tiles_T = t * (t + 1) / 2;
@@ -393,9 +394,10 @@ int batched_spd_inverse(int batch, const int* h_n, const int* d_n, double* const
   for (int t = 2; t <= L.tmax; ++t) {
     hipError_t err = hipSuccess;
     // program-order execution by one workgroup: the plan's task list as built
-    DevPlan* dp = get_plan(device, t, o, 1, 1, &err);
+    DevPlan* dp = get_plan(device, t, o, 1, chain_for(o), &err);
     if (!dp) return SPDINV_ERR_HIP;
     b.plan[t] = dp->d_tasks;
+    b.plan_links[t] = dp->d_links;
     b.plan_ntask[t] = (int)dp->host.tasks.size();
   }
   char* w = (char*)work;
@@ -527,6 +529,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
   a.ctrl = ctrl;
   a.pool = reinterpret_cast<double*>(pool);
   a.links = nullptr;
+  a.coherent_only = 0;
   a.trace = nullptr;
   a.ntask = ntask;
   a.tiles_T = t * (t + 1) / 2;

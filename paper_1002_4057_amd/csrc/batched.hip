@@ -97,7 +97,8 @@ __device__ int small_inverse(double* A, int lda, int n, int fill_upper, double* 
 // private pool `pool` (pool_tiles(t) tiles) with the control words `ctrl`.
 // Returns 0 or INFO.
 __device__ int tile_sequential(double* A, int lda, int n, int fill_upper, const DevTask* tasks,
-                               int ntask, double* pool, int32_t* ctrl, double* smem) {
+                               const int32_t* links, int ntask, double* pool, int32_t* ctrl,
+                               double* smem) {
   const int t = (n + NB - 1) / NB, T = t * (t + 1) / 2;
   const int tid = threadIdx.x;
   // copy-in with identity padding (agent-coherent stores, like every access
@@ -132,11 +133,12 @@ __device__ int tile_sequential(double* A, int lda, int n, int fill_upper, const 
   g.pool = pool;
   g.ctrl = ctrl;
   g.info_base = 0;
+  g.links = links;
+  // the pool is reused by the next matrix: keep every read device-coherent
+  g.coherent_only = 1;
   __shared__ int s_info;
   for (int k = 0; k < ntask; ++k) {
-    DevTask task = tasks[k];
-    // the pool is reused by the next matrix: keep every read device-coherent
-    task.kind &= ~(K_NC_A | K_NC_B);
+    const DevTask task = tasks[k];
     run_task(task, g, smem, T, t);
     stores_complete();
     __syncthreads();
@@ -208,7 +210,8 @@ __global__ __launch_bounds__(NTHREADS) void batched_kernel(BatchArgs b) {
     } else if (n <= NB) {
       info = small_inverse(A, lda, n, b.fill_upper, smem);
     } else {
-      info = tile_sequential(A, lda, n, b.fill_upper, b.plan[t], b.plan_ntask[t], pool, ctrl, smem);
+      info = tile_sequential(A, lda, n, b.fill_upper, b.plan[t], b.plan_links[t], b.plan_ntask[t],
+                             pool, ctrl, smem);
     }
     if (threadIdx.x == 0 && b.info) b.info[m] = info;
     __syncthreads();  // LDS (and s_m) are reused by the next matrix

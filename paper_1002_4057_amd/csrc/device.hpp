@@ -30,6 +30,7 @@ struct SchedArgs {
   int32_t* ctrl;       // Ctrl words
   double* pool;        // tile pool
   const int32_t* links;  // further links of chained products (or nullptr)
+  int coherent_only;   // 1: ignore the planner's L2-cacheable read marks
   long long* trace;    // 4 per task, or nullptr
   int ntask;
   int tiles_T;         // lower tiles per copy, T = t(t+1)/2 (pool layout)
@@ -55,6 +56,7 @@ struct BatchArgs {
   int tmax;                // largest tile count the pools are sized for
   int fill_upper;
   const DevTask* plan[MAX_BATCH_T + 1];  // program-order plan per tile count
+  const int32_t* plan_links[MAX_BATCH_T + 1];  // its chained-product links
   int plan_ntask[MAX_BATCH_T + 1];
 };
 

@@ -194,7 +194,7 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
 // the consecutive products of one output tile's update chain run as one task
 // (op(A) = A, op(B) = B^T for every link; flags as in tile_mma).  Link 0 is
 // (A, B); link p >= 1 reads the tiles named by links[2(p-1)] and
-// links[2(p-1)+1] (LINK_NC: through the L2 cache).  The accumulator starts
+// links[2(p-1)+1] (LINK_NC: through the L2 cache, unless coherent_only).  The accumulator starts
 // from +-C and takes the links' products in order, k-panel by k-panel, so
 // every rounding is that of the separate tasks (whose stores and reloads of
 // the intermediate tile are exact); C is read and written once.  The
@@ -208,7 +208,7 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
                                                          const double* B, double* copy,
                                                          double* smem, bool nca, bool ncb,
                                                          const int32_t* links, int nlink,
-                                                         double* pool) {
+                                                         double* pool, bool coherent_only) {
   f = uniform_int(f);
   C = uniform_ptr(C);
   A = uniform_ptr(A);
@@ -218,6 +218,7 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
   ncb = uniform_int(ncb) != 0;
   links = uniform_ptr(links);
   nlink = uniform_int(nlink);
+  coherent_only = uniform_int(coherent_only) != 0;
   pool = uniform_ptr(pool);
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -268,8 +269,8 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
       const int vb = __builtin_amdgcn_readfirstlane(links[2 * (p - 1) + 1]);
       ra_ = tile_rsrc(tile_ptr(pool, va & ~LINK_NC));
       rb_ = tile_rsrc(tile_ptr(pool, vb & ~LINK_NC));
-      na_ = (va & LINK_NC) != 0;
-      nb_ = (vb & LINK_NC) != 0;
+      na_ = !coherent_only && (va & LINK_NC) != 0;
+      nb_ = !coherent_only && (vb & LINK_NC) != 0;
     }
   };
   rsrc_t cA, cB;
@@ -694,12 +695,13 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
       // operation on the renamed or in-place tiles)
       if ((f & (F_TA | F_MA | F_MB)) == 0 && (f & F_TB)) {
         const int nl = (t.kind & K_LINKS_MASK) >> K_LINKS_SHIFT;
+        const bool nca = !g.coherent_only && (t.kind & K_NC_A) != 0;
+        const bool ncb = !g.coherent_only && (t.kind & K_NC_B) != 0;
         if (nl)
-          tile_mma_chain(f, out, a, b, cp, smem, (t.kind & K_NC_A) != 0, (t.kind & K_NC_B) != 0,
-                         g.links + 2 * t.aux, nl, P);
+          tile_mma_chain(f, out, a, b, cp, smem, nca, ncb, g.links + 2 * t.aux, nl, P,
+                         g.coherent_only != 0);
         else
-          tile_mma<true>(f, out, a, b, cp, smem, (t.kind & K_NC_A) != 0,
-                         (t.kind & K_NC_B) != 0);
+          tile_mma<true>(f, out, a, b, cp, smem, nca, ncb);
       }
       else
         tile_mma_general(f, out, a, b, cp, smem);
