@@ -241,7 +241,7 @@ int spdinv_plan_stats_get(int t, const spdinv_opts* opts, spdinv_plan_stats* out
  * indices (i<<20 | j<<10 | k) and the device dispatch order.  With
  * opts->chain != 1 a product task may carry further links: bits 20-23 of
  * kind count them, aux indexes the first in `links` (int32 pairs: operand
- * tiles a, b, bit 30 set where the operand is read through the L2 cache).
+ * tiles a, b).
  * Pass NULL buffers to query the sizes (ntasks, nsucc, nlinks).  `workers`
  * sizes the list-scheduling simulation that produces the order.
  */

@@ -375,11 +375,13 @@ void chain_products(int chain, Plan* p, std::vector<std::vector<int32_t>>& preds
       d.copy = z.copy;
       d.kind = (d.kind & ~(F_COPYT << 8)) | (z.kind & (F_COPYT << 8));
       d.kind |= (int32_t)(mem.size() - 1) << K_LINKS_SHIFT;
+      // the chained product reads every operand device-coherent
+      d.kind &= ~(K_NC_A | K_NC_B);
       d.aux = (int32_t)(p->links.size() / 2);
       for (size_t q = 1; q < mem.size(); ++q) {
         const DevTask& e = p->tasks[mem[q]];
-        p->links.push_back(e.a | ((e.kind & K_NC_A) ? LINK_NC : 0));
-        p->links.push_back(e.b | ((e.kind & K_NC_B) ? LINK_NC : 0));
+        p->links.push_back(e.a);
+        p->links.push_back(e.b);
       }
     }
     std::vector<int32_t> pr;

@@ -94,11 +94,10 @@ constexpr int32_t K_NC_B = 1 << 18;
 // Bits 20-23 of DevTask::kind on a tile product: number of further links of
 // a chained task.  Link p (p = 1..count) multiplies the operand tiles
 // links[2 (aux + p - 1)] and links[2 (aux + p - 1) + 1] (the same op and sign
-// as the first link, always accumulating); LINK_NC marks an operand that may
-// be read through the L2 cache (the rule of K_NC_A / K_NC_B).
+// as the first link, always accumulating).  A chained task reads every
+// operand device-coherent: it carries no K_NC_A / K_NC_B marks.
 constexpr int K_LINKS_SHIFT = 20;
 constexpr int32_t K_LINKS_MASK = 0xf << K_LINKS_SHIFT;
-constexpr int32_t LINK_NC = 1 << 30;
 inline int task_links(int32_t k) { return (k & K_LINKS_MASK) >> K_LINKS_SHIFT; }
 inline int32_t task_kind(int32_t k) { return k & 0xff; }
 inline int32_t task_flags(int32_t k) { return (k >> 8) & 0xff; }

@@ -194,31 +194,35 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
 // the consecutive products of one output tile's update chain run as one task
 // (op(A) = A, op(B) = B^T for every link; flags as in tile_mma).  Link 0 is
 // (A, B); link p >= 1 reads the tiles named by links[2(p-1)] and
-// links[2(p-1)+1] (LINK_NC: through the L2 cache, unless coherent_only).  The accumulator starts
-// from +-C and takes the links' products in order, k-panel by k-panel, so
-// every rounding is that of the separate tasks (whose stores and reloads of
-// the intermediate tile are exact); C is read and written once.  The
-// k-panels of all links form one double-buffered stream through LDS: the
-// first panel of link p+1 is loaded while the last panel of link p is
-// multiplied.  Two rolled loops (links, then panels) keep the accumulator in
-// the matrix-core registers; out of line, so that the single product's
-// register allocation is left as it is.
+// links[2(p-1)+1].  The accumulator starts from +-C and takes the links'
+// products in order, k-panel by k-panel, so every rounding is that of the
+// separate tasks (whose stores and reloads of the intermediate tile are
+// exact); C is read and written once.  The k-panels of all links form one
+// double-buffered stream through LDS, and each panel's body is a single
+// scheduling region in which the next panel's global loads (k-steps 0-1) and
+// their staging into LDS (k-steps 6-7) are interleaved with the MFMAs: a
+// wave issues in order, and issuing the 16 loads of a panel at once kept the
+// matrix cores idle for about half a microsecond per panel.  For that the
+// body has no branch: past the last panel the loads read a zero-size buffer
+// (they return zeros without touching memory), and every operand read is
+// device-coherent (the cache policy is an immediate of the instruction, so
+// L2-cacheable marks would need a branch; the planner sets none on chained
+// tasks).  Two rolled
+// loops (links, then panels) keep the accumulator in the matrix-core
+// registers; out of line, so that the single product's register allocation
+// is left as it is.
 // ---------------------------------------------------------------------------
 __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const double* A,
                                                          const double* B, double* copy,
-                                                         double* smem, bool nca, bool ncb,
-                                                         const int32_t* links, int nlink,
-                                                         double* pool, bool coherent_only) {
+                                                         double* smem, const int32_t* links,
+                                                         int nlink, double* pool) {
   f = uniform_int(f);
   C = uniform_ptr(C);
   A = uniform_ptr(A);
   B = uniform_ptr(B);
   copy = uniform_ptr(copy);
-  nca = uniform_int(nca) != 0;
-  ncb = uniform_int(ncb) != 0;
   links = uniform_ptr(links);
   nlink = uniform_int(nlink);
-  coherent_only = uniform_int(coherent_only) != 0;
   pool = uniform_ptr(pool);
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
@@ -253,31 +257,23 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
   }
 
   d2 ra[PAIRS], rb[PAIRS];
-  auto load = [&](rsrc_t r, bool nc, int k0, d2 (&dst)[PAIRS]) {
-    if (nc) panel_load<0>(r, k0, true, dst);
-    else panel_load<CPOL_AGENT>(r, k0, true, dst);
-  };
-  // operands of link p (wave-uniform)
-  auto link = [&](int p, rsrc_t& ra_, rsrc_t& rb_, bool& na_, bool& nb_) {
-    if (p == 0) {
-      ra_ = tile_rsrc(A);
-      rb_ = tile_rsrc(B);
-      na_ = nca;
-      nb_ = ncb;
-    } else {
-      const int va = __builtin_amdgcn_readfirstlane(links[2 * (p - 1)]);
-      const int vb = __builtin_amdgcn_readfirstlane(links[2 * (p - 1) + 1]);
-      ra_ = tile_rsrc(tile_ptr(pool, va & ~LINK_NC));
-      rb_ = tile_rsrc(tile_ptr(pool, vb & ~LINK_NC));
-      na_ = !coherent_only && (va & LINK_NC) != 0;
-      nb_ = !coherent_only && (vb & LINK_NC) != 0;
-    }
-  };
-  rsrc_t cA, cB;
-  bool cna, cnb;
-  link(0, cA, cB, cna, cnb);
-  load(cA, cna, 0, ra);
-  load(cB, cnb, 0, rb);
+  // The link table is read one link ahead: the entries of link p+1 are
+  // loaded at the head of link p-1, so that turning them into scalars at
+  // the head of link p waits for nothing (a load issued there and used at
+  // once stalls the wave for a memory round trip on every link).
+  // (global, not flat, loads: a flat load also counts as an LDS access, so
+  // the k-loop's LDS waits would wait for it too)
+  typedef const __attribute__((address_space(1))) int32_t* gint_ptr;
+  const gint_ptr LT = (gint_ptr)links;
+  int qa = 0, qb = 0;
+  if (nlink >= 1) {
+    qa = LT[0];
+    qb = LT[1];
+  }
+  const rsrc_t none = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(A), 0, 0, RSRC_WORD3);
+  rsrc_t cA = tile_rsrc(A), cB = tile_rsrc(B);
+  panel_load(cA, 0, true, ra);
+  panel_load(cB, 0, true, rb);
   panel_store(smem, 0, true, false, ra);
   panel_store(smem + PANEL, 0, true, false, rb);
   __syncthreads();
@@ -285,21 +281,27 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
 #pragma unroll 1
   for (int p = 0; p <= nlink; ++p) {
     const bool last = p == nlink;
-    rsrc_t nA = cA, nB = cB;
-    bool nna = cna, nnb = cnb;
-    if (!last) link(p + 1, nA, nB, nna, nnb);
+    rsrc_t nA = none, nB = none;
+    if (!last) {  // operands of link p+1, then the table entries of link p+2
+      const int va = __builtin_amdgcn_readfirstlane(qa);
+      const int vb = __builtin_amdgcn_readfirstlane(qb);
+      nA = tile_rsrc(tile_ptr(pool, va));
+      nB = tile_rsrc(tile_ptr(pool, vb));
+      if (p + 2 <= nlink) {
+        qa = LT[2 * (p + 1)];
+        qb = LT[2 * (p + 1) + 1];
+      }
+    }
 #pragma unroll 1
     for (int c = 0; c < NCH; ++c) {
       const double* As = smem + (c & 1) * 2 * PANEL;
       const double* Bs = As + PANEL;
+      double* An = smem + ((c + 1) & 1) * 2 * PANEL;
       const bool wrap = c + 1 == NCH;
-      const bool more = !wrap || !last;
-      if (more) {
-        const int k0 = wrap ? 0 : (c + 1) * KC;
-        load(wrap ? nA : cA, wrap ? nna : cna, k0, ra);
-        load(wrap ? nB : cB, wrap ? nnb : cnb, k0, rb);
-      }
-      __builtin_amdgcn_sched_barrier(0);
+      const rsrc_t sA = wrap ? nA : cA, sB = wrap ? nB : cB;
+      const int k0 = wrap ? 0 : (c + 1) * KC;
+      panel_load(sA, k0, true, ra);
+      panel_load(sB, k0, true, rb);
 #pragma unroll
       for (int ks = 0; ks < KC / 4; ++ks) {
         const double* Ar = As + (4 * ks + lk) * LDS_STRIDE + wm * 64 + lr;
@@ -316,18 +318,25 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
           for (int j = 0; j < 4; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
       }
-      __builtin_amdgcn_sched_barrier(0);
-      if (more) {
-        double* An = smem + ((c + 1) & 1) * 2 * PANEL;
-        panel_store(An, 0, true, false, ra);
-        panel_store(An + PANEL, 0, true, false, rb);
+      // the next panel's buffer was released by the previous barrier
+      panel_store(An, 0, true, false, ra);
+      panel_store(An + PANEL, 0, true, false, rb);
+      // order of the region: the operands of k-step 0, then per k-step half
+      // of its MFMAs, its share of the loads (k-steps 0-1) or LDS stores
+      // (k-steps 6-7), the next k-step's operands, the other half
+      __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+#pragma unroll
+      for (int ks = 0; ks < KC / 4; ++ks) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+        if (ks < 2) __builtin_amdgcn_sched_group_barrier(0x020, 8, 0);
+        if (ks >= 6) __builtin_amdgcn_sched_group_barrier(0x200, 8, 0);
+        if (ks + 1 < KC / 4) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
       }
       __syncthreads();
     }
     cA = nA;
     cB = nB;
-    cna = nna;
-    cnb = nnb;
   }
 
   if (active) {
@@ -698,8 +707,7 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
         const bool nca = !g.coherent_only && (t.kind & K_NC_A) != 0;
         const bool ncb = !g.coherent_only && (t.kind & K_NC_B) != 0;
         if (nl)
-          tile_mma_chain(f, out, a, b, cp, smem, nca, ncb, g.links + 2 * t.aux, nl, P,
-                         g.coherent_only != 0);
+          tile_mma_chain(f, out, a, b, cp, smem, g.links + 2 * t.aux, nl, P);
         else
           tile_mma<true>(f, out, a, b, cp, smem, nca, ncb);
       }

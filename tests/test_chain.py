@@ -17,7 +17,7 @@ import paper_1002_4057_amd as spd
 
 NOP, SYRK1, POTRF, GEMM1, TRSM1, TRTRI = 0, 1, 2, 3, 4, 5
 F_TA, F_TB, F_MA, F_MB, F_LOWER, F_NEG, F_ACC, F_COPYT = 1, 2, 4, 8, 16, 32, 64, 128
-LINKS_SHIFT, LINK_NC = 20, 1 << 30
+LINKS_SHIFT = 20
 NC_A, NC_B = 1 << 17, 1 << 18
 VARIANTS = [dict(), dict(pipelined=0), dict(renamed=0), dict(trtri_first=1), dict(loop_order=1),
             dict(renamed=0, trtri_first=1)]
@@ -28,8 +28,9 @@ def nlinks(code):
 
 
 def expand(p):
-    """Program-order list of (out, a, b, flags, nc_a, nc_b, copy) per product
-    link, plus the non-product tasks as (kind, out) markers."""
+    """Program-order list of (out, a, b, flags, copy) per product link, plus
+    the non-product tasks as (kind, out) markers.  (The L2-cacheable read
+    marks are left out: chained tasks read device-coherent.)"""
     seq = []
     for task in p["tasks"]:
         code, out, a, b, cp, aux = (int(x) for x in task[:6])
@@ -38,15 +39,12 @@ def expand(p):
             seq.append(("task", kind, out, cp))
             continue
         L = nlinks(code)
-        ops = [(a, b, bool(code & NC_A), bool(code & NC_B))]
-        for q in range(L):
-            la, lb = (int(x) for x in p["links"][aux + q])
-            ops.append((la & ~LINK_NC, lb & ~LINK_NC, bool(la & LINK_NC), bool(lb & LINK_NC)))
-        for q, (oa, ob, na, nb) in enumerate(ops):
+        ops = [(a, b)] + [tuple(int(x) for x in p["links"][aux + q]) for q in range(L)]
+        for q, (oa, ob) in enumerate(ops):
             fq = f if q == 0 else f | F_ACC
             if q < L:
                 fq &= ~F_COPYT        # the copy belongs to the last link
-            seq.append(("prod", out, oa, ob, fq, na, nb, cp if q == L else -1))
+            seq.append(("prod", out, oa, ob, fq, cp if q == L else -1))
     return seq
 
 
@@ -106,8 +104,9 @@ def test_contracted_dag_structure(t, opts):
         # a chain reads both operands along columns and never reads its output
         assert f & F_TB and not f & (F_TA | F_MA | F_MB)
         for q in range(L):
-            la, lb = (int(x) & ~LINK_NC for x in p["links"][tasks[v, 5] + q])
+            la, lb = (int(x) for x in p["links"][tasks[v, 5] + q])
             assert la != tasks[v, 1] and lb != tasks[v, 1]
+        assert not code & (NC_A | NC_B)       # chained tasks read device-coherent
 
 
 @pytest.mark.parametrize("t", [4, 8, 16])
