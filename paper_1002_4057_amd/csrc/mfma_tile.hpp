@@ -179,14 +179,18 @@ __device__ __forceinline__ void panel_mma(Acc& acc, const double* As, const doub
 // names the two contiguous tiles of link p.  Both operands are read along
 // stored columns.  The k-panels of all links form one double-buffered
 // stream through LDS (smem: 4 * PANEL doubles), so the first panel of link
-// p+1 is loaded while the last panel of link p is multiplied.  The pair
-// function must give the same pointers in every thread.  The accumulator is
-// never written to memory here.
+// p+1 is loaded while the last panel of link p is multiplied.  Each panel's
+// body is one branch-free scheduling region in which the next panel's loads
+// (k-steps 0-1) and their staging into LDS (k-steps 6-7) are interleaved
+// with the MFMAs; past the last panel the loads read a zero-size buffer
+// (zeros, no memory access).  The pair function must give the same pointers
+// in every thread.  The accumulator is never written to memory here.
 template <int CP, class PairFn>
 __device__ __forceinline__ void mma_chain(Acc& acc, int count, PairFn pair, double* smem) {
   if (count <= 0) return;
   const double *pa, *pb;
   pair(0, pa, pb);
+  const rsrc_t none = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(pa), 0, 0, RSRC_WORD3);
   d2 ra[PAIRS], rb[PAIRS];
   panel_load<CP>(tile_rsrc(pa), 0, true, ra);
   panel_load<CP>(tile_rsrc(pb), 0, true, rb);
@@ -201,25 +205,29 @@ __device__ __forceinline__ void mma_chain(Acc& acc, int count, PairFn pair, doub
   for (int p = 0; p < count; ++p) {
     const double *qa, *qb;
     pair(p + 1 < count ? p + 1 : p, qa, qb);
-    const rsrc_t rA = tile_rsrc(pa), rB = tile_rsrc(pb), nA = tile_rsrc(qa), nB = tile_rsrc(qb);
     const bool last = p + 1 >= count;
+    const rsrc_t rA = tile_rsrc(pa), rB = tile_rsrc(pb);
+    const rsrc_t nA = last ? none : tile_rsrc(qa), nB = last ? none : tile_rsrc(qb);
 #pragma unroll 1
     for (int c = 0; c < NCH; ++c) {
       const double* As = smem + (c & 1) * 2 * PANEL;
       const double* Bs = As + PANEL;
+      double* An = smem + ((c + 1) & 1) * 2 * PANEL;
       const bool wrap = c + 1 == NCH;
-      const bool more = !wrap || !last;
-      if (more) {
-        panel_load<CP>(wrap ? nA : rA, ((c + 1) % NCH) * KC, true, ra);
-        panel_load<CP>(wrap ? nB : rB, ((c + 1) % NCH) * KC, true, rb);
-      }
-      __builtin_amdgcn_sched_barrier(0);
+      panel_load<CP>(wrap ? nA : rA, ((c + 1) % NCH) * KC, true, ra);
+      panel_load<CP>(wrap ? nB : rB, ((c + 1) % NCH) * KC, true, rb);
       panel_mma(acc, As, Bs);
-      __builtin_amdgcn_sched_barrier(0);
-      if (more) {
-        double* An = smem + ((c + 1) & 1) * 2 * PANEL;
-        panel_store(An, 0, true, false, ra);
-        panel_store(An + PANEL, 0, true, false, rb);
+      // the next panel's buffer was released by the previous barrier
+      panel_store(An, 0, true, false, ra);
+      panel_store(An + PANEL, 0, true, false, rb);
+      __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+#pragma unroll
+      for (int ks = 0; ks < KC / 4; ++ks) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+        if (ks < 2) __builtin_amdgcn_sched_group_barrier(0x020, 8, 0);
+        if (ks >= 6) __builtin_amdgcn_sched_group_barrier(0x200, 8, 0);
+        if (ks + 1 < KC / 4) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
       }
       __syncthreads();
     }
