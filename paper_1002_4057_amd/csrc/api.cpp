@@ -274,6 +274,7 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   a.pool = pool;
   a.links = dp->d_links;
   a.coherent_only = 0;
+  a.last_valid = n - (t - 1) * NB;
   a.trace = trace;
   a.ntask = ntask;
   a.tiles_T = t * (t + 1) / 2;
@@ -530,6 +531,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
   a.pool = reinterpret_cast<double*>(pool);
   a.links = nullptr;
   a.coherent_only = 0;
+  a.last_valid = NB;
   a.trace = nullptr;
   a.ntask = ntask;
   a.tiles_T = t * (t + 1) / 2;

@@ -136,6 +136,7 @@ __device__ int tile_sequential(double* A, int lda, int n, int fill_upper, const 
   g.links = links;
   // the pool is reused by the next matrix: keep every read device-coherent
   g.coherent_only = 1;
+  g.last_valid = n - (t - 1) * NB;
   __shared__ int s_info;
   for (int k = 0; k < ntask; ++k) {
     const DevTask task = tasks[k];

@@ -31,6 +31,8 @@ struct SchedArgs {
   double* pool;        // tile pool
   const int32_t* links;  // further links of chained products (or nullptr)
   int coherent_only;   // 1: ignore the planner's L2-cacheable read marks
+  int last_valid;      // rows/columns of the last tile block inside the matrix
+                       // (NB when n is a multiple of NB)
   long long* trace;    // 4 per task, or nullptr
   int ntask;
   int tiles_T;         // lower tiles per copy, T = t(t+1)/2 (pool layout)

@@ -380,7 +380,7 @@ void chain_products(int chain, Plan* p, std::vector<std::vector<int32_t>>& preds
       d.aux = (int32_t)(p->links.size() / 2);
       for (size_t q = 1; q < mem.size(); ++q) {
         const DevTask& e = p->tasks[mem[q]];
-        p->links.push_back(e.a);
+        p->links.push_back(e.a | ((e.kind & K_KLAST) ? LINK_KLAST : 0));
         p->links.push_back(e.b);
       }
     }
@@ -480,6 +480,21 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
       if (cacheable(d.a)) d.kind |= K_NC_A;
       if (cacheable(d.b)) d.kind |= K_NC_B;
     }
+  }
+
+  // products whose reduction index is the last tile block: the stored
+  // columns of a pool tile are its column block for A tiles and D_j, its row
+  // block for the transposed copies B, C and D_j^T
+  {
+    const int T = p->T;
+    auto klast = [&](int x) {
+      if (x < 0) return false;
+      if (x < T) return x == T - 1;                        // A(t-1, t-1)
+      if (x < 3 * T) return (x - T) % T >= t * (t - 1) / 2;  // B(t-1, .), C(t-1, .)
+      return x == 3 * T + t - 1 || x == 3 * T + 2 * t - 1;  // D_{t-1}, D_{t-1}^T
+    };
+    for (DevTask& d : p->tasks)
+      if (column_product(d) && (klast(d.a) || klast(d.b))) d.kind |= K_KLAST;
   }
 
   // statistics of the paper's DAG: task counts and critical paths (unit

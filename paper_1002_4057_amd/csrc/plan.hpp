@@ -91,11 +91,22 @@ constexpr int32_t K_POTRF_FACTOR_DEAD = 1 << 16;
 // so a tile read in an earlier version is never read through the cache.)
 constexpr int32_t K_NC_A = 1 << 17;
 constexpr int32_t K_NC_B = 1 << 18;
+// Bit 19 of DevTask::kind on a column-form product (op(A) = A, op(B) = B^T):
+// the stored columns of its operands, i.e. its reduction index, are the last
+// tile block.  When the order n is not a multiple of NB, that block is
+// padded, and the device skips the k-panels past the valid extent: their
+// products are exact zeros (padded rows of off-diagonal tiles are zero), or
+// they only feed the padded diagonal block of the last diagonal tile, which
+// no later task reads and copy-out does not write.  On a link entry the same
+// mark is LINK_KLAST.
+constexpr int32_t K_KLAST = 1 << 19;
+constexpr int32_t LINK_KLAST = 1 << 30;
 // Bits 20-23 of DevTask::kind on a tile product: number of further links of
 // a chained task.  Link p (p = 1..count) multiplies the operand tiles
 // links[2 (aux + p - 1)] and links[2 (aux + p - 1) + 1] (the same op and sign
-// as the first link, always accumulating).  A chained task reads every
-// operand device-coherent: it carries no K_NC_A / K_NC_B marks.
+// as the first link, always accumulating; the tile index of operand a may
+// carry LINK_KLAST).  A chained task reads every operand device-coherent: it
+// carries no K_NC_A / K_NC_B marks.
 constexpr int K_LINKS_SHIFT = 20;
 constexpr int32_t K_LINKS_MASK = 0xf << K_LINKS_SHIFT;
 inline int task_links(int32_t k) { return (k & K_LINKS_MASK) >> K_LINKS_SHIFT; }

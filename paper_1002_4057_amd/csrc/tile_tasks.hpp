@@ -40,6 +40,8 @@ constexpr int SMEM_DOUBLES = GEMM_SMEM > POTRF_SMEM ? GEMM_SMEM : POTRF_SMEM;
 // not store: it runs alone on its SIMD, so skipping its work would save no
 // time).  C may alias A or B: every operand read precedes the first store.
 // copy (may be null) receives the same result, transposed with F_COPYT.
+// npan: k-panels to run (fewer than NCH skips the padded tail of a ragged
+// last tile block, see K_KLAST).
 // Waves form a 2 x 2 grid of 64 x 64 output blocks, each a 4 x 4 array of
 // 16 x 16 MFMA accumulators.  The sign is handled without touching the
 // operands: the accumulator starts from -C and the result is negated on the
@@ -52,7 +54,7 @@ constexpr int SMEM_DOUBLES = GEMM_SMEM > POTRF_SMEM ? GEMM_SMEM : POTRF_SMEM;
 template <bool FAST>
 __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, const double* B,
                                          double* copy, double* smem, bool nca = false,
-                                         bool ncb = false) {
+                                         bool ncb = false, int npan = NCH) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int wm = w & 1, wn = w >> 1;
@@ -113,10 +115,10 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
   __syncthreads();
 
 #pragma unroll 1
-  for (int c = 0; c < NCH; ++c) {
+  for (int c = 0; c < npan; ++c) {
     const double* As = smem + (c & 1) * 2 * PANEL;
     const double* Bs = As + PANEL;
-    const bool more = c + 1 < NCH;
+    const bool more = c + 1 < npan;
     if (more) {
       load_a((c + 1) * KC);
       load_b((c + 1) * KC);
@@ -194,8 +196,9 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
 // the consecutive products of one output tile's update chain run as one task
 // (op(A) = A, op(B) = B^T for every link; flags as in tile_mma).  Link 0 is
 // (A, B); link p >= 1 reads the tiles named by links[2(p-1)] and
-// links[2(p-1)+1].  The accumulator starts from +-C and takes the links'
-// products in order, k-panel by k-panel, so every rounding is that of the
+// links[2(p-1)+1].  Link 0 runs npan0 k-panels, a link marked LINK_KLAST
+// npan_last, any other NCH (see K_KLAST).  The accumulator starts from +-C
+// and takes the links' products in order, k-panel by k-panel, so every rounding is that of the
 // separate tasks (whose stores and reloads of the intermediate tile are
 // exact); C is read and written once.  The k-panels of all links form one
 // double-buffered stream through LDS, and each panel's body is a single
@@ -215,7 +218,8 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
 __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const double* A,
                                                          const double* B, double* copy,
                                                          double* smem, const int32_t* links,
-                                                         int nlink, double* pool) {
+                                                         int nlink, double* pool, int npan0,
+                                                         int npan_last) {
   f = uniform_int(f);
   C = uniform_ptr(C);
   A = uniform_ptr(A);
@@ -224,6 +228,8 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
   links = uniform_ptr(links);
   nlink = uniform_int(nlink);
   pool = uniform_ptr(pool);
+  npan0 = uniform_int(npan0);
+  npan_last = uniform_int(npan_last);
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int wm = w & 1, wn = w >> 1;
@@ -278,26 +284,31 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
   panel_store(smem + PANEL, 0, true, false, rb);
   __syncthreads();
 
+  // panels run by link p (npan) and by link p+1 (nnext); gp counts panels
+  // over the whole chain for the LDS double buffer
+  int npan = npan0, gp = 0;
 #pragma unroll 1
   for (int p = 0; p <= nlink; ++p) {
     const bool last = p == nlink;
     rsrc_t nA = none, nB = none;
+    int nnext = NCH;
     if (!last) {  // operands of link p+1, then the table entries of link p+2
       const int va = __builtin_amdgcn_readfirstlane(qa);
       const int vb = __builtin_amdgcn_readfirstlane(qb);
-      nA = tile_rsrc(tile_ptr(pool, va));
+      nA = tile_rsrc(tile_ptr(pool, va & ~LINK_KLAST));
       nB = tile_rsrc(tile_ptr(pool, vb));
+      nnext = (va & LINK_KLAST) ? npan_last : NCH;
       if (p + 2 <= nlink) {
         qa = LT[2 * (p + 1)];
         qb = LT[2 * (p + 1) + 1];
       }
     }
 #pragma unroll 1
-    for (int c = 0; c < NCH; ++c) {
-      const double* As = smem + (c & 1) * 2 * PANEL;
+    for (int c = 0; c < npan; ++c, ++gp) {
+      const double* As = smem + (gp & 1) * 2 * PANEL;
       const double* Bs = As + PANEL;
-      double* An = smem + ((c + 1) & 1) * 2 * PANEL;
-      const bool wrap = c + 1 == NCH;
+      double* An = smem + ((gp + 1) & 1) * 2 * PANEL;
+      const bool wrap = c + 1 == npan;
       const rsrc_t sA = wrap ? nA : cA, sB = wrap ? nB : cB;
       const int k0 = wrap ? 0 : (c + 1) * KC;
       panel_load(sA, k0, true, ra);
@@ -337,6 +348,7 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
     }
     cA = nA;
     cB = nB;
+    npan = nnext;
   }
 
   if (active) {
@@ -706,10 +718,13 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
         const int nl = (t.kind & K_LINKS_MASK) >> K_LINKS_SHIFT;
         const bool nca = !g.coherent_only && (t.kind & K_NC_A) != 0;
         const bool ncb = !g.coherent_only && (t.kind & K_NC_B) != 0;
+        // k-panels of a product over the (possibly ragged) last tile block
+        const int npan_last = (g.last_valid + KC - 1) / KC;
+        const int npan = (t.kind & K_KLAST) ? npan_last : NCH;
         if (nl)
-          tile_mma_chain(f, out, a, b, cp, smem, g.links + 2 * t.aux, nl, P);
+          tile_mma_chain(f, out, a, b, cp, smem, g.links + 2 * t.aux, nl, P, npan, npan_last);
         else
-          tile_mma<true>(f, out, a, b, cp, smem, nca, ncb);
+          tile_mma<true>(f, out, a, b, cp, smem, nca, ncb, npan);
       }
       else
         tile_mma_general(f, out, a, b, cp, smem);

@@ -17,7 +17,7 @@ import paper_1002_4057_amd as spd
 
 NOP, SYRK1, POTRF, GEMM1, TRSM1, TRTRI = 0, 1, 2, 3, 4, 5
 F_TA, F_TB, F_MA, F_MB, F_LOWER, F_NEG, F_ACC, F_COPYT = 1, 2, 4, 8, 16, 32, 64, 128
-LINKS_SHIFT = 20
+LINKS_SHIFT, LINK_KLAST, K_KLAST = 20, 1 << 30, 1 << 19
 NC_A, NC_B = 1 << 17, 1 << 18
 VARIANTS = [dict(), dict(pipelined=0), dict(renamed=0), dict(trtri_first=1), dict(loop_order=1),
             dict(renamed=0, trtri_first=1)]
@@ -28,7 +28,8 @@ def nlinks(code):
 
 
 def expand(p):
-    """Program-order list of (out, a, b, flags, copy) per product link, plus
+    """Program-order list of (out, a, b, flags, last-block mark, copy) per
+    product link, plus
     the non-product tasks as (kind, out) markers.  (The L2-cacheable read
     marks are left out: chained tasks read device-coherent.)"""
     seq = []
@@ -39,12 +40,15 @@ def expand(p):
             seq.append(("task", kind, out, cp))
             continue
         L = nlinks(code)
-        ops = [(a, b)] + [tuple(int(x) for x in p["links"][aux + q]) for q in range(L)]
-        for q, (oa, ob) in enumerate(ops):
+        ops = [(a, b, bool(code & K_KLAST))]
+        for q in range(L):
+            la, lb = (int(x) for x in p["links"][aux + q])
+            ops.append((la & ~LINK_KLAST, lb, bool(la & LINK_KLAST)))
+        for q, (oa, ob, kl) in enumerate(ops):
             fq = f if q == 0 else f | F_ACC
             if q < L:
                 fq &= ~F_COPYT        # the copy belongs to the last link
-            seq.append(("prod", out, oa, ob, fq, cp if q == L else -1))
+            seq.append(("prod", out, oa, ob, fq, kl, cp if q == L else -1))
     return seq
 
 
@@ -105,6 +109,7 @@ def test_contracted_dag_structure(t, opts):
         assert f & F_TB and not f & (F_TA | F_MA | F_MB)
         for q in range(L):
             la, lb = (int(x) for x in p["links"][tasks[v, 5] + q])
+            la &= ~LINK_KLAST
             assert la != tasks[v, 1] and lb != tasks[v, 1]
         assert not code & (NC_A | NC_B)       # chained tasks read device-coherent
 
@@ -163,3 +168,28 @@ def test_chain_option_range_checked():
     o = _lib.make_opts(chain=17)
     assert lib.spd_inverse(4, ctypes.c_void_p(8), 4, 0, None, 0, None, ctypes.byref(o), None,
                            None) < 0
+
+
+# reduction index of each product kind in the paper's (i, j, k) naming
+KBLOCK = {1: "k", 3: "k", 4: "j", 6: "i", 7: "k", 8: "j", 9: "i", 10: "i", 11: "k", 12: "k"}
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(pipelined=0), dict(trtri_first=1),
+                                  dict(loop_order=1), dict(renamed=0)])
+@pytest.mark.parametrize("t", [1, 2, 3, 4, 6])
+def test_last_block_reduction_marks(t, opts):
+    """K_KLAST is set exactly on the column-form products whose reduction
+    index (k for GEMM and SYRK, j for the TRSMs, i for the TRMMs and LAUUM)
+    is the last tile block; the device then skips the padded k-panels."""
+    p = spd.plan_export(t, workers=4, chain=1, **opts)
+    for task, packed in zip(p["tasks"], p["idx"]):
+        code = int(task[0])
+        kind, f = code & 0xFF, (code >> 8) & 0xFF
+        if kind not in KBLOCK:
+            assert not code & K_KLAST
+            continue
+        ijk = {"i": (int(packed) >> 20) & 1023, "j": (int(packed) >> 10) & 1023,
+               "k": int(packed) & 1023}
+        column = f & F_TB and not f & (F_TA | F_MA | F_MB)
+        expect = bool(column) and ijk[KBLOCK[kind]] == t - 1
+        assert bool(code & K_KLAST) == expect, (kind, ijk)

@@ -12,6 +12,7 @@ import numpy as np
 NOP, SYRK1, POTRF, GEMM1, TRSM1, TRTRI, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEMM3, SYRK3 = range(13)
 POTRF_FACTOR_DEAD = 1 << 16
 LINKS_SHIFT = 20   # chained products: count of further links (see plan.hpp)
+LINK_KLAST = 1 << 30   # link mark: reduction over the last tile block
 PRODUCTS = {SYRK1, GEMM1, TRSM1, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEMM3, SYRK3}
 F_TA, F_TB, F_MA, F_MB, F_LOWER, F_NEG, F_ACC, F_COPYT = 1, 2, 4, 8, 16, 32, 64, 128
 
@@ -58,6 +59,7 @@ def run_task(pool, task, t, links=None):
         ops = [(a, b)]
         for q in range((code >> LINKS_SHIFT) & 0xF):
             la, lb = (int(x) for x in links[aux + q])
+            la &= ~LINK_KLAST
             ops.append((la, lb))
         for q, (oa, ob) in enumerate(ops):
             fq = f if q == 0 else f | F_ACC
