@@ -605,11 +605,15 @@ __device__ __forceinline__ void inverse_lds(double* T, const double* XD, double*
 
 // Outputs: the factor (Lout, may be null: not stored), its transpose (LcopyT,
 // may be null), the inverse of the factor (Xout) and its transpose (XoutT),
-// each with explicit zeros in the other triangle.  Returns 0, or the 1-based local index of the
+// each with explicit zeros in the other triangle.  Only the first P blocks of
+// 16 are factored and inverted: past them the tile must be an identity block
+// with zero cross blocks (the padding of a ragged order), whose factor and
+// inverse are the identity.  Returns 0, or the 1-based local index of the
 // first pivot that is not positive (or NaN); on failure nothing is stored.
 __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, double* Lout,
                                                          double* LcopyT, double* Xout,
-                                                         double* XoutT, double* smem) {
+                                                         double* XoutT, double* smem, int P) {
+  P = uniform_int(P);
   Ain = uniform_ptr(Ain);
   Lout = uniform_ptr(Lout);
   LcopyT = uniform_ptr(LcopyT);
@@ -639,7 +643,7 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
   }
   __syncthreads();
 
-  const int ff = factor_lds(T, XD, SCR, flag, 8);
+  const int ff = factor_lds(T, XD, SCR, flag, P);
   if (ff) return ff;
 
   // the factor and its transpose, as contiguous 16-byte stores (the
@@ -663,13 +667,14 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
   }
   __syncthreads();  // the inverse below writes the upper blocks of T
 
-  inverse_lds(T, XD, SCR, 8);
+  inverse_lds(T, XD, SCR, P);
   __syncthreads();
   // X and X^T as contiguous 16-byte stores: X(r, c) is XD for diagonal
-  // blocks, T(c, r) below them (stored transposed), zero above
+  // blocks, T(c, r) below them (stored transposed), zero above; the identity
+  // on the diagonal blocks past P (the padding)
   auto xval = [&](int r, int c) -> double {
     const int br = r >> 4, bc = c >> 4;
-    if (br == bc) return XD[256 * br + (r & 15) + 16 * (c & 15)];
+    if (br == bc) return br < P ? XD[256 * br + (r & 15) + 16 * (c & 15)] : (r == c ? 1.0 : 0.0);
     return (br > bc) ? T[c + LD * r] : 0.0;
   };
 #pragma unroll 4
@@ -733,7 +738,12 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
       double* X = tile_ptr(P, t.aux);
       double* Xt = tile_ptr(P, t.aux + tiles);
       const bool live = !(t.kind & K_POTRF_FACTOR_DEAD);
-      const int fl = potrf_inv_tile(out, live ? out : nullptr, cp, X, Xt, smem);
+      // the last diagonal tile of a ragged order: its padded part is an exact
+      // identity block (zero cross blocks), so only its first
+      // ceil(last_valid / 16) blocks of 16 are factored and inverted
+      const bool ragged = t.aux - 3 * T == tiles - 1;
+      const int P16 = ragged ? (g.last_valid + 15) / 16 : NB / 16;
+      const int fl = potrf_inv_tile(out, live ? out : nullptr, cp, X, Xt, smem, P16);
       if (fl && threadIdx.x == 0) {
         const int jt = t.aux - 3 * T;  // diagonal tile index
         atomicMin(&g.ctrl[CTRL_INFO], g.info_base + jt * NB + fl);
