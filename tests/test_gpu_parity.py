@@ -260,6 +260,31 @@ def test_bench_size_against_analytic_inverse(n):
     assert res <= 1e-12 * 1e4
 
 
+def test_bench_size_chained_tasks_bit_identical_to_paper_tasks():
+    """At the benchmark size (n = 8192, 64 x 64 tiles, every resident
+    worker), the default plan with chained device tasks gives the same bits
+    as the plan with one device task per task of the paper's stream."""
+    n = 8192
+    a = inputs.spectrum(n, 1e4, seed=0, device=DEV)
+    x_chain = spd.spd_inverse(a)
+    x_paper = spd.spd_inverse(a, chain=1)
+    assert torch.equal(x_chain, x_paper)
+
+
+@pytest.mark.parametrize("n", [8192 - 100, 4096 + 1])
+def test_ragged_large_orders_against_analytic_inverse(n):
+    """Ragged orders at scale (last tile block with 28 and 1 valid rows): the
+    padded k-panels are skipped and the last diagonal tile is factored on its
+    valid blocks only; parity against Q diag(1/lambda) Q^T and bit-identity
+    with the plan of one device task per paper task."""
+    a, q, lam = inputs.spectrum(n, 1e4, seed=3, device=DEV, return_factors=True)
+    x = spd.spd_inverse(a)
+    ref = inputs.analytic_inverse(q, lam)
+    err = (torch.linalg.norm(x - ref) / torch.linalg.norm(ref)).item()
+    assert err <= 1e-12 * 1e4
+    assert torch.equal(x, spd.spd_inverse(a, chain=1))
+
+
 def test_scheduler_wait_timeout_is_reported(monkeypatch):
     """A tiny bound on the scheduler's own dependency wait (set from the host)
     makes workers give up; the kernel still drains and the call reports the
