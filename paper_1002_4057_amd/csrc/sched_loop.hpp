@@ -14,35 +14,47 @@ using tile::stores_complete;
 
 // Persistent worker loop.  On the device the tasks are numbered in dispatch
 // order (the planner's list-scheduling order, a topological order), so a
-// dispatch ticket is the task id itself.  Thread 0 of each workgroup claims
-// the next ticket at the head of every iteration and waits until that task's
-// in-degree is zero; since tickets are topological, every claimed task's
-// predecessors hold earlier tickets, which makes the loop deadlock-free for
-// any number of resident workgroups.  The successor ids of the task are
-// loaded when it starts, one per thread, so that at its end (once every
-// thread's stores have completed) the threads release the successors with
-// parallel in-degree decrements.  Every divergent region (the thread-0 claim,
-// the release) sits between workgroup barriers.  Counters and tiles are accessed with
-// agent-scope coherence, so no cache maintenance is needed.  The claim sits in
-// one thread-0 region at the loop head, which leaves the loop body (and every
-// barrier in it) in uniform control flow.
+// dispatch ticket is the task id itself.  Thread 0 claims tickets and waits
+// until a claimed task's in-degree is zero; since tickets are topological,
+// every claimed task's predecessors hold earlier tickets, which makes the
+// loop deadlock-free for any number of resident workgroups.
+// Latency hiding at the task boundary:
+//  - the ticket for the next task is claimed while the current task's
+//    stores drain (its readiness is tested only after the current task has
+//    released its successors, so a claimed task that depends on the current
+//    one cannot block it);
+//  - thread 0 fetches the task descriptor together with the in-degree poll
+//    and hands it to the workgroup through LDS;
+//  - the successor ids are loaded when the task starts, one per thread, so
+//    that at its end (once every thread's stores have completed) the threads
+//    release the successors with parallel in-degree decrements.
+// Every divergent region (the thread-0 claim and poll, the release) sits
+// between workgroup barriers, which keeps the loop body, and every barrier
+// in it, one level deep.  Counters and tiles are accessed with agent-scope
+// coherence, so no cache maintenance is needed.
 template <class Run>
 __device__ __forceinline__ void sched_loop(const SchedArgs& g, Run run) {
   __shared__ int s_task;
   __shared__ int s_skip;
-  int prev = -1;  // meaningful in thread 0 only
+  __shared__ DevTask s_desc;
+  int prev = -1;   // meaningful in thread 0 only
+  int claim = -1;  // thread 0: ticket claimed during the previous task (or -1)
+  long long t_claim = 0;
   for (;;) {
     if (threadIdx.x == 0) {
       if (prev >= 0) {
         if (g.trace) g.trace[4 * (size_t)prev + 3] = now_ticks();
         __hip_atomic_fetch_add(&g.ctrl[CTRL_DONE], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      long long t_claim = 0;
-      if (g.trace) t_claim = now_ticks();
-      const int tk = __hip_atomic_fetch_add(&g.ctrl[CTRL_TICKET], 1, __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-      int v = tk < g.ntask ? tk : -1;
+      if (claim < 0) {
+        if (g.trace) t_claim = now_ticks();
+        claim = __hip_atomic_fetch_add(&g.ctrl[CTRL_TICKET], 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+      }
+      int v = claim < g.ntask ? claim : -1;
+      claim = -1;
       if (v >= 0) {
+        const DevTask d = g.tasks[v];  // in flight during the poll
         // bounded wait: gives up after spin_limit ticks of the 100 MHz clock
         const long long t0 = now_ticks();
         long long spins = 0;
@@ -60,6 +72,7 @@ __device__ __forceinline__ void sched_loop(const SchedArgs& g, Run run) {
             }
           }
         }
+        s_desc = d;
       }
       if (v >= 0) {
         if (g.trace) {
@@ -78,10 +91,16 @@ __device__ __forceinline__ void sched_loop(const SchedArgs& g, Run run) {
     // wave-uniform
     const int v = __builtin_amdgcn_readfirstlane(s_task);
     if (v < 0) break;
-    const DevTask t = g.tasks[v];
+    const DevTask t = s_desc;
     const int nsucc = t.succ_end - t.succ_begin;
     const int my_succ = (int)threadIdx.x < nsucc ? g.succ[t.succ_begin + threadIdx.x] : -1;
     if (!__builtin_amdgcn_readfirstlane(s_skip)) run(t);
+    // claim the next ticket while the stores drain
+    if (threadIdx.x == 0) {
+      if (g.trace) t_claim = now_ticks();
+      claim = __hip_atomic_fetch_add(&g.ctrl[CTRL_TICKET], 1, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+    }
     stores_complete();
     __syncthreads();
     // every store of the task has completed: release its successors
