@@ -35,7 +35,7 @@
 namespace spdinv {
 
 // Task kinds.  The device executes each kind as one tile operation; see
-// kernels.hip for the arithmetic of each.
+// tile_tasks.hpp (run_task) for the arithmetic of each.
 enum Kind : int32_t {
   K_NOP = 0,     // barrier between steps (no work, weight 0)
   K_SYRK1 = 1,   // A_jj -= A_jk A_jk^T
