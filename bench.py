@@ -124,7 +124,9 @@ def batched_row(reps: int):
     return {"workload": "8192 SPD matrices, n uniform on [16,512] (seed 0), A_i = B_i B_i^T/n_i "
                         "+ 0.1 I, FP64, one persistent launch",
             "ms": round(ms, 3), "matrices_per_s": round(len(orders) / (ms / 1e3), 1),
-            "gflops": round(flops / (ms / 1e3) / 1e9, 1), "flops": flops, "reps": reps}
+            "gflops": round(flops / (ms / 1e3) / 1e9, 1), "flops": flops,
+            "frac_fp64_peak": round(flops / (ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+            "reps": reps}
 
 
 def backward_row(reps: int):
