@@ -603,6 +603,160 @@ __device__ __forceinline__ void inverse_lds(double* T, const double* XD, double*
   }
 }
 
+// ---------------------------------------------------------------------------
+// Diagonal tile in packed form: only the 36 lower 16 x 16 blocks of the tile
+// are held in LDS, block (i, p) (i >= p) at PK_STRIDE * (i(i+1)/2 + p),
+// column-major with the odd leading dimension PK_LD (transposed reads spread
+// over the banks).  77.6 KB with the pivots, so that the scheduler's
+// workgroups fit two per CU.
+// ---------------------------------------------------------------------------
+constexpr int PK_LD = 17;
+constexpr int PK_STRIDE = 16 * PK_LD;
+constexpr int PK_BLOCKS = 8 * 9 / 2;
+constexpr int PK_SMEM = PK_BLOCKS * PK_STRIDE + NB + 8;  // blocks + reciprocal pivots + flag
+static_assert(PK_SMEM <= SMEM_DOUBLES, "packed diagonal tile exceeds the workgroup's LDS");
+static_assert(PK_BLOCKS * 128 % NTHREADS == 0, "packed load assumes whole passes");
+
+__device__ __forceinline__ double* pk_blk(double* T, int i, int p) {
+  return T + PK_STRIDE * (i * (i + 1) / 2 + p);
+}
+
+// Blocked Cholesky factorization of the leading 16P x 16P block of the
+// packed tile, in place; the steps of factor_lds (one block of lookahead:
+// wave 0 updates and factors the next diagonal block while waves 1-3 update
+// the rest of the trailing blocks), on packed blocks.  rd receives the 16P
+// reciprocal pivots.  Returns 0 or the 1-based index of the first pivot that
+// is not positive (or NaN), uniform over the workgroup.
+__device__ __forceinline__ int factor_packed(double* T, double* rd, int* flag, int P) {
+  const int tid = threadIdx.x, w = tid >> 6;
+  if (w == 0) {
+    const int f = chol16(pk_blk(T, 0, 0), PK_LD, rd);
+    if (tid == 0) *flag = f;
+  }
+  __syncthreads();
+  int fail = __builtin_amdgcn_readfirstlane(*flag);
+  if (fail) return fail;
+  for (int p = 0; p < P; ++p) {
+    // panel: row R of the blocks below the diagonal block solves x L_pp^T = a
+    const int rows = 16 * (P - 1 - p);
+    if (tid < rows) {
+      const int R = 16 * (p + 1) + tid;
+      const double* Lpp = pk_blk(T, p, p);
+      double* a = pk_blk(T, R >> 4, p) + (R & 15);
+      double x[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        double s = a[PK_LD * c];
+#pragma unroll
+        for (int m = 0; m < c; ++m) s = fma(-x[m], Lpp[c + PK_LD * m], s);
+        x[c] = s * rd[16 * p + c];
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) a[PK_LD * c] = x[c];
+    }
+    __syncthreads();
+    if (p + 1 == P) break;
+    const int nb = P - 1 - p;
+    if (w == 0) {
+      double* Cnn = pk_blk(T, p + 1, p + 1);
+      const double* Lnp = pk_blk(T, p + 1, p);
+      d4 acc = -blk_load(Cnn, PK_LD);
+      acc = blk_mma16(acc, Lnp, PK_LD, Lnp, PK_LD, true);
+      blk_store(Cnn, PK_LD, -acc);
+      const int f = chol16(Cnn, PK_LD, rd + 16 * (p + 1));
+      if (tid == 0) *flag = f ? 16 * (p + 1) + f : 0;
+    } else {
+      for (int q = w; q < nb * (nb + 1) / 2; q += 3) {
+        int i = 0;
+        while ((i + 1) * (i + 2) / 2 <= q) ++i;
+        const int j = q - i * (i + 1) / 2;
+        const int bi = p + 1 + i, bj = p + 1 + j;
+        double* Cij = pk_blk(T, bi, bj);
+        d4 acc = -blk_load(Cij, PK_LD);
+        acc = blk_mma16(acc, pk_blk(T, bi, p), PK_LD, pk_blk(T, bj, p), PK_LD, true);
+        blk_store(Cij, PK_LD, -acc);
+      }
+    }
+    __syncthreads();
+    fail = __builtin_amdgcn_readfirstlane(*flag);
+    if (fail) return fail;
+  }
+  return 0;
+}
+
+// X = L^{-1} in place on the packed factor (its first P blocks of 16).
+// First X_pp = L_pp^{-1} for every diagonal block (16 lanes per block, one
+// column per lane, by forward substitution with the reciprocal pivots rd).
+// Then block columns p = P-2 .. 0 from the right, using X L = I:
+//   Y_mp = L_mp X_pp  (m > p; replaces L_mp),
+//   X_ip = -sum_{m=p+1..i} X_im Y_mp  (i > p; replaces Y_ip once every block
+//   of the column is formed).
+// Each phase keeps its results in registers until a barrier, so the blocks
+// of a column are formed in parallel over the waves and nothing else needs
+// LDS.
+__device__ __forceinline__ void inverse_packed(double* T, const double* rd, int P) {
+  const int tid = threadIdx.x, w = tid >> 6;
+  {
+    const int g = tid >> 4, c = tid & 15;
+    double x[16];
+    if (g < P) {
+      const double* Lb = pk_blk(T, g, g);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        double s = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int m = 0; m < r; ++m) s = fma(-Lb[r + PK_LD * m], x[m], s);
+        x[r] = s * rd[16 * g + r];
+      }
+    }
+    __syncthreads();
+    if (g < P) {
+      double* Xb = pk_blk(T, g, g);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) Xb[r + PK_LD * c] = x[r];
+    }
+    __syncthreads();
+  }
+  for (int p = P - 2; p >= 0; --p) {
+    const double* Xpp = pk_blk(T, p, p);
+    // Y_mp = L_mp X_pp, blocks m = p+1 .. P-1 over the waves (at most 2 each)
+    d4 y[2];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int m = p + 1 + w + 4 * s2;
+      y[s2] = d4{0.0, 0.0, 0.0, 0.0};
+      if (m < P) y[s2] = blk_mma16(y[s2], pk_blk(T, m, p), PK_LD, Xpp, PK_LD, false);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int m = p + 1 + w + 4 * s2;
+      if (m < P) blk_store(pk_blk(T, m, p), PK_LD, y[s2]);
+    }
+    __syncthreads();
+    // X_ip = -sum_{m=p+1..i} X_im Y_mp
+    d4 xi[2];
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int i = p + 1 + w + 4 * s2;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      if (i < P)
+        for (int m = p + 1; m <= i; ++m)
+          acc = blk_mma16(acc, pk_blk(T, i, m), PK_LD, pk_blk(T, m, p), PK_LD, false);
+      xi[s2] = -acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int i = p + 1 + w + 4 * s2;
+      if (i < P) blk_store(pk_blk(T, i, p), PK_LD, xi[s2]);
+    }
+    // the next column reads only blocks of columns < p and the finished
+    // blocks of rows > p-1: the barrier of its first phase orders them
+  }
+  __syncthreads();
+}
+
 // Outputs: the factor (Lout, may be null: not stored), its transpose (LcopyT,
 // may be null), the inverse of the factor (Xout) and its transpose (XoutT),
 // each with explicit zeros in the other triangle.  Only the first P blocks of
@@ -619,74 +773,70 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
   LcopyT = uniform_ptr(LcopyT);
   Xout = uniform_ptr(Xout);
   XoutT = uniform_ptr(XoutT);
-  constexpr int LD = POTRF_LD;
-  double* T = smem;                    // [NB * LD] the tile, column-major
-  double* XD = smem + NB * LD;         // [8][256] inverses of the diagonal blocks
-  double* SCR = XD + 8 * 256;          // [4][256] per-wave scratch block
-  int* flag = reinterpret_cast<int*>(SCR + 4 * 256);
-  const int tid = threadIdx.x, w = tid >> 6;
+  double* T = smem;                          // the 36 packed blocks
+  double* rd = smem + PK_BLOCKS * PK_STRIDE;  // reciprocal pivots
+  int* flag = reinterpret_cast<int*>(rd + NB);
+  const int tid = threadIdx.x;
   const rsrc_t rIn = tile_rsrc(Ain), rL = tile_rsrc(Lout ? Lout : Xout), rX = tile_rsrc(Xout),
                rXT = tile_rsrc(XoutT);
 
-  // load the tile: batches of independent 16-byte loads, so that their
-  // latencies overlap
-  for (int e0 = 0; e0 < NB * NB; e0 += 2 * NTHREADS * 16) {
-    d2 v[16];
+  // load the lower blocks, 16 x 16 each as 128 pairs of rows: all 18 pairs
+  // of a thread are issued before the first LDS write, so that their
+  // latencies overlap (a wave stays inside one block); entries above the
+  // diagonal of a diagonal block are zero
+  constexpr int NLD = PK_BLOCKS * 128 / NTHREADS;
+  d2 v[NLD];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = ld2(rIn, e0 + 2 * (tid + NTHREADS * u));
+  for (int u = 0; u < NLD; ++u) {
+    const int b = __builtin_amdgcn_readfirstlane((NTHREADS * u + tid) >> 7);
+    int bi = 0;
+    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+    const int bj = b - bi * (bi + 1) / 2;
+    const int e = 2 * (tid & 127);
+    v[u] = ld2(rIn, (16 * bi + (e & 15)) + NB * (16 * bj + (e >> 4)));
+  }
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int e = e0 + 2 * (tid + NTHREADS * u), rr = e & (NB - 1), cc = e >> 7;
-      T[rr + LD * cc] = (rr >= cc) ? v[u].x : 0.0;
-      T[rr + 1 + LD * cc] = (rr + 1 >= cc) ? v[u].y : 0.0;
-    }
+  for (int u = 0; u < NLD; ++u) {
+    const int b = __builtin_amdgcn_readfirstlane((NTHREADS * u + tid) >> 7);
+    int bi = 0;
+    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+    const bool diag = b == bi * (bi + 1) / 2 + bi;
+    const int e = 2 * (tid & 127), lr = e & 15, lc = e >> 4;
+    double* dst = T + PK_STRIDE * b + lr + PK_LD * lc;
+    dst[0] = (diag && lr < lc) ? 0.0 : v[u].x;
+    dst[1] = (diag && lr + 1 < lc) ? 0.0 : v[u].y;
   }
   __syncthreads();
 
-  const int ff = factor_lds(T, XD, SCR, flag, P);
+  const int ff = factor_packed(T, rd, flag, P);
   if (ff) return ff;
 
-  // the factor and its transpose, as contiguous 16-byte stores (the
-  // transpose is taken on the LDS side); skipped when nothing reads them
+  // element (r, c) of the packed lower triangle (zero above the diagonal)
+  auto pval = [&](int r, int c) -> double {
+    if (r < c) return 0.0;
+    return pk_blk(T, r >> 4, c >> 4)[(r & 15) + PK_LD * (c & 15)];
+  };
+  // the factor and its transpose, as contiguous 16-byte stores; skipped
+  // when nothing reads them
   const rsrc_t rLT = tile_rsrc(LcopyT ? LcopyT : Xout);
   if (Lout) {
 #pragma unroll 4
-  for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
-    const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
-    d2 v;
-    v.x = (rr >= cc) ? T[rr + LD * cc] : 0.0;
-    v.y = (rr + 1 >= cc) ? T[rr + 1 + LD * cc] : 0.0;
-    st2(rL, e, v);
-    if (LcopyT) {  // element (rr, cc) of L^T is L(cc, rr)
-      d2 u;
-      u.x = (cc >= rr) ? T[cc + LD * rr] : 0.0;
-      u.y = (cc >= rr + 1) ? T[cc + LD * (rr + 1)] : 0.0;
-      st2(rLT, e, u);
+    for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
+      const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
+      st2(rL, e, d2{pval(rr, cc), pval(rr + 1, cc)});
+      if (LcopyT) st2(rLT, e, d2{pval(cc, rr), pval(cc, rr + 1)});  // L^T(rr, cc) = L(cc, rr)
     }
   }
-  }
-  __syncthreads();  // the inverse below writes the upper blocks of T
+  __syncthreads();  // the inverse overwrites the factor
 
-  inverse_lds(T, XD, SCR, P);
-  __syncthreads();
-  // X and X^T as contiguous 16-byte stores: X(r, c) is XD for diagonal
-  // blocks, T(c, r) below them (stored transposed), zero above; the identity
-  // on the diagonal blocks past P (the padding)
-  auto xval = [&](int r, int c) -> double {
-    const int br = r >> 4, bc = c >> 4;
-    if (br == bc) return br < P ? XD[256 * br + (r & 15) + 16 * (c & 15)] : (r == c ? 1.0 : 0.0);
-    return (br > bc) ? T[c + LD * r] : 0.0;
-  };
+  inverse_packed(T, rd, P);
+  // X and X^T as contiguous 16-byte stores; the blocks past P (padding)
+  // still hold the identity block loaded with the tile
 #pragma unroll 4
   for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
     const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
-    d2 v, u;
-    v.x = xval(rr, cc);
-    v.y = xval(rr + 1, cc);
-    u.x = xval(cc, rr);
-    u.y = xval(cc, rr + 1);
-    st2(rX, e, v);
-    st2(rXT, e, u);
+    st2(rX, e, d2{pval(rr, cc), pval(rr + 1, cc)});
+    st2(rXT, e, d2{pval(cc, rr), pval(cc, rr + 1)});
   }
   return 0;
 }
