@@ -10,8 +10,12 @@
 namespace spdinv {
 namespace {
 
-__global__ __launch_bounds__(NTHREADS) void sched_kernel(SchedArgs g, int T, int tiles) {
-  __shared__ double smem[SMEM_DOUBLES];
+// Two workgroups per CU: a task needs at most TASK_SMEM doubles of LDS (half
+// the CU's) and 256 registers per lane, so that while one workgroup waits
+// (loads, barriers, dependencies) the other keeps the matrix cores busy.
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void sched_kernel(SchedArgs g, int T, int tiles) {
+  __shared__ double smem[TASK_SMEM];
   sched_loop(g, [&](const DevTask& t) { run_task(t, g, smem, T, tiles); });
 }
 
@@ -98,8 +102,15 @@ hipError_t launch_info_out(const int32_t* ctrl, int* d_info, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_sched(const SchedArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(sched_kernel, dim3(grid), dim3(NTHREADS), 0, s, a, a.tiles_T, a.tiles);
+// One workgroup per CU is enforced by asking for unused dynamic LDS, so that
+// a second one no longer fits (the hardware would otherwise be free to pair
+// two of the grid's workgroups on one CU and leave another CU idle).
+constexpr unsigned kSoloLdsPad = 8192;
+static_assert(TASK_SMEM * 8 + kSoloLdsPad > 80 * 1024, "the pad must exclude a second workgroup");
+
+hipError_t launch_sched(const SchedArgs& a, int grid, int per_cu, hipStream_t s) {
+  hipLaunchKernelGGL(sched_kernel, dim3(grid), dim3(NTHREADS), per_cu == 1 ? kSoloLdsPad : 0, s, a,
+                     a.tiles_T, a.tiles);
   return hipGetLastError();
 }
 

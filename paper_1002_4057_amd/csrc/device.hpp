@@ -86,7 +86,8 @@ hipError_t launch_copy_out(const double* pool, int t, double* A, int lda, int n,
 hipError_t launch_info_out(const int32_t* ctrl, int* d_info, hipStream_t s);
 
 // Persistent scheduler over the plan's tasks.
-hipError_t launch_sched(const SchedArgs& a, int grid, hipStream_t s);
+// per_cu: 1 keeps every workgroup alone on its CU, 2 lets two share one.
+hipError_t launch_sched(const SchedArgs& a, int grid, int per_cu, hipStream_t s);
 
 // Persistent workgroups per CU that fit for the scheduler kernel.
 int sched_blocks_per_cu();

@@ -78,28 +78,34 @@ __device__ __forceinline__ void st1(rsrc_t r, int elem, double v) {
 // mask treats X as lower triangular (entries above its diagonal read as 0).
 // Each thread moves PAIRS pairs of doubles per panel with 16-byte loads.
 // ---------------------------------------------------------------------------
-template <int CP = CPOL_AGENT>
-__device__ __forceinline__ void panel_load(rsrc_t X, int k0, bool contig, d2 (&r)[PAIRS]) {
+// KD is the panel depth (KC unless a caller stages shallower panels).
+template <int KD>
+constexpr int panel_pairs() { return NB * KD / 2 / NTHREADS; }
+
+template <int CP = CPOL_AGENT, int KD = KC>
+__device__ __forceinline__ void panel_load(rsrc_t X, int k0, bool contig,
+                                           d2 (&r)[panel_pairs<KD>()]) {
   const int tid = threadIdx.x;
   if (contig) {
 #pragma unroll
-    for (int q = 0; q < PAIRS; ++q) r[q] = ld2<CP>(X, NB * k0 + 2 * (tid + NTHREADS * q));
+    for (int q = 0; q < panel_pairs<KD>(); ++q) r[q] = ld2<CP>(X, NB * k0 + 2 * (tid + NTHREADS * q));
   } else {
 #pragma unroll
-    for (int q = 0; q < PAIRS; ++q) {
+    for (int q = 0; q < panel_pairs<KD>(); ++q) {
       const int p = tid + NTHREADS * q;
-      const int rr = p / (KC / 2), kk = (p % (KC / 2)) * 2;
+      const int rr = p / (KD / 2), kk = (p % (KD / 2)) * 2;
       r[q] = ld2<CP>(X, k0 + kk + NB * rr);
     }
   }
 }
 
+template <int KD = KC>
 __device__ __forceinline__ void panel_store(double* __restrict__ S, int k0, bool contig, bool mask,
-                                            const d2 (&r)[PAIRS]) {
+                                            const d2 (&r)[panel_pairs<KD>()]) {
   const int tid = threadIdx.x;
   if (contig) {
 #pragma unroll
-    for (int q = 0; q < PAIRS; ++q) {
+    for (int q = 0; q < panel_pairs<KD>(); ++q) {
       const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), kk = e >> 7;
       d2 v = r[q];
       // stored element (row rr+s, col k0+kk); lower triangle keeps row >= col
@@ -111,9 +117,9 @@ __device__ __forceinline__ void panel_store(double* __restrict__ S, int k0, bool
     }
   } else {
 #pragma unroll
-    for (int q = 0; q < PAIRS; ++q) {
+    for (int q = 0; q < panel_pairs<KD>(); ++q) {
       const int p = tid + NTHREADS * q;
-      const int rr = p / (KC / 2), kk = (p % (KC / 2)) * 2;
+      const int rr = p / (KD / 2), kk = (p % (KD / 2)) * 2;
       double v0 = r[q].x, v1 = r[q].y;
       // stored element (row k0+kk+s, col rr)
       if (mask) {
@@ -234,6 +240,53 @@ __device__ __forceinline__ void mma_chain(Acc& acc, int count, PairFn pair, doub
     pa = qa;
     pb = qb;
   }
+}
+
+// Accumulator (i, j), register r of this lane holds tile element
+// acc_lane_base() + 16 i + NB (16 j + 4 r).  The loads and stores below keep
+// only the per-lane part in a register (made opaque at every call, so that
+// the compiler recomputes it instead of keeping 64 addresses live across a
+// persistent loop) and pass the rest as the instruction's immediate and
+// scalar offsets.
+__device__ __forceinline__ int opaque_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+__device__ __forceinline__ int acc_lane_bytes() {
+  const int t = opaque_tid(), lane = t & 63, w = t >> 6;
+  return 8 * (((w & 1) * 64 + (lane & 15)) + NB * ((w >> 1) * 64 + (lane >> 4)));
+}
+
+template <int CP = CPOL_AGENT>
+__device__ __forceinline__ void acc_load(rsrc_t r, d4 (&acc)[4][4], bool neg) {
+  const int vb = acc_lane_bytes();
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double x = __builtin_bit_cast(
+            double, __builtin_amdgcn_raw_buffer_load_b64(r, vb + 128 * i, 8 * NB * (16 * j + 4 * q), CP));
+        acc[i][j][q] = neg ? -x : x;
+      }
+}
+
+template <int CP = CPOL_AGENT>
+__device__ __forceinline__ void acc_store_tile(rsrc_t r, const d4 (&acc)[4][4], bool neg) {
+  const int vb = acc_lane_bytes();
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double x = neg ? -acc[i][j][q] : acc[i][j][q];
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, x), r, vb + 128 * i,
+                                              8 * NB * (16 * j + 4 * q), CP);
+      }
 }
 
 // C <- s * acc for one output tile (s = +1 or -1, exact); `lower` skips the

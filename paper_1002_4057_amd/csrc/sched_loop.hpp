@@ -23,8 +23,8 @@ using tile::stores_complete;
 //    stores drain (its readiness is tested only after the current task has
 //    released its successors, so a claimed task that depends on the current
 //    one cannot block it);
-//  - thread 0 fetches the task descriptor together with the in-degree poll
-//    and hands it to the workgroup through LDS;
+//  - thread 0 fetches the task descriptor together with the first
+//    in-degree poll and hands it to the workgroup through LDS;
 //  - the successor ids are loaded when the task starts, one per thread, so
 //    that at its end (once every thread's stores have completed) the threads
 //    release the successors with parallel in-degree decrements.
@@ -36,7 +36,8 @@ template <class Run>
 __device__ __forceinline__ void sched_loop(const SchedArgs& g, Run run) {
   __shared__ int s_task;
   __shared__ int s_skip;
-  __shared__ DevTask s_desc;
+  __shared__ __attribute__((aligned(16))) DevTask s_desc;
+  static_assert(sizeof(DevTask) == 32, "the descriptor moves as two 16-byte vectors");
   int prev = -1;   // meaningful in thread 0 only
   int claim = -1;  // thread 0: ticket claimed during the previous task (or -1)
   long long t_claim = 0;
@@ -54,11 +55,22 @@ __device__ __forceinline__ void sched_loop(const SchedArgs& g, Run run) {
       int v = claim < g.ntask ? claim : -1;
       claim = -1;
       if (v >= 0) {
-        const DevTask d = g.tasks[v];  // in flight during the poll
+        // the descriptor and the first in-degree poll are in flight
+        // together; the descriptor goes to LDS as soon as it arrives (every
+        // thread copied the previous one two barriers ago), so that it is
+        // not held in registers across the wait
+        // (moved as two 16-byte vectors: a struct copy would go through
+        // private memory)
+        typedef int i4v __attribute__((ext_vector_type(4)));
+        const i4v* src = reinterpret_cast<const i4v*>(g.tasks + v);
+        const i4v d0 = src[0], d1 = src[1];
+        int deg = __hip_atomic_load(&g.indeg[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        reinterpret_cast<i4v*>(&s_desc)[0] = d0;
+        reinterpret_cast<i4v*>(&s_desc)[1] = d1;
         // bounded wait: gives up after spin_limit ticks of the 100 MHz clock
         const long long t0 = now_ticks();
         long long spins = 0;
-        while (__hip_atomic_load(&g.indeg[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > 0) {
+        while (deg > 0) {
           __builtin_amdgcn_s_sleep(1);
           if ((++spins & 63) == 0) {
             if (__hip_atomic_load(&g.ctrl[CTRL_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
@@ -71,8 +83,8 @@ __device__ __forceinline__ void sched_loop(const SchedArgs& g, Run run) {
               break;
             }
           }
+          deg = __hip_atomic_load(&g.indeg[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        s_desc = d;
       }
       if (v >= 0) {
         if (g.trace) {

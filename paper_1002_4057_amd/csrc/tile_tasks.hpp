@@ -26,8 +26,77 @@ namespace {
 
 using namespace tile;
 
+// The scheduler's tile products stage 16-deep k-panels (8 per tile): the
+// two double-buffered operand panels take 66.6 KB of LDS, the renaming copy
+// is staged half a tile at a time (66 KB) and the diagonal-tile task keeps
+// only the lower 16 x 16 blocks (77.6 KB), so that a task needs at most
+// TASK_SMEM doubles (under 80 KB: two workgroups per CU).
+constexpr int SKC = 16;
+constexpr int SNCH = NB / SKC;
+constexpr int SPAIRS = panel_pairs<SKC>();
+constexpr int SPANEL = SKC * LDS_STRIDE;
+constexpr int SGEMM_SMEM = 4 * SPANEL;
+constexpr int RLD = NB + 1;            // row stride of a staged copy
+constexpr int COPY_SMEM = 64 * RLD;    // half a tile
+constexpr int PK_LD = 17;              // packed diagonal tile, see pk_blk
+constexpr int PK_STRIDE = 16 * PK_LD;
+constexpr int PK_BLOCKS = 8 * 9 / 2;
+constexpr int PK_SMEM = PK_BLOCKS * PK_STRIDE + NB + 8;  // blocks + reciprocal pivots + flag
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int TASK_SMEM = cmax(cmax(SGEMM_SMEM, COPY_SMEM), PK_SMEM);
+static_assert(TASK_SMEM * 8 <= 80 * 1024, "a task must fit half of the CU's LDS");
+
+// The full-tile diagonal helpers (factor_lds, inverse_lds) of the batched
+// small matrices and the mixed form, and the kernels that run them
 constexpr int POTRF_SMEM = NB * (NB + 1) + 12 * 256 + 8;  // tile + diagonal inverses + scratch
-constexpr int SMEM_DOUBLES = GEMM_SMEM > POTRF_SMEM ? GEMM_SMEM : POTRF_SMEM;
+constexpr int SMEM_DOUBLES = cmax(cmax(GEMM_SMEM, POTRF_SMEM), TASK_SMEM);
+
+// Renaming copy of a product's result (as is, or transposed with copy_t):
+// the result is staged in LDS one half of its rows at a time, as
+// R[col + RLD * row] (odd stride RLD, conflict-free for these writes), and
+// leaves as contiguous 16-byte stores.  The caller's k-loop has ended with a
+// barrier, so smem is free.
+__device__ __forceinline__ void copy_epilogue(double* copy, const d4 (&acc)[4][4], bool neg,
+                                              bool copy_t, double* smem) {
+  const int tid = opaque_tid(), lane = tid & 63, w = tid >> 6;
+  const int wm = w & 1, wn = w >> 1, lr = lane & 15, lk = lane >> 4;
+  const rsrc_t rD = tile_rsrc(copy);
+  double* R = smem;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (wm == h) {  // the waves holding result rows 64h .. 64h+63
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int row = i * 16 + lr, col0 = wn * 64 + j * 16 + lk;
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            R[(col0 + 4 * r) + RLD * row] = neg ? -acc[i][j][r] : acc[i][j][r];
+        }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int q = 0; q < NB * 64 / 2 / NTHREADS; ++q) {
+      const int e2 = 2 * (tid + NTHREADS * q);
+      d2 v;
+      int e;
+      if (copy_t) {  // copy(rr, 64h + cl) = result(64h + cl, rr): copy columns of this half
+        const int rr = e2 & (NB - 1), cl = e2 >> 7;
+        v.x = R[rr + RLD * cl];
+        v.y = R[rr + 1 + RLD * cl];
+        e = rr + NB * (64 * h + cl);
+      } else {       // copy(64h + rl, cc) = result(64h + rl, cc): copy rows of this half
+        const int rl = e2 & 63, cc = e2 >> 6;
+        v.x = R[cc + RLD * rl];
+        v.y = R[cc + RLD * (rl + 1)];
+        e = 64 * h + rl + NB * cc;
+      }
+      st2(rD, e, v);
+    }
+    if (h == 0) __syncthreads();  // half 1 overwrites R
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Tile product on the FP64 matrix cores.
@@ -40,7 +109,7 @@ constexpr int SMEM_DOUBLES = GEMM_SMEM > POTRF_SMEM ? GEMM_SMEM : POTRF_SMEM;
 // not store: it runs alone on its SIMD, so skipping its work would save no
 // time).  C may alias A or B: every operand read precedes the first store.
 // copy (may be null) receives the same result, transposed with F_COPYT.
-// npan: k-panels to run (fewer than NCH skips the padded tail of a ragged
+// npan: k-panels to run (fewer than SNCH skips the padded tail of a ragged
 // last tile block, see K_KLAST).
 // Waves form a 2 x 2 grid of 64 x 64 output blocks, each a 4 x 4 array of
 // 16 x 16 MFMA accumulators.  The sign is handled without touching the
@@ -54,7 +123,7 @@ constexpr int SMEM_DOUBLES = GEMM_SMEM > POTRF_SMEM ? GEMM_SMEM : POTRF_SMEM;
 template <bool FAST>
 __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, const double* B,
                                          double* copy, double* smem, bool nca = false,
-                                         bool ncb = false, int npan = NCH) {
+                                         bool ncb = false, int npan = SNCH) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int wm = w & 1, wn = w >> 1;
@@ -76,20 +145,7 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
   // covers 16 consecutive rows of one column (one 128-byte segment).
   d4 acc[4][4];
   if (accum) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int off = (wm * 64 + i * 16 + lr) + NB * (wn * 64 + j * 16 + lk);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[i][j][r] = ld1(rC, off + NB * 4 * r);
-      }
-    if (neg) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = -acc[i][j];
-    }
+    acc_load(rC, acc, neg);
   } else {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -97,35 +153,35 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
       for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
   }
 
-  d2 ra[PAIRS], rb[PAIRS];
+  d2 ra[SPAIRS], rb[SPAIRS];
   // operand panels: through the L2 when the planner allows it for this read
   // (nca / ncb), device-coherent otherwise
   auto load_a = [&](int k0) {
-    if (nca) panel_load<0>(rA, k0, a_contig, ra);
-    else panel_load<CPOL_AGENT>(rA, k0, a_contig, ra);
+    if (nca) panel_load<0, SKC>(rA, k0, a_contig, ra);
+    else panel_load<CPOL_AGENT, SKC>(rA, k0, a_contig, ra);
   };
   auto load_b = [&](int k0) {
-    if (ncb) panel_load<0>(rB, k0, b_contig, rb);
-    else panel_load<CPOL_AGENT>(rB, k0, b_contig, rb);
+    if (ncb) panel_load<0, SKC>(rB, k0, b_contig, rb);
+    else panel_load<CPOL_AGENT, SKC>(rB, k0, b_contig, rb);
   };
   load_a(0);
   load_b(0);
-  panel_store(smem, 0, a_contig, ma, ra);
-  panel_store(smem + PANEL, 0, b_contig, mb, rb);
+  panel_store<SKC>(smem, 0, a_contig, ma, ra);
+  panel_store<SKC>(smem + SPANEL, 0, b_contig, mb, rb);
   __syncthreads();
 
 #pragma unroll 1
   for (int c = 0; c < npan; ++c) {
-    const double* As = smem + (c & 1) * 2 * PANEL;
-    const double* Bs = As + PANEL;
+    const double* As = smem + (c & 1) * 2 * SPANEL;
+    const double* Bs = As + SPANEL;
     const bool more = c + 1 < npan;
     if (more) {
-      load_a((c + 1) * KC);
-      load_b((c + 1) * KC);
+      load_a((c + 1) * SKC);
+      load_b((c + 1) * SKC);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int ks = 0; ks < KC / 4; ++ks) {
+    for (int ks = 0; ks < SKC / 4; ++ks) {
       const double* Ar = As + (4 * ks + lk) * LDS_STRIDE + wm * 64 + lr;
       const double* Br = Bs + (4 * ks + lk) * LDS_STRIDE + wn * 64 + lr;
       double a[4], b[4];
@@ -142,53 +198,16 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
     }
     __builtin_amdgcn_sched_barrier(0);
     if (more) {
-      double* An = smem + ((c + 1) & 1) * 2 * PANEL;
-      panel_store(An, (c + 1) * KC, a_contig, ma, ra);
-      panel_store(An + PANEL, (c + 1) * KC, b_contig, mb, rb);
+      double* An = smem + ((c + 1) & 1) * 2 * SPANEL;
+      panel_store<SKC>(An, (c + 1) * SKC, a_contig, ma, ra);
+      panel_store<SKC>(An + SPANEL, (c + 1) * SKC, b_contig, mb, rb);
     }
     __syncthreads();
   }
 
-  if (active) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int off = (wm * 64 + i * 16 + lr) + NB * (wn * 64 + j * 16 + lk);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) st1(rC, off + NB * 4 * r, neg ? -acc[i][j][r] : acc[i][j][r]);
-      }
-  }
+  if (active) acc_store_tile(rC, acc, neg);
   if (!copy) return;  // uniform: the copy pointer is the same in every thread
-  // renaming copy (as is, or transposed with F_COPYT): the result is staged
-  // in LDS as R[col + RLD * row] (odd stride RLD, conflict-free for these
-  // writes), then leaves as contiguous 16-byte stores; the panels are no
-  // longer in use after the k-loop's last barrier
-  constexpr int RLD = NB + 1;
-  double* R = smem;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = wm * 64 + i * 16 + lr, col0 = wn * 64 + j * 16 + lk;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) R[(col0 + 4 * r) + RLD * row] = neg ? -acc[i][j][r] : acc[i][j][r];
-    }
-  __syncthreads();
-  const rsrc_t rD = tile_rsrc(copy);
-#pragma unroll 4
-  for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
-    const int e = 2 * (threadIdx.x + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
-    d2 v;  // copy element (rr, cc) is result(cc, rr) or result(rr, cc)
-    if (copy_t) {
-      v.x = R[rr + RLD * cc];
-      v.y = R[rr + 1 + RLD * cc];
-    } else {
-      v.x = R[cc + RLD * rr];
-      v.y = R[cc + RLD * (rr + 1)];
-    }
-    st2(rD, e, v);
-  }
+  copy_epilogue(copy, acc, neg, copy_t, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -197,14 +216,14 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
 // (op(A) = A, op(B) = B^T for every link; flags as in tile_mma).  Link 0 is
 // (A, B); link p >= 1 reads the tiles named by links[2(p-1)] and
 // links[2(p-1)+1].  Link 0 runs npan0 k-panels, a link marked LINK_KLAST
-// npan_last, any other NCH (see K_KLAST).  The accumulator starts from +-C
+// npan_last, any other SNCH (see K_KLAST).  The accumulator starts from +-C
 // and takes the links' products in order, k-panel by k-panel, so every rounding is that of the
 // separate tasks (whose stores and reloads of the intermediate tile are
 // exact); C is read and written once.  The k-panels of all links form one
 // double-buffered stream through LDS, and each panel's body is a single
-// scheduling region in which the next panel's global loads (k-steps 0-1) and
-// their staging into LDS (k-steps 6-7) are interleaved with the MFMAs: a
-// wave issues in order, and issuing the 16 loads of a panel at once kept the
+// scheduling region in which the next panel's global loads (first k-step)
+// and their staging into LDS (last k-step) are interleaved with the MFMAs: a
+// wave issues in order, and issuing all loads of a panel at once kept the
 // matrix cores idle for about half a microsecond per panel.  For that the
 // body has no branch: past the last panel the loads read a zero-size buffer
 // (they return zeros without touching memory), and every operand read is
@@ -241,20 +260,7 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
 
   d4 acc[4][4];
   if (accum) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int off = (wm * 64 + i * 16 + lr) + NB * (wn * 64 + j * 16 + lk);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[i][j][r] = ld1(rC, off + NB * 4 * r);
-      }
-    if (neg) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = -acc[i][j];
-    }
+    acc_load(rC, acc, neg);
   } else {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -262,7 +268,7 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
       for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
   }
 
-  d2 ra[PAIRS], rb[PAIRS];
+  d2 ra[SPAIRS], rb[SPAIRS];
   // The link table is read one link ahead: the entries of link p+1 are
   // loaded at the head of link p-1, so that turning them into scalars at
   // the head of link p waits for nothing (a load issued there and used at
@@ -278,10 +284,10 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
   }
   const rsrc_t none = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(A), 0, 0, RSRC_WORD3);
   rsrc_t cA = tile_rsrc(A), cB = tile_rsrc(B);
-  panel_load(cA, 0, true, ra);
-  panel_load(cB, 0, true, rb);
-  panel_store(smem, 0, true, false, ra);
-  panel_store(smem + PANEL, 0, true, false, rb);
+  panel_load<CPOL_AGENT, SKC>(cA, 0, true, ra);
+  panel_load<CPOL_AGENT, SKC>(cB, 0, true, rb);
+  panel_store<SKC>(smem, 0, true, false, ra);
+  panel_store<SKC>(smem + SPANEL, 0, true, false, rb);
   __syncthreads();
 
   // panels run by link p (npan) and by link p+1 (nnext); gp counts panels
@@ -291,13 +297,13 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
   for (int p = 0; p <= nlink; ++p) {
     const bool last = p == nlink;
     rsrc_t nA = none, nB = none;
-    int nnext = NCH;
+    int nnext = SNCH;
     if (!last) {  // operands of link p+1, then the table entries of link p+2
       const int va = __builtin_amdgcn_readfirstlane(qa);
       const int vb = __builtin_amdgcn_readfirstlane(qb);
       nA = tile_rsrc(tile_ptr(pool, va & ~LINK_KLAST));
       nB = tile_rsrc(tile_ptr(pool, vb));
-      nnext = (va & LINK_KLAST) ? npan_last : NCH;
+      nnext = (va & LINK_KLAST) ? npan_last : SNCH;
       if (p + 2 <= nlink) {
         qa = LT[2 * (p + 1)];
         qb = LT[2 * (p + 1) + 1];
@@ -305,16 +311,16 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
     }
 #pragma unroll 1
     for (int c = 0; c < npan; ++c, ++gp) {
-      const double* As = smem + (gp & 1) * 2 * PANEL;
-      const double* Bs = As + PANEL;
-      double* An = smem + ((gp + 1) & 1) * 2 * PANEL;
+      const double* As = smem + (gp & 1) * 2 * SPANEL;
+      const double* Bs = As + SPANEL;
+      double* An = smem + ((gp + 1) & 1) * 2 * SPANEL;
       const bool wrap = c + 1 == npan;
       const rsrc_t sA = wrap ? nA : cA, sB = wrap ? nB : cB;
-      const int k0 = wrap ? 0 : (c + 1) * KC;
-      panel_load(sA, k0, true, ra);
-      panel_load(sB, k0, true, rb);
+      const int k0 = wrap ? 0 : (c + 1) * SKC;
+      panel_load<CPOL_AGENT, SKC>(sA, k0, true, ra);
+      panel_load<CPOL_AGENT, SKC>(sB, k0, true, rb);
 #pragma unroll
-      for (int ks = 0; ks < KC / 4; ++ks) {
+      for (int ks = 0; ks < SKC / 4; ++ks) {
         const double* Ar = As + (4 * ks + lk) * LDS_STRIDE + wm * 64 + lr;
         const double* Br = Bs + (4 * ks + lk) * LDS_STRIDE + wn * 64 + lr;
         double a[4], b[4];
@@ -330,18 +336,18 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
       }
       // the next panel's buffer was released by the previous barrier
-      panel_store(An, 0, true, false, ra);
-      panel_store(An + PANEL, 0, true, false, rb);
+      panel_store<SKC>(An, 0, true, false, ra);
+      panel_store<SKC>(An + SPANEL, 0, true, false, rb);
       // order of the region: the operands of k-step 0, then per k-step half
-      // of its MFMAs, its share of the loads (k-steps 0-1) or LDS stores
-      // (k-steps 6-7), the next k-step's operands, the other half
+      // of its MFMAs, the next panel's loads (k-step 0) or their LDS stores
+      // (last k-step), the next k-step's operands, the other half
       __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
 #pragma unroll
-      for (int ks = 0; ks < KC / 4; ++ks) {
+      for (int ks = 0; ks < SKC / 4; ++ks) {
         __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
-        if (ks < 2) __builtin_amdgcn_sched_group_barrier(0x020, 8, 0);
-        if (ks >= 6) __builtin_amdgcn_sched_group_barrier(0x200, 8, 0);
-        if (ks + 1 < KC / 4) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+        if (ks == 0) __builtin_amdgcn_sched_group_barrier(0x020, 8, 0);
+        if (ks == SKC / 4 - 1) __builtin_amdgcn_sched_group_barrier(0x200, 8, 0);
+        if (ks + 1 < SKC / 4) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
         __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
       }
       __syncthreads();
@@ -351,42 +357,9 @@ __device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const
     npan = nnext;
   }
 
-  if (active) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int off = (wm * 64 + i * 16 + lr) + NB * (wn * 64 + j * 16 + lk);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) st1(rC, off + NB * 4 * r, neg ? -acc[i][j][r] : acc[i][j][r]);
-      }
-  }
+  if (active) acc_store_tile(rC, acc, neg);
   if (!copy) return;  // uniform
-  constexpr int RLD = NB + 1;
-  double* R = smem;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = wm * 64 + i * 16 + lr, col0 = wn * 64 + j * 16 + lk;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) R[(col0 + 4 * r) + RLD * row] = neg ? -acc[i][j][r] : acc[i][j][r];
-    }
-  __syncthreads();
-  const rsrc_t rD = tile_rsrc(copy);
-#pragma unroll 4
-  for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
-    const int e = 2 * (threadIdx.x + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
-    d2 v;
-    if (copy_t) {
-      v.x = R[rr + RLD * cc];
-      v.y = R[rr + 1 + RLD * cc];
-    } else {
-      v.x = R[cc + RLD * rr];
-      v.y = R[cc + RLD * (rr + 1)];
-    }
-    st2(rD, e, v);
-  }
+  copy_epilogue(copy, acc, neg, copy_t, smem);
 }
 
 // The general product (transposed or triangular operands) serves only the
@@ -610,11 +583,6 @@ __device__ __forceinline__ void inverse_lds(double* T, const double* XD, double*
 // over the banks).  77.6 KB with the pivots, so that the scheduler's
 // workgroups fit two per CU.
 // ---------------------------------------------------------------------------
-constexpr int PK_LD = 17;
-constexpr int PK_STRIDE = 16 * PK_LD;
-constexpr int PK_BLOCKS = 8 * 9 / 2;
-constexpr int PK_SMEM = PK_BLOCKS * PK_STRIDE + NB + 8;  // blocks + reciprocal pivots + flag
-static_assert(PK_SMEM <= SMEM_DOUBLES, "packed diagonal tile exceeds the workgroup's LDS");
 static_assert(PK_BLOCKS * 128 % NTHREADS == 0, "packed load assumes whole passes");
 
 __device__ __forceinline__ double* pk_blk(double* T, int i, int p) {
@@ -874,8 +842,8 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
         const bool nca = !g.coherent_only && (t.kind & K_NC_A) != 0;
         const bool ncb = !g.coherent_only && (t.kind & K_NC_B) != 0;
         // k-panels of a product over the (possibly ragged) last tile block
-        const int npan_last = (g.last_valid + KC - 1) / KC;
-        const int npan = (t.kind & K_KLAST) ? npan_last : NCH;
+        const int npan_last = (g.last_valid + SKC - 1) / SKC;
+        const int npan = (t.kind & K_KLAST) ? npan_last : SNCH;
         if (nl)
           tile_mma_chain(f, out, a, b, cp, smem, g.links + 2 * t.aux, nl, P, npan, npan_last);
         else

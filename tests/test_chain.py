@@ -161,11 +161,12 @@ def test_chains_form_where_operands_are_ready_early(t, workers):
     assert nl[step3].sum() > 0.5 * step3.sum()
 
 
-def test_chain_option_range_checked():
+@pytest.mark.parametrize("bad", [dict(chain=17), dict(chain=-1), dict(per_cu=3), dict(per_cu=-1)])
+def test_chain_and_per_cu_options_range_checked(bad):
     import ctypes
     from paper_1002_4057_amd import _lib
     lib = spd._lib.load()
-    o = _lib.make_opts(chain=17)
+    o = _lib.make_opts(**bad)
     assert lib.spd_inverse(4, ctypes.c_void_p(8), 4, 0, None, 0, None, ctypes.byref(o), None,
                            None) < 0
 

@@ -271,6 +271,24 @@ def test_bench_size_chained_tasks_bit_identical_to_paper_tasks():
     assert torch.equal(x_chain, x_paper)
 
 
+@pytest.mark.parametrize("n", [300, 2000, 4096 + 1])
+def test_two_workgroups_per_cu_bit_identical(n):
+    """The scheduler's kernel fits two workgroups on a CU (80 KB of LDS, 256
+    registers per lane).  Twice the workers, each sharing its CU, compute the
+    same products in the same order: the result is bit-identical to one
+    workgroup per CU, and the grid has the size asked for."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    a = inputs.spectrum(n, 1e3, seed=5, device=DEV)
+    x1, r1 = spd.spd_inverse(a, per_cu=1, return_report=True)
+    x2, r2 = spd.spd_inverse(a, per_cu=2, return_report=True)
+    assert r1["workers"] == cus and r2["workers"] == 2 * cus
+    assert r1["info"] == 0 and r2["info"] == 0
+    assert torch.equal(x1, x2)
+    ref = oracle.spd_inverse(a.cpu().numpy()) if n <= 300 else None
+    if ref is not None:
+        assert rel_fro(x2.cpu().numpy(), ref) <= 1e-12 * 1e3
+
+
 @pytest.mark.parametrize("n", [8192 - 100, 4096 + 1])
 def test_ragged_large_orders_against_analytic_inverse(n):
     """Ragged orders at scale (last tile block with 28 and 1 valid rows): the
