@@ -230,11 +230,11 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
 // device-coherent (the cache policy is an immediate of the instruction, so
 // L2-cacheable marks would need a branch; the planner sets none on chained
 // tasks).  Two rolled
-// loops (links, then panels) keep the accumulator in the matrix-core
-// registers; out of line, so that the single product's register allocation
-// is left as it is.
+// loops (links, then panels) keep the accumulator in registers for the whole
+// chain.  Inlined into the scheduler: as an out-of-line call it saved and
+// restored 77 callee-saved registers through scratch memory on every task.
 // ---------------------------------------------------------------------------
-__device__ __attribute__((noinline)) void tile_mma_chain(int f, double* C, const double* A,
+__device__ __forceinline__ void tile_mma_chain(int f, double* C, const double* A,
                                                          const double* B, double* copy,
                                                          double* smem, const int32_t* links,
                                                          int nlink, double* pool, int npan0,
