@@ -13,9 +13,9 @@ namespace {
 // order (largest first, so that the tail of the launch holds the small
 // ones); each workgroup then claims one matrix at a time and inverts it on
 // its own, with no synchronization between workgroups:
-//   n <= NB: the whole matrix in LDS -- the blocked factorization and inverse
-//            of the diagonal-tile task over ceil(n/16) panels only, then
-//            Y = X^T X from 16 x 16 MFMA blocks;
+//   n <= NB: the whole matrix in LDS -- the packed blocked factorization and
+//            in-place inverse of the diagonal-tile task over ceil(n/16)
+//            blocks only, then Y = X^T X from 16 x 16 MFMA blocks;
 //   n >  NB: the tile plan for t = ceil(n/NB) tiles executed in program order
 //            (the sequential task stream of Algorithm 1, renamed by default)
 //            by the scheduler's own tile tasks, on the workgroup's private
@@ -27,7 +27,7 @@ namespace {
 // when tb (or B[k + ldb*n]).
 __device__ __forceinline__ d4 blk_mma16x(d4 acc, const double* A, int lda, bool ta, const double* B,
                                          int ldb, bool tb) {
-  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  const int lane = opaque_tid() & 63, lr = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int k = 4 * kk + lk;
@@ -41,53 +41,66 @@ __device__ __forceinline__ d4 blk_mma16x(d4 acc, const double* A, int lda, bool 
 // Lower triangle of A (column-major, lda, 1 <= n <= NB) <- lower triangle of
 // A^{-1} (and the strictly upper triangle <- its mirror when fill_upper).
 // Returns 0 or INFO (1-based index of the first non-positive pivot; A is then
-// left unchanged).  Padding to 16 * ceil(n/16) with the identity.
+// left unchanged).  The matrix, padded to 16 * ceil(n/16) with the identity,
+// is held as the packed lower 16 x 16 blocks of the diagonal-tile task
+// (factor_packed, then inverse_packed leave X = L^{-1} in place); then
+// Y = X^T X, Y_IJ = sum_{K >= I} X_KI^T X_KJ for I >= J, is formed in
+// registers (at most 9 blocks per wave) and written to A from there.
 __device__ int small_inverse(double* A, int lda, int n, int fill_upper, double* smem) {
-  constexpr int LD = POTRF_LD;
   double* T = smem;
-  double* XD = smem + NB * LD;
-  double* SCR = XD + 8 * 256;
-  int* flag = reinterpret_cast<int*>(SCR + 4 * 256);
-  const int tid = threadIdx.x, w = tid >> 6;
-  const int P = (n + 15) >> 4, np = 16 * P;
-  for (int e = tid; e < np * np; e += NTHREADS) {
-    const int r = e % np, c = e / np;
+  double* rd = smem + PK_BLOCKS * PK_STRIDE;
+  int* flag = reinterpret_cast<int*>(rd + NB);
+  const int tid = opaque_tid(), w = tid >> 6;
+  const int P = (n + 15) >> 4;
+  const int nblk = P * (P + 1) / 2;
+  for (int e = tid; e < nblk * 256; e += NTHREADS) {
+    const int b = e >> 8, lr = e & 15, lc = (e >> 4) & 15;
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= b) ++I;
+    const int J = b - I * (I + 1) / 2;
+    const int r = 16 * I + lr, c = 16 * J + lc;
     double v;
     if (r < n && c < n)
       v = (r >= c) ? A[r + (size_t)lda * c] : 0.0;
     else
       v = (r == c) ? 1.0 : 0.0;
-    T[r + LD * c] = v;
+    T[PK_STRIDE * b + lr + PK_LD * lc] = v;
   }
   __syncthreads();
-  const int f = factor_lds(T, XD, SCR, flag, P);
+  const int f = factor_packed(T, rd, flag, P);
   if (f) return f;
-  inverse_lds(T, XD, SCR, P);
-  __syncthreads();
-  // Y_IJ = sum_{K >= I} X_KI^T X_KJ for I >= J.  X_KK is in XD; X_KI (K > I)
-  // is stored transposed in the upper block (I, K) of T.  Only upper blocks
-  // and XD are read, so Y goes straight into the lower blocks.
-  const int nblk = P * (P + 1) / 2;
-  for (int q = w; q < nblk; q += 4) {
+  inverse_packed(T, rd, P);
+  constexpr int PER_WAVE = (PK_BLOCKS + 3) / 4;
+  d4 y[PER_WAVE];
+#pragma unroll
+  for (int s2 = 0; s2 < PER_WAVE; ++s2) {
+    const int q = w + 4 * s2;
+    y[s2] = d4{0.0, 0.0, 0.0, 0.0};
+    if (q < nblk) {
+      int I = 0;
+      while ((I + 1) * (I + 2) / 2 <= q) ++I;
+      const int J = q - I * (I + 1) / 2;
+      for (int K = I; K < P; ++K)  // X_KI^T X_KJ
+        y[s2] = blk_mma16x(y[s2], pk_blk(T, K, I), PK_LD, true, pk_blk(T, K, J), PK_LD, false);
+    }
+  }
+  // lane l, register q of block (I, J) holds Y(16 I + l % 16, 16 J + l / 16 + 4 q)
+  const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int s2 = 0; s2 < PER_WAVE; ++s2) {
+    const int q = w + 4 * s2;
+    if (q >= nblk) continue;
     int I = 0;
     while ((I + 1) * (I + 2) / 2 <= q) ++I;
     const int J = q - I * (I + 1) / 2;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-    for (int K = I; K < P; ++K) {
-      const bool kd = K == I, jd = K == J;
-      const double* a = kd ? XD + 256 * I : T + 16 * I + LD * 16 * K;
-      const double* b = jd ? XD + 256 * J : T + 16 * J + LD * 16 * K;
-      acc = blk_mma16x(acc, a, kd ? 16 : LD, kd, b, jd ? 16 : LD, !jd);
-    }
-    blk_store(T + 16 * I + LD * 16 * J, LD, acc);
-  }
-  __syncthreads();
-  for (int e = tid; e < n * n; e += NTHREADS) {
-    const int r = e % n, c = e / n;
-    if (r >= c) {
-      const double v = T[r + LD * c];
-      A[r + (size_t)lda * c] = v;
-      if (fill_upper && r > c) A[c + (size_t)lda * r] = v;
+    const int r = 16 * I + lr;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = 16 * J + lk + 4 * u;
+      if (r < n && c <= r) {
+        A[r + (size_t)lda * c] = y[s2][u];
+        if (fill_upper && r > c) A[c + (size_t)lda * r] = y[s2][u];
+      }
     }
   }
   return 0;
@@ -186,8 +199,11 @@ __device__ __forceinline__ double* read_ptr_uniform(double* const* p) {
   return (double*)(((unsigned long long)hi << 32) | lo);
 }
 
-__global__ __launch_bounds__(NTHREADS) void batched_kernel(BatchArgs b) {
-  __shared__ double smem[SMEM_DOUBLES];
+// Two workgroups per CU: every path needs at most TASK_SMEM doubles of LDS
+// and 256 registers per lane, and the matrices of a batch are independent.
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void batched_kernel(BatchArgs b) {
+  __shared__ double smem[TASK_SMEM];
   __shared__ int s_m;
   double* pool = b.pool + (size_t)blockIdx.x * (size_t)b.pool_tiles * TILE;
   int32_t* ctrl = b.ctrl + blockIdx.x * CTRL_WORDS;

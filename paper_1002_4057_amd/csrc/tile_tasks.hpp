@@ -393,7 +393,7 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
 // the reciprocal pivots 1/L_kk to rd[0..15].  Returns 0 or the 1-based index
 // of the first non-positive (or NaN) pivot (uniform).
 __device__ __forceinline__ int chol16(double* S, int ld, double* rd) {
-  const int r = threadIdx.x & 15;
+  const int tid = opaque_tid(), r = tid & 15;
   double row[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) row[c] = (c <= r) ? S[r + ld * c] : 0.0;
@@ -407,7 +407,7 @@ __device__ __forceinline__ int chol16(double* S, int ld, double* rd) {
     const double h = d * rinv;
     rinv = fma(rinv * 0.5, fma(-h, rinv, 1.0), rinv);
     const double lkk = d * rinv;
-    if ((threadIdx.x & 63) == 0) rd[k] = rinv;
+    if ((tid & 63) == 0) rd[k] = rinv;
     // column k of L: scale below the pivot
     row[k] = (r > k) ? row[k] * rinv : ((r == k) ? lkk : row[k]);
     // right-looking update of the trailing rows with column k
@@ -417,7 +417,7 @@ __device__ __forceinline__ int chol16(double* S, int ld, double* rd) {
       if (c <= r) row[c] = fma(-row[k], lck, row[c]);
     }
   }
-  if ((threadIdx.x & 63) < 16) {
+  if ((tid & 63) < 16) {
 #pragma unroll
     for (int c = 0; c < 16; ++c) S[r + ld * c] = (c <= r) ? row[c] : 0.0;
   }
@@ -429,7 +429,7 @@ __device__ __forceinline__ int chol16(double* S, int ld, double* rd) {
 // block B^T of a column-major B) or B[k + ldb*n] (!tb).
 __device__ __forceinline__ d4 blk_mma16(d4 acc, const double* A, int lda, const double* B, int ldb,
                                         bool tb) {
-  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  const int lane = opaque_tid() & 63, lr = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int k = 4 * kk + lk;
@@ -441,12 +441,12 @@ __device__ __forceinline__ d4 blk_mma16(d4 acc, const double* A, int lda, const 
 }
 
 __device__ __forceinline__ d4 blk_load(const double* S, int ld) {
-  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  const int lane = opaque_tid() & 63, lr = lane & 15, lk = lane >> 4;
   return d4{S[lr + ld * lk], S[lr + ld * (lk + 4)], S[lr + ld * (lk + 8)], S[lr + ld * (lk + 12)]};
 }
 
 __device__ __forceinline__ void blk_store(double* S, int ld, d4 v) {
-  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  const int lane = opaque_tid() & 63, lr = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int q = 0; q < 4; ++q) S[lr + ld * (lk + 4 * q)] = v[q];
 }
@@ -596,7 +596,7 @@ __device__ __forceinline__ double* pk_blk(double* T, int i, int p) {
 // reciprocal pivots.  Returns 0 or the 1-based index of the first pivot that
 // is not positive (or NaN), uniform over the workgroup.
 __device__ __forceinline__ int factor_packed(double* T, double* rd, int* flag, int P) {
-  const int tid = threadIdx.x, w = tid >> 6;
+  const int tid = opaque_tid(), w = tid >> 6;
   if (w == 0) {
     const int f = chol16(pk_blk(T, 0, 0), PK_LD, rd);
     if (tid == 0) *flag = f;
@@ -663,7 +663,7 @@ __device__ __forceinline__ int factor_packed(double* T, double* rd, int* flag, i
 // of a column are formed in parallel over the waves and nothing else needs
 // LDS.
 __device__ __forceinline__ void inverse_packed(double* T, const double* rd, int P) {
-  const int tid = threadIdx.x, w = tid >> 6;
+  const int tid = opaque_tid(), w = tid >> 6;
   {
     const int g = tid >> 4, c = tid & 15;
     double x[16];
