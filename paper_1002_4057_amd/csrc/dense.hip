@@ -87,13 +87,15 @@ __device__ __forceinline__ void out_tile(int b, int nblk, int t, bool lower, int
 // C(i, j) = Cin(i, j) + s * sum_k A(i, k) B(j, k)^T (+ the identity on the
 // first diag_n diagonal entries), one output tile per workgroup; s = -1 when
 // neg, Cin may be null (zero).  With lower = 1 only tiles i >= j are formed.
-__global__ __launch_bounds__(NTHREADS) void gemm_nt_kernel(const double* __restrict__ A,
-                                                           const double* __restrict__ B,
-                                                           double* __restrict__ C, int t,
-                                                           int lower, int neg,
-                                                           const double* __restrict__ Cin,
-                                                           int diag_n) {
-  __shared__ double smem[GEMM_SMEM];
+// 16-deep k-panels (66.6 KB of LDS) and 256 registers per lane: two
+// workgroups share a CU, one's MFMAs covering the other's loads and barriers.
+constexpr int DKD = 16;
+
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void gemm_nt_kernel(const double* __restrict__ A, const double* __restrict__ B,
+                    double* __restrict__ C, int t, int lower, int neg,
+                    const double* __restrict__ Cin, int diag_n) {
+  __shared__ double smem[4 * DKD * LDS_STRIDE];
   const int nblk = lower ? t * (t + 1) / 2 : t * t;
   int i, j;
   out_tile(blockIdx.x, nblk, t, lower != 0, i, j);
@@ -101,17 +103,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_nt_kernel(const double* __restr
   const size_t ct = (size_t)(i + t * j) * TILE;
   if (Cin) {
     // start from -Cin when negating: Cin - P is rounded as -(-Cin + P)
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int off = acc_offset(a, b);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double c = Cin[ct + off + NB * 4 * r];
-          acc[a][b][r] = neg ? -c : c;
-        }
-      }
+    acc_load<0>(tile_rsrc(Cin + ct), acc, neg != 0);
   } else {
     acc_zero(acc);
   }
@@ -119,7 +111,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_nt_kernel(const double* __restr
     pa = A + (size_t)(i + t * k) * TILE;
     pb = B + (size_t)(j + t * k) * TILE;
   };
-  mma_chain<0>(acc, t, pair, smem);
+  mma_chain<0, DKD>(acc, t, pair, smem);
   if (diag_n > 0 && i == j) {
     // lane l, register r of accumulator (a, b) holds tile element
     // (row, col) = acc_offset(a, b) + 4 NB r, i.e. column (off / NB) + 4 r
@@ -134,7 +126,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_nt_kernel(const double* __restr
           if (row == col0 + 4 * r && i * NB + row < diag_n) acc[a][b][r] += neg ? -1.0 : 1.0;
       }
   }
-  acc_store<0>(C + ct, acc, neg != 0, false);
+  acc_store_tile<0>(tile_rsrc(C + ct), acc, neg != 0);
 }
 
 // partial[b] = sum of squares of the entries of tile b (fixed summation
@@ -250,6 +242,7 @@ hipError_t launch_pack(const double* src, int ld, int n, int t, int mode, double
 
 hipError_t launch_gemm_nt(const double* A, const double* B, double* C, int t, int lower, int neg,
                           hipStream_t s, const double* Cin, int diag_n) {
+  if (t < 1) return hipErrorInvalidValue;  // the kernel's chain takes at least one link
   const int nblk = lower ? t * (t + 1) / 2 : t * t;
   hipLaunchKernelGGL(gemm_nt_kernel, dim3(nblk), dim3(NTHREADS), 0, s, A, B, C, t, lower, neg, Cin,
                      diag_n);

@@ -158,13 +158,14 @@ __device__ __forceinline__ int acc_offset(int i, int j) {
   return ((w & 1) * 64 + i * 16 + (lane & 15)) + NB * ((w >> 1) * 64 + j * 16 + (lane >> 4));
 }
 
-// One KC-deep panel step: acc += op(A)[:, k-panel] op(B)[k-panel, :] from the
+// One KD-deep panel step: acc += op(A)[:, k-panel] op(B)[k-panel, :] from the
 // LDS panels As, Bs (layout of panel_store).
+template <int KD = KC>
 __device__ __forceinline__ void panel_mma(Acc& acc, const double* As, const double* Bs) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w & 1, wn = w >> 1, lr = lane & 15, lk = lane >> 4;
 #pragma unroll
-  for (int ks = 0; ks < KC / 4; ++ks) {
+  for (int ks = 0; ks < KD / 4; ++ks) {
     const double* Ar = As + (4 * ks + lk) * LDS_STRIDE + wm * 64 + lr;
     const double* Br = Bs + (4 * ks + lk) * LDS_STRIDE + wn * 64 + lr;
     double a[4], b[4];
@@ -184,24 +185,28 @@ __device__ __forceinline__ void panel_mma(Acc& acc, const double* As, const doub
 // Chained product: acc += sum_{p < count} A_p B_p^T, where pair(p, a, b)
 // names the two contiguous tiles of link p.  Both operands are read along
 // stored columns.  The k-panels of all links form one double-buffered
-// stream through LDS (smem: 4 * PANEL doubles), so the first panel of link
-// p+1 is loaded while the last panel of link p is multiplied.  Each panel's
-// body is one branch-free scheduling region in which the next panel's loads
-// (k-steps 0-1) and their staging into LDS (k-steps 6-7) are interleaved
-// with the MFMAs; past the last panel the loads read a zero-size buffer
+// stream through LDS (smem: 4 * KD * LDS_STRIDE doubles for KD-deep
+// panels), so the first panel of link p+1 is loaded while the last panel of
+// link p is multiplied.  Each panel's body is one branch-free scheduling
+// region in which the next panel's loads (first quarter of the k-steps) and
+// their staging into LDS (last quarter) are interleaved with the MFMAs;
+// past the last panel the loads read a zero-size buffer
 // (zeros, no memory access).  The pair function must give the same pointers
-// in every thread.  The accumulator is never written to memory here.
-template <int CP, class PairFn>
+// in every thread, and count must be at least 1.  The accumulator is never
+// written to memory here.
+template <int CP, int KD = KC, class PairFn>
 __device__ __forceinline__ void mma_chain(Acc& acc, int count, PairFn pair, double* smem) {
-  if (count <= 0) return;
+  // count >= 1 (a bypass path for count = 0 would keep a second copy of the
+  // accumulator alive across the loop)
+  __builtin_assume(count >= 1);
   const double *pa, *pb;
   pair(0, pa, pb);
   const rsrc_t none = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(pa), 0, 0, RSRC_WORD3);
-  d2 ra[PAIRS], rb[PAIRS];
-  panel_load<CP>(tile_rsrc(pa), 0, true, ra);
-  panel_load<CP>(tile_rsrc(pb), 0, true, rb);
-  panel_store(smem, 0, true, false, ra);
-  panel_store(smem + PANEL, 0, true, false, rb);
+  d2 ra[panel_pairs<KD>()], rb[panel_pairs<KD>()];
+  panel_load<CP, KD>(tile_rsrc(pa), 0, true, ra);
+  panel_load<CP, KD>(tile_rsrc(pb), 0, true, rb);
+  panel_store<KD>(smem, 0, true, false, ra);
+  panel_store<KD>(smem + (KD * LDS_STRIDE), 0, true, false, rb);
   __syncthreads();
   // two rolled loops (links, then the k-panels of a link) with the next
   // link's tiles resolved once per link: this keeps the accumulator in the
@@ -215,24 +220,26 @@ __device__ __forceinline__ void mma_chain(Acc& acc, int count, PairFn pair, doub
     const rsrc_t rA = tile_rsrc(pa), rB = tile_rsrc(pb);
     const rsrc_t nA = last ? none : tile_rsrc(qa), nB = last ? none : tile_rsrc(qb);
 #pragma unroll 1
-    for (int c = 0; c < NCH; ++c) {
-      const double* As = smem + (c & 1) * 2 * PANEL;
-      const double* Bs = As + PANEL;
-      double* An = smem + ((c + 1) & 1) * 2 * PANEL;
-      const bool wrap = c + 1 == NCH;
-      panel_load<CP>(wrap ? nA : rA, ((c + 1) % NCH) * KC, true, ra);
-      panel_load<CP>(wrap ? nB : rB, ((c + 1) % NCH) * KC, true, rb);
-      panel_mma(acc, As, Bs);
+    for (int c = 0; c < (NB / KD); ++c) {
+      const double* As = smem + (c & 1) * 2 * (KD * LDS_STRIDE);
+      const double* Bs = As + (KD * LDS_STRIDE);
+      double* An = smem + ((c + 1) & 1) * 2 * (KD * LDS_STRIDE);
+      const bool wrap = c + 1 == (NB / KD);
+      panel_load<CP, KD>(wrap ? nA : rA, ((c + 1) % (NB / KD)) * KD, true, ra);
+      panel_load<CP, KD>(wrap ? nB : rB, ((c + 1) % (NB / KD)) * KD, true, rb);
+      panel_mma<KD>(acc, As, Bs);
       // the next panel's buffer was released by the previous barrier
-      panel_store(An, 0, true, false, ra);
-      panel_store(An + PANEL, 0, true, false, rb);
+      panel_store<KD>(An, 0, true, false, ra);
+      panel_store<KD>(An + (KD * LDS_STRIDE), 0, true, false, rb);
       __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
 #pragma unroll
-      for (int ks = 0; ks < KC / 4; ++ks) {
+      for (int ks = 0; ks < KD / 4; ++ks) {
         __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
-        if (ks < 2) __builtin_amdgcn_sched_group_barrier(0x020, 8, 0);
-        if (ks >= 6) __builtin_amdgcn_sched_group_barrier(0x200, 8, 0);
-        if (ks + 1 < KC / 4) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+        // the loads over the first quarter of the k-steps, their LDS
+        // stores over the last quarter
+        if (ks < KD / 16) __builtin_amdgcn_sched_group_barrier(0x020, 8, 0);
+        if (ks >= 3 * KD / 16) __builtin_amdgcn_sched_group_barrier(0x200, 8, 0);
+        if (ks + 1 < KD / 4) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
         __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
       }
       __syncthreads();
