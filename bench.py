@@ -129,6 +129,38 @@ def batched_row(reps: int):
             "reps": reps}
 
 
+def ablation_row(spd, bufs, work, n: int, reps: int):
+    """The paper's plan variants on the same n (Section 3 and its Table 1):
+    renamed against in place, UDU against UUU loop order, the TRTRI(j)
+    placement of step 2, and one device task per task of the paper
+    (chain = 1), each with the planner's critical path in tasks.  Same
+    synthetic input as the headline line; each variant is warmed once."""
+    import torch
+    variants = [("renamed UDU (default)", {}), ("in place UDU", {"renamed": 0}),
+                ("renamed UUU", {"loop_order": 1}), ("in place UUU", {"renamed": 0, "loop_order": 1}),
+                ("renamed UDU, TRTRI(j) first", {"trtri_first": 1}),
+                ("renamed UDU, one task per paper task", {"chain": 1})]
+    out = {"workload": f"single SPD inverse, n={n}, FP64 (same input as the headline line)",
+           "reps": reps, "variants": {}}
+    flops = float(n) ** 3
+    for label, opts in variants:
+        try:
+            b = bufs[0].t().clone()
+            rep = spd.spd_inverse_(b, work=work, report=True, **opts)   # plan + warm
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            for k in range(reps):
+                spd.spd_inverse_(bufs[k].t(), work=work, **opts)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - s0) / reps * 1e3
+            out["variants"][label] = {"ms": round(ms, 3), "gflops": round(flops / ms / 1e6, 1),
+                                      "critical_path_tasks": rep["critical_path"],
+                                      "device_tasks": rep["tasks"]}
+        except Exception as e:   # a variant that fails is reported, not fatal
+            out["variants"][label] = {"error": str(e)}
+    return out
+
+
 def backward_row(reps: int):
     """Differentiation workload (a): grad_A = -X sym(G) X at n = 4096."""
     import torch
@@ -202,8 +234,9 @@ def main():
     ap.add_argument("--kappa", type=float, default=1e4)
     ap.add_argument("--cpu-n", type=int, default=8192, help="oracle sample order (0 = skip)")
     ap.add_argument("--no-unpipelined", action="store_true")
-    ap.add_argument("--rows", default="batched,backward,mixed",
-                    help="extra measured rows: batched, backward, mixed (comma list, '' = none)")
+    ap.add_argument("--rows", default="batched,backward,mixed,ablation",
+                    help="extra measured rows: batched, backward, mixed, ablation "
+                         "(comma list, '' = none)")
     ap.add_argument("--input", choices=["spectrum", "wishart"], default="spectrum",
                     help="wishart (B B^T/n + I, no QR) is for profiler counter runs only")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -284,6 +317,11 @@ def main():
         pipe = {"pipelined_gflops": res["pipelined"], "unpipelined_gflops": res["unpipelined"],
                 "steps": reps}
 
+    ablation = None
+    if "ablation" in [r for r in args.rows.split(",") if r]:
+        log("[bench] ablation row")
+        ablation = ablation_row(spd, bufs, work, n, max(2, min(K, 3)))
+
     if args.calibrate_copy > 0:
         # plain copy of known size, for scaling profiler byte counters
         nel = args.calibrate_copy * (1 << 20) // 8
@@ -305,6 +343,8 @@ def main():
     if "mixed" in wanted:
         log("[bench] mixed row")
         rows["mixed"] = mixed_row(max(2, min(K, 3)))
+    if ablation is not None:
+        rows["ablation"] = ablation
 
     cpu = None
     if args.cpu_n > 0:
