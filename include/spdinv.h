@@ -150,6 +150,38 @@ int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t 
                 spdinv_stream_t stream, const spdinv_opts* opts, int* d_info,
                 spdinv_report* report);
 
+/* ---- the steps on their own ------------------------------------------------ */
+/*
+ * Cholesky factor only: A = L L^T by step 1 of Algorithm 1 (tile POTRF,
+ * SYRK, GEMM, TRSM; Section 2), on the same scheduler.  The lower triangle of
+ * A (column-major, lda >= max(1,n)) is read and overwritten with L; the
+ * strictly upper triangle is neither read nor written (opts->fill_upper is
+ * ignored).  Workspace: spd_inverse_workspace_bytes(n, SPDINV_FP64, opts)
+ * bytes.  d_info, report, stream and opts as for spd_inverse (FP64 only):
+ * INFO = k > 0 when the leading minor of order k is not positive definite
+ * (the contents of A are then unspecified).  Returns 0, -i for an invalid
+ * i-th argument, SPDINV_ERR_WORKSPACE or SPDINV_ERR_HIP.
+ */
+int spd_cholesky(int n, double* A, int lda, void* work, size_t work_bytes,
+                 spdinv_stream_t stream, const spdinv_opts* opts, int* d_info,
+                 spdinv_report* report);
+
+/*
+ * Inverse from a given Cholesky factor: (L L^T)^{-1} by steps 2 and 3 of
+ * Algorithm 1 (TRTRI: tile TRTRI, TRMM, GEMM, TRSM; LAUUM: tile LAUUM, TRMM,
+ * SYRK, GEMM).  A prologue kernel first makes what step 1 would leave for
+ * step 2 (the inverted diagonal tiles and the transposed copies of L's
+ * tiles).  The lower triangle of L (column-major, ldl >= max(1,n)) holds the
+ * factor on entry (its strictly upper triangle is not read) and the lower
+ * triangle of the inverse on exit; the strictly upper triangle receives the
+ * mirror only with opts->fill_upper.  INFO = k > 0 when L_kk = 0 (the
+ * contents are then unspecified).  Workspace, stream, opts, d_info, report
+ * and return codes as for spd_cholesky.
+ */
+int spd_inverse_from_factor(int n, double* L, int ldl, void* work, size_t work_bytes,
+                            spdinv_stream_t stream, const spdinv_opts* opts, int* d_info,
+                            spdinv_report* report);
+
 /* ---- batched form ---------------------------------------------------------- */
 /* Bytes of device workspace that batched_spd_inverse needs for these orders
    on the current device (0 when batch <= 0 or an order is invalid). */
@@ -253,6 +285,13 @@ int spdinv_plan_export(int t, const spdinv_opts* opts, int workers, int32_t* tas
                        int32_t* succ, int32_t* step, int32_t* idx, int32_t* order,
                        long long* ntasks, long long* nsucc, int32_t* links,
                        long long* nlinks);
+/* The same for a plan of some steps of Algorithm 1: steps = 7 (the SPD
+   inverse, as spdinv_plan_export), 1 (the plan of spd_cholesky) or 6 (the
+   plan of spd_inverse_from_factor).  Returns -2 for another value. */
+int spdinv_plan_export_steps(int steps, int t, const spdinv_opts* opts, int workers,
+                             int32_t* tasks8, int32_t* succ, int32_t* step, int32_t* idx,
+                             int32_t* order, long long* ntasks, long long* nsucc, int32_t* links,
+                             long long* nlinks);
 
 /* ---- per-task trace (opts.trace = 1) -------------------------------------- */
 /* Copies the per-task trace that the last spd_inverse call with

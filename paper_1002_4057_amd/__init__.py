@@ -26,6 +26,7 @@ from ._lib import LibraryNotBuilt, load, make_opts, TASK_NAMES  # noqa: F401
 __all__ = ["spd_inverse", "spd_inverse_", "workspace_bytes", "plan_stats", "plan_export",
            "spd_inverse_backward", "backward_workspace_bytes", "SpdInverse", "spd_inverse_ad",
            "batched_spd_inverse", "batched_spd_inverse_", "batched_workspace_bytes",
+           "cholesky", "cholesky_", "inverse_from_factor", "inverse_from_factor_",
            "SpdInverseError", "NotPositiveDefinite"]
 
 
@@ -105,6 +106,75 @@ def spd_inverse_(a_cm, *, mode: str = "fp64", work=None, report: bool = False, i
             raise NotPositiveDefinite(r["info"])
         return r
     return None
+
+
+def _fp64_step_entry(name: str, a_cm, work, report: bool, info, opts):
+    import torch
+    if a_cm.dtype != torch.float64 or not a_cm.is_cuda or a_cm.dim() != 2:
+        raise TypeError("expected a 2-D CUDA float64 tensor")
+    n = a_cm.shape[0]
+    if a_cm.shape[1] != n:
+        raise ValueError("matrix must be square")
+    if n > 1 and a_cm.stride(0) != 1:
+        raise ValueError("expected a column-major view (stride(0) == 1)")
+    lda = max(1, a_cm.stride(1) if n > 1 else max(1, n))
+    lib = load()
+    o = make_opts(**opts)
+    need = int(lib.spd_inverse_workspace_bytes(n, _lib.SPDINV_FP64, ctypes.byref(o)))
+    if work is None:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=a_cm.device)
+    elif work.numel() * work.element_size() < need:
+        raise ValueError(f"workspace too small: need {need} bytes")
+    rep = _lib.Report()
+    info_ptr = info.data_ptr() if info is not None else None
+    rc = getattr(lib, name)(n, a_cm.data_ptr(), lda, work.data_ptr(), need,
+                            _stream_ptr(a_cm.device), ctypes.byref(o), info_ptr,
+                            ctypes.byref(rep) if report else None)
+    if rc != 0:
+        raise SpdInverseError(f"{name} returned {rc}")
+    if report:
+        r = {f: getattr(rep, f) for f, _ in _lib.Report._fields_}
+        if r["info"] > 0:
+            raise NotPositiveDefinite(r["info"])
+        return r
+    return None
+
+
+def cholesky_(a_cm, *, work=None, report: bool = False, info=None, **opts):
+    """A <- L (A = L L^T) in place on the lower triangle of a column-major
+    CUDA float64 view (step 1 of Algorithm 1 alone); the strictly upper
+    triangle is left as it is.  Arguments as for spd_inverse_ (FP64 only)."""
+    return _fp64_step_entry("spd_cholesky", a_cm, work, report, info, opts)
+
+
+def cholesky(a, return_report: bool = False, **opts):
+    """Lower Cholesky factor L of a CUDA float64 SPD tensor (lower triangle
+    read), with zeros above the diagonal."""
+    import torch
+    n = a.shape[-1]
+    buf = a.t().contiguous()
+    rep = cholesky_(buf.t(), report=True, **opts) if n else None
+    l = torch.tril(buf.t()).contiguous() if n else torch.empty_like(a)
+    return (l, rep) if return_report else l
+
+
+def inverse_from_factor_(l_cm, *, work=None, report: bool = False, info=None, **opts):
+    """L <- (L L^T)^{-1} in place: the lower triangle of a column-major CUDA
+    float64 view holds the Cholesky factor on entry and the lower triangle of
+    the inverse on exit (steps 2 and 3 of Algorithm 1).  INFO = k > 0 when
+    L_kk = 0.  Arguments as for spd_inverse_ (FP64 only)."""
+    return _fp64_step_entry("spd_inverse_from_factor", l_cm, work, report, info, opts)
+
+
+def inverse_from_factor(l, return_report: bool = False, **opts):
+    """Full symmetric (L L^T)^{-1} from a CUDA float64 lower Cholesky factor L
+    (its strictly upper triangle is not read)."""
+    import torch
+    n = l.shape[-1]
+    buf = l.t().contiguous()
+    rep = inverse_from_factor_(buf.t(), report=True, fill_upper=1, **opts) if n else None
+    x = buf.t().contiguous() if n else torch.empty_like(l)
+    return (x, rep) if return_report else x
 
 
 def spd_inverse(a, mode: str = "fp64", return_report: bool = False, **opts):
@@ -290,16 +360,18 @@ def plan_stats(t: int, **opts) -> dict:
             "cp_plan": st.cp_plan}
 
 
-def plan_export(t: int, workers: int = 1, **opts) -> dict:
+def plan_export(t: int, workers: int = 1, steps: int = 7, **opts) -> dict:
     """The plan as numpy arrays: tasks (ntasks x 8 int32), succ, step, idx,
     order, and links (nlinks x 2 int32: the further operand pairs of chained
-    product tasks)."""
+    product tasks).  ``steps``: 7 the SPD inverse, 1 the Cholesky factor
+    only, 6 the inverse from a given factor."""
     lib = load()
     o = make_opts(**opts)
     nt, ns, nl = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
-    if lib.spdinv_plan_export(int(t), ctypes.byref(o), int(workers), None, None, None, None, None,
-                              ctypes.byref(nt), ctypes.byref(ns), None, ctypes.byref(nl)) != 0:
-        raise ValueError("invalid tile count")
+    if lib.spdinv_plan_export_steps(int(steps), int(t), ctypes.byref(o), int(workers), None, None,
+                                    None, None, None, ctypes.byref(nt), ctypes.byref(ns), None,
+                                    ctypes.byref(nl)) != 0:
+        raise ValueError("invalid tile count or steps")
     tasks = np.zeros((nt.value, 8), dtype=np.int32)
     succ = np.zeros(max(ns.value, 1), dtype=np.int32)
     step = np.zeros(nt.value, dtype=np.int32)
@@ -307,8 +379,8 @@ def plan_export(t: int, workers: int = 1, **opts) -> dict:
     order = np.zeros(nt.value, dtype=np.int32)
     links = np.zeros(max(nl.value, 2), dtype=np.int32)
     p = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
-    lib.spdinv_plan_export(int(t), ctypes.byref(o), int(workers), p(tasks), p(succ), p(step),
-                           p(idx), p(order), None, None, p(links), None)
+    lib.spdinv_plan_export_steps(int(steps), int(t), ctypes.byref(o), int(workers), p(tasks),
+                                 p(succ), p(step), p(idx), p(order), None, None, p(links), None)
     return {"tasks": tasks, "succ": succ[:ns.value], "step": step, "idx": idx, "order": order,
             "links": links[:nl.value].reshape(-1, 2), "t": int(t), "T": t * (t + 1) // 2}
 

@@ -72,6 +72,10 @@ def load():
     lib.spd_inverse_workspace_bytes.restype = sz
     lib.spd_inverse.argtypes = [i, vp, i, i, vp, sz, vp, P(Opts), vp, P(Report)]
     lib.spd_inverse.restype = i
+    for name in ("spd_cholesky", "spd_inverse_from_factor"):
+        fn = getattr(lib, name)
+        fn.argtypes = [i, vp, i, vp, sz, vp, P(Opts), vp, P(Report)]
+        fn.restype = i
     lib.spdinv_release_plans.argtypes = []
     lib.spdinv_release_plans.restype = None
     lib.spdinv_plan_stats_get.argtypes = [i, P(Opts), P(PlanStats)]
@@ -81,6 +85,8 @@ def load():
                                        P(ctypes.c_longlong), P(ctypes.c_longlong), i32p,
                                        P(ctypes.c_longlong)]
     lib.spdinv_plan_export.restype = i
+    lib.spdinv_plan_export_steps.argtypes = [i] + lib.spdinv_plan_export.argtypes
+    lib.spdinv_plan_export_steps.restype = i
     lib.spdinv_trace_copy.argtypes = [vp, i, P(Opts), P(ctypes.c_int64), ctypes.c_longlong]
     lib.spdinv_trace_copy.restype = ctypes.c_longlong
     lib.spdinv_kernel_timer.argtypes = [i]

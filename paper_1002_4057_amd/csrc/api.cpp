@@ -49,11 +49,11 @@ const double kCost[K_COUNT + 1] = {
 constexpr int kDefaultChain = 8;
 
 struct Key {
-  int device, t, renamed, loop_order, pipelined, trtri_first, workers, chain;
+  int device, t, renamed, loop_order, pipelined, trtri_first, workers, chain, steps;
   bool operator<(const Key& o) const {
-    return std::tie(device, t, renamed, loop_order, pipelined, trtri_first, workers, chain) <
+    return std::tie(device, t, renamed, loop_order, pipelined, trtri_first, workers, chain, steps) <
            std::tie(o.device, o.t, o.renamed, o.loop_order, o.pipelined, o.trtri_first, o.workers,
-                    o.chain);
+                    o.chain, o.steps);
   }
 };
 
@@ -165,9 +165,9 @@ int grid_for(int device, int t, const spdinv_opts& o) {
 // chain) and kept with its device copy.  chain: most products per device
 // task (1 for executors that run the paper's tasks one by one).
 DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, int chain,
-                  hipError_t* err) {
+                  hipError_t* err, int steps = 7) {
   Key k{device, t, o.renamed ? 1 : 0, o.loop_order, o.pipelined ? 1 : 0, o.trtri_first ? 1 : 0,
-        workers, chain};
+        workers, chain, steps};
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_plans.find(k);
   if (it != g_plans.end()) return it->second.get();
@@ -179,6 +179,7 @@ DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, int chai
   po.pipelined = k.pipelined;
   po.trtri_first = k.trtri_first;
   po.chain = k.chain;
+  po.steps = k.steps;
   build_plan(po, workers, kCost, &dp->host);
   const Plan& p = dp->host;
   const size_t nt = p.tasks.size();
@@ -262,9 +263,12 @@ long long spin_limit() {
   return 2000000000LL;  // 20 s
 }
 
-// The FP64 path: copy-in, the persistent scheduler over the plan, copy-out.
+// The FP64 path: copy-in, the persistent scheduler over the plan (the steps
+// of Algorithm 1 selected by `steps`), copy-out.  For the inverse from a
+// given factor (steps 2 and 3) a prologue kernel first makes what step 1
+// would leave for step 2.
 int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream_t stream,
-             const spdinv_opts& o, int* d_info, spdinv_report* report) {
+             const spdinv_opts& o, int* d_info, spdinv_report* report, int steps = 7) {
   const Layout L = layout(n, o);
   if (work_bytes < L.total) return SPDINV_ERR_WORKSPACE;
 
@@ -273,7 +277,7 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   const int t = tiles_for(n);
   const int grid = grid_for(device, t, o);
   hipError_t err = hipSuccess;
-  DevPlan* dp = get_plan(device, t, o, grid, chain_for(o), &err);
+  DevPlan* dp = get_plan(device, t, o, grid, chain_for(o), &err, steps);
   if (!dp) return SPDINV_ERR_HIP;
   const int ntask = (int)dp->host.tasks.size();
 
@@ -285,6 +289,8 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
 
   if (launch_reset(dp->d_indeg0, indeg, ntask, ctrl, stream) != hipSuccess) return SPDINV_ERR_HIP;
   if (launch_copy_in(A, lda, n, t, pool, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (steps == 6 && launch_factor_prologue(pool, t, ctrl, stream) != hipSuccess)
+    return SPDINV_ERR_HIP;
   SchedArgs a;
   a.tasks = dp->d_tasks;
   a.succ = dp->d_succ;
@@ -305,7 +311,9 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   if (timed && hipEventRecord(ev0, stream) != hipSuccess) return SPDINV_ERR_HIP;
   if (launch_sched(a, grid, per_cu_for(t, o), stream) != hipSuccess) return SPDINV_ERR_HIP;
   if (timed && hipEventRecord(ev1, stream) != hipSuccess) return SPDINV_ERR_HIP;
-  if (launch_copy_out(pool, t, A, lda, n, o.fill_upper, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  // the Cholesky factor leaves the strictly upper triangle untouched
+  if (launch_copy_out(pool, t, A, lda, n, steps == 1 ? 0 : o.fill_upper, stream) != hipSuccess)
+    return SPDINV_ERR_HIP;
   if (launch_info_out(ctrl, d_info, stream) != hipSuccess) return SPDINV_ERR_HIP;
 
   if (report) {
@@ -680,6 +688,42 @@ int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t 
   return run_fp64(n, A, lda, work, work_bytes, stream, o, d_info, report);
 }
 
+// Shared argument checks of the FP64 entry points over one matrix.
+static int fp64_entry(int n, double* A, int lda, void* work, size_t work_bytes,
+                      spdinv_stream_t stream_, const spdinv_opts* opts, int* d_info,
+                      spdinv_report* report, int steps) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  if (n < 0) return -1;
+  if (n > 0 && !A) return -2;
+  if (lda < (n > 1 ? n : 1)) return -3;
+  const spdinv_opts o = opts ? *opts : defaults();
+  if (check_opts(o)) return -7;
+  if (report) std::memset(report, 0, sizeof(*report));
+  if (n == 0) {
+    if (d_info) {
+      int zero = 0;
+      if (hipMemcpyAsync(d_info, &zero, sizeof(int), hipMemcpyHostToDevice, stream) != hipSuccess)
+        return SPDINV_ERR_HIP;
+      if (hipStreamSynchronize(stream) != hipSuccess) return SPDINV_ERR_HIP;
+    }
+    return 0;
+  }
+  if (!work) return -4;
+  return run_fp64(n, A, lda, work, work_bytes, stream, o, d_info, report, steps);
+}
+
+int spd_cholesky(int n, double* A, int lda, void* work, size_t work_bytes,
+                 spdinv_stream_t stream, const spdinv_opts* opts, int* d_info,
+                 spdinv_report* report) {
+  return fp64_entry(n, A, lda, work, work_bytes, stream, opts, d_info, report, 1);
+}
+
+int spd_inverse_from_factor(int n, double* L, int ldl, void* work, size_t work_bytes,
+                            spdinv_stream_t stream, const spdinv_opts* opts, int* d_info,
+                            spdinv_report* report) {
+  return fp64_entry(n, L, ldl, work, work_bytes, stream, opts, d_info, report, 6);
+}
+
 void spdinv_release_plans(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (auto& kv : g_plans)
@@ -716,9 +760,20 @@ int spdinv_plan_stats_get(int t, const spdinv_opts* opts, spdinv_plan_stats* out
 int spdinv_plan_export(int t, const spdinv_opts* opts, int workers, int32_t* tasks8, int32_t* succ,
                        int32_t* step, int32_t* idx, int32_t* order, long long* ntasks,
                        long long* nsucc, int32_t* links, long long* nlinks) {
+  return spdinv_plan_export_steps(7, t, opts, workers, tasks8, succ, step, idx, order, ntasks,
+                                  nsucc, links, nlinks);
+}
+
+int spdinv_plan_export_steps(int steps, int t, const spdinv_opts* opts, int workers,
+                             int32_t* tasks8, int32_t* succ, int32_t* step, int32_t* idx,
+                             int32_t* order, long long* ntasks, long long* nsucc, int32_t* links,
+                             long long* nlinks) {
   if (t < 1 || t > 1024) return -1;
+  if (steps != 7 && steps != 1 && steps != 6) return -2;
   Plan p;
-  build_plan(plan_options(t, opts), workers > 0 ? workers : 1, kCost, &p);
+  PlanOptions po = plan_options(t, opts);
+  po.steps = steps;
+  build_plan(po, workers > 0 ? workers : 1, kCost, &p);
   if (ntasks) *ntasks = (long long)p.tasks.size();
   if (nsucc) *nsucc = (long long)p.succ.size();
   if (tasks8) std::memcpy(tasks8, p.tasks.data(), p.tasks.size() * sizeof(DevTask));

@@ -34,6 +34,45 @@ __device__ __forceinline__ void tri_decode(int x, int& ti, int& tj) {
   tj = x - i * (i + 1) / 2;
 }
 
+// What step 1 leaves for step 2 when the Cholesky factor is given (the
+// inverse from a factor, Algorithm 1 steps 2 and 3): the transposed renaming
+// copies B_ij = L_ij^T (i > j) and the inverted diagonal tiles D_j, D_j^T.
+// One workgroup per lower tile of the pool (tile tri(i, j) holds L_ij).  A
+// zero diagonal entry of L sets INFO and the failure flag, so that the
+// scheduler skips every task.
+__global__ __launch_bounds__(NTHREADS) void factor_prologue_kernel(double* pool, int t,
+                                                                   int32_t* ctrl) {
+  __shared__ double smem[TASK_SMEM];
+  int ti, tj;
+  tri_decode(blockIdx.x, ti, tj);
+  const int T = t * (t + 1) / 2;
+  const double* L = pool + (size_t)blockIdx.x * TILE;
+  if (ti == tj) {
+    const int f = trtri_inv_tile(L, pool + (size_t)(3 * T + tj) * TILE,
+                                 pool + (size_t)(3 * T + t + tj) * TILE, smem);
+    if (f && threadIdx.x == 0) {
+      atomicMin(&ctrl[CTRL_INFO], tj * NB + f);
+      __hip_atomic_store(&ctrl[CTRL_FAILED], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return;
+  }
+  // B_ij = L_ij^T through LDS, 64 rows of L at a time: R[c + RLD * r]
+  double* B = pool + (size_t)(T + blockIdx.x) * TILE;
+  double* R = smem;
+  for (int h = 0; h < 2; ++h) {
+    for (int e = threadIdx.x; e < 64 * NB; e += NTHREADS) {
+      const int r = e & 63, c = e >> 6;  // L(64h + r, c), read down the columns
+      R[c + RLD * r] = L[(64 * h + r) + NB * c];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * NB; e += NTHREADS) {
+      const int rr = e & (NB - 1), cl = e >> 7;  // B(rr, 64h + cl) = L(64h + cl, rr)
+      B[rr + NB * (64 * h + cl)] = R[rr + RLD * cl];
+    }
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(NTHREADS) void copy_in_kernel(const double* __restrict__ A, int lda,
                                                            int n, double* __restrict__ pool) {
   int ti, tj;
@@ -80,6 +119,12 @@ hipError_t launch_reset(const int32_t* indeg0, int32_t* indeg, int ntask, int32_
   const int total = ntask > CTRL_WORDS ? ntask : CTRL_WORDS;
   const int blocks = (total + 255) / 256;
   hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, indeg0, indeg, ntask, ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_factor_prologue(double* pool, int t, int32_t* ctrl, hipStream_t s) {
+  const int T = t * (t + 1) / 2;
+  hipLaunchKernelGGL(factor_prologue_kernel, dim3(T), dim3(NTHREADS), 0, s, pool, t, ctrl);
   return hipGetLastError();
 }
 

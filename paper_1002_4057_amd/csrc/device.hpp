@@ -85,6 +85,11 @@ hipError_t launch_copy_out(const double* pool, int t, double* A, int lda, int n,
 // Copies ctrl[CTRL_INFO] to a device int (may be nullptr: no-op).
 hipError_t launch_info_out(const int32_t* ctrl, int* d_info, hipStream_t s);
 
+// Inverse from a given factor: the transposed copies B_ij = L_ij^T and the
+// inverted diagonal tiles D_j, D_j^T that step 2 reads, from the factor's
+// tiles in the pool (after copy-in).  Sets INFO on a zero diagonal entry.
+hipError_t launch_factor_prologue(double* pool, int t, int32_t* ctrl, hipStream_t s);
+
 // Persistent scheduler over the plan's tasks.
 // per_cu: 1 keeps every workgroup alone on its CU, 2 lets two share one.
 hipError_t launch_sched(const SchedArgs& a, int grid, int per_cu, hipStream_t s);

@@ -409,14 +409,17 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
   const int t = opt.t;
   p->T = t * (t + 1) / 2;
   Builder bld(opt, p);
-  bld.step1();
-  if (!opt.pipelined) bld.emit_barrier();
-  bld.step2();
-  if (!opt.pipelined) bld.emit_barrier();
-  bld.step3();
+  const bool s1 = opt.steps & 1, s2 = opt.steps & 2, s3 = opt.steps & 4;
+  if (s1) bld.step1();
+  if (s1 && (s2 || s3) && !opt.pipelined) bld.emit_barrier();
+  if (s2) bld.step2();
+  if (s2 && s3 && !opt.pipelined) bld.emit_barrier();
+  if (s3) bld.step3();
 
   // dead factor stores: a POTRF whose factor tile is not read before it is
-  // rewritten, and whose renaming copy is never read, stores only D_j, D_j^T
+  // rewritten, and whose renaming copy is never read, stores only D_j, D_j^T.
+  // A tile that no later task rewrites holds a final value (the copy-out
+  // reads it).  Renaming copies that no task reads are not stored either.
   {
     const int nt = (int)p->tasks.size();
     std::vector<char> copy_read(pool_tiles(opt.t), 0);
@@ -428,19 +431,28 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
       DevTask& d = p->tasks[u];
       if (task_kind(d.kind) != K_POTRF) continue;
       bool read = d.copy >= 0 && copy_read[d.copy];
+      bool rewritten = false;
       for (int v = u + 1; v < nt && !read; ++v) {
         const DevTask& e = p->tasks[v];
         if (task_kind(e.kind) == K_NOP) continue;
         if (e.a == d.out || e.b == d.out) read = true;
         if (e.out == d.out) {  // next writer: an accumulating product reads it first
           if (task_flags(e.kind) & F_ACC) read = true;
+          rewritten = true;
           break;
         }
       }
+      if (!rewritten) read = true;  // final value of the tile
       if (!read) {
         d.kind |= K_POTRF_FACTOR_DEAD;
         d.copy = -1;
       }
+    }
+    for (int u = 0; u < nt; ++u) {
+      DevTask& d = p->tasks[u];
+      if (d.copy < 0 || copy_read[d.copy]) continue;
+      d.copy = -1;
+      d.kind &= ~(F_COPYT << 8);
     }
   }
 

@@ -60,6 +60,12 @@ struct PlanOptions {
   int pipelined = 1;
   int trtri_first = 0;
   int chain = 1;        // most products per device task (1 <= chain <= MAX_CHAIN)
+  // Steps of Algorithm 1 in the plan: bit 0 step 1 (Cholesky), bit 1 step 2
+  // (inverse of the factor), bit 2 step 3 (the product L^-T L^-1).  7 = the
+  // SPD inverse, 1 = the Cholesky factor only, 6 = the inverse from a given
+  // factor (the caller provides what step 1 leaves for step 2: the
+  // transposed copies B = L^T and the diagonal inverses D_j, D_j^T).
+  int steps = 7;
 };
 constexpr int MAX_CHAIN = 16;
 

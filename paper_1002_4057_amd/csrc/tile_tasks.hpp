@@ -725,6 +725,52 @@ __device__ __forceinline__ void inverse_packed(double* T, const double* rd, int 
   __syncthreads();
 }
 
+// The lower 16 x 16 blocks of a tile (rIn) into the packed layout T; entries
+// above the diagonal of the diagonal blocks read as zero.  16 x 16 blocks as
+// 128 pairs of rows: all 18 pairs of a thread are issued before the first
+// LDS write, so that their latencies overlap (a wave stays inside one block).
+__device__ __forceinline__ void load_packed_tile(rsrc_t rIn, double* T) {
+  const int tid = opaque_tid();
+  constexpr int NLD = PK_BLOCKS * 128 / NTHREADS;
+  d2 v[NLD];
+#pragma unroll
+  for (int u = 0; u < NLD; ++u) {
+    const int b = __builtin_amdgcn_readfirstlane((NTHREADS * u + tid) >> 7);
+    int bi = 0;
+    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+    const int bj = b - bi * (bi + 1) / 2;
+    const int e = 2 * (tid & 127);
+    v[u] = ld2(rIn, (16 * bi + (e & 15)) + NB * (16 * bj + (e >> 4)));
+  }
+#pragma unroll
+  for (int u = 0; u < NLD; ++u) {
+    const int b = __builtin_amdgcn_readfirstlane((NTHREADS * u + tid) >> 7);
+    int bi = 0;
+    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+    const bool diag = b == bi * (bi + 1) / 2 + bi;
+    const int e = 2 * (tid & 127), lr = e & 15, lc = e >> 4;
+    double* dst = T + PK_STRIDE * b + lr + PK_LD * lc;
+    dst[0] = (diag && lr < lc) ? 0.0 : v[u].x;
+    dst[1] = (diag && lr + 1 < lc) ? 0.0 : v[u].y;
+  }
+}
+
+// X and X^T of the packed inverse T to two tiles, as contiguous 16-byte
+// stores with explicit zeros above the diagonal of X.
+__device__ __forceinline__ void store_packed_inverse(double* T, rsrc_t rX, rsrc_t rXT) {
+  const int tid = opaque_tid();
+  auto pval = [&](int r, int c) -> double {
+    if (r < c) return 0.0;
+    return pk_blk(T, r >> 4, c >> 4)[(r & 15) + PK_LD * (c & 15)];
+  };
+#pragma unroll 4
+  for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
+    const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
+    st2(rX, e, d2{pval(rr, cc), pval(rr + 1, cc)});
+    st2(rXT, e, d2{pval(cc, rr), pval(cc, rr + 1)});
+  }
+}
+
 // Outputs: the factor (Lout, may be null: not stored), its transpose (LcopyT,
 // may be null), the inverse of the factor (Xout) and its transpose (XoutT),
 // each with explicit zeros in the other triangle.  Only the first P blocks of
@@ -748,32 +794,7 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
   const rsrc_t rIn = tile_rsrc(Ain), rL = tile_rsrc(Lout ? Lout : Xout), rX = tile_rsrc(Xout),
                rXT = tile_rsrc(XoutT);
 
-  // load the lower blocks, 16 x 16 each as 128 pairs of rows: all 18 pairs
-  // of a thread are issued before the first LDS write, so that their
-  // latencies overlap (a wave stays inside one block); entries above the
-  // diagonal of a diagonal block are zero
-  constexpr int NLD = PK_BLOCKS * 128 / NTHREADS;
-  d2 v[NLD];
-#pragma unroll
-  for (int u = 0; u < NLD; ++u) {
-    const int b = __builtin_amdgcn_readfirstlane((NTHREADS * u + tid) >> 7);
-    int bi = 0;
-    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
-    const int bj = b - bi * (bi + 1) / 2;
-    const int e = 2 * (tid & 127);
-    v[u] = ld2(rIn, (16 * bi + (e & 15)) + NB * (16 * bj + (e >> 4)));
-  }
-#pragma unroll
-  for (int u = 0; u < NLD; ++u) {
-    const int b = __builtin_amdgcn_readfirstlane((NTHREADS * u + tid) >> 7);
-    int bi = 0;
-    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
-    const bool diag = b == bi * (bi + 1) / 2 + bi;
-    const int e = 2 * (tid & 127), lr = e & 15, lc = e >> 4;
-    double* dst = T + PK_STRIDE * b + lr + PK_LD * lc;
-    dst[0] = (diag && lr < lc) ? 0.0 : v[u].x;
-    dst[1] = (diag && lr + 1 < lc) ? 0.0 : v[u].y;
-  }
+  load_packed_tile(rIn, T);
   __syncthreads();
 
   const int ff = factor_packed(T, rd, flag, P);
@@ -798,14 +819,39 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
   __syncthreads();  // the inverse overwrites the factor
 
   inverse_packed(T, rd, P);
-  // X and X^T as contiguous 16-byte stores; the blocks past P (padding)
-  // still hold the identity block loaded with the tile
-#pragma unroll 4
-  for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
-    const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
-    st2(rX, e, d2{pval(rr, cc), pval(rr + 1, cc)});
-    st2(rXT, e, d2{pval(cc, rr), pval(cc, rr + 1)});
+  // the blocks past P (padding) still hold the identity block loaded with
+  // the tile
+  store_packed_inverse(T, rX, rXT);
+  return 0;
+}
+
+// Diagonal tile of a given Cholesky factor (the inverse from a factor): X =
+// L^{-1} and X^T from the lower triangle of Lin, by the steps of
+// potrf_inv_tile without the factorization; the reciprocal pivots are 1/L_kk
+// (a division).  Returns 0, or the 1-based local index of the first zero
+// diagonal entry (the factor is singular; nothing is stored).
+__device__ __attribute__((noinline)) int trtri_inv_tile(const double* Lin, double* Xout,
+                                                        double* XoutT, double* smem) {
+  Lin = uniform_ptr(Lin);
+  Xout = uniform_ptr(Xout);
+  XoutT = uniform_ptr(XoutT);
+  double* T = smem;
+  double* rd = smem + PK_BLOCKS * PK_STRIDE;
+  int* flag = reinterpret_cast<int*>(rd + NB);
+  const int tid = opaque_tid();
+  if (tid == 0) *flag = INT_MAX;
+  load_packed_tile(tile_rsrc(Lin), T);
+  __syncthreads();
+  if (tid < NB) {
+    const double d = pk_blk(T, tid >> 4, tid >> 4)[(tid & 15) * (PK_LD + 1)];
+    rd[tid] = 1.0 / d;
+    if (d == 0.0) atomicMin(flag, tid + 1);
   }
+  __syncthreads();
+  const int f = __builtin_amdgcn_readfirstlane(*flag);
+  if (f != INT_MAX) return f;
+  inverse_packed(T, rd, NB / 16);
+  store_packed_inverse(T, tile_rsrc(Xout), tile_rsrc(XoutT));
   return 0;
 }
 

@@ -1,0 +1,118 @@
+"""GPU parity of the steps of Algorithm 1 on their own, through the C-ABI:
+spd_cholesky (step 1) against the oracle's Cholesky step, and
+spd_inverse_from_factor (steps 2 and 3 after the factor prologue) against
+the oracle's inverse.  Tolerance: relative Frobenius error <= 1e-12 * kappa(A)
+as for spd_inverse; at large orders, properties that hold at any size
+(L L^T = A, the analytic inverse)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1002_4057_amd as spd
+from paper_1002_4057_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+ORDERS = [1, 2, 15, 16, 17, 127, 128, 129, 300, 511, 700]
+
+
+def rel_fro(x, y):
+    return np.linalg.norm(x - y) / np.linalg.norm(y)
+
+
+def kappa(a):
+    ev = np.linalg.eigvalsh(a)
+    return ev[-1] / ev[0]
+
+
+def run_entry(fn, m, lda=None, upper=np.nan, **opts):
+    """Calls fn on the column-major device copy of m (lower triangle used);
+    the strictly upper triangle and the rows past n are filled with `upper`.
+    Returns the whole column-major buffer (ld x n) and the report."""
+    n = m.shape[0]
+    ld = lda or n
+    host = np.full((ld, n), upper)
+    host[:n, :n] = np.tril(m) + np.triu(np.full((n, n), upper), 1)
+    buf = torch.from_numpy(np.ascontiguousarray(host.T)).to(DEV)
+    rep = fn(buf.t()[:n, :], report=True, **opts)
+    return buf.cpu().numpy().T, rep
+
+
+@pytest.mark.parametrize("n", ORDERS)
+def test_cholesky_against_oracle(n):
+    a = inputs.wishart_shift(n, seed=11).numpy()
+    out, rep = run_entry(spd.cholesky_, a, lda=n + 3)
+    assert rep["info"] == 0
+    lo = oracle.potrf(a)
+    assert rel_fro(np.tril(out[:n, :n]), lo) <= 1e-12 * kappa(a)
+    # strictly upper triangle and the rows past n untouched
+    assert np.isnan(np.triu(out[:n, :n], 1)[np.triu_indices(n, 1)]).all()
+    assert np.isnan(out[n:, :]).all()
+
+
+@pytest.mark.parametrize("n", ORDERS)
+def test_inverse_from_factor_against_oracle(n):
+    a = inputs.wishart_shift(n, seed=12).numpy()
+    lo = oracle.potrf(a)
+    out, rep = run_entry(spd.inverse_from_factor_, lo, lda=n + 2)
+    assert rep["info"] == 0
+    x = oracle.spd_inverse(a)
+    assert rel_fro(np.tril(out[:n, :n]), np.tril(x)) <= 1e-12 * kappa(a)
+    assert np.isnan(np.triu(out[:n, :n], 1)[np.triu_indices(n, 1)]).all()
+
+
+def test_cholesky_then_inverse_from_factor_is_the_inverse():
+    n = 700
+    a = inputs.wishart_shift(n, seed=13)
+    ad = a.to(DEV)
+    lo = spd.cholesky(ad)
+    assert torch.equal(lo, torch.tril(lo))
+    x = spd.inverse_from_factor(lo)
+    assert torch.equal(x, x.t())
+    ref = oracle.spd_inverse(a.numpy())
+    assert rel_fro(x.cpu().numpy(), ref) <= 1e-12 * kappa(a.numpy())
+
+
+@pytest.mark.parametrize("k", [1, 37, 129, 300])
+def test_cholesky_reports_first_nonpositive_minor(k):
+    d = np.ones(300)
+    d[k - 1] = -1.0
+    out, rep = None, None
+    with pytest.raises(spd.NotPositiveDefinite) as e:
+        run_entry(spd.cholesky_, np.diag(d))
+    assert e.value.info == k
+
+
+@pytest.mark.parametrize("k", [1, 128, 200])
+def test_inverse_from_factor_reports_zero_diagonal(k):
+    lo = np.tril(np.ones((260, 260))) * 0.01 + np.eye(260)
+    lo[k - 1, k - 1] = 0.0
+    with pytest.raises(spd.NotPositiveDefinite) as e:
+        run_entry(spd.inverse_from_factor_, lo)
+    assert e.value.info == k
+
+
+def test_exact_cases():
+    # diagonal with powers of four: every operation is exact
+    d = 4.0 ** ((np.arange(260) % 9) - 4)
+    out, _ = run_entry(spd.cholesky_, np.diag(d))
+    np.testing.assert_array_equal(np.tril(out), np.diag(np.sqrt(d)))
+    out, _ = run_entry(spd.inverse_from_factor_, np.diag(np.sqrt(d)))
+    np.testing.assert_array_equal(np.tril(out), np.diag(1.0 / d))
+
+
+@pytest.mark.parametrize("n", [4096 + 1, 8192 - 100])
+def test_large_ragged_orders(n):
+    """At scale: L L^T reproduces A, and the inverse from the GPU's own factor
+    matches Q diag(1/lambda) Q^T."""
+    a, q, lam = inputs.spectrum(n, 1e4, seed=7, device=DEV, return_factors=True)
+    lo = spd.cholesky(a)
+    res = (torch.linalg.norm(lo @ lo.t() - a) / torch.linalg.norm(a)).item()
+    assert res <= 1e-14
+    x = spd.inverse_from_factor(lo)
+    ref = inputs.analytic_inverse(q, lam)
+    assert (torch.linalg.norm(x - ref) / torch.linalg.norm(ref)).item() <= 1e-12 * 1e4
+    # n = 0 is a no-op
+    assert spd.cholesky(torch.empty((0, 0), dtype=torch.float64, device=DEV)).shape == (0, 0)
