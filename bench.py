@@ -161,6 +161,26 @@ def ablation_row(spd, bufs, work, n: int, reps: int):
     return out
 
 
+def steps_row(spd, a_cm, work, n: int, reps: int):
+    """The steps of Algorithm 1 on their own, on the headline input: the
+    Cholesky factor (step 1, n^3/3 flops) and the inverse from that factor
+    (steps 2 and 3 after the factor prologue, 2n^3/3 flops)."""
+    b = a_cm.clone()
+    spd.cholesky_(b.t(), work=work, report=True)            # plan + warm
+    lsrc = b.clone()                                         # L in the lower triangle
+    ms_chol = time_events(lambda: spd.cholesky_(b.t(), work=work), reps,
+                          prep=lambda: b.copy_(a_cm))
+    spd.inverse_from_factor_(b.t(), work=work, report=True)  # plan + warm (b holds L)
+    ms_inv = time_events(lambda: spd.inverse_from_factor_(b.t(), work=work), reps,
+                         prep=lambda: b.copy_(lsrc))
+    out = {"workload": f"n={n}, FP64, same input as the headline line", "reps": reps}
+    for key, ms, fl in (("cholesky", ms_chol, n ** 3 / 3.0), ("inverse_from_factor", ms_inv,
+                                                                2.0 * n ** 3 / 3.0)):
+        out[key] = {"ms": round(ms, 3), "gflops": round(fl / ms / 1e6, 1),
+                    "frac_fp64_peak": round(fl / ms / 1e9 / PEAK_FP64_TFLOPS, 4)}
+    return out
+
+
 def backward_row(reps: int):
     """Differentiation workload (a): grad_A = -X sym(G) X at n = 4096."""
     import torch
@@ -234,8 +254,8 @@ def main():
     ap.add_argument("--kappa", type=float, default=1e4)
     ap.add_argument("--cpu-n", type=int, default=8192, help="oracle sample order (0 = skip)")
     ap.add_argument("--no-unpipelined", action="store_true")
-    ap.add_argument("--rows", default="batched,backward,mixed,ablation",
-                    help="extra measured rows: batched, backward, mixed, ablation "
+    ap.add_argument("--rows", default="batched,backward,mixed,ablation,steps",
+                    help="extra measured rows: batched, backward, mixed, ablation, steps "
                          "(comma list, '' = none)")
     ap.add_argument("--input", choices=["spectrum", "wishart"], default="spectrum",
                     help="wishart (B B^T/n + I, no QR) is for profiler counter runs only")
@@ -345,6 +365,9 @@ def main():
         rows["mixed"] = mixed_row(max(2, min(K, 3)))
     if ablation is not None:
         rows["ablation"] = ablation
+    if "steps" in wanted:
+        log("[bench] steps row")
+        rows["steps"] = steps_row(spd, a_cm, work, n, max(2, min(K, 5)))
 
     cpu = None
     if args.cpu_n > 0:
