@@ -95,7 +95,7 @@ typedef struct {
                       are bit-identical for every value.  The last product
                       before a chain's closing task always runs alone.  */
   int per_cu;      /* FP64 form: persistent workgroups per compute unit (0 =
-                      library choice: 2 when the matrix has at least 128 tiles
+                      library choice: 2 when the matrix has at least 96 tiles
                       per side, where the DAG keeps enough tasks ready, else
                       1; or 1 or 2).  Results do not depend on it.           */
 } spdinv_opts;

@@ -126,10 +126,10 @@ int check_opts(const spdinv_opts& o) {
 
 // Persistent workgroups per CU for an order of t tiles.  The scheduler's
 // kernel fits two on a CU, which pays only where the DAG keeps twice as many
-// tasks ready: at 128 tiles per side two per CU are 4% faster, at 64 they
-// are 30% slower (workers wait for dependencies while the busy ones share
-// CUs).
-constexpr int kWideTiles = 128;
+// tasks ready.  Measured against one per CU: 30% slower at 64 tiles per
+// side (workers wait for dependencies while the busy ones share CUs), 5%
+// slower at 80, 11% faster at 96, 14% at 112, 4-8% at 128.
+constexpr int kWideTiles = 96;
 
 int per_cu_for(int t, const spdinv_opts& o) {
   static int capacity = 0;  // workgroups per CU that fit (same for every device here)
