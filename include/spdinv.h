@@ -182,6 +182,36 @@ int spd_inverse_from_factor(int n, double* L, int ldl, void* work, size_t work_b
                             spdinv_stream_t stream, const spdinv_opts* opts, int* d_info,
                             spdinv_report* report);
 
+/*
+ * Solve A X = B for an SPD A: the Cholesky factor by step 1 of Algorithm 1,
+ * then the forward substitution L Y = B and the backward substitution
+ * L^T X = Y over 128 x 128 tiles of B, all in one DAG on the scheduler (the
+ * substitutions multiply by the inverted diagonal tiles that step 1 makes,
+ * as its TRSMs do).  As LAPACK's xPOSV: the lower triangle of A is replaced
+ * by L (the strictly upper triangle is neither read nor written) and B
+ * (column-major n x nrhs, ldb >= max(1,n)) by X.  Workspace:
+ * spd_solve_workspace_bytes(n, nrhs, opts).  d_info: INFO = k > 0 when the
+ * leading minor of order k is not positive definite (A and B are then
+ * unspecified).  Returns 0, -i for an invalid i-th argument,
+ * SPDINV_ERR_WORKSPACE or SPDINV_ERR_HIP.  nrhs <= 8192.
+ */
+size_t spd_solve_workspace_bytes(int n, int nrhs, const spdinv_opts* opts);
+int spd_solve(int n, int nrhs, double* A, int lda, double* B, int ldb, void* work,
+              size_t work_bytes, spdinv_stream_t stream, const spdinv_opts* opts, int* d_info,
+              spdinv_report* report);
+
+/*
+ * Solve with a given Cholesky factor (as LAPACK's xPOTRS): the lower triangle
+ * of L (column-major, ldl) holds the factor and is only read; B (n x nrhs,
+ * ldb) is replaced by X with L L^T X = B.  The prologue of
+ * spd_inverse_from_factor makes the inverted diagonal tiles and the
+ * transposed copies of L's tiles.  INFO = k > 0 when L_kk = 0.  Workspace,
+ * return codes and the other arguments as for spd_solve.
+ */
+int spd_solve_from_factor(int n, int nrhs, const double* L, int ldl, double* B, int ldb,
+                          void* work, size_t work_bytes, spdinv_stream_t stream,
+                          const spdinv_opts* opts, int* d_info, spdinv_report* report);
+
 /* ---- batched form ---------------------------------------------------------- */
 /* Bytes of device workspace that batched_spd_inverse needs for these orders
    on the current device (0 when batch <= 0 or an order is invalid). */
@@ -261,7 +291,7 @@ enum {
   SPDINV_TASK_NOP = 0, SPDINV_TASK_SYRK1 = 1, SPDINV_TASK_POTRF = 2, SPDINV_TASK_GEMM1 = 3,
   SPDINV_TASK_TRSM1 = 4, SPDINV_TASK_TRTRI = 5, SPDINV_TASK_TRMM2L = 6, SPDINV_TASK_GEMM2 = 7,
   SPDINV_TASK_TRSM2R = 8, SPDINV_TASK_TRMM3 = 9, SPDINV_TASK_LAUUM = 10, SPDINV_TASK_GEMM3 = 11,
-  SPDINV_TASK_SYRK3 = 12
+  SPDINV_TASK_SYRK3 = 12, SPDINV_TASK_GEMMS = 13, SPDINV_TASK_TRSMS = 14
 };
 
 /* Builds (without caching) the plan for t tiles per side and returns its
@@ -286,12 +316,16 @@ int spdinv_plan_export(int t, const spdinv_opts* opts, int workers, int32_t* tas
                        long long* ntasks, long long* nsucc, int32_t* links,
                        long long* nlinks);
 /* The same for a plan of some steps of Algorithm 1: steps = 7 (the SPD
-   inverse, as spdinv_plan_export), 1 (the plan of spd_cholesky) or 6 (the
-   plan of spd_inverse_from_factor).  Returns -2 for another value. */
-int spdinv_plan_export_steps(int steps, int t, const spdinv_opts* opts, int workers,
-                             int32_t* tasks8, int32_t* succ, int32_t* step, int32_t* idx,
-                             int32_t* order, long long* ntasks, long long* nsucc, int32_t* links,
-                             long long* nlinks);
+   inverse, as spdinv_plan_export), 1 (the plan of spd_cholesky), 6 (the
+   plan of spd_inverse_from_factor), 9 (spd_solve: step 1, then the forward
+   and backward substitutions) or 8 (spd_solve_from_factor), with rhs_tiles
+   = ceil(nrhs/128) tile columns of right-hand sides (1..64) for 9 and 8 and
+   0 otherwise.  Right-hand-side tile (i, c) is pool tile 3T + 2t + i + t c.
+   Returns -2 for another combination. */
+int spdinv_plan_export_steps(int steps, int rhs_tiles, int t, const spdinv_opts* opts,
+                             int workers, int32_t* tasks8, int32_t* succ, int32_t* step,
+                             int32_t* idx, int32_t* order, long long* ntasks, long long* nsucc,
+                             int32_t* links, long long* nlinks);
 
 /* ---- per-task trace (opts.trace = 1) -------------------------------------- */
 /* Copies the per-task trace that the last spd_inverse call with

@@ -13,6 +13,7 @@ Algorithm 1 at tile order b = 1 (Section 2):
 * :func:`lauum`   -- stage 3, A^{-1} = X^T X (lower triangle)
 * :func:`spd_inverse` -- the three stages in sequence
 * :func:`inverse_grad` -- -Y S Y with S = (G + G^T)/2, Y = A^{-1}
+* :func:`potrs`   -- the solve A X = B with the factor L (substitutions)
 
 Matrices are handled as ordinary (row-major) numpy arrays of the *full*
 matrix; the wrapper converts to the column-major lower-triangle convention of
@@ -65,6 +66,8 @@ def _bind(path: str):
     lib.oracle_spd_inverse.restype = i
     lib.oracle_inverse_grad.argtypes = [i, dp, i, dp, i, dp, i]
     lib.oracle_inverse_grad.restype = i
+    lib.oracle_potrs.argtypes = [i, i, dp, i, dp, i]
+    lib.oracle_potrs.restype = i
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = i
     lib.oracle_set_num_threads.argtypes = [i]
@@ -125,6 +128,21 @@ def lauum(x: np.ndarray) -> np.ndarray:
     out = np.zeros((n, n), dtype=np.float64, order="F")
     _load().oracle_lauum(n, _ptr(x), max(1, n), _ptr(out), max(1, n))
     return np.ascontiguousarray(np.tril(out))
+
+
+def potrs(l: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Solve with the Cholesky factor: X with L L^T X = B (forward, then
+    backward substitution; only the lower triangle of ``l`` is read)."""
+    l = _colmajor(l)
+    n = l.shape[0]
+    b2 = np.array(b, dtype=np.float64, order="F", copy=True)
+    if b2.ndim == 1:
+        b2 = b2.reshape(n, 1, order="F")
+    nrhs = b2.shape[1]
+    info = _load().oracle_potrs(n, nrhs, _ptr(l), max(1, n), _ptr(b2), max(1, n))
+    if info:
+        raise OracleInfo(info)
+    return np.ascontiguousarray(b2).reshape(np.shape(b))
 
 
 def spd_inverse_lower(a: np.ndarray) -> np.ndarray:

@@ -237,3 +237,34 @@ int oracle_inverse_grad(int n, const double* Ylow, int ldy, const double* G, int
   free(Yc);
   return 0;
 }
+
+
+/*
+ * Solve with the Cholesky factor (the solve that the factor of step 1 of
+ * Alg. 1 serves, Section 2): A X = B with A = L L^T, by plain substitutions
+ * per right-hand side column, natural order:
+ *   forward   y_i = (b_i - sum_{k<i} l_ik y_k) / l_ii,     i = 0..n-1
+ *   backward  x_i = (y_i - sum_{k>i} l_ki x_k) / l_ii,     i = n-1..0
+ * L: lower triangle (column-major, ldl; the upper part is not read).
+ * B: column-major n x nrhs (ldb), overwritten by X.  Returns 0, or i+1 when
+ * l_ii = 0.
+ */
+int oracle_potrs(int n, int nrhs, const double* L, int ldl, double* B, int ldb) {
+  for (int i = 0; i < n; ++i)
+    if (CM(L, ldl, i, i) == 0.0) return i + 1;
+#pragma omp parallel for schedule(static)
+  for (int c = 0; c < nrhs; ++c) {
+    double* b = B + (size_t)ldb * c;
+    for (int i = 0; i < n; ++i) {
+      double s = b[i];
+      for (int k = 0; k < i; ++k) s -= CM(L, ldl, i, k) * b[k];
+      b[i] = s / CM(L, ldl, i, i);
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double s = b[i];
+      for (int k = i + 1; k < n; ++k) s -= CM(L, ldl, k, i) * b[k];
+      b[i] = s / CM(L, ldl, i, i);
+    }
+  }
+  return 0;
+}

@@ -27,6 +27,7 @@ __all__ = ["spd_inverse", "spd_inverse_", "workspace_bytes", "plan_stats", "plan
            "spd_inverse_backward", "backward_workspace_bytes", "SpdInverse", "spd_inverse_ad",
            "batched_spd_inverse", "batched_spd_inverse_", "batched_workspace_bytes",
            "cholesky", "cholesky_", "inverse_from_factor", "inverse_from_factor_",
+           "solve", "solve_", "solve_from_factor", "solve_from_factor_",
            "SpdInverseError", "NotPositiveDefinite"]
 
 
@@ -174,6 +175,79 @@ def inverse_from_factor(l, return_report: bool = False, **opts):
     buf = l.t().contiguous()
     rep = inverse_from_factor_(buf.t(), report=True, fill_upper=1, **opts) if n else None
     x = buf.t().contiguous() if n else torch.empty_like(l)
+    return (x, rep) if return_report else x
+
+
+def _colmajor_check(x, rows=None):
+    import torch
+    if x.dtype != torch.float64 or not x.is_cuda or x.dim() != 2:
+        raise TypeError("expected a 2-D CUDA float64 tensor")
+    if rows is not None and x.shape[0] != rows:
+        raise ValueError("row count does not match the matrix order")
+    if x.shape[0] > 1 and x.shape[1] > 0 and x.stride(0) != 1:
+        raise ValueError("expected a column-major view (stride(0) == 1)")
+    return max(1, x.stride(1) if x.shape[0] > 1 and x.shape[1] > 1 else max(1, x.shape[0]))
+
+
+def _solve_entry(name, a_cm, b_cm, work, report, info, opts):
+    import torch
+    n = a_cm.shape[0]
+    if a_cm.shape[1] != n:
+        raise ValueError("matrix must be square")
+    lda = _colmajor_check(a_cm)
+    ldb = _colmajor_check(b_cm, rows=n)
+    nrhs = b_cm.shape[1]
+    lib = load()
+    o = make_opts(**opts)
+    need = int(lib.spd_solve_workspace_bytes(n, nrhs, ctypes.byref(o)))
+    if work is None:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=a_cm.device)
+    elif work.numel() * work.element_size() < need:
+        raise ValueError(f"workspace too small: need {need} bytes")
+    rep = _lib.Report()
+    info_ptr = info.data_ptr() if info is not None else None
+    rc = getattr(lib, name)(n, nrhs, a_cm.data_ptr(), lda, b_cm.data_ptr(), ldb,
+                            work.data_ptr(), need, _stream_ptr(a_cm.device), ctypes.byref(o),
+                            info_ptr, ctypes.byref(rep) if report else None)
+    if rc != 0:
+        raise SpdInverseError(f"{name} returned {rc}")
+    if report:
+        r = {f: getattr(rep, f) for f, _ in _lib.Report._fields_}
+        if r["info"] > 0:
+            raise NotPositiveDefinite(r["info"])
+        return r
+    return None
+
+
+def solve_(a_cm, b_cm, *, work=None, report: bool = False, info=None, **opts):
+    """A X = B in place on column-major CUDA float64 views (as xPOSV): the
+    lower triangle of A is replaced by its Cholesky factor L and B (n x nrhs)
+    by X."""
+    return _solve_entry("spd_solve", a_cm, b_cm, work, report, info, opts)
+
+
+def solve(a, b, return_report: bool = False, **opts):
+    """X with A X = B for a CUDA float64 SPD A (lower triangle read) and a
+    CUDA float64 B of shape (n, nrhs); A and B are not modified."""
+    abuf = a.t().contiguous()
+    bbuf = b.t().contiguous()
+    rep = solve_(abuf.t(), bbuf.t(), report=True, **opts) if a.shape[-1] else None
+    x = bbuf.t().contiguous()
+    return (x, rep) if return_report else x
+
+
+def solve_from_factor_(l_cm, b_cm, *, work=None, report: bool = False, info=None, **opts):
+    """L L^T X = B in place on column-major CUDA float64 views (as xPOTRS):
+    the lower triangle of L holds the factor (only read); B is replaced by X."""
+    return _solve_entry("spd_solve_from_factor", l_cm, b_cm, work, report, info, opts)
+
+
+def solve_from_factor(l, b, return_report: bool = False, **opts):
+    """X with L L^T X = B for a CUDA float64 lower Cholesky factor L."""
+    lbuf = l.t().contiguous()
+    bbuf = b.t().contiguous()
+    rep = solve_from_factor_(lbuf.t(), bbuf.t(), report=True, **opts) if l.shape[-1] else None
+    x = bbuf.t().contiguous()
     return (x, rep) if return_report else x
 
 
@@ -360,16 +434,19 @@ def plan_stats(t: int, **opts) -> dict:
             "cp_plan": st.cp_plan}
 
 
-def plan_export(t: int, workers: int = 1, steps: int = 7, **opts) -> dict:
+def plan_export(t: int, workers: int = 1, steps: int = 7, rhs_tiles: int = 0, **opts) -> dict:
     """The plan as numpy arrays: tasks (ntasks x 8 int32), succ, step, idx,
     order, and links (nlinks x 2 int32: the further operand pairs of chained
     product tasks).  ``steps``: 7 the SPD inverse, 1 the Cholesky factor
-    only, 6 the inverse from a given factor."""
+    only, 6 the inverse from a given factor, 9 the solve (factor, then the
+    substitutions over ``rhs_tiles`` tile columns), 8 the solve with a given
+    factor."""
     lib = load()
     o = make_opts(**opts)
     nt, ns, nl = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
-    if lib.spdinv_plan_export_steps(int(steps), int(t), ctypes.byref(o), int(workers), None, None,
-                                    None, None, None, ctypes.byref(nt), ctypes.byref(ns), None,
+    if lib.spdinv_plan_export_steps(int(steps), int(rhs_tiles), int(t), ctypes.byref(o),
+                                    int(workers), None, None, None, None, None,
+                                    ctypes.byref(nt), ctypes.byref(ns), None,
                                     ctypes.byref(nl)) != 0:
         raise ValueError("invalid tile count or steps")
     tasks = np.zeros((nt.value, 8), dtype=np.int32)
@@ -379,8 +456,9 @@ def plan_export(t: int, workers: int = 1, steps: int = 7, **opts) -> dict:
     order = np.zeros(nt.value, dtype=np.int32)
     links = np.zeros(max(nl.value, 2), dtype=np.int32)
     p = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
-    lib.spdinv_plan_export_steps(int(steps), int(t), ctypes.byref(o), int(workers), p(tasks),
-                                 p(succ), p(step), p(idx), p(order), None, None, p(links), None)
+    lib.spdinv_plan_export_steps(int(steps), int(rhs_tiles), int(t), ctypes.byref(o),
+                                 int(workers), p(tasks), p(succ), p(step), p(idx), p(order), None,
+                                 None, p(links), None)
     return {"tasks": tasks, "succ": succ[:ns.value], "step": step, "idx": idx, "order": order,
             "links": links[:nl.value].reshape(-1, 2), "t": int(t), "T": t * (t + 1) // 2}
 

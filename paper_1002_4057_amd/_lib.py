@@ -76,6 +76,12 @@ def load():
         fn = getattr(lib, name)
         fn.argtypes = [i, vp, i, vp, sz, vp, P(Opts), vp, P(Report)]
         fn.restype = i
+    for name in ("spd_solve", "spd_solve_from_factor"):
+        fn = getattr(lib, name)
+        fn.argtypes = [i, i, vp, i, vp, i, vp, sz, vp, P(Opts), vp, P(Report)]
+        fn.restype = i
+    lib.spd_solve_workspace_bytes.argtypes = [i, i, P(Opts)]
+    lib.spd_solve_workspace_bytes.restype = sz
     lib.spdinv_release_plans.argtypes = []
     lib.spdinv_release_plans.restype = None
     lib.spdinv_plan_stats_get.argtypes = [i, P(Opts), P(PlanStats)]
@@ -85,7 +91,7 @@ def load():
                                        P(ctypes.c_longlong), P(ctypes.c_longlong), i32p,
                                        P(ctypes.c_longlong)]
     lib.spdinv_plan_export.restype = i
-    lib.spdinv_plan_export_steps.argtypes = [i] + lib.spdinv_plan_export.argtypes
+    lib.spdinv_plan_export_steps.argtypes = [i, i] + lib.spdinv_plan_export.argtypes
     lib.spdinv_plan_export_steps.restype = i
     lib.spdinv_trace_copy.argtypes = [vp, i, P(Opts), P(ctypes.c_int64), ctypes.c_longlong]
     lib.spdinv_trace_copy.restype = ctypes.c_longlong

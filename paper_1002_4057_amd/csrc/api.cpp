@@ -42,6 +42,8 @@ const double kCost[K_COUNT + 1] = {
     1.0,    // LAUUM
     1.0,    // GEMM3
     1.0,    // SYRK3
+    1.2,    // GEMMS (solve update; general product, untransposed operand)
+    1.2,    // TRSMS (solve: multiplication by D_i or D_i^T)
     0.76,   // each further link of a chained product
 };
 
@@ -49,11 +51,11 @@ const double kCost[K_COUNT + 1] = {
 constexpr int kDefaultChain = 8;
 
 struct Key {
-  int device, t, renamed, loop_order, pipelined, trtri_first, workers, chain, steps;
+  int device, t, renamed, loop_order, pipelined, trtri_first, workers, chain, steps, rhs;
   bool operator<(const Key& o) const {
-    return std::tie(device, t, renamed, loop_order, pipelined, trtri_first, workers, chain, steps) <
-           std::tie(o.device, o.t, o.renamed, o.loop_order, o.pipelined, o.trtri_first, o.workers,
-                    o.chain, o.steps);
+    return std::tie(device, t, renamed, loop_order, pipelined, trtri_first, workers, chain, steps,
+                    rhs) < std::tie(o.device, o.t, o.renamed, o.loop_order, o.pipelined,
+                                    o.trtri_first, o.workers, o.chain, o.steps, o.rhs);
   }
 };
 
@@ -103,12 +105,13 @@ struct Layout {
   size_t pool, indeg, ctrl, trace, total;
 };
 
-Layout layout(int n, const spdinv_opts& o) {
+Layout layout(int n, const spdinv_opts& o, int nrhs = 0) {
   Layout L;
   const int t = tiles_for(n);
-  const long long nt = task_count(t);
+  const int s = (nrhs + NB - 1) / NB;
+  const long long nt = task_count(t) + 2LL * t * t * s;  // + the solve's tasks
   L.pool = 0;
-  L.indeg = align_up((size_t)pool_tiles(t) * NB * NB * sizeof(double), 256);
+  L.indeg = align_up((size_t)pool_tiles(t, s) * NB * NB * sizeof(double), 256);
   L.ctrl = L.indeg + align_up((size_t)nt * sizeof(int32_t), 256);
   L.trace = L.ctrl + align_up(CTRL_WORDS * sizeof(int32_t), 256);
   L.total = L.trace + (o.trace ? align_up((size_t)nt * 4 * sizeof(long long), 256) : 0);
@@ -165,9 +168,9 @@ int grid_for(int device, int t, const spdinv_opts& o) {
 // chain) and kept with its device copy.  chain: most products per device
 // task (1 for executors that run the paper's tasks one by one).
 DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, int chain,
-                  hipError_t* err, int steps = 7) {
+                  hipError_t* err, int steps = 7, int rhs_tiles = 0) {
   Key k{device, t, o.renamed ? 1 : 0, o.loop_order, o.pipelined ? 1 : 0, o.trtri_first ? 1 : 0,
-        workers, chain, steps};
+        workers, chain, steps, rhs_tiles};
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_plans.find(k);
   if (it != g_plans.end()) return it->second.get();
@@ -180,6 +183,7 @@ DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, int chai
   po.trtri_first = k.trtri_first;
   po.chain = k.chain;
   po.steps = k.steps;
+  po.rhs_tiles = k.rhs;
   build_plan(po, workers, kCost, &dp->host);
   const Plan& p = dp->host;
   const size_t nt = p.tasks.size();
@@ -268,8 +272,10 @@ long long spin_limit() {
 // given factor (steps 2 and 3) a prologue kernel first makes what step 1
 // would leave for step 2.
 int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream_t stream,
-             const spdinv_opts& o, int* d_info, spdinv_report* report, int steps = 7) {
-  const Layout L = layout(n, o);
+             const spdinv_opts& o, int* d_info, spdinv_report* report, int steps = 7,
+             int nrhs = 0, double* Bm = nullptr, int ldb = 1) {
+  const Layout L = layout(n, o, nrhs);
+  const int s = (nrhs + NB - 1) / NB;
   if (work_bytes < L.total) return SPDINV_ERR_WORKSPACE;
 
   int device = 0;
@@ -277,7 +283,7 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   const int t = tiles_for(n);
   const int grid = grid_for(device, t, o);
   hipError_t err = hipSuccess;
-  DevPlan* dp = get_plan(device, t, o, grid, chain_for(o), &err, steps);
+  DevPlan* dp = get_plan(device, t, o, grid, chain_for(o), &err, steps, s);
   if (!dp) return SPDINV_ERR_HIP;
   const int ntask = (int)dp->host.tasks.size();
 
@@ -289,8 +295,10 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
 
   if (launch_reset(dp->d_indeg0, indeg, ntask, ctrl, stream) != hipSuccess) return SPDINV_ERR_HIP;
   if (launch_copy_in(A, lda, n, t, pool, stream) != hipSuccess) return SPDINV_ERR_HIP;
-  if (steps == 6 && launch_factor_prologue(pool, t, ctrl, stream) != hipSuccess)
+  if ((steps == 6 || steps == 8) && launch_factor_prologue(pool, t, ctrl, stream) != hipSuccess)
     return SPDINV_ERR_HIP;
+  double* rhs = pool + (size_t)pool_tiles(t) * NB * NB;  // R tiles, after the other regions
+  if (s && launch_rhs_in(Bm, ldb, n, nrhs, t, rhs, stream) != hipSuccess) return SPDINV_ERR_HIP;
   SchedArgs a;
   a.tasks = dp->d_tasks;
   a.succ = dp->d_succ;
@@ -312,8 +320,13 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   if (launch_sched(a, grid, per_cu_for(t, o), stream) != hipSuccess) return SPDINV_ERR_HIP;
   if (timed && hipEventRecord(ev1, stream) != hipSuccess) return SPDINV_ERR_HIP;
   // the Cholesky factor leaves the strictly upper triangle untouched
-  if (launch_copy_out(pool, t, A, lda, n, steps == 1 ? 0 : o.fill_upper, stream) != hipSuccess)
+  // the factor leaves the strictly upper triangle untouched; a given factor
+  // (the solve with it) is not written back
+  if (steps != 8 &&
+      launch_copy_out(pool, t, A, lda, n, (steps & 1) && !(steps & 2) ? 0 : o.fill_upper,
+                      stream) != hipSuccess)
     return SPDINV_ERR_HIP;
+  if (s && launch_rhs_out(rhs, t, n, nrhs, Bm, ldb, stream) != hipSuccess) return SPDINV_ERR_HIP;
   if (launch_info_out(ctrl, d_info, stream) != hipSuccess) return SPDINV_ERR_HIP;
 
   if (report) {
@@ -724,6 +737,64 @@ int spd_inverse_from_factor(int n, double* L, int ldl, void* work, size_t work_b
   return fp64_entry(n, L, ldl, work, work_bytes, stream, opts, d_info, report, 6);
 }
 
+size_t spd_solve_workspace_bytes(int n, int nrhs, const spdinv_opts* opts) {
+  if (n < 0 || nrhs < 0) return 0;
+  const spdinv_opts o = opts ? *opts : defaults();
+  return layout(n, o, nrhs).total;
+}
+
+// The solve entry points: the factor (steps 1, with_factor = 0) or a given
+// one (with_factor = 1), then the forward and backward substitutions.
+static int solve_entry(int n, int nrhs, double* A, int lda, double* Bm, int ldb, void* work,
+                       size_t work_bytes, spdinv_stream_t stream_, const spdinv_opts* opts,
+                       int* d_info, spdinv_report* report, bool with_factor) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  if (n < 0) return -1;
+  if (nrhs < 0 || nrhs > 64 * NB) return -2;
+  if (n > 0 && !A) return -3;
+  if (lda < (n > 1 ? n : 1)) return -4;
+  if (n > 0 && nrhs > 0 && !Bm) return -5;
+  if (ldb < (n > 1 ? n : 1)) return -6;
+  const spdinv_opts o = opts ? *opts : defaults();
+  if (check_opts(o)) return -10;
+  if (report) std::memset(report, 0, sizeof(*report));
+  if (n == 0) {
+    if (d_info) {
+      int zero = 0;
+      if (hipMemcpyAsync(d_info, &zero, sizeof(int), hipMemcpyHostToDevice, stream) != hipSuccess)
+        return SPDINV_ERR_HIP;
+      if (hipStreamSynchronize(stream) != hipSuccess) return SPDINV_ERR_HIP;
+    }
+    return 0;
+  }
+  if (!work) return -7;
+  const int steps = (with_factor ? 0 : 1) | (nrhs > 0 ? 8 : 0);
+  if (steps == 0) {  // a given factor and no right-hand side: nothing to do
+    if (d_info) {
+      int zero = 0;
+      if (hipMemcpyAsync(d_info, &zero, sizeof(int), hipMemcpyHostToDevice, stream) != hipSuccess)
+        return SPDINV_ERR_HIP;
+      if (hipStreamSynchronize(stream) != hipSuccess) return SPDINV_ERR_HIP;
+    }
+    return 0;
+  }
+  return run_fp64(n, A, lda, work, work_bytes, stream, o, d_info, report, steps, nrhs, Bm, ldb);
+}
+
+int spd_solve(int n, int nrhs, double* A, int lda, double* B, int ldb, void* work,
+              size_t work_bytes, spdinv_stream_t stream, const spdinv_opts* opts, int* d_info,
+              spdinv_report* report) {
+  return solve_entry(n, nrhs, A, lda, B, ldb, work, work_bytes, stream, opts, d_info, report,
+                     false);
+}
+
+int spd_solve_from_factor(int n, int nrhs, const double* L, int ldl, double* B, int ldb,
+                          void* work, size_t work_bytes, spdinv_stream_t stream,
+                          const spdinv_opts* opts, int* d_info, spdinv_report* report) {
+  return solve_entry(n, nrhs, const_cast<double*>(L), ldl, B, ldb, work, work_bytes, stream, opts,
+                     d_info, report, true);
+}
+
 void spdinv_release_plans(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (auto& kv : g_plans)
@@ -760,19 +831,21 @@ int spdinv_plan_stats_get(int t, const spdinv_opts* opts, spdinv_plan_stats* out
 int spdinv_plan_export(int t, const spdinv_opts* opts, int workers, int32_t* tasks8, int32_t* succ,
                        int32_t* step, int32_t* idx, int32_t* order, long long* ntasks,
                        long long* nsucc, int32_t* links, long long* nlinks) {
-  return spdinv_plan_export_steps(7, t, opts, workers, tasks8, succ, step, idx, order, ntasks,
+  return spdinv_plan_export_steps(7, 0, t, opts, workers, tasks8, succ, step, idx, order, ntasks,
                                   nsucc, links, nlinks);
 }
 
-int spdinv_plan_export_steps(int steps, int t, const spdinv_opts* opts, int workers,
+int spdinv_plan_export_steps(int steps, int rhs_tiles, int t, const spdinv_opts* opts, int workers,
                              int32_t* tasks8, int32_t* succ, int32_t* step, int32_t* idx,
                              int32_t* order, long long* ntasks, long long* nsucc, int32_t* links,
                              long long* nlinks) {
   if (t < 1 || t > 1024) return -1;
-  if (steps != 7 && steps != 1 && steps != 6) return -2;
+  if (steps != 7 && steps != 1 && steps != 6 && steps != 9 && steps != 8) return -2;
+  if ((steps & 8) ? (rhs_tiles < 1 || rhs_tiles > 64) : rhs_tiles != 0) return -2;
   Plan p;
   PlanOptions po = plan_options(t, opts);
   po.steps = steps;
+  po.rhs_tiles = rhs_tiles;
   build_plan(po, workers > 0 ? workers : 1, kCost, &p);
   if (ntasks) *ntasks = (long long)p.tasks.size();
   if (nsucc) *nsucc = (long long)p.succ.size();

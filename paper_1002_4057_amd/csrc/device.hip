@@ -112,6 +112,33 @@ __global__ void info_out_kernel(const int32_t* ctrl, int* d_info) {
   d_info[0] = (v == INT_MAX) ? 0 : v;
 }
 
+// Right-hand sides (column-major n x nrhs, ldb) <-> the transposed tiles
+// R_ic^T (tile i + t c of the block R: element (r, q) is B(128 i + q,
+// 128 c + r)), zero outside B.  Global accesses run down the columns of B.
+__global__ __launch_bounds__(NTHREADS) void rhs_in_kernel(const double* __restrict__ B, int ldb,
+                                                          int n, int nrhs, int t,
+                                                          double* __restrict__ R) {
+  const int i = blockIdx.x % t, c = blockIdx.x / t;
+  double* dst = R + (size_t)blockIdx.x * TILE;
+  for (int e = threadIdx.x; e < (int)TILE; e += NTHREADS) {
+    const int q = e & (NB - 1), r = e >> 7;  // matrix row 128 i + q, right-hand side 128 c + r
+    const int gr = i * NB + q, gc = c * NB + r;
+    dst[r + NB * q] = (gr < n && gc < nrhs) ? B[gr + (size_t)ldb * gc] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(NTHREADS) void rhs_out_kernel(const double* __restrict__ R, int t,
+                                                           int n, int nrhs, double* __restrict__ B,
+                                                           int ldb) {
+  const int i = blockIdx.x % t, c = blockIdx.x / t;
+  const double* src = R + (size_t)blockIdx.x * TILE;
+  for (int e = threadIdx.x; e < (int)TILE; e += NTHREADS) {
+    const int q = e & (NB - 1), r = e >> 7;
+    const int gr = i * NB + q, gc = c * NB + r;
+    if (gr < n && gc < nrhs) B[gr + (size_t)ldb * gc] = src[r + NB * q];
+  }
+}
+
 }  // namespace
 
 hipError_t launch_reset(const int32_t* indeg0, int32_t* indeg, int ntask, int32_t* ctrl,
@@ -119,6 +146,20 @@ hipError_t launch_reset(const int32_t* indeg0, int32_t* indeg, int ntask, int32_
   const int total = ntask > CTRL_WORDS ? ntask : CTRL_WORDS;
   const int blocks = (total + 255) / 256;
   hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, indeg0, indeg, ntask, ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_in(const double* B, int ldb, int n, int nrhs, int t, double* R,
+                         hipStream_t s) {
+  const int tiles = t * ((nrhs + NB - 1) / NB);
+  hipLaunchKernelGGL(rhs_in_kernel, dim3(tiles), dim3(NTHREADS), 0, s, B, ldb, n, nrhs, t, R);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_out(const double* R, int t, int n, int nrhs, double* B, int ldb,
+                          hipStream_t s) {
+  const int tiles = t * ((nrhs + NB - 1) / NB);
+  hipLaunchKernelGGL(rhs_out_kernel, dim3(tiles), dim3(NTHREADS), 0, s, R, t, n, nrhs, B, ldb);
   return hipGetLastError();
 }
 

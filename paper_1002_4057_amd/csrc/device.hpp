@@ -90,6 +90,14 @@ hipError_t launch_info_out(const int32_t* ctrl, int* d_info, hipStream_t s);
 // tiles in the pool (after copy-in).  Sets INFO on a zero diagonal entry.
 hipError_t launch_factor_prologue(double* pool, int t, int32_t* ctrl, hipStream_t s);
 
+// Right-hand sides of the solve: column-major B (n x nrhs, ldb) into the
+// transposed tiles R (t x ceil(nrhs/128) tiles, tile i + t c holds R_ic^T,
+// zero outside B) and back.
+hipError_t launch_rhs_in(const double* B, int ldb, int n, int nrhs, int t, double* R,
+                         hipStream_t s);
+hipError_t launch_rhs_out(const double* R, int t, int n, int nrhs, double* B, int ldb,
+                          hipStream_t s);
+
 // Persistent scheduler over the plan's tasks.
 // per_cu: 1 keeps every workgroup alone on its CU, 2 lets two share one.
 hipError_t launch_sched(const SchedArgs& a, int grid, int per_cu, hipStream_t s);

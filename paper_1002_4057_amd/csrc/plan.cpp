@@ -25,8 +25,9 @@ struct Builder {
 
   Builder(const PlanOptions& opt, Plan* plan) : o(opt), t(opt.t), p(plan) {
     T = t * (t + 1) / 2;
-    last_writer.assign(3 * (size_t)T, -1);
-    readers.resize(3 * (size_t)T);
+    const size_t names = 3 * (size_t)T + (size_t)t * opt.rhs_tiles;
+    last_writer.assign(names, -1);
+    readers.resize(names);
   }
 
   int tri(int i, int j) const { return i * (i + 1) / 2 + j; }
@@ -34,6 +35,9 @@ struct Builder {
   int B(int i, int j) const { return T + tri(i, j); }
   int C(int i, int j) const { return 2 * T + tri(i, j); }
   int D(int j) const { return 3 * T + j; }
+  // right-hand-side tile (i, c): hazard name and pool index
+  int Rh(int i, int c) const { return 3 * T + i + t * c; }
+  int Rp(int i, int c) const { return 3 * T + 2 * t + i + t * c; }
 
   // Emits one task.  reads/writes are hazard names (A/B/C tile ids); the
   // device operands are given separately.
@@ -207,6 +211,43 @@ struct Builder {
                F_TA | F_LOWER | F_ACC);
       }
     }
+  }
+
+  // The solve A X = R with A = L L^T, over the s tile columns of R: forward
+  // substitution L Y = R (row i: R_ic -= L_ik Y_kc for k = 0..i-1, then Y_ic =
+  // D_i R_ic), then backward L^T X = Y (row i from the last: R_ic -= L_ki^T
+  // X_kc for k = t-1 down to i+1, then X_ic = D_i^T R_ic).  The explicit
+  // diagonal inverses D_i replace the triangular solves with the diagonal
+  // tiles, as in steps 1 and 2.  The right-hand-side tiles are kept
+  // transposed (tile (i, c) holds R_ic^T), so that every product has the
+  // column form C -= A B^T of the renamed plan: R_ic^T -= R_kc^T L_ik^T,
+  // R_ic^T <- R_ic^T D_i^T, R_ic^T -= R_kc^T L_ki (B = the renaming copy
+  // L_ki^T), R_ic^T <- R_ic^T D_i (B = D_i^T); the in-place plan reads L_ki
+  // untransposed instead.
+  void solve() {
+    cur_step = 4;
+    const int s = o.rhs_tiles;
+    for (int i = 0; i < t; ++i)
+      for (int c = 0; c < s; ++c) {
+        for (int k = 0; k < i; ++k)
+          emit(K_GEMMS, i, c, k, {A(i, k), Rh(k, c), Rh(i, c)}, {Rh(i, c)}, Rp(i, c), Rp(k, c),
+               A(i, k), -1, -1, F_TB | F_NEG | F_ACC);
+        emit(K_TRSMS, i, c, 0, {A(i, i), Rh(i, c)}, {Rh(i, c)}, Rp(i, c), Rp(i, c), D(i), -1, -1,
+             F_TB);
+      }
+    for (int i = t - 1; i >= 0; --i)
+      for (int c = 0; c < s; ++c) {
+        for (int k = t - 1; k > i; --k) {
+          if (o.renamed)
+            emit(K_GEMMS, i, c, k, {B(k, i), Rh(k, c), Rh(i, c)}, {Rh(i, c)}, Rp(i, c), Rp(k, c),
+                 B(k, i), -1, -1, F_TB | F_NEG | F_ACC);
+          else
+            emit(K_GEMMS, i, c, k, {A(k, i), Rh(k, c), Rh(i, c)}, {Rh(i, c)}, Rp(i, c), Rp(k, c),
+                 A(k, i), -1, -1, F_NEG | F_ACC);
+        }
+        emit(K_TRSMS, i, c, 0, {A(i, i), Rh(i, c)}, {Rh(i, c)}, Rp(i, c), Rp(i, c), Dt(i), -1, -1,
+             F_TB);
+      }
   }
 };
 
@@ -415,6 +456,10 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
   if (s2) bld.step2();
   if (s2 && s3 && !opt.pipelined) bld.emit_barrier();
   if (s3) bld.step3();
+  if (opt.steps & 8) {
+    if (s1 && !opt.pipelined) bld.emit_barrier();
+    bld.solve();
+  }
 
   // dead factor stores: a POTRF whose factor tile is not read before it is
   // rewritten, and whose renaming copy is never read, stores only D_j, D_j^T.
@@ -422,7 +467,7 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
   // reads it).  Renaming copies that no task reads are not stored either.
   {
     const int nt = (int)p->tasks.size();
-    std::vector<char> copy_read(pool_tiles(opt.t), 0);
+    std::vector<char> copy_read(pool_tiles(opt.t, opt.rhs_tiles), 0);
     for (const DevTask& d : p->tasks) {
       if (d.a >= 0) copy_read[d.a] = 1;
       if (d.b >= 0) copy_read[d.b] = 1;
@@ -463,7 +508,7 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
   // earlier version during the launch is never read through the cache.
   {
     const int nt = (int)p->tasks.size();
-    const int64_t ntiles = pool_tiles(opt.t);
+    const int64_t ntiles = pool_tiles(opt.t, opt.rhs_tiles);
     std::vector<int32_t> writes(ntiles, 0);
     std::vector<char> touched_first(ntiles, 0);  // accessed before its first write
     for (int u = 0; u < nt; ++u) {
@@ -521,7 +566,7 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
       st.count[task_kind(p->tasks[v].kind)]++;
     }
     std::vector<int32_t> lp(n, 0), ls(n, 0);
-    int cp = 0, cps[4] = {0, 0, 0, 0};
+    int cp = 0, cps[5] = {0, 0, 0, 0, 0};  // by step (0 = barriers, 4 = the solve)
     for (int v = 0; v < n; ++v) {  // program order is a topological order
       int best = 0, best_s = 0;
       for (int q : bld.preds[v]) {

@@ -50,7 +50,9 @@ enum Kind : int32_t {
   K_LAUUM = 10,  // A_ii <- A_ii^T A_ii
   K_GEMM3 = 11,  // A_ij += X_ki^T X_kj
   K_SYRK3 = 12,  // A_ii += X_ki^T X_ki
-  K_COUNT = 13
+  K_GEMMS = 13,  // solve: R_ic -= L_ik R_kc (forward) or L_ki^T R_kc (backward)
+  K_TRSMS = 14,  // solve: R_ic <- L_ii^{-1} R_ic = D_i R_ic (or D_i^T R_ic)
+  K_COUNT = 15
 };
 
 struct PlanOptions {
@@ -65,7 +67,12 @@ struct PlanOptions {
   // SPD inverse, 1 = the Cholesky factor only, 6 = the inverse from a given
   // factor (the caller provides what step 1 leaves for step 2: the
   // transposed copies B = L^T and the diagonal inverses D_j, D_j^T).
+  // Bit 3: the solve A X = R with the factor (forward substitution with L,
+  // then backward with L^T) over rhs_tiles tile columns of right-hand sides:
+  // 9 = factor and solve, 8 = solve with a given factor (the same prologue
+  // as 6).
   int steps = 7;
+  int rhs_tiles = 0;
 };
 constexpr int MAX_CHAIN = 16;
 
@@ -170,10 +177,13 @@ struct Plan {
 // chained product; null = unit durations).
 void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* out);
 
-// Tile pool size in tiles for t tiles per side.
+// Tile pool size in tiles for t tiles per side (and s tile columns of
+// right-hand sides, after the other regions: R_ic at 3T + 2t + i + t c).
+inline int64_t pool_tiles(int t, int s);
 inline int64_t pool_tiles(int t) {
   int64_t T = (int64_t)t * (t + 1) / 2;
   return 3 * T + 2 * (int64_t)t;
 }
+inline int64_t pool_tiles(int t, int s) { return pool_tiles(t) + (int64_t)t * s; }
 
 }  // namespace spdinv

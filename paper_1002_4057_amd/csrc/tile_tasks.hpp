@@ -880,7 +880,7 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
   double* cp = t.copy >= 0 ? tile_ptr(P, t.copy) : nullptr;
   switch (kind) {
     case K_SYRK1: case K_GEMM1: case K_TRSM1: case K_TRMM2L: case K_GEMM2: case K_TRSM2R:
-    case K_TRMM3: case K_LAUUM: case K_GEMM3: case K_SYRK3:
+    case K_TRMM3: case K_LAUUM: case K_GEMM3: case K_SYRK3: case K_GEMMS: case K_TRSMS:
       // tile products; the planner chose operands and flags (Algorithm 1's
       // operation on the renamed or in-place tiles)
       if ((f & (F_TA | F_MA | F_MB)) == 0 && (f & F_TB)) {

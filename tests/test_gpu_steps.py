@@ -116,3 +116,76 @@ def test_large_ragged_orders(n):
     assert (torch.linalg.norm(x - ref) / torch.linalg.norm(ref)).item() <= 1e-12 * 1e4
     # n = 0 is a no-op
     assert spd.cholesky(torch.empty((0, 0), dtype=torch.float64, device=DEV)).shape == (0, 0)
+
+
+# --------------------------------------------------------------------------
+# the solve with the factor (spd_solve, spd_solve_from_factor)
+# --------------------------------------------------------------------------
+def colmajor_buffer(m, ld, fill=np.nan):
+    rows, cols = m.shape
+    host = np.full((ld, cols), fill)
+    host[:rows, :] = m
+    return torch.from_numpy(np.ascontiguousarray(host.T)).to(DEV)  # rows of host.T = columns
+
+
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (17, 3), (128, 128), (129, 1), (300, 129), (700, 40)])
+def test_solve_against_oracle(n, nrhs):
+    a = inputs.wishart_shift(n, seed=21).numpy()
+    b = np.random.default_rng(n + nrhs).standard_normal((n, nrhs))
+    abuf = colmajor_buffer(np.tril(a) + np.triu(np.full((n, n), np.nan), 1), n + 1)
+    bbuf = colmajor_buffer(b, n + 2)
+    rep = spd.solve_(abuf.t()[:n, :], bbuf.t()[:n, :], report=True)
+    assert rep["info"] == 0
+    ahost = abuf.cpu().numpy().T
+    bhost = bbuf.cpu().numpy().T
+    lo = oracle.potrf(a)
+    xo = oracle.potrs(lo, b)
+    k = kappa(a)
+    assert rel_fro(bhost[:n, :], xo) <= 1e-12 * k
+    assert rel_fro(np.tril(ahost[:n, :n]), lo) <= 1e-12 * k
+    assert np.isnan(ahost[:n, :n][np.triu_indices(n, 1)]).all()   # upper triangle untouched
+    assert np.isnan(bhost[n:, :]).all() and np.isnan(ahost[n:, :]).all()
+
+
+@pytest.mark.parametrize("n,nrhs", [(5, 2), (200, 7), (385, 130)])
+def test_solve_from_factor_against_oracle(n, nrhs):
+    a = inputs.wishart_shift(n, seed=22).numpy()
+    lo = oracle.potrf(a)
+    b = np.random.default_rng(n).standard_normal((n, nrhs))
+    lbuf = colmajor_buffer(np.tril(lo) + np.triu(np.full((n, n), np.nan), 1), n)
+    before = lbuf.clone()
+    bbuf = colmajor_buffer(b, n)
+    rep = spd.solve_from_factor_(lbuf.t()[:n, :], bbuf.t()[:n, :], report=True)
+    assert rep["info"] == 0
+    assert torch.equal(torch.nan_to_num(lbuf, nan=7.0), torch.nan_to_num(before, nan=7.0))  # L only read
+    assert rel_fro(bbuf.cpu().numpy().T[:n, :], oracle.potrs(lo, b)) <= 1e-12 * kappa(a)
+
+
+def test_solve_exact_and_info():
+    d = 4.0 ** ((np.arange(260) % 9) - 4)
+    b = np.outer(d, np.arange(1, 4, dtype=np.float64))          # A X = B with X = [1 2 3] columns
+    x = spd.solve(torch.from_numpy(np.diag(d)).to(DEV), torch.from_numpy(b).to(DEV))
+    np.testing.assert_array_equal(x.cpu().numpy(), np.outer(np.ones(260), np.arange(1, 4)))
+    dd = np.ones(200)
+    dd[150] = -1.0
+    with pytest.raises(spd.NotPositiveDefinite) as e:
+        spd.solve(torch.from_numpy(np.diag(dd)).to(DEV), torch.ones((200, 2), dtype=torch.float64, device=DEV))
+    assert e.value.info == 151
+    lo = np.eye(140)
+    lo[9, 9] = 0.0
+    with pytest.raises(spd.NotPositiveDefinite) as e:
+        spd.solve_from_factor(torch.from_numpy(lo).to(DEV), torch.ones((140, 1), dtype=torch.float64, device=DEV))
+    assert e.value.info == 10
+
+
+def test_solve_large_ragged():
+    """n = 4097, 300 right-hand sides: the residual ||A X - B|| / (||A|| ||X||)
+    at the level of binary64 rounding, and X against Q diag(1/lambda) Q^T B."""
+    n = 4097
+    a, q, lam = inputs.spectrum(n, 1e4, seed=9, device=DEV, return_factors=True)
+    b = torch.from_numpy(np.random.default_rng(1).standard_normal((n, 300))).to(DEV)
+    x = spd.solve(a, b)
+    res = (torch.linalg.norm(a @ x - b) / (torch.linalg.norm(a) * torch.linalg.norm(x))).item()
+    assert res <= 1e-14
+    ref = inputs.analytic_inverse(q, lam) @ b
+    assert (torch.linalg.norm(x - ref) / torch.linalg.norm(ref)).item() <= 1e-12 * 1e4

@@ -290,3 +290,54 @@ def test_grad_reads_only_lower_triangle_of_inverse():
     low = np.tril(y)
     low[np.triu_indices(n, 1)] = np.nan
     np.testing.assert_array_equal(oracle.inverse_grad(low, g), oracle.inverse_grad(y, g))
+
+
+# --------------------------------------------------------------------------
+# the solve with the factor (potrs): pinned by closed forms, exact integer
+# arithmetic and a library solve
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [1, 2, 7, 33, 120])
+def test_potrs_tridiag_identity_rhs_is_the_closed_form_inverse(n):
+    a = 2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    x = oracle.potrs(tridiag_L(n), np.eye(n))
+    assert rel_fro(x, tridiag_inv(n)) <= 64 * n * U
+
+
+def test_potrs_unit_lower_integer_factor_is_exact():
+    # L unit lower triangular with small integers: B = L L^T X0 is exact in
+    # binary64, and so is every step of both substitutions
+    rng = np.random.default_rng(3)
+    n = 12
+    l = np.tril(rng.integers(-2, 3, size=(n, n)).astype(np.float64), -1) + np.eye(n)
+    x0 = rng.integers(-3, 4, size=(n, 5)).astype(np.float64)
+    b = l @ (l.T @ x0)
+    np.testing.assert_array_equal(oracle.potrs(l, b), x0)
+
+
+def test_potrs_forward_and_backward_are_not_swapped():
+    # a factor that is not symmetric in its role: L = [[1, 0], [2, 1]];
+    # L L^T = [[1, 2], [2, 5]], whose inverse is [[5, -2], [-2, 1]]
+    l = np.array([[1.0, 0.0], [2.0, 1.0]])
+    np.testing.assert_array_equal(oracle.potrs(l, np.eye(2)), np.array([[5.0, -2.0], [-2.0, 1.0]]))
+
+
+@pytest.mark.parametrize("n,nrhs,seed", [(40, 1, 0), (97, 7, 1), (150, 3, 2)])
+def test_potrs_against_library_solve(n, nrhs, seed):
+    a = inputs.wishart_shift(n, seed=seed).numpy()
+    b = np.random.default_rng(seed).standard_normal((n, nrhs))
+    x = oracle.potrs(oracle.potrf(a), b)
+    ref = np.linalg.solve(a, b)
+    assert rel_fro(x, ref) <= 1e3 * U * np.linalg.cond(a)
+
+
+def test_potrs_upper_triangle_not_read_and_zero_pivot():
+    n = 9
+    a = inputs.wishart_shift(n, seed=4).numpy()
+    lo = oracle.potrf(a)
+    poisoned = lo + np.triu(np.full((n, n), np.nan), 1)
+    b = np.arange(n, dtype=np.float64)
+    np.testing.assert_array_equal(oracle.potrs(poisoned, b), oracle.potrs(lo, b))
+    lo[4, 4] = 0.0
+    with pytest.raises(oracle.OracleInfo) as e:
+        oracle.potrs(lo, b)
+    assert e.value.info == 5

@@ -141,3 +141,97 @@ def test_step_entry_points_reject_bad_options(name):
     o = _lib.make_opts(chain=40)
     assert getattr(lib, name)(4, ctypes.c_void_p(8), 4, ctypes.c_void_p(8), 1 << 20, None,
                               ctypes.byref(o), None, None) == -7
+
+
+def rhs_pool(pool, b, t, nb):
+    """The pool with right-hand-side tiles appended: R_ic^T at 3T + 2t + i + t c."""
+    n, nrhs = b.shape
+    s = -(-nrhs // nb)
+    full = np.zeros((t * nb, s * nb))
+    full[:n, :nrhs] = b
+    tiles = [full[i * nb:(i + 1) * nb, c * nb:(c + 1) * nb].T for c in range(s) for i in range(t)]
+    return np.concatenate([pool, np.array(tiles)]), s
+
+
+def rhs_from_pool(pool, t, nb, n, nrhs, s):
+    base = len(pool) - t * s
+    full = np.zeros((t * nb, s * nb))
+    for c in range(s):
+        for i in range(t):
+            full[i * nb:(i + 1) * nb, c * nb:(c + 1) * nb] = pool[base + i + t * c].T
+    return full[:n, :nrhs]
+
+
+@pytest.mark.parametrize("opts", VARIANTS, ids=lambda o: "-".join(f"{k}{v}" for k, v in o.items()) or "default")
+def test_solve_plan_factor_and_substitutions_in_any_order(opts):
+    """steps = 9: step 1 and the forward and backward substitutions in one
+    DAG; the factor in A and X in the right-hand-side tiles, in any
+    topological order, against the oracle's factor and solve."""
+    nb, n, nrhs = 4, 21, 6                 # t = 6, s = 2 (ragged in both)
+    t = -(-n // nb)
+    a = inputs.wishart_shift(n, seed=6).numpy()
+    b = np.random.default_rng(6).standard_normal((n, nrhs))
+    pool0, s = rhs_pool(tx.to_pool(a, t, nb), b, t, nb)
+    plan = spd.plan_export(t, workers=5, steps=9, rhs_tiles=s, **opts)
+    assert set(plan["step"].tolist()) <= {0, 1, 4}
+    ref_pool = run(plan, pool0.copy())
+    x = rhs_from_pool(ref_pool, t, nb, n, nrhs, s)
+    lo = oracle.potrf(a)
+    xo = oracle.potrs(lo, b)
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-12
+    assert np.linalg.norm(lower_from_pool(ref_pool, t, nb, n) - lo) / np.linalg.norm(lo) < 1e-13
+    rng = np.random.default_rng(7)
+    for _ in range(6):
+        order = tx.random_topological_order(plan["tasks"], plan["succ"], rng)
+        np.testing.assert_array_equal(run(plan, pool0.copy(), order), ref_pool)
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(renamed=0)], ids=["renamed", "in-place"])
+def test_solve_plan_with_a_given_factor(opts):
+    """steps = 8: the substitutions alone, after the factor prologue."""
+    nb, n, nrhs = 4, 18, 3
+    t = -(-n // nb)
+    a = inputs.wishart_shift(n, seed=8).numpy()
+    b = np.random.default_rng(8).standard_normal((n, nrhs))
+    lo = oracle.potrf(a)
+    pool0, s = rhs_pool(factor_prologue(tx.to_pool(lo, t, nb), t), b, t, nb)
+    plan = spd.plan_export(t, workers=3, steps=8, rhs_tiles=s, **opts)
+    assert set(plan["step"].tolist()) <= {4}
+    x = rhs_from_pool(run(plan, pool0.copy()), t, nb, n, nrhs, s)
+    xo = oracle.potrs(lo, b)
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) < 1e-12
+
+
+def test_solve_plan_task_counts_and_invalid_combinations():
+    t, s = 7, 3
+    p9 = spd.plan_export(t, steps=9, rhs_tiles=s, chain=1)
+    p1 = spd.plan_export(t, steps=1, chain=1)
+    k = p9["tasks"][:, 0] & 0xFF
+    # forward and backward: per right-hand-side tile column, t(t-1)/2 updates
+    # and t multiplications by a diagonal inverse each
+    assert int((k == tx.GEMMS).sum()) == 2 * s * t * (t - 1) // 2
+    assert int((k == tx.TRSMS).sum()) == 2 * s * t
+    assert len(p9["tasks"]) == len(p1["tasks"]) + 2 * s * (t * (t - 1) // 2 + t)
+    for steps, rhs in ((9, 0), (8, 0), (7, 1), (9, 65), (5, 0)):
+        with pytest.raises(ValueError):
+            spd.plan_export(4, steps=steps, rhs_tiles=rhs)
+
+
+@pytest.mark.parametrize("name", ["spd_solve", "spd_solve_from_factor"])
+@pytest.mark.parametrize("args,code", [
+    ((-1, 1, 8, 1, 8, 1), -1),       # n < 0
+    ((4, -1, 8, 4, 8, 4), -2),       # nrhs < 0
+    ((4, 8193, 8, 4, 8, 4), -2),     # nrhs too large
+    ((4, 1, None, 4, 8, 4), -3),     # null matrix
+    ((4, 1, 8, 3, 8, 4), -4),        # lda < n
+    ((4, 1, 8, 4, None, 4), -5),     # null right-hand sides
+    ((4, 1, 8, 4, 8, 3), -6),        # ldb < n
+    ((4, 1, 8, 4, 8, 4), -7),        # null workspace
+])
+def test_solve_entry_points_reject_invalid_arguments_on_host(name, args, code):
+    lib = _lib.load()
+    n, nrhs, a, lda, b, ldb = args
+    o = _lib.make_opts()
+    fn = getattr(lib, name)
+    assert fn(n, nrhs, a and ctypes.c_void_p(a), lda, b and ctypes.c_void_p(b), ldb, None, 0, None,
+              ctypes.byref(o), None, None) == code

@@ -10,10 +10,11 @@ oracle on the CPU.
 import numpy as np
 
 NOP, SYRK1, POTRF, GEMM1, TRSM1, TRTRI, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEMM3, SYRK3 = range(13)
+GEMMS, TRSMS = 13, 14   # the solve with the factor
 POTRF_FACTOR_DEAD = 1 << 16
 LINKS_SHIFT = 20   # chained products: count of further links (see plan.hpp)
 LINK_KLAST = 1 << 30   # link mark: reduction over the last tile block
-PRODUCTS = {SYRK1, GEMM1, TRSM1, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEMM3, SYRK3}
+PRODUCTS = {SYRK1, GEMM1, TRSM1, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEMM3, SYRK3, GEMMS, TRSMS}
 F_TA, F_TB, F_MA, F_MB, F_LOWER, F_NEG, F_ACC, F_COPYT = 1, 2, 4, 8, 16, 32, 64, 128
 
 
