@@ -173,9 +173,25 @@ def steps_row(spd, a_cm, work, n: int, reps: int):
     spd.inverse_from_factor_(b.t(), work=work, report=True)  # plan + warm (b holds L)
     ms_inv = time_events(lambda: spd.inverse_from_factor_(b.t(), work=work), reps,
                          prep=lambda: b.copy_(lsrc))
-    out = {"workload": f"n={n}, FP64, same input as the headline line", "reps": reps}
+    # the solve A X = B (factor, then both substitutions) for 128 right-hand
+    # sides, n^3/3 + 2 n^2 nrhs flops
+    import torch
+    nrhs = 128
+    bsrc = torch.randn(nrhs, n, dtype=torch.float64, device=a_cm.device)  # column-major n x nrhs
+    bb = bsrc.clone()
+    spd.solve_(b.t(), bb.t(), report=True)                    # plan + warm
+    swork = torch.empty(spd.solve_workspace_bytes(n, nrhs), dtype=torch.uint8,
+                        device=a_cm.device)
+
+    def prep_solve():
+        b.copy_(a_cm)
+        bb.copy_(bsrc)
+    ms_solve = time_events(lambda: spd.solve_(b.t(), bb.t(), work=swork), reps, prep=prep_solve)
+    out = {"workload": f"n={n}, FP64, same input as the headline line; solve with {nrhs} "
+                       "right-hand sides", "reps": reps}
     for key, ms, fl in (("cholesky", ms_chol, n ** 3 / 3.0), ("inverse_from_factor", ms_inv,
-                                                                2.0 * n ** 3 / 3.0)):
+                                                                2.0 * n ** 3 / 3.0),
+                        ("solve", ms_solve, n ** 3 / 3.0 + 2.0 * n * n * nrhs)):
         out[key] = {"ms": round(ms, 3), "gflops": round(fl / ms / 1e6, 1),
                     "frac_fp64_peak": round(fl / ms / 1e9 / PEAK_FP64_TFLOPS, 4)}
     return out

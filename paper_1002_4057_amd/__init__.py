@@ -27,7 +27,7 @@ __all__ = ["spd_inverse", "spd_inverse_", "workspace_bytes", "plan_stats", "plan
            "spd_inverse_backward", "backward_workspace_bytes", "SpdInverse", "spd_inverse_ad",
            "batched_spd_inverse", "batched_spd_inverse_", "batched_workspace_bytes",
            "cholesky", "cholesky_", "inverse_from_factor", "inverse_from_factor_",
-           "solve", "solve_", "solve_from_factor", "solve_from_factor_",
+           "solve", "solve_", "solve_from_factor", "solve_from_factor_", "solve_workspace_bytes",
            "SpdInverseError", "NotPositiveDefinite"]
 
 
@@ -217,6 +217,12 @@ def _solve_entry(name, a_cm, b_cm, work, report, info, opts):
             raise NotPositiveDefinite(r["info"])
         return r
     return None
+
+
+def solve_workspace_bytes(n: int, nrhs: int, **opts) -> int:
+    """Device workspace bytes of spd_solve / spd_solve_from_factor."""
+    o = make_opts(**opts)
+    return int(load().spd_solve_workspace_bytes(int(n), int(nrhs), ctypes.byref(o)))
 
 
 def solve_(a_cm, b_cm, *, work=None, report: bool = False, info=None, **opts):
