@@ -153,7 +153,7 @@ __device__ int tile_sequential(double* A, int lda, int n, int fill_upper, const 
   __shared__ int s_info;
   for (int k = 0; k < ntask; ++k) {
     const DevTask task = tasks[k];
-    run_task(task, g, smem, T, t);
+    run_task<true>(task, g, smem, T, t);
     stores_complete();
     __syncthreads();
     if ((task.kind & 0xff) == K_POTRF) {

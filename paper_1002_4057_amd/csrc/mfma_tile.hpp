@@ -296,6 +296,45 @@ __device__ __forceinline__ void acc_store_tile(rsrc_t r, const d4 (&acc)[4][4], 
       }
 }
 
+// The same for the upper half rows of a tile, the four waves side by side:
+// wave w holds rows 0..63 (accumulators i = 0..3) of columns 32 w .. 32 w + 31
+// (accumulators j = 0..1); register r of accumulator (i, j) of this lane
+// holds tile element 16 i + lane % 16 + NB (32 w + 16 j + lane / 16 + 4 r).
+__device__ __forceinline__ int acc_lane_bytes_r64() {
+  const int t = opaque_tid(), lane = t & 63, w = t >> 6;
+  return 8 * ((lane & 15) + NB * (32 * w + (lane >> 4)));
+}
+
+template <int CP = CPOL_AGENT>
+__device__ __forceinline__ void acc_load_r64(rsrc_t r, d4 (&acc)[4][4], bool neg) {
+  const int vb = acc_lane_bytes_r64();
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double x = __builtin_bit_cast(
+            double, __builtin_amdgcn_raw_buffer_load_b64(r, vb + 128 * i, 8 * NB * (16 * j + 4 * q), CP));
+        acc[i][j][q] = neg ? -x : x;
+      }
+}
+
+template <int CP = CPOL_AGENT>
+__device__ __forceinline__ void acc_store_r64(rsrc_t r, const d4 (&acc)[4][4], bool neg) {
+  const int vb = acc_lane_bytes_r64();
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double x = neg ? -acc[i][j][q] : acc[i][j][q];
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, x), r, vb + 128 * i,
+                                              8 * NB * (16 * j + 4 * q), CP);
+      }
+}
+
 // C <- s * acc for one output tile (s = +1 or -1, exact); `lower` skips the
 // block that lies strictly above the diagonal (rows 0-63 x columns 64-127).
 template <int CP>

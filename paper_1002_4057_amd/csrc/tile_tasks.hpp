@@ -120,7 +120,7 @@ __device__ __forceinline__ void copy_epilogue(double* copy, const d4 (&acc)[4][4
 // (scheduling barriers keep the compiler from pulling their consumers into
 // the MFMA sequence).
 // ---------------------------------------------------------------------------
-template <bool FAST>
+template <bool FAST, bool R64 = false>
 __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, const double* B,
                                          double* copy, double* smem, bool nca = false,
                                          bool ncb = false, int npan = SNCH) {
@@ -135,7 +135,10 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
   const bool neg = (f & F_NEG) != 0, copy_t = (f & F_COPYT) != 0;
   const rsrc_t rA = tile_rsrc(A), rB = tile_rsrc(B), rC = tile_rsrc(C);
   const bool accum = (f & F_ACC) != 0;
-  const bool active = !((f & F_LOWER) && wm == 0 && wn == 1);
+  const bool active = R64 ? !((f & F_LOWER) && w >= 2) : !((f & F_LOWER) && wm == 0 && wn == 1);
+  // R64: rows 0-63 only, the waves side by side (32 columns each)
+  const int row0 = R64 ? 0 : wm * 64, col0 = R64 ? w * 32 : wn * 64;
+  constexpr int JN = R64 ? 2 : 4;
 
   // v_mfma_f64_16x16x4(x, y, d): d[i][j] += sum_k x[i][k] y[k][j] with x[i][k]
   // from lane i+16k, y[k][j] from lane j+16k, and d[i][j] in register r = i/4
@@ -145,7 +148,8 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
   // covers 16 consecutive rows of one column (one 128-byte segment).
   d4 acc[4][4];
   if (accum) {
-    acc_load(rC, acc, neg);
+    if constexpr (R64) acc_load_r64(rC, acc, neg);
+    else acc_load(rC, acc, neg);
   } else {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -182,18 +186,18 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ks = 0; ks < SKC / 4; ++ks) {
-      const double* Ar = As + (4 * ks + lk) * LDS_STRIDE + wm * 64 + lr;
-      const double* Br = Bs + (4 * ks + lk) * LDS_STRIDE + wn * 64 + lr;
+      const double* Ar = As + (4 * ks + lk) * LDS_STRIDE + row0 + lr;
+      const double* Br = Bs + (4 * ks + lk) * LDS_STRIDE + col0 + lr;
       double a[4], b[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         a[i] = Ar[16 * i];
-        b[i] = Br[16 * i];
+        if (i < JN) b[i] = Br[16 * i];
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < JN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -205,9 +209,13 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
     __syncthreads();
   }
 
-  if (active) acc_store_tile(rC, acc, neg);
-  if (!copy) return;  // uniform: the copy pointer is the same in every thread
-  copy_epilogue(copy, acc, neg, copy_t, smem);
+  if constexpr (R64) {
+    if (active) acc_store_r64(rC, acc, neg);  // no renaming copy (the caller's rule)
+  } else {
+    if (active) acc_store_tile(rC, acc, neg);
+    if (!copy) return;  // uniform: the copy pointer is the same in every thread
+    copy_epilogue(copy, acc, neg, copy_t, smem);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -234,6 +242,7 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
 // chain.  Inlined into the scheduler: as an out-of-line call it saved and
 // restored 77 callee-saved registers through scratch memory on every task.
 // ---------------------------------------------------------------------------
+template <bool R64 = false>
 __device__ __forceinline__ void tile_mma_chain(int f, double* C, const double* A,
                                                          const double* B, double* copy,
                                                          double* smem, const int32_t* links,
@@ -255,12 +264,15 @@ __device__ __forceinline__ void tile_mma_chain(int f, double* C, const double* A
   const int lr = lane & 15, lk = lane >> 4;
   const bool neg = (f & F_NEG) != 0, copy_t = (f & F_COPYT) != 0;
   const bool accum = (f & F_ACC) != 0;
-  const bool active = !((f & F_LOWER) && wm == 0 && wn == 1);
+  const bool active = R64 ? !((f & F_LOWER) && w >= 2) : !((f & F_LOWER) && wm == 0 && wn == 1);
+  const int row0 = R64 ? 0 : wm * 64, col0 = R64 ? w * 32 : wn * 64;
+  constexpr int JN = R64 ? 2 : 4;
   const rsrc_t rC = tile_rsrc(C);
 
   d4 acc[4][4];
   if (accum) {
-    acc_load(rC, acc, neg);
+    if constexpr (R64) acc_load_r64(rC, acc, neg);
+    else acc_load(rC, acc, neg);
   } else {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -321,18 +333,18 @@ __device__ __forceinline__ void tile_mma_chain(int f, double* C, const double* A
       panel_load<CPOL_AGENT, SKC>(sB, k0, true, rb);
 #pragma unroll
       for (int ks = 0; ks < SKC / 4; ++ks) {
-        const double* Ar = As + (4 * ks + lk) * LDS_STRIDE + wm * 64 + lr;
-        const double* Br = Bs + (4 * ks + lk) * LDS_STRIDE + wn * 64 + lr;
+        const double* Ar = As + (4 * ks + lk) * LDS_STRIDE + row0 + lr;
+        const double* Br = Bs + (4 * ks + lk) * LDS_STRIDE + col0 + lr;
         double a[4], b[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           a[i] = Ar[16 * i];
-          b[i] = Br[16 * i];
+          if (i < JN) b[i] = Br[16 * i];
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < JN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
       }
       // the next panel's buffer was released by the previous barrier
@@ -341,14 +353,15 @@ __device__ __forceinline__ void tile_mma_chain(int f, double* C, const double* A
       // order of the region: the operands of k-step 0, then per k-step half
       // of its MFMAs, the next panel's loads (k-step 0) or their LDS stores
       // (last k-step), the next k-step's operands, the other half
-      __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+      constexpr int MF = 4 * JN / 2, DR = R64 ? 3 : 4;  // MFMAs per half k-step, LDS reads
+      __builtin_amdgcn_sched_group_barrier(0x100, DR, 0);
 #pragma unroll
       for (int ks = 0; ks < SKC / 4; ++ks) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, MF, 0);
         if (ks == 0) __builtin_amdgcn_sched_group_barrier(0x020, 8, 0);
         if (ks == SKC / 4 - 1) __builtin_amdgcn_sched_group_barrier(0x200, 8, 0);
-        if (ks + 1 < SKC / 4) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
-        __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+        if (ks + 1 < SKC / 4) __builtin_amdgcn_sched_group_barrier(0x100, DR, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, MF, 0);
       }
       __syncthreads();
     }
@@ -357,9 +370,13 @@ __device__ __forceinline__ void tile_mma_chain(int f, double* C, const double* A
     npan = nnext;
   }
 
-  if (active) acc_store_tile(rC, acc, neg);
-  if (!copy) return;  // uniform
-  copy_epilogue(copy, acc, neg, copy_t, smem);
+  if constexpr (R64) {
+    if (active) acc_store_r64(rC, acc, neg);  // no renaming copy (the caller's rule)
+  } else {
+    if (active) acc_store_tile(rC, acc, neg);
+    if (!copy) return;  // uniform
+    copy_epilogue(copy, acc, neg, copy_t, smem);
+  }
 }
 
 // The general product (transposed or triangular operands) serves only the
@@ -870,6 +887,14 @@ __device__ __forceinline__ void tile_copy(const double* src, double* dst) {
 }
 
 
+// ALLOW_R64 (the batched kernel): a product without a renaming copy whose
+// output tile lies in the last tile row of a matrix with at most 64 valid
+// rows there computes only rows 0-63, the four waves side by side.  The
+// padded rows of such an output keep their values (zero, or the identity
+// padding of the last diagonal tile): every operand row that reaches them
+// is padding too.  Per output element the MFMA sequence is the same, so the
+// result is bit-identical.
+template <bool ALLOW_R64 = false>
 __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, double* smem, int T,
                                          int tiles) {
   double* P = g.pool;
@@ -890,10 +915,18 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
         // k-panels of a product over the (possibly ragged) last tile block
         const int npan_last = (g.last_valid + SKC - 1) / SKC;
         const int npan = (t.kind & K_KLAST) ? npan_last : SNCH;
-        if (nl)
-          tile_mma_chain(f, out, a, b, cp, smem, g.links + 2 * t.aux, nl, P, npan, npan_last);
-        else
-          tile_mma<true>(f, out, a, b, cp, smem, nca, ncb, npan);
+        const bool r64 = ALLOW_R64 && !cp && g.last_valid <= 64 && t.out >= T - tiles &&
+                         t.out < T;
+        if (nl) {
+          if (r64)
+            tile_mma_chain<true>(f, out, a, b, cp, smem, g.links + 2 * t.aux, nl, P, npan,
+                                 npan_last);
+          else
+            tile_mma_chain(f, out, a, b, cp, smem, g.links + 2 * t.aux, nl, P, npan, npan_last);
+        } else {
+          if (r64) tile_mma<true, true>(f, out, a, b, cp, smem, nca, ncb, npan);
+          else tile_mma<true>(f, out, a, b, cp, smem, nca, ncb, npan);
+        }
       }
       else
         tile_mma_general(f, out, a, b, cp, smem);
