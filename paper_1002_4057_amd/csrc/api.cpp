@@ -319,7 +319,6 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   if (timed && hipEventRecord(ev0, stream) != hipSuccess) return SPDINV_ERR_HIP;
   if (launch_sched(a, grid, per_cu_for(t, o), stream) != hipSuccess) return SPDINV_ERR_HIP;
   if (timed && hipEventRecord(ev1, stream) != hipSuccess) return SPDINV_ERR_HIP;
-  // the Cholesky factor leaves the strictly upper triangle untouched
   // the factor leaves the strictly upper triangle untouched; a given factor
   // (the solve with it) is not written back
   if (steps != 8 &&
