@@ -67,7 +67,7 @@ __device__ int small_inverse(double* A, int lda, int n, int fill_upper, double* 
     T[PK_STRIDE * b + lr + PK_LD * lc] = v;
   }
   __syncthreads();
-  const int f = factor_packed(T, rd, flag, P);
+  const int f = factor_packed(T, rd, rd + NB + 8, flag, P);
   if (f) return f;
   inverse_packed(T, rd, P);
   constexpr int PER_WAVE = (PK_BLOCKS + 3) / 4;

@@ -225,7 +225,7 @@ __device__ __attribute__((noinline)) int potrf_inv_tile32(const float* Ain, floa
     }
   }
   __syncthreads();
-  const int ff = factor_lds(T, XD, SCR, flag, 8);
+  const int ff = factor_lds(T, XD, SCR, SCR + NB, flag, 8);  // pivots, then the broadcast buffer
   if (ff) return ff;
   const rsrc_t rLT = rsrc32(LcopyT ? LcopyT : Xout);
   if (Lout) {  // skipped when nothing reads the factor

@@ -29,7 +29,7 @@ using namespace tile;
 // The scheduler's tile products stage 16-deep k-panels (8 per tile): the
 // two double-buffered operand panels take 66.6 KB of LDS, the renaming copy
 // is staged half a tile at a time (66 KB) and the diagonal-tile task keeps
-// only the lower 16 x 16 blocks (77.6 KB), so that a task needs at most
+// only the lower 16 x 16 blocks (78.1 KB), so that a task needs at most
 // TASK_SMEM doubles (under 80 KB: two workgroups per CU).
 constexpr int SKC = 16;
 constexpr int SNCH = NB / SKC;
@@ -41,7 +41,8 @@ constexpr int COPY_SMEM = 64 * RLD;    // half a tile
 constexpr int PK_LD = 17;              // packed diagonal tile, see pk_blk
 constexpr int PK_STRIDE = 16 * PK_LD;
 constexpr int PK_BLOCKS = 8 * 9 / 2;
-constexpr int PK_SMEM = PK_BLOCKS * PK_STRIDE + NB + 8;  // blocks + reciprocal pivots + flag
+// blocks + reciprocal pivots + flag + the column broadcast of chol16
+constexpr int PK_SMEM = PK_BLOCKS * PK_STRIDE + NB + 8 + 64;
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int TASK_SMEM = cmax(cmax(SGEMM_SMEM, COPY_SMEM), PK_SMEM);
 static_assert(TASK_SMEM * 8 <= 80 * 1024, "a task must fit half of the CU's LDS");
@@ -404,39 +405,76 @@ __device__ __forceinline__ double readlane_d(double v, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Orders the LDS stores of some lanes of a wave before later LDS loads of
+// other lanes of the same wave.  The LDS executes one wave's operations in
+// order, so no wait is needed; the fences keep the compiler from moving the
+// accesses across each other.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Cholesky factor of the 16 x 16 block at S (column-major, ld), executed by
-// one whole wave; lane r (mod 16) holds row r, pivots and pivot columns are
-// broadcast with readlane.  Writes L (zeros above the diagonal) back to S and
-// the reciprocal pivots 1/L_kk to rd[0..15].  Returns 0 or the 1-based index
-// of the first non-positive (or NaN) pivot (uniform).
-__device__ __forceinline__ int chol16(double* S, int ld, double* rd) {
-  const int tid = opaque_tid(), r = tid & 15;
-  double row[16];
+// one whole wave.  Lane 16 q + r holds row r, columns 4 j + q (j = 0..3).
+// Step k:
+//   - the pivot d = a_kk gives 1/L_kk (hardware rsq plus one Newton step,
+//     y <- y + y (1 - d y^2) / 2) and L_kk = d / sqrt(d);
+//   - the lanes of column k scale it into the multipliers m_r = a_rk / L_kk
+//     (zero for r <= k) and broadcast them through col (64 doubles of LDS,
+//     one 16-double slice per lane group, so that no lane is masked off);
+//   - every lane applies a_rc <- a_rc - m_r m_c to its four entries.  Entries
+//     that are already final, or lie above the diagonal, see a zero
+//     multiplier (a no-op up to the sign of a zero) or are discarded.
+// The next pivot a_{k+1,k+1} - m_{k+1}^2 is formed from a_{k+1,k} and
+// a_{k+1,k+1} in uniform registers, with the operations of the lane that
+// holds it, so the chain of pivots does not wait for the broadcast.
+// Writes L (zeros above the diagonal) back to S and the reciprocal pivots
+// 1/L_kk to rd[0..15].  Returns 0, or the 1-based index of the first pivot
+// that is not positive (or NaN), uniform; S is then left unchanged.
+__device__ __forceinline__ int chol16(double* S, int ld, double* rd, double* col) {
+  const int tid = opaque_tid(), r = tid & 15, q = (tid >> 4) & 3;
+  double a[4];
 #pragma unroll
-  for (int c = 0; c < 16; ++c) row[c] = (c <= r) ? S[r + ld * c] : 0.0;
+  for (int j = 0; j < 4; ++j) {
+    const int c = 4 * j + q;
+    a[j] = (c <= r) ? S[r + ld * c] : 0.0;
+  }
+  int fail = 0;
+  double d = readlane_d(a[0], 0);
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    const double d = readlane_d(row[k], k);
-    if (!(d > 0.0)) return k + 1;  // d is a scalar: uniform exit
-    // 1/sqrt(d) from the hardware estimate and one Newton step
-    // (y <- y + y (1 - d y^2) / 2), then sqrt(d) = d / sqrt(d)
+    const int qk = k & 3, jk = k >> 2;  // column k: lane group qk, slot jk
+    if (fail == 0 && !(d > 0.0)) fail = k + 1;
     double rinv = __builtin_amdgcn_rsq(d);
     const double h = d * rinv;
     rinv = fma(rinv * 0.5, fma(-h, rinv, 1.0), rinv);
     const double lkk = d * rinv;
     if ((tid & 63) == 0) rd[k] = rinv;
-    // column k of L: scale below the pivot
-    row[k] = (r > k) ? row[k] * rinv : ((r == k) ? lkk : row[k]);
-    // right-looking update of the trailing rows with column k
-#pragma unroll
-    for (int c = k + 1; c < 16; ++c) {
-      const double lck = readlane_d(row[k], c);
-      if (c <= r) row[c] = fma(-row[k], lck, row[c]);
+    if (k == 15) {
+      if (q == qk && r == k) a[jk] = lkk;
+      break;
     }
-  }
-  if ((tid & 63) < 16) {
+    const int k1 = k + 1, q1 = k1 & 3, j1 = k1 >> 2;
+    const double u1 = readlane_d(a[jk], 16 * qk + k1);  // a_{k+1,k}
+    const double u2 = readlane_d(a[j1], 16 * q1 + k1);  // a_{k+1,k+1}
+    const double m = (r > k) ? a[jk] * rinv : 0.0;
+    col[16 * q + r] = m;
+    const double mn = u1 * rinv;
+    d = fma(-mn, mn, u2);
+    wave_lds_sync();
+    const double mr = col[16 * qk + r];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) S[r + ld * c] = (c <= r) ? row[c] : 0.0;
+    for (int j = 0; j < 4; ++j)
+      if (4 * j + 3 > k) a[j] = fma(-mr, col[16 * qk + 4 * j + q], a[j]);
+    wave_lds_sync();
+    if (q == qk) a[jk] = (r == k) ? lkk : m;
+  }
+  if (fail) return fail;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = 4 * j + q;
+    S[r + ld * c] = (c <= r) ? a[j] : 0.0;
   }
   return 0;
 }
@@ -479,16 +517,17 @@ __device__ __forceinline__ void blk_store(double* S, int ld, d4 v) {
 //     the other blocks.
 // Then the inverses X_pp = L_pp^{-1} of all diagonal blocks into XD (16 x 16
 // column-major each), 16 lanes per block, one column of X_pp per lane.
-// rd receives the 16P reciprocal pivots.  Returns 0 or the 1-based index of
-// the first pivot that is not positive (or NaN); the value is uniform over
-// the workgroup.
+// rd receives the 16P reciprocal pivots; col is chol16's broadcast buffer
+// (64 doubles).  Returns 0 or the 1-based index of the first pivot that is
+// not positive (or NaN); the value is uniform over the workgroup.
 constexpr int POTRF_LD = NB + 1;  // odd row stride: transposed LDS reads spread over banks
 
-__device__ __forceinline__ int factor_lds(double* T, double* XD, double* rd, int* flag, int P) {
+__device__ __forceinline__ int factor_lds(double* T, double* XD, double* rd, double* col, int* flag,
+                                          int P) {
   constexpr int LD = POTRF_LD;
   const int tid = threadIdx.x, w = tid >> 6;
   if (w == 0) {
-    const int f = chol16(T, LD, rd);
+    const int f = chol16(T, LD, rd, col);
     if (tid == 0) *flag = f;
   }
   __syncthreads();
@@ -523,7 +562,7 @@ __device__ __forceinline__ int factor_lds(double* T, double* XD, double* rd, int
       d4 acc = -blk_load(Cnn, LD);
       acc = blk_mma16(acc, Lnp, LD, Lnp, LD, true);
       blk_store(Cnn, LD, -acc);
-      const int f = chol16(Cnn, LD, rd + 16 * (p + 1));
+      const int f = chol16(Cnn, LD, rd + 16 * (p + 1), col);
       if (tid == 0) *flag = f ? 16 * (p + 1) + f : 0;
     } else {
       for (int q = w; q < nb * (nb + 1) / 2; q += 3) {
@@ -597,8 +636,8 @@ __device__ __forceinline__ void inverse_lds(double* T, const double* XD, double*
 // Diagonal tile in packed form: only the 36 lower 16 x 16 blocks of the tile
 // are held in LDS, block (i, p) (i >= p) at PK_STRIDE * (i(i+1)/2 + p),
 // column-major with the odd leading dimension PK_LD (transposed reads spread
-// over the banks).  77.6 KB with the pivots, so that the scheduler's
-// workgroups fit two per CU.
+// over the banks).  78.1 KB with the pivots and chol16's broadcast buffer,
+// so that the scheduler's workgroups fit two per CU.
 // ---------------------------------------------------------------------------
 static_assert(PK_BLOCKS * 128 % NTHREADS == 0, "packed load assumes whole passes");
 
@@ -610,12 +649,13 @@ __device__ __forceinline__ double* pk_blk(double* T, int i, int p) {
 // packed tile, in place; the steps of factor_lds (one block of lookahead:
 // wave 0 updates and factors the next diagonal block while waves 1-3 update
 // the rest of the trailing blocks), on packed blocks.  rd receives the 16P
-// reciprocal pivots.  Returns 0 or the 1-based index of the first pivot that
-// is not positive (or NaN), uniform over the workgroup.
-__device__ __forceinline__ int factor_packed(double* T, double* rd, int* flag, int P) {
+// reciprocal pivots; col is chol16's broadcast buffer.  Returns 0 or the
+// 1-based index of the first pivot that is not positive (or NaN), uniform
+// over the workgroup.
+__device__ __forceinline__ int factor_packed(double* T, double* rd, double* col, int* flag, int P) {
   const int tid = opaque_tid(), w = tid >> 6;
   if (w == 0) {
-    const int f = chol16(pk_blk(T, 0, 0), PK_LD, rd);
+    const int f = chol16(pk_blk(T, 0, 0), PK_LD, rd, col);
     if (tid == 0) *flag = f;
   }
   __syncthreads();
@@ -648,7 +688,7 @@ __device__ __forceinline__ int factor_packed(double* T, double* rd, int* flag, i
       d4 acc = -blk_load(Cnn, PK_LD);
       acc = blk_mma16(acc, Lnp, PK_LD, Lnp, PK_LD, true);
       blk_store(Cnn, PK_LD, -acc);
-      const int f = chol16(Cnn, PK_LD, rd + 16 * (p + 1));
+      const int f = chol16(Cnn, PK_LD, rd + 16 * (p + 1), col);
       if (tid == 0) *flag = f ? 16 * (p + 1) + f : 0;
     } else {
       for (int q = w; q < nb * (nb + 1) / 2; q += 3) {
@@ -814,7 +854,7 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
   load_packed_tile(rIn, T);
   __syncthreads();
 
-  const int ff = factor_packed(T, rd, flag, P);
+  const int ff = factor_packed(T, rd, rd + NB + 8, flag, P);
   if (ff) return ff;
 
   // element (r, c) of the packed lower triangle (zero above the diagonal)
