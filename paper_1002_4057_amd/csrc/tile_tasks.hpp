@@ -759,11 +759,17 @@ __device__ __forceinline__ void inverse_packed(double* T, const double* rd, int 
       if (m < P) blk_store(pk_blk(T, m, p), PK_LD, y[s2]);
     }
     __syncthreads();
-    // X_ip = -sum_{m=p+1..i} X_im Y_mp
+    // X_ip = -sum_{m=p+1..i} X_im Y_mp; row p + c costs c block products
+    // (c = 1..n), so wave 0 takes c = n and wave w > 0 the pair w, n - w:
+    // every wave has at most n products
+    const int n = P - 1 - p;
+    int rows_w[2];
+    rows_w[0] = w == 0 ? p + n : (w <= n - w ? p + w : P);
+    rows_w[1] = (w > 0 && w < n - w) ? p + n - w : P;
     d4 xi[2];
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
-      const int i = p + 1 + w + 4 * s2;
+      const int i = rows_w[s2];
       d4 acc = {0.0, 0.0, 0.0, 0.0};
       if (i < P)
         for (int m = p + 1; m <= i; ++m)
@@ -773,7 +779,7 @@ __device__ __forceinline__ void inverse_packed(double* T, const double* rd, int 
     __syncthreads();
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
-      const int i = p + 1 + w + 4 * s2;
+      const int i = rows_w[s2];
       if (i < P) blk_store(pk_blk(T, i, p), PK_LD, xi[s2]);
     }
     // the next column reads only blocks of columns < p and the finished
