@@ -98,6 +98,11 @@ typedef struct {
                       library choice: 2 when the matrix has at least 96 tiles
                       per side, where the DAG keeps enough tasks ready, else
                       1; or 1 or 2).  Results do not depend on it.           */
+  int no_split;    /* FP64 form: 0 (default) = with more than one worker, run
+                      each of TRSM(j+1, j) and the last SYRK into tile
+                      (j+1, j+1) -- the products between POTRF(j) and
+                      POTRF(j+1) -- as two row-half tasks on two workgroups;
+                      1 = as whole tasks.  Results do not depend on it.      */
 } spdinv_opts;
 
 typedef struct {

@@ -31,7 +31,7 @@ class Opts(ctypes.Structure):
                 ("loop_order", ctypes.c_int), ("trtri_first", ctypes.c_int),
                 ("workers", ctypes.c_int), ("fill_upper", ctypes.c_int), ("trace", ctypes.c_int),
                 ("max_refine", ctypes.c_int), ("refine_tol", ctypes.c_double),
-                ("chain", ctypes.c_int), ("per_cu", ctypes.c_int)]
+                ("chain", ctypes.c_int), ("per_cu", ctypes.c_int), ("no_split", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):

@@ -27,8 +27,9 @@ namespace {
 // (list-scheduling simulation); a single 128^3 tile product task is the unit.
 // Measured per-task times at n = 8192 on MI355X: product 25.5 us, POTRF
 // (factor + inverse of the factor tile) 63 us, TRTRI copy 8.5 us, each further
-// link of a chained product 19.5 us (the last entry).
-const double kCost[K_COUNT + 1] = {
+// link of a chained product 19.5 us (the next-to-last entry); a row half of
+// a split product, as a fraction of the whole product (the last entry).
+const double kCost[K_COUNT + 2] = {
     0.0,    // NOP
     1.0,    // SYRK1
     2.47,   // POTRF
@@ -45,17 +46,19 @@ const double kCost[K_COUNT + 1] = {
     1.2,    // GEMMS (solve update; general product, untransposed operand)
     1.2,    // TRSMS (solve: multiplication by D_i or D_i^T)
     0.76,   // each further link of a chained product
+    0.6,    // a row half of a split product (fraction of the product)
 };
 
 // Products per device task of the FP64 scheduler when opts.chain is 0.
 constexpr int kDefaultChain = 8;
 
 struct Key {
-  int device, t, renamed, loop_order, pipelined, trtri_first, workers, chain, steps, rhs;
+  int device, t, renamed, loop_order, pipelined, trtri_first, workers, chain, steps, rhs, split;
   bool operator<(const Key& o) const {
     return std::tie(device, t, renamed, loop_order, pipelined, trtri_first, workers, chain, steps,
-                    rhs) < std::tie(o.device, o.t, o.renamed, o.loop_order, o.pipelined,
-                                    o.trtri_first, o.workers, o.chain, o.steps, o.rhs);
+                    rhs, split) < std::tie(o.device, o.t, o.renamed, o.loop_order, o.pipelined,
+                                           o.trtri_first, o.workers, o.chain, o.steps, o.rhs,
+                                           o.split);
   }
 };
 
@@ -89,6 +92,7 @@ spdinv_opts defaults() {
   o.refine_tol = 0.0;
   o.chain = 0;
   o.per_cu = 0;
+  o.no_split = 0;
   return o;
 }
 
@@ -96,9 +100,11 @@ int chain_for(const spdinv_opts& o) { return o.chain > 0 ? o.chain : kDefaultCha
 
 int tiles_for(int n) { return (n + NB - 1) / NB; }
 
+// Device tasks of the plan at most: the paper's tasks, two barriers, and the
+// second halves of the split products (two per column).
 long long task_count(int t) {
   const long long tt = t;
-  return 3 * (tt * (tt - 1) * (tt - 2) / 6) + 6 * (tt * (tt - 1) / 2) + 3 * tt + 2;
+  return 3 * (tt * (tt - 1) * (tt - 2) / 6) + 6 * (tt * (tt - 1) / 2) + 3 * tt + 2 + 2 * tt;
 }
 
 struct Layout {
@@ -124,8 +130,13 @@ int check_opts(const spdinv_opts& o) {
   if (o.workers < 0) return 1;
   if (o.chain < 0 || o.chain > MAX_CHAIN) return 1;
   if (o.per_cu < 0 || o.per_cu > 2) return 1;
+  if (o.no_split < 0 || o.no_split > 1) return 1;
   return 0;
 }
+
+// Row-half split of the step-1 critical path: only with several workers (the
+// halves then run side by side) and unless the caller turned it off.
+int split_for(const spdinv_opts& o, int workers) { return !o.no_split && workers > 1 ? 1 : 0; }
 
 // Persistent workgroups per CU for an order of t tiles.  The scheduler's
 // kernel fits two on a CU, which pays only where the DAG keeps twice as many
@@ -165,12 +176,13 @@ int grid_for(int device, int t, const spdinv_opts& o) {
 }
 
 // The plan for t tiles per side, built once per (device, variant, workers,
-// chain) and kept with its device copy.  chain: most products per device
-// task (1 for executors that run the paper's tasks one by one).
+// chain, split) and kept with its device copy.  chain: most products per
+// device task (1 for executors that run the paper's tasks one by one).
+// allow_split: the executor runs row-half tasks (the FP64 scheduler).
 DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, int chain,
-                  hipError_t* err, int steps = 7, int rhs_tiles = 0) {
+                  hipError_t* err, int steps = 7, int rhs_tiles = 0, bool allow_split = false) {
   Key k{device, t, o.renamed ? 1 : 0, o.loop_order, o.pipelined ? 1 : 0, o.trtri_first ? 1 : 0,
-        workers, chain, steps, rhs_tiles};
+        workers, chain, steps, rhs_tiles, allow_split ? split_for(o, workers) : 0};
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_plans.find(k);
   if (it != g_plans.end()) return it->second.get();
@@ -184,6 +196,7 @@ DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, int chai
   po.chain = k.chain;
   po.steps = k.steps;
   po.rhs_tiles = k.rhs;
+  po.split = k.split;
   build_plan(po, workers, kCost, &dp->host);
   const Plan& p = dp->host;
   const size_t nt = p.tasks.size();
@@ -283,7 +296,7 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   const int t = tiles_for(n);
   const int grid = grid_for(device, t, o);
   hipError_t err = hipSuccess;
-  DevPlan* dp = get_plan(device, t, o, grid, chain_for(o), &err, steps, s);
+  DevPlan* dp = get_plan(device, t, o, grid, chain_for(o), &err, steps, s, true);
   if (!dp) return SPDINV_ERR_HIP;
   const int ntask = (int)dp->host.tasks.size();
 
@@ -845,6 +858,7 @@ int spdinv_plan_export_steps(int steps, int rhs_tiles, int t, const spdinv_opts*
   PlanOptions po = plan_options(t, opts);
   po.steps = steps;
   po.rhs_tiles = rhs_tiles;
+  po.split = split_for(opts ? *opts : defaults(), workers);
   build_plan(po, workers > 0 ? workers : 1, kCost, &p);
   if (ntasks) *ntasks = (long long)p.tasks.size();
   if (nsucc) *nsucc = (long long)p.succ.size();
@@ -868,7 +882,7 @@ long long spdinv_trace_copy(const void* work, int n, const spdinv_opts* opts, in
   if (hipGetDevice(&device) != hipSuccess) return -2;
   hipError_t err = hipSuccess;
   DevPlan* dp = get_plan(device, tiles_for(n), o, grid_for(device, tiles_for(n), o),
-                        chain_for(o), &err);
+                        chain_for(o), &err, 7, 0, true);
   if (!dp) return -2;
   const Plan& p = dp->host;
   const long long nt = (long long)p.tasks.size();

@@ -444,6 +444,67 @@ void chain_products(int chain, Plan* p, std::vector<std::vector<int32_t>>& preds
 
 }  // namespace
 
+// Splits the products between POTRF(j) and POTRF(j+1), TRSM(j+1, j) and the
+// last SYRK into tile (j+1, j+1), into row-half tasks (K_HALF) when they are
+// single column-form products.  Both halves take the product's
+// predecessors, every successor of the product waits for both, and the
+// second half follows the first in program order (which stays topological).
+void split_step1_path(Plan* p, std::vector<std::vector<int32_t>>& preds) {
+  const int n = (int)p->tasks.size();
+  auto single = [&](int v) {
+    const DevTask& d = p->tasks[v];
+    return column_product(d) && task_links(d.kind) == 0 && !(d.kind & K_HALF);
+  };
+  std::vector<char> mark(n, 0);
+  for (int v = 0; v < n; ++v) {
+    const DevTask& pot = p->tasks[v];
+    if (task_kind(pot.kind) != K_POTRF) continue;
+    for (int q : preds[v]) {
+      const DevTask& sy = p->tasks[q];
+      if (task_kind(sy.kind) != K_SYRK1 || sy.out != pot.out || !single(q)) continue;
+      mark[q] = 1;
+      for (int r : preds[q]) {
+        const DevTask& tr = p->tasks[r];
+        if (task_kind(tr.kind) == K_TRSM1 && tr.out == sy.a && single(r)) mark[r] = 1;
+      }
+    }
+  }
+  std::vector<int32_t> first(n), second(n, -1);
+  int m = 0;
+  for (int v = 0; v < n; ++v) {
+    first[v] = m++;
+    if (mark[v]) second[v] = m++;
+  }
+  if (m == n) return;
+  std::vector<DevTask> tasks(m);
+  std::vector<int32_t> step(m), idx(m);
+  std::vector<std::vector<int32_t>> np(m);
+  for (int v = 0; v < n; ++v) {
+    std::vector<int32_t> pv;
+    pv.reserve(preds[v].size() + 2);
+    for (int q : preds[v]) {
+      pv.push_back(first[q]);
+      if (second[q] >= 0) pv.push_back(second[q]);
+    }
+    tasks[first[v]] = p->tasks[v];
+    step[first[v]] = p->step[v];
+    idx[first[v]] = p->idx[v];
+    if (mark[v]) {
+      tasks[first[v]].kind |= K_HALF;
+      tasks[second[v]] = p->tasks[v];
+      tasks[second[v]].kind |= K_HALF | K_HALF_HI;
+      step[second[v]] = p->step[v];
+      idx[second[v]] = p->idx[v];
+      np[second[v]] = pv;
+    }
+    np[first[v]] = std::move(pv);
+  }
+  p->tasks.swap(tasks);
+  p->step.swap(step);
+  p->idx.swap(idx);
+  preds.swap(np);
+}
+
 void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p) {
   *p = Plan();
   p->opt = opt;
@@ -595,6 +656,7 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
     // slack: 5 single-product durations (the unit of `cost`)
     chain_products(opt.chain, p, bld.preds, st0, dur0, cost ? cost[K_COUNT] : 1.0, 5.0);
   }
+  if (opt.split) split_step1_path(p, bld.preds);
 
   const int n = (int)p->tasks.size();
   // CSR successors
@@ -618,10 +680,14 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
   }
 
   // dispatch order: list-scheduling simulation of the executed DAG
+  // (a row half costs cost[K_COUNT + 1] of the whole product)
   std::vector<double> dur(n);
-  for (int v = 0; v < n; ++v)
-    dur[v] = cost ? cost[task_kind(p->tasks[v].kind)] + cost[K_COUNT] * task_links(p->tasks[v].kind)
-                  : (double)weight(p->tasks[v].kind) * (1 + task_links(p->tasks[v].kind));
+  for (int v = 0; v < n; ++v) {
+    const int32_t k = p->tasks[v].kind;
+    dur[v] = cost ? cost[task_kind(k)] + cost[K_COUNT] * task_links(k)
+                  : (double)weight(k) * (1 + task_links(k));
+    if (k & K_HALF) dur[v] *= cost ? cost[K_COUNT + 1] : 0.5;
+  }
   list_schedule(bld.preds, dur, workers, &p->order, nullptr);
 }
 

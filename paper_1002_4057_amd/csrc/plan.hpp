@@ -73,6 +73,9 @@ struct PlanOptions {
   // as 6).
   int steps = 7;
   int rhs_tiles = 0;
+  // Split TRSM(j+1, j) and the last SYRK into tile (j+1, j+1), the products
+  // between POTRF(j) and POTRF(j+1), into row-half tasks (K_HALF).
+  int split = 0;
 };
 constexpr int MAX_CHAIN = 16;
 
@@ -123,6 +126,15 @@ constexpr int32_t LINK_KLAST = 1 << 30;
 constexpr int K_LINKS_SHIFT = 20;
 constexpr int32_t K_LINKS_MASK = 0xf << K_LINKS_SHIFT;
 inline int task_links(int32_t k) { return (k & K_LINKS_MASK) >> K_LINKS_SHIFT; }
+// Bit 24 of DevTask::kind on a single column-form product: a row-half task,
+// which forms and stores only rows 0-63 of the output tile (and their part of
+// the renaming copy), or rows 64-127 with bit 25.  The planner splits a
+// product on the step-1 critical path into the two halves, so that two
+// workgroups share it: both halves take the product's predecessors and every
+// successor waits for both (the halves write disjoint rows; an in-place
+// product reads only its own rows of the output tile).
+constexpr int32_t K_HALF = 1 << 24;
+constexpr int32_t K_HALF_HI = 1 << 25;
 inline int32_t task_kind(int32_t k) { return k & 0xff; }
 inline int32_t task_flags(int32_t k) { return (k >> 8) & 0xff; }
 
@@ -174,7 +186,8 @@ struct Plan {
 // Builds the plan.  `workers` and `cost` drive the list-scheduling simulation
 // that orders the dispatch list (cost[kind] = estimated duration of a task of
 // that kind, any unit; cost[K_COUNT] = duration of each further link of a
-// chained product; null = unit durations).
+// chained product; cost[K_COUNT + 1] = a row-half task's fraction of its
+// product's duration; null = unit durations, halves 0.5).
 void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* out);
 
 // Tile pool size in tiles for t tiles per side (and s tile columns of

@@ -13,6 +13,7 @@ NOP, SYRK1, POTRF, GEMM1, TRSM1, TRTRI, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEM
 GEMMS, TRSMS = 13, 14   # the solve with the factor
 POTRF_FACTOR_DEAD = 1 << 16
 LINKS_SHIFT = 20   # chained products: count of further links (see plan.hpp)
+HALF, HALF_HI = 1 << 24, 1 << 25   # row-half task: rows 0-63, or 64-127 with HALF_HI
 LINK_KLAST = 1 << 30   # link mark: reduction over the last tile block
 PRODUCTS = {SYRK1, GEMM1, TRSM1, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEMM3, SYRK3, GEMMS, TRSMS}
 F_TA, F_TB, F_MA, F_MB, F_LOWER, F_NEG, F_ACC, F_COPYT = 1, 2, 4, 8, 16, 32, 64, 128
@@ -56,7 +57,24 @@ def run_task(pool, task, t, links=None):
     factor_dead = bool(code & POTRF_FACTOR_DEAD)
     if kind == NOP:
         return
-    if kind in PRODUCTS:
+    if kind in PRODUCTS and code & HALF:
+        # one row half of a single product: only those rows of the output
+        # (and their part of the copy) are written
+        nb = pool.shape[1]
+        rows = slice(nb // 2, nb) if code & HALF_HI else slice(0, nb // 2)
+        A = pool[a].T if f & F_TA else pool[a]
+        B = pool[b].T if f & F_TB else pool[b]
+        p = (A @ B)[rows]
+        if f & F_NEG:
+            p = -p
+        r = pool[out][rows] + p if f & F_ACC else p
+        pool[out][rows] = r
+        if cp >= 0:
+            if f & F_COPYT:
+                pool[cp][:, rows] = r.T
+            else:
+                pool[cp][rows] = r
+    elif kind in PRODUCTS:
         ops = [(a, b)]
         for q in range((code >> LINKS_SHIFT) & 0xF):
             la, lb = (int(x) for x in links[aux + q])
