@@ -84,11 +84,12 @@ constexpr int panel_pairs() { return NB * KD / 2 / NTHREADS; }
 
 template <int CP = CPOL_AGENT, int KD = KC>
 __device__ __forceinline__ void panel_load(rsrc_t X, int k0, bool contig,
-                                           d2 (&r)[panel_pairs<KD>()]) {
+                                           d2 (&r)[panel_pairs<KD>()], int skip = 0) {
   const int tid = threadIdx.x;
-  if (contig) {
+  if (contig) {  // (skip: added to this lane's offsets; past the tile, a load reads zero)
 #pragma unroll
-    for (int q = 0; q < panel_pairs<KD>(); ++q) r[q] = ld2<CP>(X, NB * k0 + 2 * (tid + NTHREADS * q));
+    for (int q = 0; q < panel_pairs<KD>(); ++q)
+      r[q] = ld2<CP>(X, NB * k0 + 2 * (tid + NTHREADS * q) + skip);
   } else {
 #pragma unroll
     for (int q = 0; q < panel_pairs<KD>(); ++q) {

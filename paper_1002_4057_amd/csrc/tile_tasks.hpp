@@ -201,11 +201,16 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
   }
 
   d2 ra[SPAIRS], rb[SPAIRS];
+  // R64: a lane holds rows 2 (lane % 64) and 2 (lane % 64) + 1 of the A
+  // panel; lanes whose rows lie outside this half skip their loads (an
+  // offset past the tile reads zero without touching memory), so a row half
+  // reads only its own rows of A
+  const int a_skip = (R64 && ((threadIdx.x & 63) >> 5) != half) ? (1 << 26) : 0;
   // operand panels: through the L2 when the planner allows it for this read
   // (nca / ncb), device-coherent otherwise
   auto load_a = [&](int k0) {
-    if (nca) panel_load<0, SKC>(rA, k0, a_contig, ra);
-    else panel_load<CPOL_AGENT, SKC>(rA, k0, a_contig, ra);
+    if (nca) panel_load<0, SKC>(rA, k0, a_contig, ra, a_skip);
+    else panel_load<CPOL_AGENT, SKC>(rA, k0, a_contig, ra, a_skip);
   };
   auto load_b = [&](int k0) {
     if (ncb) panel_load<0, SKC>(rB, k0, b_contig, rb);
