@@ -99,10 +99,12 @@ typedef struct {
                       per side, where the DAG keeps enough tasks ready, else
                       1; or 1 or 2).  Results do not depend on it.           */
   int no_split;    /* FP64 form: 0 (default) = with more than one worker, run
-                      each of TRSM(j+1, j) and the last SYRK into tile
-                      (j+1, j+1) -- the products between POTRF(j) and
-                      POTRF(j+1) -- as two row-half tasks on two workgroups;
-                      1 = as whole tasks.  Results do not depend on it.      */
+                      the products on chains of dependent tasks as two
+                      row-half tasks each, on two workgroups: TRSM(j+1, j)
+                      and the last SYRK into tile (j+1, j+1), between POTRF(j)
+                      and POTRF(j+1), and in the solve each multiplication by
+                      D_i or D_i^T with the last update before it; 1 = as
+                      whole tasks.  Results do not depend on it.             */
 } spdinv_opts;
 
 typedef struct {

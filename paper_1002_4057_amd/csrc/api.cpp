@@ -134,8 +134,9 @@ int check_opts(const spdinv_opts& o) {
   return 0;
 }
 
-// Row-half split of the step-1 critical path: only with several workers (the
-// halves then run side by side) and unless the caller turned it off.
+// Row-half split of the products on chains of dependent tasks: only with
+// several workers (the halves then run side by side) and unless the caller
+// turned it off.
 int split_for(const spdinv_opts& o, int workers) { return !o.no_split && workers > 1 ? 1 : 0; }
 
 // Persistent workgroups per CU for an order of t tiles.  The scheduler's

@@ -444,18 +444,30 @@ void chain_products(int chain, Plan* p, std::vector<std::vector<int32_t>>& preds
 
 }  // namespace
 
-// Splits the products between POTRF(j) and POTRF(j+1), TRSM(j+1, j) and the
-// last SYRK into tile (j+1, j+1), into row-half tasks (K_HALF) when they are
-// single column-form products.  Both halves take the product's
-// predecessors, every successor of the product waits for both, and the
-// second half follows the first in program order (which stays topological).
-void split_step1_path(Plan* p, std::vector<std::vector<int32_t>>& preds) {
+// Splits the single column-form products of the chains of dependent tasks
+// into row-half tasks (K_HALF): between POTRF(j) and POTRF(j+1), TRSM(j+1, j)
+// and the last SYRK into tile (j+1, j+1); in the solve, each multiplication
+// by D_i or D_i^T and the last update of its right-hand-side tile before it
+// (each row's pair waits for the previous row's).  Both halves take the
+// product's predecessors, every successor of the product waits for both,
+// and the second half follows the first in program order (which stays
+// topological).
+void split_critical_products(Plan* p, std::vector<std::vector<int32_t>>& preds) {
   const int n = (int)p->tasks.size();
   auto single = [&](int v) {
     const DevTask& d = p->tasks[v];
     return column_product(d) && task_links(d.kind) == 0 && !(d.kind & K_HALF);
   };
   std::vector<char> mark(n, 0);
+  for (int v = 0; v < n; ++v) {
+    const DevTask& ts = p->tasks[v];
+    if (task_kind(ts.kind) != K_TRSMS || !single(v)) continue;
+    mark[v] = 1;
+    for (int q : preds[v]) {
+      const DevTask& up = p->tasks[q];
+      if (task_kind(up.kind) == K_GEMMS && up.out == ts.out && single(q)) mark[q] = 1;
+    }
+  }
   for (int v = 0; v < n; ++v) {
     const DevTask& pot = p->tasks[v];
     if (task_kind(pot.kind) != K_POTRF) continue;
@@ -656,7 +668,7 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
     // slack: 5 single-product durations (the unit of `cost`)
     chain_products(opt.chain, p, bld.preds, st0, dur0, cost ? cost[K_COUNT] : 1.0, 5.0);
   }
-  if (opt.split) split_step1_path(p, bld.preds);
+  if (opt.split) split_critical_products(p, bld.preds);
 
   const int n = (int)p->tasks.size();
   // CSR successors

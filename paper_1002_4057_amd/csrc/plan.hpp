@@ -73,8 +73,10 @@ struct PlanOptions {
   // as 6).
   int steps = 7;
   int rhs_tiles = 0;
-  // Split TRSM(j+1, j) and the last SYRK into tile (j+1, j+1), the products
-  // between POTRF(j) and POTRF(j+1), into row-half tasks (K_HALF).
+  // Split the products of the chains of dependent tasks into row-half tasks
+  // (K_HALF): TRSM(j+1, j) and the last SYRK into tile (j+1, j+1), between
+  // POTRF(j) and POTRF(j+1), and in the solve each multiplication by D_i or
+  // D_i^T with the last update before it.
   int split = 0;
 };
 constexpr int MAX_CHAIN = 16;
@@ -129,8 +131,8 @@ inline int task_links(int32_t k) { return (k & K_LINKS_MASK) >> K_LINKS_SHIFT; }
 // Bit 24 of DevTask::kind on a single column-form product: a row-half task,
 // which forms and stores only rows 0-63 of the output tile (and their part of
 // the renaming copy), or rows 64-127 with bit 25.  The planner splits a
-// product on the step-1 critical path into the two halves, so that two
-// workgroups share it: both halves take the product's predecessors and every
+// product on a chain of dependent tasks (see PlanOptions::split) into the
+// two halves, so that two workgroups share it: both halves take the product's predecessors and every
 // successor waits for both (the halves write disjoint rows; an in-place
 // product reads only its own rows of the output tile).
 constexpr int32_t K_HALF = 1 << 24;

@@ -80,3 +80,26 @@ def test_split_option_range_checked(bad):
     o = _lib.make_opts(no_split=bad)
     assert lib.spd_inverse(4, ctypes.c_void_p(8), 4, 0, None, 0, None, ctypes.byref(o), None,
                            None) != 0
+
+
+@pytest.mark.parametrize("steps,s", [(9, 1), (9, 2), (8, 1)])
+@pytest.mark.parametrize("t", [3, 6])
+def test_solve_chain_products_split(t, steps, s):
+    """In the solve each row's multiplication by D_i (or D_i^T) and the last
+    update of that right-hand-side tile before it form the chain of
+    dependent tasks; both run as row halves."""
+    GEMMS, TRSMS = 13, 14
+    p = spd.plan_export(t, workers=8, steps=steps, rhs_tiles=s)
+    tasks = p["tasks"]
+    code = tasks[:, 0]
+    kind = code & 0xFF
+    half, hi = (code & HALF) != 0, (code & HALF_HI) != 0
+    trsms = np.where((kind == TRSMS) & ~hi)[0]
+    assert len(trsms) == 2 * t * s and np.all(half[trsms])
+    pr = preds_of(p)
+    for v in trsms:
+        ups = [u for u in pr[v] if kind[u] == GEMMS and tasks[u, 1] == tasks[v, 1]]
+        assert all(half[u] for u in ups)
+    n_hi = int(hi.sum())
+    whole = spd.plan_export(t, workers=8, steps=steps, rhs_tiles=s, no_split=1)
+    assert len(tasks) == len(whole["tasks"]) + n_hi
