@@ -314,7 +314,10 @@ int spdinv_plan_stats_get(int t, const spdinv_opts* opts, spdinv_plan_stats* out
  * indices (i<<20 | j<<10 | k) and the device dispatch order.  With
  * opts->chain != 1 a product task may carry further links: bits 20-23 of
  * kind count them, aux indexes the first in `links` (int32 pairs: operand
- * tiles a, b).
+ * tiles a, b).  With workers > 1 and opts->no_split == 0, bit 24 of kind
+ * marks a row-half task (rows 0-63 of the output tile and of its renaming
+ * copy, or rows 64-127 with bit 25); the two halves of a product are
+ * adjacent in program order and have the same predecessors and successors.
  * Pass NULL buffers to query the sizes (ntasks, nsucc, nlinks).  `workers`
  * sizes the list-scheduling simulation that produces the order.
  */
