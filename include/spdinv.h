@@ -99,8 +99,9 @@ typedef struct {
                       per side, where the DAG keeps enough tasks ready, else
                       1; or 1 or 2).  Results do not depend on it.           */
   int no_split;    /* FP64 form: 0 (default) = with more than one worker, run
-                      the products on chains of dependent tasks as two
-                      row-half tasks each, on two workgroups: TRSM(j+1, j)
+                      the products on chains of dependent tasks as row-part
+                      tasks, run side by side (four quarters below 96 tiles
+                      per side, two halves from there): TRSM(j+1, j)
                       and the last SYRK into tile (j+1, j+1), between POTRF(j)
                       and POTRF(j+1), and in the solve each multiplication by
                       D_i or D_i^T with the last update before it; 1 = as
@@ -315,8 +316,9 @@ int spdinv_plan_stats_get(int t, const spdinv_opts* opts, spdinv_plan_stats* out
  * opts->chain != 1 a product task may carry further links: bits 20-23 of
  * kind count them, aux indexes the first in `links` (int32 pairs: operand
  * tiles a, b).  With workers > 1 and opts->no_split == 0, bit 24 of kind
- * marks a row-half task (rows 0-63 of the output tile and of its renaming
- * copy, or rows 64-127 with bit 25); the two halves of a product are
+ * marks a row-part task: part p (bits 25-26) of the output tile's rows and
+ * of its renaming copy, rows 64p..64p+63 of two halves, or rows
+ * 32p..32p+31 of four quarters with bit 27; the parts of a product are
  * adjacent in program order and have the same predecessors and successors.
  * Pass NULL buffers to query the sizes (ntasks, nsucc, nlinks).  `workers`
  * sizes the list-scheduling simulation that produces the order.

@@ -476,10 +476,11 @@ def trace(work, n: int, **opts) -> np.ndarray:
     lib = load()
     o = make_opts(**opts)
     t = -(-int(n) // 128)
-    # the paper's tasks, two barriers and the second halves of split products
+    # the paper's tasks, two barriers and the further row parts of split
+    # products (at most 3 each, for at most 2t products)
     nt = plan_stats(t, **{k: v for k, v in opts.items()
                           if k in ("renamed", "loop_order", "pipelined", "trtri_first")})["tasks"]
-    nt += 2 + 2 * t
+    nt += 2 + 6 * t
     buf = np.zeros((nt, 4), dtype=np.int64)
     import torch
     torch.cuda.synchronize()

@@ -100,11 +100,14 @@ int chain_for(const spdinv_opts& o) { return o.chain > 0 ? o.chain : kDefaultCha
 
 int tiles_for(int n) { return (n + NB - 1) / NB; }
 
-// Device tasks of the plan at most: the paper's tasks, two barriers, and the
-// second halves of the split products (two per column).
-long long task_count(int t) {
-  const long long tt = t;
-  return 3 * (tt * (tt - 1) * (tt - 2) / 6) + 6 * (tt * (tt - 1) / 2) + 3 * tt + 2 + 2 * tt;
+// Device tasks of a plan at most, for t tiles per side and s tile columns of
+// right-hand sides: the paper's tasks of the three steps, two barriers, the
+// solve's (t (t+1) s <= 2 t^2 s), and the further row parts of split products
+// (at most 3 each, for at most 2t products of step 1 and 4ts of the solve).
+long long task_count(int t, int s = 0) {
+  const long long tt = t, ss = s;
+  return 3 * (tt * (tt - 1) * (tt - 2) / 6) + 6 * (tt * (tt - 1) / 2) + 3 * tt + 2 +
+         2 * tt * tt * ss + 3 * (2 * tt + 4 * tt * ss);
 }
 
 struct Layout {
@@ -115,7 +118,7 @@ Layout layout(int n, const spdinv_opts& o, int nrhs = 0) {
   Layout L;
   const int t = tiles_for(n);
   const int s = (nrhs + NB - 1) / NB;
-  const long long nt = task_count(t) + 2LL * t * t * s;  // + the solve's tasks
+  const long long nt = task_count(t, s);
   L.pool = 0;
   L.indeg = align_up((size_t)pool_tiles(t, s) * NB * NB * sizeof(double), 256);
   L.ctrl = L.indeg + align_up((size_t)nt * sizeof(int32_t), 256);
@@ -134,10 +137,6 @@ int check_opts(const spdinv_opts& o) {
   return 0;
 }
 
-// Row-half split of the products on chains of dependent tasks: only with
-// several workers (the halves then run side by side) and unless the caller
-// turned it off.
-int split_for(const spdinv_opts& o, int workers) { return !o.no_split && workers > 1 ? 1 : 0; }
 
 // Persistent workgroups per CU for an order of t tiles.  The scheduler's
 // kernel fits two on a CU, which pays only where the DAG keeps twice as many
@@ -145,6 +144,18 @@ int split_for(const spdinv_opts& o, int workers) { return !o.no_split && workers
 // side (workers wait for dependencies while the busy ones share CUs), 5%
 // slower at 80, 11% faster at 96, 14% at 112, 4-8% at 128.
 constexpr int kWideTiles = 96;
+
+// Row-part split of the products on chains of dependent tasks: only with
+// several workers (the parts then run side by side) and unless the caller
+// turned it off.
+// Four row parts per product below kWideTiles tiles per side, two from there
+// (measured at n = 8192: quarters made the Cholesky factor 6 % and the solve
+// 7 % faster than halves, the inverse the same; at n = 16384, with two
+// workgroups per CU, the inverse was 3 % slower with quarters).
+int split_for(const spdinv_opts& o, int t, int workers) {
+  if (o.no_split || workers <= 1) return 0;
+  return t < kWideTiles ? 4 : 2;
+}
 
 int per_cu_for(int t, const spdinv_opts& o) {
   static int capacity = 0;  // workgroups per CU that fit (same for every device here)
@@ -183,7 +194,7 @@ int grid_for(int device, int t, const spdinv_opts& o) {
 DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, int chain,
                   hipError_t* err, int steps = 7, int rhs_tiles = 0, bool allow_split = false) {
   Key k{device, t, o.renamed ? 1 : 0, o.loop_order, o.pipelined ? 1 : 0, o.trtri_first ? 1 : 0,
-        workers, chain, steps, rhs_tiles, allow_split ? split_for(o, workers) : 0};
+        workers, chain, steps, rhs_tiles, allow_split ? split_for(o, t, workers) : 0};
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = g_plans.find(k);
   if (it != g_plans.end()) return it->second.get();
@@ -859,7 +870,7 @@ int spdinv_plan_export_steps(int steps, int rhs_tiles, int t, const spdinv_opts*
   PlanOptions po = plan_options(t, opts);
   po.steps = steps;
   po.rhs_tiles = rhs_tiles;
-  po.split = split_for(opts ? *opts : defaults(), workers);
+  po.split = split_for(opts ? *opts : defaults(), t, workers);
   build_plan(po, workers > 0 ? workers : 1, kCost, &p);
   if (ntasks) *ntasks = (long long)p.tasks.size();
   if (nsucc) *nsucc = (long long)p.succ.size();

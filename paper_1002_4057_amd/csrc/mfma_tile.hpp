@@ -297,21 +297,21 @@ __device__ __forceinline__ void acc_store_tile(rsrc_t r, const d4 (&acc)[4][4], 
       }
 }
 
-// The same for one half of the rows of a tile (h = 0: rows 0..63, h = 1:
-// rows 64..127), the four waves side by side: wave w holds the 64 rows
-// (accumulators i = 0..3) of columns 32 w .. 32 w + 31 (accumulators
+// The same for 16 IN rows of a tile from row row0 (IN = 4: a half, 2: a
+// quarter), the four waves side by side: wave w holds the rows
+// (accumulators i < IN) of columns 32 w .. 32 w + 31 (accumulators
 // j = 0..1); register r of accumulator (i, j) of this lane holds tile element
-// 64 h + 16 i + lane % 16 + NB (32 w + 16 j + lane / 16 + 4 r).
-__device__ __forceinline__ int acc_lane_bytes_r64(int h) {
+// row0 + 16 i + lane % 16 + NB (32 w + 16 j + lane / 16 + 4 r).
+__device__ __forceinline__ int acc_lane_bytes_r64(int row0) {
   const int t = opaque_tid(), lane = t & 63, w = t >> 6;
-  return 8 * ((lane & 15) + NB * (32 * w + (lane >> 4))) + 512 * h;
+  return 8 * ((lane & 15) + NB * (32 * w + (lane >> 4))) + 8 * row0;
 }
 
-template <int CP = CPOL_AGENT>
-__device__ __forceinline__ void acc_load_r64(rsrc_t r, d4 (&acc)[4][4], bool neg, int h = 0) {
-  const int vb = acc_lane_bytes_r64(h);
+template <int IN = 4, int CP = CPOL_AGENT>
+__device__ __forceinline__ void acc_load_r64(rsrc_t r, d4 (&acc)[4][4], bool neg, int row0 = 0) {
+  const int vb = acc_lane_bytes_r64(row0);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < IN; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -322,12 +322,12 @@ __device__ __forceinline__ void acc_load_r64(rsrc_t r, d4 (&acc)[4][4], bool neg
       }
 }
 
-template <int CP = CPOL_AGENT>
+template <int IN = 4, int CP = CPOL_AGENT>
 __device__ __forceinline__ void acc_store_r64(rsrc_t r, const d4 (&acc)[4][4], bool neg,
-                                              int h = 0) {
-  const int vb = acc_lane_bytes_r64(h);
+                                              int row0 = 0) {
+  const int vb = acc_lane_bytes_r64(row0);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < IN; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll

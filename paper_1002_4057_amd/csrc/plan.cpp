@@ -445,18 +445,18 @@ void chain_products(int chain, Plan* p, std::vector<std::vector<int32_t>>& preds
 }  // namespace
 
 // Splits the single column-form products of the chains of dependent tasks
-// into row-half tasks (K_HALF): between POTRF(j) and POTRF(j+1), TRSM(j+1, j)
+// into `parts` row-part tasks (K_PART, 2 or 4): between POTRF(j) and POTRF(j+1), TRSM(j+1, j)
 // and the last SYRK into tile (j+1, j+1); in the solve, each multiplication
 // by D_i or D_i^T and the last update of its right-hand-side tile before it
 // (each row's pair waits for the previous row's).  Both halves take the
-// product's predecessors, every successor of the product waits for both,
-// and the second half follows the first in program order (which stays
+// product's predecessors, every successor of the product waits for all of
+// them, and the parts follow each other in program order (which stays
 // topological).
-void split_critical_products(Plan* p, std::vector<std::vector<int32_t>>& preds) {
+void split_critical_products(Plan* p, std::vector<std::vector<int32_t>>& preds, int parts) {
   const int n = (int)p->tasks.size();
   auto single = [&](int v) {
     const DevTask& d = p->tasks[v];
-    return column_product(d) && task_links(d.kind) == 0 && !(d.kind & K_HALF);
+    return column_product(d) && task_links(d.kind) == 0 && !(d.kind & K_PART);
   };
   std::vector<char> mark(n, 0);
   for (int v = 0; v < n; ++v) {
@@ -481,11 +481,12 @@ void split_critical_products(Plan* p, std::vector<std::vector<int32_t>>& preds) 
       }
     }
   }
-  std::vector<int32_t> first(n), second(n, -1);
+  std::vector<int32_t> first(n), count(n, 1);
   int m = 0;
   for (int v = 0; v < n; ++v) {
-    first[v] = m++;
-    if (mark[v]) second[v] = m++;
+    first[v] = m;
+    if (mark[v]) count[v] = parts;
+    m += count[v];
   }
   if (m == n) return;
   std::vector<DevTask> tasks(m);
@@ -494,22 +495,17 @@ void split_critical_products(Plan* p, std::vector<std::vector<int32_t>>& preds) 
   for (int v = 0; v < n; ++v) {
     std::vector<int32_t> pv;
     pv.reserve(preds[v].size() + 2);
-    for (int q : preds[v]) {
-      pv.push_back(first[q]);
-      if (second[q] >= 0) pv.push_back(second[q]);
+    for (int q : preds[v])
+      for (int c = 0; c < count[q]; ++c) pv.push_back(first[q] + c);
+    for (int c = 0; c < count[v]; ++c) {
+      const int u = first[v] + c;
+      tasks[u] = p->tasks[v];
+      if (mark[v])
+        tasks[u].kind |= K_PART | (c << K_PART_SHIFT) | (parts == 4 ? K_PARTS4 : 0);
+      step[u] = p->step[v];
+      idx[u] = p->idx[v];
+      np[u] = pv;
     }
-    tasks[first[v]] = p->tasks[v];
-    step[first[v]] = p->step[v];
-    idx[first[v]] = p->idx[v];
-    if (mark[v]) {
-      tasks[first[v]].kind |= K_HALF;
-      tasks[second[v]] = p->tasks[v];
-      tasks[second[v]].kind |= K_HALF | K_HALF_HI;
-      step[second[v]] = p->step[v];
-      idx[second[v]] = p->idx[v];
-      np[second[v]] = pv;
-    }
-    np[first[v]] = std::move(pv);
   }
   p->tasks.swap(tasks);
   p->step.swap(step);
@@ -668,7 +664,7 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
     // slack: 5 single-product durations (the unit of `cost`)
     chain_products(opt.chain, p, bld.preds, st0, dur0, cost ? cost[K_COUNT] : 1.0, 5.0);
   }
-  if (opt.split) split_critical_products(p, bld.preds);
+  if (opt.split == 2 || opt.split == 4) split_critical_products(p, bld.preds, opt.split);
 
   const int n = (int)p->tasks.size();
   // CSR successors
@@ -692,13 +688,16 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
   }
 
   // dispatch order: list-scheduling simulation of the executed DAG
-  // (a row half costs cost[K_COUNT + 1] of the whole product)
+  // (a row half costs cost[K_COUNT + 1] of the whole product, a quarter
+  // 0.75 of that)
   std::vector<double> dur(n);
   for (int v = 0; v < n; ++v) {
     const int32_t k = p->tasks[v].kind;
     dur[v] = cost ? cost[task_kind(k)] + cost[K_COUNT] * task_links(k)
                   : (double)weight(k) * (1 + task_links(k));
-    if (k & K_HALF) dur[v] *= cost ? cost[K_COUNT + 1] : 0.5;
+    if (k & K_PART)
+      dur[v] *= cost ? cost[K_COUNT + 1] * ((k & K_PARTS4) ? 0.75 : 1.0)
+                     : ((k & K_PARTS4) ? 0.25 : 0.5);
   }
   list_schedule(bld.preds, dur, workers, &p->order, nullptr);
 }

@@ -73,10 +73,10 @@ struct PlanOptions {
   // as 6).
   int steps = 7;
   int rhs_tiles = 0;
-  // Split the products of the chains of dependent tasks into row-half tasks
-  // (K_HALF): TRSM(j+1, j) and the last SYRK into tile (j+1, j+1), between
-  // POTRF(j) and POTRF(j+1), and in the solve each multiplication by D_i or
-  // D_i^T with the last update before it.
+  // Split the products of the chains of dependent tasks into split (2 or 4)
+  // row-part tasks (K_PART), 0 = none: TRSM(j+1, j) and the last SYRK into
+  // tile (j+1, j+1), between POTRF(j) and POTRF(j+1), and in the solve each
+  // multiplication by D_i or D_i^T with the last update before it.
   int split = 0;
 };
 constexpr int MAX_CHAIN = 16;
@@ -128,15 +128,18 @@ constexpr int32_t LINK_KLAST = 1 << 30;
 constexpr int K_LINKS_SHIFT = 20;
 constexpr int32_t K_LINKS_MASK = 0xf << K_LINKS_SHIFT;
 inline int task_links(int32_t k) { return (k & K_LINKS_MASK) >> K_LINKS_SHIFT; }
-// Bit 24 of DevTask::kind on a single column-form product: a row-half task,
-// which forms and stores only rows 0-63 of the output tile (and their part of
-// the renaming copy), or rows 64-127 with bit 25.  The planner splits a
-// product on a chain of dependent tasks (see PlanOptions::split) into the
-// two halves, so that two workgroups share it: both halves take the product's predecessors and every
-// successor waits for both (the halves write disjoint rows; an in-place
-// product reads only its own rows of the output tile).
-constexpr int32_t K_HALF = 1 << 24;
-constexpr int32_t K_HALF_HI = 1 << 25;
+// Bit 24 of DevTask::kind on a single column-form product: a row-part task,
+// which forms and stores only part idx (bits 25-26) of the output tile's
+// rows (and their part of the renaming copy): rows 64 idx .. 64 idx + 63 of
+// two halves, or with bit 27 rows 32 idx .. 32 idx + 31 of four quarters.
+// The planner splits a product on a chain of dependent tasks (see
+// PlanOptions::split) into its parts, so that several workgroups share it:
+// every part takes the product's predecessors and every successor waits for
+// all of them (the parts write disjoint rows; an in-place product reads only
+// its own rows of the output tile).
+constexpr int32_t K_PART = 1 << 24;
+constexpr int K_PART_SHIFT = 25;
+constexpr int32_t K_PARTS4 = 1 << 27;
 inline int32_t task_kind(int32_t k) { return k & 0xff; }
 inline int32_t task_flags(int32_t k) { return (k >> 8) & 0xff; }
 
@@ -188,8 +191,9 @@ struct Plan {
 // Builds the plan.  `workers` and `cost` drive the list-scheduling simulation
 // that orders the dispatch list (cost[kind] = estimated duration of a task of
 // that kind, any unit; cost[K_COUNT] = duration of each further link of a
-// chained product; cost[K_COUNT + 1] = a row-half task's fraction of its
-// product's duration; null = unit durations, halves 0.5).
+// chained product; cost[K_COUNT + 1] = a row half's fraction of its
+// product's duration (a quarter: 0.75 of that); null = unit durations, a
+// part 1/split).
 void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* out);
 
 // Tile pool size in tiles for t tiles per side (and s tile columns of

@@ -99,18 +99,19 @@ __device__ __forceinline__ void copy_epilogue(double* copy, const d4 (&acc)[4][4
   }
 }
 
-// The renaming copy of a row-half product (rows 64h .. 64h+63, the waves side
-// by side as in acc_load_r64): the half is staged in LDS as in copy_epilogue
-// and leaves as contiguous 16-byte stores, columns 64h .. 64h+63 of the copy
-// (copy_t) or its rows 64h .. 64h+63.
+// The renaming copy of a row-part product (RN rows from row0, the waves side
+// by side as in acc_load_r64): the part is staged in LDS as in copy_epilogue
+// and leaves as contiguous 16-byte stores, columns row0 .. row0+RN-1 of the
+// copy (copy_t) or its rows row0 .. row0+RN-1.
+template <int RN>
 __device__ __forceinline__ void copy_epilogue_r64(double* copy, const d4 (&acc)[4][4], bool neg,
-                                                  bool copy_t, double* smem, int h) {
+                                                  bool copy_t, double* smem, int row0) {
   const int tid = opaque_tid(), lane = tid & 63, w = tid >> 6;
   const int lr = lane & 15, lk = lane >> 4;
   const rsrc_t rD = tile_rsrc(copy);
   double* R = smem;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < RN / 16; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int row = i * 16 + lr, col0 = w * 32 + j * 16 + lk;
@@ -119,20 +120,20 @@ __device__ __forceinline__ void copy_epilogue_r64(double* copy, const d4 (&acc)[
     }
   __syncthreads();
 #pragma unroll 4
-  for (int q = 0; q < NB * 64 / 2 / NTHREADS; ++q) {
+  for (int q = 0; q < NB * RN / 2 / NTHREADS; ++q) {
     const int e2 = 2 * (tid + NTHREADS * q);
     d2 v;
     int e;
-    if (copy_t) {  // copy(rr, 64h + cl) = result(64h + cl, rr)
+    if (copy_t) {  // copy(rr, row0 + cl) = result(row0 + cl, rr)
       const int rr = e2 & (NB - 1), cl = e2 >> 7;
       v.x = R[rr + RLD * cl];
       v.y = R[rr + 1 + RLD * cl];
-      e = rr + NB * (64 * h + cl);
-    } else {       // copy(64h + rl, cc) = result(64h + rl, cc)
-      const int rl = e2 & 63, cc = e2 >> 6;
+      e = rr + NB * (row0 + cl);
+    } else {       // copy(row0 + rl, cc) = result(row0 + rl, cc)
+      const int rl = e2 & (RN - 1), cc = e2 / RN;
       v.x = R[cc + RLD * rl];
       v.y = R[cc + RLD * (rl + 1)];
-      e = 64 * h + rl + NB * cc;
+      e = row0 + rl + NB * cc;
     }
     st2(rD, e, v);
   }
@@ -150,9 +151,9 @@ __device__ __forceinline__ void copy_epilogue_r64(double* copy, const d4 (&acc)[
 // time).  C may alias A or B: every operand read precedes the first store.
 // copy (may be null) receives the same result, transposed with F_COPYT.
 // npan: k-panels to run (fewer than SNCH skips the padded tail of a ragged
-// last tile block, see K_KLAST).  R64: only the output rows 64 half ..
-// 64 half + 63 are formed and stored (with their part of the copy); per
-// output element the MFMA sequence is that of the whole-tile product.
+// last tile block, see K_KLAST).  R64: only the RN output rows from row0
+// are formed and stored (with their part of the copy); per output element
+// the MFMA sequence is that of the whole-tile product.
 // Waves form a 2 x 2 grid of 64 x 64 output blocks, each a 4 x 4 array of
 // 16 x 16 MFMA accumulators.  The sign is handled without touching the
 // operands: the accumulator starts from -C and the result is negated on the
@@ -162,10 +163,10 @@ __device__ __forceinline__ void copy_epilogue_r64(double* copy, const d4 (&acc)[
 // (scheduling barriers keep the compiler from pulling their consumers into
 // the MFMA sequence).
 // ---------------------------------------------------------------------------
-template <bool FAST, bool R64 = false>
+template <bool FAST, bool R64 = false, int RN = 64>
 __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, const double* B,
                                          double* copy, double* smem, bool nca = false,
-                                         bool ncb = false, int npan = SNCH, int half = 0) {
+                                         bool ncb = false, int npan = SNCH, int prow = 0) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int wm = w & 1, wn = w >> 1;
@@ -177,11 +178,12 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
   const bool neg = (f & F_NEG) != 0, copy_t = (f & F_COPYT) != 0;
   const rsrc_t rA = tile_rsrc(A), rB = tile_rsrc(B), rC = tile_rsrc(C);
   const bool accum = (f & F_ACC) != 0;
-  const bool active = R64 ? !((f & F_LOWER) && half == 0 && w >= 2)
+  // (F_LOWER: the blocks skipped are those of the whole-tile product)
+  const bool active = R64 ? !((f & F_LOWER) && prow < 64 && w >= 2)
                           : !((f & F_LOWER) && wm == 0 && wn == 1);
-  // R64: 64 rows only, the waves side by side (32 columns each)
-  const int row0 = R64 ? 64 * half : wm * 64, col0 = R64 ? w * 32 : wn * 64;
-  constexpr int JN = R64 ? 2 : 4;
+  // R64: RN rows only, the waves side by side (32 columns each)
+  const int row0 = R64 ? prow : wm * 64, col0 = R64 ? w * 32 : wn * 64;
+  constexpr int JN = R64 ? 2 : 4, IN = R64 ? RN / 16 : 4;
 
   // v_mfma_f64_16x16x4(x, y, d): d[i][j] += sum_k x[i][k] y[k][j] with x[i][k]
   // from lane i+16k, y[k][j] from lane j+16k, and d[i][j] in register r = i/4
@@ -191,7 +193,7 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
   // covers 16 consecutive rows of one column (one 128-byte segment).
   d4 acc[4][4];
   if (accum) {
-    if constexpr (R64) acc_load_r64(rC, acc, neg, half);
+    if constexpr (R64) acc_load_r64<IN>(rC, acc, neg, prow);
     else acc_load(rC, acc, neg);
   } else {
 #pragma unroll
@@ -202,10 +204,11 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
 
   d2 ra[SPAIRS], rb[SPAIRS];
   // R64: a lane holds rows 2 (lane % 64) and 2 (lane % 64) + 1 of the A
-  // panel; lanes whose rows lie outside this half skip their loads (an
-  // offset past the tile reads zero without touching memory), so a row half
+  // panel; lanes whose rows lie outside this part skip their loads (an
+  // offset past the tile reads zero without touching memory), so a row part
   // reads only its own rows of A
-  const int a_skip = (R64 && ((threadIdx.x & 63) >> 5) != half) ? (1 << 26) : 0;
+  const int lrow = 2 * (threadIdx.x & 63);
+  const int a_skip = (R64 && (lrow < prow || lrow >= prow + RN)) ? (1 << 26) : 0;
   // operand panels: through the L2 when the planner allows it for this read
   // (nca / ncb), device-coherent otherwise
   auto load_a = [&](int k0) {
@@ -239,11 +242,11 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
       double a[4], b[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        a[i] = Ar[16 * i];
+        if (i < IN) a[i] = Ar[16 * i];
         if (i < JN) b[i] = Br[16 * i];
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < IN; ++i)
 #pragma unroll
         for (int j = 0; j < JN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[j], a[i], acc[i][j], 0, 0, 0);
@@ -258,9 +261,9 @@ __device__ __forceinline__ void tile_mma(int f, double* C, const double* A, cons
   }
 
   if constexpr (R64) {
-    if (active) acc_store_r64(rC, acc, neg, half);
+    if (active) acc_store_r64<IN>(rC, acc, neg, prow);
     if (!copy) return;  // uniform: the copy pointer is the same in every thread
-    copy_epilogue_r64(copy, acc, neg, copy_t, smem, half);
+    copy_epilogue_r64<RN>(copy, acc, neg, copy_t, smem, prow);
   } else {
     if (active) acc_store_tile(rC, acc, neg);
     if (!copy) return;  // uniform: the copy pointer is the same in every thread
@@ -1018,9 +1021,12 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
                                  npan_last);
           else
             tile_mma_chain(f, out, a, b, cp, smem, g.links + 2 * t.aux, nl, P, npan, npan_last);
-        } else if (t.kind & K_HALF) {  // one row half of a split product
-          tile_mma<true, true>(f, out, a, b, cp, smem, nca, ncb, npan,
-                               (t.kind & K_HALF_HI) ? 1 : 0);
+        } else if (t.kind & K_PART) {  // one row part of a split product
+          const int idx = (t.kind >> K_PART_SHIFT) & 3;
+          if (t.kind & K_PARTS4)
+            tile_mma<true, true, 32>(f, out, a, b, cp, smem, nca, ncb, npan, 32 * idx);
+          else
+            tile_mma<true, true>(f, out, a, b, cp, smem, nca, ncb, npan, 64 * idx);
         } else {
           if (r64) tile_mma<true, true>(f, out, a, b, cp, smem, nca, ncb, npan);
           else tile_mma<true>(f, out, a, b, cp, smem, nca, ncb, npan);

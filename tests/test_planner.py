@@ -114,9 +114,9 @@ def test_exported_plan_structure(opts):
     potrf = kind == 2
     assert np.all(tasks[potrf, 0] & (1 << 16)), "every POTRF factor store is dead"
     assert np.all(tasks[potrf, 4] == -1)
-    # (a split product's second row half writes the other rows of the same copy)
-    hi = (tasks[:, 0] & (1 << 25)) != 0
-    copies = tasks[:, 4][(tasks[:, 4] >= 0) & ~hi]
+    # (the later row parts of a split product write other rows of the same copy)
+    later = ((tasks[:, 0] & (1 << 24)) != 0) & (((tasks[:, 0] >> 25) & 3) != 0)
+    copies = tasks[:, 4][(tasks[:, 4] >= 0) & ~later]
     if opts.get("renamed", 1):
         assert len(copies) == 2 * T - t
         assert np.all((copies >= T) & (copies < 3 * T))
@@ -155,8 +155,8 @@ def test_l2_cacheable_reads_only_of_write_once_tiles(opts, t):
         for tile in [out, cp] + ([aux, aux + t] if k == 2 else []):
             if tile >= 0:
                 first_access.setdefault(tile, "write")
-                # the two row halves of a split product are one write of the tile
-                if not code & (1 << 25):
+                # the row parts of a split product are one write of the tile
+                if not (code & (1 << 24) and (code >> 25) & 3):
                     writes[tile] = writes.get(tile, 0) + 1
                 writer.setdefault(tile, []).append(u)
 

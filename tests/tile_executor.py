@@ -13,7 +13,7 @@ NOP, SYRK1, POTRF, GEMM1, TRSM1, TRTRI, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEM
 GEMMS, TRSMS = 13, 14   # the solve with the factor
 POTRF_FACTOR_DEAD = 1 << 16
 LINKS_SHIFT = 20   # chained products: count of further links (see plan.hpp)
-HALF, HALF_HI = 1 << 24, 1 << 25   # row-half task: rows 0-63, or 64-127 with HALF_HI
+PART, PART_SHIFT, PARTS4 = 1 << 24, 25, 1 << 27   # row-part task (see plan.hpp)
 LINK_KLAST = 1 << 30   # link mark: reduction over the last tile block
 PRODUCTS = {SYRK1, GEMM1, TRSM1, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEMM3, SYRK3, GEMMS, TRSMS}
 F_TA, F_TB, F_MA, F_MB, F_LOWER, F_NEG, F_ACC, F_COPYT = 1, 2, 4, 8, 16, 32, 64, 128
@@ -57,11 +57,13 @@ def run_task(pool, task, t, links=None):
     factor_dead = bool(code & POTRF_FACTOR_DEAD)
     if kind == NOP:
         return
-    if kind in PRODUCTS and code & HALF:
-        # one row half of a single product: only those rows of the output
+    if kind in PRODUCTS and code & PART:
+        # one row part of a single product: only those rows of the output
         # (and their part of the copy) are written
         nb = pool.shape[1]
-        rows = slice(nb // 2, nb) if code & HALF_HI else slice(0, nb // 2)
+        size = nb // (4 if code & PARTS4 else 2)
+        idx = (code >> PART_SHIFT) & 3
+        rows = slice(idx * size, (idx + 1) * size)
         A = pool[a].T if f & F_TA else pool[a]
         B = pool[b].T if f & F_TB else pool[b]
         p = (A @ B)[rows]
