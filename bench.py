@@ -1,17 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark of the tile SPD inverse on one MI355X.
 
-One step = one explicit inversion of the n = 8192 matrix A = Q diag(lambda) Q^T
-(lambda log-spaced over [1, 1e4], Q from a seeded QR) through the whole hot
-path: copy-in to tiles, the pipelined renamed three-step tile DAG on the
-persistent device scheduler, copy-out.  Each timed step inverts its own
-pre-made copy of A that is already resident in HBM.
+Headline: the precision workload's FP64 cell, n = 16384, A = Q diag(lambda)
+Q^T with lambda log-spaced over [1, 1e2] (Q from a seeded QR).  One step =
+one explicit inversion through the whole hot path: copy-in to tiles, the
+pipelined renamed three-step tile DAG on the persistent device scheduler,
+copy-out.  Each timed step inverts its own pre-made copy of A, resident in
+HBM.  Beside it ("precision" row), the FP64 form against the mixed-refined
+forms (FP32 and BF16 tile DAGs + binary64 Newton-Schulz) at each condition
+number of the workload, with each result's ||I - A X||_F / ||A||_F and error
+against the analytic inverse; the same at n = 32768 ("large" row).
 
-Prints one JSON line (rank 0).  Besides the throughput it reports the
-roofline of the dominant kernel (the scheduler kernel, which runs every tile
-task: n^3 algorithmic flops per launch, timed with HIP events on its stream),
-the oracle timed on the host cores on a bounded sample, the parity of one
-result against the analytic inverse, and pipelined vs unpipelined throughput.
+Prints one JSON line.  Besides the throughput it reports the roofline of
+the dominant kernel (the scheduler kernel, which runs every tile task: n^3
+algorithmic flops per launch, timed with HIP events on its stream), the
+oracle timed on the host cores on bounded samples (all cores and one
+thread), the parity of one result against the analytic inverse, and the
+other workloads as rows: n = 8192 pipelined vs unpipelined and the paper's
+plan variants, the batched form, the backward, the steps on their own.
 """
 from __future__ import annotations
 
@@ -20,6 +26,8 @@ import ctypes
 import hashlib
 import json
 import os
+import statistics
+import subprocess
 import sys
 import time
 
@@ -27,12 +35,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6       # MI355X dense FP64 matrix peak
+PEAK_FP32_TFLOPS = 157.3      # MI355X dense FP32 matrix peak
 # sources that determine the scheduler kernel and the plan it runs: committed
 # traffic counters are used only while these are unchanged
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1002_4057_amd", "csrc", f) for f in
                ("device.hip", "device.hpp", "tile_tasks.hpp", "mfma_tile.hpp", "sched_loop.hpp",
                 "plan.hpp", "plan.cpp", "api.cpp")]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sched_kernel_n8192.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sched_kernel_n16384.json")
 
 
 def log(*a):
@@ -46,39 +55,68 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_per_launch():
+def traffic_per_launch(n: int):
     """HBM bytes per scheduler launch from committed rocprofv3 counters, or
-    None when they are missing or were taken on a different kernel source."""
+    None when they are missing, for another order, or were taken on a
+    different kernel source."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except Exception:
         return None
-    if d.get("kernel_sha256_16") != kernel_hash():
+    if d.get("kernel_sha256_16") != kernel_hash() or d.get("n") != n:
         return None
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(n_sample: int, kappa: float):
+def cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n_all: int, n_one: int, kappa: float):
+    """The oracle (plain unblocked loops, binary64) on bounded samples of the
+    headline construction: one inversion at n_all on every host core, one at
+    n_one on one thread (the results do not depend on the thread count)."""
     import numpy as np
     import oracle
     from paper_1002_4057_amd import inputs
-    import torch
-    a = inputs.spectrum(n_sample, kappa, seed=0, device="cuda").cpu().numpy()
-    torch.cuda.synchronize()
     oracle.build()
-    t0 = time.perf_counter()
-    oracle.spd_inverse_lower(np.asfortranarray(a))
-    dt = time.perf_counter() - t0
-    return {"value": round(n_sample ** 3 / dt / 1e9, 3), "unit": "Gflop/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"one full three-stage oracle inversion at n={n_sample} "
-                      f"(same construction, kappa={kappa:g}), {dt:.1f} s wall"}
+    out = {}
+    nt0 = oracle.num_threads()
+    for label, n_s, threads in (("all", n_all, nt0), ("one", n_one, 1)):
+        if n_s <= 0:
+            continue
+        a = np.asfortranarray(inputs.spectrum(n_s, kappa, seed=0).numpy())
+        oracle.set_num_threads(threads)
+        t0 = time.perf_counter()
+        oracle.spd_inverse_lower(a)
+        dt = time.perf_counter() - t0
+        out[label] = {"value": round(n_s ** 3 / dt / 1e9, 3), "cores": oracle.num_threads(),
+                      "n": n_s, "s": round(dt, 1)}
+    oracle.set_num_threads(nt0)
+    allc, one = out.get("all"), out.get("one")
+    head = allc or one
+    res = {"value": head["value"], "unit": "Gflop/s", "cores": head["cores"], "kind": "oracle",
+           "sample": (f"one full three-stage oracle inversion at n={head['n']} of the headline "
+                      f"construction (kappa={kappa:g}) on {head['cores']} threads, "
+                      f"{head['s']} s wall"),
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+    if one is not None and allc is not None:
+        res["one_thread"] = {"value": one["value"], "unit": "Gflop/s", "cores": 1,
+                             "sample": f"one inversion at n={one['n']}, {one['s']} s wall"}
+    return res
 
 
-def time_events(fn, reps, prep=None):
-    """Average milliseconds of fn() over reps, HIP events on torch's current
-    stream (the stream the library launches on); prep() runs untimed before
-    each call."""
+def time_events(fn, reps, prep=None, agg="mean"):
+    """Milliseconds of fn() over reps (mean or median), HIP events on torch's
+    current stream (the stream the library launches on); prep() runs untimed
+    before each call."""
     import torch
     times = []
     for _ in range(reps):
@@ -90,7 +128,69 @@ def time_events(fn, reps, prep=None):
         e1.record()
         e1.synchronize()
         times.append(e0.elapsed_time(e1))
-    return sum(times) / len(times)
+    return statistics.median(times) if agg == "median" else sum(times) / len(times)
+
+
+def sym_from_lower_cm(buf_cm):
+    """Full symmetric matrix from a column-major buffer whose lower triangle
+    holds the result (buf_cm is the row-major storage, i.e. the transpose)."""
+    import torch
+    low = torch.tril(buf_cm.t())
+    return low + torch.tril(low, -1).t()
+
+
+def resid_rel(a, x):
+    import torch
+    n = a.shape[0]
+    r = torch.eye(n, dtype=torch.float64, device=a.device) - a @ x
+    return (torch.linalg.norm(r) / torch.linalg.norm(a)).item()
+
+
+def precision_cells(n, q, kappas, modes, reps, work=None):
+    """FP64 against the mixed-refined forms at each kappa: time to solution
+    (median of reps, after one warm call), ||I - A X||_F / ||A||_F of the
+    result and its relative error against the analytic inverse (both
+    untimed, with library GEMMs)."""
+    import torch
+    import paper_1002_4057_amd as spd
+    from paper_1002_4057_amd import inputs
+    dev = q.device
+    if work is None:
+        need = max(spd.workspace_bytes(n, mode=m) for m in modes)
+        work = torch.empty(need, dtype=torch.uint8, device=dev)
+    cells = {}
+    for kappa in kappas:
+        a, lam = inputs.spectrum_from_q(q, kappa)
+        a_cm = a.t().contiguous()
+        buf = torch.empty_like(a_cm)
+        row = {}
+        for mode in modes:
+            log(f"[bench] precision n={n} kappa={kappa:g} {mode}")
+            buf.copy_(a_cm)
+            rep = spd.spd_inverse_(buf.t(), mode=mode, work=work, report=True)   # warm
+            x = sym_from_lower_cm(buf)
+            ref = inputs.analytic_inverse(q, lam)
+            err = (torch.linalg.norm(x - ref) / torch.linalg.norm(ref)).item()
+            del ref
+            res = resid_rel(a, x)
+            del x
+            ms = time_events(lambda: spd.spd_inverse_(buf.t(), mode=mode, work=work), reps,
+                             prep=lambda: buf.copy_(a_cm), agg="median")
+            cell = {"ms": round(ms, 2), "gflops": round(float(n) ** 3 / (ms / 1e3) / 1e9, 1),
+                    "resid_fro_rel": res, "err_vs_analytic": err}
+            if mode != "fp64":
+                cell.update({"refine_iters": rep["refine_iters"], "fell_back": rep["fell_back"],
+                             "converged": rep["converged"], "predicted_stop": rep["predicted"],
+                             "resid0_fro_rel": rep["resid0_fro_rel"]})
+            row[mode] = cell
+        if "fp64" in row:
+            for mode in modes:
+                if mode != "fp64":
+                    row[mode]["speedup_over_fp64"] = round(row["fp64"]["ms"] / row[mode]["ms"], 3)
+        cells[f"{kappa:g}"] = row
+        del a, a_cm, buf
+        torch.cuda.empty_cache()
+    return cells
 
 
 def batched_row(reps: int):
@@ -129,42 +229,59 @@ def batched_row(reps: int):
             "reps": reps}
 
 
-def ablation_row(spd, bufs, work, n: int, reps: int):
-    """The paper's plan variants on the same n (Section 3 and its Table 1):
-    renamed against in place, UDU against UUU loop order, the TRTRI(j)
-    placement of step 2, and one device task per task of the paper
-    (chain = 1), each with the planner's critical path in tasks.  Same
-    synthetic input as the headline line; each variant is warmed once."""
+def c1_row(spd, n: int, reps: int, ablation: bool):
+    """n = 8192, kappa = 1e4 (A = Q diag(lambda) Q^T): pipelined against
+    unpipelined steps (the paper's pipelining comparison), and the paper's
+    plan variants (Section 3 and its Table 1): renamed against in place, UDU
+    against UUU loop order, the TRTRI(j) placement of step 2, and one device
+    task per task of the paper (chain = 1), each with the planner's critical
+    path in tasks."""
     import torch
-    variants = [("renamed UDU (default)", {}), ("in place UDU", {"renamed": 0}),
-                ("renamed UUU", {"loop_order": 1}), ("in place UUU", {"renamed": 0, "loop_order": 1}),
-                ("renamed UDU, TRTRI(j) first", {"trtri_first": 1}),
-                ("renamed UDU, one task per paper task", {"chain": 1})]
-    out = {"workload": f"single SPD inverse, n={n}, FP64 (same input as the headline line)",
-           "reps": reps, "variants": {}}
+    from paper_1002_4057_amd import inputs
+    dev = torch.device("cuda:0")
+    a, q, lam = inputs.spectrum(n, 1e4, seed=0, device=dev, return_factors=True)
+    a_cm = a.t().contiguous()
+    buf = a_cm.clone()
+    work = torch.empty(spd.workspace_bytes(n), dtype=torch.uint8, device=dev)
+    spd.spd_inverse_(buf.t(), work=work, report=True)
+    ref = inputs.analytic_inverse(q, lam)
+    err = (torch.linalg.norm(sym_from_lower_cm(buf) - ref) / torch.linalg.norm(ref)).item()
+    del ref, q
     flops = float(n) ** 3
+    out = {"workload": f"single SPD inverse, n={n}, FP64, A=Q diag(lambda) Q^T, lambda "
+                       f"log-spaced over [1,1e4]", "reps": reps, "err_vs_analytic": err}
+    variants = [("renamed UDU (default)", {}), ("renamed UDU, barriers between steps",
+                                                {"pipelined": 0})]
+    if ablation:
+        variants += [("in place UDU", {"renamed": 0}), ("renamed UUU", {"loop_order": 1}),
+                     ("in place UUU", {"renamed": 0, "loop_order": 1}),
+                     ("renamed UDU, TRTRI(j) first", {"trtri_first": 1}),
+                     ("renamed UDU, one task per paper task", {"chain": 1})]
+    out["variants"] = {}
     for label, opts in variants:
+        log(f"[bench] n={n} variant: {label}")
         try:
-            b = bufs[0].t().clone()
-            rep = spd.spd_inverse_(b, work=work, report=True, **opts)   # plan + warm
-            torch.cuda.synchronize()
-            s0 = time.perf_counter()
-            for k in range(reps):
-                spd.spd_inverse_(bufs[k].t(), work=work, **opts)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - s0) / reps * 1e3
+            buf.copy_(a_cm)
+            rep = spd.spd_inverse_(buf.t(), work=work, report=True, **opts)   # plan + warm
+            ms = time_events(lambda: spd.spd_inverse_(buf.t(), work=work, **opts), reps,
+                             prep=lambda: buf.copy_(a_cm))
             out["variants"][label] = {"ms": round(ms, 3), "gflops": round(flops / ms / 1e6, 1),
                                       "critical_path_tasks": rep["critical_path"],
                                       "device_tasks": rep["tasks"]}
         except Exception as e:   # a variant that fails is reported, not fatal
             out["variants"][label] = {"error": str(e)}
-    return out
+    v = out["variants"]
+    if "gflops" in v.get("renamed UDU, barriers between steps", {}):
+        out["pipelining_gain"] = round(v["renamed UDU (default)"]["gflops"] /
+                                       v["renamed UDU, barriers between steps"]["gflops"], 3)
+    return out, a_cm, work
 
 
 def steps_row(spd, a_cm, work, n: int, reps: int):
-    """The steps of Algorithm 1 on their own, on the headline input: the
-    Cholesky factor (step 1, n^3/3 flops) and the inverse from that factor
-    (steps 2 and 3 after the factor prologue, 2n^3/3 flops)."""
+    """The steps of Algorithm 1 on their own, on the n = 8192 input: the
+    Cholesky factor (step 1, n^3/3 flops), the inverse from that factor
+    (steps 2 and 3 after the factor prologue, 2n^3/3 flops) and the solve
+    with 128 right-hand sides."""
     b = a_cm.clone()
     spd.cholesky_(b.t(), work=work, report=True)            # plan + warm
     lsrc = b.clone()                                         # L in the lower triangle
@@ -173,8 +290,6 @@ def steps_row(spd, a_cm, work, n: int, reps: int):
     spd.inverse_from_factor_(b.t(), work=work, report=True)  # plan + warm (b holds L)
     ms_inv = time_events(lambda: spd.inverse_from_factor_(b.t(), work=work), reps,
                          prep=lambda: b.copy_(lsrc))
-    # the solve A X = B (factor, then both substitutions) for 128 right-hand
-    # sides, n^3/3 + 2 n^2 nrhs flops
     import torch
     nrhs = 128
     bsrc = torch.randn(nrhs, n, dtype=torch.float64, device=a_cm.device)  # column-major n x nrhs
@@ -187,8 +302,8 @@ def steps_row(spd, a_cm, work, n: int, reps: int):
         b.copy_(a_cm)
         bb.copy_(bsrc)
     ms_solve = time_events(lambda: spd.solve_(b.t(), bb.t(), work=swork), reps, prep=prep_solve)
-    out = {"workload": f"n={n}, FP64, same input as the headline line; solve with {nrhs} "
-                       "right-hand sides", "reps": reps}
+    out = {"workload": f"n={n}, FP64, the n={n} input; solve with {nrhs} right-hand sides",
+           "reps": reps}
     for key, ms, fl in (("cholesky", ms_chol, n ** 3 / 3.0), ("inverse_from_factor", ms_inv,
                                                                 2.0 * n ** 3 / 3.0),
                         ("solve", ms_solve, n ** 3 / 3.0 + 2.0 * n * n * nrhs)):
@@ -219,60 +334,27 @@ def backward_row(reps: int):
             "reps": reps}
 
 
-def mixed_row(reps: int, n: int = 16384, kappa: float = 1e2):
-    """Precision workload: FP64 form vs mixed-refined form (FP32 tile DAG +
-    binary64 Newton-Schulz) at n = 16384, kappa = 1e2, time to solution of
-    each and ||I - A X||_F / ||A||_F of each result (measured untimed with a
-    library GEMM)."""
-    import torch
-    import paper_1002_4057_amd as spd
-    from paper_1002_4057_amd import inputs
-    dev = torch.device("cuda:0")
-    a, q, lam = inputs.spectrum(n, kappa, seed=0, device="cuda", return_factors=True)
-    del q, lam
-    a_cm = a.t().contiguous()
-    need = max(spd.workspace_bytes(n), spd.workspace_bytes(n, mode="mixed_fp32"))
-    work = torch.empty(need, dtype=torch.uint8, device=dev)
-    buf = a_cm.clone()
-    anorm = torch.linalg.norm(a).item()
-
-    def resid():
-        low = torch.tril(buf.t())
-        x = low + torch.tril(low, -1).t()
-        r = torch.eye(n, dtype=torch.float64, device=dev) - a @ x
-        return (torch.linalg.norm(r) / anorm).item()
-
-    out = {"workload": f"precision form, n={n}, A = Q diag(lambda) Q^T, lambda log-spaced over "
-                       f"[1,{kappa:g}]; FP64 vs mixed (FP32 tiles + binary64 refinement, "
-                       f"stop at ||I-AX||_F/||A||_F <= 1e-13)"}
-    reports = {}
-    for label, mode in (("fp64", "fp64"), ("mixed_fp32", "mixed_fp32")):
-        buf.copy_(a_cm)
-        reports[label] = spd.spd_inverse_(buf.t(), mode=mode, work=work, report=True)   # warm
-        ms = time_events(lambda: spd.spd_inverse_(buf.t(), mode=mode, work=work, report=True),
-                         reps, prep=lambda: buf.copy_(a_cm))
-        out[label] = {"ms": round(ms, 2), "gflops": round(float(n) ** 3 / (ms / 1e3) / 1e9, 1),
-                      "resid_fro_rel": resid()}
-    rep = reports["mixed_fp32"]
-    out["mixed_fp32"].update({"refine_iters": rep["refine_iters"], "fell_back": rep["fell_back"],
-                              "resid0_fro_rel": rep["resid0_fro_rel"]})
-    out["speedup_mixed_over_fp64"] = round(out["fp64"]["ms"] / out["mixed_fp32"]["ms"], 3)
-    out["reps"] = reps
-    return out
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--kappa", type=float, default=1e4)
-    ap.add_argument("--cpu-n", type=int, default=8192, help="oracle sample order (0 = skip)")
-    ap.add_argument("--no-unpipelined", action="store_true")
-    ap.add_argument("--rows", default="batched,backward,mixed,ablation,steps",
-                    help="extra measured rows: batched, backward, mixed, ablation, steps "
-                         "(comma list, '' = none)")
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--kappa", type=float, default=1e2)
+    ap.add_argument("--cpu-n", type=int, default=8192,
+                    help="oracle sample order on every host core (0 = skip)")
+    ap.add_argument("--cpu-n1", type=int, default=3072,
+                    help="oracle sample order on one thread (0 = skip)")
+    ap.add_argument("--rows", default="precision,large,c1,ablation,batched,backward,steps",
+                    help="extra measured rows (comma list, '' = none): precision (FP64 vs "
+                         "mixed at the headline order), large (n = --large-n), c1 (n = 8192 "
+                         "pipelined vs unpipelined), ablation (plan variants at n = 8192), "
+                         "batched, backward, steps")
+    ap.add_argument("--kappas", default="1e2,1e6,1e10", help="precision row condition numbers")
+    ap.add_argument("--modes", default="fp64,mixed_fp32,mixed_bf16", help="precision row modes")
+    ap.add_argument("--large-n", type=int, default=32768)
+    ap.add_argument("--large-kappas", default="1e2")
+    ap.add_argument("--large-modes", default="fp64,mixed_fp32")
     ap.add_argument("--input", choices=["spectrum", "wishart"], default="spectrum",
                     help="wishart (B B^T/n + I, no QR) is for profiler counter runs only")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -281,7 +363,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "this benchmark runs on one GPU only (the library inverts "
+                                   "on one device); run it with --gpus 1",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
@@ -293,9 +376,11 @@ def main():
     torch.cuda.set_device(dev)
     lib = _lib.load()
     n, K, W = args.n, args.steps, args.warmup
+    wanted = [r for r in args.rows.split(",") if r]
     log(f"[bench] building input n={n} kappa={args.kappa:g} ({args.input})")
     if args.input == "spectrum":
-        a, q, lam = inputs.spectrum(n, args.kappa, seed=0, device="cuda", return_factors=True)
+        q = inputs.orthogonal(n, 0, device=dev)
+        a, lam = inputs.spectrum_from_q(q, args.kappa)
     else:
         b0 = inputs.randn((n, n), 0).to(dev)
         a = b0 @ b0.t() / n + torch.eye(n, dtype=torch.float64, device=dev)
@@ -308,18 +393,19 @@ def main():
     torch.cuda.synchronize()
 
     log(f"[bench] warmup {W}")
-    for k in range(W):
+    rep = spd.spd_inverse_(bufs[K].t(), work=work, report=True) if W else None
+    for k in range(1, W):
         spd.spd_inverse_(bufs[K + k].t(), work=work)
     torch.cuda.synchronize()
-    # parity of one result (untimed) against the analytic inverse
-    rel = None
-    if q is not None:
-        x = bufs[K].t()                               # lower triangle holds A^{-1}
+    # parity of one result (untimed) against the analytic inverse, and its residual
+    parity = None
+    if q is not None and W:
+        x = sym_from_lower_cm(bufs[K])
         ref = inputs.analytic_inverse(q, lam)
-        low = torch.tril(x)
-        xs = low + torch.tril(low, -1).t()
-        rel = (torch.linalg.norm(xs - ref) / torch.linalg.norm(ref)).item()
-        del xs, low, ref
+        parity = {"rel_fro_vs_analytic": (torch.linalg.norm(x - ref) /
+                                          torch.linalg.norm(ref)).item(),
+                  "bar": 1e-12 * args.kappa, "resid_fro_rel": resid_rel(a, x)}
+        del x, ref
 
     log(f"[bench] timing {K} steps")
     lib.spdinv_kernel_timer(1)
@@ -337,26 +423,8 @@ def main():
     value = K * flops / elapsed / 1e9
     sched_avg_s = sched_ms / 1e3 / max(1, launches.value)
     achieved = flops / sched_avg_s / 1e12
-
-    pipe = None
-    if not args.no_unpipelined:
-        reps = max(2, min(K, 4))
-        res = {}
-        for label, piped in (("pipelined", 1), ("unpipelined", 0)):
-            spd.spd_inverse_(bufs[0].t().clone(), work=work, pipelined=piped)   # plan + warm
-            torch.cuda.synchronize()
-            s0 = time.perf_counter()
-            for k in range(reps):
-                spd.spd_inverse_(bufs[k].t(), work=work, pipelined=piped)
-            torch.cuda.synchronize()
-            res[label] = round(reps * flops / (time.perf_counter() - s0) / 1e9, 1)
-        pipe = {"pipelined_gflops": res["pipelined"], "unpipelined_gflops": res["unpipelined"],
-                "steps": reps}
-
-    ablation = None
-    if "ablation" in [r for r in args.rows.split(",") if r]:
-        log("[bench] ablation row")
-        ablation = ablation_row(spd, bufs, work, n, max(2, min(K, 3)))
+    del bufs
+    torch.cuda.empty_cache()
 
     if args.calibrate_copy > 0:
         # plain copy of known size, for scaling profiler byte counters
@@ -369,26 +437,49 @@ def main():
         del src, dst
 
     rows = {}
-    wanted = [r for r in args.rows.split(",") if r]
+    kappas = [float(k) for k in args.kappas.split(",") if k]
+    modes = [m for m in args.modes.split(",") if m]
+    if "precision" in wanted and q is not None:
+        del a, a_cm
+        rows["precision"] = {
+            "workload": f"precision form, n={n}, A = Q diag(lambda) Q^T, lambda log-spaced over "
+                        "[1,kappa]; FP64 against mixed (FP32 or BF16 tile DAG, binary64 "
+                        "Newton-Schulz refinement, stop at ||I-AX||_F/||A||_F <= 1e-13); "
+                        "median of 3 after one warm call",
+            "cells": precision_cells(n, q, kappas, modes, 3, work=None)}
+    del q, work
+    torch.cuda.empty_cache()
+    if "large" in wanted and args.large_n > 0:
+        nl = args.large_n
+        log(f"[bench] large row n={nl}: building input")
+        ql = inputs.orthogonal(nl, 0, device=dev)
+        lk = [float(k) for k in args.large_kappas.split(",") if k]
+        rows["large"] = {
+            "workload": f"precision form at n={nl}, same construction; median of 2 after one "
+                        "warm call",
+            "cells": precision_cells(nl, ql, lk, [m for m in args.large_modes.split(",") if m],
+                                     2)}
+        del ql
+        torch.cuda.empty_cache()
+    if "c1" in wanted or "ablation" in wanted or "steps" in wanted:
+        c1, a8_cm, work8 = c1_row(spd, 8192, max(2, min(K, 4)), "ablation" in wanted)
+        rows["c1"] = c1
+        if "steps" in wanted:
+            log("[bench] steps row")
+            rows["steps"] = steps_row(spd, a8_cm, work8, 8192, max(2, min(K, 5)))
+        del a8_cm, work8
+        torch.cuda.empty_cache()
     if "batched" in wanted:
         log("[bench] batched row")
         rows["batched"] = batched_row(max(2, min(K, 5)))
     if "backward" in wanted:
         log("[bench] backward row")
         rows["backward"] = backward_row(max(2, min(K, 5)))
-    if "mixed" in wanted:
-        log("[bench] mixed row")
-        rows["mixed"] = mixed_row(max(2, min(K, 3)))
-    if ablation is not None:
-        rows["ablation"] = ablation
-    if "steps" in wanted:
-        log("[bench] steps row")
-        rows["steps"] = steps_row(spd, a_cm, work, n, max(2, min(K, 5)))
 
     cpu = None
-    if args.cpu_n > 0:
-        log(f"[bench] oracle sample n={args.cpu_n}")
-        cpu = cpu_baseline(args.cpu_n, args.kappa)
+    if args.cpu_n > 0 or args.cpu_n1 > 0:
+        log(f"[bench] oracle samples n={args.cpu_n} (all cores), n={args.cpu_n1} (one thread)")
+        cpu = cpu_baseline(args.cpu_n, args.cpu_n1, args.kappa)
 
     line = {
         "metric": "SPD-inverse Gflop/s (n^3 flops), FP64 vs mixed-refined at equal ‖I-AX‖",
@@ -403,18 +494,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"single SPD inverse, n={n}, FP64, A=Q diag(lambda) Q^T, "
-                               f"lambda log-spaced over [1,{args.kappa:g}]",
-                   "n": n, "nb": 128, "kappa": args.kappa,
-                   "variant": "renamed, UDU, pipelined"},
+        "config": {"workload": f"precision workload, FP64 cell: single SPD inverse, n={n}, "
+                               f"A=Q diag(lambda) Q^T, lambda log-spaced over "
+                               f"[1,{args.kappa:g}]",
+                   "n": n, "nb": rep["nb"] if rep else None, "kappa": args.kappa,
+                   "variant": "renamed, UDU, pipelined",
+                   "workers": rep["workers"] if rep else None},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                     "traffic": traffic_per_launch(), "kernel": "sched_kernel",
-                     "kernel_ms": round(sched_avg_s * 1e3, 3)},
+                     "traffic": traffic_per_launch(n), "kernel": "sched_kernel",
+                     "kernel_ms": round(sched_avg_s * 1e3, 3), "launches": launches.value},
         "cpu_baseline": cpu,
-        "parity": ({"rel_fro_vs_analytic": rel, "bar": 1e-12 * args.kappa} if rel is not None
-                   else None),
-        "pipelining": pipe,
+        "parity": parity,
         "rows": rows,
     }
     print(json.dumps(line), flush=True)

@@ -106,6 +106,9 @@ typedef struct {
                       and POTRF(j+1), and in the solve each multiplication by
                       D_i or D_i^T with the last update before it; 1 = as
                       whole tasks.  Results do not depend on it.             */
+  int parts;       /* FP64 form, with the split on: row parts per split product
+                      (0 = library choice as above; 2 = halves; 4 = quarters).
+                      Results do not depend on it.                           */
 } spdinv_opts;
 
 typedef struct {
@@ -117,12 +120,20 @@ typedef struct {
   int critical_path;   /* critical path of the executed DAG, in tasks */
   int workers;         /* persistent workgroups launched */
   int refine_iters;    /* mixed modes: refinement steps taken                    */
-  int fell_back;       /* mixed modes: 1 when the low-precision start failed (the
-                          FP32 factorization broke down or ||I - A X0||_F >= 1)
-                          and the result comes from the FP64 path               */
-  double resid_fro_rel; /* mixed modes: ||I - A X||_F / ||A||_F of the last
-                           residual computed (before the last correction)      */
-  double resid0_fro_rel; /* mixed modes: the same for the starting inverse X0   */
+  int fell_back;       /* mixed modes: the result comes from the FP64 path because
+                          1: the low-precision start failed (the FP32
+                          factorization broke down or ||I - A X0||_F >= 1), or
+                          2: the library's default step limit ran out before
+                          the stop rule was met; 0 otherwise                  */
+  double resid_fro_rel; /* mixed modes: ||I - A X||_F / ||A||_F of the returned X
+                           as the stop rule saw it: measured, or (predicted = 1)
+                           the prediction ||R_k||_F^2 plus a binary64 rounding
+                           floor of 4 u ||A||_F ||X||_F, divided by ||A||_F   */
+  double resid0_fro_rel; /* mixed modes: the same, measured, for the start X0   */
+  double resid_last_rel; /* mixed modes: the last residual actually formed      */
+  int converged;       /* mixed modes: 1 when the stop rule was met           */
+  int predicted;       /* mixed modes: 1 when the loop stopped on the prediction
+                          (the residual of the returned X was not formed)     */
 } spdinv_report;
 
 /* Fills `opts` with the defaults. */
@@ -139,10 +150,15 @@ size_t spd_inverse_workspace_bytes(int n, spdinv_mode mode, const spdinv_opts* o
  * A <- A^{-1} for one SPD matrix (Algorithm 1 with the variants of Section 3).
  * mode SPDINV_FP64 runs every task in binary64.  mode SPDINV_MIXED_FP32
  * (renamed plan only) runs the same DAG with FP32 tiles to get X0, then
- * refines: R = I - A X in binary64, stop when ||R||_F / ||A||_F <= refine_tol,
- * else X <- X + X R (binary64, lower tiles, mirrored); it synchronizes the
- * stream once per step to test convergence.  It falls back to the FP64 path
- * when the FP32 factorization breaks down or ||R_0||_F >= 1.
+ * refines by Newton-Schulz: R = I - A X in binary64, stop when
+ * ||R||_F / ||A||_F <= refine_tol, else X <- X + X R (binary64, lower tiles,
+ * mirrored); since I - A (X + X R) = R^2, the loop also stops, without
+ * forming the next residual, once (||R||_F^2 + 4 u ||A||_F ||X||_F) / ||A||_F
+ * meets the rule (u = 2^-53).  It synchronizes the stream once per step.  It
+ * falls back to the FP64 path when the FP32 factorization breaks down, when
+ * ||R_0||_F >= 1, or when the default step limit runs out first (with an
+ * explicit max_refine or refine_tol it returns the refined X instead, with
+ * report->converged = 0).
  *   n        order (>= 0)
  *   A        device, column-major, lda >= max(1,n); lower triangle read and
  *            overwritten with the lower triangle of A^{-1}

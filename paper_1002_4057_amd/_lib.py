@@ -31,7 +31,8 @@ class Opts(ctypes.Structure):
                 ("loop_order", ctypes.c_int), ("trtri_first", ctypes.c_int),
                 ("workers", ctypes.c_int), ("fill_upper", ctypes.c_int), ("trace", ctypes.c_int),
                 ("max_refine", ctypes.c_int), ("refine_tol", ctypes.c_double),
-                ("chain", ctypes.c_int), ("per_cu", ctypes.c_int), ("no_split", ctypes.c_int)]
+                ("chain", ctypes.c_int), ("per_cu", ctypes.c_int), ("no_split", ctypes.c_int),
+                ("parts", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -39,7 +40,9 @@ class Report(ctypes.Structure):
                 ("tiles", ctypes.c_int), ("tasks", ctypes.c_longlong),
                 ("critical_path", ctypes.c_int), ("workers", ctypes.c_int),
                 ("refine_iters", ctypes.c_int), ("fell_back", ctypes.c_int),
-                ("resid_fro_rel", ctypes.c_double), ("resid0_fro_rel", ctypes.c_double)]
+                ("resid_fro_rel", ctypes.c_double), ("resid0_fro_rel", ctypes.c_double),
+                ("resid_last_rel", ctypes.c_double), ("converged", ctypes.c_int),
+                ("predicted", ctypes.c_int)]
 
 
 class PlanStats(ctypes.Structure):

@@ -93,6 +93,7 @@ spdinv_opts defaults() {
   o.chain = 0;
   o.per_cu = 0;
   o.no_split = 0;
+  o.parts = 0;
   return o;
 }
 
@@ -134,6 +135,7 @@ int check_opts(const spdinv_opts& o) {
   if (o.chain < 0 || o.chain > MAX_CHAIN) return 1;
   if (o.per_cu < 0 || o.per_cu > 2) return 1;
   if (o.no_split < 0 || o.no_split > 1) return 1;
+  if (o.parts != 0 && o.parts != 2 && o.parts != 4) return 1;
   return 0;
 }
 
@@ -154,6 +156,7 @@ constexpr int kWideTiles = 96;
 // workgroups per CU, the inverse was 3 % slower with quarters).
 int split_for(const spdinv_opts& o, int t, int workers) {
   if (o.no_split || workers <= 1) return 0;
+  if (o.parts) return o.parts;
   return t < kWideTiles ? 4 : 2;
 }
 
@@ -578,7 +581,11 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
   DevPlan* dp = get_plan(device, t, o, grid, 1, &err);
   if (!dp) return SPDINV_ERR_HIP;
   const int ntask = (int)dp->host.tasks.size();
-  const int max_refine = o.max_refine > 0 ? o.max_refine : (bf16 ? 8 : 6);
+  int max_refine = o.max_refine > 0 ? o.max_refine : (bf16 ? 8 : 6);
+  if (o.max_refine <= 0) {  // test hook: a smaller library default, set from the host
+    const char* e = std::getenv("SPDINV_DEFAULT_MAX_REFINE");
+    if (e && *e && std::atoi(e) >= 0) max_refine = std::atoi(e);
+  }
   const double tol = o.refine_tol > 0.0 ? o.refine_tol : 1e-13;
 
   char* w = (char*)work;
@@ -610,8 +617,9 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
   if (c[CTRL_ABORT]) return SPDINV_ERR_TIMEOUT;
 
   bool fallback = c[CTRL_FAILED] != 0;
-  int iters = 0;
-  double r0 = -1.0, rl = -1.0;
+  int fell_back = fallback ? 1 : 0;
+  int iters = 0, converged = 0, predicted = 0;
+  double r0 = -1.0, rl = -1.0, rpred = -1.0;
   double* X = nullptr;
   if (!fallback) {
     double* Asq = (double*)(w + M.asq);
@@ -619,34 +627,65 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
     double* X2 = (double*)(w + M.x2);
     double* R = (double*)(w + M.r);
     double* partial = (double*)(w + M.partial);
-    double* dnorm = partial + (size_t)t * t;  // [0] ||A||^2, [1] ||R||^2
+    double* dnorm = partial + (size_t)t * t;  // [0] ||A||^2, [1] ||R||^2, [2] ||X0||^2
     const int sq_tiles = t * t;
     if (launch_pack(A, lda, n, t, PACK_SYM_LOWER, Asq, stream) != hipSuccess) return SPDINV_ERR_HIP;
     if (launch_sumsq(Asq, sq_tiles, partial, dnorm, stream) != hipSuccess) return SPDINV_ERR_HIP;
     if (launch_x0_to_sym64(pool, t, n, X, stream) != hipSuccess) return SPDINV_ERR_HIP;
+    if (launch_sumsq(X, sq_tiles, partial, dnorm + 2, stream) != hipSuccess) return SPDINV_ERR_HIP;
+    double anorm = 0.0, floor_abs = 0.0;
     for (int k = 0;; ++k) {
       // R^T = I - X A (A and X symmetric); ||R^T||_F = ||R||_F
       if (launch_gemm_nt(X, Asq, R, t, 0, 1, stream, nullptr, n) != hipSuccess) return SPDINV_ERR_HIP;
       if (launch_sumsq(R, sq_tiles, partial, dnorm + 1, stream) != hipSuccess) return SPDINV_ERR_HIP;
-      double h[2];
+      double h[3];
       if (hipMemcpyAsync(h, dnorm, sizeof(h), hipMemcpyDeviceToHost, stream) != hipSuccess)
         return SPDINV_ERR_HIP;
       if (hipStreamSynchronize(stream) != hipSuccess) return SPDINV_ERR_HIP;
-      const double rnorm = std::sqrt(h[1]), rel = rnorm / std::sqrt(h[0]);
+      const double rnorm = std::sqrt(h[1]);
       if (k == 0) {
-        r0 = rel;
+        anorm = std::sqrt(h[0]);
+        // binary64 rounding floor of a residual, u ||A||_F ||X||_F up to a
+        // small factor (the typical size of the rounding of I - A X and of
+        // the stored X + X R)
+        floor_abs = 4.0 * 0x1p-53 * anorm * std::sqrt(h[2]);
+        r0 = rnorm / anorm;
         if (!(rnorm < 1.0)) {  // Newton-Schulz needs ||R_0|| < 1 (NaN included)
           fallback = true;
+          fell_back = 1;
           break;
         }
       }
+      const double rel = rnorm / anorm;
       rl = rel;
-      if (rel <= tol || k >= max_refine) break;
+      if (rel <= tol) {  // the measured residual of X meets the stop rule
+        converged = 1;
+        rpred = rel;
+        break;
+      }
+      if (k >= max_refine) break;
       // X' = X + X R on the lower tiles, X R = sum_k X(i, k) (R^T)(j, k)^T; then mirror
       if (launch_gemm_nt(X, R, X2, t, 1, 0, stream, X, 0) != hipSuccess) return SPDINV_ERR_HIP;
       if (launch_mirror_lower(X2, t, stream) != hipSuccess) return SPDINV_ERR_HIP;
       std::swap(X, X2);
       ++iters;
+      // I - A X' = R^2 exactly, so ||I - A X'||_F <= ||R||_F^2 up to the
+      // rounding floor: when that prediction meets the stop rule, the
+      // residual of X' is not formed
+      const double pred = (rnorm * rnorm + floor_abs) / anorm;
+      if (pred <= tol) {
+        converged = 1;
+        predicted = 1;
+        rpred = pred;
+        break;
+      }
+    }
+    // the library's own step limit ran out before the stop rule was met:
+    // the FP64 path gives the result (a caller-chosen limit or tolerance
+    // keeps the refined X and reports converged = 0)
+    if (!fallback && !converged && o.max_refine <= 0 && !(o.refine_tol > 0.0)) {
+      fallback = true;
+      fell_back = 2;
     }
   }
   if (fallback) {
@@ -654,10 +693,13 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
     o64.trace = 0;
     const int rc = run_fp64(n, A, lda, work, work_bytes, stream, o64, d_info, report);
     if (report) {
-      report->fell_back = 1;
+      report->fell_back = fell_back;
       report->resid0_fro_rel = r0;
       report->resid_fro_rel = -1.0;
-      report->refine_iters = 0;
+      report->resid_last_rel = rl;
+      report->refine_iters = iters;
+      report->converged = 0;
+      report->predicted = 0;
     }
     return rc;
   }
@@ -675,8 +717,11 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
     report->workers = grid;
     report->refine_iters = iters;
     report->fell_back = 0;
-    report->resid_fro_rel = rl;
+    report->resid_fro_rel = rpred >= 0.0 ? rpred : rl;
     report->resid0_fro_rel = r0;
+    report->resid_last_rel = rl;
+    report->converged = converged;
+    report->predicted = predicted;
   }
   return 0;
 }

@@ -99,118 +99,161 @@ struct Builder {
 
   int Dt(int j) const { return 3 * T + t + j; }
 
-  // Device operands.  The hazard names (reads/writes) are always the paper's
-  // tiles; the device may read a different tile that holds the same values
-  // (a renaming copy, or D_j / D_j^T for the inverted diagonal tile), which
-  // is safe when that tile is written by the same task that is the last
-  // writer of the paper's tile before the reader.  In the renamed plan every
-  // product reads op(A) = A and op(B) = B^T contiguously; the in-place plan
-  // uses the paper's tiles with transposes and triangular masks.
-  void step1() {
-    cur_step = 1;
-    const int cpt = o.renamed ? F_COPYT : 0;
-    for (int j = 0; j < t; ++j) {
-      for (int k = 0; k < j; ++k)  // A_jj -= A_jk A_jk^T
-        emit(K_SYRK1, j, j, k, {A(j, k), A(j, j)}, {A(j, j)}, A(j, j), A(j, k), A(j, k), -1, -1,
+  // One tile operation of the inversion, (kind, i, j, k) in the paper's
+  // naming, emitted with its hazard names and its device operands.  The
+  // hazard names (reads/writes) are always the paper's tiles; the device may
+  // read a different tile that holds the same values (a renaming copy, or
+  // D_j / D_j^T for the inverted diagonal tile), which is safe when that tile
+  // is written by the same task that is the last writer of the paper's tile
+  // before the reader.  In the renamed plan every product reads op(A) = A and
+  // op(B) = B^T contiguously (the copies are stored transposed); the in-place
+  // plan uses the paper's tiles with transposes and triangular masks.
+  void op(int kind, int i, int j, int k) {
+    const bool rn = o.renamed != 0;
+    const int cpt = rn ? F_COPYT : 0;
+    switch (kind) {
+      // step 1, the Cholesky factor
+      case K_SYRK1:   // A_jj -= A_jk A_jk^T
+        emit(kind, j, j, k, {A(j, k), A(j, j)}, {A(j, j)}, A(j, j), A(j, k), A(j, k), -1, -1,
              F_TB | F_LOWER | F_NEG | F_ACC);
-      if (o.renamed)
-        emit(K_POTRF, j, j, 0, {A(j, j)}, {A(j, j), B(j, j)}, A(j, j), -1, -1, B(j, j), D(j));
-      else
-        emit(K_POTRF, j, j, 0, {A(j, j)}, {A(j, j)}, A(j, j), -1, -1, -1, D(j));
-      for (int i = j + 1; i < t; ++i)
-        for (int k = 0; k < j; ++k)  // A_ij -= A_ik A_jk^T
-          emit(K_GEMM1, i, j, k, {A(i, k), A(j, k), A(i, j)}, {A(i, j)}, A(i, j), A(i, k), A(j, k),
-               -1, -1, F_TB | F_NEG | F_ACC);
-      for (int i = j + 1; i < t; ++i) {  // A_ij <- A_ij L_jj^{-T} = A_ij D_j^T
-        if (o.renamed)
-          emit(K_TRSM1, i, j, 0, {A(j, j), A(i, j)}, {A(i, j), B(i, j)}, A(i, j), A(i, j), D(j),
-               B(i, j), -1, F_TB | cpt);
+        break;
+      case K_POTRF:   // A_jj <- chol(A_jj), D_j <- its inverse (B_jj <- the factor)
+        if (rn) emit(kind, j, j, 0, {A(j, j)}, {A(j, j), B(j, j)}, A(j, j), -1, -1, B(j, j), D(j));
+        else emit(kind, j, j, 0, {A(j, j)}, {A(j, j)}, A(j, j), -1, -1, -1, D(j));
+        break;
+      case K_GEMM1:   // A_ij -= A_ik A_jk^T
+        emit(kind, i, j, k, {A(i, k), A(j, k), A(i, j)}, {A(i, j)}, A(i, j), A(i, k), A(j, k), -1,
+             -1, F_TB | F_NEG | F_ACC);
+        break;
+      case K_TRSM1:   // A_ij <- A_ij L_jj^{-T} = A_ij D_j^T (B_ij <- the result)
+        emit(kind, i, j, 0, {A(j, j), A(i, j)}, rn ? std::initializer_list<int>{A(i, j), B(i, j)}
+                                                   : std::initializer_list<int>{A(i, j)},
+             A(i, j), A(i, j), D(j), rn ? B(i, j) : -1, -1, F_TB | cpt);
+        break;
+      // step 2, the inverse X = L^{-1}
+      case K_TRTRI:   // A_jj <- D_j (and C_jj <- D_j^T)
+        if (rn) emit(kind, j, j, 0, {A(j, j)}, {A(j, j), C(j, j)}, A(j, j), D(j), Dt(j), C(j, j), -1);
+        else emit(kind, j, j, 0, {A(j, j)}, {A(j, j)}, A(j, j), D(j), -1, -1, -1);
+        break;
+      case K_TRMM2L:  // A_ij <- X_ii L_ij
+        if (rn)
+          emit(kind, i, j, 0, {A(i, i), A(i, j)}, {A(i, j)}, A(i, j), A(i, i), B(i, j), -1, -1, F_TB);
         else
-          emit(K_TRSM1, i, j, 0, {A(j, j), A(i, j)}, {A(i, j)}, A(i, j), A(i, j), D(j), -1, -1,
-               F_TB);
+          emit(kind, i, j, 0, {A(i, i), A(i, j)}, {A(i, j)}, A(i, j), A(i, i), A(i, j), -1, -1, F_MA);
+        break;
+      case K_GEMM2:   // A_ij += X_ik L_kj
+        if (rn)
+          emit(kind, i, j, k, {A(i, k), B(k, j), A(i, j)}, {A(i, j)}, A(i, j), A(i, k), B(k, j), -1,
+               -1, F_TB | F_ACC);
+        else
+          emit(kind, i, j, k, {A(i, k), A(k, j), A(i, j)}, {A(i, j)}, A(i, j), A(i, k), A(k, j), -1,
+               -1, F_ACC);
+        break;
+      case K_TRSM2R: {  // A_ij <- -A_ij L_jj^{-1} = -A_ij D_j (C_ij <- the result)
+        // by L_jj (a solve) in the LAPACK order, by X_jj after TRTRI(j) otherwise
+        const int djj = (o.trtri_first || !rn) ? A(j, j) : B(j, j);
+        emit(kind, i, j, 0, {djj, A(i, j)}, rn ? std::initializer_list<int>{A(i, j), C(i, j)}
+                                               : std::initializer_list<int>{A(i, j)},
+             A(i, j), A(i, j), Dt(j), rn ? C(i, j) : -1, -1, F_TB | F_NEG | cpt);
+        break;
       }
+      // step 3, the product X^T X
+      case K_TRMM3:   // A_ij <- X_ii^T A_ij
+        if (rn)
+          emit(kind, i, j, 0, {C(i, i), A(i, j)}, {A(i, j)}, A(i, j), C(i, i), C(i, j), -1, -1, F_TB);
+        else
+          emit(kind, i, j, 0, {A(i, i), A(i, j)}, {A(i, j)}, A(i, j), A(i, i), A(i, j), -1, -1,
+               F_TA | F_MA);
+        break;
+      case K_LAUUM:   // A_ii <- A_ii^T A_ii (lower)
+        if (rn)
+          emit(kind, i, i, 0, {A(i, i)}, {A(i, i)}, A(i, i), C(i, i), C(i, i), -1, -1,
+               F_TB | F_LOWER);
+        else
+          emit(kind, i, i, 0, {A(i, i)}, {A(i, i)}, A(i, i), A(i, i), A(i, i), -1, -1,
+               F_TA | F_MA | F_MB | F_LOWER);
+        break;
+      case K_GEMM3:   // A_ij += X_ki^T X_kj
+        if (rn)
+          emit(kind, i, j, k, {C(k, i), C(k, j), A(i, j)}, {A(i, j)}, A(i, j), C(k, i), C(k, j), -1,
+               -1, F_TB | F_ACC);
+        else
+          emit(kind, i, j, k, {A(k, i), A(k, j), A(i, j)}, {A(i, j)}, A(i, j), A(k, i), A(k, j), -1,
+               -1, F_TA | F_ACC);
+        break;
+      case K_SYRK3:   // A_ii += X_ki^T X_ki (lower)
+        if (rn)
+          emit(kind, i, i, k, {C(k, i), A(i, i)}, {A(i, i)}, A(i, i), C(k, i), C(k, i), -1, -1,
+               F_TB | F_LOWER | F_ACC);
+        else
+          emit(kind, i, i, k, {A(k, i), A(i, i)}, {A(i, i)}, A(i, i), A(k, i), A(k, i), -1, -1,
+               F_TA | F_LOWER | F_ACC);
+        break;
+      default:
+        break;
     }
   }
 
-  void trtri(int j) {  // A_jj <- D_j (and C_jj <- D_j^T)
-    if (o.renamed)
-      emit(K_TRTRI, j, j, 0, {A(j, j)}, {A(j, j), C(j, j)}, A(j, j), D(j), Dt(j), C(j, j), -1);
-    else
-      emit(K_TRTRI, j, j, 0, {A(j, j)}, {A(j, j)}, A(j, j), D(j), -1, -1, -1);
+  // The three steps as recurrences over output tiles (Algorithm 1; the
+  // order of the updates of each tile is the paper's, and the tiles are
+  // visited so that every operand a tile's recurrence reads is final
+  // before the recurrence that reads it is emitted, except the tiles that
+  // the paper's own order also reads before rewriting them -- which the
+  // hazard analysis turns into anti-dependences).  Each tile's work is
+  // emitted as one run: an optional opening operation, its update chain,
+  // an optional closing operation.  The hazard DAG is that of the paper's
+  // stream: per tile the accesses come in the same order.
+
+  // Step 1: tile column j of L is final once column j's tiles have taken
+  // the updates from every earlier column: the diagonal tile j its SYRKs
+  // over k < j, then POTRF; each tile (i, j) below it its GEMMs over k < j,
+  // then the solve with the factored diagonal tile.  Columns left to right.
+  void step1() {
+    cur_step = 1;
+    for (int j = 0; j < t; ++j)
+      for (int i = j; i < t; ++i) {
+        const bool diag = i == j;
+        for (int k = 0; k < j; ++k) op(diag ? K_SYRK1 : K_GEMM1, i, j, k);
+        op(diag ? K_POTRF : K_TRSM1, i, j, 0);
+      }
   }
 
+  // Step 2: X_ij = -(X_ii L_ij + sum_{j<k<i} X_ik L_kj) L_jj^{-1} for i > j,
+  // X_jj = L_jj^{-1}.  Columns right to left, rows bottom up, so that every
+  // X_ik (k > j) a tile of column j reads is final; a tile's recurrence
+  // opens with the product by X_ii, accumulates the chain over k (downward
+  // in the UDU order, upward in UUU) and closes with the multiplication by
+  // L_jj^{-1}.  The diagonal tile of the column is inverted after its
+  // column (LAPACK order, reading L_jj) or before it (trtri_first, reading
+  // X_jj).
   void step2() {
     cur_step = 2;
     const bool down = (o.loop_order == 0);  // UDU: step-2 chain runs downward
     for (int j = t - 1; j >= 0; --j) {
-      if (o.trtri_first) trtri(j);
+      if (o.trtri_first) op(K_TRTRI, j, j, 0);
       for (int i = t - 1; i > j; --i) {
-        // A_ij <- X_ii L_ij
-        if (o.renamed)
-          emit(K_TRMM2L, i, j, 0, {A(i, i), A(i, j)}, {A(i, j)}, A(i, j), A(i, i), B(i, j), -1, -1,
-               F_TB);
-        else
-          emit(K_TRMM2L, i, j, 0, {A(i, i), A(i, j)}, {A(i, j)}, A(i, j), A(i, i), A(i, j), -1, -1,
-               F_MA);
-        for (int s = 0; s < i - j - 1; ++s) {  // A_ij += X_ik L_kj
-          const int k = down ? (i - 1 - s) : (j + 1 + s);
-          if (o.renamed)
-            emit(K_GEMM2, i, j, k, {A(i, k), B(k, j), A(i, j)}, {A(i, j)}, A(i, j), A(i, k), B(k, j),
-                 -1, -1, F_TB | F_ACC);
-          else
-            emit(K_GEMM2, i, j, k, {A(i, k), A(k, j), A(i, j)}, {A(i, j)}, A(i, j), A(i, k), A(k, j),
-                 -1, -1, F_ACC);
-        }
-        // A_ij <- -A_ij L_jj^{-1} = -A_ij D_j: by L_jj (solve) in the LAPACK
-        // order, by X_jj after TRTRI(j) otherwise
-        const int djj = (o.trtri_first || !o.renamed) ? A(j, j) : B(j, j);
-        if (o.renamed)
-          emit(K_TRSM2R, i, j, 0, {djj, A(i, j)}, {A(i, j), C(i, j)}, A(i, j), A(i, j), Dt(j),
-               C(i, j), -1, F_TB | F_NEG | F_COPYT);
-        else
-          emit(K_TRSM2R, i, j, 0, {djj, A(i, j)}, {A(i, j)}, A(i, j), A(i, j), Dt(j), -1, -1,
-               F_TB | F_NEG);
+        op(K_TRMM2L, i, j, 0);
+        for (int s = 0; s < i - j - 1; ++s) op(K_GEMM2, i, j, down ? i - 1 - s : j + 1 + s);
+        op(K_TRSM2R, i, j, 0);
       }
-      if (!o.trtri_first) trtri(j);
+      if (!o.trtri_first) op(K_TRTRI, j, j, 0);
     }
   }
 
+  // Step 3: (X^T X)_ij = sum_{k >= i} X_ki^T X_kj for i >= j.  Rows top down;
+  // in row i the tiles left of the diagonal, then the diagonal tile: each
+  // opens with its k = i term (the product by X_ii^T, or LAUUM on the
+  // diagonal) and accumulates the terms k > i upward.  (In place, X_ii is
+  // still read by the row's first products when LAUUM overwrites it, which
+  // is why the diagonal tile comes last in its row.)
   void step3() {
     cur_step = 3;
-    for (int i = 0; i < t; ++i) {
-      for (int j = 0; j < i; ++j) {  // A_ij <- X_ii^T A_ij
-        if (o.renamed)
-          emit(K_TRMM3, i, j, 0, {C(i, i), A(i, j)}, {A(i, j)}, A(i, j), C(i, i), C(i, j), -1, -1,
-               F_TB);
-        else
-          emit(K_TRMM3, i, j, 0, {A(i, i), A(i, j)}, {A(i, j)}, A(i, j), A(i, i), A(i, j), -1, -1,
-               F_TA | F_MA);
+    for (int i = 0; i < t; ++i)
+      for (int j = 0; j <= i; ++j) {
+        const bool diag = i == j;
+        op(diag ? K_LAUUM : K_TRMM3, i, j, 0);
+        for (int k = i + 1; k < t; ++k) op(diag ? K_SYRK3 : K_GEMM3, i, j, k);
       }
-      // A_ii <- A_ii^T A_ii (lower)
-      if (o.renamed)
-        emit(K_LAUUM, i, i, 0, {A(i, i)}, {A(i, i)}, A(i, i), C(i, i), C(i, i), -1, -1,
-             F_TB | F_LOWER);
-      else
-        emit(K_LAUUM, i, i, 0, {A(i, i)}, {A(i, i)}, A(i, i), A(i, i), A(i, i), -1, -1,
-             F_TA | F_MA | F_MB | F_LOWER);
-      for (int j = 0; j < i; ++j)
-        for (int k = i + 1; k < t; ++k) {  // A_ij += X_ki^T X_kj
-          if (o.renamed)
-            emit(K_GEMM3, i, j, k, {C(k, i), C(k, j), A(i, j)}, {A(i, j)}, A(i, j), C(k, i), C(k, j),
-                 -1, -1, F_TB | F_ACC);
-          else
-            emit(K_GEMM3, i, j, k, {A(k, i), A(k, j), A(i, j)}, {A(i, j)}, A(i, j), A(k, i), A(k, j),
-                 -1, -1, F_TA | F_ACC);
-        }
-      for (int k = i + 1; k < t; ++k) {  // A_ii += X_ki^T X_ki (lower)
-        if (o.renamed)
-          emit(K_SYRK3, i, i, k, {C(k, i), A(i, i)}, {A(i, i)}, A(i, i), C(k, i), C(k, i), -1, -1,
-               F_TB | F_LOWER | F_ACC);
-        else
-          emit(K_SYRK3, i, i, k, {A(k, i), A(i, i)}, {A(i, i)}, A(i, i), A(k, i), A(k, i), -1, -1,
-               F_TA | F_LOWER | F_ACC);
-      }
-    }
   }
 
   // The solve A X = R with A = L L^T, over the s tile columns of R: forward

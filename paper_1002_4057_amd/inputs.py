@@ -65,13 +65,20 @@ def orthogonal(n: int, seed: int, device: str = "cpu") -> torch.Tensor:
     return q * s.unsqueeze(0)
 
 
+def spectrum_from_q(q: torch.Tensor, kappa: float):
+    """(A, lambda): A = Q diag(lambda) Q^T, lambda log-spaced over [1, kappa],
+    for a given orthogonal Q (so that several condition numbers share one QR)."""
+    lam = log_spectrum(q.shape[0], kappa).to(q.device)
+    a = (q * lam.unsqueeze(0)) @ q.T
+    a = 0.5 * (a + a.T)
+    return a, lam
+
+
 def spectrum(n: int, kappa: float, seed: int = 0, device: str = "cpu",
              return_factors: bool = False):
     """A = Q diag(lambda) Q^T with log-spaced lambda over [1, kappa]."""
     q = orthogonal(n, seed, device)
-    lam = log_spectrum(n, kappa).to(q.device)
-    a = (q * lam.unsqueeze(0)) @ q.T
-    a = 0.5 * (a + a.T)
+    a, lam = spectrum_from_q(q, kappa)
     if return_factors:
         return a, q, lam
     return a

@@ -69,6 +69,47 @@ def test_refinement_is_quadratic():
     assert res[-1] <= floor, res
 
 
+def test_predicted_stop_skips_the_last_residual():
+    """With the default tolerance the loop stops on the prediction
+    ||I - A X'||_F <= ||R||_F^2 + floor (I - A (X + X R) = R^2), without
+    forming the residual of the returned X; that residual, measured on the
+    host, meets the stop rule."""
+    n = 700
+    a = inputs.spectrum(n, 1e2, seed=11).numpy()
+    x, rep = spd.spd_inverse(torch.from_numpy(a).to(DEV), mode="mixed_fp32", return_report=True)
+    print(rep)
+    assert rep["fell_back"] == 0 and rep["converged"] == 1
+    assert rep["predicted"] == 1 and rep["resid_fro_rel"] <= 1e-13
+    assert rep["resid_last_rel"] > 1e-13          # the last residual formed was not enough
+    assert resid_rel(a, x.cpu().numpy()) <= 1e-13  # the prediction held
+
+
+def test_explicit_step_limit_returns_unconverged_result():
+    """max_refine = 1 at the default tolerance: one step does not reach the
+    stop rule; an explicit limit keeps the refined X and says so."""
+    n = 500
+    a = inputs.spectrum(n, 1e2, seed=12).numpy()
+    x, rep = spd.spd_inverse(torch.from_numpy(a).to(DEV), mode="mixed_fp32", return_report=True,
+                             max_refine=1)
+    assert rep["fell_back"] == 0 and rep["converged"] == 0 and rep["refine_iters"] == 1
+    assert rep["resid_fro_rel"] > 1e-13
+    r = resid_rel(a, x.cpu().numpy())
+    assert r > 1e-13 and r <= 4 * rep["resid_fro_rel"]   # the report does not claim convergence
+
+
+def test_default_step_limit_exhausted_falls_back(monkeypatch):
+    """When the library's own step limit runs out before the stop rule is met
+    (forced from the host with a limit of one step), the FP64 path gives the
+    result, bit for bit, with fell_back = 2."""
+    n = 500
+    a = torch.from_numpy(inputs.spectrum(n, 1e2, seed=12).numpy()).to(DEV)
+    monkeypatch.setenv("SPDINV_DEFAULT_MAX_REFINE", "1")
+    x, rep = spd.spd_inverse(a, mode="mixed_fp32", return_report=True)
+    monkeypatch.delenv("SPDINV_DEFAULT_MAX_REFINE")
+    assert rep["fell_back"] == 2 and rep["converged"] == 0
+    assert torch.equal(x, spd.spd_inverse(a))
+
+
 def test_tolerance_controls_iterations():
     n = 400
     a = torch.from_numpy(inputs.spectrum(n, 1e2, seed=5).numpy()).to(DEV)

@@ -289,20 +289,24 @@ def test_two_workgroups_per_cu_bit_identical(n):
         assert rel_fro(x2.cpu().numpy(), ref) <= 1e-12 * 1e3
 
 
+@pytest.mark.parametrize("parts", [2, 4])
 @pytest.mark.parametrize("n", [200, 300, 1000, 2048 + 64, 4096 + 1])
-def test_row_half_split_bit_identical(n):
-    """By default TRSM(j+1, j) and the last SYRK into tile (j+1, j+1) run as
-    two row-half tasks each, on two workgroups.  A half forms the same MFMA
+def test_row_part_split_bit_identical(n, parts):
+    """With several workers, TRSM(j+1, j) and the last SYRK into tile
+    (j+1, j+1) run as row-part tasks on several workgroups: two halves or
+    four quarters (forced here with `parts`; the library picks quarters below
+    96 tiles per side and halves from there).  A part forms the same MFMA
     sequence per output element as the whole product, so the inverse, the
     Cholesky factor and the solve are bit-identical to the unsplit plan,
-    including ragged last tiles with more and with fewer than 64 valid rows."""
+    including ragged last tiles with more and with fewer valid rows than a
+    part holds."""
     a = inputs.spectrum(n, 1e3, seed=9, device=DEV)
     x_whole = spd.spd_inverse(a, no_split=1)
-    x_split = spd.spd_inverse(a)
+    x_split = spd.spd_inverse(a, parts=parts)
     assert torch.equal(x_whole, x_split)
-    assert torch.equal(spd.cholesky(a, no_split=1), spd.cholesky(a))
+    assert torch.equal(spd.cholesky(a, no_split=1), spd.cholesky(a, parts=parts))
     b = torch.randn(n, 3, dtype=torch.float64, generator=torch.Generator().manual_seed(n)).to(DEV)
-    assert torch.equal(spd.solve(a, b, no_split=1), spd.solve(a, b))
+    assert torch.equal(spd.solve(a, b, no_split=1), spd.solve(a, b, parts=parts))
     if n <= 300:
         ref = oracle.spd_inverse(a.cpu().numpy())
         assert rel_fro(x_split.cpu().numpy(), ref) <= 1e-12 * 1e3

@@ -341,3 +341,26 @@ def test_potrs_upper_triangle_not_read_and_zero_pivot():
     with pytest.raises(oracle.OracleInfo) as e:
         oracle.potrs(lo, b)
     assert e.value.info == 5
+
+
+def test_thread_count_does_not_change_a_bit():
+    """The oracle parallelizes only over independent outputs (each element is
+    one thread's sequential sum), so 1 thread and every host core give the
+    same bits; the benchmark times both."""
+    import os
+    a = inputs.spectrum(301, 1e3, seed=21).numpy()
+    g = inputs.randn((301, 301), seed=22).numpy()
+    nt0 = oracle.num_threads()
+    try:
+        oracle.set_num_threads(1)
+        x1 = oracle.spd_inverse_lower(a)
+        g1 = oracle.inverse_grad(x1, g)
+        s1 = oracle.potrs(oracle.potrf(a), g[:, :5])
+        oracle.set_num_threads(max(2, os.cpu_count() or 2))
+        assert oracle.num_threads() >= 2
+        xn = oracle.spd_inverse_lower(a)
+        gn = oracle.inverse_grad(xn, g)
+        sn = oracle.potrs(oracle.potrf(a), g[:, :5])
+    finally:
+        oracle.set_num_threads(nt0)
+    assert np.array_equal(x1, xn) and np.array_equal(g1, gn) and np.array_equal(s1, sn)

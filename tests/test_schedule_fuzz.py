@@ -22,6 +22,8 @@ VARIANTS = [
     dict(renamed=0, loop_order=0, pipelined=1),
     dict(renamed=0, loop_order=0, pipelined=1, trtri_first=1),
     dict(renamed=1, loop_order=0, pipelined=1, trtri_first=1),
+    dict(renamed=1, loop_order=0, pipelined=1, parts=2),
+    dict(renamed=1, loop_order=0, pipelined=1, parts=4),
 ]
 
 

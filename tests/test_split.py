@@ -33,10 +33,11 @@ def preds_of(p):
     return pr
 
 
+@pytest.mark.parametrize("parts", [0, 2, 4])
 @pytest.mark.parametrize("opts", [dict(), dict(chain=1), dict(renamed=0), dict(pipelined=0)])
 @pytest.mark.parametrize("t", [2, 3, 6, 9])
-def test_split_marks_the_step1_path(t, opts):
-    p = spd.plan_export(t, workers=8, **opts)
+def test_split_marks_the_step1_path(t, opts, parts):
+    p = spd.plan_export(t, workers=8, parts=parts, **opts)
     tasks = p["tasks"]
     code = tasks[:, 0]
     kind = code & 0xFF
@@ -44,6 +45,7 @@ def test_split_marks_the_step1_path(t, opts):
     heads = np.where(part & (idx == 0))[0]
     k = int(nparts[heads[0]])
     assert k in (2, 4) and np.all(nparts[part] == k)
+    assert k == (parts or 4)            # library choice below 96 tiles: quarters
     # one TRSM and one SYRK per step from POTRF(j) to POTRF(j+1)
     assert len(heads) == 2 * (t - 1) and int(part.sum()) == k * len(heads)
     assert sorted(kind[heads].tolist()) == [SYRK1] * (t - 1) + [TRSM1] * (t - 1)
@@ -81,15 +83,30 @@ def test_no_split_with_one_worker_or_when_turned_off(t):
     assert len(split["tasks"]) == len(whole["tasks"]) + (k - 1) * 2 * (t - 1)
 
 
-@pytest.mark.parametrize("bad", [2, -1])
+@pytest.mark.parametrize("bad", [dict(no_split=2), dict(no_split=-1), dict(parts=1),
+                                 dict(parts=3), dict(parts=8), dict(parts=-2)])
 def test_split_option_range_checked(bad):
-    """An out-of-range no_split is rejected before anything touches the device."""
+    """An out-of-range no_split or parts is rejected before anything touches
+    the device."""
     import ctypes
     from paper_1002_4057_amd import _lib
     lib = _lib.load()
-    o = _lib.make_opts(no_split=bad)
+    o = _lib.make_opts(**bad)
     assert lib.spd_inverse(4, ctypes.c_void_p(8), 4, 0, None, 0, None, ctypes.byref(o), None,
-                           None) != 0
+                           None) == -8
+
+
+@pytest.mark.parametrize("parts", [2, 4])
+def test_forced_parts_at_wide_orders(parts):
+    """At 96 tiles per side and more the library picks halves; `parts` forces
+    halves or quarters there too (the plan the GPU tests run at n = 16384)."""
+    t = 100
+    p = spd.plan_export(t, workers=512, parts=parts)
+    part, idx, nparts = parts_of(p["tasks"][:, 0])
+    assert np.all(nparts[part] == parts) and int(part.sum()) == parts * 2 * (t - 1)
+    lib_choice = spd.plan_export(t, workers=512)
+    part0, _, nparts0 = parts_of(lib_choice["tasks"][:, 0])
+    assert np.all(nparts0[part0] == 2)
 
 
 @pytest.mark.parametrize("steps,s", [(9, 1), (9, 2), (8, 1)])
@@ -129,3 +146,39 @@ def test_workspace_task_bound_covers_every_plan():
                     p = spd.plan_export(t, workers=256, steps=steps, rhs_tiles=s, chain=chain,
                                         **opts)
                     assert len(p["tasks"]) <= bound(t, s), (t, steps, s, chain, opts)
+
+
+def _plan_sizes(t, workers, **opts):
+    import ctypes
+    from paper_1002_4057_amd import _lib
+    lib = _lib.load()
+    o = _lib.make_opts(**opts)
+    nt, ns, nl = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
+    rc = lib.spdinv_plan_export_steps(7, 0, t, ctypes.byref(o), workers, None, None, None, None,
+                                      None, ctypes.byref(nt), ctypes.byref(ns), None,
+                                      ctypes.byref(nl))
+    assert rc == 0
+    return nt.value, ns.value, nl.value
+
+
+def test_largest_order_plans_fit_int32_and_the_workspace_bound():
+    """n = 32768 (t = 256, the largest order of the precision workload), in
+    the launch the library uses there (512 workers): the default chained plan
+    is exported and its int32 fields checked against the pool and the task
+    count; the unchained plan with quarters (the most device tasks any FP64
+    plan has at this order) must still fit the workspace's task bound."""
+    t, T = 256, 256 * 257 // 2
+    bound = 3 * (t * (t - 1) * (t - 2) // 6) + 6 * (t * (t - 1) // 2) + 3 * t + 2 + 3 * (2 * t)
+    nt, ns, nl = _plan_sizes(t, 512, chain=1, parts=4)
+    assert nt <= bound and ns < 2 ** 31
+    p = spd.plan_export(t, workers=512)
+    tasks, succ, links = p["tasks"], p["succ"], p["links"]
+    ntask = len(tasks)
+    assert ntask <= bound and len(succ) < 2 ** 31 and links.size < 2 ** 31
+    pool = 3 * T + 2 * t
+    assert tasks[:, 1:5].max() < pool and tasks[:, 1:5].min() >= -1
+    assert np.all(tasks[:, 6] <= tasks[:, 7]) and tasks[-1, 7] == len(succ)
+    assert succ.min() >= 0 and succ.max() < ntask
+    assert (links[:, 0] & ~(1 << 30)).max() < pool and links[:, 1].max() < pool
+    order = p["order"]
+    assert np.array_equal(np.sort(order), np.arange(ntask))   # a permutation of the tasks
