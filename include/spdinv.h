@@ -297,7 +297,40 @@ size_t spd_inverse_backward_workspace_bytes(int n);
 int spd_inverse_backward(int n, const double* X, int ldx, const double* G, int ldg, double* gradA,
                          int ldga, void* work, size_t work_bytes, spdinv_stream_t stream);
 
-/* Frees every cached plan (device arena and host tables). */
+/* ---- allocation-free entry point -------------------------------------------- */
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FP64
+ * inverse of spd_inverse, same plan and kernels and therefore the same bits,
+ * with the workspace and the plan's device tables in a scratch array that the
+ * library holds in device memory: SPDINV_NOALLOC_SCRATCH_BYTES (57 MiB) on
+ * each GPU the library runs on, from the first call on that GPU until the
+ * process ends.  The call performs no hipMalloc, hipFree or other device
+ * allocation; it copies the plan's tables (host memory kept by the library)
+ * into the scratch with hipMemcpyAsync on `stream` when the previous call on
+ * this GPU used another plan.
+ *   n        order, 0 <= n <= SPDINV_NOALLOC_MAX_N; a larger n returns -1
+ *            (nothing is enqueued)
+ *   A, lda   as for spd_inverse (device, column-major, lower triangle read
+ *            and overwritten; lda >= max(1,n))
+ *   stream   HIP stream; the call is asynchronous (it never waits)
+ *   opts     host or NULL, as for spd_inverse (FP64 variants, chain, per_cu,
+ *            no_split, parts, fill_upper, workers); trace is rejected (-5)
+ *   d_info   device int or NULL: INFO as for spd_inverse
+ * Returns 0, -i for an invalid i-th argument, or SPDINV_ERR_HIP.
+ * Every call on one GPU uses that GPU's single scratch array, whose contents
+ * persist between calls (each call first resets what must start at zero):
+ * calls that may overlap on one GPU (other streams, other host threads)
+ * race and give unspecified results.  Serialize them on one stream.
+ */
+#define SPDINV_NOALLOC_MAX_N 2048
+#define SPDINV_NOALLOC_SCRATCH_BYTES ((size_t)59768832)
+int spd_inverse_noalloc(int n, double* A, int lda, spdinv_stream_t stream,
+                        const spdinv_opts* opts, int* d_info);
+
+/* Frees every cached plan (device arena and host tables).  The host tables of
+   spd_inverse_noalloc's plans are kept, since an upload from them may still
+   be pending on a stream. */
 void spdinv_release_plans(void);
 
 /* ---- planner introspection (host only; no GPU needed) -------------------- */

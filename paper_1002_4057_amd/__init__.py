@@ -28,7 +28,7 @@ __all__ = ["spd_inverse", "spd_inverse_", "workspace_bytes", "plan_stats", "plan
            "batched_spd_inverse", "batched_spd_inverse_", "batched_workspace_bytes",
            "cholesky", "cholesky_", "inverse_from_factor", "inverse_from_factor_",
            "solve", "solve_", "solve_from_factor", "solve_from_factor_", "solve_workspace_bytes",
-           "SpdInverseError", "NotPositiveDefinite"]
+           "spd_inverse_noalloc_", "SpdInverseError", "NotPositiveDefinite"]
 
 
 class SpdInverseError(RuntimeError):
@@ -107,6 +107,28 @@ def spd_inverse_(a_cm, *, mode: str = "fp64", work=None, report: bool = False, i
             raise NotPositiveDefinite(r["info"])
         return r
     return None
+
+
+def spd_inverse_noalloc_(a_cm, *, info=None, **opts):
+    """A <- A^{-1} in place on a column-major CUDA float64 view, as
+    ``spd_inverse_`` in FP64, through the library's allocation-free entry
+    point: no workspace argument (the library's per-GPU device scratch holds
+    it), n <= 2048, asynchronous on the current stream.  Calls that may
+    overlap on one GPU race."""
+    import torch
+    if a_cm.dtype != torch.float64 or not a_cm.is_cuda or a_cm.dim() != 2:
+        raise TypeError("expected a 2-D CUDA float64 tensor")
+    n = a_cm.shape[0]
+    if a_cm.shape[1] != n:
+        raise ValueError("matrix must be square")
+    if n > 1 and a_cm.stride(0) != 1:
+        raise ValueError("expected a column-major view (stride(0) == 1)")
+    lda = max(1, a_cm.stride(1) if n > 1 else max(1, n))
+    o = make_opts(**opts)
+    rc = load().spd_inverse_noalloc(n, a_cm.data_ptr(), lda, _stream_ptr(a_cm.device),
+                                    ctypes.byref(o), info.data_ptr() if info is not None else None)
+    if rc != 0:
+        raise SpdInverseError(f"spd_inverse_noalloc returned {rc}")
 
 
 def _fp64_step_entry(name: str, a_cm, work, report: bool, info, opts):

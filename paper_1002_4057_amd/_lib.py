@@ -22,6 +22,8 @@ ERR_HIP = 2
 ERR_TIMEOUT = 3
 ERR_UNSUPPORTED = 4
 
+NOALLOC_MAX_N = 2048
+
 TASK_NAMES = ["NOP", "SYRK1", "POTRF", "GEMM1", "TRSM1", "TRTRI", "TRMM2L", "GEMM2", "TRSM2R",
               "TRMM3", "LAUUM", "GEMM3", "SYRK3"]
 
@@ -111,6 +113,8 @@ def load():
     lib.spd_inverse_backward_workspace_bytes.restype = sz
     lib.spd_inverse_backward.argtypes = [i, vp, i, vp, i, vp, i, vp, sz, vp]
     lib.spd_inverse_backward.restype = i
+    lib.spd_inverse_noalloc.argtypes = [i, vp, i, vp, P(Opts), vp]
+    lib.spd_inverse_noalloc.restype = i
     lib.spdinv_version.argtypes = []
     lib.spdinv_version.restype = ctypes.c_char_p
     _lib = lib

@@ -62,8 +62,18 @@ struct Key {
   }
 };
 
+// The device tables of a plan as one host image (tasks in dispatch order,
+// CSR successors by dispatch position, initial in-degrees, chain links), at
+// 256-byte aligned offsets, ready to be copied to device memory as a whole.
+struct PlanImage {
+  std::vector<char> bytes;
+  size_t o_tasks = 0, o_succ = 0, o_indeg = 0, o_links = 0;
+  bool has_links = false;
+};
+
 struct DevPlan {
   Plan host;
+  PlanImage image;
   void* arena = nullptr;
   DevTask* d_tasks = nullptr;  // dispatch order
   int32_t* d_succ = nullptr;
@@ -190,32 +200,11 @@ int grid_for(int device, int t, const spdinv_opts& o) {
   return g;
 }
 
-// The plan for t tiles per side, built once per (device, variant, workers,
-// chain, split) and kept with its device copy.  chain: most products per
-// device task (1 for executors that run the paper's tasks one by one).
-// allow_split: the executor runs row-half tasks (the FP64 scheduler).
-DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, int chain,
-                  hipError_t* err, int steps = 7, int rhs_tiles = 0, bool allow_split = false) {
-  Key k{device, t, o.renamed ? 1 : 0, o.loop_order, o.pipelined ? 1 : 0, o.trtri_first ? 1 : 0,
-        workers, chain, steps, rhs_tiles, allow_split ? split_for(o, t, workers) : 0};
-  std::lock_guard<std::mutex> lk(g_mu);
-  auto it = g_plans.find(k);
-  if (it != g_plans.end()) return it->second.get();
-  std::unique_ptr<DevPlan> dp(new DevPlan);
-  PlanOptions po;
-  po.t = t;
-  po.renamed = k.renamed;
-  po.loop_order = k.loop_order;
-  po.pipelined = k.pipelined;
-  po.trtri_first = k.trtri_first;
-  po.chain = k.chain;
-  po.steps = k.steps;
-  po.rhs_tiles = k.rhs;
-  po.split = k.split;
-  build_plan(po, workers, kCost, &dp->host);
-  const Plan& p = dp->host;
+// Device-table image of a built plan: the task list permuted into dispatch
+// order (a task's id on the device is its dispatch ticket), successors
+// renumbered to dispatch positions.
+void make_image(const Plan& p, PlanImage* im) {
   const size_t nt = p.tasks.size();
-  // device arrays in dispatch order: task id on the device = dispatch ticket
   std::vector<int32_t> pos(nt);
   for (size_t k = 0; k < nt; ++k) pos[p.order[k]] = (int32_t)k;
   std::vector<DevTask> dtask(nt);
@@ -232,31 +221,76 @@ DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, int chai
     dtask[k] = d;
     dindeg[k] = p.indeg[v];
   }
-  const size_t o_tasks = 0;
-  const size_t o_succ = align_up(o_tasks + nt * sizeof(DevTask), 256);
-  const size_t o_indeg = align_up(o_succ + dsucc.size() * sizeof(int32_t) + 4, 256);
-  const size_t o_links = align_up(o_indeg + nt * sizeof(int32_t), 256);
-  const size_t bytes = align_up(o_links + p.links.size() * sizeof(int32_t) + 4, 256);
+  im->o_tasks = 0;
+  im->o_succ = align_up(im->o_tasks + nt * sizeof(DevTask), 256);
+  im->o_indeg = align_up(im->o_succ + dsucc.size() * sizeof(int32_t) + 4, 256);
+  im->o_links = align_up(im->o_indeg + nt * sizeof(int32_t), 256);
+  const size_t bytes = align_up(im->o_links + p.links.size() * sizeof(int32_t) + 4, 256);
+  im->bytes.assign(bytes, 0);
+  char* h = im->bytes.data();
+  std::memcpy(h + im->o_tasks, dtask.data(), nt * sizeof(DevTask));
+  if (!dsucc.empty()) std::memcpy(h + im->o_succ, dsucc.data(), dsucc.size() * sizeof(int32_t));
+  std::memcpy(h + im->o_indeg, dindeg.data(), nt * sizeof(int32_t));
+  if (!p.links.empty())
+    std::memcpy(h + im->o_links, p.links.data(), p.links.size() * sizeof(int32_t));
+  im->has_links = !p.links.empty();
+}
+
+// Points the device-table pointers of dp into `base`, where its image lives.
+void bind_tables(DevPlan* dp, char* base) {
+  dp->d_tasks = (DevTask*)(base + dp->image.o_tasks);
+  dp->d_succ = (int32_t*)(base + dp->image.o_succ);
+  dp->d_indeg0 = (int32_t*)(base + dp->image.o_indeg);
+  dp->d_links = dp->image.has_links ? (int32_t*)(base + dp->image.o_links) : nullptr;
+}
+
+Key plan_key(int device, int t, const spdinv_opts& o, int workers, int chain, int steps,
+             int rhs_tiles, bool allow_split) {
+  return Key{device, t, o.renamed ? 1 : 0, o.loop_order, o.pipelined ? 1 : 0,
+             o.trtri_first ? 1 : 0, workers, chain, steps, rhs_tiles,
+             allow_split ? split_for(o, t, workers) : 0};
+}
+
+std::unique_ptr<DevPlan> build_dev_plan(const Key& k) {
+  std::unique_ptr<DevPlan> dp(new DevPlan);
+  PlanOptions po;
+  po.t = k.t;
+  po.renamed = k.renamed;
+  po.loop_order = k.loop_order;
+  po.pipelined = k.pipelined;
+  po.trtri_first = k.trtri_first;
+  po.chain = k.chain;
+  po.steps = k.steps;
+  po.rhs_tiles = k.rhs;
+  po.split = k.split;
+  build_plan(po, k.workers, kCost, &dp->host);
+  make_image(dp->host, &dp->image);
+  return dp;
+}
+
+// The plan for t tiles per side, built once per (device, variant, workers,
+// chain, split) and kept with its device copy in a library-owned arena.
+// chain: most products per device task (1 for executors that run the
+// paper's tasks one by one).  allow_split: the executor runs row-half tasks
+// (the FP64 scheduler).
+DevPlan* get_plan(int device, int t, const spdinv_opts& o, int workers, int chain,
+                  hipError_t* err, int steps = 7, int rhs_tiles = 0, bool allow_split = false) {
+  const Key k = plan_key(device, t, o, workers, chain, steps, rhs_tiles, allow_split);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_plans.find(k);
+  if (it != g_plans.end()) return it->second.get();
+  std::unique_ptr<DevPlan> dp = build_dev_plan(k);
+  const size_t bytes = dp->image.bytes.size();
   void* arena = nullptr;
   *err = hipMalloc(&arena, bytes);
   if (*err != hipSuccess) return nullptr;
-  char* base = (char*)arena;
-  std::vector<char> host(bytes, 0);
-  std::memcpy(host.data() + o_tasks, dtask.data(), nt * sizeof(DevTask));
-  if (!dsucc.empty()) std::memcpy(host.data() + o_succ, dsucc.data(), dsucc.size() * sizeof(int32_t));
-  std::memcpy(host.data() + o_indeg, dindeg.data(), nt * sizeof(int32_t));
-  if (!p.links.empty())
-    std::memcpy(host.data() + o_links, p.links.data(), p.links.size() * sizeof(int32_t));
-  *err = hipMemcpy(arena, host.data(), bytes, hipMemcpyHostToDevice);
+  *err = hipMemcpy(arena, dp->image.bytes.data(), bytes, hipMemcpyHostToDevice);
   if (*err != hipSuccess) {
     (void)hipFree(arena);
     return nullptr;
   }
   dp->arena = arena;
-  dp->d_tasks = (DevTask*)(base + o_tasks);
-  dp->d_succ = (int32_t*)(base + o_succ);
-  dp->d_indeg0 = (int32_t*)(base + o_indeg);
-  dp->d_links = p.links.empty() ? nullptr : (int32_t*)(base + o_links);
+  bind_tables(dp.get(), (char*)arena);
   DevPlan* raw = dp.get();
   g_plans[k] = std::move(dp);
   return raw;
@@ -299,9 +333,11 @@ long long spin_limit() {
 // of Algorithm 1 selected by `steps`), copy-out.  For the inverse from a
 // given factor (steps 2 and 3) a prologue kernel first makes what step 1
 // would leave for step 2.
+// `given`: the plan with its device tables already in place (the
+// allocation-free entry point); null = the cached plan in its arena.
 int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream_t stream,
              const spdinv_opts& o, int* d_info, spdinv_report* report, int steps = 7,
-             int nrhs = 0, double* Bm = nullptr, int ldb = 1) {
+             int nrhs = 0, double* Bm = nullptr, int ldb = 1, DevPlan* given = nullptr) {
   const Layout L = layout(n, o, nrhs);
   const int s = (nrhs + NB - 1) / NB;
   if (work_bytes < L.total) return SPDINV_ERR_WORKSPACE;
@@ -311,7 +347,7 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   const int t = tiles_for(n);
   const int grid = grid_for(device, t, o);
   hipError_t err = hipSuccess;
-  DevPlan* dp = get_plan(device, t, o, grid, chain_for(o), &err, steps, s, true);
+  DevPlan* dp = given ? given : get_plan(device, t, o, grid, chain_for(o), &err, steps, s, true);
   if (!dp) return SPDINV_ERR_HIP;
   const int ntask = (int)dp->host.tasks.size();
 
@@ -343,7 +379,7 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   a.info_base = 0;
   a.spin_limit = spin_limit();
   hipEvent_t ev0, ev1;
-  const bool timed = timer_pair(&ev0, &ev1);
+  const bool timed = !given && timer_pair(&ev0, &ev1);
   if (timed && hipEventRecord(ev0, stream) != hipSuccess) return SPDINV_ERR_HIP;
   if (launch_sched(a, grid, per_cu_for(t, o), stream) != hipSuccess) return SPDINV_ERR_HIP;
   if (timed && hipEventRecord(ev1, stream) != hipSuccess) return SPDINV_ERR_HIP;
@@ -862,6 +898,65 @@ int spd_solve_from_factor(int n, int nrhs, const double* L, int ldl, double* B, 
                           const spdinv_opts* opts, int* d_info, spdinv_report* report) {
   return solve_entry(n, nrhs, const_cast<double*>(L), ldl, B, ldb, work, work_bytes, stream, opts,
                      d_info, report, true);
+}
+
+// ---- allocation-free entry point -------------------------------------------
+// Plans whose device tables live in the device scratch, and per device the
+// plan whose tables the scratch currently holds (uploaded again only when a
+// call needs another one).
+static_assert(NOALLOC_SCRATCH_BYTES == SPDINV_NOALLOC_SCRATCH_BYTES, "scratch size in the header");
+static_assert(NOALLOC_MAX_N == SPDINV_NOALLOC_MAX_N, "largest order in the header");
+static_assert(NOALLOC_MAX_N <= MAX_BATCH_T * NB, "the pool is sized for 16 tiles per side");
+static std::map<Key, std::unique_ptr<DevPlan>> g_static_plans;
+static std::map<int, Key> g_static_loaded;
+
+int spd_inverse_noalloc(int n, double* A, int lda, spdinv_stream_t stream_,
+                        const spdinv_opts* opts, int* d_info) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  if (n < 0 || n > SPDINV_NOALLOC_MAX_N) return -1;
+  if (n > 0 && !A) return -2;
+  if (lda < (n > 1 ? n : 1)) return -3;
+  const spdinv_opts o = opts ? *opts : defaults();
+  if (check_opts(o) || o.trace) return -5;
+  if (n == 0) return launch_info_zero(d_info, stream) == hipSuccess ? 0 : SPDINV_ERR_HIP;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return SPDINV_ERR_HIP;
+  char* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  if (noalloc_scratch((void**)&scratch, &scratch_bytes) != hipSuccess) return SPDINV_ERR_HIP;
+  char* tables = scratch;
+  char* work = scratch + NOALLOC_PLAN_BYTES;
+  const size_t work_bytes = scratch_bytes - NOALLOC_PLAN_BYTES;
+  const Layout L = layout(n, o);
+  if (L.total > work_bytes) return SPDINV_ERR_WORKSPACE;  // not reached for n <= the maximum
+  const int t = tiles_for(n);
+  const int grid = grid_for(device, t, o);
+  const Key k = plan_key(device, t, o, grid, chain_for(o), 7, 0, true);
+  DevPlan* dp = nullptr;
+  bool upload = false;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_static_plans.find(k);
+    if (it == g_static_plans.end()) {
+      std::unique_ptr<DevPlan> p = build_dev_plan(k);
+      if (p->image.bytes.size() > NOALLOC_PLAN_BYTES) return SPDINV_ERR_WORKSPACE;
+      bind_tables(p.get(), tables);
+      it = g_static_plans.emplace(k, std::move(p)).first;
+    }
+    dp = it->second.get();
+    auto ld = g_static_loaded.find(device);
+    upload = ld == g_static_loaded.end() || ld->second < k || k < ld->second;
+    if (upload) g_static_loaded[device] = k;
+  }
+  // the image stays in the host cache for the life of the process, so the
+  // copy may complete after this call returns
+  if (upload && hipMemcpyAsync(tables, dp->image.bytes.data(), dp->image.bytes.size(),
+                               hipMemcpyHostToDevice, stream) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_static_loaded.erase(device);
+    return SPDINV_ERR_HIP;
+  }
+  return run_fp64(n, A, lda, work, work_bytes, stream, o, d_info, nullptr, 7, 0, nullptr, 1, dp);
 }
 
 void spdinv_release_plans(void) {

@@ -6,6 +6,8 @@
 #include "tile_tasks.hpp"
 
 #include <climits>
+#include <map>
+#include <mutex>
 
 namespace spdinv {
 namespace {
@@ -107,6 +109,8 @@ __global__ __launch_bounds__(NTHREADS) void copy_out_kernel(const double* __rest
   }
 }
 
+__global__ void info_zero_kernel(int* d_info) { d_info[0] = 0; }
+
 __global__ void info_out_kernel(const int32_t* ctrl, int* d_info) {
   const int v = ctrl[CTRL_INFO];
   d_info[0] = (v == INT_MAX) ? 0 : v;
@@ -182,6 +186,12 @@ hipError_t launch_copy_out(const double* pool, int t, double* A, int lda, int n,
   return hipGetLastError();
 }
 
+hipError_t launch_info_zero(int* d_info, hipStream_t s) {
+  if (!d_info) return hipSuccess;
+  hipLaunchKernelGGL(info_zero_kernel, dim3(1), dim3(1), 0, s, d_info);
+  return hipGetLastError();
+}
+
 hipError_t launch_info_out(const int32_t* ctrl, int* d_info, hipStream_t s) {
   if (!d_info) return hipSuccess;
   hipLaunchKernelGGL(info_out_kernel, dim3(1), dim3(1), 0, s, ctrl, d_info);
@@ -205,6 +215,33 @@ int sched_blocks_per_cu() {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sched_kernel, NTHREADS, 0) != hipSuccess)
     return 1;
   return blocks > 0 ? blocks : 1;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free entry point.  Host code never uses the
+// array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device with that device current.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+hipError_t noalloc_scratch(void** ptr, size_t* bytes) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;  // device -> address of its scratch
+  int device = 0;
+  hipError_t e = hipGetDevice(&device);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = addr.find(device);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    it = addr.emplace(device, p).first;
+  }
+  *ptr = it->second;
+  *bytes = NOALLOC_SCRATCH_BYTES;
+  return hipSuccess;
 }
 
 }  // namespace spdinv

@@ -98,6 +98,23 @@ hipError_t launch_rhs_in(const double* B, int ldb, int n, int nrhs, int t, doubl
 hipError_t launch_rhs_out(const double* R, int t, int n, int nrhs, double* B, int ldb,
                           hipStream_t s);
 
+// Writes 0 to a device int (nullptr: no-op), as a kernel so that the call
+// can be captured in a graph.
+hipError_t launch_info_zero(int* d_info, hipStream_t s);
+
+// Device scratch of the allocation-free entry point: a file-scope device
+// array, one per GPU, holding a plan's device tables (the first
+// NOALLOC_PLAN_BYTES) and the workspace of an inversion of order up to
+// NOALLOC_MAX_N (the pool of pool_tiles(16) = 440 tiles, then the in-degree
+// counters and the control words).
+constexpr int NOALLOC_MAX_N = 2048;
+constexpr size_t NOALLOC_PLAN_BYTES = size_t(1) << 20;
+constexpr size_t NOALLOC_WORK_BYTES = size_t(440) * NB * NB * sizeof(double) + (size_t(1) << 20);
+constexpr size_t NOALLOC_SCRATCH_BYTES = NOALLOC_PLAN_BYTES + NOALLOC_WORK_BYTES;
+// Device address of the current device's scratch (looked up once per device
+// with that device current) and its size.
+hipError_t noalloc_scratch(void** ptr, size_t* bytes);
+
 // Persistent scheduler over the plan's tasks.
 // per_cu: 1 keeps every workgroup alone on its CU, 2 lets two share one.
 hipError_t launch_sched(const SchedArgs& a, int grid, int per_cu, hipStream_t s);
