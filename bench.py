@@ -193,40 +193,65 @@ def precision_cells(n, q, kappas, modes, reps, work=None):
     return cells
 
 
-def batched_row(reps: int):
+def batched_row(reps: int, mode: str = "fp64", group: int = 0):
     """Batched workload: 8192 matrices, n uniform on {16..512} (seed 0),
-    A_i = B_i B_i^T / n_i + 0.1 I, one persistent launch per step."""
+    A_i = B_i B_i^T / n_i + 0.1 I, in FP64 or FP32: one DAG over the batch in
+    one persistent launch per step, timed eagerly and as the replay of a
+    captured HIP graph (the matrices are restored untimed between steps)."""
     import numpy as np
     import torch
     import paper_1002_4057_amd as spd
     from paper_1002_4057_amd import inputs
     dev = torch.device("cuda:0")
+    dtype = torch.float64 if mode == "fp64" else torch.float32
+    esize = 8 if mode == "fp64" else 4
     orders = inputs.batch_orders(8192, 16, 512, seed=0)
     mats = inputs.batched_wishart(orders, seed=0, shift=0.1)
     offs = np.concatenate([[0], np.cumsum([n * n for n in orders])]).astype(np.int64)
-    host = torch.empty(int(offs[-1]), dtype=torch.float64)
+    host = torch.empty(int(offs[-1]), dtype=dtype)
     for m, n, o in zip(mats, orders, offs[:-1]):
-        host[int(o):int(o) + n * n] = m.t().reshape(-1)   # column-major
+        host[int(o):int(o) + n * n] = m.t().reshape(-1).to(dtype)   # column-major
     src = host.to(dev)
     buf = src.clone()
-    ptrs = torch.tensor([buf.data_ptr() + 8 * int(o) for o in offs[:-1]], dtype=torch.int64,
+    ptrs = torch.tensor([buf.data_ptr() + esize * int(o) for o in offs[:-1]], dtype=torch.int64,
                         device=dev)
     n_dev = torch.tensor(orders, dtype=torch.int32, device=dev)
     info = torch.zeros(len(orders), dtype=torch.int32, device=dev)
-    work = spd.batched_spd_inverse_(ptrs, orders, n_dev, n_dev, info=info)   # warm: plans
+    opts = {"batch_group": group} if group else {}
+    work = spd.batched_spd_inverse_(ptrs, orders, n_dev, n_dev, mode=mode, info=info,
+                                    **opts)   # warm: task lists
     torch.cuda.synchronize()
     if int(info.abs().sum()) != 0:
         raise RuntimeError("batched warm-up reported INFO != 0")
-    ms = time_events(lambda: spd.batched_spd_inverse_(ptrs, orders, n_dev, n_dev, work=work,
-                                                      info=info),
+    ms = time_events(lambda: spd.batched_spd_inverse_(ptrs, orders, n_dev, n_dev, mode=mode,
+                                                      work=work, info=info, **opts),
                      reps, prep=lambda: buf.copy_(src))
+    # the same call captured in a HIP graph, replayed
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            spd.batched_spd_inverse_(ptrs, orders, n_dev, n_dev, mode=mode, work=work, info=info,
+                                     **opts)
+    torch.cuda.current_stream().wait_stream(s)
+    ms_graph = time_events(g.replay, reps, prep=lambda: buf.copy_(src))
+    torch.cuda.synchronize()
+    if int(info.abs().sum()) != 0:
+        raise RuntimeError("batched graph replay reported INFO != 0")
     flops = float(sum(float(n) ** 3 for n in orders))
-    return {"workload": "8192 SPD matrices, n uniform on [16,512] (seed 0), A_i = B_i B_i^T/n_i "
-                        "+ 0.1 I, FP64, one persistent launch",
-            "ms": round(ms, 3), "matrices_per_s": round(len(orders) / (ms / 1e3), 1),
-            "gflops": round(flops / (ms / 1e3) / 1e9, 1), "flops": flops,
-            "frac_fp64_peak": round(flops / (ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
-            "reps": reps}
+    peak = PEAK_FP64_TFLOPS if mode == "fp64" else PEAK_FP32_TFLOPS
+    best = min(ms, ms_graph)
+    out = {"workload": "8192 SPD matrices, n uniform on [16,512] (seed 0), A_i = B_i B_i^T/n_i "
+                       f"+ 0.1 I, {mode.upper()}, one DAG over the batch in one persistent launch",
+           "ms": round(ms, 3), "ms_graph_replay": round(ms_graph, 3),
+           "matrices_per_s": round(len(orders) / (best / 1e3), 1),
+           "gflops": round(flops / (best / 1e3) / 1e9, 1), "flops": flops,
+           f"frac_{mode}_peak": round(flops / (best / 1e3) / 1e12 / peak, 4),
+           "workspace_gb": round(work.numel() / 1e9, 2), "reps": reps}
+    del work, buf, src
+    torch.cuda.empty_cache()
+    return out
 
 
 def c1_row(spd, n: int, reps: int, ablation: bool):
@@ -355,6 +380,8 @@ def main():
     ap.add_argument("--large-n", type=int, default=32768)
     ap.add_argument("--large-kappas", default="1e2")
     ap.add_argument("--large-modes", default="fp64,mixed_fp32")
+    ap.add_argument("--batch-group", type=int, default=0,
+                    help="batched rows: matrices per dispatch group (0 = library choice)")
     ap.add_argument("--input", choices=["spectrum", "wishart"], default="spectrum",
                     help="wishart (B B^T/n + I, no QR) is for profiler counter runs only")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -470,8 +497,10 @@ def main():
         del a8_cm, work8
         torch.cuda.empty_cache()
     if "batched" in wanted:
-        log("[bench] batched row")
-        rows["batched"] = batched_row(max(2, min(K, 5)))
+        log("[bench] batched row (FP64)")
+        rows["batched"] = batched_row(max(2, min(K, 5)), "fp64", args.batch_group)
+        log("[bench] batched row (FP32)")
+        rows["batched_fp32"] = batched_row(max(2, min(K, 5)), "fp32", args.batch_group)
     if "backward" in wanted:
         log("[bench] backward row")
         rows["backward"] = backward_row(max(2, min(K, 5)))

@@ -61,7 +61,9 @@ enum {
 
 typedef enum {
   SPDINV_FP64 = 0,       /* every tile task in binary64 */
-  SPDINV_FP32 = 1,       /* reserved */
+  SPDINV_FP32 = 1,       /* FP32 storage (float matrices): tile products on FP32 matrix
+                            cores with FP32 accumulation, diagonal tiles factored and
+                            inverted in binary64 and rounded to FP32; no refinement */
   SPDINV_MIXED_FP32 = 2, /* tile products on FP32 matrix cores (FP32 accumulation),
                             diagonal tiles in binary64, then Newton-Schulz refinement
                             X <- X + X (I - A X) with binary64 residuals */
@@ -109,6 +111,19 @@ typedef struct {
   int parts;       /* FP64 form, with the split on: row parts per split product
                       (0 = library choice as above; 2 = halves; 4 = quarters).
                       Results do not depend on it.                           */
+  int batch_group; /* batched form: schedule.  -1 = one workgroup per matrix
+                      (largest first), running its tasks in order on the
+                      workgroup's own pool; -2 = one DAG over the batch,
+                      dispatched in the order of a list-scheduling
+                      simulation on 512 workers (or `workers`): the largest
+                      matrices first, each matrix's longest remaining path
+                      first, matrices that run one after another sharing
+                      pool slots; g > 0 = one DAG, the matrices' task lists
+                      interleaved position by position in groups of g
+                      matrices, each with its own pool; 0 (default) = the
+                      library's choice: -1 when the batch has at least two
+                      matrices per worker, else -2.  Results do not depend
+                      on it.                                                 */
 } spdinv_opts;
 
 typedef struct {
@@ -148,7 +163,11 @@ size_t spd_inverse_workspace_bytes(int n, spdinv_mode mode, const spdinv_opts* o
 
 /*
  * A <- A^{-1} for one SPD matrix (Algorithm 1 with the variants of Section 3).
- * mode SPDINV_FP64 runs every task in binary64.  mode SPDINV_MIXED_FP32
+ * A holds doubles, except in mode SPDINV_FP32, where it holds floats.
+ * mode SPDINV_FP64 runs every task in binary64.  mode SPDINV_FP32 (renamed
+ * plan only) runs the same DAG on FP32 tiles: products on FP32 matrix cores,
+ * diagonal tiles in binary64 rounded to FP32; the result is the FP32 inverse
+ * without refinement.  mode SPDINV_MIXED_FP32
  * (renamed plan only) runs the same DAG with FP32 tiles to get X0, then
  * refines by Newton-Schulz: R = I - A X in binary64, stop when
  * ||R||_F / ||A||_F <= refine_tol, else X <- X + X R (binary64, lower tiles,
@@ -170,7 +189,7 @@ size_t spd_inverse_workspace_bytes(int n, spdinv_mode mode, const spdinv_opts* o
  *   report   host or NULL; when given, the call waits for the stream and
  *            fills it (INFO is then also returned through report->info)
  */
-int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t work_bytes,
+int spd_inverse(int n, void* A, int lda, spdinv_mode mode, void* work, size_t work_bytes,
                 spdinv_stream_t stream, const spdinv_opts* opts, int* d_info,
                 spdinv_report* report);
 
@@ -243,30 +262,43 @@ size_t batched_spd_inverse_workspace_bytes(int batch, const int* h_n, spdinv_mod
                                            const spdinv_opts* opts);
 
 /*
- * A_i <- A_i^{-1} for `batch` independent SPD matrices of uneven orders, in
- * one persistent launch (plus a one-block sort that orders the matrices by
- * decreasing n).  Each matrix is inverted by one workgroup: n <= 128 entirely
- * in LDS, larger n through the tile plan of Section 3 executed in program
- * order (the sequential task stream of Algorithm 1) on a private tile pool.
- *   batch   number of matrices (>= 0)
- *   h_n     host int[batch], orders 0 <= n_i <= 2048 (sizes the workspace)
+ * A_i <- A_i^{-1} for `batch` independent SPD matrices of uneven orders, as
+ * one dependency-tracked DAG in one persistent launch (after a reset kernel).
+ * Every matrix with n > 128 runs the tile plan of Section 3 for its tile
+ * count (renamed, UDU, pipelined) between a copy-in task (its lower triangle
+ * to its own tiles) and a copy-out task; a matrix with n <= 128 is one task
+ * that inverts it in LDS in binary64.  The host merges the task lists into
+ * one dispatch order by simulating the launch (opts->batch_group), so the
+ * persistent workers run the tasks of many matrices side by side.
+ *   batch   number of matrices (0 <= batch < 2^19)
+ *   h_n     host int[batch], orders 0 <= n_i <= 2048 (the tile count of each
+ *           matrix selects its task list; sizes the workspace)
  *   d_n     device int[batch], the same orders
- *   d_A     device array of batch device pointers, column-major matrices;
- *           the lower triangle of each is read and overwritten
+ *   d_A     device array of batch device pointers to column-major matrices of
+ *           doubles (SPDINV_FP64) or floats (SPDINV_FP32); the lower triangle
+ *           of each is read and overwritten
  *   d_lda   device int[batch], leading dimensions (>= max(1, n_i))
+ *   mode    SPDINV_FP64 or SPDINV_FP32 (FP32 tiles and matrix cores,
+ *           binary64 diagonal tiles and small matrices, rounded to FP32)
  *   work    device workspace of batched_spd_inverse_workspace_bytes bytes
- *   opts    host or NULL: renamed, loop_order, trtri_first select the tile
- *           plan; fill_upper mirrors each result; workers caps the grid
+ *           (each matrix of tile count t >= 2 has its own pool of 3T + 2t
+ *           tiles, T = t(t+1)/2: about 20 GB in FP64 for 8192 orders uniform
+ *           on 16..512)
+ *   opts    host or NULL: renamed, loop_order, trtri_first and chain select
+ *           the tile plan (FP32: renamed only, chain 1); batch_group the
+ *           interleaving; fill_upper mirrors each result; workers caps the
+ *           grid
  *   d_info  device int[batch] or NULL: INFO of each matrix (0, k > 0 as for
- *           spd_inverse, or -1 when its d_n/d_lda entry is invalid on the
- *           device or exceeds the orders given in h_n)
+ *           spd_inverse, or -1 when its d_n/d_lda/d_A entry is invalid on the
+ *           device or its order is not of the tile count given in h_n)
  * Returns 0, -i for an invalid i-th argument, SPDINV_ERR_WORKSPACE or
- * SPDINV_ERR_HIP.  The launch is asynchronous.  It allocates nothing once the
- * tile plans for the tile counts present have been built by an earlier call,
- * so such a call can be captured in a HIP graph.  The matrices must not
- * overlap.
+ * SPDINV_ERR_HIP.  The launch is asynchronous.  The first call for a new set
+ * of tile counts (per matrix) builds and uploads its task lists into a
+ * library-owned device arena; a later call with the same tile counts
+ * allocates nothing and can be captured in a HIP graph.  The matrices must
+ * not overlap.
  */
-int batched_spd_inverse(int batch, const int* h_n, const int* d_n, double* const* d_A,
+int batched_spd_inverse(int batch, const int* h_n, const int* d_n, void* const* d_A,
                         const int* d_lda, spdinv_mode mode, void* work, size_t work_bytes,
                         spdinv_stream_t stream, const spdinv_opts* opts, int* d_info);
 
@@ -387,6 +419,31 @@ int spdinv_plan_export_steps(int steps, int rhs_tiles, int t, const spdinv_opts*
                              int workers, int32_t* tasks8, int32_t* succ, int32_t* step,
                              int32_t* idx, int32_t* order, long long* ntasks, long long* nsucc,
                              int32_t* links, long long* nlinks);
+
+/*
+ * The batched form's task list for one matrix of t tiles per side (1 <= t <=
+ * 16; t = 1 is the single small-matrix task): per position (the device id)
+ * the 8 int32 fields of spdinv_plan_export, with the kinds 16 (copy-in:
+ * lower triangle to the matrix's tiles), 17 (copy-out, writes INFO) and 18
+ * (a matrix of order <= 128 inverted in LDS) besides the plan's; successors
+ * are positions; links as for spdinv_plan_export.  Position 0 is the copy-in
+ * task and the last position the copy-out task.  NULL buffers query the
+ * sizes.  Returns 0, or a negative value for an invalid t, mode or opts.
+ */
+int spdinv_batch_template_export(int t, spdinv_mode mode, const spdinv_opts* opts,
+                                 int32_t* tasks8, int32_t* succ, int32_t* links, long long* ntask,
+                                 long long* nsucc, long long* nlinks);
+/*
+ * The batched form's dispatch order for the orders h_n (as batched_spd_inverse
+ * builds it for a launch of `workers` workgroups): per ticket
+ * (matrix << 12) | template position, and per matrix 4 int32 (its template
+ * tile count, first counter index, first pool tile, 0).  NULL buffers query
+ * the size.  Returns the number of tickets, or a negative value for invalid
+ * arguments.
+ */
+long long spdinv_batch_plan_export(int batch, const int* h_n, spdinv_mode mode,
+                                   const spdinv_opts* opts, int workers, int32_t* disp,
+                                   int32_t* mat4);
 
 /* ---- per-task trace (opts.trace = 1) -------------------------------------- */
 /* Copies the per-task trace that the last spd_inverse call with

@@ -46,8 +46,13 @@ def _stream_ptr(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
 
-MODES = {"fp64": _lib.SPDINV_FP64, "mixed_fp32": _lib.SPDINV_MIXED_FP32,
+MODES = {"fp64": _lib.SPDINV_FP64, "fp32": _lib.SPDINV_FP32, "mixed_fp32": _lib.SPDINV_MIXED_FP32,
          "mixed_bf16": _lib.SPDINV_MIXED_BF16}
+
+
+def _dtype_of(mode: str):
+    import torch
+    return torch.float32 if mode == "fp32" else torch.float64
 
 
 def _mode(mode) -> int:
@@ -64,7 +69,8 @@ def workspace_bytes(n: int, mode: str = "fp64", **opts) -> int:
 
 def spd_inverse_(a_cm, *, mode: str = "fp64", work=None, report: bool = False, info=None,
                  **opts):
-    """A <- A^{-1} in place on a column-major CUDA float64 view.
+    """A <- A^{-1} in place on a column-major CUDA view (float64; float32 for
+    mode "fp32").
 
     ``a_cm`` must have strides (1, ld) with ld >= n (e.g. ``x.t()`` of a
     row-major tensor).  Its lower triangle in column-major indexing, i.e.
@@ -73,13 +79,16 @@ def spd_inverse_(a_cm, *, mode: str = "fp64", work=None, report: bool = False, i
     ``info`` may be a CUDA int32 tensor of one element receiving INFO.  With
     ``report=True`` the call synchronises and returns the library report as a
     dict (raising NotPositiveDefinite on INFO > 0).  ``mode`` is "fp64",
-    "mixed_fp32" (FP32 tile DAG + binary64 Newton-Schulz refinement; the
-    report then carries refine_iters, fell_back and the relative residuals)
-    or "mixed_bf16" (the same with bfloat16 operands in the tile products).
+    "fp32" (FP32 storage and tile products, binary64 diagonal tiles, no
+    refinement), "mixed_fp32" (FP32 tile DAG + binary64 Newton-Schulz
+    refinement; the report then carries refine_iters, fell_back and the
+    relative residuals) or "mixed_bf16" (the same with bfloat16 operands in
+    the tile products).
     """
     import torch
-    if a_cm.dtype != torch.float64 or not a_cm.is_cuda or a_cm.dim() != 2:
-        raise TypeError("expected a 2-D CUDA float64 tensor")
+    want = _dtype_of(mode)
+    if a_cm.dtype != want or not a_cm.is_cuda or a_cm.dim() != 2:
+        raise TypeError(f"expected a 2-D CUDA {want} tensor")
     n = a_cm.shape[0]
     if a_cm.shape[1] != n:
         raise ValueError("matrix must be square")
@@ -280,7 +289,8 @@ def solve_from_factor(l, b, return_report: bool = False, **opts):
 
 
 def spd_inverse(a, mode: str = "fp64", return_report: bool = False, **opts):
-    """Full symmetric A^{-1} of a CUDA float64 tensor (lower triangle read)."""
+    """Full symmetric A^{-1} of a CUDA float64 tensor (float32 for mode
+    "fp32"); the lower triangle is read."""
     import torch
     n = a.shape[-1]
     buf = a.t().contiguous()          # column-major storage of a: lower triangle = a's lower
@@ -294,25 +304,33 @@ def _int_array(values):
     return arr
 
 
-def batched_workspace_bytes(orders, **opts) -> int:
+def batched_workspace_bytes(orders, mode: str = "fp64", **opts) -> int:
     o = make_opts(**opts)
     arr = _int_array(orders)
-    return int(load().batched_spd_inverse_workspace_bytes(len(orders), arr, _lib.SPDINV_FP64,
+    return int(load().batched_spd_inverse_workspace_bytes(len(orders), arr, _batched_mode(mode),
                                                           ctypes.byref(o)))
 
 
-def batched_spd_inverse_(ptrs, orders, n_dev, lda_dev, *, work=None, info=None, **opts):
+def _batched_mode(mode: str) -> int:
+    if mode not in ("fp64", "fp32"):
+        raise ValueError("batched mode must be 'fp64' or 'fp32'")
+    return MODES[mode]
+
+
+def batched_spd_inverse_(ptrs, orders, n_dev, lda_dev, *, mode: str = "fp64", work=None,
+                         info=None, **opts):
     """Low-level batched call: ``ptrs`` a CUDA int64 tensor of device pointers
-    to column-major matrices, ``orders`` the host list of orders, ``n_dev`` and
-    ``lda_dev`` CUDA int32 tensors, ``info`` an optional CUDA int32 tensor of
-    the batch size.  Asynchronous on the current stream; returns ``work``."""
+    to column-major matrices (float64, or float32 for mode "fp32"),
+    ``orders`` the host list of orders, ``n_dev`` and ``lda_dev`` CUDA int32
+    tensors, ``info`` an optional CUDA int32 tensor of the batch size.
+    Asynchronous on the current stream; returns ``work``."""
     import torch
     batch = len(orders)
     lib = load()
     o = make_opts(**opts)
+    m = _batched_mode(mode)
     h_n = _int_array(orders)
-    need = int(lib.batched_spd_inverse_workspace_bytes(batch, h_n, _lib.SPDINV_FP64,
-                                                       ctypes.byref(o)))
+    need = int(lib.batched_spd_inverse_workspace_bytes(batch, h_n, m, ctypes.byref(o)))
     if batch and need == 0:
         raise ValueError("invalid orders (0 <= n <= 2048) or no device")
     dev = ptrs.device
@@ -321,7 +339,7 @@ def batched_spd_inverse_(ptrs, orders, n_dev, lda_dev, *, work=None, info=None, 
     elif work.numel() * work.element_size() < need:
         raise ValueError(f"workspace too small: need {need} bytes")
     rc = lib.batched_spd_inverse(batch, h_n, n_dev.data_ptr(), ptrs.data_ptr(), lda_dev.data_ptr(),
-                                 _lib.SPDINV_FP64, work.data_ptr(), need, _stream_ptr(dev),
+                                 m, work.data_ptr(), need, _stream_ptr(dev),
                                  ctypes.byref(o), info.data_ptr() if info is not None else None)
     if rc != 0:
         raise SpdInverseError(f"batched_spd_inverse returned {rc}")
@@ -329,28 +347,34 @@ def batched_spd_inverse_(ptrs, orders, n_dev, lda_dev, *, work=None, info=None, 
 
 
 def batched_spd_inverse(mats, **opts):
-    """Full symmetric inverses of a list of square CUDA float64 tensors (the
-    lower triangle of each is read), computed in one batched launch.  Raises
-    NotPositiveDefinite for the first matrix whose INFO is positive."""
+    """Full symmetric inverses of a list of square CUDA tensors, all float64
+    (mode "fp64") or all float32 (mode "fp32"); the lower triangle of each is
+    read; computed in one batched launch.  Raises NotPositiveDefinite for the
+    first matrix whose INFO is positive."""
     import torch
     if not mats:
         return []
     dev = mats[0].device
+    dtype = mats[0].dtype
+    if dtype not in (torch.float64, torch.float32) or any(m.dtype != dtype for m in mats):
+        raise TypeError("expected CUDA tensors, all float64 or all float32")
+    mode = "fp64" if dtype == torch.float64 else "fp32"
+    esize = 8 if mode == "fp64" else 4
     orders = [int(m.shape[0]) for m in mats]
     sizes = [max(1, n) * max(1, n) for n in orders]
     offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
-    buf = torch.empty(int(offs[-1]), dtype=torch.float64, device=dev)
+    buf = torch.empty(int(offs[-1]), dtype=dtype, device=dev)
     for m, n, off in zip(mats, orders, offs[:-1]):
         if n:
             # column-major storage of m: its lower triangle is m's lower triangle
             buf[int(off):int(off) + n * n].view(n, n).copy_(m.t())
     base = buf.data_ptr()
-    ptrs = torch.tensor([base + 8 * int(o) for o in offs[:-1]], dtype=torch.int64, device=dev)
+    ptrs = torch.tensor([base + esize * int(o) for o in offs[:-1]], dtype=torch.int64, device=dev)
     n_dev = torch.tensor(orders, dtype=torch.int32, device=dev)
     lda_dev = torch.tensor([max(1, n) for n in orders], dtype=torch.int32, device=dev)
     info = torch.zeros(len(mats), dtype=torch.int32, device=dev)
     opts.setdefault("fill_upper", 1)
-    batched_spd_inverse_(ptrs, orders, n_dev, lda_dev, info=info, **opts)
+    batched_spd_inverse_(ptrs, orders, n_dev, lda_dev, mode=mode, info=info, **opts)
     inf = info.cpu().numpy()
     bad = np.nonzero(inf != 0)[0]
     if len(bad):
@@ -361,7 +385,7 @@ def batched_spd_inverse(mats, **opts):
     out = []
     for n, off in zip(orders, offs[:-1]):
         out.append(buf[int(off):int(off) + n * n].view(n, n).t() if n else
-                   torch.empty((0, 0), dtype=torch.float64, device=dev))
+                   torch.empty((0, 0), dtype=dtype, device=dev))
     return out
 
 
@@ -489,6 +513,46 @@ def plan_export(t: int, workers: int = 1, steps: int = 7, rhs_tiles: int = 0, **
                                  None, p(links), None)
     return {"tasks": tasks, "succ": succ[:ns.value], "step": step, "idx": idx, "order": order,
             "links": links[:nl.value].reshape(-1, 2), "t": int(t), "T": t * (t + 1) // 2}
+
+
+def batch_template_export(t: int, mode: str = "fp64", **opts) -> dict:
+    """The batched form's task list for a matrix of t tiles per side:
+    tasks (ntask x 8 int32; position 0 the copy-in task, the last the
+    copy-out task), succ (positions) and links (nlinks x 2)."""
+    lib = load()
+    o = make_opts(**opts)
+    nt, ns, nl = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_longlong()
+    m = _batched_mode(mode)
+    if lib.spdinv_batch_template_export(int(t), m, ctypes.byref(o), None, None, None,
+                                        ctypes.byref(nt), ctypes.byref(ns), ctypes.byref(nl)):
+        raise ValueError("invalid tile count, mode or options")
+    tasks = np.zeros((nt.value, 8), dtype=np.int32)
+    succ = np.zeros(max(ns.value, 1), dtype=np.int32)
+    links = np.zeros((max(nl.value, 1), 2), dtype=np.int32)
+    p = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
+    lib.spdinv_batch_template_export(int(t), m, ctypes.byref(o), p(tasks), p(succ), p(links),
+                                     None, None, None)
+    return {"tasks": tasks, "succ": succ[:ns.value], "links": links[:nl.value], "t": int(t)}
+
+
+def batch_plan_export(orders, mode: str = "fp64", workers: int = 512, **opts) -> dict:
+    """The batched form's dispatch list for these orders: disp (tickets, each
+    (matrix << 12) | position) and mat (batch x 4 int32: template tile count,
+    first counter, first pool tile, 0)."""
+    lib = load()
+    o = make_opts(**opts)
+    h_n = _int_array(orders)
+    m = _batched_mode(mode)
+    nt = lib.spdinv_batch_plan_export(len(orders), h_n, m, ctypes.byref(o), int(workers), None,
+                                      None)
+    if nt < 0:
+        raise ValueError("invalid orders, mode or options")
+    disp = np.zeros(nt, dtype=np.int32)
+    mat = np.zeros((len(orders), 4), dtype=np.int32)
+    p = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
+    lib.spdinv_batch_plan_export(len(orders), h_n, m, ctypes.byref(o), int(workers), p(disp),
+                                 p(mat))
+    return {"disp": disp, "mat": mat}
 
 
 def trace(work, n: int, **opts) -> np.ndarray:

@@ -34,7 +34,7 @@ class Opts(ctypes.Structure):
                 ("workers", ctypes.c_int), ("fill_upper", ctypes.c_int), ("trace", ctypes.c_int),
                 ("max_refine", ctypes.c_int), ("refine_tol", ctypes.c_double),
                 ("chain", ctypes.c_int), ("per_cu", ctypes.c_int), ("no_split", ctypes.c_int),
-                ("parts", ctypes.c_int)]
+                ("parts", ctypes.c_int), ("batch_group", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -113,6 +113,12 @@ def load():
     lib.spd_inverse_backward_workspace_bytes.restype = sz
     lib.spd_inverse_backward.argtypes = [i, vp, i, vp, i, vp, i, vp, sz, vp]
     lib.spd_inverse_backward.restype = i
+    ll = ctypes.c_longlong
+    lib.spdinv_batch_template_export.argtypes = [i, i, P(Opts), i32p, i32p, i32p, P(ll), P(ll),
+                                                 P(ll)]
+    lib.spdinv_batch_template_export.restype = i
+    lib.spdinv_batch_plan_export.argtypes = [i, ip, i, P(Opts), i, i32p, i32p]
+    lib.spdinv_batch_plan_export.restype = ll
     lib.spd_inverse_noalloc.argtypes = [i, vp, i, vp, P(Opts), vp]
     lib.spd_inverse_noalloc.restype = i
     lib.spdinv_version.argtypes = []

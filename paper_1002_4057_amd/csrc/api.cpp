@@ -10,6 +10,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <queue>
 #include <tuple>
 #include <vector>
 
@@ -104,6 +105,7 @@ spdinv_opts defaults() {
   o.per_cu = 0;
   o.no_split = 0;
   o.parts = 0;
+  o.batch_group = 0;
   return o;
 }
 
@@ -146,6 +148,7 @@ int check_opts(const spdinv_opts& o) {
   if (o.per_cu < 0 || o.per_cu > 2) return 1;
   if (o.no_split < 0 || o.no_split > 1) return 1;
   if (o.parts != 0 && o.parts != 2 && o.parts != 4) return 1;
+  if (o.batch_group < -2) return 1;
   return 0;
 }
 
@@ -412,18 +415,445 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
 
 namespace {
 
-struct BatchLayout {
-  size_t order, ctrl, pool, total;
-  int grid, tmax, maxn;
-  long long pool_tiles;
+// ---- batched form: one DAG over the batch ---------------------------------
+// Task template of one matrix of t tiles per side: the plan of Algorithm 1
+// in dispatch order, preceded by its copy-in task (an edge to every task
+// without predecessors) and followed by its copy-out task (an edge from every
+// task without successors); for t = 1 a single small-matrix task.  Positions
+// in the template are the device ids; successors are positions.  The host
+// part (image, durations, bottom levels) is built once per variant; its
+// device copy once per device.
+struct BTemplate {
+  int ntask = 0;
+  PlanImage image;
+  std::vector<double> cost;     // estimated duration per position (product units)
+  std::vector<double> bottom;   // longest cost path from each position to the end
+  std::vector<int32_t> succ;    // successors (positions), CSR by the tasks' fields
+  std::vector<DevTask> tasks;   // host copy of the tasks
+  std::vector<int32_t> indeg0;  // initial in-degrees
+  std::vector<int32_t> links;   // chained-product links
 };
 
-int batched_grid(int device, const spdinv_opts& o) {
-  static std::map<int, int> grids;
+struct BTemplateDev {
+  const BTemplate* h = nullptr;
+  void* arena = nullptr;
+  const DevTask* d_tasks = nullptr;
+  const int32_t* d_succ = nullptr;
+  const int32_t* d_indeg0 = nullptr;
+  const int32_t* d_links = nullptr;
+};
+
+void make_btemplate(const Plan* p, BTemplate* bt) {
+  std::vector<DevTask> tasks;
+  std::vector<std::vector<int32_t>> succ;
+  std::vector<int32_t> indeg;
+  auto special = [](int32_t kind) { return DevTask{kind, -1, -1, -1, -1, -1, 0, 0}; };
+  if (!p) {
+    tasks.push_back(special(K_BSMALL));
+    succ.resize(1);
+    indeg.assign(1, 0);
+  } else {
+    const int nt = (int)p->tasks.size(), N = nt + 2;
+    std::vector<int32_t> pos(nt);
+    for (int k = 0; k < nt; ++k) pos[p->order[k]] = k + 1;
+    tasks.assign(N, special(K_NOP));
+    succ.resize(N);
+    indeg.assign(N, 0);
+    tasks[0] = special(K_BCOPYIN);
+    tasks[N - 1] = special(K_BCOPYOUT);
+    for (int k = 0; k < nt; ++k) {
+      const int v = p->order[k];
+      const DevTask& d = p->tasks[v];
+      tasks[k + 1] = d;
+      for (int e = d.succ_begin; e < d.succ_end; ++e) succ[k + 1].push_back(pos[p->succ[e]]);
+      indeg[k + 1] = p->indeg[v];
+      if (p->indeg[v] == 0) {
+        succ[0].push_back(k + 1);
+        ++indeg[k + 1];
+      }
+      if (d.succ_begin == d.succ_end) {
+        succ[k + 1].push_back(N - 1);
+        ++indeg[N - 1];
+      }
+    }
+    bt->links = p->links;
+  }
+  const int N = (int)tasks.size();
+  bt->succ.clear();
+  for (int k = 0; k < N; ++k) {
+    tasks[k].succ_begin = (int32_t)bt->succ.size();
+    bt->succ.insert(bt->succ.end(), succ[k].begin(), succ[k].end());
+    tasks[k].succ_end = (int32_t)bt->succ.size();
+  }
+  bt->tasks = tasks;
+  bt->indeg0 = indeg;
+  bt->ntask = N;
+  PlanImage* im = &bt->image;
+  const size_t nl = bt->links.size();
+  im->o_tasks = 0;
+  im->o_succ = align_up(N * sizeof(DevTask), 256);
+  im->o_indeg = align_up(im->o_succ + bt->succ.size() * sizeof(int32_t) + 4, 256);
+  im->o_links = align_up(im->o_indeg + N * sizeof(int32_t), 256);
+  im->bytes.assign(align_up(im->o_links + nl * sizeof(int32_t) + 4, 256), 0);
+  char* h = im->bytes.data();
+  std::memcpy(h + im->o_tasks, tasks.data(), N * sizeof(DevTask));
+  if (!bt->succ.empty())
+    std::memcpy(h + im->o_succ, bt->succ.data(), bt->succ.size() * sizeof(int32_t));
+  std::memcpy(h + im->o_indeg, indeg.data(), N * sizeof(int32_t));
+  if (nl) std::memcpy(h + im->o_links, bt->links.data(), nl * sizeof(int32_t));
+  im->has_links = nl > 0;
+}
+
+// Estimated durations of the template tasks (the planner's cost units: a
+// single 128^3 product is 1) and their bottom levels.  A copy task moves the
+// matrix's lower tiles (about 0.12 per tile); the small-matrix task costs
+// about what the diagonal-tile task costs.
+void btemplate_costs(BTemplate* bt, int t) {
+  const int N = bt->ntask;
+  bt->cost.assign(N, 0.0);
+  const double tiles = t * (t + 1) / 2.0;
+  for (int k = 0; k < N; ++k) {
+    const int32_t kind = bt->tasks[k].kind;
+    const int kd = kind & 0xff;
+    double c;
+    if (kd == K_BCOPYIN || kd == K_BCOPYOUT) c = 0.12 * tiles;
+    else if (kd == K_BSMALL) c = 2.5;
+    else if (kd < K_COUNT) c = kCost[kd] + kCost[K_COUNT] * task_links(kind);
+    else c = 1.0;
+    bt->cost[k] = c;
+  }
+  bt->bottom.assign(N, 0.0);
+  for (int k = N - 1; k >= 0; --k) {  // positions are topological
+    double b = 0.0;
+    for (int e = bt->tasks[k].succ_begin; e < bt->tasks[k].succ_end; ++e)
+      b = std::max(b, bt->bottom[bt->succ[e]]);
+    bt->bottom[k] = b + bt->cost[k];
+  }
+}
+
+int btemplate_chain(const spdinv_opts& o, bool fp32) { return fp32 ? 1 : chain_for(o); }
+
+// Device tasks of the template of t at most (without building it).
+long long btemplate_bound(int t) { return t <= 1 ? 1 : task_count(t) + 2; }
+
+// Template key: template tile count, FP32, chain, renamed, loop order,
+// TRTRI(j) placement.
+typedef std::tuple<int, int, int, int, int, int> BTKey;
+std::map<BTKey, std::unique_ptr<BTemplate>> g_btmpl;
+std::map<std::pair<int, BTKey>, std::unique_ptr<BTemplateDev>> g_btmpl_dev;
+
+// Host template (built once per variant).  Called with g_mu held.
+const BTemplate* btemplate_host(int t, bool fp32, const spdinv_opts& o) {
+  const BTKey k{t, fp32 ? 1 : 0, btemplate_chain(o, fp32), o.renamed ? 1 : 0, o.loop_order,
+                o.trtri_first ? 1 : 0};
+  auto it = g_btmpl.find(k);
+  if (it != g_btmpl.end()) return it->second.get();
+  std::unique_ptr<BTemplate> bt(new BTemplate);
+  if (t <= 1) {
+    make_btemplate(nullptr, bt.get());
+  } else {
+    PlanOptions po;
+    po.t = t;
+    po.renamed = o.renamed ? 1 : 0;
+    po.loop_order = o.loop_order;
+    po.pipelined = 1;
+    po.trtri_first = o.trtri_first ? 1 : 0;
+    po.chain = btemplate_chain(o, fp32);
+    Plan p;
+    // one worker: the list-scheduling order is a priority order of the
+    // matrix's tasks, and chains form wherever the contraction rules allow
+    // (the other matrices of the batch keep the workers busy)
+    build_plan(po, 1, kCost, &p);
+    make_btemplate(&p, bt.get());
+  }
+  btemplate_costs(bt.get(), t);
+  const BTemplate* raw = bt.get();
+  g_btmpl[k] = std::move(bt);
+  return raw;
+}
+
+BTemplateDev* get_btemplate(int device, int t, bool fp32, const spdinv_opts& o, hipError_t* err) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  const BTemplate* h = btemplate_host(t, fp32, o);
+  const BTKey k{t, fp32 ? 1 : 0, btemplate_chain(o, fp32), o.renamed ? 1 : 0, o.loop_order,
+                o.trtri_first ? 1 : 0};
+  auto it = g_btmpl_dev.find({device, k});
+  if (it != g_btmpl_dev.end()) return it->second.get();
+  if (h->ntask > BT_MASK + 1) {
+    *err = hipErrorInvalidValue;
+    return nullptr;
+  }
+  std::unique_ptr<BTemplateDev> bd(new BTemplateDev);
+  bd->h = h;
+  void* arena = nullptr;
+  *err = hipMalloc(&arena, h->image.bytes.size());
+  if (*err != hipSuccess) return nullptr;
+  *err = hipMemcpy(arena, h->image.bytes.data(), h->image.bytes.size(), hipMemcpyHostToDevice);
+  if (*err != hipSuccess) {
+    (void)hipFree(arena);
+    return nullptr;
+  }
+  char* base = (char*)arena;
+  bd->arena = arena;
+  bd->d_tasks = (const DevTask*)(base + h->image.o_tasks);
+  bd->d_succ = (const int32_t*)(base + h->image.o_succ);
+  bd->d_indeg0 = (const int32_t*)(base + h->image.o_indeg);
+  bd->d_links = h->image.has_links ? (const int32_t*)(base + h->image.o_links) : nullptr;
+  BTemplateDev* raw = bd.get();
+  g_btmpl_dev[{device, k}] = std::move(bd);
+  return raw;
+}
+
+int tiles_of_order(int n) { return n <= NB ? 1 : (n + NB - 1) / NB; }
+
+// Dispatch order by a list-scheduling simulation of the whole batch on
+// `workers` workers with the templates' estimated durations: whenever a
+// worker is free it starts the ready task of the earliest matrix in `order`
+// (the longest matrices first), the task with the longest path to its
+// matrix's end first.  The order of the simulated starts is topological.
+// Pool slots: a matrix of t >= 2 tiles takes a free slot of its tile count
+// when its copy-in task starts and frees it when its copy-out task ends;
+// slot[m] receives the slot, prev[m] the slot's previous occupant (or -1),
+// nslots[t] the slots of each tile count.
+void batch_list_schedule(const std::vector<int>& order, const std::vector<int8_t>& tv,
+                         const BTemplate* const* tmpl, const std::vector<int4>& mat, int workers,
+                         std::vector<int32_t>* disp, std::vector<int>* slot,
+                         std::vector<int>* prev, std::vector<int>* nslots) {
+  const int batch = (int)tv.size();
+  std::vector<int> rank(batch);
+  for (int r = 0; r < (int)order.size(); ++r) rank[order[r]] = r;
+  long long total = 0;
+  for (int m = 0; m < batch; ++m) total += tmpl[tv[m]]->ntask;
+  std::vector<int32_t> left((size_t)total);
+  for (int m = 0; m < batch; ++m) {
+    const BTemplate* bt = tmpl[tv[m]];
+    std::copy(bt->indeg0.begin(), bt->indeg0.end(), left.begin() + mat[m].y);
+  }
+  struct Ready {
+    int rank;
+    double bottom;
+    int m, pos;
+    bool operator<(const Ready& o) const {  // priority_queue: top is the largest
+      if (rank != o.rank) return rank > o.rank;
+      if (bottom != o.bottom) return bottom < o.bottom;
+      return pos > o.pos;
+    }
+  };
+  struct Done {
+    double time;
+    int m, pos;
+    bool operator<(const Done& o) const { return time > o.time; }
+  };
+  std::priority_queue<Ready> ready;
+  std::priority_queue<Done> running;
+  for (int m = 0; m < batch; ++m) ready.push(Ready{rank[m], tmpl[tv[m]]->bottom[0], m, 0});
+  slot->assign(batch, -1);
+  prev->assign(batch, -1);
+  nslots->assign(MAX_BATCH_T + 1, 0);
+  std::vector<std::vector<int>> free_slots(MAX_BATCH_T + 1);
+  std::vector<std::vector<int>> last(MAX_BATCH_T + 1);  // last occupant of each slot
+  int free_workers = std::max(1, workers);
+  double now = 0.0;
+  while (!ready.empty() || !running.empty()) {
+    while (free_workers > 0 && !ready.empty()) {
+      const Ready r = ready.top();
+      ready.pop();
+      const int t = tv[r.m];
+      if (r.pos == 0 && t >= 2) {  // copy-in: take a pool slot
+        int sl;
+        if (!free_slots[t].empty()) {
+          sl = free_slots[t].back();
+          free_slots[t].pop_back();
+        } else {
+          sl = (*nslots)[t]++;
+          last[t].push_back(-1);
+        }
+        (*slot)[r.m] = sl;
+        (*prev)[r.m] = last[t][sl];
+        last[t][sl] = r.m;
+      }
+      disp->push_back((r.m << BT_SHIFT) | r.pos);
+      running.push(Done{now + tmpl[t]->cost[r.pos], r.m, r.pos});
+      --free_workers;
+    }
+    const Done d = running.top();
+    running.pop();
+    now = d.time;
+    ++free_workers;
+    const BTemplate* bt = tmpl[tv[d.m]];
+    if (tv[d.m] >= 2 && d.pos == bt->ntask - 1) free_slots[tv[d.m]].push_back((*slot)[d.m]);
+    const DevTask& task = bt->tasks[d.pos];
+    for (int e = task.succ_begin; e < task.succ_end; ++e) {
+      const int q = bt->succ[e];
+      if (--left[(size_t)mat[d.m].y + q] == 0) ready.push(Ready{rank[d.m], bt->bottom[q], d.m, q});
+    }
+  }
+}
+
+// Composition of a batch (host): per matrix its template, first counter and
+// first pool tile; the dispatch list.  The matrices are ranked by decreasing
+// tile count (the longest first, stable).  group > 0: the templates are
+// interleaved position by position in groups of `group` matrices; group < 0:
+// one ticket per matrix, run whole by one of `workers` workgroups; else the
+// list-scheduling order on `workers` workers.  Returns 0 or -1 when the
+// counters or pool tiles overflow int32.
+struct BCompHost {
+  std::vector<int32_t> disp;
+  std::vector<int4> mat;
+  long long ncnt = 0;
+  long long pool_tiles = 0;
+  long long wg_pool_tiles = 0;  // one workgroup per matrix: pool tiles per workgroup
+};
+
+int build_bcomp(const std::vector<int8_t>& tv, const BTemplate* const* tmpl, int group,
+                int workers, BCompHost* out) {
+  const int batch = (int)tv.size();
+  std::vector<int> order;
+  order.reserve(batch);
+  for (int t = MAX_BATCH_T; t >= 1; --t)
+    for (int i = 0; i < batch; ++i)
+      if (tv[i] == t) order.push_back(i);
+  out->mat.assign(batch, make_int4(0, 0, 0, -1));
+  long long cnt = 0, ptile = 0;
+  for (int m : order) {
+    const int t = tv[m];
+    out->mat[m] = make_int4(t, (int)cnt, (int)ptile, -1);
+    cnt += tmpl[t]->ntask;
+    if (t >= 2) ptile += pool_tiles(t);
+    if (cnt > INT_MAX || ptile > INT_MAX) return -1;
+  }
+  out->ncnt = cnt;
+  out->pool_tiles = ptile;
+  out->disp.clear();
+  out->disp.reserve((size_t)cnt);
+  if (group == -1) {  // one workgroup per matrix: a ticket per matrix, pools per workgroup
+    int tmax = 1;
+    for (int m : order) {
+      out->disp.push_back(m << BT_SHIFT);
+      tmax = std::max(tmax, (int)tv[m]);
+    }
+    out->ncnt = 0;
+    out->pool_tiles = tmax >= 2 ? (long long)workers * pool_tiles(tmax) : 0;
+    out->wg_pool_tiles = tmax >= 2 ? pool_tiles(tmax) : 0;
+    return 0;
+  }
+  if (group > 0) {  // every matrix keeps its own pool
+    for (size_t g0 = 0; g0 < order.size(); g0 += group) {
+      const size_t g1 = std::min(order.size(), g0 + (size_t)group);
+      int longest = 0;
+      for (size_t q = g0; q < g1; ++q) longest = std::max(longest, tmpl[tv[order[q]]]->ntask);
+      for (int pos = 0; pos < longest; ++pos)
+        for (size_t q = g0; q < g1; ++q)
+          if (pos < tmpl[tv[order[q]]]->ntask) out->disp.push_back((order[q] << BT_SHIFT) | pos);
+    }
+    return 0;
+  }
+  std::vector<int> slot, prev, nslots;
+  batch_list_schedule(order, tv, tmpl, out->mat, workers, &out->disp, &slot, &prev, &nslots);
+  // pool: the slots of each tile count, largest tile count first
+  std::vector<long long> slot_base(MAX_BATCH_T + 1, 0);
+  ptile = 0;
+  for (int t = MAX_BATCH_T; t >= 2; --t) {
+    slot_base[t] = ptile;
+    ptile += (long long)nslots[t] * pool_tiles(t);
+  }
+  if (ptile > INT_MAX) return -1;
+  out->pool_tiles = ptile;
+  for (int m = 0; m < batch; ++m) {
+    const int t = tv[m];
+    if (t < 2) continue;
+    out->mat[m].z = (int)(slot_base[t] + (long long)slot[m] * pool_tiles(t));
+    if (prev[m] >= 0) {
+      out->mat[m].x |= BM_PREV;
+      out->mat[prev[m]].w = out->mat[m].y;  // copy-in of m is position 0
+    }
+  }
+  return 0;
+}
+
+// Host compositions, cached per (precision, template variant, dispatch rule
+// with its worker count, tile counts of the batch).
+typedef std::tuple<int, int, int, int, int, int, std::vector<int8_t>> BHKey;
+std::map<BHKey, std::unique_ptr<BCompHost>> g_bcomp_host;
+
+// The batched schedule the library picks when opts.batch_group is 0: one
+// workgroup per matrix when the batch has at least two matrices per worker
+// (every worker then runs whole matrices, no dependency waits), else the
+// list-scheduled DAG (a few large matrices spread over every worker).
+// Measured on 8192 orders uniform on 16..512 (FP64): one workgroup per
+// matrix 20.7 ms, the list-scheduled DAG 26.3 ms, groups of 512 23.5 ms.
+int batch_schedule(int batch, const spdinv_opts& o, int workers) {
+  if (o.batch_group != 0) return o.batch_group;
+  return batch >= 2 * workers ? -1 : -2;
+}
+
+// Called with g_mu held.  Returns null when the composition overflows.
+const BCompHost* bcomp_host(const std::vector<int8_t>& tv, bool fp32, const spdinv_opts& o,
+                            int workers) {
+  const int group = batch_schedule((int)tv.size(), o, workers);
+  const BHKey k{fp32 ? 1 : 0, btemplate_chain(o, fp32),
+                group > 0 ? group : (group == -1 ? -(1 << 30) - workers : -workers),
+                o.renamed ? 1 : 0, o.loop_order, o.trtri_first ? 1 : 0, tv};
+  auto it = g_bcomp_host.find(k);
+  if (it != g_bcomp_host.end()) return it->second.get();
+  const BTemplate* tmpl[MAX_BATCH_T + 1] = {};
+  for (size_t i = 0; i < tv.size(); ++i)
+    if (!tmpl[tv[i]]) tmpl[tv[i]] = btemplate_host(tv[i], fp32, o);
+  std::unique_ptr<BCompHost> hc(new BCompHost);
+  if (build_bcomp(tv, tmpl, group, workers, hc.get())) return nullptr;
+  const BCompHost* raw = hc.get();
+  g_bcomp_host[k] = std::move(hc);
+  return raw;
+}
+
+// Device copy of a composition, cached per (device, precision, template
+// variant, dispatch rule, tile counts of the batch).
+struct BComp {
+  void* arena = nullptr;
+  const int32_t* d_disp = nullptr;
+  const int4* d_mat = nullptr;
+  int ntotal = 0;
+  long long ncnt = 0;
+  long long pool_tiles = 0;
+  long long wg_pool_tiles = 0;
+};
+typedef std::tuple<int, int, int, int, int, int, int, std::vector<int8_t>> BCKey;
+std::map<BCKey, std::unique_ptr<BComp>> g_bcomp;
+
+struct BLayout {
+  size_t ctrl, mctrl, indeg, pool, total;
+};
+
+BLayout blayout(int batch, long long ncnt, long long pool_tiles_total, bool fp32) {
+  BLayout L;
+  L.ctrl = 0;
+  L.mctrl = 256;
+  L.indeg = L.mctrl + align_up((size_t)batch * CTRL_WORDS * sizeof(int32_t), 256);
+  L.pool = L.indeg + align_up((size_t)ncnt * sizeof(int32_t), 256);
+  L.total = L.pool + (size_t)pool_tiles_total * NB * NB * (fp32 ? sizeof(float) : sizeof(double));
+  return L;
+}
+
+// Upper bound of the counters and the pool tiles of a batch, from its orders;
+// -2 when an order is out of range.
+int batch_bounds(int batch, const int* h_n, long long* ncnt, long long* ptiles) {
+  *ncnt = 0;
+  *ptiles = 0;
+  for (int i = 0; i < batch; ++i) {
+    if (h_n[i] < 0 || h_n[i] > MAX_BATCH_T * NB) return -2;
+    const int t = tiles_of_order(h_n[i]);
+    *ncnt += btemplate_bound(t);
+    if (t >= 2) *ptiles += pool_tiles(t);
+  }
+  return 0;
+}
+
+int batched_grid(int device, const spdinv_opts& o, bool fp32) {
+  static std::map<std::pair<int, int>, int> grids;
   int g;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = grids.find(device);
+    auto it = grids.find({device, fp32 ? 1 : 0});
     if (it != grids.end()) {
       g = it->second;
     } else {
@@ -431,30 +861,62 @@ int batched_grid(int device, const spdinv_opts& o) {
       if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
           cus <= 0)
         cus = 1;
-      g = cus * batched_blocks_per_cu();
-      grids[device] = g;
+      g = cus * (fp32 ? bsched32_blocks_per_cu() : bsched_blocks_per_cu());
+      grids[{device, fp32 ? 1 : 0}] = g;
     }
   }
   if (o.workers > 0 && o.workers < g) g = o.workers;
   return g;
 }
 
-// Returns 0, or -2 when an order is negative or above the supported maximum.
-int batch_layout(int batch, const int* h_n, int grid, BatchLayout* L) {
-  int maxn = 0;
-  for (int i = 0; i < batch; ++i) {
-    if (h_n[i] < 0 || h_n[i] > MAX_BATCH_T * NB) return -2;
-    if (h_n[i] > maxn) maxn = h_n[i];
+// Workers of the list-scheduling simulation: the caller's cap, else 512 (two
+// workgroups on each of the MI355X's 256 CUs).  A fixed count keeps the
+// dispatch order and the pool size (its slots) independent of the device;
+// any topological order is correct.
+constexpr int kBatchSimWorkers = 512;
+int batch_sim_workers(const spdinv_opts& o) { return o.workers > 0 ? o.workers : kBatchSimWorkers; }
+
+BComp* get_bcomp(int device, int batch, const int* h_n, bool fp32, const spdinv_opts& o,
+                 int workers, hipError_t* err) {
+  const int group = batch_schedule(batch, o, workers);
+  std::vector<int8_t> tv(batch);
+  for (int i = 0; i < batch; ++i) tv[i] = (int8_t)tiles_of_order(h_n[i]);
+  BCKey k{device, fp32 ? 1 : 0, btemplate_chain(o, fp32),
+          group > 0 ? group : (group == -1 ? -(1 << 30) - workers : -workers),
+          o.renamed ? 1 : 0, o.loop_order, o.trtri_first ? 1 : 0, tv};
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_bcomp.find(k);
+  if (it != g_bcomp.end()) return it->second.get();
+  const BCompHost* hp = bcomp_host(tv, fp32, o, workers);
+  if (!hp) {
+    *err = hipErrorInvalidValue;
+    return nullptr;
   }
-  L->maxn = maxn;
-  L->tmax = (maxn + NB - 1) / NB;
-  L->grid = grid;
-  L->pool_tiles = L->tmax >= 2 ? pool_tiles(L->tmax) : 0;
-  L->order = 256;  // [0, 256): dispatch ticket
-  L->ctrl = L->order + align_up((size_t)batch * sizeof(int32_t), 256);
-  L->pool = L->ctrl + align_up((size_t)grid * CTRL_WORDS * sizeof(int32_t), 256);
-  L->total = L->pool + (size_t)grid * (size_t)L->pool_tiles * NB * NB * sizeof(double);
-  return 0;
+  const BCompHost& hc = *hp;
+  std::unique_ptr<BComp> bc(new BComp);
+  const size_t o_mat = align_up(hc.disp.size() * sizeof(int32_t), 256);
+  const size_t bytes = align_up(o_mat + (size_t)batch * sizeof(int4), 256);
+  std::vector<char> img(bytes, 0);
+  std::memcpy(img.data(), hc.disp.data(), hc.disp.size() * sizeof(int32_t));
+  std::memcpy(img.data() + o_mat, hc.mat.data(), (size_t)batch * sizeof(int4));
+  void* arena = nullptr;
+  *err = hipMalloc(&arena, bytes);
+  if (*err != hipSuccess) return nullptr;
+  *err = hipMemcpy(arena, img.data(), bytes, hipMemcpyHostToDevice);
+  if (*err != hipSuccess) {
+    (void)hipFree(arena);
+    return nullptr;
+  }
+  bc->arena = arena;
+  bc->d_disp = (const int32_t*)arena;
+  bc->d_mat = (const int4*)((char*)arena + o_mat);
+  bc->ntotal = (int)hc.disp.size();
+  bc->ncnt = hc.ncnt;
+  bc->pool_tiles = hc.pool_tiles;
+  bc->wg_pool_tiles = hc.wg_pool_tiles;
+  BComp* raw = bc.get();
+  g_bcomp[k] = std::move(bc);
+  return raw;
 }
 
 }  // namespace
@@ -463,61 +925,85 @@ extern "C" {
 
 size_t batched_spd_inverse_workspace_bytes(int batch, const int* h_n, spdinv_mode mode,
                                            const spdinv_opts* opts) {
-  (void)mode;
-  if (batch <= 0 || !h_n) return 0;
+  if (batch <= 0 || batch > MAX_BATCH || !h_n) return 0;
+  if (mode != SPDINV_FP64 && mode != SPDINV_FP32) return 0;
   const spdinv_opts o = opts ? *opts : defaults();
-  int device = 0;
-  if (hipGetDevice(&device) != hipSuccess) return 0;
-  BatchLayout L;
-  if (batch_layout(batch, h_n, batched_grid(device, o), &L)) return 0;
-  return L.total;
+  if (check_opts(o)) return 0;
+  const bool fp32 = mode == SPDINV_FP32;
+  long long ncnt, ptiles;
+  if (batch_bounds(batch, h_n, &ncnt, &ptiles)) return 0;
+  const int workers = batch_sim_workers(o);
+  std::vector<int8_t> tv(batch);
+  for (int i = 0; i < batch; ++i) tv[i] = (int8_t)tiles_of_order(h_n[i]);
+  std::lock_guard<std::mutex> lk(g_mu);
+  const BCompHost* hc = bcomp_host(tv, fp32, o, workers);
+  if (!hc) return 0;
+  return blayout(batch, hc->ncnt, hc->pool_tiles, fp32).total;
 }
 
-int batched_spd_inverse(int batch, const int* h_n, const int* d_n, double* const* d_A,
+int batched_spd_inverse(int batch, const int* h_n, const int* d_n, void* const* d_A,
                         const int* d_lda, spdinv_mode mode, void* work, size_t work_bytes,
                         spdinv_stream_t stream_, const spdinv_opts* opts, int* d_info) {
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
-  if (batch < 0) return -1;
+  if (batch < 0 || batch > MAX_BATCH) return -1;
   if (batch == 0) return 0;
   if (!h_n) return -2;
   if (!d_n) return -3;
   if (!d_A) return -4;
   if (!d_lda) return -5;
-  if (mode != SPDINV_FP64) return -6;
+  if (mode != SPDINV_FP64 && mode != SPDINV_FP32) return -6;
+  const bool fp32 = mode == SPDINV_FP32;
   const spdinv_opts o = opts ? *opts : defaults();
-  if (check_opts(o)) return -10;
+  if (check_opts(o) || (fp32 && !o.renamed)) return -10;
+  long long ncnt_bound, ptiles;
+  if (batch_bounds(batch, h_n, &ncnt_bound, &ptiles)) return -2;
+  if (!work) return -7;
+  if (work_bytes < batched_spd_inverse_workspace_bytes(batch, h_n, mode, &o))
+    return SPDINV_ERR_WORKSPACE;
   int device = 0;
   if (hipGetDevice(&device) != hipSuccess) return SPDINV_ERR_HIP;
-  BatchLayout L;
-  if (batch_layout(batch, h_n, batched_grid(device, o), &L)) return -2;
-  if (!work) return -7;
-  if (work_bytes < L.total) return SPDINV_ERR_WORKSPACE;
 
-  BatchArgs b;
+  BSchedArgs b;
   std::memset(&b, 0, sizeof(b));
-  for (int t = 2; t <= L.tmax; ++t) {
+  BTemplateDev* tmpl[MAX_BATCH_T + 1] = {};
+  for (int i = 0; i < batch; ++i) {
+    const int t = tiles_of_order(h_n[i]);
+    if (tmpl[t]) continue;
     hipError_t err = hipSuccess;
-    // program-order execution by one workgroup: the plan's task list as built
-    DevPlan* dp = get_plan(device, t, o, 1, chain_for(o), &err);
-    if (!dp) return SPDINV_ERR_HIP;
-    b.plan[t] = dp->d_tasks;
-    b.plan_links[t] = dp->d_links;
-    b.plan_ntask[t] = (int)dp->host.tasks.size();
+    tmpl[t] = get_btemplate(device, t, fp32, o, &err);
+    if (!tmpl[t]) return SPDINV_ERR_HIP;
+    b.tmpl[t] = tmpl[t]->d_tasks;
+    b.tsucc[t] = tmpl[t]->d_succ;
+    b.tlinks[t] = tmpl[t]->d_links;
+    b.tindeg0[t] = tmpl[t]->d_indeg0;
   }
+  hipError_t err = hipSuccess;
+  const int grid = batched_grid(device, o, fp32);
+  BComp* bc = get_bcomp(device, batch, h_n, fp32, o, batch_sim_workers(o), &err);
+  if (!bc) return SPDINV_ERR_HIP;
+  const BLayout L = blayout(batch, bc->ncnt, bc->pool_tiles, fp32);
   char* w = (char*)work;
+  b.disp = bc->d_disp;
+  b.mat = bc->d_mat;
+  b.indeg = (int32_t*)(w + L.indeg);
+  b.ctrl = (int32_t*)(w + L.ctrl);
+  b.mctrl = (int32_t*)(w + L.mctrl);
+  b.pool = (void*)(w + L.pool);
   b.n = d_n;
   b.A = d_A;
   b.lda = d_lda;
   b.info = d_info;
-  b.order = (const int32_t*)(w + L.order);
-  b.batch = batch;
-  b.ticket = (int32_t*)w;
-  b.pool = (double*)(w + L.pool);
-  b.pool_tiles = L.pool_tiles;
-  b.ctrl = (int32_t*)(w + L.ctrl);
-  b.tmax = L.tmax;
+  b.ntotal = bc->ntotal;
   b.fill_upper = o.fill_upper ? 1 : 0;
-  if (launch_batched(b, L.grid, L.maxn, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  b.spin_limit = spin_limit();
+  b.seq = batch_schedule(batch, o, batch_sim_workers(o)) == -1 ? 1 : 0;
+  b.wg_pool_tiles = bc->wg_pool_tiles;
+  for (int t = 1; t <= MAX_BATCH_T; ++t) b.tntask[t] = tmpl[t] ? tmpl[t]->h->ntask : 0;
+  if (launch_breset(b, batch, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  // one workgroup per matrix: at most as many workgroups as per-workgroup pools
+  const int g2 = b.seq ? std::min(grid, batch_sim_workers(o)) : grid;
+  if ((fp32 ? launch_bsched32(b, g2, stream) : launch_bsched(b, g2, stream)) != hipSuccess)
+    return SPDINV_ERR_HIP;
   return 0;
 }
 
@@ -603,6 +1089,71 @@ int grid32_for(int device, const spdinv_opts& o) {
   }
   if (o.workers > 0 && o.workers < g) g = o.workers;
   return g;
+}
+
+// The FP32 form (SPDINV_FP32): FP32 tiles of the caller's FP32 matrix, the
+// renamed plan on the FP32 scheduler, copy-out; no refinement.
+struct Fp32Layout {
+  size_t indeg, ctrl, total;
+};
+
+Fp32Layout fp32_layout(int n) {
+  Fp32Layout F;
+  const int t = tiles_for(n);
+  F.indeg = align_up(pool_bytes32(t), 256);
+  F.ctrl = F.indeg + align_up((size_t)task_count(t) * sizeof(int32_t), 256);
+  F.total = F.ctrl + align_up(CTRL_WORDS * sizeof(int32_t), 256);
+  return F;
+}
+
+int run_fp32(int n, float* A, int lda, void* work, size_t work_bytes, hipStream_t stream,
+             const spdinv_opts& o, int* d_info, spdinv_report* report) {
+  const Fp32Layout F = fp32_layout(n);
+  if (work_bytes < F.total) return SPDINV_ERR_WORKSPACE;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return SPDINV_ERR_HIP;
+  const int t = tiles_for(n);
+  const int grid = grid32_for(device, o);
+  hipError_t err = hipSuccess;
+  DevPlan* dp = get_plan(device, t, o, grid, 1, &err);
+  if (!dp) return SPDINV_ERR_HIP;
+  const int ntask = (int)dp->host.tasks.size();
+  char* w = (char*)work;
+  float* pool = (float*)w;
+  int32_t* indeg = (int32_t*)(w + F.indeg);
+  int32_t* ctrl = (int32_t*)(w + F.ctrl);
+  if (launch_reset(dp->d_indeg0, indeg, ntask, ctrl, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (launch_copy_in32f(A, lda, n, t, pool, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  SchedArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.tasks = dp->d_tasks;
+  a.succ = dp->d_succ;
+  a.indeg = indeg;
+  a.ctrl = ctrl;
+  a.pool = reinterpret_cast<double*>(pool);
+  a.last_valid = NB;
+  a.ntask = ntask;
+  a.tiles_T = t * (t + 1) / 2;
+  a.tiles = t;
+  a.spin_limit = spin_limit();
+  if (launch_sched32(a, grid, false, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (launch_copy_out32f(pool, t, A, lda, n, o.fill_upper, stream) != hipSuccess)
+    return SPDINV_ERR_HIP;
+  if (launch_info_out(ctrl, d_info, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (report) {
+    if (hipStreamSynchronize(stream) != hipSuccess) return SPDINV_ERR_HIP;
+    int32_t c[CTRL_WORDS];
+    if (hipMemcpy(c, ctrl, sizeof(c), hipMemcpyDeviceToHost) != hipSuccess) return SPDINV_ERR_HIP;
+    report->info = (c[CTRL_INFO] == INT_MAX) ? 0 : c[CTRL_INFO];
+    report->status = c[CTRL_ABORT] ? SPDINV_ERR_TIMEOUT : 0;
+    report->nb = NB;
+    report->tiles = t;
+    report->tasks = c[CTRL_DONE];
+    report->critical_path = dp->host.stats.cp_plan;
+    report->workers = grid;
+    if (c[CTRL_ABORT]) return SPDINV_ERR_TIMEOUT;
+  }
+  return 0;
 }
 
 int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStream_t stream,
@@ -774,21 +1325,25 @@ size_t spd_inverse_workspace_bytes(int n, spdinv_mode mode, const spdinv_opts* o
   if (n <= 0) return 0;
   const spdinv_opts o = opts ? *opts : defaults();
   if (mode == SPDINV_MIXED_FP32 || mode == SPDINV_MIXED_BF16) return mixed_layout(n, o).total;
+  if (mode == SPDINV_FP32) return fp32_layout(n).total;
   return layout(n, o).total;
 }
 
-int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t work_bytes,
+int spd_inverse(int n, void* A_, int lda, spdinv_mode mode, void* work, size_t work_bytes,
                 spdinv_stream_t stream_, const spdinv_opts* opts, int* d_info,
                 spdinv_report* report) {
   hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  double* A = static_cast<double*>(A_);
   if (n < 0) return -1;
   if (n > 0 && !A) return -2;
   if (lda < (n > 1 ? n : 1)) return -3;
-  if (mode != SPDINV_FP64 && mode != SPDINV_MIXED_FP32 && mode != SPDINV_MIXED_BF16) return -4;
+  if (mode != SPDINV_FP64 && mode != SPDINV_FP32 && mode != SPDINV_MIXED_FP32 &&
+      mode != SPDINV_MIXED_BF16)
+    return -4;
   const spdinv_opts o = opts ? *opts : defaults();
   if (check_opts(o)) return -8;
   const bool mixed = mode == SPDINV_MIXED_FP32 || mode == SPDINV_MIXED_BF16;
-  if (mixed && (!o.renamed || o.trace)) return -8;
+  if ((mixed || mode == SPDINV_FP32) && (!o.renamed || o.trace)) return -8;
   if (report) std::memset(report, 0, sizeof(*report));
   if (n == 0) {
     if (d_info) {
@@ -800,6 +1355,8 @@ int spd_inverse(int n, double* A, int lda, spdinv_mode mode, void* work, size_t 
     return 0;
   }
   if (!work) return -5;
+  if (mode == SPDINV_FP32)
+    return run_fp32(n, static_cast<float*>(A_), lda, work, work_bytes, stream, o, d_info, report);
   if (mixed)
     return run_mixed(n, A, lda, work, work_bytes, stream, o, mode == SPDINV_MIXED_BF16, d_info,
                      report);
@@ -1023,6 +1580,52 @@ int spdinv_plan_export_steps(int steps, int rhs_tiles, int t, const spdinv_opts*
   if (links && !p.links.empty())
     std::memcpy(links, p.links.data(), p.links.size() * sizeof(int32_t));
   return 0;
+}
+
+int spdinv_batch_template_export(int t, spdinv_mode mode, const spdinv_opts* opts,
+                                 int32_t* tasks8, int32_t* succ, int32_t* links, long long* ntask,
+                                 long long* nsucc, long long* nlinks) {
+  if (t < 1 || t > MAX_BATCH_T) return -1;
+  if (mode != SPDINV_FP64 && mode != SPDINV_FP32) return -2;
+  const spdinv_opts o = opts ? *opts : defaults();
+  if (check_opts(o)) return -3;
+  std::lock_guard<std::mutex> lk(g_mu);
+  const BTemplate* bt = btemplate_host(t, mode == SPDINV_FP32, o);
+  if (ntask) *ntask = bt->ntask;
+  if (nsucc) *nsucc = (long long)bt->succ.size();
+  if (nlinks) *nlinks = (long long)bt->links.size() / 2;
+  if (tasks8) std::memcpy(tasks8, bt->tasks.data(), bt->tasks.size() * sizeof(DevTask));
+  if (succ && !bt->succ.empty())
+    std::memcpy(succ, bt->succ.data(), bt->succ.size() * sizeof(int32_t));
+  if (links && !bt->links.empty())
+    std::memcpy(links, bt->links.data(), bt->links.size() * sizeof(int32_t));
+  return 0;
+}
+
+long long spdinv_batch_plan_export(int batch, const int* h_n, spdinv_mode mode,
+                                   const spdinv_opts* opts, int workers, int32_t* disp,
+                                   int32_t* mat4) {
+  if (batch < 1 || batch > MAX_BATCH || !h_n) return -1;
+  if (mode != SPDINV_FP64 && mode != SPDINV_FP32) return -2;
+  const spdinv_opts o = opts ? *opts : defaults();
+  if (check_opts(o)) return -3;
+  std::vector<int8_t> tv(batch);
+  for (int i = 0; i < batch; ++i) {
+    if (h_n[i] < 0 || h_n[i] > MAX_BATCH_T * NB) return -1;
+    tv[i] = (int8_t)tiles_of_order(h_n[i]);
+  }
+  BCompHost hc;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    const BTemplate* tmpl[MAX_BATCH_T + 1] = {};
+    for (int i = 0; i < batch; ++i)
+      if (!tmpl[tv[i]]) tmpl[tv[i]] = btemplate_host(tv[i], mode == SPDINV_FP32, o);
+    const int w = workers > 0 ? workers : 1;
+    if (build_bcomp(tv, tmpl, batch_schedule(batch, o, w), w, &hc)) return -4;
+  }
+  if (disp) std::memcpy(disp, hc.disp.data(), hc.disp.size() * sizeof(int32_t));
+  if (mat4) std::memcpy(mat4, hc.mat.data(), hc.mat.size() * sizeof(int4));
+  return (long long)hc.disp.size();
 }
 
 long long spdinv_trace_copy(const void* work, int n, const spdinv_opts* opts, int64_t* host,

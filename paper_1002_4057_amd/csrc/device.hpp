@@ -41,37 +41,69 @@ struct SchedArgs {
   long long spin_limit;  // longest dependency wait, in 100 MHz clock ticks
 };
 
-// Batched form (one persistent launch over many matrices).
-constexpr int MAX_BATCH_T = 16;  // largest tile count per matrix (n <= 2048)
-
-struct BatchArgs {
-  const int* n;            // device, order of each matrix
-  double* const* A;        // device array of device pointers (column-major)
-  const int* lda;          // device, leading dimensions
-  int* info;               // device INFO per matrix (may be nullptr)
-  const int32_t* order;    // workspace: dispatch order (written by the sort)
-  int batch;
-  int32_t* ticket;         // workspace: dispatch counter
-  double* pool;            // workspace: pool_tiles per workgroup
-  long long pool_tiles;    // tiles per workgroup pool
-  int32_t* ctrl;           // workspace: CTRL_WORDS per workgroup
-  int tmax;                // largest tile count the pools are sized for
-  int fill_upper;
-  const DevTask* plan[MAX_BATCH_T + 1];  // program-order plan per tile count
-  const int32_t* plan_links[MAX_BATCH_T + 1];  // its chained-product links
-  int plan_ntask[MAX_BATCH_T + 1];
-};
-
-// Sort by decreasing order (device-side), then the persistent batched kernel.
-hipError_t launch_batched(const BatchArgs& b, int grid, int maxn, hipStream_t s);
-
-// Persistent workgroups per CU that fit for the batched kernel.
-int batched_blocks_per_cu();
+// Batched form: the largest tile count per matrix (n <= 2048).
+constexpr int MAX_BATCH_T = 16;
 
 // Resets the in-degree counters and the control block (a fill kernel, so
 // that the sequence stays capturable in a graph).
 hipError_t launch_reset(const int32_t* indeg0, int32_t* indeg, int ntask, int32_t* ctrl,
                         hipStream_t s);
+
+// ---- batched form as one DAG over the batch (bsched_loop.hpp) ----
+// Task kinds that only the batched templates use (after the plan's kinds).
+enum BatchKind : int32_t {
+  K_BCOPYIN = 16,   // the matrix's lower triangle -> its A tiles (identity padding);
+                    // checks its order and leading dimension first
+  K_BCOPYOUT = 17,  // A tiles -> lower triangle of the matrix; writes its INFO
+  K_BSMALL = 18     // a matrix of order <= NB inverted in LDS; writes its INFO
+};
+// Bit of BSchedArgs::mat[m].x: the copy-in task of matrix m waits for the
+// copy-out task of the previous occupant of its pool slot.
+constexpr int BM_PREV = 1 << 8;
+constexpr int BM_T = 0xff;
+// Dispatch entry: (matrix << BT_SHIFT) | template position.
+constexpr int BT_SHIFT = 12;
+constexpr int BT_MASK = (1 << BT_SHIFT) - 1;
+constexpr int MAX_BATCH = (1 << (31 - BT_SHIFT)) - 1;
+
+struct BSchedArgs {
+  const int32_t* disp;                      // ticket -> matrix and template position
+  const int4* mat;                          // per matrix: x = template tile count (1 for
+                                            // n <= NB) | BM_PREV if the matrix's pool
+                                            // slot had an earlier occupant; y = first
+                                            // counter; z = first pool tile; w = counter
+                                            // of the copy-in task of the slot's next
+                                            // occupant, or -1
+  const DevTask* tmpl[MAX_BATCH_T + 1];     // per tile count: template tasks
+  const int32_t* tsucc[MAX_BATCH_T + 1];    // their successors (template positions)
+  const int32_t* tlinks[MAX_BATCH_T + 1];   // their chained-product links
+  const int32_t* tindeg0[MAX_BATCH_T + 1];  // their initial in-degrees
+  int32_t* indeg;                           // counters, per (matrix, template task)
+  int32_t* ctrl;                            // CTRL_WORDS: ticket, abort, done
+  int32_t* mctrl;                           // CTRL_WORDS per matrix: INFO, FAILED
+  void* pool;                               // tiles of every matrix (FP64 or FP32)
+  const int* n;                             // device: orders
+  void* const* A;                           // device: matrix pointers
+  const int* lda;                           // device: leading dimensions
+  int* info;                                // device INFO per matrix (or nullptr)
+  int ntotal;                               // tickets
+  int fill_upper;
+  long long spin_limit;
+  // One workgroup per matrix (seq = 1): a ticket is a matrix (disp holds
+  // (m << BT_SHIFT) entries, largest matrices first), whose template tasks
+  // the workgroup runs in template order on its own pool of wg_pool_tiles
+  // tiles (reused by its next matrix); no counters.
+  int seq;
+  long long wg_pool_tiles;
+  int tntask[MAX_BATCH_T + 1];              // tasks of each template
+};
+
+// Resets the counters of a batch (from each template's initial in-degrees),
+// the per-matrix INFO/FAILED words and the control words.
+hipError_t launch_breset(const BSchedArgs& b, int batch, hipStream_t s);
+// The FP64 batched scheduler (two workgroups per CU).
+hipError_t launch_bsched(const BSchedArgs& b, int grid, hipStream_t s);
+int bsched_blocks_per_cu();
 
 // Column-major lower triangle of A -> A tiles of the pool, identity padding
 // beyond n (the padded matrix is block diagonal with an identity block, whose

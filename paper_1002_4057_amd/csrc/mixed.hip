@@ -10,10 +10,12 @@
 // FP32 tiles are NB x NB floats, column-major, contiguous (64 KiB), in the
 // same pool layout as the FP64 path: A tiles, the transposed renaming copies
 // B and C, the inverted diagonal factor tiles D_j and D_j^T.
+#include "bsched_loop.hpp"
 #include "device.hpp"
 #include "mfma_tile.hpp"
 #include "mixed.hpp"
 #include "sched_loop.hpp"
+#include "small_inverse.hpp"
 #include "tile_tasks.hpp"
 
 namespace spdinv {
@@ -382,7 +384,176 @@ __global__ __launch_bounds__(NTHREADS) void x0_to_sym64_kernel(const float* __re
   }
 }
 
+// FP32 storage (the SPDINV_FP32 mode): lower triangle of the FP32
+// column-major A -> FP32 lower tiles, identity padding beyond n; and back.
+__global__ __launch_bounds__(NTHREADS) void copy_in32f_kernel(const float* __restrict__ A, int lda,
+                                                              int n, float* __restrict__ pool) {
+  int ti, tj;
+  tri_decode32(blockIdx.x, ti, tj);
+  float* dst = pool + (size_t)blockIdx.x * TILE;
+  for (int e = threadIdx.x; e < (int)TILE; e += NTHREADS) {
+    const int r = e & (NB - 1), c = e >> 7;
+    const int gr = ti * NB + r, gc = tj * NB + c;
+    float v;
+    if (gr < n && gc < n)
+      v = (gr >= gc) ? A[gr + (size_t)lda * gc] : 0.0f;
+    else
+      v = (gr == gc) ? 1.0f : 0.0f;
+    dst[e] = v;
+  }
+}
+
+__global__ __launch_bounds__(NTHREADS) void copy_out32f_kernel(const float* __restrict__ pool,
+                                                               float* __restrict__ A, int lda, int n,
+                                                               int fill_upper) {
+  int ti, tj;
+  tri_decode32(blockIdx.x, ti, tj);
+  const float* src = pool + (size_t)blockIdx.x * TILE;
+  for (int e = threadIdx.x; e < (int)TILE; e += NTHREADS) {
+    const int r = e & (NB - 1), c = e >> 7;
+    const int gr = ti * NB + r, gc = tj * NB + c;
+    if (gr < n && gc < n && gr >= gc) {
+      const float v = src[e];
+      A[gr + (size_t)lda * gc] = v;
+      if (fill_upper && gr > gc) A[gc + (size_t)lda * gr] = v;
+    }
+  }
+}
+
+// ---- batched form in FP32 (bsched_loop.hpp): the FP32 tile tasks --------
+// Copy-in of one matrix of the batch into its FP32 tiles (agent-coherent
+// stores), and the copy-out.
+__device__ void bcopy_in32(const float* A, int lda, int n, int t, float* pool) {
+  const int T = t * (t + 1) / 2;
+  for (int x = 0; x < T; ++x) {
+    int ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= x) ++ti;
+    const int tj = x - ti * (ti + 1) / 2;
+    const rsrc_t rd = rsrc32(tile32(pool, x));
+#pragma unroll 4
+    for (int q = 0; q < NB * NB / 4 / NTHREADS; ++q) {
+      const int e = 4 * (threadIdx.x + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
+      const int gc = tj * NB + cc;
+      f4 v;
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int r = ti * NB + rr + h;
+        if (r < n && gc < n)
+          v[h] = (r >= gc) ? A[r + (size_t)lda * gc] : 0.0f;
+        else
+          v[h] = (r == gc) ? 1.0f : 0.0f;
+      }
+      st4f(rd, e, v);
+    }
+  }
+}
+
+__device__ void bcopy_out32(float* pool, int t, float* A, int lda, int n, int fill_upper) {
+  const int T = t * (t + 1) / 2;
+  for (int x = 0; x < T; ++x) {
+    int ti = 0;
+    while ((ti + 1) * (ti + 2) / 2 <= x) ++ti;
+    const int tj = x - ti * (ti + 1) / 2;
+    const rsrc_t rs = rsrc32(tile32(pool, x));
+#pragma unroll 4
+    for (int q = 0; q < NB * NB / 4 / NTHREADS; ++q) {
+      const int e = 4 * (threadIdx.x + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
+      const int gc = tj * NB + cc;
+      const f4 v = ld4f(rs, e);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int r = ti * NB + rr + h;
+        if (r < n && gc < n && r >= gc) {
+          A[r + (size_t)lda * gc] = v[h];
+          if (fill_upper && r > gc) A[gc + (size_t)lda * r] = v[h];
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ int load_uniform32(int32_t* p) {
+  return __builtin_amdgcn_readfirstlane(
+      __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+__global__ __launch_bounds__(NTHREADS) void bsched_kernel32(BSchedArgs g) {
+  __shared__ double smem[SMEM_DOUBLES];
+  auto run = [&](const DevTask& d, int m, int t) {
+    const int kind = d.kind & 0xff;
+    int32_t* mc = g.mctrl + CTRL_WORDS * m;
+    int n, lda;
+    float* A;
+    if (kind == K_BSMALL) {
+      int info = -1;
+      if (batch_entry(g, m, 1, &n, &lda, &A))
+        info = n ? small_inverse<float>(A, lda, n, g.fill_upper, smem) : 0;
+      batch_info(g, m, info);
+      return;
+    }
+    // one workgroup per matrix: the workgroup's own pool, else the matrix's slot
+    const size_t first = g.seq ? (size_t)blockIdx.x * (size_t)g.wg_pool_tiles
+                               : (size_t)__builtin_amdgcn_readfirstlane(g.mat[m].z);
+    float* pool = static_cast<float*>(g.pool) + first * TILE;
+    if (kind == K_BCOPYIN) {
+      if (batch_entry(g, m, t, &n, &lda, &A)) {
+        bcopy_in32(A, lda, n, t, pool);
+      } else if (threadIdx.x == 0) {
+        __hip_atomic_store(&mc[CTRL_INFO], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&mc[CTRL_FAILED], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      return;
+    }
+    if (kind == K_BCOPYOUT) {
+      if (load_uniform32(&mc[CTRL_FAILED])) {
+        batch_info(g, m, load_uniform32(&mc[CTRL_INFO]));
+        return;
+      }
+      batch_entry(g, m, t, &n, &lda, &A);
+      bcopy_out32(pool, t, A, lda, n, g.fill_upper);
+      batch_info(g, m, 0);
+      return;
+    }
+    SchedArgs s{};
+    s.pool = reinterpret_cast<double*>(pool);
+    s.ctrl = mc;
+    s.info_base = 0;
+    run_task32<false>(d, s, smem, t * (t + 1) / 2, t);
+  };
+  if (g.seq)
+    bseq_loop(g, run);
+  else
+    bsched_loop(g, run);
+}
+
 }  // namespace
+
+hipError_t launch_copy_in32f(const float* A, int lda, int n, int t, float* pool, hipStream_t s) {
+  const int T = t * (t + 1) / 2;
+  hipLaunchKernelGGL(copy_in32f_kernel, dim3(T), dim3(NTHREADS), 0, s, A, lda, n, pool);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_out32f(const float* pool, int t, float* A, int lda, int n, int fill_upper,
+                              hipStream_t s) {
+  const int T = t * (t + 1) / 2;
+  hipLaunchKernelGGL(copy_out32f_kernel, dim3(T), dim3(NTHREADS), 0, s, pool, A, lda, n,
+                     fill_upper);
+  return hipGetLastError();
+}
+
+hipError_t launch_bsched32(const BSchedArgs& b, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(bsched_kernel32, dim3(grid), dim3(NTHREADS), 0, s, b);
+  return hipGetLastError();
+}
+
+int bsched32_blocks_per_cu() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, bsched_kernel32, NTHREADS, 0) !=
+      hipSuccess)
+    return 1;
+  return blocks > 0 ? blocks : 1;
+}
 
 size_t pool_bytes32(int t) { return (size_t)pool_tiles(t) * TILE_BYTES32; }
 

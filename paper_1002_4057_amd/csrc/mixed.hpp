@@ -23,4 +23,13 @@ hipError_t launch_x0_to_sym64(const float* pool, int t, int n, double* X, hipStr
 
 int sched32_blocks_per_cu();
 
+// FP32 storage (SPDINV_FP32): FP32 column-major lower triangle <-> FP32 tiles.
+hipError_t launch_copy_in32f(const float* A, int lda, int n, int t, float* pool, hipStream_t s);
+hipError_t launch_copy_out32f(const float* pool, int t, float* A, int lda, int n, int fill_upper,
+                              hipStream_t s);
+
+// The FP32 batched scheduler (bsched_loop.hpp with the FP32 tile tasks).
+hipError_t launch_bsched32(const BSchedArgs& b, int grid, hipStream_t s);
+int bsched32_blocks_per_cu();
+
 }  // namespace spdinv

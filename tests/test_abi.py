@@ -110,6 +110,30 @@ def test_batched_invalid_arguments_rejected_on_host():
     assert lib.batched_spd_inverse(2, n, 1, 1, 1, 2, 1, 1 << 40, None, None, None) == -6
     o = spd.make_opts(nb=64)
     assert lib.batched_spd_inverse(2, n, 1, 1, 1, 0, 1, 1 << 40, None, ctypes.byref(o), None) == -10
+    o = spd.make_opts(renamed=0)     # the FP32 tile tasks take the renamed plan only
+    assert lib.batched_spd_inverse(2, n, 1, 1, 1, _lib.SPDINV_FP32, 1, 1 << 40, None,
+                                   ctypes.byref(o), None) == -10
+    big = (ctypes.c_int * 2)(4, 2049)
+    assert lib.batched_spd_inverse(2, big, 1, 1, 1, 0, 1, 1 << 40, None, None, None) == -2
+    assert lib.batched_spd_inverse(2, n, 1, 1, 1, 0, 1, 16, None, None, None) == _lib.ERR_WORKSPACE
+
+
+def test_batched_workspace_bytes():
+    # with three matrices and 512 simulated workers all run at once: every
+    # matrix above one tile has a pool slot of its own, 3T + 2t tiles
+    orders = [100, 129, 256, 300]
+    b64 = spd.batched_workspace_bytes(orders)
+    b32 = spd.batched_workspace_bytes(orders, mode="fp32")
+    pools = sum(3 * t * (t + 1) // 2 + 2 * t for t in (2, 2, 3)) * 128 * 128
+    assert b64 >= pools * 8 and b32 >= pools * 4 and b32 < b64
+    assert spd.batched_workspace_bytes([2049]) == 0
+    # the list-scheduled DAG on one simulated worker: the two matrices of two
+    # tiles share one slot
+    one = spd.batched_workspace_bytes(orders, workers=1, batch_group=-2)
+    assert one < b64 and one >= (3 * 3 + 4 + 3 * 6 + 6) * 128 * 128 * 8
+    # one workgroup per matrix: a pool of the largest tile count per workgroup
+    seq = spd.batched_workspace_bytes(orders, workers=2, batch_group=-1)
+    assert 2 * (3 * 6 + 6) * 128 * 128 * 8 <= seq < 2 * (3 * 6 + 6) * 128 * 128 * 8 + (1 << 20)
 
 
 def test_mixed_mode_host_checks():
@@ -117,8 +141,13 @@ def test_mixed_mode_host_checks():
     o = spd.make_opts(renamed=0)
     assert lib.spd_inverse(4, 1, 4, _lib.SPDINV_MIXED_FP32, 1, 1 << 30, None, ctypes.byref(o),
                            None, None) == -8
-    assert lib.spd_inverse(4, 1, 4, _lib.SPDINV_FP32, 1, 1 << 30, None, None, None,
-                           None) == -4
+    # the FP32 form runs the renamed plan only and checks its workspace
+    assert lib.spd_inverse(4, 1, 4, _lib.SPDINV_FP32, 1, 1 << 30, None, ctypes.byref(o), None,
+                           None) == -8
+    assert lib.spd_inverse(512, 1, 512, _lib.SPDINV_FP32, 1, 16, None, None, None,
+                           None) == _lib.ERR_WORKSPACE
+    assert 0 < spd.workspace_bytes(1000, mode="fp32") < spd.workspace_bytes(1000)
+    assert lib.spd_inverse(4, 1, 4, 9, 1, 1 << 30, None, None, None, None) == -4
     assert lib.spd_inverse(4, 1, 4, _lib.SPDINV_MIXED_BF16, 1, 1 << 30, None, ctypes.byref(o),
                            None, None) == -8
     assert spd.workspace_bytes(1000, mode="mixed_bf16") == spd.workspace_bytes(1000,

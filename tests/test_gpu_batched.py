@@ -181,3 +181,83 @@ def test_full_batched_workload_sampled_oracle_and_residuals():
         # kappa <= (lambda_max + 0.1)/0.1 with lambda_max <= (1 + 1)^2 + 0.1 w.h.p.; use 60
         worst = max(worst, (torch.linalg.norm(r) / n ** 0.5).item())
     assert worst <= 1e-12 * 60, worst
+
+
+def test_dispatch_groups_and_chain_give_the_same_bits():
+    """The schedule (batch_group: list-scheduled DAG, interleaved groups, one
+    workgroup per matrix) and the chain length change only the order in which
+    tasks run: every product runs in the same per-tile order, so the results
+    are the same bits."""
+    orders = inputs.batch_orders(40, 16, 600, seed=12)
+    mats = [m.to(DEV) for m in inputs.batched_wishart(orders, seed=12, shift=0.1)]
+    ref = spd.batched_spd_inverse(mats)
+    for opts in (dict(batch_group=1), dict(batch_group=7), dict(batch_group=1000),
+                 dict(batch_group=-1), dict(batch_group=-1, workers=5), dict(batch_group=-2), dict(chain=1),
+                 dict(workers=3)):
+        got = spd.batched_spd_inverse(mats, **opts)
+        for k, (x, y) in enumerate(zip(ref, got)):
+            assert torch.equal(x, y), (opts, k)
+
+
+# ---- FP32 storage (SPDINV_FP32) ------------------------------------------
+U32 = 2.0 ** -24
+
+
+def _fp32_bar(n, kap):
+    # first-order error of an inverse computed with unit roundoff u through a
+    # Cholesky factor: (c n + c') u kappa_2(A), c = 1, c' = 4 for the stored
+    # inverted diagonal tiles and the stored result (typical errors are far
+    # below: sqrt(n) u kappa)
+    return (n + 4) * U32 * kap
+
+
+def test_fp32_edge_orders_against_oracle():
+    """Each FP32 result against the oracle's binary64 inverse of the same
+    FP32 input (widened exactly)."""
+    mats = [m.to(torch.float32) for m in inputs.batched_wishart(EDGE_ORDERS, seed=17, shift=0.1)]
+    got = spd.batched_spd_inverse([m.to(DEV) for m in mats])
+    for n, a, x in zip(EDGE_ORDERS, mats, got):
+        assert x.dtype == torch.float32
+        an = a.double().numpy()
+        ref = oracle.spd_inverse(an)
+        xn = x.cpu().double().numpy()
+        assert rel_fro(xn, ref) <= _fp32_bar(n, kappa(an)), n
+        assert np.array_equal(xn, xn.T), n
+
+
+def test_fp32_tile_path_bit_identical_to_single_fp32_call():
+    orders = [129, 256, 300, 512, 700]
+    mats = [m.to(torch.float32) for m in inputs.batched_wishart(orders, seed=18, shift=0.1)]
+    got = spd.batched_spd_inverse([m.to(DEV) for m in mats])
+    for a, x in zip(mats, got):
+        single = spd.spd_inverse(a.to(DEV), mode="fp32")
+        assert torch.equal(x, single)
+
+
+def test_fp32_info_and_invalid_entries():
+    orders = [40, 150, 60]
+    mats = [m.to(torch.float32) for m in inputs.batched_wishart(orders, seed=19, shift=0.1)]
+    mats[1][77, 77] = -1.0e3      # breaks down at pivot 78 (tile path)
+    buf = torch.cat([m.t().contiguous().reshape(-1) for m in mats]).to(DEV)
+    offs = np.concatenate([[0], np.cumsum([n * n for n in orders])])
+    ptrs = torch.tensor([buf.data_ptr() + 4 * int(o) for o in offs[:-1]], dtype=torch.int64,
+                        device=DEV)
+    n_dev = torch.tensor(orders, dtype=torch.int32, device=DEV)
+    lda_dev = torch.tensor([40, 150, 7], dtype=torch.int32, device=DEV)   # third lda < n
+    info = torch.full((3,), 99, dtype=torch.int32, device=DEV)
+    spd.batched_spd_inverse_(ptrs, orders, n_dev, lda_dev, mode="fp32", info=info)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0, 78, -1]
+
+
+def test_fp32_batched_workload_sample():
+    """2048 matrices of the batched workload's order distribution in FP32:
+    a seeded sample against the oracle."""
+    orders = inputs.batch_orders(2048, 16, 512, seed=5)
+    mats = [m.to(torch.float32) for m in inputs.batched_wishart(orders, seed=5, shift=0.1)]
+    got = spd.batched_spd_inverse([m.to(DEV) for m in mats])
+    rng = np.random.default_rng(2)
+    for k in sorted(set(rng.choice(len(orders), 24, replace=False).tolist())):
+        an = mats[k].double().numpy()
+        ref = oracle.spd_inverse(an)
+        assert rel_fro(got[k].cpu().double().numpy(), ref) <= _fp32_bar(orders[k], kappa(an)), k
