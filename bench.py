@@ -353,10 +353,29 @@ def backward_row(reps: int):
     torch.cuda.synchronize()
     ms = time_events(lambda: spd.spd_inverse_backward(x, g, work=work, out=out), reps)
     flops = 3.0 * float(n) ** 3
-    return {"workload": "backward of the inverse, n=4096, FP64 (3 n^3 flops)",
-            "ms": round(ms, 3), "gflops": round(flops / (ms / 1e3) / 1e9, 1),
-            "frac_fp64_peak": round(flops / (ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
-            "reps": reps}
+    row = {"workload": "backward of the inverse, n=4096, FP64 (3 n^3 flops)",
+           "ms": round(ms, 3), "gflops": round(flops / (ms / 1e3) / 1e9, 1),
+           "frac_fp64_peak": round(flops / (ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+           "reps": reps}
+    del x, g, out, work
+    # workload (b): 256 matrices of n = 256, forward and backward each one
+    # batched launch
+    nb, batch = 256, 256
+    a = torch.stack([inputs.wishart_shift(nb, seed=k) for k in range(batch)]).to(dev)
+    xs = spd.batched_spd_inverse(list(a))
+    gs = [inputs.randn((nb, nb), seed=10000 + k).to(dev) for k in range(batch)]
+    outs = [torch.empty_like(v) for v in xs]
+    bwork = torch.empty(spd.batched_backward_workspace_bytes([nb] * batch), dtype=torch.uint8,
+                        device=dev)
+    spd.batched_spd_inverse_backward(xs, gs, work=bwork, out=outs)
+    torch.cuda.synchronize()
+    msb = time_events(lambda: spd.batched_spd_inverse_backward(xs, gs, work=bwork, out=outs), reps)
+    fb = 3.0 * float(nb) ** 3 * batch
+    row["batched"] = {"workload": "backward of 256 inverses of n=256, FP64, one batched launch "
+                                  "(3 n^3 flops each)",
+                      "ms": round(msb, 3), "gflops": round(fb / (msb / 1e3) / 1e9, 1),
+                      "frac_fp64_peak": round(fb / (msb / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
+    return row
 
 
 def main():

@@ -360,6 +360,39 @@ int spd_inverse_backward(int n, const double* X, int ldx, const double* G, int l
 int spd_inverse_noalloc(int n, double* A, int lda, spdinv_stream_t stream,
                         const spdinv_opts* opts, int* d_info);
 
+/*
+ * The same adjoint for `batch` matrices of uneven orders in one persistent
+ * launch (after a fill kernel that clears its counters): grad_i =
+ * -X_i sym(G_i) X_i.  The tile tasks of every matrix (packing of X_i from
+ * its lower triangle and of sym(G_i), the tiles of W_i = X_i S_i, the lower
+ * tiles of -W_i X_i, the output tiles) run in phase order on persistent
+ * workgroups, each waiting for the tiles it reads through per-matrix
+ * counters.
+ *   batch    number of matrices (0 <= batch < 2^19)
+ *   h_n      host int[batch], orders 0 <= n_i <= 2048
+ *   d_n      device int[batch], the same orders (an order or leading
+ *            dimension on the device that does not fit leaves that
+ *            matrix's output unwritten)
+ *   d_X      device array of device pointers: X_i = A_i^{-1}, column-major,
+ *            lower triangle used;  d_ldx device int[batch]
+ *   d_G      device array of device pointers: G_i, full; d_ldg device int[batch]
+ *   d_gradA  device array of device pointers: the full symmetric gradients
+ *            (must not overlap X_i or G_i);  d_ldga device int[batch]
+ *   work     device workspace of batched_spd_inverse_backward_workspace_bytes
+ *            bytes: 4 t_i^2 tiles of 128 x 128 doubles per matrix
+ *            (t_i = ceil(n_i/128)) and the counters
+ * Returns 0, -i for an invalid i-th argument, SPDINV_ERR_WORKSPACE or
+ * SPDINV_ERR_HIP.  The first call for a set of tile counts uploads its task
+ * list into a library-owned device arena; later calls with the same tile
+ * counts allocate nothing and can be captured in a HIP graph.
+ */
+size_t batched_spd_inverse_backward_workspace_bytes(int batch, const int* h_n);
+int batched_spd_inverse_backward(int batch, const int* h_n, const int* d_n,
+                                 const double* const* d_X, const int* d_ldx,
+                                 const double* const* d_G, const int* d_ldg,
+                                 double* const* d_gradA, const int* d_ldga, void* work,
+                                 size_t work_bytes, spdinv_stream_t stream);
+
 /* Frees every cached plan (device arena and host tables).  The host tables of
    spd_inverse_noalloc's plans are kept, since an upload from them may still
    be pending on a stream. */

@@ -28,7 +28,8 @@ __all__ = ["spd_inverse", "spd_inverse_", "workspace_bytes", "plan_stats", "plan
            "batched_spd_inverse", "batched_spd_inverse_", "batched_workspace_bytes",
            "cholesky", "cholesky_", "inverse_from_factor", "inverse_from_factor_",
            "solve", "solve_", "solve_from_factor", "solve_from_factor_", "solve_workspace_bytes",
-           "spd_inverse_noalloc_", "SpdInverseError", "NotPositiveDefinite"]
+           "spd_inverse_noalloc_", "batched_spd_inverse_backward",
+           "batched_backward_workspace_bytes", "SpdInverseError", "NotPositiveDefinite"]
 
 
 class SpdInverseError(RuntimeError):
@@ -429,6 +430,63 @@ def spd_inverse_backward(x, g, *, work=None, out=None):
     return out
 
 
+def batched_backward_workspace_bytes(orders) -> int:
+    return int(load().batched_spd_inverse_backward_workspace_bytes(len(orders),
+                                                                   _int_array(orders)))
+
+
+def batched_spd_inverse_backward(xs, gs, *, work=None, out=None):
+    """Gradients -X_i sym(g_i) X_i for lists of square CUDA float64 tensors
+    (X_i symmetric, e.g. outputs of ``spd_inverse``; g_i any), computed in one
+    persistent launch.  Returns a list of full symmetric gradients (written
+    into the tensors of ``out`` when given, contiguous n_i x n_i).  Row-major
+    buffers are passed as column-major ones of the transposes, as in
+    ``spd_inverse_backward``."""
+    import torch
+    if len(xs) != len(gs):
+        raise ValueError("xs and gs differ in length")
+    if not xs:
+        return []
+    dev = xs[0].device
+    orders = []
+    for x, g in zip(xs, gs):
+        n = x.shape[0]
+        if x.dtype != torch.float64 or g.dtype != torch.float64 or not x.is_cuda or not g.is_cuda:
+            raise TypeError("expected CUDA float64 tensors")
+        if x.shape != (n, n) or g.shape != (n, n):
+            raise ValueError("each x and g must be n x n")
+        orders.append(int(n))
+    xc = [x.contiguous() for x in xs]
+    gc = [g.contiguous() for g in gs]
+    if out is None:
+        out = [torch.empty((n, n), dtype=torch.float64, device=dev) for n in orders]
+    elif len(out) != len(xs) or any(o.shape != (n, n) or not o.is_contiguous()
+                                    for o, n in zip(out, orders)):
+        raise ValueError("out must hold contiguous n_i x n_i tensors")
+    lib = load()
+    h_n = _int_array(orders)
+    need = int(lib.batched_spd_inverse_backward_workspace_bytes(len(orders), h_n))
+    if need == 0:
+        raise ValueError("invalid orders (0 <= n <= 2048)")
+    if work is None:
+        work = torch.empty(need, dtype=torch.uint8, device=dev)
+    elif work.numel() * work.element_size() < need:
+        raise ValueError(f"workspace too small: need {need} bytes")
+    ptr = lambda ts: torch.tensor([t.data_ptr() for t in ts], dtype=torch.int64, device=dev)  # noqa: E731
+    ld = torch.tensor([max(1, n) for n in orders], dtype=torch.int32, device=dev)
+    n_dev = torch.tensor(orders, dtype=torch.int32, device=dev)
+    px, pg, po = ptr(xc), ptr(gc), ptr(out)
+    rc = lib.batched_spd_inverse_backward(len(orders), h_n, n_dev.data_ptr(), px.data_ptr(),
+                                          ld.data_ptr(), pg.data_ptr(), ld.data_ptr(),
+                                          po.data_ptr(), ld.data_ptr(), work.data_ptr(), need,
+                                          _stream_ptr(dev))
+    if rc != 0:
+        raise SpdInverseError(f"batched_spd_inverse_backward returned {rc}")
+    # (the pointer tables may be freed now: torch reuses their memory only for
+    # work ordered after this launch on the stream)
+    return out
+
+
 def _autograd_function():
     import torch
 
@@ -436,14 +494,15 @@ def _autograd_function():
         """A -> A^{-1} for symmetric positive definite A (lower triangle read),
         with the gradient taken over symmetric matrices: dL/dA =
         -A^{-1} sym(dL/dA^{-1}) A^{-1}.  Both directions run in the HIP
-        library.  A leading batch dimension is handled one matrix at a time."""
+        library; with a leading batch dimension each direction is one batched
+        launch (batched_spd_inverse, batched_spd_inverse_backward)."""
 
         @staticmethod
         def forward(ctx, a):
             if a.dim() == 2:
                 x = spd_inverse(a)
             else:
-                x = torch.stack([spd_inverse(m) for m in a])
+                x = torch.stack(batched_spd_inverse(list(a)))
             ctx.save_for_backward(x)
             return x
 
@@ -452,7 +511,9 @@ def _autograd_function():
             (x,) = ctx.saved_tensors
             if x.dim() == 2:
                 return spd_inverse_backward(x, gx)
-            return torch.stack([spd_inverse_backward(xm, gm) for xm, gm in zip(x, gx)])
+            out = torch.empty_like(x)
+            batched_spd_inverse_backward(list(x), list(gx), out=list(out))
+            return out
 
     return SpdInverse
 

@@ -119,6 +119,10 @@ def load():
     lib.spdinv_batch_template_export.restype = i
     lib.spdinv_batch_plan_export.argtypes = [i, ip, i, P(Opts), i, i32p, i32p]
     lib.spdinv_batch_plan_export.restype = ll
+    lib.batched_spd_inverse_backward_workspace_bytes.argtypes = [i, ip]
+    lib.batched_spd_inverse_backward_workspace_bytes.restype = sz
+    lib.batched_spd_inverse_backward.argtypes = [i, ip, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.batched_spd_inverse_backward.restype = i
     lib.spd_inverse_noalloc.argtypes = [i, vp, i, vp, P(Opts), vp]
     lib.spd_inverse_noalloc.restype = i
     lib.spdinv_version.argtypes = []

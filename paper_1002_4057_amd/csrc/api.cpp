@@ -415,6 +415,89 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
 
 namespace {
 
+// ---- batched backward --------------------------------------------------------
+// Per matrix of t = ceil(n/NB) tiles: 4 t^2 workspace tiles and 1 + t + t^2
+// counters; tasks in phase order (all packs, all W tiles, all lower gradient
+// tiles, all output tiles), the matrices of each phase largest first.
+struct BBackComp {
+  void* arena = nullptr;
+  const int2* d_task = nullptr;
+  const int4* d_mat = nullptr;
+  int ntask = 0;
+  long long tiles = 0, ncnt = 0;
+};
+std::map<std::pair<int, std::vector<int8_t>>, std::unique_ptr<BBackComp>> g_bbcomp;
+
+void bback_sizes(int batch, const int* h_n, long long* tiles, long long* ncnt) {
+  *tiles = 0;
+  *ncnt = 0;
+  for (int i = 0; i < batch; ++i) {
+    const long long t = tiles_for(h_n[i]);
+    *tiles += 4 * t * t;
+    *ncnt += t ? 1 + t + t * t : 0;
+  }
+}
+
+size_t bback_bytes(long long tiles, long long ncnt) {
+  return 256 + align_up((size_t)ncnt * sizeof(int32_t), 256) + (size_t)tiles * NB * NB * sizeof(double);
+}
+
+BBackComp* get_bbcomp(int device, int batch, const int* h_n, hipError_t* err) {
+  std::vector<int8_t> tv(batch);
+  for (int i = 0; i < batch; ++i) tv[i] = (int8_t)tiles_for(h_n[i]);
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(device, tv);
+  auto it = g_bbcomp.find(key);
+  if (it != g_bbcomp.end()) return it->second.get();
+  std::vector<int> order;
+  for (int t = MAX_BATCH_T; t >= 1; --t)
+    for (int i = 0; i < batch; ++i)
+      if (tv[i] == t) order.push_back(i);
+  std::vector<int4> mat(batch, make_int4(0, 0, 0, 0));
+  long long tb = 0, cb = 0;
+  for (int m : order) {
+    const int t = tv[m];
+    mat[m] = make_int4(t, (int)tb, (int)cb, 0);
+    tb += 4LL * t * t;
+    cb += 1 + t + t * t;
+  }
+  if (tb > INT_MAX || cb > INT_MAX) {
+    *err = hipErrorInvalidValue;
+    return nullptr;
+  }
+  std::vector<int2> task;
+  for (int phase = 0; phase < 4; ++phase)
+    for (int m : order) {
+      const int t = tv[m];
+      for (int j = 0; j < t; ++j)
+        for (int i = 0; i < t; ++i)
+          if (phase != 2 || i >= j) task.push_back(make_int2(m, (phase << BB_PHASE_SHIFT) | (i << 8) | j));
+    }
+  std::unique_ptr<BBackComp> bc(new BBackComp);
+  const size_t o_mat = align_up(task.size() * sizeof(int2), 256);
+  const size_t bytes = align_up(o_mat + (size_t)batch * sizeof(int4), 256);
+  std::vector<char> img(bytes, 0);
+  if (!task.empty()) std::memcpy(img.data(), task.data(), task.size() * sizeof(int2));
+  std::memcpy(img.data() + o_mat, mat.data(), (size_t)batch * sizeof(int4));
+  void* arena = nullptr;
+  *err = hipMalloc(&arena, bytes);
+  if (*err != hipSuccess) return nullptr;
+  *err = hipMemcpy(arena, img.data(), bytes, hipMemcpyHostToDevice);
+  if (*err != hipSuccess) {
+    (void)hipFree(arena);
+    return nullptr;
+  }
+  bc->arena = arena;
+  bc->d_task = (const int2*)arena;
+  bc->d_mat = (const int4*)((char*)arena + o_mat);
+  bc->ntask = (int)task.size();
+  bc->tiles = tb;
+  bc->ncnt = cb;
+  BBackComp* raw = bc.get();
+  g_bbcomp[key] = std::move(bc);
+  return raw;
+}
+
 // ---- batched form: one DAG over the batch ---------------------------------
 // Task template of one matrix of t tiles per side: the plan of Algorithm 1
 // in dispatch order, preceded by its copy-in task (an edge to every task
@@ -1004,6 +1087,78 @@ int batched_spd_inverse(int batch, const int* h_n, const int* d_n, void* const* 
   const int g2 = b.seq ? std::min(grid, batch_sim_workers(o)) : grid;
   if ((fp32 ? launch_bsched32(b, g2, stream) : launch_bsched(b, g2, stream)) != hipSuccess)
     return SPDINV_ERR_HIP;
+  return 0;
+}
+
+size_t batched_spd_inverse_backward_workspace_bytes(int batch, const int* h_n) {
+  if (batch <= 0 || batch > MAX_BATCH || !h_n) return 0;
+  for (int i = 0; i < batch; ++i)
+    if (h_n[i] < 0 || h_n[i] > MAX_BATCH_T * NB) return 0;
+  long long tiles, ncnt;
+  bback_sizes(batch, h_n, &tiles, &ncnt);
+  return bback_bytes(tiles, ncnt);
+}
+
+int batched_spd_inverse_backward(int batch, const int* h_n, const int* d_n,
+                                 const double* const* d_X, const int* d_ldx,
+                                 const double* const* d_G, const int* d_ldg,
+                                 double* const* d_gradA, const int* d_ldga, void* work,
+                                 size_t work_bytes, spdinv_stream_t stream_) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  if (batch < 0 || batch > MAX_BATCH) return -1;
+  if (batch == 0) return 0;
+  if (!h_n) return -2;
+  for (int i = 0; i < batch; ++i)
+    if (h_n[i] < 0 || h_n[i] > MAX_BATCH_T * NB) return -2;
+  if (!d_n) return -3;
+  if (!d_X) return -4;
+  if (!d_ldx) return -5;
+  if (!d_G) return -6;
+  if (!d_ldg) return -7;
+  if (!d_gradA) return -8;
+  if (!d_ldga) return -9;
+  if (!work) return -10;
+  long long tiles, ncnt;
+  bback_sizes(batch, h_n, &tiles, &ncnt);
+  if (work_bytes < bback_bytes(tiles, ncnt)) return SPDINV_ERR_WORKSPACE;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return SPDINV_ERR_HIP;
+  hipError_t err = hipSuccess;
+  BBackComp* bc = get_bbcomp(device, batch, h_n, &err);
+  if (!bc) return SPDINV_ERR_HIP;
+  if (bc->ntask == 0) return 0;  // every order is 0
+  static std::map<int, int> grids;
+  int grid;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = grids.find(device);
+    if (it == grids.end()) {
+      int cus = 0;
+      if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+          cus <= 0)
+        cus = 1;
+      it = grids.emplace(device, cus * bback_blocks_per_cu()).first;
+    }
+    grid = it->second;
+  }
+  char* w = (char*)work;
+  BBackArgs b;
+  std::memset(&b, 0, sizeof(b));
+  b.task = bc->d_task;
+  b.ntask = bc->ntask;
+  b.mat = bc->d_mat;
+  b.n = d_n;
+  b.X = d_X;
+  b.ldx = d_ldx;
+  b.G = d_G;
+  b.ldg = d_ldg;
+  b.gradA = d_gradA;
+  b.ldga = d_ldga;
+  b.ctrl = (int32_t*)w;
+  b.cnt = (int32_t*)(w + 256);
+  b.tiles = (double*)(w + 256 + align_up((size_t)bc->ncnt * sizeof(int32_t), 256));
+  b.spin_limit = spin_limit();
+  if (launch_bback(b, (int)bc->ncnt, grid, stream) != hipSuccess) return SPDINV_ERR_HIP;
   return 0;
 }
 

@@ -232,7 +232,197 @@ __global__ __launch_bounds__(NTHREADS) void unpack_sym_kernel(const double* __re
   }
 }
 
+// ---- batched backward (see BBackArgs) ------------------------------------
+// Counters and control words <- 0 (a fill kernel: the sequence stays
+// capturable in a graph).
+__global__ void zero_kernel(int32_t* __restrict__ cnt, int ncnt, int32_t* __restrict__ ctrl) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x < ncnt) cnt[x] = 0;
+  if (x < CTRL_WORDS) ctrl[x] = 0;
+}
+
+// Tile (bi, bj) of the square tile-major form of a column-major source of
+// order n (mode as pack_kernel), written with agent-coherent stores (other
+// workgroups read it in the same launch).
+__device__ void bb_pack_tile(const double* __restrict__ src, int ld, int n, int mode, int bi,
+                             int bj, double* out, double (*L)[SB + 1]) {
+  const rsrc_t ro = tile_rsrc(out);
+  const int tx = threadIdx.x & (SB - 1), ty = threadIdx.x / SB;
+  for (int sb = 0; sb < (NB / SB) * (NB / SB); ++sb) {
+    const int lr0 = (sb % (NB / SB)) * SB, lc0 = (sb / (NB / SB)) * SB;
+    const int r0 = bi * NB + lr0, c0 = bj * NB + lc0;
+#pragma unroll
+    for (int q = 0; q < SB / 8; ++q) {
+      const int j = ty + 8 * q;
+      const int sr = c0 + tx, sc = r0 + j;
+      L[tx][j] = (sr < n && sc < n) ? src[sr + (size_t)ld * sc] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SB / 8; ++q) {
+      const int j = ty + 8 * q;
+      const int gr = r0 + tx, gc = c0 + j;
+      const double tv = L[j][tx];
+      const double dv = (gr < n && gc < n) ? src[gr + (size_t)ld * gc] : 0.0;
+      const double v = mode == PACK_SYM_LOWER ? ((gr >= gc) ? dv : tv) : 0.5 * (dv + tv);
+      st1(ro, (lr0 + tx) + NB * (lc0 + j), v);
+    }
+    __syncthreads();
+  }
+}
+
+// Output tile (bi, bj) of the column-major symmetric matrix whose lower tiles
+// are in the square tile-major src (as unpack_sym_kernel, both triangles).
+__device__ void bb_unpack_tile(const double* src, int t, int n, double* out, int ld, int bi,
+                               int bj, double (*L)[SB + 1]) {
+  const int tx = threadIdx.x & (SB - 1), ty = threadIdx.x / SB;
+  const int si = bi >= bj ? bi : bj, sj = bi >= bj ? bj : bi;
+  const rsrc_t rs = tile_rsrc(src + (size_t)(si + t * sj) * TILE);
+  for (int sb = 0; sb < (NB / SB) * (NB / SB); ++sb) {
+    const int lr0 = (sb % (NB / SB)) * SB, lc0 = (sb / (NB / SB)) * SB;
+#pragma unroll
+    for (int q = 0; q < SB / 8; ++q) {
+      const int j = ty + 8 * q;
+      L[tx][j] = ld1(rs, (lc0 + tx) + NB * (lr0 + j));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SB / 8; ++q) {
+      const int j = ty + 8 * q;
+      const int lr = lr0 + tx, lc = lc0 + j;
+      const int gr = bi * NB + lr, gc = bj * NB + lc;
+      if (gr < n && gc < n) {
+        const double v = (bi > bj || (bi == bj && lr >= lc)) ? ld1(rs, lr + NB * lc) : L[j][tx];
+        out[gr + (size_t)ld * gc] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// C tile <- s sum_k A(i, k) B(j, k)^T over t links (s = -1 when neg), stored
+// agent-coherent.  The operand tiles are written once in the launch and read
+// only after that write, so they are read through the L2.
+__device__ void bb_gemm_tile(const double* A, const double* B, double* C, int t, int i, int j,
+                             bool neg, double* smem) {
+  Acc acc;
+  acc_zero(acc);
+  auto pair = [&](int k, const double*& pa, const double*& pb) {
+    pa = A + (size_t)(i + t * k) * TILE;
+    pb = B + (size_t)(j + t * k) * TILE;
+  };
+  mma_chain<0, DKD>(acc, t, pair, smem);
+  acc_store_tile<CPOL_AGENT>(tile_rsrc(C), acc, neg);
+}
+
+__device__ __forceinline__ int bb_ready(int32_t* c, int target, const BBackArgs& g) {
+  const long long t0 = now_ticks();
+  long long spins = 0;
+  while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    __builtin_amdgcn_s_sleep(1);
+    if ((++spins & 63) == 0) {
+      if (__hip_atomic_load(&g.ctrl[CTRL_ABORT], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        return 0;
+      if (now_ticks() - t0 > g.spin_limit) {
+        __hip_atomic_store(&g.ctrl[CTRL_ABORT], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return 0;
+      }
+    }
+  }
+  return 1;
+}
+
+// The persistent loop: thread 0 claims a ticket and waits for the task's
+// inputs (counters of earlier phases, which hold earlier tickets: the loop is
+// deadlock-free for any grid); the workgroup runs the task; once its stores
+// have completed, thread 0 counts it.  Divergent regions sit between
+// barriers, and a barrier closes the loop body.
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void bback_kernel(BBackArgs g) {
+  __shared__ double smem[4 * DKD * LDS_STRIDE];
+  __shared__ int s_v;
+  double(*L)[SB + 1] = reinterpret_cast<double(*)[SB + 1]>(smem);
+  int32_t* done = nullptr;  // thread 0: counter of the previous task (or null)
+  for (;;) {
+    if (threadIdx.x == 0) {
+      if (done) __hip_atomic_fetch_add(done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      done = nullptr;
+      int v = __hip_atomic_fetch_add(&g.ctrl[CTRL_TICKET], 1, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT);
+      if (v >= g.ntask) v = -1;
+      if (v >= 0) {
+        const int2 tk = g.task[v];
+        const int4 mi = g.mat[tk.x];
+        const int t = mi.x, phase = tk.y >> BB_PHASE_SHIFT, i = (tk.y >> 8) & 0xff,
+                  j = tk.y & 0xff;
+        int32_t* c = g.cnt + mi.z;
+        int ok = 1;
+        if (phase == 1) ok = bb_ready(c, t * t, g);
+        else if (phase == 2) ok = bb_ready(c + 1 + i, t, g);
+        else if (phase == 3) ok = bb_ready(c + 1 + t + (i >= j ? i + t * j : j + t * i), 1, g);
+        if (!ok) v = -1;
+        if (phase == 0) done = c;
+        else if (phase == 1) done = c + 1 + i;
+        else if (phase == 2) done = c + 1 + t + i + t * j;
+      }
+      s_v = v;
+    }
+    __syncthreads();
+    const int v = __builtin_amdgcn_readfirstlane(s_v);
+    if (v < 0) break;
+    const int2 tk = g.task[v];
+    const int m = __builtin_amdgcn_readfirstlane(tk.x);
+    const int code = __builtin_amdgcn_readfirstlane(tk.y);
+    const int4 mi = g.mat[m];
+    const int t = __builtin_amdgcn_readfirstlane(mi.x);
+    const long long tb = (long long)__builtin_amdgcn_readfirstlane(mi.y);
+    const int phase = code >> BB_PHASE_SHIFT, i = (code >> 8) & 0xff, j = code & 0xff;
+    double* Xt = g.tiles + (size_t)tb * TILE;
+    double* St = Xt + (size_t)t * t * TILE;
+    double* Wt = St + (size_t)t * t * TILE;
+    double* Gt = Wt + (size_t)t * t * TILE;
+    // an order or leading dimension that does not fit the matrix's tile
+    // count is taken as order 0: its tasks run on zero tiles and write nothing
+    const int n0 = __builtin_amdgcn_readfirstlane(g.n[m]);
+    const int n = ((n0 + NB - 1) / NB == t) ? n0 : 0;
+    if (phase == 0) {
+      const int lx = __builtin_amdgcn_readfirstlane(g.ldx[m]);
+      const int lg = __builtin_amdgcn_readfirstlane(g.ldg[m]);
+      const int nn = (lx >= n && lg >= n) ? n : 0;
+      bb_pack_tile(uniform_ptr(g.X[m]), lx, nn, PACK_SYM_LOWER, i, j, Xt + (size_t)(i + t * j) * TILE, L);
+      bb_pack_tile(uniform_ptr(g.G[m]), lg, nn, PACK_SYM_AVG, i, j, St + (size_t)(i + t * j) * TILE, L);
+    } else if (phase == 1) {
+      // W = X S: W(i, j) = sum_k X(i, k) S(j, k)^T (S symmetric)
+      bb_gemm_tile(Xt, St, Wt + (size_t)(i + t * j) * TILE, t, i, j, false, smem);
+    } else if (phase == 2) {
+      // lower tile of -W X: -sum_k W(i, k) X(j, k)^T (X symmetric)
+      bb_gemm_tile(Wt, Xt, Gt + (size_t)(i + t * j) * TILE, t, i, j, true, smem);
+    } else {
+      const int lo = __builtin_amdgcn_readfirstlane(g.ldga[m]);
+      bb_unpack_tile(Gt, t, lo >= n ? n : 0, uniform_ptr(g.gradA[m]), lo, i, j, L);
+    }
+    stores_complete();
+    __syncthreads();
+  }
+}
+
 }  // namespace
+
+hipError_t launch_bback(const BBackArgs& b, int ncnt, int grid, hipStream_t s) {
+  const int total = ncnt > CTRL_WORDS ? ncnt : CTRL_WORDS;
+  hipLaunchKernelGGL(zero_kernel, dim3((total + 255) / 256), dim3(256), 0, s, b.cnt, ncnt, b.ctrl);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(bback_kernel, dim3(grid), dim3(NTHREADS), 0, s, b);
+  return hipGetLastError();
+}
+
+int bback_blocks_per_cu() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, bback_kernel, NTHREADS, 0) != hipSuccess)
+    return 1;
+  return blocks > 0 ? blocks : 1;
+}
 
 hipError_t launch_pack(const double* src, int ld, int n, int t, int mode, double* dst,
                        hipStream_t s) {

@@ -35,4 +35,33 @@ hipError_t launch_sumsq(const double* M, int ntiles, double* partial, double* ou
 // Upper tiles (and the upper part of diagonal tiles) <- mirror of the lower.
 hipError_t launch_mirror_lower(double* M, int t, hipStream_t s);
 
+// Batched backward: grad_i = -X_i sym(G_i) X_i for every matrix of a batch in
+// one persistent launch.  Tasks (m, code) with code = phase << 16 | i << 8 | j
+// run in ticket order, phases in order: 0 packs tile (i, j) of X_m (from its
+// lower triangle) and of S_m = sym(G_m); 1 forms W_m(i, j) = sum_k X(i, k)
+// S(j, k)^T once every tile of m is packed; 2 forms the lower tile (i, j) of
+// -W X once tile row i of W is complete; 3 writes output tile (i, j) of
+// grad_m (column-major, both triangles) once its lower source tile is done.
+// Per matrix (mat[m]: t, first workspace tile, first counter, 0): 4 t^2
+// tiles (X, S, W, the gradient) and 1 + t + t^2 counters.
+constexpr int BB_PHASE_SHIFT = 16;
+struct BBackArgs {
+  const int2* task;
+  int ntask;
+  const int4* mat;
+  const int* n;
+  const double* const* X;
+  const int* ldx;
+  const double* const* G;
+  const int* ldg;
+  double* const* gradA;
+  const int* ldga;
+  double* tiles;
+  int32_t* cnt;    // counters of every matrix
+  int32_t* ctrl;   // CTRL_WORDS: ticket, abort
+  long long spin_limit;
+};
+hipError_t launch_bback(const BBackArgs& b, int ncnt, int grid, hipStream_t s);
+int bback_blocks_per_cu();
+
 }  // namespace spdinv

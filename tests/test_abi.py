@@ -162,3 +162,23 @@ def test_every_source_is_built():
     csrc = os.path.join(ROOT, "paper_1002_4057_amd", "csrc")
     srcs = {f for f in os.listdir(csrc) if f.endswith((".hip", ".cpp"))}
     assert srcs == set(build.SOURCES)
+
+
+def test_batched_backward_arguments_rejected_on_host():
+    lib = _lib.load()
+    n = (ctypes.c_int * 2)(4, 300)
+    # 4 t^2 tiles per matrix (t = 1 and 3) and the counters
+    tiles = (4 * 1 + 4 * 9) * 128 * 128 * 8
+    assert tiles <= lib.batched_spd_inverse_backward_workspace_bytes(2, n) < tiles + 4096
+    assert lib.batched_spd_inverse_backward_workspace_bytes(1, (ctypes.c_int * 1)(2049)) == 0
+    args = [1, 1, 1, 1, 1, 1, 1, 1, 1, 1 << 40, None]
+    assert lib.batched_spd_inverse_backward(-1, n, *args) == -1
+    assert lib.batched_spd_inverse_backward(0, None, *args) == 0
+    assert lib.batched_spd_inverse_backward(2, None, *args) == -2
+    for pos in range(1, 9):   # d_n, d_X, d_ldx, d_G, d_ldg, d_gradA, d_ldga, work
+        a = list(args)
+        a[pos - 1] = None
+        assert lib.batched_spd_inverse_backward(2, n, *a) == -(pos + 2)
+    a = list(args)
+    a[9] = 16
+    assert lib.batched_spd_inverse_backward(2, n, *a) == _lib.ERR_WORKSPACE

@@ -165,3 +165,59 @@ def test_batched_small_matrices_against_oracle():
         r = rel_fro(got[i], ref) / (1e-12 * ev[-1] / ev[0])
         worst = max(worst, r)
     assert worst <= 1.0, worst
+
+
+# ---- batched backward (batched_spd_inverse_backward, one launch) ----------
+def test_batched_backward_matches_single_calls_and_oracle():
+    """Uneven orders in one launch: each gradient is the single-matrix
+    kernel's bit for bit (same tile products in the same order) and within
+    the rounding bound of the oracle's gradient."""
+    orders = [1, 5, 100, 128, 129, 300, 700, 0, 256]
+    xs, gs, refs = [], [], []
+    for k, n in enumerate(orders):
+        a = inputs.wishart_shift(n, seed=70 + k).numpy() if n else np.zeros((0, 0))
+        x = oracle.spd_inverse(a) if n else a
+        g = inputs.randn((n, n), seed=80 + k).numpy() if n else a
+        xs.append(dev(x))
+        gs.append(dev(g))
+        refs.append(oracle.inverse_grad(x, g) if n else a)
+    got = spd.batched_spd_inverse_backward(xs, gs)
+    for n, x, g, r, y in zip(orders, xs, gs, refs, got):
+        if n == 0:
+            continue
+        assert torch.equal(y, spd.spd_inverse_backward(x, g)), n
+        xn, gn = x.cpu().numpy(), g.cpu().numpy()
+        s = 0.5 * (gn + gn.T)
+        bound = 4.0 * gamma(n) * (np.abs(xn) @ np.abs(s) @ np.abs(xn)) + 1e-300
+        assert np.all(np.abs(y.cpu().numpy() - r) <= bound), n
+
+
+def test_batched_backward_workload_256_of_256():
+    """Differentiation workload (b): 256 matrices of n = 256 in one launch,
+    every gradient against the single-matrix call, 8 against the oracle."""
+    n, batch = 256, 256
+    a = torch.stack([inputs.wishart_shift(n, seed=900 + k) for k in range(batch)]).to(DEV)
+    x = torch.stack(spd.batched_spd_inverse(list(a)))
+    g = torch.stack([inputs.randn((n, n), seed=2000 + k) for k in range(batch)]).to(DEV)
+    got = spd.batched_spd_inverse_backward(list(x), list(g))
+    for k in range(batch):
+        assert torch.equal(got[k], spd.spd_inverse_backward(x[k], g[k])), k
+    for k in range(0, batch, 32):
+        xn, gn = x[k].cpu().numpy(), g[k].cpu().numpy()
+        ref = oracle.inverse_grad(xn, gn)
+        assert rel_fro(got[k].cpu().numpy(), ref) <= 1e-12
+
+
+def test_autograd_batched_branch_uses_the_batched_launches():
+    """SpdInverse on a (B, n, n) tensor: forward by batched_spd_inverse,
+    backward by batched_spd_inverse_backward; the gradient equals the
+    per-matrix autograd gradient."""
+    n, batch = 150, 12
+    a = torch.stack([inputs.wishart_shift(n, seed=300 + k) for k in range(batch)]).to(DEV)
+    g = torch.stack([inputs.randn((n, n), seed=400 + k) for k in range(batch)]).to(DEV)
+    ab = a.clone().requires_grad_(True)
+    (spd.spd_inverse_ad(ab) * g).sum().backward()
+    for k in range(batch):
+        ak = a[k].clone().requires_grad_(True)
+        (spd.spd_inverse_ad(ak) * g[k]).sum().backward()
+        assert torch.equal(ab.grad[k], ak.grad), k
