@@ -193,7 +193,7 @@ def precision_cells(n, q, kappas, modes, reps, work=None):
     return cells
 
 
-def batched_row(reps: int, mode: str = "fp64", group: int = 0):
+def batched_row(reps: int, mode: str = "fp64", group: int = 0, tune: bool = True):
     """Batched workload: 8192 matrices, n uniform on {16..512} (seed 0),
     A_i = B_i B_i^T / n_i + 0.1 I, in FP64 or FP32: one DAG over the batch in
     one persistent launch per step, timed eagerly and as the replay of a
@@ -218,6 +218,9 @@ def batched_row(reps: int, mode: str = "fp64", group: int = 0):
     n_dev = torch.tensor(orders, dtype=torch.int32, device=dev)
     info = torch.zeros(len(orders), dtype=torch.int32, device=dev)
     opts = {"batch_group": group} if group else {}
+    tuned = None
+    if tune and not group:
+        tuned = spd.autotune_batched(orders, mode, reps=2)
     work = spd.batched_spd_inverse_(ptrs, orders, n_dev, n_dev, mode=mode, info=info,
                                     **opts)   # warm: task lists
     torch.cuda.synchronize()
@@ -242,13 +245,17 @@ def batched_row(reps: int, mode: str = "fp64", group: int = 0):
     flops = float(sum(float(n) ** 3 for n in orders))
     peak = PEAK_FP64_TFLOPS if mode == "fp64" else PEAK_FP32_TFLOPS
     best = min(ms, ms_graph)
+    sched = (tuned or {}).get("batch_group", group)
+    how = {-1: "one workgroup per matrix", -2: "one list-scheduled DAG over the batch"}.get(
+        sched, f"one DAG over the batch in groups of {sched}" if sched and sched > 0
+        else "the library's schedule")
     out = {"workload": "8192 SPD matrices, n uniform on [16,512] (seed 0), A_i = B_i B_i^T/n_i "
-                       f"+ 0.1 I, {mode.upper()}, one DAG over the batch in one persistent launch",
+                       f"+ 0.1 I, {mode.upper()}, one persistent launch ({how})",
            "ms": round(ms, 3), "ms_graph_replay": round(ms_graph, 3),
            "matrices_per_s": round(len(orders) / (best / 1e3), 1),
            "gflops": round(flops / (best / 1e3) / 1e9, 1), "flops": flops,
            f"frac_{mode}_peak": round(flops / (best / 1e3) / 1e12 / peak, 4),
-           "workspace_gb": round(work.numel() / 1e9, 2), "reps": reps}
+           "workspace_gb": round(work.numel() / 1e9, 2), "reps": reps, "tuned": tuned}
     del work, buf, src
     torch.cuda.empty_cache()
     return out
@@ -364,12 +371,18 @@ def backward_row(reps: int):
     a = torch.stack([inputs.wishart_shift(nb, seed=k) for k in range(batch)]).to(dev)
     xs = spd.batched_spd_inverse(list(a))
     gs = [inputs.randn((nb, nb), seed=10000 + k).to(dev) for k in range(batch)]
-    outs = [torch.empty_like(v) for v in xs]
+    outs = [torch.empty((nb, nb), dtype=torch.float64, device=dev) for _ in xs]
     bwork = torch.empty(spd.batched_backward_workspace_bytes([nb] * batch), dtype=torch.uint8,
                         device=dev)
-    spd.batched_spd_inverse_backward(xs, gs, work=bwork, out=outs)
+    xs = [v.contiguous() for v in xs]
+    ptr = lambda ts: torch.tensor([v.data_ptr() for v in ts], dtype=torch.int64, device=dev)  # noqa
+    px, pg, po = ptr(xs), ptr(gs), ptr(outs)
+    nd = torch.full((batch,), nb, dtype=torch.int32, device=dev)
+    orders = [nb] * batch
+    spd.batched_spd_inverse_backward_(orders, nd, px, nd, pg, nd, po, nd, bwork)
     torch.cuda.synchronize()
-    msb = time_events(lambda: spd.batched_spd_inverse_backward(xs, gs, work=bwork, out=outs), reps)
+    msb = time_events(lambda: spd.batched_spd_inverse_backward_(orders, nd, px, nd, pg, nd, po, nd,
+                                                                bwork), reps)
     fb = 3.0 * float(nb) ** 3 * batch
     row["batched"] = {"workload": "backward of 256 inverses of n=256, FP64, one batched launch "
                                   "(3 n^3 flops each)",
@@ -399,6 +412,8 @@ def main():
     ap.add_argument("--large-n", type=int, default=32768)
     ap.add_argument("--large-kappas", default="1e2")
     ap.add_argument("--large-modes", default="fp64,mixed_fp32")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (built-in schedule choices)")
     ap.add_argument("--batch-group", type=int, default=0,
                     help="batched rows: matrices per dispatch group (0 = library choice)")
     ap.add_argument("--input", choices=["spectrum", "wishart"], default="spectrum",
@@ -433,6 +448,12 @@ def main():
         a = 0.5 * (a + a.t())
         del b0
         q = lam = None
+    tuned = None
+    if not args.no_tune:
+        log(f"[bench] autotuning the schedule at n={n}")
+        t0 = time.perf_counter()
+        tuned = spd.autotune(n, reps=2)
+        tuned["tuning_s"] = round(time.perf_counter() - t0, 1)
     a_cm = a.t().contiguous()                       # column-major storage of A
     bufs = [a_cm.clone() for _ in range(K + W)]
     work = torch.empty(spd.workspace_bytes(n), dtype=torch.uint8, device=dev)
@@ -517,9 +538,11 @@ def main():
         torch.cuda.empty_cache()
     if "batched" in wanted:
         log("[bench] batched row (FP64)")
-        rows["batched"] = batched_row(max(2, min(K, 5)), "fp64", args.batch_group)
+        rows["batched"] = batched_row(max(2, min(K, 5)), "fp64", args.batch_group,
+                                      not args.no_tune)
         log("[bench] batched row (FP32)")
-        rows["batched_fp32"] = batched_row(max(2, min(K, 5)), "fp32", args.batch_group)
+        rows["batched_fp32"] = batched_row(max(2, min(K, 5)), "fp32", args.batch_group,
+                                           not args.no_tune)
     if "backward" in wanted:
         log("[bench] backward row")
         rows["backward"] = backward_row(max(2, min(K, 5)))
@@ -547,7 +570,7 @@ def main():
                                f"[1,{args.kappa:g}]",
                    "n": n, "nb": rep["nb"] if rep else None, "kappa": args.kappa,
                    "variant": "renamed, UDU, pipelined",
-                   "workers": rep["workers"] if rep else None},
+                   "workers": rep["workers"] if rep else None, "tuned": tuned},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                      "traffic": traffic_per_launch(n), "kernel": "sched_kernel",

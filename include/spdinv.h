@@ -393,6 +393,54 @@ int batched_spd_inverse_backward(int batch, const int* h_n, const int* d_n,
                                  double* const* d_gradA, const int* d_ldga, void* work,
                                  size_t work_bytes, spdinv_stream_t stream);
 
+/* ---- autotuner ------------------------------------------------------------ */
+typedef struct {
+  int nb;            /* tile order (128: the tile kernels of this library)        */
+  int per_cu;        /* FP64 form: workgroups per CU chosen                       */
+  int chain;         /* products per device task chosen                           */
+  int parts;         /* FP64 form: row parts of split products (0 = whole)        */
+  int batch_group;   /* batched form: schedule chosen (as spdinv_opts.batch_group) */
+  double ms;         /* median time of the chosen candidate                       */
+  double ms_default; /* median time of the built-in choice                        */
+  int candidates;    /* candidates timed                                          */
+} spdinv_tuning;
+
+/*
+ * Autotuner of the FP64 single-matrix form for order n (1 <= n <= 65536):
+ * times schedules on a synthetic SPD matrix of order n (generated on the
+ * device; the task DAG does not depend on the values), `reps` timed calls
+ * each (median, HIP events on `stream`, after one untimed call), by
+ * coordinate descent from the built-in choice over workgroups per CU {1, 2},
+ * products per device task {6, 8, 12} and row parts of the split products
+ * {whole, halves, quarters}.  The fastest becomes the library's choice for
+ * every matrix of the same tile count, for the fields that callers leave at
+ * 0 in spdinv_opts.  Allocates and frees its own device buffers (two n x n
+ * matrices and the workspace) and synchronizes the stream.  Returns 0, -1
+ * for an invalid n, or SPDINV_ERR_HIP.
+ */
+int spdinv_autotune(int n, int reps, spdinv_stream_t stream, spdinv_tuning* out);
+
+/*
+ * Autotuner of the batched form for a batch of these orders (as for
+ * batched_spd_inverse) in mode SPDINV_FP64 or SPDINV_FP32: times the
+ * schedules batch_group = -1, -2 and 512, and in FP64 chains of 4 and 8
+ * products, on synthetic SPD matrices of the same orders; the fastest
+ * becomes the library's choice for batches with the same number of
+ * matrices of each tile count.  Allocates and frees its own device buffers
+ * and synchronizes the stream.  Returns 0, -i for an invalid i-th argument,
+ * or SPDINV_ERR_HIP.
+ */
+int spdinv_autotune_batched(int batch, const int* h_n, spdinv_mode mode, int reps,
+                            spdinv_stream_t stream, spdinv_tuning* out);
+
+/* Forgets every tuned choice (the built-in choices apply again). */
+int spdinv_tuning_clear(void);
+/* Writes the tuned choices to a text file / adds those of a file written by
+   spdinv_tuning_save.  Return 0, or a negative value when the file cannot
+   be written or read or is malformed (nothing is added then). */
+int spdinv_tuning_save(const char* path);
+int spdinv_tuning_load(const char* path);
+
 /* Frees every cached plan (device arena and host tables).  The host tables of
    spd_inverse_noalloc's plans are kept, since an upload from them may still
    be pending on a stream. */

@@ -29,7 +29,8 @@ __all__ = ["spd_inverse", "spd_inverse_", "workspace_bytes", "plan_stats", "plan
            "cholesky", "cholesky_", "inverse_from_factor", "inverse_from_factor_",
            "solve", "solve_", "solve_from_factor", "solve_from_factor_", "solve_workspace_bytes",
            "spd_inverse_noalloc_", "batched_spd_inverse_backward",
-           "batched_backward_workspace_bytes", "SpdInverseError", "NotPositiveDefinite"]
+           "batched_backward_workspace_bytes", "batched_spd_inverse_backward_", "autotune", "autotune_batched", "tuning_save",
+           "tuning_load", "tuning_clear", "SpdInverseError", "NotPositiveDefinite"]
 
 
 class SpdInverseError(RuntimeError):
@@ -435,6 +436,24 @@ def batched_backward_workspace_bytes(orders) -> int:
                                                                    _int_array(orders)))
 
 
+def batched_spd_inverse_backward_(orders, n_dev, px, ldx, pg, ldg, pout, ldo, work):
+    """Low-level batched backward: CUDA int64 tensors of device pointers (px,
+    pg, pout: column-major float64 matrices), CUDA int32 tensors of orders
+    and leading dimensions, the host list of orders and a workspace of at
+    least ``batched_backward_workspace_bytes(orders)`` bytes.  Asynchronous
+    on the current stream."""
+    lib = load()
+    need = int(lib.batched_spd_inverse_backward_workspace_bytes(len(orders), _int_array(orders)))
+    if work.numel() * work.element_size() < need:
+        raise ValueError(f"workspace too small: need {need} bytes")
+    rc = lib.batched_spd_inverse_backward(len(orders), _int_array(orders), n_dev.data_ptr(),
+                                          px.data_ptr(), ldx.data_ptr(), pg.data_ptr(),
+                                          ldg.data_ptr(), pout.data_ptr(), ldo.data_ptr(),
+                                          work.data_ptr(), need, _stream_ptr(work.device))
+    if rc != 0:
+        raise SpdInverseError(f"batched_spd_inverse_backward returned {rc}")
+
+
 def batched_spd_inverse_backward(xs, gs, *, work=None, out=None):
     """Gradients -X_i sym(g_i) X_i for lists of square CUDA float64 tensors
     (X_i symmetric, e.g. outputs of ``spd_inverse``; g_i any), computed in one
@@ -485,6 +504,53 @@ def batched_spd_inverse_backward(xs, gs, *, work=None, out=None):
     # (the pointer tables may be freed now: torch reuses their memory only for
     # work ordered after this launch on the stream)
     return out
+
+
+def _tuning_dict(t) -> dict:
+    return {f: getattr(t, f) for f, _ in _lib.Tuning._fields_}
+
+
+def autotune(n: int, reps: int = 3) -> dict:
+    """Times the FP64 form's schedules at order n on the current device (a
+    synthetic SPD matrix, coordinate descent over workgroups per CU, products
+    per device task and the row parts of split products) and makes the
+    fastest the library's choice for that tile count.  Returns the choice,
+    its time and the built-in choice's time."""
+    import torch
+    t = _lib.Tuning()
+    rc = load().spdinv_autotune(int(n), int(reps), _stream_ptr(torch.cuda.current_device()),
+                                ctypes.byref(t))
+    if rc != 0:
+        raise SpdInverseError(f"spdinv_autotune returned {rc}")
+    return _tuning_dict(t)
+
+
+def autotune_batched(orders, mode: str = "fp64", reps: int = 3) -> dict:
+    """Times the batched form's schedules for a batch of these orders (on
+    synthetic SPD matrices) and makes the fastest the library's choice for
+    batches with the same number of matrices of each tile count."""
+    import torch
+    t = _lib.Tuning()
+    rc = load().spdinv_autotune_batched(len(orders), _int_array(orders), _batched_mode(mode),
+                                        int(reps),
+                                        _stream_ptr(torch.cuda.current_device()), ctypes.byref(t))
+    if rc != 0:
+        raise SpdInverseError(f"spdinv_autotune_batched returned {rc}")
+    return _tuning_dict(t)
+
+
+def tuning_save(path: str) -> None:
+    if load().spdinv_tuning_save(path.encode()) != 0:
+        raise OSError(f"cannot write the tuning file {path}")
+
+
+def tuning_load(path: str) -> None:
+    if load().spdinv_tuning_load(path.encode()) != 0:
+        raise OSError(f"cannot read the tuning file {path}")
+
+
+def tuning_clear() -> None:
+    load().spdinv_tuning_clear()
 
 
 def _autograd_function():

@@ -47,6 +47,12 @@ class Report(ctypes.Structure):
                 ("predicted", ctypes.c_int)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("nb", ctypes.c_int), ("per_cu", ctypes.c_int), ("chain", ctypes.c_int),
+                ("parts", ctypes.c_int), ("batch_group", ctypes.c_int), ("ms", ctypes.c_double),
+                ("ms_default", ctypes.c_double), ("candidates", ctypes.c_int)]
+
+
 class PlanStats(ctypes.Structure):
     _fields_ = [("tasks", ctypes.c_longlong), ("edges", ctypes.c_longlong),
                 ("count", ctypes.c_longlong * 16), ("cp_step", ctypes.c_int * 3),
@@ -123,6 +129,16 @@ def load():
     lib.batched_spd_inverse_backward_workspace_bytes.restype = sz
     lib.batched_spd_inverse_backward.argtypes = [i, ip, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.batched_spd_inverse_backward.restype = i
+    lib.spdinv_autotune.argtypes = [i, i, vp, P(Tuning)]
+    lib.spdinv_autotune.restype = i
+    lib.spdinv_autotune_batched.argtypes = [i, ip, i, i, vp, P(Tuning)]
+    lib.spdinv_autotune_batched.restype = i
+    lib.spdinv_tuning_clear.argtypes = []
+    lib.spdinv_tuning_clear.restype = i
+    lib.spdinv_tuning_save.argtypes = [ctypes.c_char_p]
+    lib.spdinv_tuning_save.restype = i
+    lib.spdinv_tuning_load.argtypes = [ctypes.c_char_p]
+    lib.spdinv_tuning_load.restype = i
     lib.spd_inverse_noalloc.argtypes = [i, vp, i, vp, P(Opts), vp]
     lib.spd_inverse_noalloc.restype = i
     lib.spdinv_version.argtypes = []

@@ -6,6 +6,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -203,6 +204,62 @@ int grid_for(int device, int t, const spdinv_opts& o) {
   return g;
 }
 
+// ---- tuning tables (filled by spdinv_autotune*, read by the entry points) ---
+// FP64 single-matrix form, per tile count: the schedule that the autotuner
+// measured fastest.  Entry points apply it to every field the caller left at
+// 0 (library choice).
+struct TunedFp64 {
+  int per_cu, chain, split;  // split: 0 = whole products, 2 = halves, 4 = quarters
+};
+std::map<int, TunedFp64> g_tuned64;
+
+// Batched form, per (precision, count of matrices of each tile count).
+struct TunedBatch {
+  int group, chain;
+};
+typedef std::pair<int, std::vector<int>> TBKey;
+std::map<TBKey, TunedBatch> g_tuned_batch;
+
+// o with the library-choice fields of the FP64 form at t tiles per side
+// resolved from the tuning table (fields without an entry keep 0, the
+// built-in choice).
+spdinv_opts tuned_fp64(const spdinv_opts& o, int t) {
+  spdinv_opts r = o;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_tuned64.find(t);
+  if (it == g_tuned64.end()) return r;
+  if (r.per_cu == 0) r.per_cu = it->second.per_cu;
+  if (r.chain == 0) r.chain = it->second.chain;
+  if (r.parts == 0 && !r.no_split) {
+    if (it->second.split == 0) r.no_split = 1;
+    else r.parts = it->second.split;
+  }
+  return r;
+}
+
+TBKey batch_key(bool fp32, const int* h_n, int batch) {
+  std::vector<int> counts(MAX_BATCH_T + 1, 0);
+  for (int i = 0; i < batch; ++i) {
+    const int n = h_n[i];
+    const int t = n <= NB ? 1 : (n + NB - 1) / NB;
+    if (t >= 1 && t <= MAX_BATCH_T) ++counts[t];
+  }
+  return TBKey(fp32 ? 1 : 0, counts);
+}
+
+// The batched form's options with batch_group and chain resolved from the
+// tuning table when the caller left them at 0.
+spdinv_opts tuned_batch(const spdinv_opts& o, bool fp32, const int* h_n, int batch) {
+  spdinv_opts r = o;
+  if (r.batch_group != 0 && r.chain != 0) return r;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_tuned_batch.find(batch_key(fp32, h_n, batch));
+  if (it == g_tuned_batch.end()) return r;
+  if (r.batch_group == 0) r.batch_group = it->second.group;
+  if (r.chain == 0 && !fp32) r.chain = it->second.chain;
+  return r;
+}
+
 // Device-table image of a built plan: the task list permuted into dispatch
 // order (a task's id on the device is its dispatch ticket), successors
 // renumbered to dispatch positions.
@@ -339,8 +396,9 @@ long long spin_limit() {
 // `given`: the plan with its device tables already in place (the
 // allocation-free entry point); null = the cached plan in its arena.
 int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream_t stream,
-             const spdinv_opts& o, int* d_info, spdinv_report* report, int steps = 7,
+             const spdinv_opts& o_in, int* d_info, spdinv_report* report, int steps = 7,
              int nrhs = 0, double* Bm = nullptr, int ldb = 1, DevPlan* given = nullptr) {
+  const spdinv_opts o = tuned_fp64(o_in, tiles_for(n));
   const Layout L = layout(n, o, nrhs);
   const int s = (nrhs + NB - 1) / NB;
   if (work_bytes < L.total) return SPDINV_ERR_WORKSPACE;
@@ -1010,9 +1068,9 @@ size_t batched_spd_inverse_workspace_bytes(int batch, const int* h_n, spdinv_mod
                                            const spdinv_opts* opts) {
   if (batch <= 0 || batch > MAX_BATCH || !h_n) return 0;
   if (mode != SPDINV_FP64 && mode != SPDINV_FP32) return 0;
-  const spdinv_opts o = opts ? *opts : defaults();
-  if (check_opts(o)) return 0;
   const bool fp32 = mode == SPDINV_FP32;
+  const spdinv_opts o = tuned_batch(opts ? *opts : defaults(), fp32, h_n, batch);
+  if (check_opts(o)) return 0;
   long long ncnt, ptiles;
   if (batch_bounds(batch, h_n, &ncnt, &ptiles)) return 0;
   const int workers = batch_sim_workers(o);
@@ -1036,7 +1094,7 @@ int batched_spd_inverse(int batch, const int* h_n, const int* d_n, void* const* 
   if (!d_lda) return -5;
   if (mode != SPDINV_FP64 && mode != SPDINV_FP32) return -6;
   const bool fp32 = mode == SPDINV_FP32;
-  const spdinv_opts o = opts ? *opts : defaults();
+  const spdinv_opts o = tuned_batch(opts ? *opts : defaults(), fp32, h_n, batch);
   if (check_opts(o) || (fp32 && !o.renamed)) return -10;
   long long ncnt_bound, ptiles;
   if (batch_bounds(batch, h_n, &ncnt_bound, &ptiles)) return -2;
@@ -1628,9 +1686,10 @@ int spd_inverse_noalloc(int n, double* A, int lda, spdinv_stream_t stream_,
   if (n < 0 || n > SPDINV_NOALLOC_MAX_N) return -1;
   if (n > 0 && !A) return -2;
   if (lda < (n > 1 ? n : 1)) return -3;
-  const spdinv_opts o = opts ? *opts : defaults();
-  if (check_opts(o) || o.trace) return -5;
+  const spdinv_opts o0 = opts ? *opts : defaults();
+  if (check_opts(o0) || o0.trace) return -5;
   if (n == 0) return launch_info_zero(d_info, stream) == hipSuccess ? 0 : SPDINV_ERR_HIP;
+  const spdinv_opts o = tuned_fp64(o0, tiles_for(n));
   int device = 0;
   if (hipGetDevice(&device) != hipSuccess) return SPDINV_ERR_HIP;
   char* scratch = nullptr;
@@ -1669,6 +1728,297 @@ int spd_inverse_noalloc(int n, double* A, int lda, spdinv_stream_t stream_,
     return SPDINV_ERR_HIP;
   }
   return run_fp64(n, A, lda, work, work_bytes, stream, o, d_info, nullptr, 7, 0, nullptr, 1, dp);
+}
+
+// ---- autotuner ---------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+// Median over reps of one timed call (HIP events on `stream`); prep runs
+// before each call, untimed.  Returns a negative value on an error.
+template <class Prep, class Call>
+double time_median(hipStream_t stream, int reps, Prep prep, Call call) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return -1.0;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return -1.0;
+  }
+  std::vector<double> ms;
+  bool ok = true;
+  for (int r = 0; r < reps && ok; ++r) {
+    ok = prep() == hipSuccess && hipEventRecord(e0, stream) == hipSuccess && call() == 0 &&
+         hipEventRecord(e1, stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+    float v = 0.0f;
+    ok = ok && hipEventElapsedTime(&v, e0, e1) == hipSuccess;
+    ms.push_back(v);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!ok) return -1.0;
+  std::sort(ms.begin(), ms.end());
+  return ms[ms.size() / 2];
+}
+
+// Device buffers of a tuning run, freed on every exit.
+struct DevBufs {
+  std::vector<void*> p;
+  void* get(size_t bytes, hipError_t* e) {
+    void* q = nullptr;
+    *e = hipMalloc(&q, bytes ? bytes : 1);
+    if (*e == hipSuccess) p.push_back(q);
+    return *e == hipSuccess ? q : nullptr;
+  }
+  ~DevBufs() {
+    for (void* q : p) (void)hipFree(q);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int spdinv_autotune(int n, int reps, spdinv_stream_t stream_, spdinv_tuning* out) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  if (n < 1 || n > 65536) return -1;
+  if (reps < 1) reps = 3;
+  const int t = tiles_for(n);
+  // the built-in choice, then coordinate descent over one knob at a time
+  TunedFp64 best{t >= kWideTiles ? 2 : 1, kDefaultChain, t < kWideTiles ? 4 : 2};
+  const int per_cu_c[] = {1, 2}, chain_c[] = {6, 8, 12}, split_c[] = {0, 2, 4};
+  size_t wmax = 0;
+  for (int pc : per_cu_c)
+    for (int sp : split_c) {
+      spdinv_opts o = defaults();
+      o.per_cu = pc;
+      o.parts = sp;
+      o.no_split = sp == 0;
+      wmax = std::max(wmax, layout(n, o).total);
+    }
+  DevBufs bufs;
+  hipError_t e = hipSuccess;
+  double* A0 = (double*)bufs.get((size_t)n * n * sizeof(double), &e);
+  double* A = (double*)bufs.get((size_t)n * n * sizeof(double), &e);
+  void* work = bufs.get(wmax, &e);
+  void** ptr = (void**)bufs.get(sizeof(void*), &e);
+  int* ord = (int*)bufs.get(sizeof(int), &e);
+  if (e != hipSuccess) return SPDINV_ERR_HIP;
+  if (hipMemcpyAsync(ptr, &A0, sizeof(void*), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(ord, &n, sizeof(int), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      launch_fill_spd(ptr, ord, 1, false, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return SPDINV_ERR_HIP;
+  int count = 0;
+  auto measure = [&](const TunedFp64& c) -> double {
+    spdinv_opts o = defaults();
+    o.per_cu = c.per_cu;
+    o.chain = c.chain;
+    o.parts = c.split;
+    o.no_split = c.split == 0;
+    auto prep = [&]() {
+      return hipMemcpyAsync(A, A0, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, stream);
+    };
+    auto call = [&]() {
+      return spd_inverse(n, A, n, SPDINV_FP64, work, wmax, (spdinv_stream_t)stream, &o, nullptr,
+                         nullptr);
+    };
+    if (time_median(stream, 1, prep, call) < 0.0) return -1.0;  // plan and warm-up
+    ++count;
+    return time_median(stream, reps, prep, call);
+  };
+  const double ms_default = measure(best);
+  if (ms_default < 0.0) return SPDINV_ERR_HIP;
+  double ms_best = ms_default;
+  for (int dim = 0; dim < 3; ++dim) {
+    const int* cand = dim == 0 ? per_cu_c : dim == 1 ? chain_c : split_c;
+    const int nc = dim == 0 ? 2 : 3;
+    TunedFp64 base = best;
+    for (int q = 0; q < nc; ++q) {
+      TunedFp64 c = base;
+      (dim == 0 ? c.per_cu : dim == 1 ? c.chain : c.split) = cand[q];
+      if (c.per_cu == base.per_cu && c.chain == base.chain && c.split == base.split) continue;
+      const double ms = measure(c);
+      if (ms < 0.0) return SPDINV_ERR_HIP;
+      if (ms < ms_best) {
+        ms_best = ms;
+        best = c;
+      }
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tuned64[t] = best;
+  }
+  if (out) {
+    std::memset(out, 0, sizeof(*out));
+    out->nb = NB;
+    out->per_cu = best.per_cu;
+    out->chain = best.chain;
+    out->parts = best.split;
+    out->ms = ms_best;
+    out->ms_default = ms_default;
+    out->candidates = count;
+  }
+  return 0;
+}
+
+int spdinv_autotune_batched(int batch, const int* h_n, spdinv_mode mode, int reps,
+                            spdinv_stream_t stream_, spdinv_tuning* out) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+  if (batch < 1 || batch > MAX_BATCH) return -1;
+  if (!h_n) return -2;
+  for (int i = 0; i < batch; ++i)
+    if (h_n[i] < 0 || h_n[i] > MAX_BATCH_T * NB) return -2;
+  if (mode != SPDINV_FP64 && mode != SPDINV_FP32) return -3;
+  if (reps < 1) reps = 3;
+  const bool fp32 = mode == SPDINV_FP32;
+  const size_t es = fp32 ? sizeof(float) : sizeof(double);
+  // candidates: one workgroup per matrix, the list-scheduled DAG, groups of
+  // 512; chains of 4 and 8 products (FP64)
+  std::vector<TunedBatch> cand;
+  for (int g : {-1, -2, 512})
+    for (int c : {4, 8})
+      if (!fp32 || c == 4) cand.push_back(TunedBatch{g, fp32 ? 1 : c});
+  std::vector<size_t> off(batch + 1, 0);
+  for (int i = 0; i < batch; ++i) off[i + 1] = off[i] + (size_t)h_n[i] * h_n[i] * es;
+  size_t wmax = 0;
+  for (const TunedBatch& c : cand) {
+    spdinv_opts o = defaults();
+    o.batch_group = c.group;
+    o.chain = fp32 ? 0 : c.chain;
+    wmax = std::max(wmax, batched_spd_inverse_workspace_bytes(batch, h_n, mode, &o));
+  }
+  DevBufs bufs;
+  hipError_t e = hipSuccess;
+  char* A0 = (char*)bufs.get(off[batch], &e);
+  char* A = (char*)bufs.get(off[batch], &e);
+  void** p0 = (void**)bufs.get(batch * sizeof(void*), &e);
+  void** p = (void**)bufs.get(batch * sizeof(void*), &e);
+  int* dn = (int*)bufs.get(batch * sizeof(int), &e);
+  void* work = bufs.get(wmax, &e);
+  if (e != hipSuccess) return SPDINV_ERR_HIP;
+  std::vector<void*> hp0(batch), hp(batch);
+  for (int i = 0; i < batch; ++i) {
+    hp0[i] = A0 + off[i];
+    hp[i] = A + off[i];
+  }
+  if (hipMemcpy(p0, hp0.data(), batch * sizeof(void*), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p, hp.data(), batch * sizeof(void*), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(dn, h_n, batch * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      launch_fill_spd(p0, dn, batch, fp32, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return SPDINV_ERR_HIP;
+  TunedBatch best{0, 0};
+  double ms_best = -1.0, ms_default = -1.0;
+  int count = 0;
+  for (const TunedBatch& c : cand) {
+    spdinv_opts o = defaults();
+    o.batch_group = c.group;
+    o.chain = fp32 ? 0 : c.chain;
+    auto prep = [&]() { return hipMemcpyAsync(A, A0, off[batch], hipMemcpyDeviceToDevice, stream); };
+    auto call = [&]() {
+      return batched_spd_inverse(batch, h_n, dn, p, dn, mode, work, wmax,
+                                 (spdinv_stream_t)stream, &o, nullptr);
+    };
+    if (time_median(stream, 1, prep, call) < 0.0) return SPDINV_ERR_HIP;
+    ++count;
+    const double ms = time_median(stream, reps, prep, call);
+    if (ms < 0.0) return SPDINV_ERR_HIP;
+    // the built-in choice: the schedule picked by batch size, chain 8
+    const int builtin = batch >= 2 * kBatchSimWorkers ? -1 : -2;
+    if (c.group == builtin && (fp32 || c.chain == kDefaultChain)) ms_default = ms;
+    if (ms_best < 0.0 || ms < ms_best) {
+      ms_best = ms;
+      best = c;
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tuned_batch[batch_key(fp32, h_n, batch)] = best;
+  }
+  if (out) {
+    std::memset(out, 0, sizeof(*out));
+    out->nb = NB;
+    out->chain = best.chain;
+    out->batch_group = best.group;
+    out->ms = ms_best;
+    out->ms_default = ms_default;
+    out->candidates = count;
+  }
+  return 0;
+}
+
+int spdinv_tuning_clear(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_tuned64.clear();
+  g_tuned_batch.clear();
+  return 0;
+}
+
+int spdinv_tuning_save(const char* path) {
+  if (!path) return -1;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return -1;
+  std::lock_guard<std::mutex> lk(g_mu);
+  std::fprintf(f, "spdinv-tuning 1\n");
+  for (const auto& kv : g_tuned64)
+    std::fprintf(f, "fp64 %d %d %d %d\n", kv.first, kv.second.per_cu, kv.second.chain,
+                 kv.second.split);
+  for (const auto& kv : g_tuned_batch) {
+    std::fprintf(f, "batch %d %d %d", kv.first.first, kv.second.group, kv.second.chain);
+    for (int c : kv.first.second) std::fprintf(f, " %d", c);
+    std::fprintf(f, "\n");
+  }
+  const int rc = std::fclose(f) == 0 ? 0 : -1;
+  return rc;
+}
+
+int spdinv_tuning_load(const char* path) {
+  if (!path) return -1;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return -1;
+  char tag[32];
+  int ver = 0;
+  if (std::fscanf(f, "%31s %d", tag, &ver) != 2 || std::strcmp(tag, "spdinv-tuning") != 0 ||
+      ver != 1) {
+    std::fclose(f);
+    return -2;
+  }
+  std::map<int, TunedFp64> t64;
+  std::map<TBKey, TunedBatch> tb;
+  int rc = 0;
+  while (std::fscanf(f, "%31s", tag) == 1) {
+    if (std::strcmp(tag, "fp64") == 0) {
+      int t, pc, ch, sp;
+      if (std::fscanf(f, "%d %d %d %d", &t, &pc, &ch, &sp) != 4 || t < 1 || pc < 1 || pc > 2 ||
+          ch < 1 || ch > MAX_CHAIN || (sp != 0 && sp != 2 && sp != 4)) {
+        rc = -2;
+        break;
+      }
+      t64[t] = TunedFp64{pc, ch, sp};
+    } else if (std::strcmp(tag, "batch") == 0) {
+      int fp, g, ch;
+      if (std::fscanf(f, "%d %d %d", &fp, &g, &ch) != 3 || g < -2 || ch < 1 || ch > MAX_CHAIN) {
+        rc = -2;
+        break;
+      }
+      std::vector<int> counts(MAX_BATCH_T + 1, 0);
+      for (int k = 0; k <= MAX_BATCH_T && rc == 0; ++k)
+        if (std::fscanf(f, "%d", &counts[k]) != 1) rc = -2;
+      if (rc) break;
+      tb[TBKey(fp ? 1 : 0, counts)] = TunedBatch{g, ch};
+    } else {
+      rc = -2;
+      break;
+    }
+  }
+  std::fclose(f);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> lk(g_mu);
+  for (const auto& kv : t64) g_tuned64[kv.first] = kv.second;
+  for (const auto& kv : tb) g_tuned_batch[kv.first] = kv.second;
+  return 0;
 }
 
 void spdinv_release_plans(void) {
@@ -1762,7 +2112,9 @@ long long spdinv_batch_plan_export(int batch, const int* h_n, spdinv_mode mode,
                                    int32_t* mat4) {
   if (batch < 1 || batch > MAX_BATCH || !h_n) return -1;
   if (mode != SPDINV_FP64 && mode != SPDINV_FP32) return -2;
-  const spdinv_opts o = opts ? *opts : defaults();
+  for (int i = 0; i < batch; ++i)
+    if (h_n[i] < 0 || h_n[i] > MAX_BATCH_T * NB) return -1;
+  const spdinv_opts o = tuned_batch(opts ? *opts : defaults(), mode == SPDINV_FP32, h_n, batch);
   if (check_opts(o)) return -3;
   std::vector<int8_t> tv(batch);
   for (int i = 0; i < batch; ++i) {
@@ -1786,7 +2138,7 @@ long long spdinv_batch_plan_export(int batch, const int* h_n, spdinv_mode mode,
 long long spdinv_trace_copy(const void* work, int n, const spdinv_opts* opts, int64_t* host,
                             long long max_tasks) {
   if (!work || !host || n <= 0 || !opts || !opts->trace) return -1;
-  const spdinv_opts o = *opts;
+  const spdinv_opts o = tuned_fp64(*opts, tiles_for(n));
   const Layout L = layout(n, o);
   int device = 0;
   if (hipGetDevice(&device) != hipSuccess) return -2;

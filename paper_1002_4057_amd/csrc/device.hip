@@ -111,6 +111,23 @@ __global__ __launch_bounds__(NTHREADS) void copy_out_kernel(const double* __rest
 
 __global__ void info_zero_kernel(int* d_info) { d_info[0] = 0; }
 
+// A synthetic SPD matrix for timing runs (the autotuner): a_ij = 1/(1+|i-j|)
+// off the diagonal, a_ii = n (strictly diagonally dominant), column-major
+// with ld = n; in FP64 or FP32, for every matrix of a pointer array.
+template <class E>
+__global__ void fill_spd_kernel(E* const* mats, const int* orders, int count) {
+  for (int m = blockIdx.y; m < count; m += gridDim.y) {
+    const int n = orders[m];
+    E* A = mats[m];
+    const long long total = (long long)n * n;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+      const int r = (int)(e % n), c = (int)(e / n);
+      A[e] = r == c ? (E)n : (E)(1.0 / (1.0 + (r > c ? r - c : c - r)));
+    }
+  }
+}
+
 __global__ void info_out_kernel(const int32_t* ctrl, int* d_info) {
   const int v = ctrl[CTRL_INFO];
   d_info[0] = (v == INT_MAX) ? 0 : v;
@@ -183,6 +200,18 @@ hipError_t launch_copy_out(const double* pool, int t, double* A, int lda, int n,
                            hipStream_t s) {
   const int T = t * (t + 1) / 2;
   hipLaunchKernelGGL(copy_out_kernel, dim3(T), dim3(NTHREADS), 0, s, pool, A, lda, n, fill_upper);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_spd(void* const* mats, const int* orders, int count, bool fp32,
+                           hipStream_t s) {
+  const dim3 grid(64, count < 4096 ? count : 4096);
+  if (fp32)
+    hipLaunchKernelGGL(fill_spd_kernel<float>, grid, dim3(256), 0, s, (float* const*)mats, orders,
+                       count);
+  else
+    hipLaunchKernelGGL(fill_spd_kernel<double>, grid, dim3(256), 0, s, (double* const*)mats,
+                       orders, count);
   return hipGetLastError();
 }
 

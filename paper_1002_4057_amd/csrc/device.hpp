@@ -130,6 +130,11 @@ hipError_t launch_rhs_in(const double* B, int ldb, int n, int nrhs, int t, doubl
 hipError_t launch_rhs_out(const double* R, int t, int n, int nrhs, double* B, int ldb,
                           hipStream_t s);
 
+// Synthetic SPD matrices for timing runs (the autotuner): mats[m] (device
+// pointers, column-major, ld = orders[m]) <- a_ij = 1/(1+|i-j|), a_ii = n.
+hipError_t launch_fill_spd(void* const* mats, const int* orders, int count, bool fp32,
+                           hipStream_t s);
+
 // Writes 0 to a device int (nullptr: no-op), as a kernel so that the call
 // can be captured in a graph.
 hipError_t launch_info_zero(int* d_info, hipStream_t s);
