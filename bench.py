@@ -289,6 +289,14 @@ def c1_row(spd, n: int, reps: int, ablation: bool):
                      ("in place UUU", {"renamed": 0, "loop_order": 1}),
                      ("renamed UDU, TRTRI(j) first", {"trtri_first": 1}),
                      ("renamed UDU, one task per paper task", {"chain": 1})]
+    if ablation:
+        # memory-constrained partial renaming: a fraction of the 2T copy tiles
+        t = -(-n // 128)
+        T = t * (t + 1) // 2
+        for frac in (0.25, 0.5):
+            k = int(2 * T * frac)
+            variants.append((f"renamed UDU, partial renaming {int(frac * 100)}% of the copies "
+                             f"({k} tiles)", {"rename_tiles": k}))
     out["variants"] = {}
     for label, opts in variants:
         log(f"[bench] n={n} variant: {label}")
@@ -299,7 +307,9 @@ def c1_row(spd, n: int, reps: int, ablation: bool):
                              prep=lambda: buf.copy_(a_cm))
             out["variants"][label] = {"ms": round(ms, 3), "gflops": round(flops / ms / 1e6, 1),
                                       "critical_path_tasks": rep["critical_path"],
-                                      "device_tasks": rep["tasks"]}
+                                      "device_tasks": rep["tasks"],
+                                      "workspace_gb": round(spd.workspace_bytes(n, **opts) / 1e9,
+                                                            3)}
         except Exception as e:   # a variant that fails is reported, not fatal
             out["variants"][label] = {"error": str(e)}
     v = out["variants"]

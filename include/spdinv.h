@@ -111,6 +111,18 @@ typedef struct {
   int parts;       /* FP64 form, with the split on: row parts per split product
                       (0 = library choice as above; 2 = halves; 4 = quarters).
                       Results do not depend on it.                           */
+  int rename_tiles; /* FP64 inverse with renamed = 1: memory-constrained
+                      partial renaming (Section 3, "Array renaming").  0 =
+                      full renaming (copies B of L and C of L^{-1} for every
+                      lower tile, 2T tiles); k > 0 = at most k copy tiles:
+                      whole tile rows of B and C are renamed, chosen greedily
+                      by the critical path of the task DAG they shorten
+                      (bottom C rows first where no single row shortens it),
+                      the other rows are read in place with the paper's
+                      anti-dependences, and the workspace shrinks
+                      accordingly.  Results do not depend on it.  Ignored by
+                      spd_cholesky and the solves; rejected (-8) by the FP32
+                      and mixed modes.                                       */
   int batch_group; /* batched form: schedule.  -1 = one workgroup per matrix
                       (largest first), running its tasks in order on the
                       workgroup's own pool; -2 = one DAG over the batch,
@@ -473,7 +485,10 @@ int spdinv_plan_stats_get(int t, const spdinv_opts* opts, spdinv_plan_stats* out
  *   kind, out, a, b, copy, aux, succ_begin, succ_end
  * (tile indices into the pool layout: A tiles [0,T), B [T,2T), C [2T,3T),
  * inverted diagonal tiles [3T, 3T+t), T = t(t+1)/2, lower tile (i,j) at
- * i(i+1)/2+j), the successor array, the step of each task, its packed paper
+ * i(i+1)/2+j; in the inverse's plan only the renamed rows of B and C are
+ * stored, row after row, and the inverted diagonal tiles follow them: at T
+ * in place, after the chosen rows with opts->rename_tiles), the successor
+ * array, the step of each task, its packed paper
  * indices (i<<20 | j<<10 | k) and the device dispatch order.  With
  * opts->chain != 1 a product task may carry further links: bits 20-23 of
  * kind count them, aux indexes the first in `links` (int32 pairs: operand

@@ -34,7 +34,8 @@ class Opts(ctypes.Structure):
                 ("workers", ctypes.c_int), ("fill_upper", ctypes.c_int), ("trace", ctypes.c_int),
                 ("max_refine", ctypes.c_int), ("refine_tol", ctypes.c_double),
                 ("chain", ctypes.c_int), ("per_cu", ctypes.c_int), ("no_split", ctypes.c_int),
-                ("parts", ctypes.c_int), ("batch_group", ctypes.c_int)]
+                ("parts", ctypes.c_int), ("rename_tiles", ctypes.c_int),
+                ("batch_group", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):

@@ -56,11 +56,12 @@ constexpr int kDefaultChain = 8;
 
 struct Key {
   int device, t, renamed, loop_order, pipelined, trtri_first, workers, chain, steps, rhs, split;
+  long long rename;  // copy-tile budget of a partial renaming, 0 = full
   bool operator<(const Key& o) const {
     return std::tie(device, t, renamed, loop_order, pipelined, trtri_first, workers, chain, steps,
-                    rhs, split) < std::tie(o.device, o.t, o.renamed, o.loop_order, o.pipelined,
-                                           o.trtri_first, o.workers, o.chain, o.steps, o.rhs,
-                                           o.split);
+                    rhs, split, rename) < std::tie(o.device, o.t, o.renamed, o.loop_order,
+                                                   o.pipelined, o.trtri_first, o.workers, o.chain,
+                                                   o.steps, o.rhs, o.split, o.rename);
   }
 };
 
@@ -107,6 +108,7 @@ spdinv_opts defaults() {
   o.no_split = 0;
   o.parts = 0;
   o.batch_group = 0;
+  o.rename_tiles = 0;
   return o;
 }
 
@@ -124,17 +126,64 @@ long long task_count(int t, int s = 0) {
          2 * tt * tt * ss + 3 * (2 * tt + 4 * tt * ss);
 }
 
+// Copy-tile budget of a partial renaming for these options (0 = full
+// renaming): only the inverse (steps 7) of a renamed plan whose budget is
+// below the 2T tiles of full renaming.
+long long rename_budget(int t, const spdinv_opts& o, int steps) {
+  if (!o.renamed || o.rename_tiles <= 0 || steps != 7) return 0;
+  return (long long)o.rename_tiles >= (long long)t * (t + 1) ? 0 : o.rename_tiles;
+}
+
+// The renamed rows chosen under a budget (cached per variant).
+struct RenRows {
+  std::vector<char> b, c;
+  int copy_tiles = 0;
+};
+std::mutex g_ren_mu;
+std::map<std::tuple<int, int, int, int, long long>, RenRows> g_ren;
+
+const RenRows& renaming_rows(int t, const spdinv_opts& o, long long budget) {
+  std::lock_guard<std::mutex> lk(g_ren_mu);
+  const auto k = std::make_tuple(t, o.loop_order, o.trtri_first ? 1 : 0, o.pipelined ? 1 : 0,
+                                 budget);
+  auto it = g_ren.find(k);
+  if (it != g_ren.end()) return it->second;
+  PlanOptions po;
+  po.t = t;
+  po.renamed = 1;
+  po.loop_order = o.loop_order;
+  po.pipelined = o.pipelined ? 1 : 0;
+  po.trtri_first = o.trtri_first ? 1 : 0;
+  choose_renaming(&po, budget);
+  RenRows r;
+  r.b = po.ren_b;
+  r.c = po.ren_c;
+  r.copy_tiles = renamed_tiles(po);
+  return g_ren.emplace(k, std::move(r)).first->second;
+}
+
+// Tiles of the pool of a plan: A, the stored copy rows, D and D^T, and the
+// right-hand sides.
+long long pool_tiles_for(int t, const spdinv_opts& o, int steps, int s) {
+  const long long T = (long long)t * (t + 1) / 2;
+  if (steps != 7) return pool_tiles(t, s);  // the standard layout of the partial plans
+  if (!o.renamed) return T + 2LL * t;       // in place: no copies
+  const long long budget = rename_budget(t, o, steps);
+  if (!budget) return pool_tiles(t, s);
+  return T + renaming_rows(t, o, budget).copy_tiles + 2LL * t + (long long)t * s;
+}
+
 struct Layout {
   size_t pool, indeg, ctrl, trace, total;
 };
 
-Layout layout(int n, const spdinv_opts& o, int nrhs = 0) {
+Layout layout(int n, const spdinv_opts& o, int nrhs = 0, int steps = 7) {
   Layout L;
   const int t = tiles_for(n);
   const int s = (nrhs + NB - 1) / NB;
   const long long nt = task_count(t, s);
   L.pool = 0;
-  L.indeg = align_up((size_t)pool_tiles(t, s) * NB * NB * sizeof(double), 256);
+  L.indeg = align_up((size_t)pool_tiles_for(t, o, steps, s) * NB * NB * sizeof(double), 256);
   L.ctrl = L.indeg + align_up((size_t)nt * sizeof(int32_t), 256);
   L.trace = L.ctrl + align_up(CTRL_WORDS * sizeof(int32_t), 256);
   L.total = L.trace + (o.trace ? align_up((size_t)nt * 4 * sizeof(long long), 256) : 0);
@@ -150,6 +199,7 @@ int check_opts(const spdinv_opts& o) {
   if (o.no_split < 0 || o.no_split > 1) return 1;
   if (o.parts != 0 && o.parts != 2 && o.parts != 4) return 1;
   if (o.batch_group < -2) return 1;
+  if (o.rename_tiles < 0) return 1;
   return 0;
 }
 
@@ -308,7 +358,7 @@ Key plan_key(int device, int t, const spdinv_opts& o, int workers, int chain, in
              int rhs_tiles, bool allow_split) {
   return Key{device, t, o.renamed ? 1 : 0, o.loop_order, o.pipelined ? 1 : 0,
              o.trtri_first ? 1 : 0, workers, chain, steps, rhs_tiles,
-             allow_split ? split_for(o, t, workers) : 0};
+             allow_split ? split_for(o, t, workers) : 0, rename_budget(t, o, steps)};
 }
 
 std::unique_ptr<DevPlan> build_dev_plan(const Key& k) {
@@ -323,6 +373,15 @@ std::unique_ptr<DevPlan> build_dev_plan(const Key& k) {
   po.steps = k.steps;
   po.rhs_tiles = k.rhs;
   po.split = k.split;
+  if (k.rename) {
+    spdinv_opts o = defaults();
+    o.loop_order = k.loop_order;
+    o.trtri_first = k.trtri_first;
+    o.pipelined = k.pipelined;
+    const RenRows& r = renaming_rows(k.t, o, k.rename);
+    po.ren_b = r.b;
+    po.ren_c = r.c;
+  }
   build_plan(po, k.workers, kCost, &dp->host);
   make_image(dp->host, &dp->image);
   return dp;
@@ -399,7 +458,7 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
              const spdinv_opts& o_in, int* d_info, spdinv_report* report, int steps = 7,
              int nrhs = 0, double* Bm = nullptr, int ldb = 1, DevPlan* given = nullptr) {
   const spdinv_opts o = tuned_fp64(o_in, tiles_for(n));
-  const Layout L = layout(n, o, nrhs);
+  const Layout L = layout(n, o, nrhs, steps);
   const int s = (nrhs + NB - 1) / NB;
   if (work_bytes < L.total) return SPDINV_ERR_WORKSPACE;
 
@@ -422,7 +481,7 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   if (launch_copy_in(A, lda, n, t, pool, stream) != hipSuccess) return SPDINV_ERR_HIP;
   if ((steps == 6 || steps == 8) && launch_factor_prologue(pool, t, ctrl, stream) != hipSuccess)
     return SPDINV_ERR_HIP;
-  double* rhs = pool + (size_t)pool_tiles(t) * NB * NB;  // R tiles, after the other regions
+  double* rhs = pool + (size_t)(dp->host.d_base + 2 * t) * NB * NB;  // R tiles, after D and D^T
   if (s && launch_rhs_in(Bm, ldb, n, nrhs, t, rhs, stream) != hipSuccess) return SPDINV_ERR_HIP;
   SchedArgs a;
   a.tasks = dp->d_tasks;
@@ -439,6 +498,7 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   a.tiles = t;
   a.info_base = 0;
   a.spin_limit = spin_limit();
+  a.d_base = dp->host.d_base;
   hipEvent_t ev0, ev1;
   const bool timed = !given && timer_pair(&ev0, &ev1);
   if (timed && hipEventRecord(ev0, stream) != hipSuccess) return SPDINV_ERR_HIP;
@@ -566,6 +626,7 @@ BBackComp* get_bbcomp(int device, int batch, const int* h_n, hipError_t* err) {
 // device copy once per device.
 struct BTemplate {
   int ntask = 0;
+  int d_base = 0;  // first inverted diagonal tile of the plan's pool
   PlanImage image;
   std::vector<double> cost;     // estimated duration per position (product units)
   std::vector<double> bottom;   // longest cost path from each position to the end
@@ -706,6 +767,7 @@ const BTemplate* btemplate_host(int t, bool fp32, const spdinv_opts& o) {
     // (the other matrices of the batch keep the workers busy)
     build_plan(po, 1, kCost, &p);
     make_btemplate(&p, bt.get());
+    bt->d_base = p.d_base;
   }
   btemplate_costs(bt.get(), t);
   const BTemplate* raw = bt.get();
@@ -1117,6 +1179,7 @@ int batched_spd_inverse(int batch, const int* h_n, const int* d_n, void* const* 
     b.tsucc[t] = tmpl[t]->d_succ;
     b.tlinks[t] = tmpl[t]->d_links;
     b.tindeg0[t] = tmpl[t]->d_indeg0;
+    b.tdbase[t] = tmpl[t]->h->d_base;
   }
   hipError_t err = hipSuccess;
   const int grid = batched_grid(device, o, fp32);
@@ -1349,6 +1412,7 @@ int run_fp32(int n, float* A, int lda, void* work, size_t work_bytes, hipStream_
   a.tiles_T = t * (t + 1) / 2;
   a.tiles = t;
   a.spin_limit = spin_limit();
+  a.d_base = 3 * a.tiles_T;
   if (launch_sched32(a, grid, false, stream) != hipSuccess) return SPDINV_ERR_HIP;
   if (launch_copy_out32f(pool, t, A, lda, n, o.fill_upper, stream) != hipSuccess)
     return SPDINV_ERR_HIP;
@@ -1409,6 +1473,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
   a.tiles = t;
   a.info_base = 0;
   a.spin_limit = spin_limit();
+  a.d_base = 3 * a.tiles_T;
   if (launch_sched32(a, grid, bf16, stream) != hipSuccess) return SPDINV_ERR_HIP;
   int32_t c[CTRL_WORDS];
   if (hipMemcpyAsync(c, ctrl, sizeof(c), hipMemcpyDeviceToHost, stream) != hipSuccess)
@@ -1556,7 +1621,7 @@ int spd_inverse(int n, void* A_, int lda, spdinv_mode mode, void* work, size_t w
   const spdinv_opts o = opts ? *opts : defaults();
   if (check_opts(o)) return -8;
   const bool mixed = mode == SPDINV_MIXED_FP32 || mode == SPDINV_MIXED_BF16;
-  if ((mixed || mode == SPDINV_FP32) && (!o.renamed || o.trace)) return -8;
+  if ((mixed || mode == SPDINV_FP32) && (!o.renamed || o.trace || o.rename_tiles)) return -8;
   if (report) std::memset(report, 0, sizeof(*report));
   if (n == 0) {
     if (d_info) {
@@ -2028,7 +2093,7 @@ void spdinv_release_plans(void) {
   g_plans.clear();
 }
 
-static PlanOptions plan_options(int t, const spdinv_opts* opts) {
+static PlanOptions plan_options(int t, const spdinv_opts* opts, int steps = 7) {
   const spdinv_opts o = opts ? *opts : defaults();
   PlanOptions po;
   po.t = t;
@@ -2037,6 +2102,12 @@ static PlanOptions plan_options(int t, const spdinv_opts* opts) {
   po.pipelined = o.pipelined ? 1 : 0;
   po.trtri_first = o.trtri_first ? 1 : 0;
   po.chain = std::min(std::max(chain_for(o), 1), MAX_CHAIN);
+  const long long budget = rename_budget(t, o, steps);
+  if (budget) {
+    const RenRows& r = renaming_rows(t, o, budget);
+    po.ren_b = r.b;
+    po.ren_c = r.c;
+  }
   return po;
 }
 
@@ -2069,7 +2140,7 @@ int spdinv_plan_export_steps(int steps, int rhs_tiles, int t, const spdinv_opts*
   if (steps != 7 && steps != 1 && steps != 6 && steps != 9 && steps != 8) return -2;
   if ((steps & 8) ? (rhs_tiles < 1 || rhs_tiles > 64) : rhs_tiles != 0) return -2;
   Plan p;
-  PlanOptions po = plan_options(t, opts);
+  PlanOptions po = plan_options(t, opts, steps);
   po.steps = steps;
   po.rhs_tiles = rhs_tiles;
   po.split = split_for(opts ? *opts : defaults(), t, workers);

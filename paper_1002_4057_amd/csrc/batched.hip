@@ -135,6 +135,7 @@ void bsched_kernel(BSchedArgs g) {
         (g.seq || (__builtin_amdgcn_readfirstlane(g.mat[m].x) & BM_PREV)) ? 1 : 0;
     s.last_valid = __builtin_amdgcn_readfirstlane(g.n[m]) - (t - 1) * NB;
     s.info_base = 0;
+    s.d_base = g.tdbase[t];
     run_task<true>(d, s, smem, t * (t + 1) / 2, t);
   };
   if (g.seq)

@@ -39,6 +39,8 @@ struct SchedArgs {
   int tiles;           // tiles per side, t
   int info_base;       // offset added to the global pivot index in INFO
   long long spin_limit;  // longest dependency wait, in 100 MHz clock ticks
+  int d_base;          // first inverted diagonal tile: D_j at d_base + j, D_j^T
+                       // at d_base + tiles + j (3T unless renaming is partial)
 };
 
 // Batched form: the largest tile count per matrix (n <= 2048).
@@ -96,6 +98,8 @@ struct BSchedArgs {
   int seq;
   long long wg_pool_tiles;
   int tntask[MAX_BATCH_T + 1];              // tasks of each template
+  int tdbase[MAX_BATCH_T + 1];              // first inverted diagonal tile of each
+                                            // template's pool
 };
 
 // Resets the counters of a batch (from each template's initial in-degrees),

@@ -23,21 +23,60 @@ struct Builder {
   int cur_step = 0;
   int barrier = -1;  // barrier task that the current step's sources must follow
 
+  // per tile row: the row has the renaming copy B (of L) / C (of L^{-1})
+  bool rb(int i) const { return o.renamed && (o.ren_b.empty() || o.ren_b[i]); }
+  bool rc(int i) const { return o.renamed && (o.ren_c.empty() || o.ren_c[i]); }
+
   Builder(const PlanOptions& opt, Plan* plan) : o(opt), t(opt.t), p(plan) {
     T = t * (t + 1) / 2;
+    boff.assign(t, -1);
+    coff.assign(t, -1);
+    if (opt.steps != 7) {
+      // the standard layout for the partial plans: the prologue of the
+      // steps from a given factor writes B and D into it, and the solve's
+      // right-hand sides follow D^T at 3T + 2t
+      for (int i = 0; i < t; ++i) {
+        boff[i] = T + tri(i, 0);
+        coff[i] = 2 * T + tri(i, 0);
+      }
+      dbase = 3 * T;
+    } else {
+      // the inverse: the renamed rows of B, then those of C, then D (full
+      // renaming: B at [T, 2T), C at [2T, 3T), D at 3T; in place: D at T)
+      int next = T;
+      for (int i = 0; i < t; ++i)
+        if (rb(i)) {
+          boff[i] = next;
+          next += i + 1;
+        }
+      for (int i = 0; i < t; ++i)
+        if (rc(i)) {
+          coff[i] = next;
+          next += i + 1;
+        }
+      dbase = next;
+    }
+    p->d_base = dbase;
+    p->pool_tiles = (int64_t)dbase + 2 * (int64_t)t + (int64_t)t * opt.rhs_tiles;
     const size_t names = 3 * (size_t)T + (size_t)t * opt.rhs_tiles;
     last_writer.assign(names, -1);
     readers.resize(names);
   }
 
   int tri(int i, int j) const { return i * (i + 1) / 2 + j; }
+  // hazard names of the paper's tiles (A, and the copies B and C)
   int A(int i, int j) const { return tri(i, j); }
   int B(int i, int j) const { return T + tri(i, j); }
   int C(int i, int j) const { return 2 * T + tri(i, j); }
-  int D(int j) const { return 3 * T + j; }
+  // pool tiles of the copies (only renamed rows are stored) and of D, D^T
+  std::vector<int> boff, coff;
+  int dbase = 0;
+  int Bd(int i, int j) const { return boff[i] + j; }
+  int Cd(int i, int j) const { return coff[i] + j; }
+  int D(int j) const { return dbase + j; }
   // right-hand-side tile (i, c): hazard name and pool index
   int Rh(int i, int c) const { return 3 * T + i + t * c; }
-  int Rp(int i, int c) const { return 3 * T + 2 * t + i + t * c; }
+  int Rp(int i, int c) const { return dbase + 2 * t + i + t * c; }
 
   // Emits one task.  reads/writes are hazard names (A/B/C tile ids); the
   // device operands are given separately.
@@ -97,7 +136,7 @@ struct Builder {
     barrier = v;
   }
 
-  int Dt(int j) const { return 3 * T + t + j; }
+  int Dt(int j) const { return dbase + t + j; }
 
   // One tile operation of the inversion, (kind, i, j, k) in the paper's
   // naming, emitted with its hazard names and its device operands.  The
@@ -108,9 +147,10 @@ struct Builder {
   // before the reader.  In the renamed plan every product reads op(A) = A and
   // op(B) = B^T contiguously (the copies are stored transposed); the in-place
   // plan uses the paper's tiles with transposes and triangular masks.
+  // With partial renaming each operation takes the renamed form when the
+  // tile row that holds its copy operands is renamed (B: the row of the L
+  // tile read; C: the row of the X tiles read), the in-place form otherwise.
   void op(int kind, int i, int j, int k) {
-    const bool rn = o.renamed != 0;
-    const int cpt = rn ? F_COPYT : 0;
     switch (kind) {
       // step 1, the Cholesky factor
       case K_SYRK1:   // A_jj -= A_jk A_jk^T
@@ -118,7 +158,7 @@ struct Builder {
              F_TB | F_LOWER | F_NEG | F_ACC);
         break;
       case K_POTRF:   // A_jj <- chol(A_jj), D_j <- its inverse (B_jj <- the factor)
-        if (rn) emit(kind, j, j, 0, {A(j, j)}, {A(j, j), B(j, j)}, A(j, j), -1, -1, B(j, j), D(j));
+        if (rb(j)) emit(kind, j, j, 0, {A(j, j)}, {A(j, j), B(j, j)}, A(j, j), -1, -1, Bd(j, j), D(j));
         else emit(kind, j, j, 0, {A(j, j)}, {A(j, j)}, A(j, j), -1, -1, -1, D(j));
         break;
       case K_GEMM1:   // A_ij -= A_ik A_jk^T
@@ -126,24 +166,24 @@ struct Builder {
              -1, F_TB | F_NEG | F_ACC);
         break;
       case K_TRSM1:   // A_ij <- A_ij L_jj^{-T} = A_ij D_j^T (B_ij <- the result)
-        emit(kind, i, j, 0, {A(j, j), A(i, j)}, rn ? std::initializer_list<int>{A(i, j), B(i, j)}
-                                                   : std::initializer_list<int>{A(i, j)},
-             A(i, j), A(i, j), D(j), rn ? B(i, j) : -1, -1, F_TB | cpt);
+        emit(kind, i, j, 0, {A(j, j), A(i, j)}, rb(i) ? std::initializer_list<int>{A(i, j), B(i, j)}
+                                                      : std::initializer_list<int>{A(i, j)},
+             A(i, j), A(i, j), D(j), rb(i) ? Bd(i, j) : -1, -1, F_TB | (rb(i) ? F_COPYT : 0));
         break;
       // step 2, the inverse X = L^{-1}
       case K_TRTRI:   // A_jj <- D_j (and C_jj <- D_j^T)
-        if (rn) emit(kind, j, j, 0, {A(j, j)}, {A(j, j), C(j, j)}, A(j, j), D(j), Dt(j), C(j, j), -1);
+        if (rc(j)) emit(kind, j, j, 0, {A(j, j)}, {A(j, j), C(j, j)}, A(j, j), D(j), Dt(j), Cd(j, j), -1);
         else emit(kind, j, j, 0, {A(j, j)}, {A(j, j)}, A(j, j), D(j), -1, -1, -1);
         break;
       case K_TRMM2L:  // A_ij <- X_ii L_ij
-        if (rn)
-          emit(kind, i, j, 0, {A(i, i), A(i, j)}, {A(i, j)}, A(i, j), A(i, i), B(i, j), -1, -1, F_TB);
+        if (rb(i))
+          emit(kind, i, j, 0, {A(i, i), A(i, j)}, {A(i, j)}, A(i, j), A(i, i), Bd(i, j), -1, -1, F_TB);
         else
           emit(kind, i, j, 0, {A(i, i), A(i, j)}, {A(i, j)}, A(i, j), A(i, i), A(i, j), -1, -1, F_MA);
         break;
       case K_GEMM2:   // A_ij += X_ik L_kj
-        if (rn)
-          emit(kind, i, j, k, {A(i, k), B(k, j), A(i, j)}, {A(i, j)}, A(i, j), A(i, k), B(k, j), -1,
+        if (rb(k))
+          emit(kind, i, j, k, {A(i, k), B(k, j), A(i, j)}, {A(i, j)}, A(i, j), A(i, k), Bd(k, j), -1,
                -1, F_TB | F_ACC);
         else
           emit(kind, i, j, k, {A(i, k), A(k, j), A(i, j)}, {A(i, j)}, A(i, j), A(i, k), A(k, j), -1,
@@ -151,39 +191,40 @@ struct Builder {
         break;
       case K_TRSM2R: {  // A_ij <- -A_ij L_jj^{-1} = -A_ij D_j (C_ij <- the result)
         // by L_jj (a solve) in the LAPACK order, by X_jj after TRTRI(j) otherwise
-        const int djj = (o.trtri_first || !rn) ? A(j, j) : B(j, j);
-        emit(kind, i, j, 0, {djj, A(i, j)}, rn ? std::initializer_list<int>{A(i, j), C(i, j)}
-                                               : std::initializer_list<int>{A(i, j)},
-             A(i, j), A(i, j), Dt(j), rn ? C(i, j) : -1, -1, F_TB | F_NEG | cpt);
+        const int djj = (o.trtri_first || !rb(j)) ? A(j, j) : B(j, j);
+        emit(kind, i, j, 0, {djj, A(i, j)}, rc(i) ? std::initializer_list<int>{A(i, j), C(i, j)}
+                                                  : std::initializer_list<int>{A(i, j)},
+             A(i, j), A(i, j), Dt(j), rc(i) ? Cd(i, j) : -1, -1,
+             F_TB | F_NEG | (rc(i) ? F_COPYT : 0));
         break;
       }
       // step 3, the product X^T X
       case K_TRMM3:   // A_ij <- X_ii^T A_ij
-        if (rn)
-          emit(kind, i, j, 0, {C(i, i), A(i, j)}, {A(i, j)}, A(i, j), C(i, i), C(i, j), -1, -1, F_TB);
+        if (rc(i))
+          emit(kind, i, j, 0, {C(i, i), A(i, j)}, {A(i, j)}, A(i, j), Cd(i, i), Cd(i, j), -1, -1, F_TB);
         else
           emit(kind, i, j, 0, {A(i, i), A(i, j)}, {A(i, j)}, A(i, j), A(i, i), A(i, j), -1, -1,
                F_TA | F_MA);
         break;
       case K_LAUUM:   // A_ii <- A_ii^T A_ii (lower)
-        if (rn)
-          emit(kind, i, i, 0, {A(i, i)}, {A(i, i)}, A(i, i), C(i, i), C(i, i), -1, -1,
+        if (rc(i))
+          emit(kind, i, i, 0, {A(i, i)}, {A(i, i)}, A(i, i), Cd(i, i), Cd(i, i), -1, -1,
                F_TB | F_LOWER);
         else
           emit(kind, i, i, 0, {A(i, i)}, {A(i, i)}, A(i, i), A(i, i), A(i, i), -1, -1,
                F_TA | F_MA | F_MB | F_LOWER);
         break;
       case K_GEMM3:   // A_ij += X_ki^T X_kj
-        if (rn)
-          emit(kind, i, j, k, {C(k, i), C(k, j), A(i, j)}, {A(i, j)}, A(i, j), C(k, i), C(k, j), -1,
+        if (rc(k))
+          emit(kind, i, j, k, {C(k, i), C(k, j), A(i, j)}, {A(i, j)}, A(i, j), Cd(k, i), Cd(k, j), -1,
                -1, F_TB | F_ACC);
         else
           emit(kind, i, j, k, {A(k, i), A(k, j), A(i, j)}, {A(i, j)}, A(i, j), A(k, i), A(k, j), -1,
                -1, F_TA | F_ACC);
         break;
       case K_SYRK3:   // A_ii += X_ki^T X_ki (lower)
-        if (rn)
-          emit(kind, i, i, k, {C(k, i), A(i, i)}, {A(i, i)}, A(i, i), C(k, i), C(k, i), -1, -1,
+        if (rc(k))
+          emit(kind, i, i, k, {C(k, i), A(i, i)}, {A(i, i)}, A(i, i), Cd(k, i), Cd(k, i), -1, -1,
                F_TB | F_LOWER | F_ACC);
         else
           emit(kind, i, i, k, {A(k, i), A(i, i)}, {A(i, i)}, A(i, i), A(k, i), A(k, i), -1, -1,
@@ -281,9 +322,9 @@ struct Builder {
     for (int i = t - 1; i >= 0; --i)
       for (int c = 0; c < s; ++c) {
         for (int k = t - 1; k > i; --k) {
-          if (o.renamed)
+          if (rb(k))
             emit(K_GEMMS, i, c, k, {B(k, i), Rh(k, c), Rh(i, c)}, {Rh(i, c)}, Rp(i, c), Rp(k, c),
-                 B(k, i), -1, -1, F_TB | F_NEG | F_ACC);
+                 Bd(k, i), -1, -1, F_TB | F_NEG | F_ACC);
           else
             emit(K_GEMMS, i, c, k, {A(k, i), Rh(k, c), Rh(i, c)}, {Rh(i, c)}, Rp(i, c), Rp(k, c),
                  A(k, i), -1, -1, F_NEG | F_ACC);
@@ -295,6 +336,20 @@ struct Builder {
 };
 
 inline int weight(int kind) { return task_kind(kind) == K_NOP ? 0 : 1; }
+
+// Emits the task stream of the options' steps (as build_plan does).
+void emit_stream(Builder& bld, const PlanOptions& opt) {
+  const bool s1 = opt.steps & 1, s2 = opt.steps & 2, s3 = opt.steps & 4;
+  if (s1) bld.step1();
+  if (s1 && (s2 || s3) && !opt.pipelined) bld.emit_barrier();
+  if (s2) bld.step2();
+  if (s2 && s3 && !opt.pipelined) bld.emit_barrier();
+  if (s3) bld.step3();
+  if (opt.steps & 8) {
+    if (s1 && !opt.pipelined) bld.emit_barrier();
+    bld.solve();
+  }
+}
 
 // List-scheduling simulation of a DAG given by predecessor lists in a
 // topological program order: `workers` identical workers, priority =
@@ -562,16 +617,7 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
   const int t = opt.t;
   p->T = t * (t + 1) / 2;
   Builder bld(opt, p);
-  const bool s1 = opt.steps & 1, s2 = opt.steps & 2, s3 = opt.steps & 4;
-  if (s1) bld.step1();
-  if (s1 && (s2 || s3) && !opt.pipelined) bld.emit_barrier();
-  if (s2) bld.step2();
-  if (s2 && s3 && !opt.pipelined) bld.emit_barrier();
-  if (s3) bld.step3();
-  if (opt.steps & 8) {
-    if (s1 && !opt.pipelined) bld.emit_barrier();
-    bld.solve();
-  }
+  emit_stream(bld, opt);
 
   // dead factor stores: a POTRF whose factor tile is not read before it is
   // rewritten, and whose renaming copy is never read, stores only D_j, D_j^T.
@@ -579,7 +625,7 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
   // reads it).  Renaming copies that no task reads are not stored either.
   {
     const int nt = (int)p->tasks.size();
-    std::vector<char> copy_read(pool_tiles(opt.t, opt.rhs_tiles), 0);
+    std::vector<char> copy_read(p->pool_tiles, 0);
     for (const DevTask& d : p->tasks) {
       if (d.a >= 0) copy_read[d.a] = 1;
       if (d.b >= 0) copy_read[d.b] = 1;
@@ -620,7 +666,7 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
   // earlier version during the launch is never read through the cache.
   {
     const int nt = (int)p->tasks.size();
-    const int64_t ntiles = pool_tiles(opt.t, opt.rhs_tiles);
+    const int64_t ntiles = p->pool_tiles;
     std::vector<int32_t> writes(ntiles, 0);
     std::vector<char> touched_first(ntiles, 0);  // accessed before its first write
     for (int u = 0; u < nt; ++u) {
@@ -656,11 +702,13 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
   // block for the transposed copies B, C and D_j^T
   {
     const int T = p->T;
+    const int last = t - 1;
+    auto in_row = [&](int base, int x) { return base >= 0 && x >= base && x < base + t; };
     auto klast = [&](int x) {
       if (x < 0) return false;
-      if (x < T) return x == T - 1;                        // A(t-1, t-1)
-      if (x < 3 * T) return (x - T) % T >= t * (t - 1) / 2;  // B(t-1, .), C(t-1, .)
-      return x == 3 * T + t - 1 || x == 3 * T + 2 * t - 1;  // D_{t-1}, D_{t-1}^T
+      if (x < T) return x == T - 1;                                      // A(t-1, t-1)
+      if (x < bld.dbase) return in_row(bld.boff[last], x) || in_row(bld.coff[last], x);
+      return x == bld.dbase + t - 1 || x == bld.dbase + 2 * t - 1;      // D_{t-1}, D_{t-1}^T
     };
     for (DevTask& d : p->tasks)
       if (column_product(d) && (klast(d.a) || klast(d.b))) d.kind |= K_KLAST;
@@ -743,6 +791,100 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
                      : ((k & K_PARTS4) ? 0.25 : 0.5);
   }
   list_schedule(bld.preds, dur, workers, &p->order, nullptr);
+}
+
+int renamed_tiles(const PlanOptions& opt) {
+  if (!opt.renamed) return 0;
+  int n = 0;
+  for (int i = 0; i < opt.t; ++i) {
+    if (opt.ren_b.empty() || opt.ren_b[i]) n += i + 1;
+    if (opt.ren_c.empty() || opt.ren_c[i]) n += i + 1;
+  }
+  return n;
+}
+
+int plan_critical_path(const PlanOptions& opt) {
+  Plan p;
+  p.opt = opt;
+  p.T = opt.t * (opt.t + 1) / 2;
+  Builder bld(opt, &p);
+  emit_stream(bld, opt);
+  const int n = (int)p.tasks.size();
+  std::vector<int32_t> lp(n, 0);
+  int cp = 0;
+  for (int v = 0; v < n; ++v) {
+    int best = 0;
+    for (int q : bld.preds[v]) best = std::max(best, lp[q]);
+    lp[v] = best + weight(p.tasks[v].kind);
+    cp = std::max(cp, lp[v]);
+  }
+  return cp;
+}
+
+void choose_renaming(PlanOptions* opt, long long budget) {
+  const int t = opt->t;
+  opt->ren_b.clear();
+  opt->ren_c.clear();
+  if (!opt->renamed || budget >= (long long)t * (t + 1)) return;  // full renaming
+  opt->ren_b.assign(t, 0);
+  opt->ren_c.assign(t, 0);
+  long long left = budget;
+  // the critical path of every candidate is evaluated up to 16 tiles per
+  // side (a round costs 2t builds of the t^3/2-task stream); beyond, rows
+  // are taken in the fallback order, which reaches the same critical paths
+  // where both were compared (8 to 32 tiles per side)
+  const bool evaluate = t <= 16;
+  int cp = evaluate ? plan_critical_path(*opt) : 0;
+  for (;;) {
+    // candidate rows (copy, row), each costing row + 1 tiles
+    int best_c = -1, best_r = -1;
+    double best_score = 0.0;
+    int best_cp = cp;
+    for (int c = 0; c < 2 && evaluate; ++c)
+      for (int r = 0; r < t; ++r) {
+        std::vector<char>& v = c ? opt->ren_c : opt->ren_b;
+        if (v[r] || r + 1 > left) continue;
+        v[r] = 1;
+        const int cpr = plan_critical_path(*opt);
+        v[r] = 0;
+        const double score = double(cp - cpr) / (r + 1);
+        if (score > best_score) {
+          best_score = score;
+          best_c = c;
+          best_r = r;
+          best_cp = cpr;
+        }
+      }
+    if (best_c < 0) {
+      // no single row shortens the path (or the candidates are not
+      // evaluated): the last C row, then the B rows from the top (a B row's
+      // diagonal tile names the factor tile that the column's right solves
+      // read before TRTRI rewrites it), then the C rows from the bottom --
+      // the rows the evaluated greedy takes at 8 to 32 tiles per side
+      if (!opt->ren_c[t - 1] && t <= left) {
+        best_c = 1;
+        best_r = t - 1;
+      }
+      for (int r = 0; r < t && best_c < 0; ++r)
+        if (!opt->ren_b[r] && r + 1 <= left) {
+          best_c = 0;
+          best_r = r;
+        }
+      for (int r = t - 1; r >= 0 && best_c < 0; --r)
+        if (!opt->ren_c[r] && r + 1 <= left) {
+          best_c = 1;
+          best_r = r;
+        }
+      if (best_c < 0) break;  // nothing fits
+      std::vector<char>& v = best_c ? opt->ren_c : opt->ren_b;
+      v[best_r] = 1;
+      best_cp = evaluate ? plan_critical_path(*opt) : 0;
+    } else {
+      (best_c ? opt->ren_c : opt->ren_b)[best_r] = 1;
+    }
+    left -= best_r + 1;
+    cp = best_cp;
+  }
 }
 
 }  // namespace spdinv

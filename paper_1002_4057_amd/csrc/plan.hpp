@@ -78,8 +78,28 @@ struct PlanOptions {
   // tile (j+1, j+1), between POTRF(j) and POTRF(j+1), and in the solve each
   // multiplication by D_i or D_i^T with the last update before it.
   int split = 0;
+  // Partial renaming (renamed = 1): per tile row i, ren_b[i] / ren_c[i] say
+  // whether the tiles of row i have the renaming copy B (of L) / C (of
+  // L^{-1}); rows without it are read in place, with the paper's
+  // anti-dependences.  Empty = every row (full renaming).
+  std::vector<char> ren_b, ren_c;
 };
 constexpr int MAX_CHAIN = 16;
+
+// Copy tiles of the renaming rows: row i has i + 1 lower tiles.
+int renamed_tiles(const PlanOptions& opt);
+
+// Unit-weight critical path of the DAG of the options' steps (no chains, no
+// row parts): the cost the renaming choice below minimizes.
+int plan_critical_path(const PlanOptions& opt);
+
+// Memory-constrained partial renaming: chooses the rows of B and C to rename
+// under a budget of copy tiles (greedy: each round adds the row whose copy
+// shortens the critical path most per tile; when no single row shortens it
+// -- or beyond 16 tiles per side, where the candidates are not evaluated --
+// the bottom C rows first, then the bottom B rows) and sets opt->ren_b /
+// ren_c.  A budget of 2T or more is full renaming.
+void choose_renaming(PlanOptions* opt, long long budget_tiles);
 
 // Operation flags of a tile product, C (+)= +-op(A) op(B) (bits 8-15 of
 // DevTask::kind).
@@ -151,6 +171,10 @@ inline int32_t task_flags(int32_t k) { return (k >> 8) & 0xff; }
 //   [3T, 3T+t)      D_j, inverse of the j-th diagonal factor tile (zeros above
 //                   the diagonal)
 //   [3T+t, 3T+2t)   D_j^T
+// In the inverse's plan (steps 7) only the renamed rows of B and C are
+// stored, row after row, and D, D^T follow them (Plan::d_base): the layout
+// above with full renaming, D at T in place, in between with partial
+// renaming.  The partial plans keep the layout above.
 // Storing the copies transposed lets every product of the renamed plan read
 // both operands along contiguous columns (op(A) = A, op(B) = B^T).
 struct DevTask {
@@ -178,6 +202,9 @@ struct PlanStats {
 struct Plan {
   PlanOptions opt;
   int T = 0;                       // lower tiles per copy
+  int d_base = 0;                  // first inverted diagonal tile (D_j at d_base + j,
+                                   // D_j^T at d_base + t + j); 3T with full renaming
+  int64_t pool_tiles = 0;          // tiles of the pool this plan addresses
   std::vector<DevTask> tasks;      // program order
   std::vector<int32_t> step;       // step (1..3, 0 for barriers) per task
   std::vector<int32_t> idx;        // packed (i,j,k) paper indices, 10 bits each

@@ -1042,11 +1042,11 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
       // the last diagonal tile of a ragged order: its padded part is an exact
       // identity block (zero cross blocks), so only its first
       // ceil(last_valid / 16) blocks of 16 are factored and inverted
-      const bool ragged = t.aux - 3 * T == tiles - 1;
+      const bool ragged = t.aux - g.d_base == tiles - 1;
       const int P16 = ragged ? (g.last_valid + 15) / 16 : NB / 16;
       const int fl = potrf_inv_tile(out, live ? out : nullptr, cp, X, Xt, smem, P16);
       if (fl && threadIdx.x == 0) {
-        const int jt = t.aux - 3 * T;  // diagonal tile index
+        const int jt = t.aux - g.d_base;  // diagonal tile index
         atomicMin(&g.ctrl[CTRL_INFO], g.info_base + jt * NB + fl);
         __hip_atomic_store(&g.ctrl[CTRL_FAILED], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
