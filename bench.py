@@ -274,14 +274,6 @@ def c1_row(spd, n: int, reps: int, ablation: bool):
     a, q, lam = inputs.spectrum(n, 1e4, seed=0, device=dev, return_factors=True)
     a_cm = a.t().contiguous()
     buf = a_cm.clone()
-    work = torch.empty(spd.workspace_bytes(n), dtype=torch.uint8, device=dev)
-    spd.spd_inverse_(buf.t(), work=work, report=True)
-    ref = inputs.analytic_inverse(q, lam)
-    err = (torch.linalg.norm(sym_from_lower_cm(buf) - ref) / torch.linalg.norm(ref)).item()
-    del ref, q
-    flops = float(n) ** 3
-    out = {"workload": f"single SPD inverse, n={n}, FP64, A=Q diag(lambda) Q^T, lambda "
-                       f"log-spaced over [1,1e4]", "reps": reps, "err_vs_analytic": err}
     variants = [("renamed UDU (default)", {}), ("renamed UDU, barriers between steps",
                                                 {"pipelined": 0})]
     if ablation:
@@ -297,6 +289,21 @@ def c1_row(spd, n: int, reps: int, ablation: bool):
             k = int(2 * T * frac)
             variants.append((f"renamed UDU, partial renaming {int(frac * 100)}% of the copies "
                              f"({k} tiles)", {"rename_tiles": k}))
+        # tree reduction of the step-2 chains (associativity, Section 4)
+        for levels in (1, 2):
+            variants.append((f"renamed UDU, step-2 chains as a {1 << levels}-leaf tree",
+                             {"tree_levels": levels}))
+            variants.append((f"renamed UUU, step-2 chains as a {1 << levels}-leaf tree",
+                             {"loop_order": 1, "tree_levels": levels}))
+    work = torch.empty(max(spd.workspace_bytes(n, **o) for _, o in variants), dtype=torch.uint8,
+                       device=dev)
+    spd.spd_inverse_(buf.t(), work=work, report=True)
+    ref = inputs.analytic_inverse(q, lam)
+    err = (torch.linalg.norm(sym_from_lower_cm(buf) - ref) / torch.linalg.norm(ref)).item()
+    del ref, q
+    flops = float(n) ** 3
+    out = {"workload": f"single SPD inverse, n={n}, FP64, A=Q diag(lambda) Q^T, lambda "
+                       f"log-spaced over [1,1e4]", "reps": reps, "err_vs_analytic": err}
     out["variants"] = {}
     for label, opts in variants:
         log(f"[bench] n={n} variant: {label}")
@@ -317,6 +324,41 @@ def c1_row(spd, n: int, reps: int, ablation: bool):
         out["pipelining_gain"] = round(v["renamed UDU (default)"]["gflops"] /
                                        v["renamed UDU, barriers between steps"]["gflops"], 3)
     return out, a_cm, work
+
+
+def tree_row(spd, reps: int):
+    """Small orders (4 to 16 tiles per side, where the dependency chains and
+    not the products bound the time): UDU and UUU loop orders with the step-2
+    chains summed sequentially (the paper's plan) or as a fixed tree
+    (associativity, Section 4), each against the FP64 oracle's bar through
+    the analytic inverse."""
+    import torch
+    from paper_1002_4057_amd import inputs
+    dev = torch.device("cuda:0")
+    out = {"workload": "single SPD inverse, FP64, A=Q diag(lambda) Q^T, lambda log-spaced over "
+                       "[1,1e4]", "reps": reps, "orders": {}}
+    for n in (512, 1024, 2048):
+        a, q, lam = inputs.spectrum(n, 1e4, seed=1, device=dev, return_factors=True)
+        ref = inputs.analytic_inverse(q, lam)
+        a_cm = a.t().contiguous()
+        buf = a_cm.clone()
+        work = torch.empty(spd.workspace_bytes(n, tree_levels=2), dtype=torch.uint8, device=dev)
+        row = {}
+        for lo, name in ((0, "UDU"), (1, "UUU")):
+            for levels in (0, 1, 2):
+                opts = {"loop_order": lo, "tree_levels": levels}
+                log(f"[bench] tree n={n} {name} levels={levels}")
+                buf.copy_(a_cm)
+                rep = spd.spd_inverse_(buf.t(), work=work, report=True, **opts)
+                err = (torch.linalg.norm(sym_from_lower_cm(buf) - ref) /
+                       torch.linalg.norm(ref)).item()
+                us = 1e3 * time_events(lambda: spd.spd_inverse_(buf.t(), work=work, **opts), reps,
+                                       prep=lambda: buf.copy_(a_cm), agg="median")
+                row[f"{name} tree_levels={levels}"] = {
+                    "us": round(us, 1), "critical_path_tasks": rep["critical_path"],
+                    "device_tasks": rep["tasks"], "err_vs_analytic": err}
+        out["orders"][str(n)] = row
+    return out
 
 
 def steps_row(spd, a_cm, work, n: int, reps: int):
@@ -412,11 +454,11 @@ def main():
                     help="oracle sample order on every host core (0 = skip)")
     ap.add_argument("--cpu-n1", type=int, default=3072,
                     help="oracle sample order on one thread (0 = skip)")
-    ap.add_argument("--rows", default="precision,large,c1,ablation,batched,backward,steps",
+    ap.add_argument("--rows", default="precision,large,c1,ablation,tree,batched,backward,steps",
                     help="extra measured rows (comma list, '' = none): precision (FP64 vs "
                          "mixed at the headline order), large (n = --large-n), c1 (n = 8192 "
                          "pipelined vs unpipelined), ablation (plan variants at n = 8192), "
-                         "batched, backward, steps")
+                         "tree (step-2 tree reduction at small orders), batched, backward, steps")
     ap.add_argument("--kappas", default="1e2,1e6,1e10", help="precision row condition numbers")
     ap.add_argument("--modes", default="fp64,mixed_fp32,mixed_bf16", help="precision row modes")
     ap.add_argument("--large-n", type=int, default=32768)
@@ -546,6 +588,9 @@ def main():
             rows["steps"] = steps_row(spd, a8_cm, work8, 8192, max(2, min(K, 5)))
         del a8_cm, work8
         torch.cuda.empty_cache()
+    if "tree" in wanted:
+        log("[bench] tree row")
+        rows["tree"] = tree_row(spd, max(5, min(K, 20)))
     if "batched" in wanted:
         log("[bench] batched row (FP64)")
         rows["batched"] = batched_row(max(2, min(K, 5)), "fp64", args.batch_group,

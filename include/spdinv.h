@@ -123,6 +123,17 @@ typedef struct {
                       accordingly.  Results do not depend on it.  Ignored by
                       spd_cholesky and the solves; rejected (-8) by the FP32
                       and mixed modes.                                       */
+  int tree_levels; /* FP64 plans with step 2: tree reduction of the step-2
+                      update chains A_ij += sum_k X_ik L_kj (associativity,
+                      the paper's conclusion).  0 = the sequential chains
+                      (default); L = 1 or 2: each chain is cut into 2^L
+                      consecutive segments accumulated side by side (into
+                      A_ij and into 2^L - 1 partial-sum tiles per lower
+                      tile, after the pool's other regions) and added in a
+                      fixed binary tree, so results are bit-identical across
+                      schedules but differ in rounding from L = 0.  Ignored by
+                      the batched form; rejected (-8) by the FP32 and mixed
+                      modes.                                                  */
   int batch_group; /* batched form: schedule.  -1 = one workgroup per matrix
                       (largest first), running its tasks in order on the
                       workgroup's own pool; -2 = one DAG over the batch,
@@ -212,7 +223,9 @@ int spd_inverse(int n, void* A, int lda, spdinv_mode mode, void* work, size_t wo
  * A (column-major, lda >= max(1,n)) is read and overwritten with L; the
  * strictly upper triangle is neither read nor written (opts->fill_upper is
  * ignored).  Workspace: spd_inverse_workspace_bytes(n, SPDINV_FP64, opts)
- * bytes.  d_info, report, stream and opts as for spd_inverse (FP64 only):
+ * bytes.  d_info, report, stream and opts as for spd_inverse (FP64 only;
+ * the steps on their own run the renamed plan, so renamed = 0 and
+ * rename_tiles > 0 are rejected as invalid options):
  * INFO = k > 0 when the leading minor of order k is not positive definite
  * (the contents of A are then unspecified).  Returns 0, -i for an invalid
  * i-th argument, SPDINV_ERR_WORKSPACE or SPDINV_ERR_HIP.
@@ -245,9 +258,10 @@ int spd_inverse_from_factor(int n, double* L, int ldl, void* work, size_t work_b
  * as its TRSMs do).  As LAPACK's xPOSV: the lower triangle of A is replaced
  * by L (the strictly upper triangle is neither read nor written) and B
  * (column-major n x nrhs, ldb >= max(1,n)) by X.  Workspace:
- * spd_solve_workspace_bytes(n, nrhs, opts).  d_info: INFO = k > 0 when the
- * leading minor of order k is not positive definite (A and B are then
- * unspecified).  Returns 0, -i for an invalid i-th argument,
+ * spd_solve_workspace_bytes(n, nrhs, opts).  opts as for spd_cholesky (the
+ * renamed plan: renamed = 0 and rename_tiles > 0 are invalid).  d_info:
+ * INFO = k > 0 when the leading minor of order k is not positive definite
+ * (A and B are then unspecified).  Returns 0, -i for an invalid i-th argument,
  * SPDINV_ERR_WORKSPACE or SPDINV_ERR_HIP.  nrhs <= 8192.
  */
 size_t spd_solve_workspace_bytes(int n, int nrhs, const spdinv_opts* opts);
@@ -359,7 +373,9 @@ int spd_inverse_backward(int n, const double* X, int ldx, const double* G, int l
  *            and overwritten; lda >= max(1,n))
  *   stream   HIP stream; the call is asynchronous (it never waits)
  *   opts     host or NULL, as for spd_inverse (FP64 variants, chain, per_cu,
- *            no_split, parts, fill_upper, workers); trace is rejected (-5)
+ *            no_split, parts, fill_upper, workers, rename_tiles); trace
+ *            and tree_levels (whose partial sums need more than the
+ *            scratch array holds) are rejected (-5)
  *   d_info   device int or NULL: INFO as for spd_inverse
  * Returns 0, -i for an invalid i-th argument, or SPDINV_ERR_HIP.
  * Every call on one GPU uses that GPU's single scratch array, whose contents
@@ -473,7 +489,8 @@ enum {
   SPDINV_TASK_NOP = 0, SPDINV_TASK_SYRK1 = 1, SPDINV_TASK_POTRF = 2, SPDINV_TASK_GEMM1 = 3,
   SPDINV_TASK_TRSM1 = 4, SPDINV_TASK_TRTRI = 5, SPDINV_TASK_TRMM2L = 6, SPDINV_TASK_GEMM2 = 7,
   SPDINV_TASK_TRSM2R = 8, SPDINV_TASK_TRMM3 = 9, SPDINV_TASK_LAUUM = 10, SPDINV_TASK_GEMM3 = 11,
-  SPDINV_TASK_SYRK3 = 12, SPDINV_TASK_GEMMS = 13, SPDINV_TASK_TRSMS = 14
+  SPDINV_TASK_SYRK3 = 12, SPDINV_TASK_GEMMS = 13, SPDINV_TASK_TRSMS = 14,
+  SPDINV_TASK_TADD = 15
 };
 
 /* Builds (without caching) the plan for t tiles per side and returns its

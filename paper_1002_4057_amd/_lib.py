@@ -25,7 +25,7 @@ ERR_UNSUPPORTED = 4
 NOALLOC_MAX_N = 2048
 
 TASK_NAMES = ["NOP", "SYRK1", "POTRF", "GEMM1", "TRSM1", "TRTRI", "TRMM2L", "GEMM2", "TRSM2R",
-              "TRMM3", "LAUUM", "GEMM3", "SYRK3"]
+              "TRMM3", "LAUUM", "GEMM3", "SYRK3", "GEMMS", "TRSMS", "TADD"]
 
 
 class Opts(ctypes.Structure):
@@ -35,7 +35,7 @@ class Opts(ctypes.Structure):
                 ("max_refine", ctypes.c_int), ("refine_tol", ctypes.c_double),
                 ("chain", ctypes.c_int), ("per_cu", ctypes.c_int), ("no_split", ctypes.c_int),
                 ("parts", ctypes.c_int), ("rename_tiles", ctypes.c_int),
-                ("batch_group", ctypes.c_int)]
+                ("tree_levels", ctypes.c_int), ("batch_group", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):

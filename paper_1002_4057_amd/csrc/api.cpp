@@ -47,6 +47,7 @@ const double kCost[K_COUNT + 2] = {
     1.0,    // SYRK3
     1.2,    // GEMMS (solve update; general product, untransposed operand)
     1.2,    // TRSMS (solve: multiplication by D_i or D_i^T)
+    0.15,   // TADD (a partial sum of a tree-reduced chain added to its tile)
     0.76,   // each further link of a chained product
     0.6,    // a row half of a split product (fraction of the product)
 };
@@ -57,11 +58,12 @@ constexpr int kDefaultChain = 8;
 struct Key {
   int device, t, renamed, loop_order, pipelined, trtri_first, workers, chain, steps, rhs, split;
   long long rename;  // copy-tile budget of a partial renaming, 0 = full
+  int tree;          // tree-reduction levels of the step-2 chains
   bool operator<(const Key& o) const {
     return std::tie(device, t, renamed, loop_order, pipelined, trtri_first, workers, chain, steps,
-                    rhs, split, rename) < std::tie(o.device, o.t, o.renamed, o.loop_order,
-                                                   o.pipelined, o.trtri_first, o.workers, o.chain,
-                                                   o.steps, o.rhs, o.split, o.rename);
+                    rhs, split, rename, tree) <
+           std::tie(o.device, o.t, o.renamed, o.loop_order, o.pipelined, o.trtri_first, o.workers,
+                    o.chain, o.steps, o.rhs, o.split, o.rename, o.tree);
   }
 };
 
@@ -109,6 +111,7 @@ spdinv_opts defaults() {
   o.parts = 0;
   o.batch_group = 0;
   o.rename_tiles = 0;
+  o.tree_levels = 0;
   return o;
 }
 
@@ -118,13 +121,20 @@ int tiles_for(int n) { return (n + NB - 1) / NB; }
 
 // Device tasks of a plan at most, for t tiles per side and s tile columns of
 // right-hand sides: the paper's tasks of the three steps, two barriers, the
-// solve's (t (t+1) s <= 2 t^2 s), and the further row parts of split products
-// (at most 3 each, for at most 2t products of step 1 and 4ts of the solve).
-long long task_count(int t, int s = 0) {
+// solve's (t (t+1) s <= 2 t^2 s), the further row parts of split products
+// (at most 3 each, for at most 2t products of step 1 and 4ts of the solve),
+// and with a tree reduction of `tree` levels at most 2^tree - 1 tile
+// additions per off-diagonal tile.
+long long task_count(int t, int s = 0, int tree = 0) {
   const long long tt = t, ss = s;
   return 3 * (tt * (tt - 1) * (tt - 2) / 6) + 6 * (tt * (tt - 1) / 2) + 3 * tt + 2 +
-         2 * tt * tt * ss + 3 * (2 * tt + 4 * tt * ss);
+         2 * tt * tt * ss + 3 * (2 * tt + 4 * tt * ss) +
+         (tree > 0 ? ((1LL << tree) - 1) * (tt * (tt - 1) / 2) : 0);
 }
+
+// Tree-reduction levels of the step-2 chains for these options: plans that
+// contain step 2 (the inverse and the inverse from a factor).
+int tree_for(const spdinv_opts& o, int steps) { return (steps & 2) ? o.tree_levels : 0; }
 
 // Copy-tile budget of a partial renaming for these options (0 = full
 // renaming): only the inverse (steps 7) of a renamed plan whose budget is
@@ -166,11 +176,13 @@ const RenRows& renaming_rows(int t, const spdinv_opts& o, long long budget) {
 // right-hand sides.
 long long pool_tiles_for(int t, const spdinv_opts& o, int steps, int s) {
   const long long T = (long long)t * (t + 1) / 2;
-  if (steps != 7) return pool_tiles(t, s);  // the standard layout of the partial plans
-  if (!o.renamed) return T + 2LL * t;       // in place: no copies
+  const int tree = tree_for(o, steps);
+  const long long z = tree ? T * ((1LL << tree) - 1) : 0;  // partial sums, after the rest
+  if (steps != 7) return pool_tiles(t, s) + z;  // the standard layout of the partial plans
+  if (!o.renamed) return T + 2LL * t + z;       // in place: no copies
   const long long budget = rename_budget(t, o, steps);
-  if (!budget) return pool_tiles(t, s);
-  return T + renaming_rows(t, o, budget).copy_tiles + 2LL * t + (long long)t * s;
+  if (!budget) return pool_tiles(t, s) + z;
+  return T + renaming_rows(t, o, budget).copy_tiles + 2LL * t + (long long)t * s + z;
 }
 
 struct Layout {
@@ -181,7 +193,7 @@ Layout layout(int n, const spdinv_opts& o, int nrhs = 0, int steps = 7) {
   Layout L;
   const int t = tiles_for(n);
   const int s = (nrhs + NB - 1) / NB;
-  const long long nt = task_count(t, s);
+  const long long nt = task_count(t, s, tree_for(o, steps));
   L.pool = 0;
   L.indeg = align_up((size_t)pool_tiles_for(t, o, steps, s) * NB * NB * sizeof(double), 256);
   L.ctrl = L.indeg + align_up((size_t)nt * sizeof(int32_t), 256);
@@ -200,6 +212,7 @@ int check_opts(const spdinv_opts& o) {
   if (o.parts != 0 && o.parts != 2 && o.parts != 4) return 1;
   if (o.batch_group < -2) return 1;
   if (o.rename_tiles < 0) return 1;
+  if (o.tree_levels < 0 || o.tree_levels > 2) return 1;
   return 0;
 }
 
@@ -358,7 +371,8 @@ Key plan_key(int device, int t, const spdinv_opts& o, int workers, int chain, in
              int rhs_tiles, bool allow_split) {
   return Key{device, t, o.renamed ? 1 : 0, o.loop_order, o.pipelined ? 1 : 0,
              o.trtri_first ? 1 : 0, workers, chain, steps, rhs_tiles,
-             allow_split ? split_for(o, t, workers) : 0, rename_budget(t, o, steps)};
+             allow_split ? split_for(o, t, workers) : 0, rename_budget(t, o, steps),
+             tree_for(o, steps)};
 }
 
 std::unique_ptr<DevPlan> build_dev_plan(const Key& k) {
@@ -373,6 +387,7 @@ std::unique_ptr<DevPlan> build_dev_plan(const Key& k) {
   po.steps = k.steps;
   po.rhs_tiles = k.rhs;
   po.split = k.split;
+  po.tree_levels = k.tree;
   if (k.rename) {
     spdinv_opts o = defaults();
     o.loop_order = k.loop_order;
@@ -470,6 +485,8 @@ int run_fp64(int n, double* A, int lda, void* work, size_t work_bytes, hipStream
   DevPlan* dp = given ? given : get_plan(device, t, o, grid, chain_for(o), &err, steps, s, true);
   if (!dp) return SPDINV_ERR_HIP;
   const int ntask = (int)dp->host.tasks.size();
+  // the in-degree counters fill the region sized for the bound
+  if ((size_t)ntask * sizeof(int32_t) > L.ctrl - L.indeg) return SPDINV_ERR_WORKSPACE;
 
   char* w = (char*)work;
   double* pool = (double*)(w + L.pool);
@@ -1621,7 +1638,9 @@ int spd_inverse(int n, void* A_, int lda, spdinv_mode mode, void* work, size_t w
   const spdinv_opts o = opts ? *opts : defaults();
   if (check_opts(o)) return -8;
   const bool mixed = mode == SPDINV_MIXED_FP32 || mode == SPDINV_MIXED_BF16;
-  if ((mixed || mode == SPDINV_FP32) && (!o.renamed || o.trace || o.rename_tiles)) return -8;
+  if ((mixed || mode == SPDINV_FP32) &&
+      (!o.renamed || o.trace || o.rename_tiles || o.tree_levels))
+    return -8;
   if (report) std::memset(report, 0, sizeof(*report));
   if (n == 0) {
     if (d_info) {
@@ -1650,7 +1669,8 @@ static int fp64_entry(int n, double* A, int lda, void* work, size_t work_bytes,
   if (n > 0 && !A) return -2;
   if (lda < (n > 1 ? n : 1)) return -3;
   const spdinv_opts o = opts ? *opts : defaults();
-  if (check_opts(o)) return -7;
+  // the steps on their own run the renamed plan in the standard layout
+  if (check_opts(o) || !o.renamed || o.rename_tiles) return -7;
   if (report) std::memset(report, 0, sizeof(*report));
   if (n == 0) {
     if (d_info) {
@@ -1696,7 +1716,7 @@ static int solve_entry(int n, int nrhs, double* A, int lda, double* Bm, int ldb,
   if (n > 0 && nrhs > 0 && !Bm) return -5;
   if (ldb < (n > 1 ? n : 1)) return -6;
   const spdinv_opts o = opts ? *opts : defaults();
-  if (check_opts(o)) return -10;
+  if (check_opts(o) || !o.renamed || o.rename_tiles) return -10;
   if (report) std::memset(report, 0, sizeof(*report));
   if (n == 0) {
     if (d_info) {
@@ -1752,7 +1772,7 @@ int spd_inverse_noalloc(int n, double* A, int lda, spdinv_stream_t stream_,
   if (n > 0 && !A) return -2;
   if (lda < (n > 1 ? n : 1)) return -3;
   const spdinv_opts o0 = opts ? *opts : defaults();
-  if (check_opts(o0) || o0.trace) return -5;
+  if (check_opts(o0) || o0.trace || o0.tree_levels) return -5;
   if (n == 0) return launch_info_zero(d_info, stream) == hipSuccess ? 0 : SPDINV_ERR_HIP;
   const spdinv_opts o = tuned_fp64(o0, tiles_for(n));
   int device = 0;
@@ -2102,6 +2122,7 @@ static PlanOptions plan_options(int t, const spdinv_opts* opts, int steps = 7) {
   po.pipelined = o.pipelined ? 1 : 0;
   po.trtri_first = o.trtri_first ? 1 : 0;
   po.chain = std::min(std::max(chain_for(o), 1), MAX_CHAIN);
+  po.tree_levels = tree_for(o, steps);
   const long long budget = rename_budget(t, o, steps);
   if (budget) {
     const RenRows& r = renaming_rows(t, o, budget);

@@ -27,6 +27,11 @@ struct Builder {
   bool rb(int i) const { return o.renamed && (o.ren_b.empty() || o.ren_b[i]); }
   bool rc(int i) const { return o.renamed && (o.ren_c.empty() || o.ren_c[i]); }
 
+  // partial-sum tiles of the tree reduction: tile (i, j), segment l >= 1
+  int zper = 0, zname = 0, zbase = 0;
+  int Zh(int i, int j, int l) const { return zname + tri(i, j) * zper + (l - 1); }
+  int Zd(int i, int j, int l) const { return zbase + tri(i, j) * zper + (l - 1); }
+
   Builder(const PlanOptions& opt, Plan* plan) : o(opt), t(opt.t), p(plan) {
     T = t * (t + 1) / 2;
     boff.assign(t, -1);
@@ -57,8 +62,12 @@ struct Builder {
       dbase = next;
     }
     p->d_base = dbase;
-    p->pool_tiles = (int64_t)dbase + 2 * (int64_t)t + (int64_t)t * opt.rhs_tiles;
-    const size_t names = 3 * (size_t)T + (size_t)t * opt.rhs_tiles;
+    const int levels = std::min(std::max(opt.tree_levels, 0), 2);
+    zper = (levels > 0 && (opt.steps & 2)) ? (1 << levels) - 1 : 0;
+    zbase = dbase + 2 * t + t * opt.rhs_tiles;
+    p->pool_tiles = (int64_t)zbase + (int64_t)T * zper;
+    zname = 3 * T + t * opt.rhs_tiles;
+    const size_t names = (size_t)zname + (size_t)T * zper;
     last_writer.assign(names, -1);
     readers.resize(names);
   }
@@ -266,7 +275,9 @@ struct Builder {
   // in the UDU order, upward in UUU) and closes with the multiplication by
   // L_jj^{-1}.  The diagonal tile of the column is inverted after its
   // column (LAPACK order, reading L_jj) or before it (trtri_first, reading
-  // X_jj).
+  // X_jj).  With tree levels, the chain's sum is reassociated (the
+  // associativity the conclusion, Section 4, points to) into segments run
+  // side by side.
   void step2() {
     cur_step = 2;
     const bool down = (o.loop_order == 0);  // UDU: step-2 chain runs downward
@@ -274,11 +285,66 @@ struct Builder {
       if (o.trtri_first) op(K_TRTRI, j, j, 0);
       for (int i = t - 1; i > j; --i) {
         op(K_TRMM2L, i, j, 0);
-        for (int s = 0; s < i - j - 1; ++s) op(K_GEMM2, i, j, down ? i - 1 - s : j + 1 + s);
+        const int m = i - j - 1;
+        auto kk = [&](int s) { return down ? i - 1 - s : j + 1 + s; };
+        if (!zper || m < 2) {
+          for (int s = 0; s < m; ++s) op(K_GEMM2, i, j, kk(s));
+        } else {
+          // the chain cut into segs consecutive ranges of k (as equal as
+          // possible, none empty), each in the loop order: segment l >= 1
+          // (larger k, whose X_ik are final earlier) into its partial sum
+          // Z_l, the partial sums added into A_ij in a fixed binary tree,
+          // then segment 0 (k from j + 1, the last tiles to become final)
+          // straight into A_ij, so that the chain's tail stays where the
+          // sequential chain has it
+          const int segs = std::min(zper + 1, m);
+          auto terms = [&](int l, auto f) {
+            const int k0 = j + 1 + (int)((long long)m * l / segs);
+            const int k1 = j + 1 + (int)((long long)m * (l + 1) / segs);
+            if (down)
+              for (int k = k1 - 1; k >= k0; --k) f(k, k == k1 - 1);
+            else
+              for (int k = k0; k < k1; ++k) f(k, k == k0);
+          };
+          for (int l = 1; l < segs; ++l)
+            terms(l, [&](int k, bool first) { gemm2_partial(i, j, k, l, first); });
+          auto add = [&](int dst, int src) {
+            if (dst == 0)
+              emit(K_TADD, i, j, src, {Zh(i, j, src), A(i, j)}, {A(i, j)}, A(i, j), Zd(i, j, src),
+                   -1, -1, -1, F_ACC);
+            else
+              emit(K_TADD, i, j, src, {Zh(i, j, src), Zh(i, j, dst)}, {Zh(i, j, dst)},
+                   Zd(i, j, dst), Zd(i, j, src), -1, -1, -1, F_ACC);
+          };
+          if (segs == 2) {
+            add(0, 1);
+          } else if (segs == 3) {
+            add(1, 2);
+            add(0, 1);
+          } else {
+            add(1, 2);
+            add(0, 3);
+            add(0, 1);
+          }
+          terms(0, [&](int k, bool) { op(K_GEMM2, i, j, k); });
+        }
         op(K_TRSM2R, i, j, 0);
       }
       if (!o.trtri_first) op(K_TRTRI, j, j, 0);
     }
+  }
+
+  // One term X_ik L_kj of the chain of tile (i, j) into its partial sum Z_l
+  // (the first term of a segment overwrites it), in the form op() gives the
+  // renamed or in-place step-2 product.
+  void gemm2_partial(int i, int j, int k, int l, bool first) {
+    const int acc = first ? 0 : F_ACC;
+    if (rb(k))
+      emit(K_GEMM2, i, j, k, {A(i, k), B(k, j), Zh(i, j, l)}, {Zh(i, j, l)}, Zd(i, j, l), A(i, k),
+           Bd(k, j), -1, -1, F_TB | acc);
+    else
+      emit(K_GEMM2, i, j, k, {A(i, k), A(k, j), Zh(i, j, l)}, {Zh(i, j, l)}, Zd(i, j, l), A(i, k),
+           A(k, j), -1, -1, acc);
   }
 
   // Step 3: (X^T X)_ij = sum_{k >= i} X_ki^T X_kj for i >= j.  Rows top down;
@@ -420,7 +486,7 @@ void list_schedule(const std::vector<std::vector<int32_t>>& preds, const std::ve
 // op(B) = B^T, no masks): the form the chained device product executes.
 bool column_product(const DevTask& d) {
   const int k = task_kind(d.kind);
-  if (k == K_NOP || k == K_POTRF || k == K_TRTRI) return false;
+  if (k == K_NOP || k == K_POTRF || k == K_TRTRI || k == K_TADD) return false;
   const int f = task_flags(d.kind);
   return (f & (F_TA | F_MA | F_MB)) == 0 && (f & F_TB) != 0;
 }
@@ -691,7 +757,7 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
     for (int u = 0; u < nt; ++u) {
       DevTask& d = p->tasks[u];
       const int k = task_kind(d.kind);
-      if (k == K_NOP || k == K_POTRF || k == K_TRTRI) continue;
+      if (k == K_NOP || k == K_POTRF || k == K_TRTRI || k == K_TADD) continue;
       if (cacheable(d.a)) d.kind |= K_NC_A;
       if (cacheable(d.b)) d.kind |= K_NC_B;
     }

@@ -52,7 +52,8 @@ enum Kind : int32_t {
   K_SYRK3 = 12,  // A_ii += X_ki^T X_ki
   K_GEMMS = 13,  // solve: R_ic -= L_ik R_kc (forward) or L_ki^T R_kc (backward)
   K_TRSMS = 14,  // solve: R_ic <- L_ii^{-1} R_ic = D_i R_ic (or D_i^T R_ic)
-  K_COUNT = 15
+  K_TADD = 15,   // tree reduction of a step-2 update chain: A_ij += Z (a partial sum)
+  K_COUNT = 16
 };
 
 struct PlanOptions {
@@ -78,6 +79,15 @@ struct PlanOptions {
   // tile (j+1, j+1), between POTRF(j) and POTRF(j+1), and in the solve each
   // multiplication by D_i or D_i^T with the last update before it.
   int split = 0;
+  // Tree reduction of the step-2 update chains (associativity; the
+  // conclusion's proposal): 0 = the paper's sequential chains; L = 1 or 2:
+  // each chain A_ij += sum_k X_ik L_kj is cut into 2^L consecutive segments
+  // (in the chain's order), accumulated side by side -- the first into A_ij,
+  // the others into partial-sum tiles Z -- and the partial sums are added in
+  // a fixed binary tree (K_TADD), so the result does not depend on the
+  // schedule.  The 2^L - 1 partial-sum tiles of each lower tile follow the
+  // pool's other regions.
+  int tree_levels = 0;
   // Partial renaming (renamed = 1): per tile row i, ren_b[i] / ren_c[i] say
   // whether the tiles of row i have the renaming copy B (of L) / C (of
   // L^{-1}); rows without it are read in place, with the paper's

@@ -972,6 +972,18 @@ __device__ __attribute__((noinline)) int trtri_inv_tile(const double* Lin, doubl
 
 // dst <- src for one tile; loads are issued in batches of 16 independent
 // 16-byte loads per thread so that their latencies overlap.
+// dst += src (dst -= src with neg), elementwise over the tile, with
+// agent-coherent accesses like every pool access of the scheduler.
+__device__ __forceinline__ void tile_add(const double* src, double* dst, bool neg) {
+  const rsrc_t rs = tile_rsrc(src), rd = tile_rsrc(dst);
+#pragma unroll 4
+  for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
+    const int e = 2 * (threadIdx.x + NTHREADS * q);
+    const d2 x = ld2(rs, e), y = ld2(rd, e);
+    st2(rd, e, neg ? y - x : y + x);
+  }
+}
+
 __device__ __forceinline__ void tile_copy(const double* src, double* dst) {
   const rsrc_t rs = tile_rsrc(src), rd = tile_rsrc(dst);
 #pragma unroll
@@ -1052,6 +1064,9 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
       }
       break;
     }
+    case K_TADD:    // tree reduction: A_ij (or a partial sum) += the partial sum a
+      tile_add(a, out, (f & F_NEG) != 0);
+      break;
     case K_TRTRI:   // A_jj <- D_j, and C_jj <- D_j^T (inverse made by POTRF(j))
       tile_copy(a, out);
       if (cp) tile_copy(b, cp);

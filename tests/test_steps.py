@@ -235,3 +235,18 @@ def test_solve_entry_points_reject_invalid_arguments_on_host(name, args, code):
     fn = getattr(lib, name)
     assert fn(n, nrhs, a and ctypes.c_void_p(a), lda, b and ctypes.c_void_p(b), ldb, None, 0, None,
               ctypes.byref(o), None, None) == code
+
+
+@pytest.mark.parametrize("name", ["spd_cholesky", "spd_inverse_from_factor"])
+@pytest.mark.parametrize("opts", [dict(renamed=0), dict(rename_tiles=5)])
+def test_step_entry_points_run_the_renamed_plan_only(name, opts):
+    """The steps on their own use the standard layout of the renamed plan
+    (the factor prologue writes every copy): the in-place and partially
+    renamed options, whose workspace query is smaller, are rejected."""
+    lib = _lib.load()
+    o = _lib.make_opts(**opts)
+    assert getattr(lib, name)(4, ctypes.c_void_p(8), 4, ctypes.c_void_p(8), 1 << 20, None,
+                              ctypes.byref(o), None, None) == -7
+    b = ctypes.c_void_p(8)
+    assert lib.spd_solve(4, 1, ctypes.c_void_p(8), 4, b, 4, ctypes.c_void_p(8), 1 << 20, None,
+                         ctypes.byref(o), None, None) == -10

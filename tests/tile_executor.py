@@ -11,6 +11,7 @@ import numpy as np
 
 NOP, SYRK1, POTRF, GEMM1, TRSM1, TRTRI, TRMM2L, GEMM2, TRSM2R, TRMM3, LAUUM, GEMM3, SYRK3 = range(13)
 GEMMS, TRSMS = 13, 14   # the solve with the factor
+TADD = 15               # tree reduction: out (+/-)= a
 POTRF_FACTOR_DEAD = 1 << 16
 LINKS_SHIFT = 20   # chained products: count of further links (see plan.hpp)
 PART, PART_SHIFT, PARTS4 = 1 << 24, 25, 1 << 27   # row-part task (see plan.hpp)
@@ -23,14 +24,15 @@ def tri(i, j):
     return i * (i + 1) // 2 + j
 
 
-def to_pool(a, t, nb):
-    """Lower tiles of a (zero-padded, identity on the padded diagonal)."""
+def to_pool(a, t, nb, extra=0):
+    """Lower tiles of a (zero-padded, identity on the padded diagonal), in a
+    pool of the standard 3T + 2t tiles plus `extra`."""
     n = a.shape[0]
     m = t * nb
     full = np.eye(m)
     full[:n, :n] = np.tril(a)
     T = t * (t + 1) // 2
-    pool = np.zeros((3 * T + 2 * t, nb, nb))
+    pool = np.zeros((3 * T + 2 * t + extra, nb, nb))
     for i in range(t):
         for j in range(i + 1):
             pool[tri(i, j)] = full[i * nb:(i + 1) * nb, j * nb:(j + 1) * nb]
@@ -107,6 +109,8 @@ def run_task(pool, task, t, links=None):
             pool[out] = L
             if cp >= 0:
                 pool[cp] = L.T
+    elif kind == TADD:
+        pool[out] = pool[out] - pool[a] if f & F_NEG else pool[out] + pool[a]
     elif kind == TRTRI:
         pool[out] = pool[a]
         if cp >= 0:
@@ -138,9 +142,9 @@ def random_topological_order(tasks, succ, rng, removed=None):
     return order
 
 
-def execute(plan, a, nb, order=None):
+def execute(plan, a, nb, order=None, extra=0):
     t = plan["t"]
-    pool = to_pool(a, t, nb)
+    pool = to_pool(a, t, nb, extra)
     tasks = plan["tasks"]
     for v in (range(len(tasks)) if order is None else order):
         run_task(pool, tasks[v], t, plan.get("links"))
