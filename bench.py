@@ -156,7 +156,7 @@ def precision_cells(n, q, kappas, modes, reps, work=None):
     from paper_1002_4057_amd import inputs
     dev = q.device
     if work is None:
-        need = max(spd.workspace_bytes(n, mode=m) for m in modes)
+        need = max(spd.workspace_bytes(n, mode=m.partition("+")[0]) for m in modes)
         work = torch.empty(need, dtype=torch.uint8, device=dev)
     cells = {}
     for kappa in kappas:
@@ -164,29 +164,34 @@ def precision_cells(n, q, kappas, modes, reps, work=None):
         a_cm = a.t().contiguous()
         buf = torch.empty_like(a_cm)
         row = {}
-        for mode in modes:
-            log(f"[bench] precision n={n} kappa={kappa:g} {mode}")
+        for label in modes:
+            # "mode+c64": every refinement correction in binary64
+            mode, _, flag = label.partition("+")
+            mopts = {"correction64": 1} if flag == "c64" else {}
+            log(f"[bench] precision n={n} kappa={kappa:g} {label}")
             buf.copy_(a_cm)
-            rep = spd.spd_inverse_(buf.t(), mode=mode, work=work, report=True)   # warm
+            rep = spd.spd_inverse_(buf.t(), mode=mode, work=work, report=True, **mopts)   # warm
             x = sym_from_lower_cm(buf)
             ref = inputs.analytic_inverse(q, lam)
             err = (torch.linalg.norm(x - ref) / torch.linalg.norm(ref)).item()
             del ref
             res = resid_rel(a, x)
             del x
-            ms = time_events(lambda: spd.spd_inverse_(buf.t(), mode=mode, work=work), reps,
-                             prep=lambda: buf.copy_(a_cm), agg="median")
+            ms = time_events(lambda: spd.spd_inverse_(buf.t(), mode=mode, work=work, **mopts),
+                             reps, prep=lambda: buf.copy_(a_cm), agg="median")
             cell = {"ms": round(ms, 2), "gflops": round(float(n) ** 3 / (ms / 1e3) / 1e9, 1),
                     "resid_fro_rel": res, "err_vs_analytic": err}
             if mode != "fp64":
                 cell.update({"refine_iters": rep["refine_iters"], "fell_back": rep["fell_back"],
                              "converged": rep["converged"], "predicted_stop": rep["predicted"],
-                             "resid0_fro_rel": rep["resid0_fro_rel"]})
-            row[mode] = cell
+                             "resid0_fro_rel": rep["resid0_fro_rel"],
+                             "fp32_corrections": rep["low_corrections"]})
+            row[label] = cell
         if "fp64" in row:
-            for mode in modes:
-                if mode != "fp64":
-                    row[mode]["speedup_over_fp64"] = round(row["fp64"]["ms"] / row[mode]["ms"], 3)
+            for label in modes:
+                if label != "fp64":
+                    row[label]["speedup_over_fp64"] = round(row["fp64"]["ms"] / row[label]["ms"],
+                                                            3)
         cells[f"{kappa:g}"] = row
         del a, a_cm, buf
         torch.cuda.empty_cache()
@@ -460,7 +465,8 @@ def main():
                          "pipelined vs unpipelined), ablation (plan variants at n = 8192), "
                          "tree (step-2 tree reduction at small orders), batched, backward, steps")
     ap.add_argument("--kappas", default="1e2,1e6,1e10", help="precision row condition numbers")
-    ap.add_argument("--modes", default="fp64,mixed_fp32,mixed_bf16", help="precision row modes")
+    ap.add_argument("--modes", default="fp64,mixed_fp32,mixed_fp32+c64,mixed_bf16",
+                    help="precision row modes (+c64: every refinement correction in binary64)")
     ap.add_argument("--large-n", type=int, default=32768)
     ap.add_argument("--large-kappas", default="1e2")
     ap.add_argument("--large-modes", default="fp64,mixed_fp32")
@@ -562,9 +568,10 @@ def main():
         del a, a_cm
         rows["precision"] = {
             "workload": f"precision form, n={n}, A = Q diag(lambda) Q^T, lambda log-spaced over "
-                        "[1,kappa]; FP64 against mixed (FP32 or BF16 tile DAG, binary64 "
-                        "Newton-Schulz refinement, stop at ||I-AX||_F/||A||_F <= 1e-13); "
-                        "median of 3 after one warm call",
+                        "[1,kappa]; FP64 against mixed (FP32 or BF16 tile DAG, "
+                        "Newton-Schulz refinement with binary64 residuals and FP32-MFMA "
+                        "corrections but the last, or (+c64) every correction in binary64; "
+                        "stop at ||I-AX||_F/||A||_F <= 1e-13); median of 3 after one warm call",
             "cells": precision_cells(n, q, kappas, modes, 3, work=None)}
     del q, work
     torch.cuda.empty_cache()

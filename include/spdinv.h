@@ -147,6 +147,14 @@ typedef struct {
                       library's choice: -1 when the batch has at least two
                       matrices per worker, else -2.  Results do not depend
                       on it.                                                 */
+  int correction64; /* mixed modes: 0 (default) = the correction X R of each
+                      refinement step that another residual follows runs on
+                      the FP32 matrix cores (X and R rounded to FP32, FP32
+                      accumulation, added to X in binary64), the last step's
+                      in binary64; a low-precision step that fails to square
+                      the residual (within a factor 100) switches the
+                      remaining steps to binary64.  1 = every correction in
+                      binary64.                                               */
 } spdinv_opts;
 
 typedef struct {
@@ -172,6 +180,8 @@ typedef struct {
   int converged;       /* mixed modes: 1 when the stop rule was met           */
   int predicted;       /* mixed modes: 1 when the loop stopped on the prediction
                           (the residual of the returned X was not formed)     */
+  int low_corrections; /* mixed modes: refinement steps whose correction ran on
+                          the FP32 matrix cores                               */
 } spdinv_report;
 
 /* Fills `opts` with the defaults. */
@@ -193,10 +203,11 @@ size_t spd_inverse_workspace_bytes(int n, spdinv_mode mode, const spdinv_opts* o
  * without refinement.  mode SPDINV_MIXED_FP32
  * (renamed plan only) runs the same DAG with FP32 tiles to get X0, then
  * refines by Newton-Schulz: R = I - A X in binary64, stop when
- * ||R||_F / ||A||_F <= refine_tol, else X <- X + X R (binary64, lower tiles,
- * mirrored); since I - A (X + X R) = R^2, the loop also stops, without
- * forming the next residual, once (||R||_F^2 + 4 u ||A||_F ||X||_F) / ||A||_F
- * meets the rule (u = 2^-53).  It synchronizes the stream once per step.  It
+ * ||R||_F / ||A||_F <= refine_tol, else X <- X + X R (lower tiles, mirrored);
+ * since I - A (X + X R) = R^2, the loop also stops, without forming the
+ * next residual, once (||R||_F^2 + 4 u ||A||_F ||X||_F) / ||A||_F meets the
+ * rule (u = 2^-53).  That last correction is formed in binary64, the earlier
+ * ones on the FP32 matrix cores (see opts->correction64).  It synchronizes the stream once per step.  It
  * falls back to the FP64 path when the FP32 factorization breaks down, when
  * ||R_0||_F >= 1, or when the default step limit runs out first (with an
  * explicit max_refine or refine_tol it returns the refined X instead, with

@@ -35,7 +35,8 @@ class Opts(ctypes.Structure):
                 ("max_refine", ctypes.c_int), ("refine_tol", ctypes.c_double),
                 ("chain", ctypes.c_int), ("per_cu", ctypes.c_int), ("no_split", ctypes.c_int),
                 ("parts", ctypes.c_int), ("rename_tiles", ctypes.c_int),
-                ("tree_levels", ctypes.c_int), ("batch_group", ctypes.c_int)]
+                ("tree_levels", ctypes.c_int), ("batch_group", ctypes.c_int),
+                ("correction64", ctypes.c_int)]
 
 
 class Report(ctypes.Structure):
@@ -45,7 +46,7 @@ class Report(ctypes.Structure):
                 ("refine_iters", ctypes.c_int), ("fell_back", ctypes.c_int),
                 ("resid_fro_rel", ctypes.c_double), ("resid0_fro_rel", ctypes.c_double),
                 ("resid_last_rel", ctypes.c_double), ("converged", ctypes.c_int),
-                ("predicted", ctypes.c_int)]
+                ("predicted", ctypes.c_int), ("low_corrections", ctypes.c_int)]
 
 
 class Tuning(ctypes.Structure):

@@ -112,6 +112,7 @@ spdinv_opts defaults() {
   o.batch_group = 0;
   o.rename_tiles = 0;
   o.tree_levels = 0;
+  o.correction64 = 0;
   return o;
 }
 
@@ -213,6 +214,7 @@ int check_opts(const spdinv_opts& o) {
   if (o.batch_group < -2) return 1;
   if (o.rename_tiles < 0) return 1;
   if (o.tree_levels < 0 || o.tree_levels > 2) return 1;
+  if (o.correction64 < 0 || o.correction64 > 1) return 1;
   return 0;
 }
 
@@ -1337,11 +1339,13 @@ int spd_inverse_backward(int n, const double* X, int ldx, const double* G, int l
 
 // Mixed-precision form.  Workspace: the FP32 tile pool and the scheduler
 // state, then four square tile-major binary64 matrices (A, X, the next X, the
-// residual) and the norm scratch.  The FP64 fallback reuses the workspace
-// from offset 0 (everything in it is dead by then; A itself is untouched
-// until the final copy-out).
+// residual), the norm scratch and the FP32 copy of the residual for the
+// low-precision correction (the FP32 copy of X takes the pool's place, dead
+// once X0 is widened).  The FP64 fallback reuses the workspace from offset 0
+// (everything in it is dead by then; A itself is untouched until the final
+// copy-out).
 struct MixedLayout {
-  size_t indeg, ctrl, asq, x, x2, r, partial, total;
+  size_t indeg, ctrl, asq, x, x2, r, partial, r32, total;
 };
 
 MixedLayout mixed_layout(int n, const spdinv_opts& o) {
@@ -1356,7 +1360,8 @@ MixedLayout mixed_layout(int n, const spdinv_opts& o) {
   M.x2 = M.x + sq;
   M.r = M.x2 + sq;
   M.partial = M.r + sq;
-  M.total = M.partial + align_up(((size_t)t * t + 8) * sizeof(double), 256);
+  M.r32 = M.partial + align_up(((size_t)t * t + 8) * sizeof(double), 256);
+  M.total = M.r32 + align_up(sq / 2, 256);
   spdinv_opts o64 = o;
   o64.trace = 0;
   M.total = std::max(M.total, layout(n, o64).total);
@@ -1500,7 +1505,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
 
   bool fallback = c[CTRL_FAILED] != 0;
   int fell_back = fallback ? 1 : 0;
-  int iters = 0, converged = 0, predicted = 0;
+  int iters = 0, converged = 0, predicted = 0, low_steps = 0;
   double r0 = -1.0, rl = -1.0, rpred = -1.0;
   double* X = nullptr;
   if (!fallback) {
@@ -1515,6 +1520,14 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
     if (launch_sumsq(Asq, sq_tiles, partial, dnorm, stream) != hipSuccess) return SPDINV_ERR_HIP;
     if (launch_x0_to_sym64(pool, t, n, X, stream) != hipSuccess) return SPDINV_ERR_HIP;
     if (launch_sumsq(X, sq_tiles, partial, dnorm + 2, stream) != hipSuccess) return SPDINV_ERR_HIP;
+    float* X32 = (float*)w;  // the FP32 pool is dead once X0 is widened
+    float* R32 = (float*)(w + M.r32);
+    const size_t sq_elems = (size_t)sq_tiles * NB * NB;
+    // the correction X R runs on the FP32 matrix cores while another
+    // residual follows it, as long as the steps it made stay quadratic
+    bool low_ok = !o.correction64;
+    bool last_low = false;
+    double prev_rnorm = 0.0;
     double anorm = 0.0, floor_abs = 0.0;
     for (int k = 0;; ++k) {
       // R^T = I - X A (A and X symmetric); ||R^T||_F = ||R||_F
@@ -1546,16 +1559,33 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
         break;
       }
       if (k >= max_refine) break;
+      // a low-precision step that did not square the residual (to within a
+      // factor: its rounding, about u_32 ||X|| ||R|| times kappa, has caught
+      // up with ||R||^2) leaves the remaining corrections to binary64
+      if (last_low && rnorm > 0.01 * prev_rnorm) low_ok = false;
+      prev_rnorm = rnorm;
+      // I - A X' = R^2 exactly for X' = X + X R, so ||I - A X'||_F <=
+      // ||R||_F^2 up to the rounding floor: when that prediction meets the
+      // stop rule, the step is the last (in binary64) and the residual of X'
+      // is not formed; otherwise another residual follows and the step's
+      // correction may run in FP32
+      const double pred = (rnorm * rnorm + floor_abs) / anorm;
+      const bool low = low_ok && pred > tol;
       // X' = X + X R on the lower tiles, X R = sum_k X(i, k) (R^T)(j, k)^T; then mirror
-      if (launch_gemm_nt(X, R, X2, t, 1, 0, stream, X, 0) != hipSuccess) return SPDINV_ERR_HIP;
+      if (low) {
+        if (launch_round32(X, X32, sq_elems, stream) != hipSuccess) return SPDINV_ERR_HIP;
+        if (launch_round32(R, R32, sq_elems, stream) != hipSuccess) return SPDINV_ERR_HIP;
+        if (launch_gemm_nt32_lower(X32, R32, X, X2, t, stream) != hipSuccess)
+          return SPDINV_ERR_HIP;
+        ++low_steps;
+      } else if (launch_gemm_nt(X, R, X2, t, 1, 0, stream, X, 0) != hipSuccess) {
+        return SPDINV_ERR_HIP;
+      }
       if (launch_mirror_lower(X2, t, stream) != hipSuccess) return SPDINV_ERR_HIP;
       std::swap(X, X2);
       ++iters;
-      // I - A X' = R^2 exactly, so ||I - A X'||_F <= ||R||_F^2 up to the
-      // rounding floor: when that prediction meets the stop rule, the
-      // residual of X' is not formed
-      const double pred = (rnorm * rnorm + floor_abs) / anorm;
-      if (pred <= tol) {
+      last_low = low;
+      if (!low && pred <= tol) {
         converged = 1;
         predicted = 1;
         rpred = pred;
@@ -1582,6 +1612,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
       report->refine_iters = iters;
       report->converged = 0;
       report->predicted = 0;
+      report->low_corrections = low_steps;
     }
     return rc;
   }
@@ -1604,6 +1635,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
     report->resid_last_rel = rl;
     report->converged = converged;
     report->predicted = predicted;
+    report->low_corrections = low_steps;
   }
   return 0;
 }

@@ -10,6 +10,8 @@
 // FP32 tiles are NB x NB floats, column-major, contiguous (64 KiB), in the
 // same pool layout as the FP64 path: A tiles, the transposed renaming copies
 // B and C, the inverted diagonal factor tiles D_j and D_j^T.
+#include <algorithm>
+
 #include "bsched_loop.hpp"
 #include "device.hpp"
 #include "mfma_tile.hpp"
@@ -330,6 +332,95 @@ __device__ __forceinline__ void tri_decode32(int x, int& ti, int& tj) {
   tj = x - i * (i + 1) / 2;
 }
 
+// dst = src rounded to FP32 (round to nearest), 4 elements per thread and
+// step; count4 = elements / 4.
+__global__ __launch_bounds__(NTHREADS) void round32_kernel(const double* __restrict__ src,
+                                                         float* __restrict__ dst, size_t count4) {
+  const size_t stride = (size_t)gridDim.x * NTHREADS;
+  for (size_t q = (size_t)blockIdx.x * NTHREADS + threadIdx.x; q < count4; q += stride) {
+    const double2 a = reinterpret_cast<const double2*>(src)[2 * q];
+    const double2 b = reinterpret_cast<const double2*>(src)[2 * q + 1];
+    const f4 v = {(float)a.x, (float)a.y, (float)b.x, (float)b.y};
+    reinterpret_cast<f4*>(dst)[q] = v;
+  }
+}
+
+// C(i, j) = Cin(i, j) + sum_k A(i, k) B(j, k)^T for the lower tiles i >= j
+// of square tile-major matrices (t x t tiles of NB x NB, tile (i, j) at
+// i + t j, column-major): the products on the FP32 matrix cores from FP32
+// operands with FP32 accumulation over the whole sum, added to Cin in
+// binary64.  One output tile per workgroup (blockIdx.x = i (i + 1) / 2 + j);
+// the k-panels of the t tile pairs stream through LDS double-buffered as in
+// tile_mma32.  Cin and C are distinct.
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void gemm_nt32_lower_kernel(const float* __restrict__ A, const float* __restrict__ B,
+                            const double* __restrict__ Cin, double* __restrict__ C, int t) {
+  __shared__ float smem[4 * PANEL32];
+  int ti, tj;
+  tri_decode32(blockIdx.x, ti, tj);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = w & 1, wn = w >> 1, lr = lane & 15, lk = lane >> 4;
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  f4 va[Q32], vb[Q32];
+  auto load = [&](int p) {
+    const int k = p / NCH, c = p - NCH * k;
+    panel_load32(rsrc32(A + (size_t)(ti + t * k) * TILE), c * KC, va);
+    panel_load32(rsrc32(B + (size_t)(tj + t * k) * TILE), c * KC, vb);
+  };
+  const int np = t * NCH;
+  load(0);
+  panel_store32(smem, va);
+  panel_store32(smem + PANEL32, vb);
+  __syncthreads();
+#pragma unroll 1
+  for (int p = 0; p < np; ++p) {
+    const float* As = smem + (p & 1) * 2 * PANEL32;
+    const float* Bs = As + PANEL32;
+    const bool more = p + 1 < np;
+    if (more) load(p + 1);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      const float* Ar = As + (4 * ks + lk) * LDS32 + wm * 64 + lr;
+      const float* Br = Bs + (4 * ks + lk) * LDS32 + wn * 64 + lr;
+      float a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = Ar[16 * i];
+        b[i] = Br[16 * i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[j], a[i], acc[i][j], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (more) {
+      float* Sn = smem + ((p + 1) & 1) * 2 * PANEL32;
+      panel_store32(Sn, va);
+      panel_store32(Sn + PANEL32, vb);
+    }
+    __syncthreads();
+  }
+  // lane l, register r of accumulator (i, j): row wm*64 + 16 i + l%16,
+  // column wn*64 + 16 j + 4 (l/16) + r
+  const size_t ct = (size_t)(ti + t * tj) * TILE;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const size_t e = ct + (wm * 64 + i * 16 + lr) + (size_t)NB * (wn * 64 + j * 16 + 4 * lk + r);
+        C[e] = Cin[e] + (double)acc[i][j][r];
+      }
+}
+
 // Lower triangle of the FP64 column-major A -> FP32 lower tiles (rounded to
 // nearest), identity padding beyond n.
 __global__ __launch_bounds__(NTHREADS) void copy_in32_kernel(const double* __restrict__ A, int lda,
@@ -569,6 +660,23 @@ hipError_t launch_sched32(const SchedArgs& a, int grid, bool bf16, hipStream_t s
   else
     hipLaunchKernelGGL(sched_kernel32<false>, dim3(grid), dim3(NTHREADS), 0, s, a, a.tiles_T,
                        a.tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_round32(const double* src, float* dst, size_t count, hipStream_t s) {
+  if (count % 4) return hipErrorInvalidValue;
+  const size_t q = count / 4;
+  const size_t blocks = std::min<size_t>((q + NTHREADS - 1) / NTHREADS, 8192);
+  if (!blocks) return hipSuccess;
+  hipLaunchKernelGGL(round32_kernel, dim3((unsigned)blocks), dim3(NTHREADS), 0, s, src, dst, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_nt32_lower(const float* A, const float* B, const double* Cin, double* C,
+                                  int t, hipStream_t s) {
+  if (t < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gemm_nt32_lower_kernel, dim3(t * (t + 1) / 2), dim3(NTHREADS), 0, s, A, B,
+                     Cin, C, t);
   return hipGetLastError();
 }
 

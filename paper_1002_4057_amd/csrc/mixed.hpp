@@ -23,6 +23,15 @@ hipError_t launch_x0_to_sym64(const float* pool, int t, int n, double* X, hipStr
 
 int sched32_blocks_per_cu();
 
+// dst = src rounded to FP32 (count a multiple of 4).
+hipError_t launch_round32(const double* src, float* dst, size_t count, hipStream_t s);
+
+// C = Cin + A B^T on the lower tiles of square tile-major matrices (t x t
+// tiles): FP32 operands and FP32 accumulation on the matrix cores, the sum
+// with Cin in binary64 (the refinement's low-precision correction X R).
+hipError_t launch_gemm_nt32_lower(const float* A, const float* B, const double* Cin, double* C,
+                                  int t, hipStream_t s);
+
 // FP32 storage (SPDINV_FP32): FP32 column-major lower triangle <-> FP32 tiles.
 hipError_t launch_copy_in32f(const float* A, int lda, int n, int t, float* pool, hipStream_t s);
 hipError_t launch_copy_out32f(const float* pool, int t, float* A, int lda, int n, int fill_upper,

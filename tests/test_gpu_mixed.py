@@ -57,7 +57,8 @@ def test_refinement_is_quadratic():
     res = []
     for k in range(0, 3):
         _, rep = spd.spd_inverse(torch.from_numpy(a).to(DEV), mode="mixed_fp32",
-                                 return_report=True, max_refine=k + 1, refine_tol=1e-300)
+                                 return_report=True, max_refine=k + 1, refine_tol=1e-300,
+                                 correction64=1)
         if k == 0:
             res.append(rep["resid0_fro_rel"])
         res.append(rep["resid_fro_rel"])
@@ -67,6 +68,50 @@ def test_refinement_is_quadratic():
     for r_prev, r_next in zip(res, res[1:]):
         assert r_next * anorm <= 4 * (r_prev * anorm) ** 2 + floor * anorm, res
     assert res[-1] <= floor, res
+
+
+@pytest.mark.parametrize("n", [300, 1000, 2100])
+def test_low_precision_corrections_against_oracle(n):
+    """The default loop runs the corrections that another residual follows
+    on the FP32 matrix cores and the last one in binary64: the result meets
+    the stop rule and the FP64 bar against the oracle, as with every
+    correction in binary64, in at most one more step."""
+    a = inputs.spectrum(n, 1e2, seed=20 + n).numpy()
+    ad = torch.from_numpy(a).to(DEV)
+    x, rep = spd.spd_inverse(ad, mode="mixed_fp32", return_report=True)
+    x64, rep64 = spd.spd_inverse(ad, mode="mixed_fp32", return_report=True, correction64=1)
+    print(f"n={n}: {rep}\n  binary64 corrections: {rep64}", flush=True)
+    assert rep["fell_back"] == 0 and rep["converged"] == 1
+    assert rep["low_corrections"] >= 1 and rep64["low_corrections"] == 0
+    assert rep["refine_iters"] <= rep64["refine_iters"] + 1
+    x = x.cpu().numpy()
+    assert rel_fro(x, oracle.spd_inverse(a)) <= 1e-12 * 1e2
+    assert resid_rel(a, x) <= 1e-13
+    assert np.array_equal(x, x.T)
+
+
+def test_low_precision_step_within_its_rounding_bound():
+    """One FP32 correction X1 = X0 + fl(X0 R0): I - A X1 = R0^2 - A E with E
+    the rounding of the FP32 product (operands rounded to FP32, FP32
+    accumulation over n terms), |E| <= (n + 4) u_32 |X0| |R0| entrywise, so
+    ||I - A X1||_F <= ||R0||_F^2 + ||A||_2 (n + 4) u_32 ||X0||_F ||R0||_F
+    (u_32 = 2^-24), up to the binary64 floor.  A product that dropped or
+    transposed a term would leave a residual of the size of ||R0||_F."""
+    n = 1000
+    a = inputs.spectrum(n, 1e2, seed=21).numpy()
+    ad = torch.from_numpy(a).to(DEV)
+    x1, rep = spd.spd_inverse(ad, mode="mixed_fp32", return_report=True, max_refine=1,
+                              refine_tol=1e-300)
+    assert rep["low_corrections"] == 1 and rep["refine_iters"] == 1
+    anorm = np.linalg.norm(a)
+    r0 = rep["resid0_fro_rel"] * anorm
+    x1 = x1.cpu().numpy()
+    r1 = np.linalg.norm(np.eye(n) - a @ x1)
+    xf = np.linalg.norm(x1)               # ||X0||_F to within ||X0 R0||_F
+    bound = r0 ** 2 + 1e2 * (n + 4) * 2.0 ** -24 * xf * r0 + 64 * 2.0 ** -53 * anorm * xf
+    print(f"r0 {r0:.3e}, r1 {r1:.3e}, bound {bound:.3e}")
+    assert r1 <= bound
+    assert r1 < 0.1 * r0
 
 
 def test_predicted_stop_skips_the_last_residual():
