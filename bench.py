@@ -474,6 +474,10 @@ def main():
                     help="skip the autotuner (built-in schedule choices)")
     ap.add_argument("--batch-group", type=int, default=0,
                     help="batched rows: matrices per dispatch group (0 = library choice)")
+    ap.add_argument("--tuning-save", default="", metavar="FILE",
+                    help="save the autotuner's table to FILE")
+    ap.add_argument("--tuning-load", default="", metavar="FILE",
+                    help="load a saved tuning table instead of running the autotuner")
     ap.add_argument("--input", choices=["spectrum", "wishart"], default="spectrum",
                     help="wishart (B B^T/n + I, no QR) is for profiler counter runs only")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -507,11 +511,18 @@ def main():
         del b0
         q = lam = None
     tuned = None
-    if not args.no_tune:
+    if args.tuning_load:
+        # a table saved by an earlier run (the profiler runs use it, so that
+        # their kernel statistics hold only the timed schedule's launches)
+        spd.tuning_load(args.tuning_load)
+        tuned = {"loaded_from": os.path.basename(args.tuning_load)}
+    elif not args.no_tune:
         log(f"[bench] autotuning the schedule at n={n}")
         t0 = time.perf_counter()
         tuned = spd.autotune(n, reps=2)
         tuned["tuning_s"] = round(time.perf_counter() - t0, 1)
+        if args.tuning_save:
+            spd.tuning_save(args.tuning_save)
     a_cm = a.t().contiguous()                       # column-major storage of A
     bufs = [a_cm.clone() for _ in range(K + W)]
     work = torch.empty(spd.workspace_bytes(n), dtype=torch.uint8, device=dev)

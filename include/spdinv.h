@@ -317,10 +317,13 @@ size_t batched_spd_inverse_workspace_bytes(int batch, const int* h_n, spdinv_mod
  *   d_lda   device int[batch], leading dimensions (>= max(1, n_i))
  *   mode    SPDINV_FP64 or SPDINV_FP32 (FP32 tiles and matrix cores,
  *           binary64 diagonal tiles and small matrices, rounded to FP32)
- *   work    device workspace of batched_spd_inverse_workspace_bytes bytes
- *           (each matrix of tile count t >= 2 has its own pool of 3T + 2t
- *           tiles, T = t(t+1)/2: about 20 GB in FP64 for 8192 orders uniform
- *           on 16..512)
+ *   work    device workspace of batched_spd_inverse_workspace_bytes bytes:
+ *           the tile pools (3T + 2t tiles for a matrix of tile count t >= 2,
+ *           T = t(t+1)/2) - one per workgroup with batch_group = -1 (each
+ *           workgroup's matrices use it in turn), slots shared by matrices
+ *           that the dispatch order runs one after another with -2, one per
+ *           matrix with g > 0 - and the per-task counters (2.6 GB in FP64
+ *           for 8192 orders uniform on 16..512 with the library's choice)
  *   opts    host or NULL: renamed, loop_order, trtri_first and chain select
  *           the tile plan (FP32: renamed only, chain 1); batch_group the
  *           interleaving; fill_upper mirrors each result; workers caps the
