@@ -96,10 +96,11 @@ typedef struct {
                       at most 16).  Same products in the same order: results
                       are bit-identical for every value.  The last product
                       before a chain's closing task always runs alone.  */
-  int per_cu;      /* FP64 form: persistent workgroups per compute unit (0 =
-                      library choice: 2 when the matrix has at least 96 tiles
-                      per side, where the DAG keeps enough tasks ready, else
-                      1; or 1 or 2).  Results do not depend on it.           */
+  int per_cu;      /* FP64, FP32 and mixed forms: persistent workgroups per
+                      compute unit (0 = library choice: in FP64 2 when the
+                      matrix has at least 96 tiles per side, where the DAG
+                      keeps enough tasks ready, else 1; 1 for the FP32 tile
+                      DAG; or 1 or 2).  Results do not depend on it.         */
   int no_split;    /* FP64 form: 0 (default) = with more than one worker, run
                       the products on chains of dependent tasks as row-part
                       tasks, run side by side (four quarters below 96 tiles

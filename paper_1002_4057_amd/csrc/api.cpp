@@ -1368,23 +1368,37 @@ MixedLayout mixed_layout(int n, const spdinv_opts& o) {
   return M;
 }
 
-int grid32_for(int device, const spdinv_opts& o) {
-  static std::map<int, int> grids;
-  int g;
+// Workgroups per CU of the FP32 scheduler: the caller's per_cu within what
+// fits, else one.  (The FP32 DAG runs one product per task; measured at
+// n = 4096, 8192 and 16384, a second workgroup per CU made it 13-22 %
+// slower at every order, unlike the chained FP64 DAG from 96 tiles.)
+int per_cu32_for(int /*t*/, const spdinv_opts& o) {
+  static int capacity = 0;
   {
     std::lock_guard<std::mutex> lk(g_mu);
-    auto it = grids.find(device);
-    if (it != grids.end()) {
-      g = it->second;
+    if (!capacity) capacity = sched32_blocks_per_cu();
+  }
+  const int want = o.per_cu ? o.per_cu : 1;
+  return want < capacity ? want : capacity;
+}
+
+int grid32_for(int device, int t, const spdinv_opts& o) {
+  static std::map<int, int> cus_of;
+  int cus;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = cus_of.find(device);
+    if (it != cus_of.end()) {
+      cus = it->second;
     } else {
-      int cus = 0;
+      cus = 0;
       if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
           cus <= 0)
         cus = 1;
-      g = cus * sched32_blocks_per_cu();
-      grids[device] = g;
+      cus_of[device] = cus;
     }
   }
+  int g = cus * per_cu32_for(t, o);
   if (o.workers > 0 && o.workers < g) g = o.workers;
   return g;
 }
@@ -1411,7 +1425,7 @@ int run_fp32(int n, float* A, int lda, void* work, size_t work_bytes, hipStream_
   int device = 0;
   if (hipGetDevice(&device) != hipSuccess) return SPDINV_ERR_HIP;
   const int t = tiles_for(n);
-  const int grid = grid32_for(device, o);
+  const int grid = grid32_for(device, t, o);
   hipError_t err = hipSuccess;
   DevPlan* dp = get_plan(device, t, o, grid, 1, &err);
   if (!dp) return SPDINV_ERR_HIP;
@@ -1435,7 +1449,8 @@ int run_fp32(int n, float* A, int lda, void* work, size_t work_bytes, hipStream_
   a.tiles = t;
   a.spin_limit = spin_limit();
   a.d_base = 3 * a.tiles_T;
-  if (launch_sched32(a, grid, false, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (launch_sched32(a, grid, per_cu32_for(t, o), false, stream) != hipSuccess)
+    return SPDINV_ERR_HIP;
   if (launch_copy_out32f(pool, t, A, lda, n, o.fill_upper, stream) != hipSuccess)
     return SPDINV_ERR_HIP;
   if (launch_info_out(ctrl, d_info, stream) != hipSuccess) return SPDINV_ERR_HIP;
@@ -1462,7 +1477,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
   int device = 0;
   if (hipGetDevice(&device) != hipSuccess) return SPDINV_ERR_HIP;
   const int t = tiles_for(n);
-  const int grid = grid32_for(device, o);
+  const int grid = grid32_for(device, t, o);
   hipError_t err = hipSuccess;
   DevPlan* dp = get_plan(device, t, o, grid, 1, &err);
   if (!dp) return SPDINV_ERR_HIP;
@@ -1496,7 +1511,8 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
   a.info_base = 0;
   a.spin_limit = spin_limit();
   a.d_base = 3 * a.tiles_T;
-  if (launch_sched32(a, grid, bf16, stream) != hipSuccess) return SPDINV_ERR_HIP;
+  if (launch_sched32(a, grid, per_cu32_for(t, o), bf16, stream) != hipSuccess)
+    return SPDINV_ERR_HIP;
   int32_t c[CTRL_WORDS];
   if (hipMemcpyAsync(c, ctrl, sizeof(c), hipMemcpyDeviceToHost, stream) != hipSuccess)
     return SPDINV_ERR_HIP;

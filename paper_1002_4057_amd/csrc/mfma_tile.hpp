@@ -24,8 +24,6 @@ constexpr int NCH = NB / KC;              // k-panels per tile
 // of a k-row are conflict-free, and operand reads (16 consecutive r of 4
 // consecutive k) conflict at most 2-way.
 constexpr int LDS_STRIDE = NB + 2;
-constexpr int PANEL = KC * LDS_STRIDE;    // doubles per operand panel
-constexpr int GEMM_SMEM = 4 * PANEL;      // 2 buffers x 2 operands (133,120 bytes)
 constexpr size_t TILE = (size_t)NB * NB;
 constexpr int PAIRS = NB * KC / 2 / NTHREADS;  // 16-byte loads per thread per panel
 

@@ -202,71 +202,90 @@ __device__ __forceinline__ void tile_mma32(int f, float* C, const float* A, cons
   }
 }
 
-// Diagonal tile in binary64: the FP32 tile is widened (exactly) into LDS,
-// factored and inverted by the FP64 path's LDS code, and L, L^T, X = L^{-1}
-// and X^T are rounded to FP32.  Returns 0 or the 1-based local index of the
-// first non-positive pivot (nothing is stored then).
+// Diagonal tile in binary64, in the packed layout of the FP64 path (only
+// the 36 lower 16 x 16 blocks in LDS, 78 KB, so that two workgroups share a
+// CU): the FP32 tile is widened (exactly) into LDS, factored and inverted
+// by the FP64 path's packed code, and L, L^T, X = L^{-1} and X^T are rounded
+// to FP32.  Returns 0 or the 1-based local index of the first non-positive
+// pivot (nothing is stored then).
 __device__ __attribute__((noinline)) int potrf_inv_tile32(const float* Ain, float* Lout,
                                                            float* LcopyT, float* Xout,
                                                            float* XoutT, double* smem) {
-  constexpr int LD = POTRF_LD;
-  double* T = smem;
-  double* XD = smem + NB * LD;
-  double* SCR = XD + 8 * 256;
-  int* flag = reinterpret_cast<int*>(SCR + 4 * 256);
-  const int tid = threadIdx.x;
+  Ain = uniform_ptr(Ain);
+  Lout = uniform_ptr(Lout);
+  LcopyT = uniform_ptr(LcopyT);
+  Xout = uniform_ptr(Xout);
+  XoutT = uniform_ptr(XoutT);
+  double* T = smem;                          // the 36 packed blocks
+  double* rd = smem + PK_BLOCKS * PK_STRIDE;  // reciprocal pivots
+  int* flag = reinterpret_cast<int*>(rd + NB);
+  const int tid = opaque_tid();
   const rsrc_t rIn = rsrc32(Ain), rL = rsrc32(Lout ? Lout : Xout), rX = rsrc32(Xout),
                rXT = rsrc32(XoutT);
-  for (int e0 = 0; e0 < NB * NB; e0 += 4 * NTHREADS * 8) {
-    f4 v[8];
+  // the lower blocks: 64 16-byte loads per block (4 rows of one column
+  // each), every wave inside one block; all loads of a thread are issued
+  // before the first LDS write
+  constexpr int NLD = PK_BLOCKS * 64 / NTHREADS;
+  static_assert(PK_BLOCKS * 64 % NTHREADS == 0, "whole passes");
+  f4 v[NLD];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = ld4f(rIn, e0 + 4 * (tid + NTHREADS * u));
+  for (int u = 0; u < NLD; ++u) {
+    const int b = __builtin_amdgcn_readfirstlane((NTHREADS * u + tid) >> 6);
+    int bi = 0;
+    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+    const int bj = b - bi * (bi + 1) / 2;
+    const int e = tid & 63, lr = 4 * (e & 3), lc = e >> 2;
+    v[u] = ld4f(rIn, (16 * bi + lr) + NB * (16 * bj + lc));
+  }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int e = e0 + 4 * (tid + NTHREADS * u), rr = e & (NB - 1), cc = e >> 7;
+  for (int u = 0; u < NLD; ++u) {
+    const int b = __builtin_amdgcn_readfirstlane((NTHREADS * u + tid) >> 6);
+    int bi = 0;
+    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+    const bool diag = b == bi * (bi + 1) / 2 + bi;
+    const int e = tid & 63, lr = 4 * (e & 3), lc = e >> 2;
+    double* dst = T + PK_STRIDE * b + lr + PK_LD * lc;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) T[rr + s + LD * cc] = (rr + s >= cc) ? (double)v[u][s] : 0.0;
-    }
+    for (int s = 0; s < 4; ++s) dst[s] = (diag && lr + s < lc) ? 0.0 : (double)v[u][s];
   }
   __syncthreads();
-  const int ff = factor_lds(T, XD, SCR, SCR + NB, flag, 8);  // pivots, then the broadcast buffer
+  const int ff = factor_packed(T, rd, rd + NB + 8, flag, NB / 16);
   if (ff) return ff;
+  // element (r, c) of the packed lower triangle (zero above the diagonal)
+  auto pval = [&](int r, int c) -> double {
+    if (r < c) return 0.0;
+    return pk_blk(T, r >> 4, c >> 4)[(r & 15) + PK_LD * (c & 15)];
+  };
   const rsrc_t rLT = rsrc32(LcopyT ? LcopyT : Xout);
   if (Lout) {  // skipped when nothing reads the factor
 #pragma unroll 2
     for (int q = 0; q < NB * NB / 4 / NTHREADS; ++q) {
       const int e = 4 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
-      f4 v;
+      f4 x;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) v[s] = (rr + s >= cc) ? (float)T[rr + s + LD * cc] : 0.0f;
-      st4f(rL, e, v);
+      for (int s = 0; s < 4; ++s) x[s] = (float)pval(rr + s, cc);
+      st4f(rL, e, x);
       if (LcopyT) {
-        f4 u;
+        f4 y;
 #pragma unroll
-        for (int s = 0; s < 4; ++s) u[s] = (cc >= rr + s) ? (float)T[cc + LD * (rr + s)] : 0.0f;
-        st4f(rLT, e, u);
+        for (int s = 0; s < 4; ++s) y[s] = (float)pval(cc, rr + s);
+        st4f(rLT, e, y);
       }
     }
   }
-  __syncthreads();
-  inverse_lds(T, XD, SCR, 8);
-  __syncthreads();
-  auto xval = [&](int r, int c) -> double {
-    const int br = r >> 4, bc = c >> 4;
-    if (br == bc) return XD[256 * br + (r & 15) + 16 * (c & 15)];
-    return (br > bc) ? T[c + LD * r] : 0.0;
-  };
+  __syncthreads();  // the inverse overwrites the factor
+  inverse_packed(T, rd, NB / 16);
 #pragma unroll 2
   for (int q = 0; q < NB * NB / 4 / NTHREADS; ++q) {
     const int e = 4 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
-    f4 v, u;
+    f4 x, y;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      v[s] = (float)xval(rr + s, cc);
-      u[s] = (float)xval(cc, rr + s);
+      x[s] = (float)pval(rr + s, cc);
+      y[s] = (float)pval(cc, rr + s);
     }
-    st4f(rX, e, v);
-    st4f(rXT, e, u);
+    st4f(rX, e, x);
+    st4f(rXT, e, y);
   }
   return 0;
 }
@@ -318,9 +337,15 @@ __device__ __forceinline__ void run_task32(const DevTask& t, const SchedArgs& g,
   }
 }
 
+constexpr unsigned kSoloLdsPad32 = 8192;
+static_assert(TASK_SMEM * 8 + kSoloLdsPad32 > 80 * 1024, "the pad must exclude a second workgroup");
+
+// Two workgroups per CU: every task fits TASK_SMEM doubles of LDS and 256
+// registers per lane.
 template <bool BF16>
-__global__ __launch_bounds__(NTHREADS) void sched_kernel32(SchedArgs g, int T, int tiles) {
-  __shared__ double smem[SMEM_DOUBLES];
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void sched_kernel32(SchedArgs g, int T, int tiles) {
+  __shared__ double smem[TASK_SMEM];
   sched_loop(g, [&](const DevTask& t) { run_task32<BF16>(t, g, smem, T, tiles); });
 }
 
@@ -568,8 +593,10 @@ __device__ __forceinline__ int load_uniform32(int32_t* p) {
       __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
-__global__ __launch_bounds__(NTHREADS) void bsched_kernel32(BSchedArgs g) {
-  __shared__ double smem[SMEM_DOUBLES];
+// Two workgroups per CU, as the FP32 scheduler.
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void bsched_kernel32(BSchedArgs g) {
+  __shared__ double smem[TASK_SMEM];
   auto run = [&](const DevTask& d, int m, int t) {
     const int kind = d.kind & 0xff;
     int32_t* mc = g.mctrl + CTRL_WORDS * m;
@@ -654,11 +681,14 @@ hipError_t launch_copy_in32(const double* A, int lda, int n, int t, float* pool,
   return hipGetLastError();
 }
 
-hipError_t launch_sched32(const SchedArgs& a, int grid, bool bf16, hipStream_t s) {
+hipError_t launch_sched32(const SchedArgs& a, int grid, int per_cu, bool bf16, hipStream_t s) {
+  // one workgroup per CU: unused dynamic LDS keeps a second one off the CU
+  const unsigned pad = per_cu == 1 ? kSoloLdsPad32 : 0;
   if (bf16)
-    hipLaunchKernelGGL(sched_kernel32<true>, dim3(grid), dim3(NTHREADS), 0, s, a, a.tiles_T, a.tiles);
+    hipLaunchKernelGGL(sched_kernel32<true>, dim3(grid), dim3(NTHREADS), pad, s, a, a.tiles_T,
+                       a.tiles);
   else
-    hipLaunchKernelGGL(sched_kernel32<false>, dim3(grid), dim3(NTHREADS), 0, s, a, a.tiles_T,
+    hipLaunchKernelGGL(sched_kernel32<false>, dim3(grid), dim3(NTHREADS), pad, s, a, a.tiles_T,
                        a.tiles);
   return hipGetLastError();
 }

@@ -16,7 +16,7 @@ hipError_t launch_copy_in32(const double* A, int lda, int n, int t, float* pool,
 
 // Persistent scheduler over the renamed plan with FP32 tile tasks (bf16: the
 // products take bfloat16 operands).
-hipError_t launch_sched32(const SchedArgs& a, int grid, bool bf16, hipStream_t s);
+hipError_t launch_sched32(const SchedArgs& a, int grid, int per_cu, bool bf16, hipStream_t s);
 
 // FP32 lower tiles -> square tile-major FP64 symmetric matrix (zero beyond n).
 hipError_t launch_x0_to_sym64(const float* pool, int t, int n, double* X, hipStream_t s);

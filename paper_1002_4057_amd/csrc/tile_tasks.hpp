@@ -12,8 +12,8 @@
 //     operand and a lower-only output, staged through LDS in k-panels, and
 //     an optional second destination (the renaming copy of Section 3);
 //   * the diagonal-tile factorization POTRF, which also produces the inverse
-//     of the factor tile, blocked by 16 with the tile resident in LDS (see
-//     factor_lds and inverse_lds);
+//     of the factor tile, blocked by 16 with the lower blocks of the tile
+//     resident in LDS (factor_packed and inverse_packed);
 //   * a tile copy (TRTRI reuses the inverse made by POTRF, bit for bit).
 #pragma once
 #include <climits>
@@ -47,10 +47,6 @@ constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int TASK_SMEM = cmax(cmax(SGEMM_SMEM, COPY_SMEM), PK_SMEM);
 static_assert(TASK_SMEM * 8 <= 80 * 1024, "a task must fit half of the CU's LDS");
 
-// The full-tile diagonal helpers (factor_lds, inverse_lds) of the batched
-// small matrices and the mixed form, and the kernels that run them
-constexpr int POTRF_SMEM = NB * (NB + 1) + 12 * 256 + 8;  // tile + diagonal inverses + scratch
-constexpr int SMEM_DOUBLES = cmax(cmax(GEMM_SMEM, POTRF_SMEM), TASK_SMEM);
 
 // Renaming copy of a product's result (as is, or transposed with copy_t):
 // the result is staged in LDS one half of its rows at a time, as
@@ -444,9 +440,8 @@ __device__ __attribute__((noinline)) void tile_mma_general(int f, double* C, con
 
 // ---------------------------------------------------------------------------
 // Diagonal tile: Cholesky factor L of the lower triangle of A and its inverse
-// X = L^{-1}, blocked by 16 with the tile held in LDS (factor_lds, then
-// inverse_lds: X by block forward substitution, one block column per wave,
-// X_ip = -X_ii (sum_{m=p..i-1} L_im X_mp)).
+// X = L^{-1}, blocked by 16 with the lower blocks of the tile held in LDS
+// (factor_packed, then inverse_packed, below).
 // MFMA 16x16 blocks use the same lane layout as tile_mma: lane l, register r
 // holds row l%16, column l/16 + 4r of the block.
 // ---------------------------------------------------------------------------
@@ -558,132 +553,6 @@ __device__ __forceinline__ void blk_store(double* S, int ld, d4 v) {
   for (int q = 0; q < 4; ++q) S[lr + ld * (lk + 4 * q)] = v[q];
 }
 
-// Blocked Cholesky factorization, in place, of the leading 16P x 16P block
-// of the lower triangle held in LDS (T, column-major, ld POTRF_LD; entries
-// above the diagonal are zero), with one block of lookahead:
-//   wave 0 factors the 16 x 16 diagonal block p (chol16);
-//   panel p: L_ip = A_ip L_pp^{-T} by forward substitution, one row per
-//     thread, L_pp read from LDS;
-//   trailing update A_ij -= L_ip L_jp^T (16x16x16 MFMA blocks): wave 0 first
-//     updates the next diagonal block and factors it while waves 1-3 update
-//     the other blocks.
-// Then the inverses X_pp = L_pp^{-1} of all diagonal blocks into XD (16 x 16
-// column-major each), 16 lanes per block, one column of X_pp per lane.
-// rd receives the 16P reciprocal pivots; col is chol16's broadcast buffer
-// (64 doubles).  Returns 0 or the 1-based index of the first pivot that is
-// not positive (or NaN); the value is uniform over the workgroup.
-constexpr int POTRF_LD = NB + 1;  // odd row stride: transposed LDS reads spread over banks
-
-__device__ __forceinline__ int factor_lds(double* T, double* XD, double* rd, double* col, int* flag,
-                                          int P) {
-  constexpr int LD = POTRF_LD;
-  const int tid = threadIdx.x, w = tid >> 6;
-  if (w == 0) {
-    const int f = chol16(T, LD, rd, col);
-    if (tid == 0) *flag = f;
-  }
-  __syncthreads();
-  int fail = __builtin_amdgcn_readfirstlane(*flag);
-  if (fail) return fail;
-  for (int p = 0; p < P; ++p) {
-    // panel: row R of the blocks below the diagonal block solves x L_pp^T = a
-    const int rows = 16 * (P - 1 - p);
-    if (tid < rows) {
-      const int R = 16 * (p + 1) + tid;
-      const double* Lpp = T + 16 * p * (LD + 1);
-      double* a = T + R + LD * 16 * p;
-      double x[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        double s = a[LD * c];
-#pragma unroll
-        for (int m = 0; m < c; ++m) s = fma(-x[m], Lpp[c + LD * m], s);
-        x[c] = s * rd[16 * p + c];
-      }
-#pragma unroll
-      for (int c = 0; c < 16; ++c) a[LD * c] = x[c];
-    }
-    __syncthreads();
-    if (p + 1 == P) break;
-    // trailing update: A_ij -= L_ip L_jp^T, p < j <= i; block (p+1, p+1)
-    // first (wave 0, which then factors it), the others on waves 1-3
-    const int nb = P - 1 - p;
-    if (w == 0) {
-      double* Cnn = T + 16 * (p + 1) * (LD + 1);
-      const double* Lnp = T + 16 * (p + 1) + LD * 16 * p;
-      d4 acc = -blk_load(Cnn, LD);
-      acc = blk_mma16(acc, Lnp, LD, Lnp, LD, true);
-      blk_store(Cnn, LD, -acc);
-      const int f = chol16(Cnn, LD, rd + 16 * (p + 1), col);
-      if (tid == 0) *flag = f ? 16 * (p + 1) + f : 0;
-    } else {
-      for (int q = w; q < nb * (nb + 1) / 2; q += 3) {
-        int i = 0;
-        while ((i + 1) * (i + 2) / 2 <= q) ++i;
-        const int j = q - i * (i + 1) / 2;
-        const int bi = p + 1 + i, bj = p + 1 + j;
-        double* Cij = T + 16 * bi + LD * 16 * bj;
-        d4 acc = -blk_load(Cij, LD);
-        acc = blk_mma16(acc, T + 16 * bi + LD * 16 * p, LD, T + 16 * bj + LD * 16 * p, LD, true);
-        blk_store(Cij, LD, -acc);
-      }
-    }
-    __syncthreads();
-    fail = __builtin_amdgcn_readfirstlane(*flag);
-    if (fail) return fail;
-  }
-  // X_bb = L_bb^{-1}: lane c of group b solves L_bb x = e_c by forward
-  // substitution (x_r = 0 for r < c comes out exactly)
-  const int g = tid >> 4, c = tid & 15;
-  if (g < P) {
-    const double* Lb = T + 16 * g * (LD + 1);
-    double x[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      double s = (r == c) ? 1.0 : 0.0;
-#pragma unroll
-      for (int m = 0; m < r; ++m) s = fma(-Lb[r + LD * m], x[m], s);
-      x[r] = s * rd[16 * g + r];
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) XD[256 * g + r + 16 * c] = x[r];
-  }
-  __syncthreads();
-  return 0;
-}
-
-// Inverse of the factor left by factor_lds: X_ip = -X_ii sum_{m=p..i-1}
-// L_im X_mp by block forward substitution, one block column per wave.  The
-// diagonal blocks X_pp are in XD; X_ip (i > p) is written transposed into the
-// upper block (p, i) of T; the lower blocks (L) are only read.
-__device__ __forceinline__ void inverse_lds(double* T, const double* XD, double* SCR, int P) {
-  constexpr int LD = POTRF_LD;
-  const int tid = threadIdx.x, w = tid >> 6;
-  // inverse by block columns; wave w takes columns w and P - 1 - w (the
-  // latter when it is not among the first four).  X_mp for m > p is kept
-  // transposed in the (unused) upper block (p, m) of T.
-  double* scr = SCR + 256 * w;
-  for (int side = 0; side < 2; ++side) {
-    const int p = side ? P - 1 - w : w;
-    if (side ? (p < 4) : (p >= P)) continue;
-    for (int i = p + 1; i < P; ++i) {
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
-      // L_ip X_pp
-      acc = blk_mma16(acc, T + 16 * i + LD * 16 * p, LD, XD + 256 * p, 16, false);
-      for (int m = p + 1; m < i; ++m)  // L_im X_mp, X_mp^T stored at block (p, m)
-        acc = blk_mma16(acc, T + 16 * i + LD * 16 * m, LD, T + 16 * p + LD * 16 * m, LD, true);
-      blk_store(scr, 16, acc);
-      d4 xip = {0.0, 0.0, 0.0, 0.0};
-      xip = blk_mma16(xip, XD + 256 * i, 16, scr, 16, false);  // X_ii S
-      xip = -xip;
-      // X_ip transposed into block (p, i) of T
-      const int lane = tid & 63, lr = lane & 15, lk = lane >> 4;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) T[(16 * p + lk + 4 * q) + LD * (16 * i + lr)] = xip[q];
-    }
-  }
-}
-
 // ---------------------------------------------------------------------------
 // Diagonal tile in packed form: only the 36 lower 16 x 16 blocks of the tile
 // are held in LDS, block (i, p) (i >= p) at PK_STRIDE * (i(i+1)/2 + p),
@@ -698,9 +567,12 @@ __device__ __forceinline__ double* pk_blk(double* T, int i, int p) {
 }
 
 // Blocked Cholesky factorization of the leading 16P x 16P block of the
-// packed tile, in place; the steps of factor_lds (one block of lookahead:
-// wave 0 updates and factors the next diagonal block while waves 1-3 update
-// the rest of the trailing blocks), on packed blocks.  rd receives the 16P
+// packed tile, in place, with one block of lookahead: wave 0 factors the
+// 16 x 16 diagonal block (chol16); the panel below it solves
+// L_ip = A_ip L_pp^{-T} by forward substitution, one row per thread; in the
+// trailing update A_ij -= L_ip L_jp^T (16x16x16 MFMA blocks) wave 0 first
+// updates and factors the next diagonal block while waves 1-3 update the
+// rest of the trailing blocks.  rd receives the 16P
 // reciprocal pivots; col is chol16's broadcast buffer.  Returns 0 or the
 // 1-based index of the first pivot that is not positive (or NaN), uniform
 // over the workgroup.

@@ -68,3 +68,13 @@ def test_fp32_info_and_untouched_upper():
     out = buf.cpu()
     assert torch.isnan(out[iu[1], iu[0]]).all()
     assert not torch.isnan(torch.tril(out.t())).any()
+
+
+@pytest.mark.parametrize("n", [700, 3000])
+def test_fp32_workers_per_cu_do_not_change_the_bits(n):
+    """One or two workgroups per CU (and a capped grid) run the same tasks
+    with the same per-tile order of products: the same FP32 bits."""
+    a32 = inputs.wishart_shift(n, seed=33).float().to(DEV)
+    ref = spd.spd_inverse(a32, mode="fp32")
+    for opts in (dict(per_cu=2), dict(per_cu=1), dict(workers=37)):
+        assert torch.equal(spd.spd_inverse(a32, mode="fp32", **opts), ref), opts
