@@ -89,7 +89,7 @@ typedef struct {
                       6 for MIXED_FP32, 8 for MIXED_BF16)                     */
   double refine_tol; /* mixed modes: stop once ||I - A X||_F / ||A||_F <= refine_tol
                         (0 = library default, 1e-13)                            */
-  int chain;       /* FP64 and batched forms: most consecutive products of one output
+  int chain;       /* FP64, FP32, mixed and batched forms: most consecutive products of one output
                       tile's update chain that run as one device task, the tile
                       staying in registers between them (0 = library default,
                       8; 1 = one device task per task of the paper's stream;
@@ -97,10 +97,10 @@ typedef struct {
                       are bit-identical for every value.  The last product
                       before a chain's closing task always runs alone.  */
   int per_cu;      /* FP64, FP32 and mixed forms: persistent workgroups per
-                      compute unit (0 = library choice: in FP64 2 when the
-                      matrix has at least 96 tiles per side, where the DAG
-                      keeps enough tasks ready, else 1; 1 for the FP32 tile
-                      DAG; or 1 or 2).  Results do not depend on it.         */
+                      compute unit (0 = library choice: 2 when the matrix has
+                      at least 96 tiles per side, where the DAG keeps enough
+                      tasks ready, else 1; or 1 or 2).  Results do not
+                      depend on it.                                          */
   int no_split;    /* FP64 form: 0 (default) = with more than one worker, run
                       the products on chains of dependent tasks as row-part
                       tasks, run side by side (four quarters below 96 tiles
@@ -326,7 +326,7 @@ size_t batched_spd_inverse_workspace_bytes(int batch, const int* h_n, spdinv_mod
  *           matrix with g > 0 - and the per-task counters (2.6 GB in FP64
  *           for 8192 orders uniform on 16..512 with the library's choice)
  *   opts    host or NULL: renamed, loop_order, trtri_first and chain select
- *           the tile plan (FP32: renamed only, chain 1); batch_group the
+ *           the tile plan (FP32: renamed only); batch_group the
  *           interleaving; fill_upper mirrors each result; workers caps the
  *           grid
  *   d_info  device int[batch] or NULL: INFO of each matrix (0, k > 0 as for
@@ -466,7 +466,7 @@ int spdinv_autotune(int n, int reps, spdinv_stream_t stream, spdinv_tuning* out)
 /*
  * Autotuner of the batched form for a batch of these orders (as for
  * batched_spd_inverse) in mode SPDINV_FP64 or SPDINV_FP32: times the
- * schedules batch_group = -1, -2 and 512, and in FP64 chains of 4 and 8
+ * schedules batch_group = -1, -2 and 512, each with chains of 1, 4 and 8
  * products, on synthetic SPD matrices of the same orders; the fastest
  * becomes the library's choice for batches with the same number of
  * matrices of each tile count.  Allocates and frees its own device buffers

@@ -321,7 +321,7 @@ spdinv_opts tuned_batch(const spdinv_opts& o, bool fp32, const int* h_n, int bat
   auto it = g_tuned_batch.find(batch_key(fp32, h_n, batch));
   if (it == g_tuned_batch.end()) return r;
   if (r.batch_group == 0) r.batch_group = it->second.group;
-  if (r.chain == 0 && !fp32) r.chain = it->second.chain;
+  if (r.chain == 0) r.chain = it->second.chain;
   return r;
 }
 
@@ -752,7 +752,7 @@ void btemplate_costs(BTemplate* bt, int t) {
   }
 }
 
-int btemplate_chain(const spdinv_opts& o, bool fp32) { return fp32 ? 1 : chain_for(o); }
+int btemplate_chain(const spdinv_opts& o, bool /*fp32*/) { return chain_for(o); }
 
 // Device tasks of the template of t at most (without building it).
 long long btemplate_bound(int t) { return t <= 1 ? 1 : task_count(t) + 2; }
@@ -1368,17 +1368,17 @@ MixedLayout mixed_layout(int n, const spdinv_opts& o) {
   return M;
 }
 
-// Workgroups per CU of the FP32 scheduler: the caller's per_cu within what
-// fits, else one.  (The FP32 DAG runs one product per task; measured at
-// n = 4096, 8192 and 16384, a second workgroup per CU made it 13-22 %
-// slower at every order, unlike the chained FP64 DAG from 96 tiles.)
-int per_cu32_for(int /*t*/, const spdinv_opts& o) {
+// Workgroups per CU of the FP32 scheduler: as for the FP64 one (two from
+// kWideTiles tiles per side, where the DAG keeps enough tasks ready: with
+// chained tasks, 46.3 against 50.1 ms at n = 16384 and 12.5 against 9.6 ms
+// at n = 8192), or the caller's per_cu, within what fits.
+int per_cu32_for(int t, const spdinv_opts& o) {
   static int capacity = 0;
   {
     std::lock_guard<std::mutex> lk(g_mu);
     if (!capacity) capacity = sched32_blocks_per_cu();
   }
-  const int want = o.per_cu ? o.per_cu : 1;
+  const int want = o.per_cu ? o.per_cu : (t >= kWideTiles ? 2 : 1);
   return want < capacity ? want : capacity;
 }
 
@@ -1427,7 +1427,7 @@ int run_fp32(int n, float* A, int lda, void* work, size_t work_bytes, hipStream_
   const int t = tiles_for(n);
   const int grid = grid32_for(device, t, o);
   hipError_t err = hipSuccess;
-  DevPlan* dp = get_plan(device, t, o, grid, 1, &err);
+  DevPlan* dp = get_plan(device, t, o, grid, chain_for(o), &err);
   if (!dp) return SPDINV_ERR_HIP;
   const int ntask = (int)dp->host.tasks.size();
   char* w = (char*)work;
@@ -1443,6 +1443,7 @@ int run_fp32(int n, float* A, int lda, void* work, size_t work_bytes, hipStream_
   a.indeg = indeg;
   a.ctrl = ctrl;
   a.pool = reinterpret_cast<double*>(pool);
+  a.links = dp->d_links;
   a.last_valid = NB;
   a.ntask = ntask;
   a.tiles_T = t * (t + 1) / 2;
@@ -1479,7 +1480,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
   const int t = tiles_for(n);
   const int grid = grid32_for(device, t, o);
   hipError_t err = hipSuccess;
-  DevPlan* dp = get_plan(device, t, o, grid, 1, &err);
+  DevPlan* dp = get_plan(device, t, o, grid, chain_for(o), &err);
   if (!dp) return SPDINV_ERR_HIP;
   const int ntask = (int)dp->host.tasks.size();
   int max_refine = o.max_refine > 0 ? o.max_refine : (bf16 ? 8 : 6);
@@ -1501,7 +1502,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
   a.indeg = indeg;
   a.ctrl = ctrl;
   a.pool = reinterpret_cast<double*>(pool);
-  a.links = nullptr;
+  a.links = dp->d_links;
   a.coherent_only = 0;
   a.last_valid = NB;
   a.trace = nullptr;
@@ -2008,18 +2009,17 @@ int spdinv_autotune_batched(int batch, const int* h_n, spdinv_mode mode, int rep
   const bool fp32 = mode == SPDINV_FP32;
   const size_t es = fp32 ? sizeof(float) : sizeof(double);
   // candidates: one workgroup per matrix, the list-scheduled DAG, groups of
-  // 512; chains of 4 and 8 products (FP64)
+  // 512; chains of 1, 4 and 8 products
   std::vector<TunedBatch> cand;
   for (int g : {-1, -2, 512})
-    for (int c : {4, 8})
-      if (!fp32 || c == 4) cand.push_back(TunedBatch{g, fp32 ? 1 : c});
+    for (int c : {1, 4, 8}) cand.push_back(TunedBatch{g, c});
   std::vector<size_t> off(batch + 1, 0);
   for (int i = 0; i < batch; ++i) off[i + 1] = off[i] + (size_t)h_n[i] * h_n[i] * es;
   size_t wmax = 0;
   for (const TunedBatch& c : cand) {
     spdinv_opts o = defaults();
     o.batch_group = c.group;
-    o.chain = fp32 ? 0 : c.chain;
+    o.chain = c.chain;
     wmax = std::max(wmax, batched_spd_inverse_workspace_bytes(batch, h_n, mode, &o));
   }
   DevBufs bufs;
@@ -2048,7 +2048,7 @@ int spdinv_autotune_batched(int batch, const int* h_n, spdinv_mode mode, int rep
   for (const TunedBatch& c : cand) {
     spdinv_opts o = defaults();
     o.batch_group = c.group;
-    o.chain = fp32 ? 0 : c.chain;
+    o.chain = c.chain;
     auto prep = [&]() { return hipMemcpyAsync(A, A0, off[batch], hipMemcpyDeviceToDevice, stream); };
     auto call = [&]() {
       return batched_spd_inverse(batch, h_n, dn, p, dn, mode, work, wmax,

@@ -76,14 +76,22 @@ __device__ __forceinline__ void panel_store32(float* S, const f4 (&v)[Q32]) {
 // Tile product C (+)= +-A B^T on the FP32 matrix cores (the renamed plan's
 // only form: both operands read along stored columns), with the flags of the
 // FP64 product: F_NEG, F_ACC, F_LOWER (the block above the diagonal is not
-// stored), and the renaming copy (transposed with F_COPYT).
+// stored), and the renaming copy (transposed with F_COPYT).  A chained task
+// (nl further links) adds the products of the link pairs links[2(p-1)],
+// links[2(p-1)+1] (tile indices into pool; the last-block mark is ignored:
+// the FP32 forms run every k-panel) in order, the k-panels of all links
+// forming one double-buffered stream; the accumulator stays in registers,
+// and as a separate task's FP32 store and reload of C would be exact, every
+// rounding is that of the separate tasks.
 // v_mfma_f32_16x16x4f32(x, y, d): x[i][k] from lane i+16k, y[k][j] from lane
 // j+16k, d[i][j] in register i%4 of lane j + 16*(i/4).  The operands are
 // passed as (B block, A block), so lane l, register r holds output row l%16
 // of column 4*(l/16) + r.
 template <bool BF16>
 __device__ __forceinline__ void tile_mma32(int f, float* C, const float* A, const float* B,
-                                           float* copy, double* smem_d) {
+                                           float* copy, double* smem_d,
+                                           const int32_t* links = nullptr, int nl = 0,
+                                           float* pool = nullptr) {
   float* smem = reinterpret_cast<float*>(smem_d);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = w & 1, wn = w >> 1, lr = lane & 15, lk = lane >> 4;
@@ -109,14 +117,30 @@ __device__ __forceinline__ void tile_mma32(int f, float* C, const float* A, cons
   panel_store32(smem, va);
   panel_store32(smem + PANEL32, vb);
   __syncthreads();
+  // operand tiles of link l (0: A and B)
+  auto link_rsrc = [&](int l, rsrc_t& ra, rsrc_t& rb) {
+    if (l == 0) {
+      ra = rA;
+      rb = rB;
+    } else {
+      const int ia = __builtin_amdgcn_readfirstlane(links[2 * (l - 1)]) & ~LINK_KLAST;
+      const int ib = __builtin_amdgcn_readfirstlane(links[2 * (l - 1) + 1]);
+      ra = rsrc32(tile32(pool, ia));
+      rb = rsrc32(tile32(pool, ib));
+    }
+  };
+  const int npan = (1 + nl) * NCH;
 #pragma unroll 1
-  for (int c = 0; c < NCH; ++c) {
+  for (int c = 0; c < npan; ++c) {
     const float* As = smem + (c & 1) * 2 * PANEL32;
     const float* Bs = As + PANEL32;
-    const bool more = c + 1 < NCH;
+    const bool more = c + 1 < npan;
     if (more) {
-      panel_load32(rA, (c + 1) * KC, va);
-      panel_load32(rB, (c + 1) * KC, vb);
+      const int l = (c + 1) / NCH, k0 = ((c + 1) - NCH * l) * KC;
+      rsrc_t ra, rb;
+      link_rsrc(l, ra, rb);
+      panel_load32(ra, k0, va);
+      panel_load32(rb, k0, vb);
     }
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (!BF16) {
@@ -314,7 +338,11 @@ __device__ __forceinline__ void run_task32(const DevTask& t, const SchedArgs& g,
   switch (kind) {
     case K_SYRK1: case K_GEMM1: case K_TRSM1: case K_TRMM2L: case K_GEMM2: case K_TRSM2R:
     case K_TRMM3: case K_LAUUM: case K_GEMM3: case K_SYRK3:
-      tile_mma32<BF16>(f, out, a, b, cp, smem);  // renamed plan: A B^T products only
+      // renamed plan: A B^T products only, single or chained
+      {
+        const int nl = (t.kind & K_LINKS_MASK) >> K_LINKS_SHIFT;
+        tile_mma32<BF16>(f, out, a, b, cp, smem, nl ? g.links + 2 * t.aux : nullptr, nl, P);
+      }
       break;
     case K_POTRF: {
       float* X = tile32(P, t.aux);
@@ -635,6 +663,7 @@ void bsched_kernel32(BSchedArgs g) {
     SchedArgs s{};
     s.pool = reinterpret_cast<double*>(pool);
     s.ctrl = mc;
+    s.links = g.tlinks[t];  // the template's chained-product links
     s.info_base = 0;
     run_task32<false>(d, s, smem, t * (t + 1) / 2, t);
   };

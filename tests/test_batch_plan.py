@@ -97,12 +97,16 @@ def test_dispatch_is_topological_and_executes_to_the_inverse(opts, workers):
         assert err <= 1e-12 * ev[-1] / ev[0], (m, n)
 
 
-def test_fp32_templates_run_one_product_per_task():
+def test_fp32_templates_wrap_the_fp64_plan():
+    """The FP32 templates are those of FP64, chained products included (the
+    FP32 tile product runs chains too)."""
     tmpl = _templates([300, 700], mode="fp32")
+    ref = _templates([300, 700])
     for t, tp in tmpl.items():
-        assert len(tp["links"]) == 0
         kinds = tp["tasks"][:, 0] & 0xFF
         assert kinds[0] == BCOPYIN and kinds[-1] == BCOPYOUT
+        assert np.array_equal(tp["tasks"], ref[t]["tasks"])
+        assert np.array_equal(tp["links"], ref[t]["links"])
     plan = spd.batch_plan_export([300, 700, 90], mode="fp32", workers=64, batch_group=-2)
     _check_order([300, 700, 90], tmpl | _templates([90], mode="fp32"), plan)
 

@@ -78,3 +78,20 @@ def test_fp32_workers_per_cu_do_not_change_the_bits(n):
     ref = spd.spd_inverse(a32, mode="fp32")
     for opts in (dict(per_cu=2), dict(per_cu=1), dict(workers=37)):
         assert torch.equal(spd.spd_inverse(a32, mode="fp32", **opts), ref), opts
+
+
+@pytest.mark.parametrize("n", [700, 3000])
+def test_fp32_chained_tasks_give_the_bits_of_single_products(n):
+    """Chained FP32 products keep the accumulator in registers where separate
+    tasks store and reload it (exact in FP32): the same bits for every chain
+    length, single matrix and batched."""
+    a32 = inputs.wishart_shift(n, seed=34).float().to(DEV)
+    ref = spd.spd_inverse(a32, mode="fp32", chain=1)
+    for c in (0, 4, 12):
+        assert torch.equal(spd.spd_inverse(a32, mode="fp32", chain=c), ref), c
+    mats = [inputs.wishart_shift(m, seed=35 + m).float().to(DEV) for m in (700, 300, 1500)]
+    one = spd.batched_spd_inverse(mats, chain=1, batch_group=-1)
+    for c in (4, 8):
+        got = spd.batched_spd_inverse(mats, chain=c, batch_group=-1)
+        assert all(torch.equal(x, y) for x, y in zip(got, one)), c
+    assert torch.equal(one[2], spd.spd_inverse(mats[2], mode="fp32"))
