@@ -57,11 +57,14 @@ def test_default_launch_n16384_against_analytic_inverse(q16384, kappa):
 
 
 def test_launch_shapes_bit_identical_n16384(q16384):
-    """Default (512 workers, row halves) against one workgroup per CU, whole
-    products, and row quarters: the same bits."""
+    """Default (512 workers, row halves, chains of 8) against one workgroup
+    per CU, whole products, row quarters, and the chain lengths the
+    autotuner chooses among (12 is its choice at this order): the same
+    bits."""
     a, _ = inputs.spectrum_from_q(q16384, 1e6)
     x = spd.spd_inverse(a)
-    for opts in (dict(per_cu=1), dict(no_split=1), dict(parts=4)):
+    for opts in (dict(per_cu=1), dict(no_split=1), dict(parts=4), dict(chain=12),
+                 dict(chain=6, parts=2, per_cu=2)):
         assert torch.equal(x, spd.spd_inverse(a, **opts)), opts
 
 
