@@ -39,8 +39,8 @@ def test_autotune_batched_form_and_tuning_file(tmp_path):
     before = spd.batched_spd_inverse(mats)
     tb = spd.autotune_batched(orders, "fp64", reps=2)
     print("tuned:", tb, flush=True)
-    assert tb["batch_group"] in (-1, -2, 512) and tb["chain"] in (4, 8)
-    assert tb["candidates"] == 6 and 0 < tb["ms"] <= tb["ms_default"]
+    assert tb["batch_group"] in (-1, -2, 512) and tb["chain"] in (1, 4, 8)
+    assert tb["candidates"] == 9 and 0 < tb["ms"] <= tb["ms_default"]
     after = spd.batched_spd_inverse(mats)
     assert all(torch.equal(x, y) for x, y in zip(before, after))
     f = tmp_path / "tune.txt"
@@ -49,4 +49,5 @@ def test_autotune_batched_form_and_tuning_file(tmp_path):
     spd.tuning_load(str(f))
     assert all(torch.equal(x, y) for x, y in zip(before, spd.batched_spd_inverse(mats)))
     t32 = spd.autotune_batched(orders, "fp32", reps=2)
-    assert t32["batch_group"] in (-1, -2, 512) and t32["candidates"] == 3
+    assert t32["batch_group"] in (-1, -2, 512) and t32["chain"] in (1, 4, 8)
+    assert t32["candidates"] == 9
