@@ -469,7 +469,7 @@ def main():
                     help="precision row modes (+c64: every refinement correction in binary64)")
     ap.add_argument("--large-n", type=int, default=32768)
     ap.add_argument("--large-kappas", default="1e2")
-    ap.add_argument("--large-modes", default="fp64,mixed_fp32")
+    ap.add_argument("--large-modes", default="fp64,mixed_fp32,mixed_bf16")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (built-in schedule choices)")
     ap.add_argument("--batch-group", type=int, default=0,
