@@ -1,11 +1,15 @@
-// Mixed-precision form of the SPD inverse on gfx950 (MI355X): the renamed,
-// pipelined tile DAG of Section 3 executed with FP32 tiles.  Tile products
-// run on the FP32 matrix cores (v_mfma_f32_16x16x4f32, FP32 accumulation) or,
-// in the BF16 variant, on bfloat16 operands rounded from the FP32 tiles
-// (v_mfma_f32_16x16x16_bf16, FP32 accumulation);
-// the diagonal tiles are factored and inverted in binary64 (the same LDS code
-// as the FP64 path) and rounded back.  The result is the starting inverse X0
-// that the Newton-Schulz refinement (FP64 residuals, dense.hip) corrects.
+// FP32 and mixed-precision forms of the SPD inverse on gfx950 (MI355X): the
+// renamed, pipelined tile DAG of Section 3 executed with FP32 tiles, chained
+// tasks included.  Tile products run on the FP32 matrix cores
+// (v_mfma_f32_16x16x4f32, FP32 accumulation) or, in the BF16 variant, on
+// bfloat16 operands rounded from the FP32 tiles (v_mfma_f32_16x16x16_bf16,
+// FP32 accumulation); the diagonal tiles are factored and inverted in
+// binary64 (the packed LDS code of the FP64 path) and rounded back.  The FP32
+// form stops there; in the mixed forms the result is the starting inverse X0
+// that the Newton-Schulz refinement corrects (binary64 residuals in
+// dense.hip; the corrections that another residual follows on the FP32
+// matrix cores, gemm_nt32_lower_kernel below).  The batched FP32 form runs
+// the same tasks per matrix (bsched_kernel32).
 //
 // FP32 tiles are NB x NB floats, column-major, contiguous (64 KiB), in the
 // same pool layout as the FP64 path: A tiles, the transposed renaming copies
