@@ -169,7 +169,9 @@ typedef struct {
   int refine_iters;    /* mixed modes: refinement steps taken                    */
   int fell_back;       /* mixed modes: the result comes from the FP64 path because
                           1: the low-precision start failed (the FP32
-                          factorization broke down or ||I - A X0||_F >= 1), or
+                          factorization broke down, its residual
+                          ||I - A X0||_F was estimated above 2 from random
+                          probes, or measured >= 1), or
                           2: the library's default step limit ran out before
                           the stop rule was met; 0 otherwise                  */
   double resid_fro_rel; /* mixed modes: ||I - A X||_F / ||A||_F of the returned X
@@ -183,6 +185,10 @@ typedef struct {
                           (the residual of the returned X was not formed)     */
   int low_corrections; /* mixed modes: refinement steps whose correction ran on
                           the FP32 matrix cores                               */
+  double resid0_probe_rel; /* mixed modes: ||I - A X0||_F / ||A||_F estimated from
+                          128 random sign probes V (||R0 V||_F^2 / 128
+                          estimates ||R0||_F^2) before the full residual is
+                          formed; -1 when not taken                           */
 } spdinv_report;
 
 /* Fills `opts` with the defaults. */
@@ -208,8 +214,10 @@ size_t spd_inverse_workspace_bytes(int n, spdinv_mode mode, const spdinv_opts* o
  * since I - A (X + X R) = R^2, the loop also stops, without forming the
  * next residual, once (||R||_F^2 + 4 u ||A||_F ||X||_F) / ||A||_F meets the
  * rule (u = 2^-53).  That last correction is formed in binary64, the earlier
- * ones on the FP32 matrix cores (see opts->correction64).  It synchronizes the stream once per step.  It
- * falls back to the FP64 path when the FP32 factorization breaks down, when
+ * ones on the FP32 matrix cores (see opts->correction64).  It synchronizes
+ * the stream once per step.  It falls back to the FP64 path when the FP32
+ * factorization breaks down, when ||R_0||_F estimated from 128 random sign
+ * probes (two thin products, before the full residual) exceeds 2, when
  * ||R_0||_F >= 1, or when the default step limit runs out first (with an
  * explicit max_refine or refine_tol it returns the refined X instead, with
  * report->converged = 0).

@@ -46,7 +46,8 @@ class Report(ctypes.Structure):
                 ("refine_iters", ctypes.c_int), ("fell_back", ctypes.c_int),
                 ("resid_fro_rel", ctypes.c_double), ("resid0_fro_rel", ctypes.c_double),
                 ("resid_last_rel", ctypes.c_double), ("converged", ctypes.c_int),
-                ("predicted", ctypes.c_int), ("low_corrections", ctypes.c_int)]
+                ("predicted", ctypes.c_int), ("low_corrections", ctypes.c_int),
+                ("resid0_probe_rel", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):

@@ -1345,7 +1345,7 @@ int spd_inverse_backward(int n, const double* X, int ldx, const double* G, int l
 // (everything in it is dead by then; A itself is untouched until the final
 // copy-out).
 struct MixedLayout {
-  size_t indeg, ctrl, asq, x, x2, r, partial, r32, total;
+  size_t indeg, ctrl, asq, x, x2, r, partial, r32, probe, total;
 };
 
 MixedLayout mixed_layout(int n, const spdinv_opts& o) {
@@ -1361,7 +1361,8 @@ MixedLayout mixed_layout(int n, const spdinv_opts& o) {
   M.r = M.x2 + sq;
   M.partial = M.r + sq;
   M.r32 = M.partial + align_up(((size_t)t * t + 8) * sizeof(double), 256);
-  M.total = M.r32 + align_up(sq / 2, 256);
+  M.probe = M.r32 + align_up(sq / 2, 256);  // 3 tile columns: V^T, (A V)^T, (R V)^T
+  M.total = M.probe + align_up((size_t)3 * t * NB * NB * sizeof(double), 256);
   spdinv_opts o64 = o;
   o64.trace = 0;
   M.total = std::max(M.total, layout(n, o64).total);
@@ -1523,7 +1524,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
   bool fallback = c[CTRL_FAILED] != 0;
   int fell_back = fallback ? 1 : 0;
   int iters = 0, converged = 0, predicted = 0, low_steps = 0;
-  double r0 = -1.0, rl = -1.0, rpred = -1.0;
+  double r0 = -1.0, rl = -1.0, rpred = -1.0, r0_probe = -1.0;
   double* X = nullptr;
   if (!fallback) {
     double* Asq = (double*)(w + M.asq);
@@ -1531,12 +1532,38 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
     double* X2 = (double*)(w + M.x2);
     double* R = (double*)(w + M.r);
     double* partial = (double*)(w + M.partial);
-    double* dnorm = partial + (size_t)t * t;  // [0] ||A||^2, [1] ||R||^2, [2] ||X0||^2
+    double* dnorm = partial + (size_t)t * t;  // [0] ||A||^2, [1] ||R||^2, [2] ||X0||^2,
+                                              // [3] ||R0 V||^2 of the probes
     const int sq_tiles = t * t;
     if (launch_pack(A, lda, n, t, PACK_SYM_LOWER, Asq, stream) != hipSuccess) return SPDINV_ERR_HIP;
     if (launch_sumsq(Asq, sq_tiles, partial, dnorm, stream) != hipSuccess) return SPDINV_ERR_HIP;
     if (launch_x0_to_sym64(pool, t, n, X, stream) != hipSuccess) return SPDINV_ERR_HIP;
     if (launch_sumsq(X, sq_tiles, partial, dnorm + 2, stream) != hipSuccess) return SPDINV_ERR_HIP;
+    // Newton-Schulz needs ||R_0|| < 1.  Estimate ||R_0||_F from NB random
+    // sign probes first, E ||R_0 V||_F^2 = NB ||R_0||_F^2 (relative spread
+    // at most sqrt(2 / NB) = 0.125): a start estimated above 2 falls back
+    // at once, without the 2 n^3 of the full residual
+    {
+      double* Vt = (double*)(w + M.probe);
+      double* Yt = Vt + (size_t)t * NB * NB;
+      double* RVt = Yt + (size_t)t * NB * NB;
+      if (launch_fill_probe(Vt, t, n, stream) != hipSuccess ||
+          launch_gemm_thin(Vt, Asq, Yt, t, 0, stream) != hipSuccess ||      // (A V)^T
+          launch_gemm_thin(Yt, X, RVt, t, 1, stream, Vt) != hipSuccess ||   // (V - X0 A V)^T
+          launch_sumsq(RVt, t, partial, dnorm + 3, stream) != hipSuccess)
+        return SPDINV_ERR_HIP;
+      double h[4];
+      if (hipMemcpyAsync(h, dnorm, sizeof(h), hipMemcpyDeviceToHost, stream) != hipSuccess)
+        return SPDINV_ERR_HIP;
+      if (hipStreamSynchronize(stream) != hipSuccess) return SPDINV_ERR_HIP;
+      const double est = std::sqrt(h[3] / NB);
+      r0_probe = est / std::sqrt(h[0]);
+      if (!(est <= 2.0)) {  // NaN included
+        fallback = true;
+        fell_back = 1;
+        r0 = r0_probe;
+      }
+    }
     float* X32 = (float*)w;  // the FP32 pool is dead once X0 is widened
     float* R32 = (float*)(w + M.r32);
     const size_t sq_elems = (size_t)sq_tiles * NB * NB;
@@ -1546,7 +1573,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
     bool last_low = false;
     double prev_rnorm = 0.0;
     double anorm = 0.0, floor_abs = 0.0;
-    for (int k = 0;; ++k) {
+    for (int k = 0; !fallback; ++k) {
       // R^T = I - X A (A and X symmetric); ||R^T||_F = ||R||_F
       if (launch_gemm_nt(X, Asq, R, t, 0, 1, stream, nullptr, n) != hipSuccess) return SPDINV_ERR_HIP;
       if (launch_sumsq(R, sq_tiles, partial, dnorm + 1, stream) != hipSuccess) return SPDINV_ERR_HIP;
@@ -1630,6 +1657,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
       report->converged = 0;
       report->predicted = 0;
       report->low_corrections = low_steps;
+      report->resid0_probe_rel = r0_probe;
     }
     return rc;
   }
@@ -1653,6 +1681,7 @@ int run_mixed(int n, double* A, int lda, void* work, size_t work_bytes, hipStrea
     report->converged = converged;
     report->predicted = predicted;
     report->low_corrections = low_steps;
+    report->resid0_probe_rel = r0_probe;
   }
   return 0;
 }

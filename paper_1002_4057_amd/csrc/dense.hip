@@ -7,6 +7,8 @@
 // Square tile-major layout: t x t tiles of NB x NB, tile (i, j) at index
 // i + t*j, each tile column-major and contiguous.  Entries beyond the order n
 // are zero, so the padding adds nothing to any product.
+#include <algorithm>
+
 #include "dense.hpp"
 #include "mfma_tile.hpp"
 
@@ -127,6 +129,51 @@ void gemm_nt_kernel(const double* __restrict__ A, const double* __restrict__ B,
       }
   }
   acc_store_tile<0>(tile_rsrc(C + ct), acc, neg != 0);
+}
+
+// Thin chained product: C(i) = Cin(i) +- sum_k P(k) Q(i, k)^T for i < t,
+// where P and C are tile columns (t tiles of NB x NB, tile k at k) and Q is
+// square tile-major (tile (i, k) at i + t k).  One output tile per
+// workgroup, the k-panels of the t links streamed as in gemm_nt_kernel.
+// (With symmetric Q, P the transposed tiles of a thin matrix V, the result
+// holds the transposed tiles of Q V.)
+__global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void gemm_thin_kernel(const double* __restrict__ P, const double* __restrict__ Q,
+                      double* __restrict__ C, int t, int neg, const double* __restrict__ Cin) {
+  __shared__ double smem[4 * DKD * LDS_STRIDE];
+  const int i = blockIdx.x;
+  Acc acc;
+  const size_t ct = (size_t)i * TILE;
+  if (Cin)
+    acc_load<0>(tile_rsrc(Cin + ct), acc, neg != 0);
+  else
+    acc_zero(acc);
+  auto pair = [&](int k, const double*& pa, const double*& pb) {
+    pa = P + (size_t)k * TILE;
+    pb = Q + (size_t)(i + t * k) * TILE;
+  };
+  mma_chain<0, DKD>(acc, t, pair, smem);
+  acc_store_tile<0>(tile_rsrc(C + ct), acc, neg != 0);
+}
+
+// Random sign probes: the transposed tiles of V (n rows padded to t tiles,
+// NB columns), V(r, c) = +-1 from a hash of (r, c) for r < n, 0 beyond n:
+// tile k holds V^T's columns 128 k .. 128 k + 127, element (c, rr) at
+// c + NB rr for matrix row 128 k + rr.
+__global__ __launch_bounds__(NTHREADS) void fill_probe_kernel(double* __restrict__ Vt, int t,
+                                                              int n) {
+  const size_t total = (size_t)t * TILE;
+  for (size_t e = (size_t)blockIdx.x * NTHREADS + threadIdx.x; e < total;
+       e += (size_t)gridDim.x * NTHREADS) {
+    const int k = (int)(e / TILE), w = (int)(e % TILE), c = w & (NB - 1), rr = w >> 7;
+    const int r = NB * k + rr;
+    // splitmix64 of (r, c): a fixed, platform-independent sign pattern
+    unsigned long long z = ((unsigned long long)r << 32 | (unsigned)c) + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    Vt[e] = r < n ? ((z & 1) ? 1.0 : -1.0) : 0.0;
+  }
 }
 
 // partial[b] = sum of squares of the entries of tile b (fixed summation
@@ -427,6 +474,20 @@ int bback_blocks_per_cu() {
 hipError_t launch_pack(const double* src, int ld, int n, int t, int mode, double* dst,
                        hipStream_t s) {
   hipLaunchKernelGGL(pack_kernel, dim3(t * t), dim3(NTHREADS), 0, s, src, ld, n, t, mode, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_thin(const double* P, const double* Q, double* C, int t, int neg,
+                            hipStream_t s, const double* Cin) {
+  if (t < 1) return hipErrorInvalidValue;  // the chain takes at least one link
+  hipLaunchKernelGGL(gemm_thin_kernel, dim3(t), dim3(NTHREADS), 0, s, P, Q, C, t, neg, Cin);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_probe(double* Vt, int t, int n, hipStream_t s) {
+  const size_t total = (size_t)t * TILE;
+  const size_t blocks = std::min<size_t>((total + NTHREADS - 1) / NTHREADS, 4096);
+  hipLaunchKernelGGL(fill_probe_kernel, dim3((unsigned)blocks), dim3(NTHREADS), 0, s, Vt, t, n);
   return hipGetLastError();
 }
 

@@ -24,6 +24,15 @@ hipError_t launch_pack(const double* src, int ld, int n, int t, int mode, double
 hipError_t launch_gemm_nt(const double* A, const double* B, double* C, int t, int lower, int neg,
                           hipStream_t s, const double* Cin = nullptr, int diag_n = 0);
 
+// C(i) = Cin(i) -+ sum_k P(k) Q(i, k)^T for the t tiles of a tile column:
+// P and C tile columns, Q square tile-major (the residual probes of the
+// mixed form); Cin may be null.
+hipError_t launch_gemm_thin(const double* P, const double* Q, double* C, int t, int neg,
+                            hipStream_t s, const double* Cin = nullptr);
+
+// The transposed tiles of an n x NB matrix of random signs (zero rows past n).
+hipError_t launch_fill_probe(double* Vt, int t, int n, hipStream_t s);
+
 // Column-major symmetric matrix (both triangles, or the lower one) from the
 // lower tiles of src.
 hipError_t launch_unpack_sym(const double* src, int t, int n, double* out, int ld, hipStream_t s,

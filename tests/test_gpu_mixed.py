@@ -114,6 +114,36 @@ def test_low_precision_step_within_its_rounding_bound():
     assert r1 < 0.1 * r0
 
 
+@pytest.mark.parametrize("n", [300, 1000, 2100])
+def test_probe_estimate_tracks_the_measured_start_residual(n):
+    """Before forming R0 = I - A X0 the library estimates ||R0||_F from 128
+    random sign probes (E ||R0 V||_F^2 = 128 ||R0||_F^2, relative spread at
+    most sqrt(2/128)): within a factor 1.5 of the measured value."""
+    a = inputs.spectrum(n, 1e2, seed=40 + n).numpy()
+    _, rep = spd.spd_inverse(torch.from_numpy(a).to(DEV), mode="mixed_fp32", return_report=True)
+    print(rep, flush=True)
+    assert rep["fell_back"] == 0
+    ratio = rep["resid0_probe_rel"] / rep["resid0_fro_rel"]
+    assert 1 / 1.5 <= ratio <= 1.5
+
+
+def test_probe_rejects_a_hopeless_start_without_the_residual():
+    """kappa = 1e7 at n = 2000: the FP32 start has ||R0||_F far above 1 (it
+    grows with kappa: about 0.8 at kappa = 1e6 here); the probe estimate
+    rejects it (reported in resid0_fro_rel, no residual formed) and the FP64
+    path gives the result, bit for bit."""
+    n = 2000
+    a = torch.from_numpy(inputs.spectrum(n, 1e7, seed=41).numpy()).to(DEV)
+    x, rep = spd.spd_inverse(a, mode="mixed_fp32", return_report=True)
+    print(rep, flush=True)
+    assert rep["fell_back"] == 1 and rep["refine_iters"] == 0
+    anorm = torch.linalg.norm(a).item()
+    assert rep["resid0_probe_rel"] * anorm > 2.0
+    assert rep["resid0_fro_rel"] == rep["resid0_probe_rel"]
+    assert rep["resid_last_rel"] == -1.0              # no residual was formed
+    assert torch.equal(x, spd.spd_inverse(a))
+
+
 def test_predicted_stop_skips_the_last_residual():
     """With the default tolerance the loop stops on the prediction
     ||I - A X'||_F <= ||R||_F^2 + floor (I - A (X + X R) = R^2), without
