@@ -182,3 +182,24 @@ def test_batched_backward_arguments_rejected_on_host():
     a = list(args)
     a[9] = 16
     assert lib.batched_spd_inverse_backward(2, n, *a) == _lib.ERR_WORKSPACE
+
+
+@pytest.mark.parametrize("opts,mode,code", [
+    (dict(correction64=2), 2, -8),          # not 0 or 1
+    (dict(tree_levels=1), 1, -8),           # the FP32 form runs the sequential chains
+    (dict(tree_levels=1), 2, -8),           # so do the mixed forms
+    (dict(tree_levels=3), 0, -8),           # at most 2 levels
+    (dict(rename_tiles=10), 3, -8),         # partial renaming is FP64 only
+])
+def test_options_of_the_forms_rejected_on_host(opts, mode, code):
+    """Rejected by the host checks, before any device call."""
+    lib = _lib.load()
+    o = spd.make_opts(**opts)
+    assert lib.spd_inverse(4, 1, 4, mode, 1, 1 << 30, None, ctypes.byref(o), None, None) == code
+
+
+def test_noalloc_rejects_the_tree_and_the_trace():
+    lib = _lib.load()
+    for opts in (dict(tree_levels=1), dict(trace=1)):
+        o = spd.make_opts(**opts)
+        assert lib.spd_inverse_noalloc(4, 1, 4, None, ctypes.byref(o), None) == -5
