@@ -780,6 +780,7 @@ const BTemplate* btemplate_host(int t, bool fp32, const spdinv_opts& o) {
     po.pipelined = 1;
     po.trtri_first = o.trtri_first ? 1 : 0;
     po.chain = btemplate_chain(o, fp32);
+    po.chain_tails = 1;  // one workgroup runs a matrix's tasks in order: every operand is ready
     Plan p;
     // one worker: the list-scheduling order is a priority order of the
     // matrix's tasks, and chains form wherever the contraction rules allow

@@ -508,7 +508,8 @@ bool chainable(const DevTask& u, const DevTask& v) {
 //    program order stays topological);
 //  - v is not the last product of its chain (the one followed by a
 //    non-chainable writer of the tile, or by none): that product waits for
-//    the most recently finished operand, so it stays a task of its own;
+//    the most recently finished operand, so it stays a task of its own
+//    (unless `tails`: a plan run in order by one workgroup);
 //  - in the simulated schedule of the uncontracted DAG (start times `st`,
 //    durations `dur`, `link` per further link), v's other predecessors have
 //    finished by the time the contracted task would reach v, give or take
@@ -520,7 +521,7 @@ bool chainable(const DevTask& u, const DevTask& v) {
 // union of the members' external predecessors.
 void chain_products(int chain, Plan* p, std::vector<std::vector<int32_t>>& preds,
                     const std::vector<double>& st, const std::vector<double>& dur, double link,
-                    double slack) {
+                    double slack, bool tails) {
   const int n = (int)p->tasks.size();
   std::vector<int32_t> next_out(n, -1);
   {
@@ -533,7 +534,8 @@ void chain_products(int chain, Plan* p, std::vector<std::vector<int32_t>>& preds
       last[o] = v;
     }
   }
-  auto tail = [&](int v) {  // v is the last product of its chain
+  auto tail = [&](int v) {  // v is the last product of its chain (and must run alone)
+    if (tails) return false;
     const int w = next_out[v];
     return w < 0 || !chainable(p->tasks[v], p->tasks[w]);
   };
@@ -819,7 +821,8 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
       dur0[v] = cost ? cost[task_kind(p->tasks[v].kind)] : (double)weight(p->tasks[v].kind);
     list_schedule(bld.preds, dur0, workers, nullptr, &st0);
     // slack: 5 single-product durations (the unit of `cost`)
-    chain_products(opt.chain, p, bld.preds, st0, dur0, cost ? cost[K_COUNT] : 1.0, 5.0);
+    chain_products(opt.chain, p, bld.preds, st0, dur0, cost ? cost[K_COUNT] : 1.0, 5.0,
+                   opt.chain_tails != 0);
   }
   if (opt.split == 2 || opt.split == 4) split_critical_products(p, bld.preds, opt.split);
 

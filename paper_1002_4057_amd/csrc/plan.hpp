@@ -63,6 +63,12 @@ struct PlanOptions {
   int pipelined = 1;
   int trtri_first = 0;
   int chain = 1;        // most products per device task (1 <= chain <= MAX_CHAIN)
+  // 1: the last product of an update chain (the one before the tile's
+  // closing task) may join the chain too.  In a parallel DAG it runs alone,
+  // as it waits for the most recently finished operand; a plan that one
+  // workgroup runs in order (the batched form's per-matrix templates) has
+  // every operand ready.
+  int chain_tails = 0;
   // Steps of Algorithm 1 in the plan: bit 0 step 1 (Cholesky), bit 1 step 2
   // (inverse of the factor), bit 2 step 3 (the product L^-T L^-1).  7 = the
   // SPD inverse, 1 = the Cholesky factor only, 6 = the inverse from a given

@@ -111,17 +111,35 @@ def test_fp32_templates_wrap_the_fp64_plan():
     _check_order([300, 700, 90], tmpl | _templates([90], mode="fp32"), plan)
 
 
+def _expanded(tasks, links):
+    """(out, a, b) of every tile product, chained links expanded, and the
+    kinds of the other tasks."""
+    prods, others = [], []
+    for task in tasks:
+        kind = int(task[0])
+        if (kind & 0xFF) in tx.PRODUCTS:
+            prods.append((int(task[1]), int(task[2]), int(task[3])))
+            nl = (kind >> tx.LINKS_SHIFT) & 0xF
+            for q in range(nl):
+                la, lb = links[int(task[5]) + q]
+                prods.append((int(task[1]), int(la) & ~tx.LINK_KLAST, int(lb)))
+        else:
+            others.append(kind & 0xFF)
+    return sorted(prods), sorted(others)
+
+
 def test_templates_wrap_the_plan_of_algorithm_1():
-    """Template of t: the copy-in task, then exactly the tasks of the plan
-    that one worker would run (same kinds and tiles), then the copy-out."""
+    """Template of t: the copy-in task, then the tile products and the other
+    tasks of the plan that one worker would run (the same operand tiles; the
+    template also chains each update chain's last product, as one workgroup
+    runs the matrix's tasks in order), then the copy-out."""
     for t in (2, 3, 4, 16):
         tp = spd.batch_template_export(t)
         pl = spd.plan_export(t, workers=1)
-        inner = tp["tasks"][1:-1]
-        assert len(inner) == len(pl["tasks"])
-        assert sorted(map(tuple, inner[:, :6].tolist())) == sorted(map(tuple, pl["tasks"][:, :6]
-                                                                       .tolist()))
+        assert _expanded(tp["tasks"][1:-1], tp["links"]) == _expanded(pl["tasks"], pl["links"])
+        assert len(tp["tasks"]) - 2 <= len(pl["tasks"])
         assert tp["tasks"][0, 0] == BCOPYIN and tp["tasks"][-1, 0] == BCOPYOUT
+    assert len(spd.batch_template_export(16)["tasks"]) - 2 < len(spd.plan_export(16, workers=1)["tasks"])
     small = spd.batch_template_export(1)
     assert small["tasks"].shape[0] == 1 and small["tasks"][0, 0] == BSMALL
 
