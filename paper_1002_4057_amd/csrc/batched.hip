@@ -89,7 +89,7 @@ __device__ __forceinline__ int load_uniform(int32_t* p) {
 __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bsched_kernel(BSchedArgs g) {
   __shared__ double smem[TASK_SMEM];
-  auto run = [&](const DevTask& d, int m, int t) {
+  auto run = [&](const DevTask& d, int m, int t) __attribute__((always_inline)) {
     const int kind = d.kind & 0xff;
     int32_t* mc = g.mctrl + CTRL_WORDS * m;
     int n, lda;

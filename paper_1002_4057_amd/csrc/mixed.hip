@@ -259,8 +259,7 @@ __device__ __attribute__((noinline)) int potrf_inv_tile32(const float* Ain, floa
 #pragma unroll
   for (int u = 0; u < NLD; ++u) {
     const int b = __builtin_amdgcn_readfirstlane((NTHREADS * u + tid) >> 6);
-    int bi = 0;
-    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+    const int bi = pk_row(b);
     const int bj = b - bi * (bi + 1) / 2;
     const int e = tid & 63, lr = 4 * (e & 3), lc = e >> 2;
     v[u] = ld4f(rIn, (16 * bi + lr) + NB * (16 * bj + lc));
@@ -268,8 +267,7 @@ __device__ __attribute__((noinline)) int potrf_inv_tile32(const float* Ain, floa
 #pragma unroll
   for (int u = 0; u < NLD; ++u) {
     const int b = __builtin_amdgcn_readfirstlane((NTHREADS * u + tid) >> 6);
-    int bi = 0;
-    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+    const int bi = pk_row(b);
     const bool diag = b == bi * (bi + 1) / 2 + bi;
     const int e = tid & 63, lr = 4 * (e & 3), lc = e >> 2;
     double* dst = T + PK_STRIDE * b + lr + PK_LD * lc;
@@ -629,7 +627,7 @@ __device__ __forceinline__ int load_uniform32(int32_t* p) {
 __global__ __launch_bounds__(NTHREADS) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void bsched_kernel32(BSchedArgs g) {
   __shared__ double smem[TASK_SMEM];
-  auto run = [&](const DevTask& d, int m, int t) {
+  auto run = [&](const DevTask& d, int m, int t) __attribute__((always_inline)) {
     const int kind = d.kind & 0xff;
     int32_t* mc = g.mctrl + CTRL_WORDS * m;
     int n, lda;

@@ -44,8 +44,7 @@ __device__ int small_inverse(E* A, int lda, int n, int fill_upper, double* smem)
   const int nblk = P * (P + 1) / 2;
   for (int e = tid; e < nblk * 256; e += NTHREADS) {
     const int b = e >> 8, lr = e & 15, lc = (e >> 4) & 15;
-    int I = 0;
-    while ((I + 1) * (I + 2) / 2 <= b) ++I;
+    const int I = pk_row(b);
     const int J = b - I * (I + 1) / 2;
     const int r = 16 * I + lr, c = 16 * J + lc;
     double v;
@@ -66,8 +65,7 @@ __device__ int small_inverse(E* A, int lda, int n, int fill_upper, double* smem)
     const int q = w + 4 * s2;
     y[s2] = d4{0.0, 0.0, 0.0, 0.0};
     if (q < nblk) {
-      int I = 0;
-      while ((I + 1) * (I + 2) / 2 <= q) ++I;
+      const int I = pk_row(q);
       const int J = q - I * (I + 1) / 2;
       for (int K = I; K < P; ++K)  // X_KI^T X_KJ
         y[s2] = blk_mma16x(y[s2], pk_blk(T, K, I), PK_LD, true, pk_blk(T, K, J), PK_LD, false);
@@ -79,8 +77,7 @@ __device__ int small_inverse(E* A, int lda, int n, int fill_upper, double* smem)
   for (int s2 = 0; s2 < PER_WAVE; ++s2) {
     const int q = w + 4 * s2;
     if (q >= nblk) continue;
-    int I = 0;
-    while ((I + 1) * (I + 2) / 2 <= q) ++I;
+    const int I = pk_row(q);
     const int J = q - I * (I + 1) / 2;
     const int r = 16 * I + lr;
 #pragma unroll

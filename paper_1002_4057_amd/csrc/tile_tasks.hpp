@@ -566,13 +566,23 @@ __device__ __forceinline__ double* pk_blk(double* T, int i, int p) {
   return T + PK_STRIDE * (i * (i + 1) / 2 + p);
 }
 
+// Block row i of the packed index b = i(i+1)/2 + j (0 <= b < 36), without a
+// loop: a loop of taken branches per block cost half the tile load's time.
+__device__ __forceinline__ int pk_row(int b) {
+  return (b >= 1) + (b >= 3) + (b >= 6) + (b >= 10) + (b >= 15) + (b >= 21) + (b >= 28);
+}
+
 // Blocked Cholesky factorization of the leading 16P x 16P block of the
 // packed tile, in place, with one block of lookahead: wave 0 factors the
 // 16 x 16 diagonal block (chol16); the panel below it solves
-// L_ip = A_ip L_pp^{-T} by forward substitution, one row per thread; in the
-// trailing update A_ij -= L_ip L_jp^T (16x16x16 MFMA blocks) wave 0 first
-// updates and factors the next diagonal block while waves 1-3 update the
-// rest of the trailing blocks.  rd receives the 16P
+// L_ip = A_ip L_pp^{-T} by forward substitution, one row per thread; of the
+// updates A_ij -= L_im L_jm^T (16x16x16 MFMA blocks), wave 0 applies the
+// last one to the next diagonal block and factors it, while waves 1-3 bring
+// the rest of the next block column up to date and apply panel p to the
+// later diagonal blocks.  Every block sums its updates in the order
+// m = 0, 1, ... as a right-looking update would (the LDS round trips and
+// sign changes between them are exact); deferring the off-diagonal ones
+// keeps each step's work near the diagonal block's.  rd receives the 16P
 // reciprocal pivots; col is chol16's broadcast buffer.  Returns 0 or the
 // 1-based index of the first pivot that is not positive (or NaN), uniform
 // over the workgroup.
@@ -615,15 +625,20 @@ __device__ __forceinline__ int factor_packed(double* T, double* rd, double* col,
       const int f = chol16(Cnn, PK_LD, rd + 16 * (p + 1), col);
       if (tid == 0) *flag = f ? 16 * (p + 1) + f : 0;
     } else {
-      for (int q = w; q < nb * (nb + 1) / 2; q += 3) {
-        int i = 0;
-        while ((i + 1) * (i + 2) / 2 <= q) ++i;
-        const int j = q - i * (i + 1) / 2;
-        const int bi = p + 1 + i, bj = p + 1 + j;
-        double* Cij = pk_blk(T, bi, bj);
+      // waves 1-3: the blocks below the diagonal in column p+1 (the next
+      // panel) take all their updates m = 0..p now, as one chain, and the
+      // later diagonal blocks take the update of panel p
+      for (int u = w - 1; u < nb - 1; u += 3) {
+        const int bi = p + 2 + u;
+        double* Cij = pk_blk(T, bi, p + 1);
         d4 acc = -blk_load(Cij, PK_LD);
-        acc = blk_mma16(acc, pk_blk(T, bi, p), PK_LD, pk_blk(T, bj, p), PK_LD, true);
+        for (int m = 0; m <= p; ++m)
+          acc = blk_mma16(acc, pk_blk(T, bi, m), PK_LD, pk_blk(T, p + 1, m), PK_LD, true);
         blk_store(Cij, PK_LD, -acc);
+        double* Cjj = pk_blk(T, bi, bi);
+        d4 acd = -blk_load(Cjj, PK_LD);
+        acd = blk_mma16(acd, pk_blk(T, bi, p), PK_LD, pk_blk(T, bi, p), PK_LD, true);
+        blk_store(Cjj, PK_LD, -acd);
       }
     }
     __syncthreads();
@@ -633,16 +648,73 @@ __device__ __forceinline__ int factor_packed(double* T, double* rd, double* col,
   return 0;
 }
 
+// acc += A_blk * op(B)_blk as blk_mma16, with A_blk held in registers in
+// the accumulator layout (lane l, register r: row l%16, column l/16 + 4r),
+// which is the layout in which each MFMA step takes its A operand: the
+// result of one block product feeds the next without a trip through LDS.
+__device__ __forceinline__ d4 blk_mma16_areg(d4 acc, const d4& A, const double* B, int ldb,
+                                             bool tb) {
+  const int lane = opaque_tid() & 63, lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int k = 4 * kk + lk;
+    const double b = tb ? B[lr + ldb * k] : B[k + ldb * lr];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(b, A[kk], acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// One level of the recursive inverse: the groups of S diagonal blocks
+// starting at 2 S g are joined pairwise.  With L = [L11 0; L21 L22] over a
+// pair and X11 = L11^{-1}, X22 = L22^{-1} already formed, the off-diagonal
+// part of the inverse is X21 = -(X22 L21) X11.  Phase A forms
+// W = X22 L21 in place of L21, wave w taking one block column of one pair
+// (every column costs S(S+1)/2 block products); phase B forms -W X11 in
+// place of W, wave w taking one block row (the same count).  A pair whose
+// second group starts at or past P is skipped: its L21 is zero (padding),
+// so is its X21.
+template <int S>
+__device__ __forceinline__ void inverse_level(double* T, int P) {
+  const int w = opaque_tid() >> 6, g = w / S, u = w % S;
+  const int b1 = 2 * S * g, b2 = b1 + S;   // first blocks of the two groups
+  const bool live = b2 < P;
+  d4 acc[S];
+  if (live) {                              // column u of W
+#pragma unroll
+    for (int i = 0; i < S; ++i) {
+      acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k <= i; ++k)
+        acc[i] = blk_mma16(acc[i], pk_blk(T, b2 + i, b2 + k), PK_LD, pk_blk(T, b2 + k, b1 + u),
+                           PK_LD, false);
+    }
+#pragma unroll
+    for (int i = 0; i < S; ++i) blk_store(pk_blk(T, b2 + i, b1 + u), PK_LD, acc[i]);
+  }
+  __syncthreads();
+  if (live) {                              // row u of X21
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = j; k < S; ++k)
+        acc[j] = blk_mma16(acc[j], pk_blk(T, b2 + u, b1 + k), PK_LD, pk_blk(T, b1 + k, b1 + j),
+                           PK_LD, false);
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) blk_store(pk_blk(T, b2 + u, b1 + j), PK_LD, -acc[j]);
+  }
+  __syncthreads();
+}
+
 // X = L^{-1} in place on the packed factor (its first P blocks of 16).
 // First X_pp = L_pp^{-1} for every diagonal block (16 lanes per block, one
 // column per lane, by forward substitution with the reciprocal pivots rd).
-// Then block columns p = P-2 .. 0 from the right, using X L = I:
-//   Y_mp = L_mp X_pp  (m > p; replaces L_mp),
-//   X_ip = -sum_{m=p+1..i} X_im Y_mp  (i > p; replaces Y_ip once every block
-//   of the column is formed).
-// Each phase keeps its results in registers until a barrier, so the blocks
-// of a column are formed in parallel over the waves and nothing else needs
-// LDS.
+// Then recursive doubling: pairs of single blocks (wave w joins blocks 2w
+// and 2w + 1, the product X22 L21 passed to the second product in
+// registers), then pairs of 2-block groups and the pair of 4-block groups
+// (inverse_level).  Blocks past P are the identity with zero cross blocks
+// and stay so.
 __device__ __forceinline__ void inverse_packed(double* T, const double* rd, int P) {
   const int tid = opaque_tid(), w = tid >> 6;
   {
@@ -666,50 +738,18 @@ __device__ __forceinline__ void inverse_packed(double* T, const double* rd, int 
     }
     __syncthreads();
   }
-  for (int p = P - 2; p >= 0; --p) {
-    const double* Xpp = pk_blk(T, p, p);
-    // Y_mp = L_mp X_pp, blocks m = p+1 .. P-1 over the waves (at most 2 each)
-    d4 y[2];
-#pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2) {
-      const int m = p + 1 + w + 4 * s2;
-      y[s2] = d4{0.0, 0.0, 0.0, 0.0};
-      if (m < P) y[s2] = blk_mma16(y[s2], pk_blk(T, m, p), PK_LD, Xpp, PK_LD, false);
+  {
+    const int a = 2 * w;
+    if (a + 1 < P) {
+      d4 y = blk_mma16(d4{0.0, 0.0, 0.0, 0.0}, pk_blk(T, a + 1, a + 1), PK_LD,
+                       pk_blk(T, a + 1, a), PK_LD, false);
+      d4 x = blk_mma16_areg(d4{0.0, 0.0, 0.0, 0.0}, y, pk_blk(T, a, a), PK_LD, false);
+      blk_store(pk_blk(T, a + 1, a), PK_LD, -x);
     }
     __syncthreads();
-#pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2) {
-      const int m = p + 1 + w + 4 * s2;
-      if (m < P) blk_store(pk_blk(T, m, p), PK_LD, y[s2]);
-    }
-    __syncthreads();
-    // X_ip = -sum_{m=p+1..i} X_im Y_mp; row p + c costs c block products
-    // (c = 1..n), so wave 0 takes c = n and wave w > 0 the pair w, n - w:
-    // every wave has at most n products
-    const int n = P - 1 - p;
-    int rows_w[2];
-    rows_w[0] = w == 0 ? p + n : (w <= n - w ? p + w : P);
-    rows_w[1] = (w > 0 && w < n - w) ? p + n - w : P;
-    d4 xi[2];
-#pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2) {
-      const int i = rows_w[s2];
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
-      if (i < P)
-        for (int m = p + 1; m <= i; ++m)
-          acc = blk_mma16(acc, pk_blk(T, i, m), PK_LD, pk_blk(T, m, p), PK_LD, false);
-      xi[s2] = -acc;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s2 = 0; s2 < 2; ++s2) {
-      const int i = rows_w[s2];
-      if (i < P) blk_store(pk_blk(T, i, p), PK_LD, xi[s2]);
-    }
-    // the next column reads only blocks of columns < p and the finished
-    // blocks of rows > p-1: the barrier of its first phase orders them
   }
-  __syncthreads();
+  inverse_level<2>(T, P);
+  inverse_level<4>(T, P);
 }
 
 // The lower 16 x 16 blocks of a tile (rIn) into the packed layout T; entries
@@ -722,18 +762,16 @@ __device__ __forceinline__ void load_packed_tile(rsrc_t rIn, double* T) {
   d2 v[NLD];
 #pragma unroll
   for (int u = 0; u < NLD; ++u) {
-    const int b = __builtin_amdgcn_readfirstlane((NTHREADS * u + tid) >> 7);
-    int bi = 0;
-    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+    const int b = (NTHREADS * u + tid) >> 7;  // per lane: keeps the caller's scalar registers free
+    const int bi = pk_row(b);
     const int bj = b - bi * (bi + 1) / 2;
     const int e = 2 * (tid & 127);
     v[u] = ld2(rIn, (16 * bi + (e & 15)) + NB * (16 * bj + (e >> 4)));
   }
 #pragma unroll
   for (int u = 0; u < NLD; ++u) {
-    const int b = __builtin_amdgcn_readfirstlane((NTHREADS * u + tid) >> 7);
-    int bi = 0;
-    while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+    const int b = (NTHREADS * u + tid) >> 7;  // per lane: keeps the caller's scalar registers free
+    const int bi = pk_row(b);
     const bool diag = b == bi * (bi + 1) / 2 + bi;
     const int e = 2 * (tid & 127), lr = e & 15, lc = e >> 4;
     double* dst = T + PK_STRIDE * b + lr + PK_LD * lc;
@@ -742,19 +780,24 @@ __device__ __forceinline__ void load_packed_tile(rsrc_t rIn, double* T) {
   }
 }
 
-// X and X^T of the packed inverse T to two tiles, as contiguous 16-byte
-// stores with explicit zeros above the diagonal of X.
-__device__ __forceinline__ void store_packed_inverse(double* T, rsrc_t rX, rsrc_t rXT) {
-  const int tid = opaque_tid();
-  auto pval = [&](int r, int c) -> double {
-    if (r < c) return 0.0;
-    return pk_blk(T, r >> 4, c >> 4)[(r & 15) + PK_LD * (c & 15)];
-  };
+// The packed lower triangle T as a full tile X (explicit zeros above the
+// diagonal) and, with both, as X^T too, in contiguous 16-byte stores.  Lane
+// l of wave w stores rows 2(l%64), 2(l%64) + 1 of columns w, w + 4, ...:
+// the row's block and offset are fixed per lane and the column's per wave,
+// so each element costs one LDS read and a select.
+__device__ __forceinline__ void store_packed(const double* T, rsrc_t rX, rsrc_t rXT, bool both) {
+  const int tid = opaque_tid(), w = tid >> 6;
+  const int rr = 2 * (tid & 63), rb = rr >> 4, rl = rr & 15, rtri = rb * (rb + 1) / 2;
 #pragma unroll 4
   for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
-    const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
-    st2(rX, e, d2{pval(rr, cc), pval(rr + 1, cc)});
-    st2(rXT, e, d2{pval(cc, rr), pval(cc, rr + 1)});
+    const int cc = w + 4 * q, cb = cc >> 4, cl = cc & 15, e = rr + NB * cc;
+    const double* x = T + PK_STRIDE * (rtri + cb) + rl + PK_LD * cl;  // X(rr, cc)
+    st2(rX, e, d2{rr >= cc ? x[0] : 0.0, rr + 1 >= cc ? x[1] : 0.0});
+    if (both) {
+      // X(cc, rr): block (cb, rb), in bounds even above the diagonal
+      const double* y = T + PK_STRIDE * (cb * (cb + 1) / 2 + rb) + cl + PK_LD * rl;
+      st2(rXT, e, d2{cc >= rr ? y[0] : 0.0, cc >= rr + 1 ? y[PK_LD] : 0.0});
+    }
   }
 }
 
@@ -777,7 +820,6 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
   double* T = smem;                          // the 36 packed blocks
   double* rd = smem + PK_BLOCKS * PK_STRIDE;  // reciprocal pivots
   int* flag = reinterpret_cast<int*>(rd + NB);
-  const int tid = threadIdx.x;
   const rsrc_t rIn = tile_rsrc(Ain), rL = tile_rsrc(Lout ? Lout : Xout), rX = tile_rsrc(Xout),
                rXT = tile_rsrc(XoutT);
 
@@ -787,28 +829,14 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
   const int ff = factor_packed(T, rd, rd + NB + 8, flag, P);
   if (ff) return ff;
 
-  // element (r, c) of the packed lower triangle (zero above the diagonal)
-  auto pval = [&](int r, int c) -> double {
-    if (r < c) return 0.0;
-    return pk_blk(T, r >> 4, c >> 4)[(r & 15) + PK_LD * (c & 15)];
-  };
-  // the factor and its transpose, as contiguous 16-byte stores; skipped
-  // when nothing reads them
-  const rsrc_t rLT = tile_rsrc(LcopyT ? LcopyT : Xout);
-  if (Lout) {
-#pragma unroll 4
-    for (int q = 0; q < NB * NB / 2 / NTHREADS; ++q) {
-      const int e = 2 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
-      st2(rL, e, d2{pval(rr, cc), pval(rr + 1, cc)});
-      if (LcopyT) st2(rLT, e, d2{pval(cc, rr), pval(cc, rr + 1)});  // L^T(rr, cc) = L(cc, rr)
-    }
-  }
+  // the factor and its transpose; skipped when nothing reads them
+  if (Lout) store_packed(T, rL, tile_rsrc(LcopyT ? LcopyT : Xout), LcopyT != nullptr);
   __syncthreads();  // the inverse overwrites the factor
 
   inverse_packed(T, rd, P);
   // the blocks past P (padding) still hold the identity block loaded with
   // the tile
-  store_packed_inverse(T, rX, rXT);
+  store_packed(T, rX, rXT, true);
   return 0;
 }
 
@@ -838,7 +866,7 @@ __device__ __attribute__((noinline)) int trtri_inv_tile(const double* Lin, doubl
   const int f = __builtin_amdgcn_readfirstlane(*flag);
   if (f != INT_MAX) return f;
   inverse_packed(T, rd, NB / 16);
-  store_packed_inverse(T, tile_rsrc(Xout), tile_rsrc(XoutT));
+  store_packed(T, tile_rsrc(Xout), tile_rsrc(XoutT), true);
   return 0;
 }
 
