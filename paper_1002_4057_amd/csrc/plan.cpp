@@ -618,6 +618,38 @@ void chain_products(int chain, Plan* p, std::vector<std::vector<int32_t>>& preds
 // product's predecessors, every successor of the product waits for all of
 // them, and the parts follow each other in program order (which stays
 // topological).
+// Duration of a device task in the dispatch cost model: `cost` per kind
+// and per further chain link (else unit weights); a row half costs
+// cost[K_COUNT + 1] of the whole product, a quarter 0.75 of that.
+double model_duration(int32_t k, const double* cost) {
+  double d = cost ? cost[task_kind(k)] + cost[K_COUNT] * task_links(k)
+                  : (double)weight(k) * (1 + task_links(k));
+  if (k & K_PART)
+    d *= cost ? cost[K_COUNT + 1] * ((k & K_PARTS4) ? 0.75 : 1.0) : ((k & K_PARTS4) ? 0.25 : 0.5);
+  return d;
+}
+
+// Slack of every task in the cost model: the critical path minus the
+// longest path through the task (earliest start plus longest remaining
+// path).  Tasks are in a topological program order.
+std::vector<double> model_slack(const Plan& p, const std::vector<std::vector<int32_t>>& preds,
+                                const double* cost) {
+  const int n = (int)p.tasks.size();
+  std::vector<double> dur(n), tl(n, 0.0), best(n, 0.0), bl(n, 0.0);
+  for (int v = 0; v < n; ++v) dur[v] = model_duration(p.tasks[v].kind, cost);
+  for (int v = 0; v < n; ++v)
+    for (int q : preds[v]) tl[v] = std::max(tl[v], tl[q] + dur[q]);
+  double cpl = 0.0;
+  for (int v = n - 1; v >= 0; --v) {  // successors have larger indices
+    bl[v] = dur[v] + best[v];
+    for (int q : preds[v]) best[q] = std::max(best[q], bl[v]);
+    cpl = std::max(cpl, tl[v] + bl[v]);
+  }
+  std::vector<double> slack(n);
+  for (int v = 0; v < n; ++v) slack[v] = cpl - (tl[v] + bl[v]);
+  return slack;
+}
+
 void split_critical_products(Plan* p, std::vector<std::vector<int32_t>>& preds, int parts) {
   const int n = (int)p->tasks.size();
   auto single = [&](int v) {
@@ -851,13 +883,13 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
   // (a row half costs cost[K_COUNT + 1] of the whole product, a quarter
   // 0.75 of that)
   std::vector<double> dur(n);
-  for (int v = 0; v < n; ++v) {
-    const int32_t k = p->tasks[v].kind;
-    dur[v] = cost ? cost[task_kind(k)] + cost[K_COUNT] * task_links(k)
-                  : (double)weight(k) * (1 + task_links(k));
-    if (k & K_PART)
-      dur[v] *= cost ? cost[K_COUNT + 1] * ((k & K_PARTS4) ? 0.75 : 1.0)
-                     : ((k & K_PARTS4) ? 0.25 : 0.5);
+  for (int v = 0; v < n; ++v) dur[v] = model_duration(p->tasks[v].kind, cost);
+  // near-critical tasks (K_URGENT): slack under half a single product
+  {
+    const std::vector<double> slack = model_slack(*p, bld.preds, cost);
+    const double eps = 0.5 * (cost ? cost[K_COUNT] : 1.0);
+    for (int v = 0; v < n; ++v)
+      if (dur[v] > 0.0 && slack[v] < eps) p->tasks[v].kind |= K_URGENT;
   }
   list_schedule(bld.preds, dur, workers, &p->order, nullptr);
 }

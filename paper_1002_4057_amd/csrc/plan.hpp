@@ -176,6 +176,11 @@ inline int task_links(int32_t k) { return (k & K_LINKS_MASK) >> K_LINKS_SHIFT; }
 constexpr int32_t K_PART = 1 << 24;
 constexpr int K_PART_SHIFT = 25;
 constexpr int32_t K_PARTS4 = 1 << 27;
+// Bit 28: the task is near-critical (its slack in the dispatch cost model
+// is under half a single product): its waves run at a raised issue
+// priority, ahead of a co-resident workgroup's.  Scheduling only; results
+// do not depend on it.
+constexpr int32_t K_URGENT = 1 << 28;
 inline int32_t task_kind(int32_t k) { return k & 0xff; }
 inline int32_t task_flags(int32_t k) { return (k >> 8) & 0xff; }
 

@@ -913,6 +913,10 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
   const double* a = t.a >= 0 ? tile_ptr(P, t.a) : nullptr;
   const double* b = t.b >= 0 ? tile_ptr(P, t.b) : nullptr;
   double* cp = t.copy >= 0 ? tile_ptr(P, t.copy) : nullptr;
+  // a near-critical task issues ahead of the co-resident workgroup's waves
+  // (one workgroup per matrix in the batched form: nothing to overtake)
+  const bool urgent = !ALLOW_R64 && (t.kind & K_URGENT) != 0;
+  if (urgent) __builtin_amdgcn_s_setprio(2);
   switch (kind) {
     case K_SYRK1: case K_GEMM1: case K_TRSM1: case K_TRMM2L: case K_GEMM2: case K_TRSM2R:
     case K_TRMM3: case K_LAUUM: case K_GEMM3: case K_SYRK3: case K_GEMMS: case K_TRSMS:
@@ -956,7 +960,13 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
       // ceil(last_valid / 16) blocks of 16 are factored and inverted
       const bool ragged = t.aux - g.d_base == tiles - 1;
       const int P16 = ragged ? (g.last_valid + 15) / 16 : NB / 16;
+      // POTRF heads the step-1 critical path and is bound by the latency of
+      // its dependent chains: its waves issue ahead of the co-resident
+      // workgroup's product waves while it runs
+      __builtin_amdgcn_s_setprio(3);
       const int fl = potrf_inv_tile(out, live ? out : nullptr, cp, X, Xt, smem, P16);
+      if (urgent) __builtin_amdgcn_s_setprio(2);
+      else __builtin_amdgcn_s_setprio(0);
       if (fl && threadIdx.x == 0) {
         const int jt = t.aux - g.d_base;  // diagonal tile index
         atomicMin(&g.ctrl[CTRL_INFO], g.info_base + jt * NB + fl);
@@ -974,6 +984,7 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
     default:
       break;
   }
+  if (urgent) __builtin_amdgcn_s_setprio(0);
 }
 
 }  // namespace
