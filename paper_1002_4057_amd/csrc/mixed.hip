@@ -236,6 +236,32 @@ __device__ __forceinline__ void tile_mma32(int f, float* C, const float* A, cons
 // by the FP64 path's packed code, and L, L^T, X = L^{-1} and X^T are rounded
 // to FP32.  Returns 0 or the 1-based local index of the first non-positive
 // pivot (nothing is stored then).
+// The packed lower triangle T, rounded to FP32, as a full tile X (explicit
+// zeros above the diagonal) and, with both, as X^T too, in 16-byte stores:
+// lane l stores rows 4(l%32) .. 4(l%32) + 3 of columns l/32, l/32 + 8, ...,
+// with its rows' block offsets computed once.
+__device__ __forceinline__ void store_packed32(const double* T, rsrc_t rX, rsrc_t rXT, bool both) {
+  const int tid = opaque_tid();
+  const int rr = 4 * (tid & 31), rb = rr >> 4, rl = rr & 15, rtri = rb * (rb + 1) / 2;
+#pragma unroll 2
+  for (int q = 0; q < NB * NB / 4 / NTHREADS; ++q) {
+    const int cc = (tid >> 5) + 8 * q, cb = cc >> 4, cl = cc & 15, e = rr + NB * cc;
+    const double* x = T + PK_STRIDE * (rtri + cb) + rl + PK_LD * cl;  // X(rr + s, cc)
+    f4 vx;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) vx[s] = (float)(rr + s >= cc ? x[s] : 0.0);
+    st4f(rX, e, vx);
+    if (both) {
+      // X(cc, rr + s): block (cb, rb), in bounds even above the diagonal
+      const double* y = T + PK_STRIDE * (cb * (cb + 1) / 2 + rb) + cl + PK_LD * rl;
+      f4 vy;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) vy[s] = (float)(cc >= rr + s ? y[PK_LD * s] : 0.0);
+      st4f(rXT, e, vy);
+    }
+  }
+}
+
 __device__ __attribute__((noinline)) int potrf_inv_tile32(const float* Ain, float* Lout,
                                                            float* LcopyT, float* Xout,
                                                            float* XoutT, double* smem) {
@@ -258,7 +284,7 @@ __device__ __attribute__((noinline)) int potrf_inv_tile32(const float* Ain, floa
   f4 v[NLD];
 #pragma unroll
   for (int u = 0; u < NLD; ++u) {
-    const int b = __builtin_amdgcn_readfirstlane((NTHREADS * u + tid) >> 6);
+    const int b = (NTHREADS * u + tid) >> 6;  // per lane: keeps the caller's scalar registers free
     const int bi = pk_row(b);
     const int bj = b - bi * (bi + 1) / 2;
     const int e = tid & 63, lr = 4 * (e & 3), lc = e >> 2;
@@ -266,7 +292,7 @@ __device__ __attribute__((noinline)) int potrf_inv_tile32(const float* Ain, floa
   }
 #pragma unroll
   for (int u = 0; u < NLD; ++u) {
-    const int b = __builtin_amdgcn_readfirstlane((NTHREADS * u + tid) >> 6);
+    const int b = (NTHREADS * u + tid) >> 6;  // per lane: keeps the caller's scalar registers free
     const int bi = pk_row(b);
     const bool diag = b == bi * (bi + 1) / 2 + bi;
     const int e = tid & 63, lr = 4 * (e & 3), lc = e >> 2;
@@ -277,42 +303,11 @@ __device__ __attribute__((noinline)) int potrf_inv_tile32(const float* Ain, floa
   __syncthreads();
   const int ff = factor_packed(T, rd, rd + NB + 8, flag, NB / 16);
   if (ff) return ff;
-  // element (r, c) of the packed lower triangle (zero above the diagonal)
-  auto pval = [&](int r, int c) -> double {
-    if (r < c) return 0.0;
-    return pk_blk(T, r >> 4, c >> 4)[(r & 15) + PK_LD * (c & 15)];
-  };
-  const rsrc_t rLT = rsrc32(LcopyT ? LcopyT : Xout);
-  if (Lout) {  // skipped when nothing reads the factor
-#pragma unroll 2
-    for (int q = 0; q < NB * NB / 4 / NTHREADS; ++q) {
-      const int e = 4 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
-      f4 x;
-#pragma unroll
-      for (int s = 0; s < 4; ++s) x[s] = (float)pval(rr + s, cc);
-      st4f(rL, e, x);
-      if (LcopyT) {
-        f4 y;
-#pragma unroll
-        for (int s = 0; s < 4; ++s) y[s] = (float)pval(cc, rr + s);
-        st4f(rLT, e, y);
-      }
-    }
-  }
+  // the factor and its transpose; skipped when nothing reads them
+  if (Lout) store_packed32(T, rL, rsrc32(LcopyT ? LcopyT : Xout), LcopyT != nullptr);
   __syncthreads();  // the inverse overwrites the factor
   inverse_packed(T, rd, NB / 16);
-#pragma unroll 2
-  for (int q = 0; q < NB * NB / 4 / NTHREADS; ++q) {
-    const int e = 4 * (tid + NTHREADS * q), rr = e & (NB - 1), cc = e >> 7;
-    f4 x, y;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      x[s] = (float)pval(rr + s, cc);
-      y[s] = (float)pval(cc, rr + s);
-    }
-    st4f(rX, e, x);
-    st4f(rXT, e, y);
-  }
+  store_packed32(T, rX, rXT, true);
   return 0;
 }
 
