@@ -750,6 +750,7 @@ void build_plan(const PlanOptions& opt, int workers, const double* cost, Plan* p
         d.kind |= K_POTRF_FACTOR_DEAD;
         d.copy = -1;
       }
+      if (d.aux >= 0 && !copy_read[d.aux + p->opt.t]) d.kind |= K_POTRF_INVT_DEAD;
     }
     for (int u = 0; u < nt; ++u) {
       DevTask& d = p->tasks[u];

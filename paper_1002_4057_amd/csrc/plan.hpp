@@ -134,6 +134,9 @@ enum ProductFlags : int32_t {
 // D_j instead -- so only D_j and D_j^T are stored.  The task keeps every
 // hazard edge of the paper's DAG.
 constexpr int32_t K_POTRF_FACTOR_DEAD = 1 << 16;
+// Bit 29 of DevTask::kind on a POTRF task: no task reads D_j^T (the
+// factor alone, whose TRSMs read D_j), so it is not stored.
+constexpr int32_t K_POTRF_INVT_DEAD = 1 << 29;
 // Bits 17/18 of DevTask::kind on a tile product: operand a / b may be read
 // through the L2 cache (default cache policy) instead of the device-coherent
 // policy.  The planner grants it only for tiles that are written exactly once

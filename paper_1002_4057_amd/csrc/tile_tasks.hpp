@@ -802,8 +802,8 @@ __device__ __forceinline__ void store_packed(const double* T, rsrc_t rX, rsrc_t 
 }
 
 // Outputs: the factor (Lout, may be null: not stored), its transpose (LcopyT,
-// may be null), the inverse of the factor (Xout) and its transpose (XoutT),
-// each with explicit zeros in the other triangle.  Only the first P blocks of
+// may be null), the inverse of the factor (Xout) and its transpose (XoutT,
+// may be null), each with explicit zeros in the other triangle.  Only the first P blocks of
 // 16 are factored and inverted: past them the tile must be an identity block
 // with zero cross blocks (the padding of a ragged order), whose factor and
 // inverse are the identity.  Returns 0, or the 1-based local index of the
@@ -836,7 +836,7 @@ __device__ __attribute__((noinline)) int potrf_inv_tile(const double* Ain, doubl
   inverse_packed(T, rd, P);
   // the blocks past P (padding) still hold the identity block loaded with
   // the tile
-  store_packed(T, rX, rXT, true);
+  store_packed(T, rX, rXT, XoutT != nullptr);
   return 0;
 }
 
@@ -964,7 +964,8 @@ __device__ __forceinline__ void run_task(const DevTask& t, const SchedArgs& g, d
       // its dependent chains: its waves issue ahead of the co-resident
       // workgroup's product waves while it runs
       __builtin_amdgcn_s_setprio(3);
-      const int fl = potrf_inv_tile(out, live ? out : nullptr, cp, X, Xt, smem, P16);
+      const int fl = potrf_inv_tile(out, live ? out : nullptr, cp, X,
+                                    (t.kind & K_POTRF_INVT_DEAD) ? nullptr : Xt, smem, P16);
       if (urgent) __builtin_amdgcn_s_setprio(2);
       else __builtin_amdgcn_s_setprio(0);
       if (fl && threadIdx.x == 0) {
