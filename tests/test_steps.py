@@ -82,6 +82,31 @@ def test_cholesky_plan_stores_every_factor_tile_and_no_unread_copy():
     assert (fk[(fk & 0xFF) == tx.POTRF] & tx.POTRF_FACTOR_DEAD).all()
 
 
+INVT_DEAD = 1 << 29
+
+
+@pytest.mark.parametrize("opts", [dict(), dict(renamed=0, trtri_first=1), dict(chain=1)])
+def test_transposed_inverse_stored_only_where_read(opts):
+    """POTRF(j) stores D_j and D_j^T; no task of the factor alone reads D_j^T
+    (its TRSMs multiply by D_j), so there the planner marks every POTRF to
+    skip it, and in the inverse and the solve (TRSM2R, TRTRI's copy into
+    C_jj, the backward substitution read D_j^T) it marks none.  Checked
+    against the operands of the plan itself: D_j^T is tile d_base + t + j."""
+    t = 7
+    for steps, s in ((1, 0), (7, 0), (9, 2)):
+        plan = spd.plan_export(t, workers=4, steps=steps, rhs_tiles=s, **opts)
+        tk = plan["tasks"]
+        kinds = tk[:, 0]
+        potrf = np.where((kinds & 0xFF) == tx.POTRF)[0]
+        assert len(potrf) == t
+        read = set(tk[:, 2].tolist()) | set(tk[:, 3].tolist())
+        read |= set((plan["links"][:, 0] & ~(1 << 30)).tolist()) | set(plan["links"][:, 1].tolist())
+        for v in potrf:
+            dt = int(tk[v, 5]) + t          # aux = D_j, D_j^T follows the t tiles of D
+            assert bool(kinds[v] & INVT_DEAD) == (dt not in read), (steps, v)
+        assert (kinds[potrf] & INVT_DEAD).all() == (steps == 1)
+
+
 @pytest.mark.parametrize("opts", VARIANTS, ids=lambda o: "-".join(f"{k}{v}" for k, v in o.items()) or "default")
 def test_inverse_from_factor_plan_in_any_order(opts):
     nb, n = 4, 21
