@@ -69,6 +69,21 @@ def test_ragged_sizes_against_oracle(n):
     assert rel_fro(sym_from_lower(out), oracle.spd_inverse(a)) <= 1e-12 * kappa(a)
 
 
+@pytest.mark.parametrize("p16", range(1, 9))
+@pytest.mark.parametrize("tiles", [1, 2, 3])
+def test_every_count_of_valid_blocks_in_the_last_tile(tiles, p16):
+    """The diagonal-tile task factors and inverts only the first P blocks of
+    16 of a ragged last tile (the rest is identity padding), and its
+    recursive inverse skips the pairs of block groups that start past P:
+    every P from 1 to 8, in the only tile and behind one or two full ones."""
+    n = 128 * (tiles - 1) + 16 * p16 - 3
+    print(f"last-tile blocks n={n} tiles={tiles} P={p16}", flush=True)
+    a = inputs.wishart_shift(n, seed=1000 + n).numpy()
+    out, rep = run(a)
+    assert rep["info"] == 0
+    assert rel_fro(sym_from_lower(out), oracle.spd_inverse(a)) <= 1e-12 * kappa(a)
+
+
 def test_tridiag_closed_form_n512():
     n = 512
     out, _ = run(inputs.tridiag(n))
